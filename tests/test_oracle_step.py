@@ -1,0 +1,161 @@
+"""Pins for one augmented-subspace step (Algorithm 3) of the oracle.
+
+Brute force on tiny meshes (dense generalised eigensolves, numpy.linalg /
+scipy.linalg used only as independent checking tools), Courant-Fischer
+bounds, the fixed-point property, span invariance, orthonormality, charge
+conservation, Anderson's least-squares property and agreement of a converged
+run of Algorithm 3 with a direct dense SCF on the fine space."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from ks_inputs import make_workload
+from oracle.step import (KSProblem, ks_scf_step, initial_guess, anderson_mix, small_eig)
+from oracle.xc import lda_xc
+
+
+def _tiny_linear(n=6, k=1, n_H=4, mu=8.0):
+    w = make_workload("hydrogen", n=n, k=k)
+    w.n_H = n_H
+    return KSProblem.from_workload(w, mu=mu)
+
+
+def _tiny_nonlinear(n=6, order=1, n_H=3, mu=5.0, k=None):
+    w = make_workload("small_molecule", n=n, order=order, k=k)
+    w.n_H = n_H
+    return KSProblem.from_workload(w, mu=mu)
+
+
+def test_linear_step_obeys_courant_fischer_bounds():
+    p = _tiny_linear(k=4)
+    A = p.A_linear().toarray()
+    lam_h = sla.eigh(A, p.M_II.toarray(), eigvals_only=True)[:4]
+    th0, Psi = initial_guess(p, 4)
+    r = ks_scf_step(p, Psi, th0, tol_solve=1e-13)
+    assert r.inner_iters == 1
+    assert np.all(lam_h <= r.lam + 1e-12)
+    assert np.all(r.lam <= th0 + 1e-12)
+    # repeated steps approach the discrete eigenvalues monotonically
+    lam_prev = r.lam
+    for _ in range(5):
+        r = ks_scf_step(p, r.Psi, r.lam, tol_solve=1e-13)
+        assert np.all(r.lam <= lam_prev + 1e-12) and np.all(lam_h <= r.lam + 1e-12)
+        lam_prev = r.lam
+
+
+def test_fixed_point_at_exact_discrete_eigenpairs():
+    """Started at exact eigenpairs of (A, M), S psi = (lambda + mu) M psi, so
+    psi_hat = psi and the Ritz step returns the same pairs."""
+    p = _tiny_linear(k=2)
+    A = p.A_linear().toarray()
+    lam, V = sla.eigh(A, p.M_II.toarray())
+    r = ks_scf_step(p, V[:, :2], lam[:2], tol_solve=1e-14)
+    assert np.abs(r.lam - lam[:2]).max() < 1e-10
+    assert np.abs(r.Psi_hat - V[:, :2]).max() < 1e-10
+    d = r.rho_q - p.density(V[:, :2])
+    assert np.sqrt(p.inner(d, d)) < 1e-9
+
+
+def test_orthonormality_and_charge():
+    p = _tiny_nonlinear(order=2, n=4)
+    th0, Psi = initial_guess(p, 5)
+    r = ks_scf_step(p, Psi, th0, tol_solve=1e-12, tol_inner=1e-11)
+    G = r.Psi.T @ (p.M_II @ r.Psi)
+    assert np.abs(G - np.eye(5)).max() < 1e-11
+    assert abs(np.sum(p.dV * r.rho_q) - p.occ.sum()) < 1e-10
+    # the output is an eigenpair of the projected pencil
+    res = r.FA @ r.U - r.FB @ r.U * r.lam[None, :]
+    assert np.abs(res).max() < 1e-9 * np.abs(r.FA).max()
+
+
+def test_span_invariance_under_rhs_scaling():
+    """Changing lambda^l rescales each BVP solution; the augmented space and
+    therefore the step's output do not change."""
+    p = _tiny_nonlinear(order=1, n=6)
+    th0, Psi = initial_guess(p, 5)
+    r1 = ks_scf_step(p, Psi, th0, tol_solve=1e-14, tol_inner=1e-12)
+    r2 = ks_scf_step(p, Psi, th0 + np.array([0.1, 0.3, -0.2, 0.05, 0.7]), tol_solve=1e-14,
+                     tol_inner=1e-12)
+    assert np.abs(r1.lam - r2.lam).max() < 1e-9
+    d = r1.rho_q - r2.rho_q
+    assert np.sqrt(p.inner(d, d)) < 1e-8
+
+
+def test_small_eig_invariant_to_basis_change():
+    rng = np.random.default_rng(0)
+    m, k = 12, 3
+    Zb = rng.normal(size=(40, m))
+    Mf = np.diag(rng.uniform(1, 2, 40))
+    Af = rng.normal(size=(40, 40)); Af = Af + Af.T
+    FA, FB = Zb.T @ Af @ Zb, Zb.T @ Mf @ Zb
+    th, U, rank, _ = small_eig(FA, FB, k)
+    Rm = rng.normal(size=(m, m))
+    th2, U2, _, _ = small_eig(Rm.T @ FA @ Rm, Rm.T @ FB @ Rm, k)
+    assert rank == m
+    assert np.allclose(th, th2, rtol=1e-10)
+    ref = sla.eigh(FA, FB, eigvals_only=True)[:k]
+    assert np.allclose(th, ref, rtol=1e-10)
+    # a duplicated column is dropped, not amplified
+    Zd = np.hstack([Zb, Zb[:, :1]])
+    th3, _, rank3, _ = small_eig(Zd.T @ Af @ Zd, Zd.T @ Mf @ Zd, k)
+    assert rank3 == m and np.allclose(th3, th, rtol=1e-9)
+
+
+def test_anderson_coefficients_minimise_residual_norm():
+    rng = np.random.default_rng(2)
+    wts = rng.uniform(0.5, 1.5, 30)
+    inner = lambda a, b: float(np.sum(wts * a * b))
+    hin = [rng.normal(size=30) for _ in range(4)]
+    hout = [rng.normal(size=30) for _ in range(4)]
+    beta = 0.7
+    new = anderson_mix(hin, hout, inner, beta=beta, depth=5)
+    F = [o - i for i, o in zip(hin, hout)]
+    D = np.stack([F[-1] - F[j] for j in range(3)], 1) * np.sqrt(wts)[:, None]
+    alpha, *_ = np.linalg.lstsq(D, F[-1] * np.sqrt(wts), rcond=None)
+    rin = hin[-1] + sum(alpha[j] * (hin[j] - hin[-1]) for j in range(3))
+    rout = hout[-1] + sum(alpha[j] * (hout[j] - hout[-1]) for j in range(3))
+    assert np.allclose(new, beta * rout + (1 - beta) * rin, atol=1e-9)
+    # first step: plain linear mixing
+    one = anderson_mix(hin[:1], hout[:1], inner, beta=beta)
+    assert np.allclose(one, beta * hout[0] + (1 - beta) * hin[0])
+
+
+def _direct_dense_scf(p, k, tol=1e-12, beta=0.5, max_it=400):
+    """Self-consistent field on the whole fine space with dense eigensolves."""
+    A0 = (0.5 * p.K_II + p.Mext_II).toarray()
+    Md = p.M_II.toarray()
+    lam, V = sla.eigh(A0, Md)
+    rho = p.density(V[:, :k])
+    for it in range(max_it):
+        wB = p.boundary_data(rho)
+        VH, _ = p.hartree_nodes(rho, wB, 1e-14)
+        _, vxc = lda_xc(rho, p.xc_mode)
+        A = A0 + p.potential_matrix(p.at_quad(VH) + vxc).toarray()
+        lam, V = sla.eigh(A, Md)
+        rho_out = p.density(V[:, :k])
+        d = rho_out - rho
+        if np.sqrt(p.inner(d, d)) < tol:
+            return lam[:k], rho_out, it
+        rho = rho + beta * d
+    raise RuntimeError("direct SCF did not converge")
+
+
+@pytest.mark.slow
+def test_converged_augmented_iteration_equals_direct_scf():
+    p = _tiny_nonlinear(order=1, n=6, n_H=4, mu=4.0, k=2)
+    k = 2
+    lam_d, rho_d, _ = _direct_dense_scf(p, k)
+    th, Psi = initial_guess(p, k)
+    rho_prev = p.density(Psi)
+    for step in range(300):
+        r = ks_scf_step(p, Psi, th, tol_solve=1e-13, tol_inner=1e-12, tol_poisson=1e-14)
+        d = r.rho_q - rho_prev
+        Psi, th, rho_prev = r.Psi, r.lam, r.rho_q
+        if np.sqrt(p.inner(d, d)) < 1e-11:
+            break
+    assert np.abs(th - lam_d).max() < 1e-8
+    d = r.rho_q - rho_d
+    assert np.sqrt(p.inner(d, d)) < 1e-8
+    # at outer convergence the two energy expressions coincide
+    E = r.energies
+    assert abs(E["total"] - E["KS"]) < 1e-8
