@@ -1,0 +1,204 @@
+/*
+ * ks.h -- C ABI of the MI355X library for one step of the augmented subspace
+ * method for the Kohn-Sham equation (Xu, Xie et al., "A Nonnested Augmented
+ * Subspace Method for Kohn-Sham Equation", arXiv 2404.19249).
+ *
+ * Conventions
+ *  - Pointers whose name ends in _host are host memory; every other array
+ *    pointer is HIP device memory.  The caller owns all buffers it passes; the
+ *    library owns the context and every workspace inside it.
+ *  - Unknowns are numbered by the interior (non-Dirichlet) nodes in ascending
+ *    node order: row i of an orbital block is the i-th node whose dirichlet
+ *    flag is 0.  Orbital blocks are row-major [N][k] (node-major, the k
+ *    right-hand sides contiguous), FP64.
+ *  - Quadrature-point arrays are [n_elems][n_q], FP64.
+ *  - All work is enqueued on the stream given to ks_create.  Entry points
+ *    that return results in _host memory synchronise that stream before they
+ *    return.
+ *  - Every entry point returns a ks_status; negative values are errors (the
+ *    outputs are then undefined) and ks_last_error() describes the last one on
+ *    the calling thread.  Positive values are usable results with a warning.
+ *  - A context is not thread safe; separate contexts on separate streams may
+ *    be used concurrently.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ks_ctx ks_ctx;
+
+typedef enum {
+  KS_OK = 0,
+  KS_NOT_CONVERGED = 1,     /* iteration limit reached; stats hold the residuals */
+  KS_WARN_DEGENERATE = 2,   /* lambda_{k+1} - lambda_k < 1e-8: occupied set ambiguous */
+  KS_ERR_ARG = -1,          /* invalid argument (null pointer, size out of range) */
+  KS_ERR_HIP = -2,          /* a HIP runtime call failed */
+  KS_ERR_NOMEM = -3,        /* device allocation failed */
+  KS_ERR_MESH = -4,         /* element with det J <= 0, node id out of range */
+  KS_ERR_BREAKDOWN = -5,    /* PCG breakdown: p^T S p <= 0 or NaN (operator not SPD) */
+  KS_ERR_EIG = -6,          /* small eigensolver failed (no positive mass direction) */
+  KS_ERR_STATE = -7         /* call order violated (e.g. project before a solve) */
+} ks_status;
+
+/* Mesh: a conforming tetrahedral decomposition of the box [-L, L]^3 with
+ * Lagrange elements of order 1 (4 nodes) or 2 (10 nodes: v0..v3 then the
+ * midpoints of edges 01, 02, 03, 12, 13, 23).  Elements must be positively
+ * oriented (det J > 0).  The finite element space is the one of Sec. 2 of
+ * the paper (linear elements; quadratic ones accepted as an extension). */
+typedef struct {
+  int32_t n_nodes, n_elems, order;
+  const double *coords_host;       /* [n_nodes][3], Bohr */
+  const int32_t *elems_host;       /* [n_elems][4 or 10] node ids */
+  const uint8_t *dirichlet_host;   /* [n_nodes], 1 = on the boundary (psi = 0) */
+  double L;                        /* half side of the box, for the coarse space */
+} ks_mesh_desc;
+
+/* Quadrature rule on the reference tetrahedron: barycentric points and
+ * weights summing to 1/6.  Densities and potentials live at these points. */
+typedef struct {
+  int32_t n_q;                     /* <= 64 */
+  const double *bary_host;         /* [n_q][4] */
+  const double *w_host;            /* [n_q] */
+} ks_quad_desc;
+
+/* Nuclei (Sec. 2): charges Z_k and positions R_k, atomic units. */
+typedef struct {
+  int32_t n_atoms;
+  const double *Z_host;            /* [n_atoms] */
+  const double *R_host;            /* [n_atoms][3] */
+} ks_atoms_desc;
+
+enum { KS_XC_NONE = 0, KS_XC_X = 1, KS_XC_X_PZ81 = 2 };
+enum { KS_HARTREE_OFF = 0, KS_HARTREE_MULTIPOLE = 1, KS_HARTREE_MULTIPOLE_LITERAL = 2 };
+enum { KS_PREC_FP64 = 0, KS_PREC_MIXED = 1 };
+
+typedef struct {
+  double mu;               /* shift of the BVPs; < 0 selects 8 M sum_k Z_k^2 (Sec. 4) */
+  int32_t n_H;             /* coarse space: uniform Kuhn P1 mesh with n_H hexes per side */
+  int32_t xc_mode;         /* KS_XC_*: LDA of Sec. 3.1 (Slater exchange + Perdew-Zunger) */
+  int32_t hartree_mode;    /* KS_HARTREE_*: Poisson with multipole boundary data (eq. bd);
+                              LITERAL drops the 1/2 of the quadrupole term */
+  int32_t k_max;           /* largest number of orbitals used with this context (<= 64) */
+  double tol_solve;        /* BVP relative residual (default 1e-8) */
+  double tol_inner;        /* inner SCF: ||rho_out - rho_in||_0 (default 1e-8) */
+  double tol_poisson;      /* Hartree Poisson relative residual (default 1e-10) */
+  int32_t max_it_solve, max_it_inner, max_it_poisson;
+  int32_t anderson_depth;  /* default 5 (Sec. 4) */
+  double anderson_beta;    /* default 0.7 (Sec. 4) */
+  double mixed_inner_tol;  /* FP32 inner PCG tolerance in the mixed form (default 1e-5) */
+  int32_t deterministic;   /* 1: fixed-order reductions (always on in this version) */
+} ks_options;
+
+/* Fill *o with the defaults above. */
+int ks_options_default(ks_options *o);
+
+/* Per-mesh setup (not part of a step): interior numbering, CSR pattern,
+ * element colouring, geometry, stiffness and mass matrices, the external
+ * potential at the quadrature points (V_ext = -sum Z_k/|x - R_k|, Sec. 2),
+ * A^L = 1/2 K + M[V_ext] (eq. st3), and the coarse interpolation I_H^h by
+ * closed-form point location on the uniform coarse mesh (Algorithm 1 on a
+ * structured coarse mesh).  Copies every host input; *out receives the
+ * context.  Errors: KS_ERR_ARG, KS_ERR_MESH (inverted element or bad id),
+ * KS_ERR_NOMEM, KS_ERR_HIP. */
+int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad, const ks_atoms_desc *atoms,
+              const ks_options *opt, hipStream_t stream, ks_ctx **out);
+int ks_destroy(ks_ctx *ctx);
+const char *ks_last_error(void);
+
+/* Sizes: out_host[0..9] = N (interior unknowns), n_nodes, n_elems, n_q,
+ * N_H (coarse unknowns), nnz of the interior CSR pattern, n_loc, number of
+ * element colours, leading dimension of the augmented basis Z, mu. */
+int ks_get_sizes(const ks_ctx *ctx, double *out_host);
+
+/* Assemble the Hamiltonian of the density of psi (Sec. 3.1 and 3.3):
+ * rho = sum_i occ_i psi_i^2 at the quadrature points, Hartree potential by
+ * the Poisson problem with multipole boundary data w_D(rho), LDA potential,
+ * V_eff = V_ext + V_H + V_xc, and the BVP operator
+ *     S = 1/2 K + M[V_eff] + mu M           (H-tilde of Sec. 3.3)
+ * which later calls use.  psi [N][k] may be NULL (then V_eff = V_ext).
+ * Optional device outputs (NULL to skip): rho_q, veff_q ([n_elems][n_q]),
+ * vh_nodes ([n_nodes], all nodes).  energies_host (NULL to skip) receives
+ * { <V_H, rho>/2, <rho, eps_xc>, <V_xc, rho>, <V_ext, rho>, Poisson iterations }. */
+int ks_assemble(ks_ctx *ctx, const double *psi, int32_t k, const double *occ_host,
+                double *rho_q, double *veff_q, double *vh_nodes, double *energies_host);
+
+/* Copy an assembled operator's CSR arrays out (for inspection):
+ * which = 0 S, 1 K (stiffness, interior), 2 M (mass), 3 A^L = 1/2 K + M[V_ext],
+ * 4 M[V_nl] of the last inner iteration.  row_ptr [N+1], col [nnz], val [nnz]
+ * are device buffers (any may be NULL). */
+int ks_export_operator(ks_ctx *ctx, int32_t which, int32_t *row_ptr, int32_t *col, double *val);
+
+typedef struct {
+  int32_t iters[64];      /* PCG iterations per column (mixed: FP32 inner iterations summed) */
+  int32_t refinements;    /* mixed form: FP64 residual evaluations */
+  int32_t converged;      /* 1 if every column met the tolerance */
+  double relres[64];      /* final ||b - S x|| / ||b|| per column (true residual, FP64) */
+  double seconds;         /* device time of the solve (HIP events) */
+} ks_solve_stats;
+
+/* The N boundary value problems of Algorithm 3 (eq. Aux_Linear_Problem):
+ *     S psi_hat_i = (lambda_i + mu) M psi_old_i,   i = 1..k,
+ * with S from the last ks_assemble, one Jacobi-preconditioned CG recurrence
+ * per column sharing every SpMM, started at psi_old, stopped per column at
+ * ||b_i - S x_i||_2 <= tol_solve ||b_i||_2.  precision = KS_PREC_MIXED runs
+ * FP32 PCG inside FP64 iterative refinement (FP64 residuals).
+ * psi_old, psi_hat: device [N][k]; lambda_host [k]; st_host may be NULL.
+ * Returns KS_NOT_CONVERGED if max_it_solve was reached. */
+int ks_block_solve(ks_ctx *ctx, const double *psi_old, const double *lambda_host, int32_t k,
+                   int32_t precision, double *psi_hat, ks_solve_stats *st_host);
+
+/* Generic form S X = B (B, X0, X device [N][k]; X0 may be NULL = zero). */
+int ks_block_solve_rhs(ks_ctx *ctx, const double *B, const double *X0, int32_t k,
+                       int32_t precision, double tol, double *X, ks_solve_stats *st_host);
+
+/* Galerkin projection onto the augmented space (eqs. st1-st7):
+ * Z = [I_H^h | psi_tilde] with psi_tilde = psi_hat M-orthogonalised against
+ * span(I_H^h) (same span); F = Z^T H Z for H = M (which = 0), A^L (1) or the
+ * nonlinear part M[V_H + V_xc] of the last assembly (2).  F is device
+ * [m][m], m = N_H + k, row-major.  Also stores Z in the context for
+ * ks_scf_step-style use.  FP64 with FP64 MFMA accumulation. */
+int ks_augmented_project(ks_ctx *ctx, const double *psi_hat, int32_t k, int32_t which, double *F);
+
+/* Lowest k eigenpairs of the pencil (F_A, F_B) (eq. st1), both device
+ * [m][m]: diagonal scaling, canonical orthogonalisation of F_B (directions
+ * below 1e-12 of the largest eigenvalue dropped), symmetric Jacobi
+ * eigensolve.  U device [m][k]; lambda_host [k]; rank_host may be NULL. */
+int ks_small_eig(ks_ctx *ctx, const double *FA, const double *FB, int32_t m, int32_t k,
+                 double *U, double *lambda_host, int32_t *rank_host);
+
+/* Initial guess: Ritz pairs of (1/2 K + M[V_ext], M) in span(I_H^h).
+ * psi device [N][k], lambda_host [k]. */
+int ks_initial_guess(ks_ctx *ctx, int32_t k, double *psi, double *lambda_host);
+
+typedef struct {
+  double E_total;        /* sum f lambda - <V_H/2 + V_xc, rho_in> + <rho_in, eps_xc> + E_nn */
+  double E_band, E_H, E_xc, E_vxc, E_nn;
+  double res_inner;      /* final ||rho_out - rho_in||_0 */
+  int32_t inner_iters;   /* nonlinear iterations in the augmented space */
+  int32_t poisson_iters; /* PCG iterations of all Hartree solves in the step */
+  int32_t rank;          /* numerical rank of F_B */
+  int32_t status_solve;
+  ks_solve_stats solve;
+  double seconds[8];     /* assemble, block solve, project, inner SCF, energies, total */
+} ks_step_report;
+
+/* One iteration of Algorithm 3: assemble S from the density of psi, solve
+ * the BVPs, project onto the augmented space, solve the small nonlinear
+ * Kohn-Sham problem there by the Anderson-mixed inner iteration of Sec. 4
+ * (Hartree boundary data w_D frozen at the step's input density), and write
+ * the new orbitals and eigenvalues back in place.
+ * psi: device [N][k] in/out; lambda_host [k] in/out; occ_host [k];
+ * rho_q (device [n_elems][n_q], may be NULL) receives the new density. */
+int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
+                int32_t precision, double *rho_q, ks_step_report *rep_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

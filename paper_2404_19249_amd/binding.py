@@ -1,0 +1,130 @@
+"""ctypes binding of the C ABI in include/ks.h.
+
+Argument marshalling only: every computation runs in the HIP library.
+PyTorch supplies device memory and the stream.  Loading fails loudly when the
+built library is missing; there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libks.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ks.h")
+
+KS_OK, KS_NOT_CONVERGED, KS_WARN_DEGENERATE = 0, 1, 2
+STATUS_NAMES = {0: "KS_OK", 1: "KS_NOT_CONVERGED", 2: "KS_WARN_DEGENERATE", -1: "KS_ERR_ARG",
+                -2: "KS_ERR_HIP", -3: "KS_ERR_NOMEM", -4: "KS_ERR_MESH", -5: "KS_ERR_BREAKDOWN",
+                -6: "KS_ERR_EIG", -7: "KS_ERR_STATE"}
+XC = {"none": 0, "x_only": 1, "x_pz81": 2}
+HARTREE = {"off": 0, "multipole": 1, "multipole_literal": 2}
+PREC = {"fp64": 0, "mixed": 1}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_elems", C.c_int32), ("order", C.c_int32),
+                ("coords_host", C.POINTER(C.c_double)), ("elems_host", C.POINTER(C.c_int32)),
+                ("dirichlet_host", C.POINTER(C.c_uint8)), ("L", C.c_double)]
+
+
+class QuadDesc(C.Structure):
+    _fields_ = [("n_q", C.c_int32), ("bary_host", C.POINTER(C.c_double)),
+                ("w_host", C.POINTER(C.c_double))]
+
+
+class AtomsDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("Z_host", C.POINTER(C.c_double)),
+                ("R_host", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("mu", C.c_double), ("n_H", C.c_int32), ("xc_mode", C.c_int32),
+                ("hartree_mode", C.c_int32), ("k_max", C.c_int32), ("tol_solve", C.c_double),
+                ("tol_inner", C.c_double), ("tol_poisson", C.c_double),
+                ("max_it_solve", C.c_int32), ("max_it_inner", C.c_int32),
+                ("max_it_poisson", C.c_int32), ("anderson_depth", C.c_int32),
+                ("anderson_beta", C.c_double), ("mixed_inner_tol", C.c_double),
+                ("deterministic", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 64), ("refinements", C.c_int32), ("converged", C.c_int32),
+                ("relres", C.c_double * 64), ("seconds", C.c_double)]
+
+
+class StepReport(C.Structure):
+    _fields_ = [("E_total", C.c_double), ("E_band", C.c_double), ("E_H", C.c_double),
+                ("E_xc", C.c_double), ("E_vxc", C.c_double), ("E_nn", C.c_double),
+                ("res_inner", C.c_double), ("inner_iters", C.c_int32),
+                ("poisson_iters", C.c_int32), ("rank", C.c_int32), ("status_solve", C.c_int32),
+                ("solve", SolveStats), ("seconds", C.c_double * 8)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "ks_options_default": (C.c_int, [C.POINTER(Options)]),
+    "ks_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(QuadDesc), C.POINTER(AtomsDesc),
+                            C.POINTER(Options), _P, C.POINTER(_P)]),
+    "ks_destroy": (C.c_int, [_P]),
+    "ks_last_error": (C.c_char_p, []),
+    "ks_get_sizes": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "ks_assemble": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double), _P, _P, _P,
+                              C.POINTER(C.c_double)]),
+    "ks_export_operator": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "ks_block_solve": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.c_int32, _P,
+                                 C.POINTER(SolveStats)]),
+    "ks_block_solve_rhs": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.c_double, _P,
+                                     C.POINTER(SolveStats)]),
+    "ks_augmented_project": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P]),
+    "ks_small_eig": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
+                               C.POINTER(C.c_int32)]),
+    "ks_initial_guess": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
+    "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                              C.c_int32, _P, C.POINTER(StepReport)]),
+}
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libks.so (built by paper_2404_19249_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class KSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, lib=None):
+    if code < 0:
+        lib = lib or load_library()
+        raise KSError(code, lib.ks_last_error().decode(errors="replace"))
+    return code
+
+
+def dptr(x):
+    """Host numpy float64 array -> double*."""
+    return x.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def header_functions():
+    """Names of the functions declared in include/ks.h."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(ks_\w+)\s*\(", txt, re.M)))

@@ -1,0 +1,204 @@
+"""Python front end of the library: one KSContext per mesh.
+
+Every method marshals torch tensors (device memory) and numpy arrays (host
+inputs) into one C ABI call; the arithmetic happens in the HIP kernels.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import binding as B
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class KSContext:
+    """Per-mesh state of the augmented subspace step on one GPU."""
+
+    def __init__(self, coords, elems, dirichlet, order, L, quad_bary, quad_w, Z, R, *, n_H=4,
+                 mu=None, xc="x_pz81", hartree="multipole", k_max=8, tol_solve=1e-8,
+                 tol_inner=1e-8, tol_poisson=1e-10, max_it_solve=5000, max_it_inner=50,
+                 max_it_poisson=20000, anderson_depth=5, anderson_beta=0.7,
+                 mixed_inner_tol=1e-5, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("KSContext needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.lib = B.load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        # host inputs are copied by ks_create; keep them alive for the call
+        self._coords = _f64(coords)
+        self._elems = _i32(elems)
+        self._dir = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        self._bary = _f64(quad_bary)
+        self._w = _f64(quad_w)
+        self._Z = _f64(Z)
+        self._R = _f64(np.asarray(R).reshape(-1, 3))
+        mesh = B.MeshDesc(self._coords.shape[0], self._elems.shape[0], int(order),
+                          self._coords.ctypes.data_as(C.POINTER(C.c_double)),
+                          self._elems.ctypes.data_as(C.POINTER(C.c_int32)),
+                          self._dir.ctypes.data_as(C.POINTER(C.c_uint8)), float(L))
+        quad = B.QuadDesc(self._w.shape[0], self._bary.ctypes.data_as(C.POINTER(C.c_double)),
+                          self._w.ctypes.data_as(C.POINTER(C.c_double)))
+        atoms = B.AtomsDesc(self._Z.shape[0], self._Z.ctypes.data_as(C.POINTER(C.c_double)),
+                            self._R.ctypes.data_as(C.POINTER(C.c_double)))
+        opt = B.Options()
+        B.check(self.lib.ks_options_default(C.byref(opt)))
+        opt.mu = -1.0 if mu is None else float(mu)
+        opt.n_H = int(n_H)
+        opt.xc_mode = B.XC[xc]
+        opt.hartree_mode = B.HARTREE[hartree]
+        opt.k_max = int(k_max)
+        opt.tol_solve, opt.tol_inner, opt.tol_poisson = tol_solve, tol_inner, tol_poisson
+        opt.max_it_solve, opt.max_it_inner, opt.max_it_poisson = max_it_solve, max_it_inner, max_it_poisson
+        opt.anderson_depth, opt.anderson_beta = anderson_depth, anderson_beta
+        opt.mixed_inner_tol = mixed_inner_tol
+        self.opt = opt
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            B.check(self.lib.ks_create(C.byref(mesh), C.byref(quad), C.byref(atoms), C.byref(opt),
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)), self.lib)
+        self.h = h
+        sz = (C.c_double * 10)()
+        B.check(self.lib.ks_get_sizes(self.h, sz))
+        self.N, self.n_nodes, self.n_elems, self.n_q, self.N_H, self.nnz, self.n_loc, \
+            self.n_colours, self.ld_z = [int(v) for v in sz[:9]]
+        self.mu = float(sz[9])
+        self.k_max = k_max
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        kw.setdefault("n_H", w.n_H)
+        kw.setdefault("xc", "x_pz81" if w.xc else "none")
+        kw.setdefault("hartree", "multipole" if w.hartree else "off")
+        kw.setdefault("k_max", max(w.k, 1))
+        m = w.mesh
+        return cls(m.coords, m.elems, m.dirichlet, m.order, m.L, w.quad.bary, w.quad.w,
+                   w.atoms.Z, w.atoms.R, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- helpers
+    def empty(self, *shape, dtype=None):
+        return self.torch.empty(*shape, dtype=dtype or self.torch.float64, device=self.device)
+
+    def _ptr(self, t):
+        if t is None:
+            return None
+        assert t.is_contiguous() and t.device == self.device, "device tensor expected"
+        return C.c_void_p(t.data_ptr())
+
+    # ------------------------------------------------------------------- API
+    def assemble(self, psi=None, occ=None, want_fields=True):
+        """ks_assemble: S of the density of psi; returns rho_q, veff_q, V_H
+        (nodes) and the energy terms."""
+        k = 0 if psi is None else psi.shape[1]
+        occ_a = None if psi is None else _f64(occ)
+        out = {}
+        if want_fields:
+            out["rho_q"] = self.empty(self.n_elems, self.n_q)
+            out["veff_q"] = self.empty(self.n_elems, self.n_q)
+            out["vh_nodes"] = self.empty(self.n_nodes)
+        e = np.zeros(5)
+        B.check(self.lib.ks_assemble(self.h, self._ptr(psi), k,
+                                     None if occ_a is None else B.dptr(occ_a),
+                                     self._ptr(out.get("rho_q")), self._ptr(out.get("veff_q")),
+                                     self._ptr(out.get("vh_nodes")), B.dptr(e)), self.lib)
+        out["energies"] = {"E_H": e[0], "E_xc": e[1], "E_vxc": e[2], "E_ext": e[3],
+                           "poisson_iters": int(e[4])}
+        return out
+
+    def export_operator(self, which):
+        """CSR arrays (host numpy) of operator `which` (0 S, 1 K, 2 M, 3 A^L, 4 M[V_nl])."""
+        rp = self.empty(self.N + 1, dtype=self.torch.int32)
+        cl = self.empty(self.nnz, dtype=self.torch.int32)
+        vl = self.empty(self.nnz)
+        B.check(self.lib.ks_export_operator(self.h, int(which), self._ptr(rp), self._ptr(cl),
+                                            self._ptr(vl)), self.lib)
+        return rp.cpu().numpy(), cl.cpu().numpy(), vl.cpu().numpy()
+
+    @staticmethod
+    def _stats(st, k):
+        return {"iters": list(st.iters[:k]), "relres": list(st.relres[:k]),
+                "refinements": st.refinements, "converged": bool(st.converged),
+                "seconds": st.seconds}
+
+    def block_solve(self, psi_old, lam, precision="fp64", out=None):
+        k = psi_old.shape[1]
+        lam_a = _f64(lam)
+        out = out if out is not None else self.empty(self.N, k)
+        st = B.SolveStats()
+        code = B.check(self.lib.ks_block_solve(self.h, self._ptr(psi_old), B.dptr(lam_a), k,
+                                               B.PREC[precision], self._ptr(out), C.byref(st)),
+                       self.lib)
+        s = self._stats(st, k)
+        s["status"] = code
+        return out, s
+
+    def block_solve_rhs(self, Bm, X0=None, precision="fp64", tol=0.0):
+        k = Bm.shape[1]
+        X = self.empty(self.N, k)
+        st = B.SolveStats()
+        code = B.check(self.lib.ks_block_solve_rhs(self.h, self._ptr(Bm), self._ptr(X0), k,
+                                                   B.PREC[precision], float(tol), self._ptr(X),
+                                                   C.byref(st)), self.lib)
+        s = self._stats(st, k)
+        s["status"] = code
+        return X, s
+
+    def augmented_project(self, psi_hat, which):
+        k = psi_hat.shape[1]
+        m = self.N_H + k
+        F = self.empty(m, m)
+        B.check(self.lib.ks_augmented_project(self.h, self._ptr(psi_hat), k, int(which),
+                                              self._ptr(F)), self.lib)
+        return F
+
+    def small_eig(self, FA, FB, k):
+        m = FA.shape[0]
+        U = self.empty(m, k)
+        lam = np.zeros(k)
+        rank = C.c_int32()
+        B.check(self.lib.ks_small_eig(self.h, self._ptr(FA.contiguous()), self._ptr(FB.contiguous()),
+                                      m, k, self._ptr(U), B.dptr(lam), C.byref(rank)), self.lib)
+        return U, lam, rank.value
+
+    def initial_guess(self, k):
+        psi = self.empty(self.N, k)
+        lam = np.zeros(k)
+        B.check(self.lib.ks_initial_guess(self.h, k, self._ptr(psi), B.dptr(lam)), self.lib)
+        return psi, lam
+
+    def scf_step(self, psi, lam, occ, precision="fp64", rho_out=None):
+        """One iteration of Algorithm 3 in place: psi (device [N][k]) and the
+        returned eigenvalues are the new iterate."""
+        k = psi.shape[1]
+        lam_a = _f64(lam).copy()
+        occ_a = _f64(occ)
+        rep = B.StepReport()
+        code = B.check(self.lib.ks_scf_step(self.h, self._ptr(psi), B.dptr(lam_a), k,
+                                            B.dptr(occ_a), B.PREC[precision], self._ptr(rho_out),
+                                            C.byref(rep)), self.lib)
+        r = {f: getattr(rep, f) for f in ("E_total", "E_band", "E_H", "E_xc", "E_vxc", "E_nn",
+                                          "res_inner", "inner_iters", "poisson_iters", "rank",
+                                          "status_solve")}
+        r["solve"] = self._stats(rep.solve, k)
+        r["seconds"] = list(rep.seconds[:6])
+        r["status"] = code
+        return lam_a, r

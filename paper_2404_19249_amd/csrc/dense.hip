@@ -1,0 +1,465 @@
+// Dense parts of the augmented subspace step (Sec. 3.3, eqs. st1-st7):
+//  * tall-skinny products C = Z^T Y (N ~ 1e6 rows, <= 256 columns) on the
+//    FP64 matrix cores (v_mfma_f64_16x16x4f64), rows staged through LDS,
+//    split over workgroups and reduced in a fixed order;
+//  * products with the coarse interpolation I_H^h stored as ELL-4 (every fine
+//    node lies in one coarse tetrahedron: at most four weights);
+//  * the small generalised eigenproblem F_A u = lambda F_B u solved in one
+//    workgroup: diagonal scaling, canonical orthogonalisation of F_B and
+//    cyclic Jacobi (round-robin parallel ordering) for both symmetric
+//    eigenproblems.
+#include "common.h"
+#include "kernels.h"
+#include <algorithm>
+
+namespace ks {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- GEMM TN
+constexpr int GT_ROWS = 16;        // rows staged per LDS slab (multiple of 4)
+constexpr int GT_THREADS = 512;    // 8 waves
+constexpr int GT_MAXC = 256;       // max padded columns per operand
+
+static inline int pad16(int x) { return (x + 15) / 16 * 16; }
+
+static int gemm_blocks(int N) {
+  int b = (N + 1023) / 1024;  // at least 1024 rows per workgroup
+  return std::max(1, std::min(b, 512));
+}
+size_t gemm_tn_work_doubles(int N, int ma, int nb) {
+  return (size_t)gemm_blocks(N) * pad16(ma) * pad16(nb);
+}
+
+// work[blk][ma_p][nb_p] = sum over the block's rows of Z^T Y.  Wave w owns
+// the 16x16 output tiles w, w + 8, ...; MAXT bounds the tiles per wave so
+// the accumulators stay in registers (static indexing after unrolling).
+template <int MAXT>
+__global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, int ma_p, int nb_p,
+                                                       const double *__restrict__ Z, int ldz,
+                                                       const double *__restrict__ Y, int ldy,
+                                                       double *__restrict__ work, int rows_per_blk) {
+  extern __shared__ double sm[];
+  double *sZ = sm;                       // [GT_ROWS][ma_p]
+  double *sY = sm + GT_ROWS * ma_p;      // [GT_ROWS][nb_p]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = GT_THREADS / 64;
+  const int tb_n = nb_p / 16, ntiles = (ma_p / 16) * tb_n;
+  f64x4 acc[MAXT];
+#pragma unroll
+  for (int ti = 0; ti < MAXT; ++ti) acc[ti] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int r0 = blockIdx.x * rows_per_blk;
+  const int r1 = min(N, r0 + rows_per_blk);
+  for (int base = r0; base < r1; base += GT_ROWS) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < GT_ROWS * ma_p; idx += GT_THREADS) {
+      const int rr = idx / ma_p, c = idx % ma_p, row = base + rr;
+      sZ[idx] = (row < r1 && c < ma) ? Z[(int64_t)row * ldz + c] : 0.0;
+    }
+    for (int idx = threadIdx.x; idx < GT_ROWS * nb_p; idx += GT_THREADS) {
+      const int rr = idx / nb_p, c = idx % nb_p, row = base + rr;
+      sY[idx] = (row < r1 && c < nb) ? Y[(int64_t)row * ldy + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = wave + ti * nwaves;
+      if (t < ntiles) {
+        const int ta = t / tb_n, tb = t % tb_n;
+        f64x4 c = acc[ti];
+#pragma unroll
+        for (int kk = 0; kk < GT_ROWS; kk += 4) {
+          const int rr = kk + (lane >> 4);
+          const double a = sZ[rr * ma_p + ta * 16 + (lane & 15)];
+          const double b = sY[rr * nb_p + tb * 16 + (lane & 15)];
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        }
+        acc[ti] = c;
+      }
+    }
+  }
+  // D layout: lane l, item r -> row 4*(l/16)+r, col l%16
+  double *out = work + (int64_t)blockIdx.x * ma_p * nb_p;
+#pragma unroll
+  for (int ti = 0; ti < MAXT; ++ti) {
+    const int t = wave + ti * nwaves;
+    if (t < ntiles) {
+      const int ta = t / tb_n, tb = t % tb_n;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ta * 16 + 4 * (lane >> 4) + r, col = tb * 16 + (lane & 15);
+        out[(int64_t)row * nb_p + col] = acc[ti][r];
+      }
+    }
+  }
+}
+
+__global__ void k_gemm_reduce(int nblk, int ma, int nb, int ma_p, int nb_p,
+                              const double *__restrict__ work, double *__restrict__ C, int ldc) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ma * nb) return;
+  const int a = idx / nb, b = idx % nb;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += work[(int64_t)k * ma_p * nb_p + a * nb_p + b];
+  C[(int64_t)a * ldc + b] = s;
+}
+
+void launch_gemm_tn(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy,
+                    double *C, int ldc, double *work, size_t work_doubles, hipStream_t s) {
+  const int ma_p = pad16(ma), nb_p = pad16(nb);
+  const int nblk = gemm_blocks(N);
+  int rows_per_blk = (N + nblk - 1) / nblk;
+  rows_per_blk = (rows_per_blk + GT_ROWS - 1) / GT_ROWS * GT_ROWS;
+  const size_t shm = sizeof(double) * GT_ROWS * (ma_p + nb_p);
+  const int per_wave = ((ma_p / 16) * (nb_p / 16) + 7) / 8;
+  dim3 g(nblk), b(GT_THREADS);
+  if (per_wave <= 2)
+    hipLaunchKernelGGL(k_gemm_tn<2>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+  else if (per_wave <= 4)
+    hipLaunchKernelGGL(k_gemm_tn<4>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+  else if (per_wave <= 8)
+    hipLaunchKernelGGL(k_gemm_tn<8>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+  else if (per_wave <= 16)
+    hipLaunchKernelGGL(k_gemm_tn<16>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+  else
+    hipLaunchKernelGGL(k_gemm_tn<32>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+  hipLaunchKernelGGL(k_gemm_reduce, dim3((ma * nb + 255) / 256), dim3(256), 0, s, nblk, ma, nb, ma_p,
+                     nb_p, work, C, ldc);
+}
+
+// ------------------------------------------------------------ ELL-4 P
+__global__ void k_ellP_times(int N, const int32_t *__restrict__ Pidx, const double *__restrict__ Pw,
+                             const double *__restrict__ T, int ldt, int k, double alpha,
+                             const double *__restrict__ Y, int ldy, double *__restrict__ Out, int ldo) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * k) return;
+  const int i = (int)(t / k), j = (int)(t % k);
+  double s = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int id = Pidx[4 * (int64_t)i + c];
+    if (id >= 0) s += Pw[4 * (int64_t)i + c] * T[(int64_t)id * ldt + j];
+  }
+  s *= alpha;
+  if (Y) s += Y[(int64_t)i * ldy + j];
+  Out[(int64_t)i * ldo + j] = s;
+}
+void launch_ellP_times(int N, const int32_t *Pidx, const double *Pw, const double *T, int ldt, int k,
+                       double alpha, const double *Y, int ldy, double *Out, int ldo, hipStream_t s) {
+  int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_ellP_times, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, Pidx, Pw,
+                       T, ldt, k, alpha, Y, ldy, Out, ldo);
+}
+
+// Psi = Z U with Z = [P | tail]: P part through the ELL form
+__global__ void k_zu(int N, const int32_t *__restrict__ Pidx, const double *__restrict__ Pw, int n_H,
+                     const double *__restrict__ Z, int ldz, int kt, const double *__restrict__ U,
+                     int k, double *__restrict__ Psi) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * k) return;
+  const int i = (int)(t / k), j = (int)(t % k);
+  double s = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    const int id = Pidx[4 * (int64_t)i + c];
+    if (id >= 0) s += Pw[4 * (int64_t)i + c] * U[(int64_t)id * k + j];
+  }
+  const double *zr = Z + (int64_t)i * ldz + n_H;
+  for (int a = 0; a < kt; ++a) s += zr[a] * U[(int64_t)(n_H + a) * k + j];
+  Psi[t] = s;
+}
+void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const double *Z, int ldz, int kt,
+               const double *U, int k, double *Psi, hipStream_t s) {
+  int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_zu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, Pidx, Pw, n_H, Z,
+                       ldz, kt, U, k, Psi);
+}
+
+__global__ void k_small_gemm(int m, int n, int p, const double *__restrict__ A, int lda,
+                             const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
+                             double beta) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * n) return;
+  const int i = t / n, j = t % n;
+  double s = 0.0;
+  for (int a = 0; a < p; ++a) s += A[(int64_t)i * lda + a] * B[(int64_t)a * ldb + j];
+  C[(int64_t)i * ldc + j] = (beta == 0.0 ? 0.0 : beta * C[(int64_t)i * ldc + j]) + s;
+}
+void launch_small_gemm(int m, int n, int p, const double *A, int lda, const double *B, int ldb,
+                       double *C, int ldc, double beta, hipStream_t s) {
+  if (m * n > 0)
+    hipLaunchKernelGGL(k_small_gemm, dim3((m * n + 255) / 256), dim3(256), 0, s, m, n, p, A, lda, B,
+                       ldb, C, ldc, beta);
+}
+
+__global__ void k_dense_P(int N, const int32_t *__restrict__ Pidx, const double *__restrict__ Pw,
+                          int n_H, double *__restrict__ Z, int ldz) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * n_H) return;
+  const int i = (int)(t / n_H), c = (int)(t % n_H);
+  double s = 0.0;
+  for (int a = 0; a < 4; ++a)
+    if (Pidx[4 * (int64_t)i + a] == c) s += Pw[4 * (int64_t)i + a];
+  Z[(int64_t)i * ldz + c] = s;
+}
+void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,
+                    hipStream_t s) {
+  int64_t n = (int64_t)N * n_H;
+  if (n > 0)
+    hipLaunchKernelGGL(k_dense_P, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, Pidx, Pw, n_H,
+                       Z, ldz);
+}
+__global__ void k_copy_cols(int N, int k, const double *__restrict__ X, int ldx,
+                            double *__restrict__ Z, int ldz, int c0) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * k) return;
+  const int i = (int)(t / k), j = (int)(t % k);
+  Z[(int64_t)i * ldz + c0 + j] = X[(int64_t)i * ldx + j];
+}
+void launch_copy_cols(int N, int k, const double *X, int ldx, double *Z, int ldz, int c0,
+                      hipStream_t s) {
+  int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, k, X, ldx, Z,
+                       ldz, c0);
+}
+__global__ void k_zero_cols(int N, int c0, int c1, double *__restrict__ Z, int ldz) {
+  const int w = c1 - c0;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * w) return;
+  Z[(t / w) * ldz + c0 + (t % w)] = 0.0;
+}
+void launch_zero_cols(int N, int c0, int c1, double *Z, int ldz, hipStream_t s) {
+  int64_t n = (int64_t)N * (c1 - c0);
+  if (n > 0)
+    hipLaunchKernelGGL(k_zero_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, c0, c1, Z,
+                       ldz);
+}
+
+// ----------------------------------------------------- small eigensolver
+constexpr int EIG_THREADS = 1024;
+constexpr int EIG_MAXN = 256;
+
+size_t small_eig_work_doubles(int m) { return (size_t)6 * m * m + 8 * m + 64; }
+
+// Cyclic Jacobi on the symmetric n x n matrix A (ld n, global memory),
+// accumulating eigenvectors in V (V := V J).  Round-robin ordering: n/2
+// disjoint pairs rotated per round, n-1 rounds per sweep.  A pair is
+// rotated only while |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|) (and an absolute
+// floor); the sweep loop ends when a whole sweep rotates nothing.
+__device__ int jacobi_eig(int n, double *A, double *V, int *s_top, int *s_bot, int *s_p, int *s_q,
+                          double *s_c, double *s_s, int *s_cnt, double *s_red) {
+  const int tid = threadIdx.x;
+  const int ne = (n + 1) & ~1, h = ne / 2;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+  // Frobenius norm for the absolute floor
+  double loc = 0.0;
+  for (int idx = tid; idx < n * n; idx += blockDim.x) loc += A[idx] * A[idx];
+  double fro2 = block_sum(loc, s_red);
+  if (tid == 0) s_red[16] = sqrt(fro2);
+  for (int t = tid; t < h; t += blockDim.x) {
+    s_top[t] = 2 * t;
+    s_bot[t] = 2 * t + 1;
+  }
+  __syncthreads();
+  const double floor_abs = 1e-300 + 1e-18 * s_red[16];
+  int sweeps = 0;
+  for (; sweeps < 60; ++sweeps) {
+    if (tid == 0) *s_cnt = 0;
+    __syncthreads();
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int t = tid; t < h; t += blockDim.x) {
+        int p = s_top[t], q = s_bot[t];
+        if (p > q) { int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          const double app = A[p * n + p], aqq = A[q * n + q];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+            const double th = (aqq - app) / (2.0 * apq);
+            double tt;
+            if (fabs(th) > 1e150) tt = 0.5 / th;
+            else tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+            atomicAdd(s_cnt, 1);
+          }
+        }
+        s_p[t] = p; s_q[t] = q; s_c[t] = c; s_s[t] = s;
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int idx = tid; idx < h * n; idx += blockDim.x) {
+        const int t = idx / n, j = idx % n;
+        const double s = s_s[t];
+        if (s == 0.0 || s_q[t] >= n) continue;
+        const int p = s_p[t], q = s_q[t];
+        const double c = s_c[t];
+        const double ap = A[p * n + j], aq = A[q * n + j];
+        A[p * n + j] = c * ap - s * aq;
+        A[q * n + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and V
+      for (int idx = tid; idx < h * n; idx += blockDim.x) {
+        const int t = idx / n, i = idx % n;
+        const double s = s_s[t];
+        if (s == 0.0 || s_q[t] >= n) continue;
+        const int p = s_p[t], q = s_q[t];
+        const double c = s_c[t];
+        const double ap = A[i * n + p], aq = A[i * n + q];
+        A[i * n + p] = c * ap - s * aq;
+        A[i * n + q] = s * ap + c * aq;
+        const double vp = V[i * n + p], vq = V[i * n + q];
+        V[i * n + p] = c * vp - s * vq;
+        V[i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // next round-robin arrangement (player top[0] fixed)
+      if (tid == 0) {
+        const int lt = s_top[h - 1], b0 = s_bot[0];
+        for (int t = h - 1; t >= 2; --t) s_top[t] = s_top[t - 1];
+        if (h > 1) s_top[1] = b0;
+        for (int t = 0; t < h - 1; ++t) s_bot[t] = s_bot[t + 1];
+        s_bot[h - 1] = (h > 1) ? lt : b0;
+      }
+      __syncthreads();
+    }
+    const int cnt = *s_cnt;
+    __syncthreads();
+    if (cnt == 0) break;
+  }
+  return sweeps;
+}
+
+// Lowest k eigenpairs of (FA, FB); see the header for the method.
+// work: D[m], A[m*m], V[m*m], X[m*m], T1[m*m], W[m*m], s[m], idx[m] ...
+__global__ void __launch_bounds__(EIG_THREADS) k_small_eig(int m, int k, const double *__restrict__ FA,
+                                                           int ldfa, const double *__restrict__ FB,
+                                                           int ldfb, double *__restrict__ work,
+                                                           double *__restrict__ theta,
+                                                           double *__restrict__ U, int *info) {
+  __shared__ int s_top[EIG_MAXN / 2 + 1], s_bot[EIG_MAXN / 2 + 1], s_p[EIG_MAXN / 2 + 1],
+      s_q[EIG_MAXN / 2 + 1];
+  __shared__ double s_c[EIG_MAXN / 2 + 1], s_s[EIG_MAXN / 2 + 1];
+  __shared__ double s_red[32];
+  __shared__ int s_cnt, s_rank, s_keep[EIG_MAXN], s_sel[EIG_MAXN];
+  __shared__ double s_sv[EIG_MAXN];
+  const int tid = threadIdx.x;
+  double *D = work;
+  double *A = D + m;
+  double *V = A + m * m;
+  double *X = V + m * m;
+  double *T1 = X + m * m;
+  double *W = T1 + m * m;
+  // 1. scaling
+  for (int i = tid; i < m; i += blockDim.x) {
+    const double b = FB[(int64_t)i * ldfb + i];
+    D[i] = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+    if (!(b > 0.0)) info[2] = 1;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m * m; idx += blockDim.x) {
+    const int i = idx / m, j = idx % m;
+    A[idx] = D[i] * D[j] * 0.5 * (FB[(int64_t)i * ldfb + j] + FB[(int64_t)j * ldfb + i]);
+  }
+  __syncthreads();
+  // 2. eigen-decomposition of the scaled F_B
+  const int sw1 = jacobi_eig(m, A, V, s_top, s_bot, s_p, s_q, s_c, s_s, &s_cnt, s_red);
+  // 3. keep s > 1e-12 s_max (ascending index order)
+  for (int i = tid; i < m; i += blockDim.x) s_sv[i] = A[i * m + i];
+  __syncthreads();
+  if (tid == 0) {
+    double smax = 0.0;
+    for (int i = 0; i < m; ++i) smax = fmax(smax, s_sv[i]);
+    int r = 0;
+    for (int i = 0; i < m; ++i)
+      if (s_sv[i] > 1e-12 * smax) s_keep[r++] = i;
+    s_rank = r;
+  }
+  __syncthreads();
+  const int r = s_rank;
+  // X[i][a] = V[i][keep_a] / sqrt(s_keep_a), ld r
+  for (int idx = tid; idx < m * r; idx += blockDim.x) {
+    const int i = idx / r, a = idx % r;
+    const int c = s_keep[a];
+    X[idx] = V[i * m + c] / sqrt(s_sv[c]);
+  }
+  // scaled F_A into A
+  __syncthreads();
+  for (int idx = tid; idx < m * m; idx += blockDim.x) {
+    const int i = idx / m, j = idx % m;
+    A[idx] = D[i] * D[j] * 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]);
+  }
+  __syncthreads();
+  // T1 = A X  (m x r)
+  for (int idx = tid; idx < m * r; idx += blockDim.x) {
+    const int i = idx / r, a = idx % r;
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += A[i * m + j] * X[j * r + a];
+    T1[idx] = s;
+  }
+  __syncthreads();
+  // C = X^T T1 (r x r), symmetrised, stored in A (ld r)
+  for (int idx = tid; idx < r * r; idx += blockDim.x) {
+    const int a = idx / r, b = idx % r;
+    if (b < a) continue;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      s1 += X[i * r + a] * T1[i * r + b];
+      s2 += X[i * r + b] * T1[i * r + a];
+    }
+    const double v = 0.5 * (s1 + s2);
+    V[a * r + b] = v;
+    V[b * r + a] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += blockDim.x) A[idx] = V[idx];
+  __syncthreads();
+  // 4. eigen-decomposition of C; eigenvectors in W (ld r)
+  const int sw2 = jacobi_eig(r, A, W, s_top, s_bot, s_p, s_q, s_c, s_s, &s_cnt, s_red);
+  // 5. ascending order by rank (ties by index)
+  for (int i = tid; i < r; i += blockDim.x) s_sv[i] = A[i * r + i];
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) {
+    const double v = s_sv[i];
+    int rk = 0;
+    for (int j = 0; j < r; ++j) rk += (s_sv[j] < v) || (s_sv[j] == v && j < i);
+    s_sel[rk] = i;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += blockDim.x) theta[i] = s_sv[s_sel[i]];
+  // 6. U = D X W_sel (m x k)
+  for (int idx = tid; idx < m * k; idx += blockDim.x) {
+    const int i = idx / k, j = idx % k;
+    double s = 0.0;
+    if (j < r) {
+      const int c = s_sel[j];
+      for (int a = 0; a < r; ++a) s += X[i * r + a] * W[a * r + c];
+    }
+    U[idx] = D[i] * s;
+  }
+  __syncthreads();
+  // 7. sign: largest-magnitude entry of each column positive (first max)
+  for (int j = tid; j < k; j += blockDim.x) {
+    int im = 0;
+    double vm = -1.0;
+    for (int i = 0; i < m; ++i) {
+      const double a = fabs(U[i * k + j]);
+      if (a > vm) { vm = a; im = i; }
+    }
+    if (U[im * k + j] < 0.0)
+      for (int i = 0; i < m; ++i) U[i * k + j] = -U[i * k + j];
+  }
+  if (tid == 0) {
+    info[0] = r;
+    info[1] = sw1 + sw2;
+  }
+}
+
+void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB, int ldfb,
+                      double *work, double *theta, double *U, int *info, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(EIG_THREADS), 0, s, m, k, FA, ldfa, FB, ldfb, work,
+                     theta, U, info);
+}
+
+}  // namespace ks

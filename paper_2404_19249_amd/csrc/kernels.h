@@ -1,0 +1,150 @@
+// Launchers of the device kernels (all enqueue on `s`, no synchronisation).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ks {
+
+// ---------------------------------------------------------------- geometry
+// absdet[e] = |det J_e|, gl[e][4][3] = barycentric gradients; bad[0] counts
+// elements with det J <= 0.
+void launch_geometry(const double *coords, const int32_t *elems, int n_loc, int n_e,
+                     double *absdet, double *gl, int32_t *bad, hipStream_t s);
+
+// ---------------------------------------------------------------- assembly
+// Element tables in device memory: phi [n_q][n_loc], dphi [n_q][n_loc][4],
+// w [n_q].  `list` holds the element ids of one colour.
+void launch_assemble_KM(const int32_t *list, int count, int n_loc, int n_q,
+                        const int32_t *slot, const double *absdet, const double *gl,
+                        const double *phi, const double *dphi, const double *w,
+                        double *K, double *M, hipStream_t s);
+// out[slot] += sum_q w_q |J| V_q phi_a phi_b (one colour).  pairtab: [n_q][n_pairs]
+// products phi_a phi_b for a <= b.
+void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_q,
+                               const int32_t *slot, const double *absdet, const double *pairtab,
+                               const double *w, const double *V_q, double *out, hipStream_t s);
+// out[dof_a] += sum_q w_q |J| f_q phi_a (one colour; dof = interior index or -1).
+void launch_load_vector(const int32_t *list, int count, int n_loc, int n_q,
+                        const int32_t *edof, const double *absdet, const double *phi,
+                        const double *w, const double *f_q, double scale, double *out,
+                        hipStream_t s);
+
+// y = a*x + b*y on n doubles; also used for copies (a=1,b=0).
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+void launch_fill(int64_t n, double v, double *y, hipStream_t s);
+void launch_combine3(int64_t n, double a, const double *x, double b, const double *y, double c,
+                     const double *z, double *out, hipStream_t s);
+void launch_to_float(int64_t n, const double *x, float *y, hipStream_t s);
+// diag[i] = val[slot of (i,i)]
+void launch_extract_diag(int N, const int32_t *rowptr, const int32_t *col, const double *val,
+                         double *diag, hipStream_t s);
+
+// ------------------------------------------------------------------ fields
+void launch_vext(const double *coords, const int32_t *elems, int n_loc, int n_e, int n_q,
+                 const double *bary, int n_atoms, const double *Z, const double *R, double *out,
+                 hipStream_t s);
+// rho_q = sum_i occ_i (sum_a phi_qa X[dof_a][i])^2
+void launch_density(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi,
+                    const double *X, int ldx, int k, const double *occ, double *rho, hipStream_t s);
+// u_q = sum_a phi_qa U[node_a]  (U over all nodes)
+void launch_eval_nodal(const int32_t *elems, int n_loc, int n_e, int n_q, const double *phi,
+                       const double *U, double *out, hipStream_t s);
+void launch_xc(int64_t n, const double *rho, int mode, double *eps, double *v, hipStream_t s);
+// partial sums over (e,q) of dV rho * {1, x, y, z} (stage 1) -> part[nblk][4]
+// or of dV rho * {dx, dy, dz, dxdx, dxdy, dxdz, dydy, dydz, dzdz} about c.
+int moments_blocks(int n_e);
+void launch_moments(const double *coords, const int32_t *elems, int n_loc, int n_e, int n_q,
+                    const double *bary, const double *w, const double *absdet, const double *rho,
+                    const double *center /*device [3] or null*/, double *part, int nvals,
+                    hipStream_t s);
+// out[j] = sum_b part[b][j], j < nvals (single block, fixed order)
+void launch_reduce_cols(const double *part, int nblk, int nvals, double *out, hipStream_t s);
+// multipole boundary values (eq. bd) from mom = {Q, cx, cy, cz, px, py, pz, qxx..qzz}
+void launch_multipole(const double *coords, const int32_t *bnodes, int nb, const double *mom,
+                      double quad_factor, double *wB, hipStream_t s);
+// V[node] = interior value or boundary value
+void launch_scatter_nodes(int n_nodes, const int32_t *node2int, const int32_t *node2bnd,
+                          const double *vint, const double *vbnd, double *V, hipStream_t s);
+// multi weighted dot: out_part[blk][j] = sum dV a_j b_j over the block's points
+int wdot_blocks(int64_t npts);
+void launch_wdots(int64_t npts, int n_q, const double *absdet, const double *w, int ndots,
+                  const double *const *a, const double *const *b, double *part, hipStream_t s);
+// out = sum_j c_j x_j  (nvec <= 12)
+void launch_lincomb(int64_t n, int nvec, const double *coef_dev, const double *const *x,
+                    double *out, hipStream_t s);
+
+// ------------------------------------------------------------- sparse / CG
+struct ColState;  // per-column PCG scalars, defined in spmm_cg.hip
+
+// Y = A X (mode 0) or Y = B - A X (mode 1) for [N][k] blocks, row stride ldx/ldy.
+void launch_spmm(int N, const int32_t *rowptr, const int32_t *col, const double *val,
+                 const double *X, int ldx, double *Y, int ldy, int k, const double *B, int ldb,
+                 int mode, hipStream_t s);
+void launch_spmm_f32(int N, const int32_t *rowptr, const int32_t *col, const float *val,
+                     const float *X, float *Y, int k, hipStream_t s);
+// Y[i][j] *= scale[j]
+void launch_scale_cols(int N, int k, double *Y, const double *scale_dev, hipStream_t s);
+
+// PCG driver (device-side per-column scalars; host polls every `chunk`
+// iterations).  Solves S X = B for k columns from X (in/out) to tol.
+struct PCGWork {
+  void *R, *P, *Q;       // [N][k] of T
+  void *part;            // block partials [nblk][2k] doubles
+  void *state;           // device ColState[k] + control
+  unsigned int *counter; // last-block counters
+  int nblk_max;
+};
+template <typename T>
+int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
+              const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
+              double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s);
+size_t pcg_state_bytes(int k);
+
+// ------------------------------------------------------------------- dense
+// C[a][b] = sum_i Z[i][a] Y[i][b] for a < ma, b < nb (tall-skinny, FP64
+// MFMA), Z row stride ldz, Y row stride ldy, C row stride ldc.
+void launch_gemm_tn(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy,
+                    double *C, int ldc, double *work, size_t work_doubles, hipStream_t s);
+size_t gemm_tn_work_doubles(int N, int ma, int nb);
+// Out[i][j] = sum_{c<4} Pw[i][c] T[Pidx[i][c]][j] (+ Y[i][j] if Y) ; T row stride ldt
+void launch_ellP_times(int N, const int32_t *Pidx, const double *Pw, const double *T, int ldt,
+                       int k, double alpha, const double *Y, int ldy, double *Out, int ldo,
+                       hipStream_t s);
+// Psi[i][j] = sum_c Pw Ut[Pidx][j] + sum_a Zt[i][a] Ut2[a][j]  (Zt: tail block of Z)
+void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const double *Z, int ldz,
+               int kt, const double *U, int k, double *Psi, hipStream_t s);
+// C (m x n) = A (m x p) * B (p x n), small dense, row-major
+void launch_small_gemm(int m, int n, int p, const double *A, int lda, const double *B, int ldb,
+                       double *C, int ldc, double beta, hipStream_t s);
+// Lowest k eigenpairs of (FA, FB), m <= 256: see ks_small_eig.
+// out_theta[m], out_U[m][k], info[0] = rank, info[1] = sweeps
+void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB, int ldfb,
+                      double *work, double *theta, double *U, int *info, hipStream_t s);
+size_t small_eig_work_doubles(int m);
+// Dense P (first n_H columns of Z) from the ELL form
+void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,
+                    hipStream_t s);
+// copy [N][k] block into columns [c0, c0+k) of Z
+void launch_copy_cols(int N, int k, const double *X, int ldx, double *Z, int ldz, int c0,
+                      hipStream_t s);
+void launch_zero_cols(int N, int c0, int c1, double *Z, int ldz, hipStream_t s);
+
+}  // namespace ks
+
+namespace ks {
+// per-column sums of squares of an [N][k] block: part[blk][k]; returns nblk
+int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s);
+// X[i][j] += scale[j] * (double)D[i][j]   (mixed-precision refinement update)
+void launch_refine_update(int N, int k, const float *D, const double *scale, double *X, hipStream_t s);
+// Anderson normal equations in one pass: with D_j = Fm - F_j (j < nh <= 4):
+// out[0] = <Fm,Fm>, out[1+j] = <D_j, Fm>, out[5 + 4j + l] = <D_j, D_l>
+// (block partials of 21 values: part[blk][21]); returns nblk
+int launch_anderson_gram(int64_t npts, int n_q, const double *absdet, const double *w,
+                         const double *Fm, int nh, const double *const *Fj, double *part,
+                         hipStream_t s);
+// F = A (m x m) assembled from blocks: PP [nH][nH] (ld nH), tail [m][kt] (ld kt)
+void launch_fill_pencil(int m, int nH, const double *PP, const double *tail, double *F,
+                        hipStream_t s);
+// out = a + b  (n doubles)
+void launch_add(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+}  // namespace ks

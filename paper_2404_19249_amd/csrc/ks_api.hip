@@ -1,0 +1,1206 @@
+// Host runtime and C ABI of the KS library: per-mesh setup (interior
+// numbering, CSR pattern, element colouring, element->CSR slot map, coarse
+// interpolation) and the entry points of one augmented-subspace step
+// (Algorithm 3 of the paper), which enqueue the device kernels on the
+// context's stream.
+#include "../../include/ks.h"
+#include "common.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace ks;
+
+static thread_local std::string g_err;
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(KS_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+namespace {
+
+// simple parallel-for over [0, n) on the host (setup only)
+template <typename F>
+void parallel_for(int64_t n, F f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 4096 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=, &f]() {
+      for (int64_t i = a; i < b; ++i) f(i);
+    });
+  }
+  for (auto &x : th) x.join();
+}
+
+struct DevBuf {
+  std::vector<void *> ptrs;
+  ~DevBuf() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct ks_ctx {
+  hipStream_t s = nullptr;
+  ks_options opt;
+  int order = 1, n_loc = 4, n_nodes = 0, n_e = 0, n_q = 0, N = 0, NB = 0, N_H = 0, n_H = 0;
+  int k_max = 0, mp = 0;  // leading dimension of Z
+  double L = 0.0, mu = 0.0;
+  int n_atoms = 0;
+  std::vector<double> hZ, hR;
+  double E_nn = 0.0;
+  int64_t nnz = 0, nnzB = 0, nnz_ext = 0;
+  int n_colours = 0;
+  std::vector<int> colour_off;
+
+  DevBuf mem;
+  // mesh / tables
+  double *coords = nullptr;
+  int32_t *elems = nullptr, *edof = nullptr, *slot = nullptr, *node2int = nullptr,
+          *node2bnd = nullptr, *bnodes = nullptr, *elem_perm = nullptr;
+  double *absdet = nullptr, *gl = nullptr, *phi = nullptr, *dphi = nullptr, *pairtab = nullptr,
+         *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
+  // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
+  int32_t *rowptr = nullptr, *col = nullptr, *rowptrB = nullptr, *colB = nullptr;
+  double *K = nullptr, *M = nullptr, *AL = nullptr, *base = nullptr, *S = nullptr,
+         *MNL = nullptr, *diagS = nullptr, *diagK = nullptr;
+  float *S32 = nullptr, *diagS32 = nullptr;
+  bool have_S = false, have_S32 = false;
+  // quadrature fields [n_e][n_q]
+  double *vext_q = nullptr, *rho_l = nullptr, *rho_in = nullptr, *rho_out = nullptr,
+         *vh_q = nullptr, *vxc_q = nullptr, *exc_q = nullptr, *vnl_q = nullptr;
+  double *hist_in[5] = {}, *hist_F[5] = {};
+  // Hartree
+  double *vh_int = nullptr, *vh_nodes = nullptr, *wB = nullptr, *load = nullptr, *rhs = nullptr,
+         *mom = nullptr, *mpart = nullptr;
+  bool vh_warm = false;
+  // coarse
+  int32_t *Pidx = nullptr;
+  double *Pw = nullptr, *Z = nullptr, *Y = nullptr, *GPP = nullptr, *GPPinv = nullptr,
+         *FAL_PP = nullptr;
+  // small dense
+  double *FB = nullptr, *FAL = nullptr, *FA = nullptr, *Ftail = nullptr, *Ctmp = nullptr,
+         *Ttmp = nullptr, *U = nullptr, *theta = nullptr, *eigwork = nullptr, *gwork = nullptr,
+         *coef = nullptr, *redpart = nullptr;
+  size_t gwork_n = 0;
+  int *einfo = nullptr;
+  // block vectors [N][k_max]
+  double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
+         *occ_d = nullptr, *scal = nullptr;
+  float *B32 = nullptr, *X32 = nullptr;
+  PCGWork pw64{}, pw32{}, pwP{};
+  unsigned int *counters = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  template <typename T>
+  int alloc(T **p, size_t count) {
+    void *q = nullptr;
+    size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
+    if (hipMalloc(&q, bytes) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+    mem.ptrs.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return KS_OK;
+  }
+  ~ks_ctx() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+#define TRY(x)                 \
+  do {                         \
+    int r_ = (x);              \
+    if (r_ < 0) return r_;     \
+  } while (0)
+
+extern "C" const char *ks_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ks_options_default(ks_options *o) {
+  if (!o) return fail(KS_ERR_ARG, "null options");
+  std::memset(o, 0, sizeof(*o));
+  o->mu = -1.0;
+  o->n_H = 4;
+  o->xc_mode = KS_XC_X_PZ81;
+  o->hartree_mode = KS_HARTREE_MULTIPOLE;
+  o->k_max = 8;
+  o->tol_solve = 1e-8;
+  o->tol_inner = 1e-8;
+  o->tol_poisson = 1e-10;
+  o->max_it_solve = 5000;
+  o->max_it_inner = 50;
+  o->max_it_poisson = 20000;
+  o->anderson_depth = 5;
+  o->anderson_beta = 0.7;
+  o->mixed_inner_tol = 1e-5;
+  o->deterministic = 1;
+  return KS_OK;
+}
+
+// ------------------------------------------------------------ basis tables
+static void basis_tables(int order, int n_q, const double *bary, std::vector<double> &phi,
+                         std::vector<double> &dphi) {
+  const int nl = order == 1 ? 4 : 10;
+  static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  phi.assign((size_t)n_q * nl, 0.0);
+  dphi.assign((size_t)n_q * nl * 4, 0.0);
+  for (int q = 0; q < n_q; ++q) {
+    const double *l = bary + 4 * q;
+    if (order == 1) {
+      for (int a = 0; a < 4; ++a) {
+        phi[q * nl + a] = l[a];
+        dphi[(q * nl + a) * 4 + a] = 1.0;
+      }
+    } else {
+      for (int a = 0; a < 4; ++a) {
+        phi[q * nl + a] = l[a] * (2.0 * l[a] - 1.0);
+        dphi[(q * nl + a) * 4 + a] = 4.0 * l[a] - 1.0;
+      }
+      for (int e = 0; e < 6; ++e) {
+        const int a = E[e][0], b = E[e][1];
+        phi[q * nl + 4 + e] = 4.0 * l[a] * l[b];
+        dphi[(q * nl + 4 + e) * 4 + a] = 4.0 * l[b];
+        dphi[(q * nl + 4 + e) * 4 + b] = 4.0 * l[a];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- helpers
+static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *out_host) {
+  launch_reduce_cols(part, nblk, nvals, c->mom + 64, c->s);
+  HIPCHK(hipMemcpyAsync(out_host, c->mom + 64, sizeof(double) * nvals, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return KS_OK;
+}
+
+// colour loop helpers
+static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out) {
+  for (int col = 0; col < c->n_colours; ++col) {
+    const int a = c->colour_off[col], b = c->colour_off[col + 1];
+    launch_assemble_potential(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->slot, c->absdet,
+                              c->pairtab, c->qw, Vq, out, c->s);
+  }
+}
+
+// V_H at the quadrature points for density rho with the frozen boundary
+// data c->wB (Sec. 3.1): K_II V_I = 4 pi <rho, phi_I> - K_IB w_B.
+static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
+  launch_fill(c->N, 0.0, c->load, c->s);
+  for (int col = 0; col < c->n_colours; ++col) {
+    const int a = c->colour_off[col], b = c->colour_off[col + 1];
+    launch_load_vector(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->edof, c->absdet, c->phi,
+                       c->qw, rho, 4.0 * M_PI, c->load, c->s);
+  }
+  // rhs = load - K_IB wB
+  launch_spmm(c->N, c->rowptrB, c->colB, c->K + c->nnz, c->wB, 1, c->rhs, 1, 1, c->load, 1, 1,
+              c->s);
+  if (!c->vh_warm) launch_fill(c->N, 0.0, c->vh_int, c->s);
+  int it[1] = {0}, conv = 0, brk = 0;
+  double rr[1];
+  int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->diagK, c->rhs, c->vh_int,
+                            c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
+                            c->s);
+  if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
+  if (brk) return fail(KS_ERR_BREAKDOWN, "Poisson PCG breakdown");
+  c->vh_warm = true;
+  if (iters) *iters += it[0];
+  launch_scatter_nodes(c->n_nodes, c->node2int, c->node2bnd, c->vh_int, c->wB, c->vh_nodes, c->s);
+  launch_eval_nodal(c->elems, c->n_loc, c->n_e, c->n_q, c->phi, c->vh_nodes, c->vh_q, c->s);
+  return conv ? KS_OK : KS_NOT_CONVERGED;
+}
+
+// w_D(rho) at the boundary nodes (eq. bd), stored in c->wB
+static int boundary_data(ks_ctx *c, const double *rho) {
+  const int nb = moments_blocks(c->n_e);
+  double h[16];
+  launch_moments(c->coords, c->elems, c->n_loc, c->n_e, c->n_q, c->qbary, c->qw, c->absdet, rho,
+                 nullptr, c->mpart, 4, c->s);
+  TRY(reduce_small(c, c->mpart, nb, 4, h));
+  double mom[16] = {0};
+  mom[0] = h[0];
+  if (!(h[0] > 0.0)) return fail(KS_ERR_ARG, "density has no charge: cannot place the multipole centre");
+  for (int d = 0; d < 3; ++d) mom[1 + d] = h[1 + d] / h[0];
+  HIPCHK(hipMemcpyAsync(c->mom, mom, sizeof(double) * 16, hipMemcpyHostToDevice, c->s));
+  launch_moments(c->coords, c->elems, c->n_loc, c->n_e, c->n_q, c->qbary, c->qw, c->absdet, rho,
+                 c->mom + 1, c->mpart, 9, c->s);
+  TRY(reduce_small(c, c->mpart, nb, 9, h));
+  for (int j = 0; j < 9; ++j) mom[4 + j] = h[j];
+  // mom[7..12] = q_xx q_xy q_xz q_yy q_yz q_zz (h[3..8])
+  HIPCHK(hipMemcpyAsync(c->mom, mom, sizeof(double) * 16, hipMemcpyHostToDevice, c->s));
+  const double f = c->opt.hartree_mode == KS_HARTREE_MULTIPOLE_LITERAL ? 1.0 : 0.5;
+  launch_multipole(c->coords, c->bnodes, c->NB, c->mom, f, c->wB, c->s);
+  return KS_OK;
+}
+
+static int weighted_dots(ks_ctx *c, int nd, const double *const *a, const double *const *b,
+                         double *out) {
+  const int64_t npts = (int64_t)c->n_e * c->n_q;
+  launch_wdots(npts, c->n_q, c->absdet, c->qw, nd, a, b, c->redpart, c->s);
+  return reduce_small(c, c->redpart, wdot_blocks(npts), nd, out);
+}
+
+// ------------------------------------------------------------------- create
+extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
+                         const ks_atoms_desc *atoms, const ks_options *opt, hipStream_t stream,
+                         ks_ctx **out) {
+  if (!mesh || !quad || !atoms || !out) return fail(KS_ERR_ARG, "null argument");
+  if (!mesh->coords_host || !mesh->elems_host || !mesh->dirichlet_host)
+    return fail(KS_ERR_ARG, "mesh arrays missing");
+  if (mesh->order != 1 && mesh->order != 2) return fail(KS_ERR_ARG, "order must be 1 or 2");
+  if (mesh->n_nodes <= 0 || mesh->n_elems <= 0) return fail(KS_ERR_ARG, "empty mesh");
+  if (quad->n_q <= 0 || quad->n_q > MAX_NQ || !quad->bary_host || !quad->w_host)
+    return fail(KS_ERR_ARG, "quadrature must have 1..27 points");
+  if ((quad->n_q != 8 && quad->n_q != 27))
+    return fail(KS_ERR_ARG, "quadrature rules with 8 or 27 points are supported");
+  if (atoms->n_atoms < 0 || (atoms->n_atoms > 0 && (!atoms->Z_host || !atoms->R_host)))
+    return fail(KS_ERR_ARG, "bad atoms");
+  ks_options o;
+  if (opt) o = *opt;
+  else ks_options_default(&o);
+  if (o.k_max < 1 || o.k_max > MAX_K) return fail(KS_ERR_ARG, "k_max must be in 1..64");
+  if (o.n_H < 2) return fail(KS_ERR_ARG, "n_H must be >= 2");
+  if (o.anderson_depth < 1 || o.anderson_depth > 5) return fail(KS_ERR_ARG, "anderson_depth in 1..5");
+
+  ks_ctx *c = new ks_ctx();
+  auto bail = [&](int code) {
+    delete c;
+    return code;
+  };
+  c->s = stream;
+  c->opt = o;
+  c->order = mesh->order;
+  c->n_loc = mesh->order == 1 ? 4 : 10;
+  c->n_nodes = mesh->n_nodes;
+  c->n_e = mesh->n_elems;
+  c->n_q = quad->n_q;
+  c->L = mesh->L;
+  c->n_H = o.n_H;
+  c->N_H = (o.n_H - 1) * (o.n_H - 1) * (o.n_H - 1);
+  c->k_max = o.k_max;
+  if (c->N_H + c->k_max > 256) return bail(fail(KS_ERR_ARG, "N_H + k_max must be <= 256"));
+  c->mp = (c->N_H + c->k_max + 15) / 16 * 16;
+  c->n_atoms = atoms->n_atoms;
+  c->hZ.assign(atoms->Z_host, atoms->Z_host + atoms->n_atoms);
+  c->hR.assign(atoms->R_host, atoms->R_host + 3 * atoms->n_atoms);
+  double sz2 = 0.0;
+  for (double z : c->hZ) sz2 += z * z;
+  c->mu = o.mu >= 0.0 ? o.mu : 8.0 * c->n_atoms * sz2;
+  for (int j = 0; j < c->n_atoms; ++j)
+    for (int k = 0; k < j; ++k) {
+      double dx = c->hR[3 * j] - c->hR[3 * k], dy = c->hR[3 * j + 1] - c->hR[3 * k + 1],
+             dz = c->hR[3 * j + 2] - c->hR[3 * k + 2];
+      c->E_nn += c->hZ[j] * c->hZ[k] / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+
+  const int nl = c->n_loc, ne = c->n_e, nn = c->n_nodes;
+  const int32_t *el = mesh->elems_host;
+  for (int64_t i = 0; i < (int64_t)ne * nl; ++i)
+    if (el[i] < 0 || el[i] >= nn) return bail(fail(KS_ERR_MESH, "element node id out of range"));
+  // interior / boundary numbering
+  std::vector<int32_t> node2int(nn, -1), node2bnd(nn, -1), bnodes;
+  int N = 0;
+  for (int i = 0; i < nn; ++i) {
+    if (mesh->dirichlet_host[i]) {
+      node2bnd[i] = (int)bnodes.size();
+      bnodes.push_back(i);
+    } else {
+      node2int[i] = N++;
+    }
+  }
+  c->N = N;
+  c->NB = (int)bnodes.size();
+  if (N == 0) return bail(fail(KS_ERR_MESH, "mesh has no interior node"));
+  std::vector<int32_t> edof((size_t)ne * nl);
+  for (int64_t i = 0; i < (int64_t)ne * nl; ++i) edof[i] = node2int[el[i]];
+  // node -> element adjacency
+  std::vector<int64_t> nadj_off(nn + 1, 0);
+  for (int64_t i = 0; i < (int64_t)ne * nl; ++i) nadj_off[el[i] + 1]++;
+  for (int i = 0; i < nn; ++i) nadj_off[i + 1] += nadj_off[i];
+  std::vector<int32_t> nadj(nadj_off[nn]);
+  {
+    std::vector<int64_t> pos(nadj_off.begin(), nadj_off.end() - 1);
+    for (int e = 0; e < ne; ++e)
+      for (int a = 0; a < nl; ++a) nadj[pos[el[(int64_t)e * nl + a]]++] = e;
+  }
+  // CSR pattern: interior rows; interior columns, then boundary columns (K_IB)
+  std::vector<int32_t> rowptr(N + 1, 0), rowptrB(N + 1, 0);
+  std::vector<int32_t> interior_nodes(N);
+  for (int i = 0; i < nn; ++i)
+    if (node2int[i] >= 0) interior_nodes[node2int[i]] = i;
+  auto row_cols = [&](int r, std::vector<int32_t> &ci, std::vector<int32_t> &cb) {
+    ci.clear();
+    cb.clear();
+    const int nd = interior_nodes[r];
+    for (int64_t p = nadj_off[nd]; p < nadj_off[nd + 1]; ++p) {
+      const int e = nadj[p];
+      for (int b = 0; b < nl; ++b) {
+        const int m = el[(int64_t)e * nl + b];
+        if (node2int[m] >= 0) ci.push_back(node2int[m]);
+        else cb.push_back(node2bnd[m]);
+      }
+    }
+    std::sort(ci.begin(), ci.end());
+    ci.erase(std::unique(ci.begin(), ci.end()), ci.end());
+    std::sort(cb.begin(), cb.end());
+    cb.erase(std::unique(cb.begin(), cb.end()), cb.end());
+  };
+  {
+    std::vector<int32_t> cntI(N), cntB(N);
+    parallel_for(N, [&](int64_t r) {
+      thread_local std::vector<int32_t> ci, cb;
+      row_cols((int)r, ci, cb);
+      cntI[r] = (int32_t)ci.size();
+      cntB[r] = (int32_t)cb.size();
+    });
+    int64_t sI = 0, sB = 0;
+    for (int r = 0; r < N; ++r) {
+      sI += cntI[r];
+      sB += cntB[r];
+      if (sI > 2000000000LL) return bail(fail(KS_ERR_ARG, "nnz exceeds int32 range"));
+      rowptr[r + 1] = (int32_t)sI;
+      rowptrB[r + 1] = (int32_t)sB;
+    }
+  }
+  c->nnz = rowptr[N];
+  c->nnzB = rowptrB[N];
+  c->nnz_ext = c->nnz + c->nnzB;
+  std::vector<int32_t> colI(c->nnz), colB(std::max<int64_t>(1, c->nnzB));
+  parallel_for(N, [&](int64_t r) {
+    thread_local std::vector<int32_t> ci, cb;
+    row_cols((int)r, ci, cb);
+    std::copy(ci.begin(), ci.end(), colI.begin() + rowptr[r]);
+    std::copy(cb.begin(), cb.end(), colB.begin() + rowptrB[r]);
+  });
+  // element -> value slot map (interior rows only)
+  std::vector<int32_t> slot((size_t)ne * nl * nl, -1);
+  parallel_for(ne, [&](int64_t e) {
+    for (int a = 0; a < nl; ++a) {
+      const int ra = edof[e * nl + a];
+      if (ra < 0) continue;
+      for (int b = 0; b < nl; ++b) {
+        const int m = el[e * nl + b];
+        int32_t sidx;
+        if (node2int[m] >= 0) {
+          const int cb = node2int[m];
+          const int32_t *p = std::lower_bound(colI.data() + rowptr[ra], colI.data() + rowptr[ra + 1], cb);
+          sidx = (int32_t)(p - colI.data());
+        } else {
+          const int cb = node2bnd[m];
+          const int32_t *p =
+              std::lower_bound(colB.data() + rowptrB[ra], colB.data() + rowptrB[ra + 1], cb);
+          sidx = (int32_t)(c->nnz + (p - colB.data()));
+        }
+        slot[(e * nl + a) * nl + b] = sidx;
+      }
+    }
+  });
+  // greedy element colouring: no two elements of one colour share a node
+  std::vector<int16_t> colour(ne, -1);
+  int ncol = 0;
+  {
+    std::vector<uint8_t> used(1024, 0);
+    std::vector<int> touched;
+    for (int e = 0; e < ne; ++e) {
+      touched.clear();
+      for (int a = 0; a < nl; ++a) {
+        const int nd = el[(int64_t)e * nl + a];
+        for (int64_t p = nadj_off[nd]; p < nadj_off[nd + 1]; ++p) {
+          const int f = nadj[p];
+          const int cf = colour[f];
+          if (cf >= 0 && !used[cf]) {
+            used[cf] = 1;
+            touched.push_back(cf);
+          }
+        }
+      }
+      int cc = 0;
+      while (cc < 1024 && used[cc]) ++cc;
+      if (cc >= 1024) return bail(fail(KS_ERR_MESH, "element colouring needs more than 1024 colours"));
+      colour[e] = (int16_t)cc;
+      ncol = std::max(ncol, cc + 1);
+      for (int t : touched) used[t] = 0;
+    }
+  }
+  c->n_colours = ncol;
+  c->colour_off.assign(ncol + 1, 0);
+  for (int e = 0; e < ne; ++e) c->colour_off[colour[e] + 1]++;
+  for (int k = 0; k < ncol; ++k) c->colour_off[k + 1] += c->colour_off[k];
+  std::vector<int32_t> perm(ne);
+  {
+    std::vector<int> pos(c->colour_off.begin(), c->colour_off.end() - 1);
+    for (int e = 0; e < ne; ++e) perm[pos[colour[e]]++] = e;
+  }
+  // coarse interpolation (closed-form location in the uniform Kuhn mesh)
+  std::vector<int32_t> Pidx((size_t)N * 4, -1);
+  std::vector<double> Pw((size_t)N * 4, 0.0);
+  {
+    const int nH = c->n_H, ni = nH - 1;
+    const double h = 2.0 * c->L / nH;
+    parallel_for(N, [&](int64_t r) {
+      const double *x = mesh->coords_host + 3 * (int64_t)interior_nodes[r];
+      int cell[3];
+      double xi[3];
+      for (int d = 0; d < 3; ++d) {
+        const double t = (x[d] + c->L) / h;
+        int ci = (int)std::floor(t);
+        ci = std::max(0, std::min(nH - 1, ci));
+        cell[d] = ci;
+        xi[d] = t - ci;
+      }
+      int ord[3] = {0, 1, 2};
+      // descending xi, ties by axis index
+      std::sort(ord, ord + 3, [&](int a, int b) { return xi[a] > xi[b] || (xi[a] == xi[b] && a < b); });
+      const double lam[4] = {1.0 - xi[ord[0]], xi[ord[0]] - xi[ord[1]], xi[ord[1]] - xi[ord[2]],
+                             xi[ord[2]]};
+      int v[3] = {cell[0], cell[1], cell[2]};
+      int cnt = 0;
+      for (int j = 0; j < 4; ++j) {
+        if (j > 0) v[ord[j - 1]] += 1;
+        bool inner = true;
+        for (int d = 0; d < 3; ++d)
+          if (v[d] <= 0 || v[d] >= nH) inner = false;
+        if (!inner) continue;
+        Pidx[4 * r + cnt] = (v[0] - 1) + ni * ((v[1] - 1) + ni * (v[2] - 1));
+        Pw[4 * r + cnt] = lam[j];
+        ++cnt;
+      }
+    });
+  }
+  // basis tables
+  std::vector<double> phi, dphi;
+  basis_tables(c->order, c->n_q, quad->bary_host, phi, dphi);
+  const int npairs = nl * (nl + 1) / 2;
+  std::vector<double> pairtab((size_t)c->n_q * npairs);
+  for (int q = 0; q < c->n_q; ++q) {
+    int p = 0;
+    for (int a = 0; a < nl; ++a)
+      for (int b = a; b < nl; ++b, ++p) pairtab[q * npairs + p] = phi[q * nl + a] * phi[q * nl + b];
+  }
+
+  // ---------------- device allocations and uploads
+  const int64_t nqt = (int64_t)ne * c->n_q;
+  const int km = c->k_max;
+#define A_(p, n) \
+  if (c->alloc(&c->p, (n)) < 0) return bail(KS_ERR_NOMEM)
+  A_(coords, (size_t)nn * 3);
+  A_(elems, (size_t)ne * nl);
+  A_(edof, (size_t)ne * nl);
+  A_(slot, (size_t)ne * nl * nl);
+  A_(node2int, nn);
+  A_(node2bnd, nn);
+  A_(bnodes, std::max(1, c->NB));
+  A_(elem_perm, ne);
+  A_(absdet, ne);
+  A_(gl, (size_t)ne * 12);
+  A_(phi, phi.size());
+  A_(dphi, dphi.size());
+  A_(pairtab, pairtab.size());
+  A_(qw, c->n_q);
+  A_(qbary, 4 * c->n_q);
+  A_(dZ, std::max(1, c->n_atoms));
+  A_(dR, std::max(3, 3 * c->n_atoms));
+  A_(rowptr, N + 1);
+  A_(col, c->nnz);
+  A_(rowptrB, N + 1);
+  A_(colB, std::max<int64_t>(1, c->nnzB));
+  A_(K, c->nnz_ext);
+  A_(M, c->nnz_ext);
+  A_(AL, c->nnz_ext);
+  A_(base, c->nnz_ext);
+  A_(S, c->nnz_ext);
+  A_(MNL, c->nnz_ext);
+  A_(diagS, N);
+  A_(diagK, N);
+  A_(S32, c->nnz);
+  A_(diagS32, N);
+  A_(vext_q, nqt);
+  A_(rho_l, nqt);
+  A_(rho_in, nqt);
+  A_(rho_out, nqt);
+  A_(vh_q, nqt);
+  A_(vxc_q, nqt);
+  A_(exc_q, nqt);
+  A_(vnl_q, nqt);
+  for (int j = 0; j < o.anderson_depth; ++j) {
+    A_(hist_in[j], nqt);
+    A_(hist_F[j], nqt);
+  }
+  A_(vh_int, N);
+  A_(vh_nodes, nn);
+  A_(wB, std::max(1, c->NB));
+  A_(load, N);
+  A_(rhs, N);
+  A_(mom, 128);
+  A_(mpart, (size_t)moments_blocks(ne) * 16);
+  A_(Pidx, (size_t)N * 4);
+  A_(Pw, (size_t)N * 4);
+  A_(Z, (size_t)N * c->mp);
+  A_(Y, (size_t)N * c->mp);
+  const int mm = c->mp;
+  A_(GPP, (size_t)c->N_H * c->N_H);
+  A_(GPPinv, (size_t)c->N_H * c->N_H);
+  A_(FAL_PP, (size_t)c->N_H * c->N_H);
+  A_(FB, (size_t)mm * mm);
+  A_(FAL, (size_t)mm * mm);
+  A_(FA, (size_t)mm * mm);
+  A_(Ftail, (size_t)mm * mm);
+  A_(Ctmp, (size_t)mm * mm);
+  A_(Ttmp, (size_t)mm * mm);
+  A_(U, (size_t)mm * km);
+  A_(theta, mm);
+  A_(eigwork, small_eig_work_doubles(mm));
+  c->gwork_n = gemm_tn_work_doubles(N, mm, mm);
+  A_(gwork, c->gwork_n);
+  A_(coef, 64);
+  A_(redpart, (size_t)1024 * 32);
+  A_(einfo, 8);
+  A_(Bv, (size_t)N * km);
+  A_(Xv, (size_t)N * km);
+  A_(Wv, (size_t)N * km);
+  A_(PsiHat, (size_t)N * km);
+  A_(PsiNew, (size_t)N * km);
+  A_(occ_d, 64);
+  A_(scal, 64);
+  A_(B32, (size_t)N * km);
+  A_(X32, (size_t)N * km);
+  A_(counters, 16);
+  {
+    const int nblk = 2048;
+    auto mk = [&](PCGWork &w, size_t elem, int k, int cidx) -> int {
+      void *r, *p, *q, *part, *st;
+      if (c->alloc(reinterpret_cast<char **>(&r), elem * N * k) < 0) return -1;
+      if (c->alloc(reinterpret_cast<char **>(&p), elem * N * k) < 0) return -1;
+      if (c->alloc(reinterpret_cast<char **>(&q), elem * N * k) < 0) return -1;
+      if (c->alloc(reinterpret_cast<double **>(&part), (size_t)nblk * 3 * k) < 0) return -1;
+      if (c->alloc(reinterpret_cast<char **>(&st), pcg_state_bytes(k)) < 0) return -1;
+      w.R = r; w.P = p; w.Q = q; w.part = part; w.state = st;
+      w.counter = c->counters + cidx;
+      w.nblk_max = nblk;
+      return 0;
+    };
+    if (mk(c->pw64, sizeof(double), km, 0) < 0) return bail(KS_ERR_NOMEM);
+    if (mk(c->pw32, sizeof(float), km, 4) < 0) return bail(KS_ERR_NOMEM);
+    if (mk(c->pwP, sizeof(double), 1, 8) < 0) return bail(KS_ERR_NOMEM);
+  }
+#undef A_
+  hipStream_t s = c->s;
+#define H2D(dst, src, n) \
+  if (hipMemcpyAsync(dst, src, sizeof(*(dst)) * (n), hipMemcpyHostToDevice, s) != hipSuccess) \
+    return bail(fail(KS_ERR_HIP, "upload failed"))
+  H2D(c->coords, mesh->coords_host, (size_t)nn * 3);
+  H2D(c->elems, el, (size_t)ne * nl);
+  H2D(c->edof, edof.data(), edof.size());
+  H2D(c->slot, slot.data(), slot.size());
+  H2D(c->node2int, node2int.data(), nn);
+  H2D(c->node2bnd, node2bnd.data(), nn);
+  if (c->NB) H2D(c->bnodes, bnodes.data(), c->NB);
+  H2D(c->elem_perm, perm.data(), ne);
+  H2D(c->phi, phi.data(), phi.size());
+  H2D(c->dphi, dphi.data(), dphi.size());
+  H2D(c->pairtab, pairtab.data(), pairtab.size());
+  H2D(c->qw, quad->w_host, c->n_q);
+  H2D(c->qbary, quad->bary_host, 4 * c->n_q);
+  if (c->n_atoms) {
+    H2D(c->dZ, c->hZ.data(), c->n_atoms);
+    H2D(c->dR, c->hR.data(), 3 * c->n_atoms);
+  }
+  H2D(c->rowptr, rowptr.data(), N + 1);
+  H2D(c->col, colI.data(), c->nnz);
+  H2D(c->rowptrB, rowptrB.data(), N + 1);
+  H2D(c->colB, colB.data(), colB.size());
+  H2D(c->Pidx, Pidx.data(), Pidx.size());
+  H2D(c->Pw, Pw.data(), Pw.size());
+#undef H2D
+  if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned int), s) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "memset failed"));
+  if (hipMemsetAsync(c->einfo, 0, 8 * sizeof(int), s) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "memset failed"));
+  // ---------------- a1: geometry, K, M, V_ext, M[V_ext]
+  launch_geometry(c->coords, c->elems, nl, ne, c->absdet, c->gl, c->einfo, s);
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, c->einfo, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "geometry kernel failed"));
+  if (bad) return bail(fail(KS_ERR_MESH, "mesh has " + std::to_string(bad) + " element(s) with det J <= 0"));
+  launch_fill(c->nnz_ext, 0.0, c->K, s);
+  launch_fill(c->nnz_ext, 0.0, c->M, s);
+  for (int k = 0; k < ncol; ++k) {
+    const int a = c->colour_off[k], b = c->colour_off[k + 1];
+    launch_assemble_KM(c->elem_perm + a, b - a, nl, c->n_q, c->slot, c->absdet, c->gl, c->phi,
+                       c->dphi, c->qw, c->K, c->M, s);
+  }
+  launch_vext(c->coords, c->elems, nl, ne, c->n_q, c->qbary, c->n_atoms, c->dZ, c->dR, c->vext_q, s);
+  launch_fill(c->nnz_ext, 0.0, c->AL, s);
+  assemble_potential_all(c, c->vext_q, c->AL);
+  launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);                  // A^L = K/2 + M[V_ext]
+  launch_combine3(c->nnz_ext, 1.0, c->AL, c->mu, c->M, 0.0, nullptr, c->base, s);  // + mu M
+  launch_extract_diag(N, c->rowptr, c->col, c->K, c->diagK, s);
+  // ---------------- coarse blocks: dense P in Z, G_PP = P^T M P, P^T A^L P
+  launch_fill((int64_t)N * c->mp, 0.0, c->Z, s);
+  launch_dense_P(N, c->Pidx, c->Pw, c->N_H, c->Z, c->mp, s);
+  launch_spmm(N, c->rowptr, c->col, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
+  launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->GPP, c->N_H, c->gwork, c->gwork_n, s);
+  launch_spmm(N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
+  launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork, c->gwork_n,
+                 s);
+  {
+    // G_PP^{-1} on the host (N_H <= 255): Gauss-Jordan with partial pivoting
+    const int n = c->N_H;
+    std::vector<double> G((size_t)n * n), I((size_t)n * n, 0.0);
+    if (hipMemcpyAsync(G.data(), c->GPP, sizeof(double) * n * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail(fail(KS_ERR_HIP, "coarse mass matrix download failed"));
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int p = 0; p < n; ++p) {
+      int piv = p;
+      for (int r = p + 1; r < n; ++r)
+        if (std::fabs(G[(size_t)r * n + p]) > std::fabs(G[(size_t)piv * n + p])) piv = r;
+      if (!(std::fabs(G[(size_t)piv * n + p]) > 0.0))
+        return bail(fail(KS_ERR_MESH, "coarse space is rank deficient on this mesh (mesh too coarse for n_H)"));
+      if (piv != p)
+        for (int j = 0; j < n; ++j) {
+          std::swap(G[(size_t)p * n + j], G[(size_t)piv * n + j]);
+          std::swap(I[(size_t)p * n + j], I[(size_t)piv * n + j]);
+        }
+      const double d = 1.0 / G[(size_t)p * n + p];
+      for (int j = 0; j < n; ++j) {
+        G[(size_t)p * n + j] *= d;
+        I[(size_t)p * n + j] *= d;
+      }
+      for (int r = 0; r < n; ++r) {
+        if (r == p) continue;
+        const double f = G[(size_t)r * n + p];
+        if (f == 0.0) continue;
+        for (int j = 0; j < n; ++j) {
+          G[(size_t)r * n + j] -= f * G[(size_t)p * n + j];
+          I[(size_t)r * n + j] -= f * I[(size_t)p * n + j];
+        }
+      }
+    }
+    if (hipMemcpyAsync(c->GPPinv, I.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail(fail(KS_ERR_HIP, "upload failed"));
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "event creation failed"));
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(KS_ERR_HIP, "setup failed"));
+  *out = c;
+  return KS_OK;
+}
+
+extern "C" int ks_destroy(ks_ctx *c) {
+  if (!c) return KS_OK;
+  (void)hipStreamSynchronize(c->s);
+  delete c;
+  return KS_OK;
+}
+
+extern "C" int ks_get_sizes(const ks_ctx *c, double *o) {
+  if (!c || !o) return fail(KS_ERR_ARG, "null argument");
+  o[0] = c->N;
+  o[1] = c->n_nodes;
+  o[2] = c->n_e;
+  o[3] = c->n_q;
+  o[4] = c->N_H;
+  o[5] = (double)c->nnz;
+  o[6] = c->n_loc;
+  o[7] = c->n_colours;
+  o[8] = c->mp;
+  o[9] = c->mu;
+  return KS_OK;
+}
+
+// --------------------------------------------------------------- assemble
+// rho_l, w_B, V_H, V_xc of the density of psi; S = base + M[V_H + V_xc].
+static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_host, int *p_iters) {
+  hipStream_t s = c->s;
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  const bool nonlinear = psi && (c->opt.hartree_mode != KS_HARTREE_OFF || c->opt.xc_mode != KS_XC_NONE);
+  if (psi) {
+    HIPCHK(hipMemcpyAsync(c->occ_d, occ_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
+    launch_density(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, psi, k, k, c->occ_d, c->rho_l, s);
+  } else {
+    launch_fill(nqt, 0.0, c->rho_l, s);
+  }
+  launch_fill(nqt, 0.0, c->vh_q, s);
+  if (psi && c->opt.hartree_mode != KS_HARTREE_OFF) {
+    TRY(boundary_data(c, c->rho_l));
+    int r = hartree_solve(c, c->rho_l, p_iters);
+    if (r < 0) return r;
+  } else {
+    launch_fill(std::max(1, c->NB), 0.0, c->wB, s);
+    launch_fill(c->n_nodes, 0.0, c->vh_nodes, s);
+  }
+  launch_xc(nqt, c->rho_l, psi ? c->opt.xc_mode : KS_XC_NONE, c->exc_q, c->vxc_q, s);
+  launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
+  launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
+  if (nonlinear) assemble_potential_all(c, c->vnl_q, c->S);
+  launch_extract_diag(c->N, c->rowptr, c->col, c->S, c->diagS, s);
+  c->have_S = true;
+  c->have_S32 = false;
+  return KS_OK;
+}
+
+extern "C" int ks_assemble(ks_ctx *c, const double *psi, int32_t k, const double *occ_host,
+                           double *rho_q, double *veff_q, double *vh_nodes, double *energies_host) {
+  if (!c) return fail(KS_ERR_ARG, "null context");
+  if (psi && (k < 1 || k > c->k_max || !occ_host)) return fail(KS_ERR_ARG, "k must be in 1..k_max with occupations");
+  int piters = 0;
+  TRY(assemble_impl(c, psi, k, occ_host, &piters));
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  if (rho_q) HIPCHK(hipMemcpyAsync(rho_q, c->rho_l, sizeof(double) * nqt, hipMemcpyDeviceToDevice, c->s));
+  if (veff_q) launch_combine3(nqt, 1.0, c->vext_q, 1.0, c->vh_q, 1.0, c->vxc_q, veff_q, c->s);
+  if (vh_nodes) HIPCHK(hipMemcpyAsync(vh_nodes, c->vh_nodes, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->s));
+  if (energies_host) {
+    const double *a[4] = {c->vh_q, c->exc_q, c->vxc_q, c->vext_q};
+    const double *b[4] = {c->rho_l, c->rho_l, c->rho_l, c->rho_l};
+    double e[4];
+    TRY(weighted_dots(c, 4, a, b, e));
+    energies_host[0] = 0.5 * e[0];
+    energies_host[1] = e[1];
+    energies_host[2] = e[2];
+    energies_host[3] = e[3];
+    energies_host[4] = piters;
+  }
+  HIPCHK(hipStreamSynchronize(c->s));
+  return KS_OK;
+}
+
+extern "C" int ks_export_operator(ks_ctx *c, int32_t which, int32_t *row_ptr, int32_t *colp,
+                                  double *val) {
+  if (!c) return fail(KS_ERR_ARG, "null context");
+  const double *src = nullptr;
+  switch (which) {
+    case 0: src = c->S; if (!c->have_S) return fail(KS_ERR_STATE, "S not assembled"); break;
+    case 1: src = c->K; break;
+    case 2: src = c->M; break;
+    case 3: src = c->AL; break;
+    case 4: src = c->MNL; break;
+    default: return fail(KS_ERR_ARG, "which must be 0..4");
+  }
+  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, c->rowptr, sizeof(int32_t) * (c->N + 1), hipMemcpyDeviceToDevice, c->s));
+  if (colp) HIPCHK(hipMemcpyAsync(colp, c->col, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToDevice, c->s));
+  if (val) HIPCHK(hipMemcpyAsync(val, src, sizeof(double) * c->nnz, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return KS_OK;
+}
+
+// ------------------------------------------------------------ block solve
+static int true_residual(ks_ctx *c, const double *B, const double *X, int k, double *relres,
+                         bool *ok) {
+  launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->s);
+  std::vector<double> rn(k), bn(k), tmp((size_t)256 * k);
+  int nb = launch_colnorms(c->N, k, c->Wv, c->redpart, c->s);
+  TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
+  nb = launch_colnorms(c->N, k, B, c->redpart, c->s);
+  TRY(reduce_small(c, c->redpart, nb, k, bn.data()));
+  *ok = true;
+  for (int j = 0; j < k; ++j) {
+    relres[j] = bn[j] > 0 ? std::sqrt(rn[j] / bn[j]) : std::sqrt(rn[j]);
+    if (!(relres[j] <= c->opt.tol_solve * 1.0000001) && bn[j] > 0) *ok = false;
+  }
+  return KS_OK;
+}
+
+// S X = B from X (in/out), FP64 or FP32-in-FP64-refinement
+static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precision, double tol,
+                      ks_solve_stats *st) {
+  hipStream_t s = c->s;
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled: call ks_assemble first");
+  ks_solve_stats loc;
+  std::memset(&loc, 0, sizeof(loc));
+  HIPCHK(hipEventRecord(c->ev0, s));
+  int conv = 0, brk = 0;
+  if (precision == KS_PREC_FP64) {
+    int r = pcg_solve<double>(c->N, k, c->rowptr, c->col, c->S, c->diagS, B, X, tol,
+                              c->opt.max_it_solve, c->pw64, loc.iters, loc.relres, &conv, &brk, s);
+    if (r < 0) return fail(KS_ERR_HIP, "PCG launch failed");
+    if (brk) return fail(KS_ERR_BREAKDOWN, "PCG breakdown: p^T S p <= 0 (S not positive definite; increase mu)");
+    loc.refinements = 0;
+  } else {
+    // FP32 operator copy (once per assembly)
+    if (!c->have_S32) {
+      launch_to_float(c->nnz, c->S, c->S32, s);
+      launch_to_float(c->N, c->diagS, c->diagS32, s);
+      c->have_S32 = true;
+    }
+    const int max_ref = 20;
+    std::vector<double> rn(k), bn(k), sc(k);
+    int nb = launch_colnorms(c->N, k, B, c->redpart, s);
+    TRY(reduce_small(c, c->redpart, nb, k, bn.data()));
+    int total_it[MAX_K] = {0};
+    conv = 0;
+    for (int ref = 0; ref < max_ref; ++ref) {
+      // FP64 residual
+      launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, s);
+      nb = launch_colnorms(c->N, k, c->Wv, c->redpart, s);
+      TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
+      loc.refinements = ref + 1;
+      bool all = true;
+      for (int j = 0; j < k; ++j) {
+        const double rel = bn[j] > 0 ? std::sqrt(rn[j] / bn[j]) : 0.0;
+        if (rel > tol) all = false;
+        sc[j] = rn[j] > 0 ? 1.0 / std::sqrt(rn[j]) : 0.0;
+      }
+      if (all) {
+        conv = 1;
+        break;
+      }
+      // scaled FP32 right-hand side, FP32 PCG from zero
+      HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      launch_scale_cols(c->N, k, c->Wv, c->scal, s);
+      launch_to_float((int64_t)c->N * k, c->Wv, c->B32, s);
+      HIPCHK(hipMemsetAsync(c->X32, 0, sizeof(float) * c->N * k, s));
+      int it[MAX_K] = {0};
+      double rr[MAX_K];
+      int c32 = 0;
+      int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->diagS32, c->B32, c->X32,
+                               c->opt.mixed_inner_tol, c->opt.max_it_solve, c->pw32, it, rr, &c32,
+                               &brk, s);
+      if (r < 0) return fail(KS_ERR_HIP, "FP32 PCG launch failed");
+      if (brk) return fail(KS_ERR_BREAKDOWN, "FP32 PCG breakdown");
+      for (int j = 0; j < k; ++j) total_it[j] += it[j];
+      // X += ||r|| d
+      for (int j = 0; j < k; ++j) sc[j] = std::sqrt(rn[j]);
+      HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      launch_refine_update(c->N, k, c->X32, c->scal, X, s);
+    }
+    for (int j = 0; j < k; ++j) loc.iters[j] = total_it[j];
+  }
+  HIPCHK(hipEventRecord(c->ev1, s));
+  bool ok = true;
+  TRY(true_residual(c, B, X, k, loc.relres, &ok));
+  float ms = 0.f;
+  HIPCHK(hipEventSynchronize(c->ev1));
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  loc.seconds = ms * 1e-3;
+  loc.converged = conv ? 1 : 0;
+  if (st) *st = loc;
+  return conv ? KS_OK : KS_NOT_CONVERGED;
+}
+
+extern "C" int ks_block_solve_rhs(ks_ctx *c, const double *B, const double *X0, int32_t k,
+                                  int32_t precision, double tol, double *X, ks_solve_stats *st) {
+  if (!c || !B || !X) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  if (X0) HIPCHK(hipMemcpyAsync(X, X0, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
+  else HIPCHK(hipMemsetAsync(X, 0, sizeof(double) * c->N * k, c->s));
+  return solve_impl(c, B, X, k, precision, tol > 0 ? tol : c->opt.tol_solve, st);
+}
+
+// B = M psi diag(lambda + mu)
+static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, int k, double *B) {
+  launch_spmm(c->N, c->rowptr, c->col, c->M, psi, k, B, k, k, nullptr, 0, 0, c->s);
+  double sc[MAX_K];
+  for (int j = 0; j < k; ++j) sc[j] = lambda_host[j] + c->mu;
+  HIPCHK(hipMemcpyAsync(c->scal, sc, sizeof(double) * k, hipMemcpyHostToDevice, c->s));
+  launch_scale_cols(c->N, k, B, c->scal, c->s);
+  return KS_OK;
+}
+
+extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *lambda_host, int32_t k,
+                              int32_t precision, double *psi_hat, ks_solve_stats *st) {
+  if (!c || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  TRY(build_rhs(c, psi_old, lambda_host, k, c->Bv));
+  if (psi_hat != psi_old)
+    HIPCHK(hipMemcpyAsync(psi_hat, psi_old, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
+  return solve_impl(c, c->Bv, psi_hat, k, precision, c->opt.tol_solve, st);
+}
+
+// -------------------------------------------------------- augmented basis
+// Z[:, N_H : N_H + k] = psi_hat - P G^{-1} P^T M psi_hat ; zero padding after.
+static int build_tail(ks_ctx *c, const double *psi_hat, int k) {
+  hipStream_t s = c->s;
+  const int N = c->N, nH = c->N_H;
+  launch_spmm(N, c->rowptr, c->col, c->M, psi_hat, k, c->Wv, k, k, nullptr, 0, 0, s);
+  launch_gemm_tn(N, nH, k, c->Z, c->mp, c->Wv, k, c->Ctmp, k, c->gwork, c->gwork_n, s);
+  launch_small_gemm(nH, k, nH, c->GPPinv, nH, c->Ctmp, k, c->Ttmp, k, 0.0, s);
+  launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, -1.0, psi_hat, k, c->Z + nH, c->mp, s);
+  if (nH + k < c->mp) launch_zero_cols(N, nH + k, c->mp, c->Z, c->mp, s);
+  return KS_OK;
+}
+
+// F (m x m, ld m) = Z^T H Z with the P-P block taken from PP if given
+static void project_full(ks_ctx *c, const double *H, int m, double *F) {
+  launch_spmm(c->N, c->rowptr, c->col, H, c->Z, c->mp, c->Y, c->mp, c->mp, nullptr, 0, 0, c->s);
+  launch_gemm_tn(c->N, m, m, c->Z, c->mp, c->Y, c->mp, F, m, c->gwork, c->gwork_n, c->s);
+}
+// F from the fixed P-P block and the tail columns Z^T (H psi_tilde)
+static void project_tail(ks_ctx *c, const double *H, const double *PP, int k, double *F) {
+  const int m = c->N_H + k;
+  launch_spmm(c->N, c->rowptr, c->col, H, c->Z + c->N_H, c->mp, c->Wv, k, k, nullptr, 0, 0, c->s);
+  launch_gemm_tn(c->N, m, k, c->Z, c->mp, c->Wv, k, c->Ftail, k, c->gwork, c->gwork_n, c->s);
+  launch_fill_pencil(m, c->N_H, PP, c->Ftail, F, c->s);
+}
+
+extern "C" int ks_augmented_project(ks_ctx *c, const double *psi_hat, int32_t k, int32_t which,
+                                    double *F) {
+  if (!c || !psi_hat || !F) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  const double *H = nullptr;
+  if (which == 0) H = c->M;
+  else if (which == 1) H = c->AL;
+  else if (which == 2) {
+    if (!c->have_S) return fail(KS_ERR_STATE, "no assembly");
+    launch_fill(c->nnz_ext, 0.0, c->MNL, c->s);
+    assemble_potential_all(c, c->vnl_q, c->MNL);
+    H = c->MNL;
+  } else
+    return fail(KS_ERR_ARG, "which must be 0, 1 or 2");
+  TRY(build_tail(c, psi_hat, k));
+  project_full(c, H, c->N_H + k, F);
+  HIPCHK(hipStreamSynchronize(c->s));
+  return KS_OK;
+}
+
+// ---------------------------------------------------------------- eigen
+static int eig_impl(ks_ctx *c, const double *FA, const double *FB, int m, int k, double *U,
+                    std::vector<double> &theta_all, int *rank) {
+  HIPCHK(hipMemsetAsync(c->einfo, 0, 8 * sizeof(int), c->s));
+  launch_small_eig(m, k, FA, m, FB, m, c->eigwork, c->theta, U, c->einfo, c->s);
+  int info[8];
+  theta_all.resize(m);
+  HIPCHK(hipMemcpyAsync(info, c->einfo, sizeof(int) * 8, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * m, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (info[2]) return fail(KS_ERR_EIG, "F_B has a non-positive diagonal entry");
+  if (info[0] < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(info[0]) + " < k");
+  theta_all.resize(info[0]);
+  if (rank) *rank = info[0];
+  return KS_OK;
+}
+
+extern "C" int ks_small_eig(ks_ctx *c, const double *FA, const double *FB, int32_t m, int32_t k,
+                            double *U, double *lambda_host, int32_t *rank_host) {
+  if (!c || !FA || !FB || !U || !lambda_host) return fail(KS_ERR_ARG, "null argument");
+  if (m < 1 || m > 256 || k < 1 || k > m || m > c->mp) return fail(KS_ERR_ARG, "bad sizes");
+  std::vector<double> th;
+  int rank = 0;
+  TRY(eig_impl(c, FA, FB, m, k, U, th, &rank));
+  for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
+  if (rank_host) *rank_host = rank;
+  return KS_OK;
+}
+
+extern "C" int ks_initial_guess(ks_ctx *c, int32_t k, double *psi, double *lambda_host) {
+  if (!c || !psi || !lambda_host) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max || k > c->N_H) return fail(KS_ERR_ARG, "bad k");
+  std::vector<double> th;
+  int rank = 0;
+  TRY(eig_impl(c, c->FAL_PP, c->GPP, c->N_H, k, c->U, th, &rank));
+  launch_ellP_times(c->N, c->Pidx, c->Pw, c->U, k, k, 1.0, nullptr, 0, psi, k, c->s);
+  for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
+  HIPCHK(hipStreamSynchronize(c->s));
+  return KS_OK;
+}
+
+// ---------------------------------------------------------------- SCF step
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Anderson mixing (Sec. 4): coefficients from the normal equations of
+// min ||F~||, new input = rho~_in + beta F~.
+static int solve_small_spd(int n, std::vector<double> A, std::vector<double> b, std::vector<double> &x) {
+  x.assign(n, 0.0);
+  for (int p = 0; p < n; ++p) {
+    int piv = p;
+    for (int r = p + 1; r < n; ++r)
+      if (std::fabs(A[r * n + p]) > std::fabs(A[piv * n + p])) piv = r;
+    if (!(std::fabs(A[piv * n + p]) > 0.0)) return -1;
+    if (piv != p) {
+      for (int j = 0; j < n; ++j) std::swap(A[p * n + j], A[piv * n + j]);
+      std::swap(b[p], b[piv]);
+    }
+    for (int r = p + 1; r < n; ++r) {
+      const double f = A[r * n + p] / A[p * n + p];
+      for (int j = p; j < n; ++j) A[r * n + j] -= f * A[p * n + j];
+      b[r] -= f * b[p];
+    }
+  }
+  for (int p = n - 1; p >= 0; --p) {
+    double t = b[p];
+    for (int j = p + 1; j < n; ++j) t -= A[p * n + j] * x[j];
+    x[p] = t / A[p * n + p];
+  }
+  return 0;
+}
+
+extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t k,
+                           const double *occ_host, int32_t precision, double *rho_q,
+                           ks_step_report *rep) {
+  if (!c || !psi || !lambda_host || !occ_host) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  hipStream_t s = c->s;
+  ks_step_report R;
+  std::memset(&R, 0, sizeof(R));
+  const double t0 = now_s();
+  const int N = c->N, nH = c->N_H, m = nH + k;
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  const bool hartree = c->opt.hartree_mode != KS_HARTREE_OFF;
+  const bool nonlinear = hartree || c->opt.xc_mode != KS_XC_NONE;
+  // 1. S of the input density (w_D frozen from here on)
+  int piters = 0;
+  TRY(assemble_impl(c, psi, k, occ_host, &piters));
+  HIPCHK(hipStreamSynchronize(s));
+  const double t1 = now_s();
+  // 2. BVPs
+  TRY(build_rhs(c, psi, lambda_host, k, c->Bv));
+  HIPCHK(hipMemcpyAsync(c->PsiHat, psi, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
+  int st = solve_impl(c, c->Bv, c->PsiHat, k, precision, c->opt.tol_solve, &R.solve);
+  if (st < 0) return st;
+  R.status_solve = st;
+  const double t2 = now_s();
+  // 3. augmented basis and the fixed blocks of the pencil
+  TRY(build_tail(c, c->PsiHat, k));
+  project_tail(c, c->M, c->GPP, k, c->FB);
+  project_tail(c, c->AL, c->FAL_PP, k, c->FAL);
+  HIPCHK(hipStreamSynchronize(s));
+  const double t3 = now_s();
+  // 4. inner nonlinear iteration
+  HIPCHK(hipMemcpyAsync(c->rho_in, c->rho_l, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->occ_d, occ_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
+  const int depth = c->opt.anderson_depth;
+  int nhist = 0, head = 0;  // ring buffer of (rho_in, F)
+  std::vector<double> th;
+  double res = 0.0;
+  int it = 0, rank = 0;
+  for (it = 0; it < c->opt.max_it_inner; ++it) {
+    if (nonlinear) {
+      if (hartree) {
+        int r = hartree_solve(c, c->rho_in, &piters);
+        if (r < 0) return r;
+      } else {
+        launch_fill(nqt, 0.0, c->vh_q, s);
+      }
+      launch_xc(nqt, c->rho_in, c->opt.xc_mode, c->exc_q, c->vxc_q, s);
+      launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
+      launch_fill(c->nnz_ext, 0.0, c->MNL, s);
+      assemble_potential_all(c, c->vnl_q, c->MNL);
+      project_full(c, c->MNL, m, c->Ctmp);
+      launch_combine3((int64_t)m * m, 1.0, c->FAL, 1.0, c->Ctmp, 0.0, nullptr, c->FA, s);
+    } else {
+      HIPCHK(hipMemcpyAsync(c->FA, c->FAL, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
+    }
+    TRY(eig_impl(c, c->FA, c->FB, m, k, c->U, th, &rank));
+    launch_zu(N, c->Pidx, c->Pw, nH, c->Z, c->mp, k, c->U, k, c->PsiNew, s);
+    launch_density(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->PsiNew, k, k, c->occ_d,
+                   c->rho_out, s);
+    if (!nonlinear) {
+      it += 1;
+      break;
+    }
+    // F_m = rho_out - rho_in into the history ring
+    double *Fm = c->hist_F[head], *Im = c->hist_in[head];
+    launch_combine3(nqt, 1.0, c->rho_out, -1.0, c->rho_in, 0.0, nullptr, Fm, s);
+    HIPCHK(hipMemcpyAsync(Im, c->rho_in, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
+    const int nh = std::min(nhist, depth - 1);  // previous iterates used
+    const double *Fj[4];
+    int jidx[4];
+    for (int j = 0; j < nh; ++j) {
+      // oldest first: j = 0 is the oldest kept
+      jidx[j] = (head - nh + j + depth) % depth;
+      Fj[j] = c->hist_F[jidx[j]];
+    }
+    double g[21];
+    int nb = launch_anderson_gram(nqt, c->n_q, c->absdet, c->qw, Fm, nh, Fj, c->redpart, s);
+    TRY(reduce_small(c, c->redpart, nb, 21, g));
+    res = std::sqrt(std::max(g[0], 0.0));
+    if (res < c->opt.tol_inner) {
+      it += 1;
+      break;
+    }
+    std::vector<double> alpha;
+    if (nh > 0) {
+      std::vector<double> G(nh * nh), b(nh);
+      double tr = 0.0;
+      for (int j = 0; j < nh; ++j) {
+        b[j] = g[1 + j];
+        for (int l = 0; l < nh; ++l) G[j * nh + l] = g[5 + 4 * j + l];
+        tr += G[j * nh + j];
+      }
+      for (int j = 0; j < nh; ++j) G[j * nh + j] += 1e-12 * std::max(tr, 1e-300);
+      if (solve_small_spd(nh, G, b, alpha) < 0) alpha.assign(nh, 0.0);
+    }
+    // new rho_in = sum coef * {in_j, F_j}
+    const double beta = c->opt.anderson_beta;
+    double sa = 0.0;
+    for (int j = 0; j < nh; ++j) sa += alpha[j];
+    double coefs[12];
+    const double *vecs[12];
+    int nv = 0;
+    coefs[nv] = 1.0 - sa; vecs[nv++] = Im;
+    coefs[nv] = beta * (1.0 - sa); vecs[nv++] = Fm;
+    for (int j = 0; j < nh; ++j) {
+      coefs[nv] = alpha[j]; vecs[nv++] = c->hist_in[jidx[j]];
+      coefs[nv] = beta * alpha[j]; vecs[nv++] = c->hist_F[jidx[j]];
+    }
+    HIPCHK(hipMemcpyAsync(c->coef, coefs, sizeof(double) * nv, hipMemcpyHostToDevice, s));
+    launch_lincomb(nqt, nv, c->coef, vecs, c->rho_in, s);
+    head = (head + 1) % depth;
+    nhist = std::min(nhist + 1, depth);
+  }
+  R.inner_iters = it;
+  R.res_inner = res;
+  R.rank = rank;
+  const double t4 = now_s();
+  // 5. outputs and energies
+  HIPCHK(hipMemcpyAsync(psi, c->PsiNew, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
+  if (rho_q) HIPCHK(hipMemcpyAsync(rho_q, c->rho_out, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
+  double band = 0.0;
+  for (int j = 0; j < k; ++j) {
+    lambda_host[j] = th[j];
+    band += occ_host[j] * th[j];
+  }
+  R.E_band = band;
+  R.E_nn = c->E_nn;
+  if (nonlinear) {
+    const double *a[3] = {c->vh_q, c->exc_q, c->vxc_q};
+    const double *b[3] = {c->rho_in, c->rho_in, c->rho_in};
+    double e[3];
+    TRY(weighted_dots(c, 3, a, b, e));
+    R.E_H = 0.5 * e[0];
+    R.E_xc = e[1];
+    R.E_vxc = e[2];
+  }
+  R.E_total = R.E_band - R.E_H - R.E_vxc + R.E_xc + R.E_nn;
+  R.poisson_iters = piters;
+  HIPCHK(hipStreamSynchronize(s));
+  const double t5 = now_s();
+  R.seconds[0] = t1 - t0;
+  R.seconds[1] = t2 - t1;
+  R.seconds[2] = t3 - t2;
+  R.seconds[3] = t4 - t3;
+  R.seconds[4] = t5 - t4;
+  R.seconds[5] = t5 - t0;
+  if (rep) *rep = R;
+  int ret = KS_OK;
+  if ((int)th.size() > k && th[k] - th[k - 1] < 1e-8) ret = KS_WARN_DEGENERATE;
+  if (nonlinear && res >= c->opt.tol_inner) ret = KS_NOT_CONVERGED;
+  if (st == KS_NOT_CONVERGED) ret = KS_NOT_CONVERGED;
+  return ret;
+}

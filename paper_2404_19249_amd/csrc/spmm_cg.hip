@@ -1,0 +1,609 @@
+// Multi-right-hand-side CSR SpMM and the block Jacobi-preconditioned CG of
+// the boundary value problems of Algorithm 3 (eq. Aux_Linear_Problem).
+//
+// Layout: every [N][k] block is row-major with the k right-hand sides
+// contiguous, so the k values of one gathered row form one coalesced
+// segment.  A group of CG = k/VW lanes owns one matrix row, each lane VW
+// consecutive columns; for k = 1 (Hartree Poisson) NG lanes split the
+// nonzeros of a row instead and combine them with cross-lane shuffles.
+//
+// One PCG iteration is three launches:
+//   A  q = S p            and per-column p.q   -> alpha
+//   B  r -= alpha q       and per-column r.z, r.r  -> beta, convergence
+//   C  x += alpha p,  p = D^{-1} r + beta p
+// Per-column scalars live on the device; the last workgroup of each launch
+// (ticket counter) combines the per-block partial sums in a fixed order, so
+// results are bitwise reproducible.  Converged columns are frozen
+// (alpha = 0).  Launches after convergence return at once; the host polls
+// the state every few iterations.
+#include "common.h"
+#include "kernels.h"
+#include <vector>
+#include <algorithm>
+
+namespace ks {
+
+// per-column scalars and control words
+struct ColState {
+  double rz, pq, alpha, beta, rr, bb, rz_new;
+  int active, iters;
+};
+struct Control {
+  int stop;       // set when no column is active (or breakdown)
+  int skip;       // copy of stop taken after the x/p update of the same iteration
+  int breakdown;  // p^T S p <= 0 or NaN in an active column
+  int pad;
+};
+size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
+
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) VecT {
+  T v[VW];
+};
+
+// ------------------------------------------------------------------ mapping
+struct RowMap {
+  int lane, wave, LPR, RPW, slot, cg, ng;
+  bool valid;  // lane owns a (row slot, column group)
+};
+template <int NG>
+__device__ __forceinline__ RowMap row_map(int CG) {
+  RowMap m;
+  m.lane = threadIdx.x & 63;
+  m.wave = threadIdx.x >> 6;
+  m.LPR = CG * NG;
+  m.RPW = 64 / m.LPR;
+  m.slot = m.lane / m.LPR;
+  const int r = m.lane % m.LPR;
+  m.cg = r / NG;
+  m.ng = r % NG;
+  m.valid = m.slot < m.RPW;
+  return m;
+}
+
+// Block reduction of per-lane column partials (VW columns per lane) into
+// part[blockIdx][col] for col < k.  s_red: 256 * VW doubles.
+template <int VW, int NG>
+__device__ __forceinline__ void block_cols(const double (&acc)[VW], const RowMap &m, int k, int CG,
+                                           double *s_red, double *part, int stride, int off) {
+  for (int v = 0; v < VW; ++v) s_red[threadIdx.x * VW + v] = (m.valid && m.ng == 0) ? acc[v] : 0.0;
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    const int cg = c / VW, v = c % VW;
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w)
+      for (int sl = 0; sl < m.RPW; ++sl) s += s_red[(w * 64 + sl * m.LPR + cg * NG) * VW + v];
+    part[(int64_t)blockIdx.x * stride + off + c] = s;
+  }
+  __syncthreads();
+}
+
+// Returns true in every thread of the last block to finish (after a fence).
+__device__ __forceinline__ bool last_block(unsigned int *counter) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(counter, 1u);
+    s_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last;
+}
+
+// ---------------------------------------------------------------- SpMM row
+template <typename T, int VW, int NG>
+__device__ __forceinline__ void row_product(int row, const RowMap &m,
+                                            const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, const T *__restrict__ X,
+                                            int ldx, int k, T (&acc)[VW]) {
+  for (int v = 0; v < VW; ++v) acc[v] = T(0);
+  const int c0 = m.cg * VW;
+  const bool colok = c0 < k;
+  const int jb = rowptr[row], je = rowptr[row + 1];
+  int j = jb + m.ng;
+  // two nonzeros per trip for memory-level parallelism
+  for (; j + NG < je; j += 2 * NG) {
+    const int ca = col[j], cb = col[j + NG];
+    const T va = val[j], vb = val[j + NG];
+    if (colok) {
+      if (VW > 1 && (ldx % VW) == 0) {
+        const VecT<T, VW> xa = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)ca * ldx + c0);
+        const VecT<T, VW> xb = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)cb * ldx + c0);
+        for (int v = 0; v < VW; ++v) acc[v] += va * xa.v[v] + vb * xb.v[v];
+      } else {
+        for (int v = 0; v < VW; ++v)
+          if (c0 + v < k)
+            acc[v] += va * X[(int64_t)ca * ldx + c0 + v] + vb * X[(int64_t)cb * ldx + c0 + v];
+      }
+    }
+  }
+  if (j < je) {
+    const int ca = col[j];
+    const T va = val[j];
+    if (colok) {
+      if (VW > 1 && (ldx % VW) == 0) {
+        const VecT<T, VW> xa = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)ca * ldx + c0);
+        for (int v = 0; v < VW; ++v) acc[v] += va * xa.v[v];
+      } else {
+        for (int v = 0; v < VW; ++v)
+          if (c0 + v < k) acc[v] += va * X[(int64_t)ca * ldx + c0 + v];
+      }
+    }
+  }
+  if (NG > 1) {
+    for (int off = 1; off < NG; off <<= 1)
+      for (int v = 0; v < VW; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void load_row(const T *__restrict__ A, int64_t row, int ld, int c0, int k,
+                                         T (&x)[VW]) {
+  if (VW > 1 && (ld % VW) == 0 && c0 + VW <= k) {
+    const VecT<T, VW> t = *reinterpret_cast<const VecT<T, VW> *>(A + row * ld + c0);
+    for (int v = 0; v < VW; ++v) x[v] = t.v[v];
+  } else {
+    for (int v = 0; v < VW; ++v) x[v] = (c0 + v < k) ? A[row * ld + c0 + v] : T(0);
+  }
+}
+template <typename T, int VW>
+__device__ __forceinline__ void store_row(T *__restrict__ A, int64_t row, int ld, int c0, int k,
+                                          const T (&x)[VW]) {
+  if (VW > 1 && (ld % VW) == 0 && c0 + VW <= k) {
+    VecT<T, VW> t;
+    for (int v = 0; v < VW; ++v) t.v[v] = x[v];
+    *reinterpret_cast<VecT<T, VW> *>(A + row * ld + c0) = t;
+  } else {
+    for (int v = 0; v < VW; ++v)
+      if (c0 + v < k) A[row * ld + c0 + v] = x[v];
+  }
+}
+
+// -------------------------------------------------------- generic SpMM
+template <typename T, int VW, int NG>
+__global__ void __launch_bounds__(256) k_spmm(int N, const int32_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col,
+                                              const T *__restrict__ val, const T *__restrict__ X,
+                                              int ldx, T *__restrict__ Y, int ldy, int k, int CG,
+                                              const T *__restrict__ B, int ldb, int mode) {
+  const RowMap m = row_map<NG>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
+       row += gridDim.x * rows_per_block) {
+    // uniform trip count per wave: every lane of a row group stays in the loop
+    const int base = row - m.slot;
+    if (base >= N) break;
+    const bool rv = m.valid && row < N;
+    T acc[VW];
+    if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, ldx, k, acc);
+    else {
+      for (int v = 0; v < VW; ++v) acc[v] = T(0);
+      if (NG > 1)
+        for (int off = 1; off < NG; off <<= 1)
+          for (int v = 0; v < VW; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+    }
+    if (rv && m.ng == 0 && m.cg * VW < k) {
+      if (mode == 1) {
+        T b[VW];
+        load_row<T, VW>(B, row, ldb, m.cg * VW, k, b);
+        for (int v = 0; v < VW; ++v) acc[v] = b[v] - acc[v];
+      }
+      store_row<T, VW>(Y, row, ldy, m.cg * VW, k, acc);
+    }
+  }
+}
+
+struct Shape {
+  int VW, CG, NG;
+};
+static Shape pick_shape(int k, int ld) {
+  Shape s;
+  if (k == 1) {
+    s.VW = 1; s.CG = 1; s.NG = 8;
+    return s;
+  }
+  if (k % 4 == 0 && ld % 4 == 0 && k / 4 <= 64) s.VW = 4;
+  else if (k % 2 == 0 && ld % 2 == 0 && k / 2 <= 64) s.VW = 2;
+  else s.VW = 1;
+  if (k > 64 * s.VW) s.VW = 4;  // wide blocks: VW=4 covers up to 256 columns
+  s.CG = (k + s.VW - 1) / s.VW;
+  s.NG = 1;
+  return s;
+}
+static int grid_rows(int N, int RPW, int cap = 4096) {
+  int rows_per_block = 4 * RPW;
+  int b = (N + rows_per_block - 1) / rows_per_block;
+  return std::max(1, std::min(b, cap));
+}
+
+template <typename T>
+static void spmm_dispatch(int N, const int32_t *rowptr, const int32_t *col, const T *val, const T *X,
+                          int ldx, T *Y, int ldy, int k, const T *B, int ldb, int mode,
+                          hipStream_t s) {
+  if (N <= 0 || k <= 0) return;
+  Shape sh = pick_shape(k, std::min(ldx, ldy));
+  // vector loads need VW-aligned rows: drop to scalar access otherwise
+  auto aligned = [&](const void *p, int ld) {
+    return p == nullptr || ((reinterpret_cast<uintptr_t>(p) % (sizeof(T) * sh.VW)) == 0 &&
+                            (ld % sh.VW) == 0);
+  };
+  if (sh.VW > 1 && (!aligned(X, ldx) || !aligned(Y, ldy) || (mode == 1 && !aligned(B, ldb)))) {
+    if (k > 64) sh = Shape{4, (k + 3) / 4, 1};  // wide: scalar fallback inside the kernel
+    else sh = Shape{1, k, 1};
+  }
+  if (sh.CG > 64) sh = Shape{4, (k + 3) / 4, 1};
+  const int RPW = 64 / (sh.CG * sh.NG);
+  dim3 g(grid_rows(N, RPW)), b(256);
+  if (sh.NG == 8)
+    hipLaunchKernelGGL((k_spmm<T, 1, 8>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, 1, B,
+                       ldb, mode);
+  else if (sh.VW == 4)
+    hipLaunchKernelGGL((k_spmm<T, 4, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
+                       B, ldb, mode);
+  else if (sh.VW == 2)
+    hipLaunchKernelGGL((k_spmm<T, 2, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
+                       B, ldb, mode);
+  else
+    hipLaunchKernelGGL((k_spmm<T, 1, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
+                       B, ldb, mode);
+}
+
+void launch_spmm(int N, const int32_t *rowptr, const int32_t *col, const double *val,
+                 const double *X, int ldx, double *Y, int ldy, int k, const double *B, int ldb,
+                 int mode, hipStream_t s) {
+  spmm_dispatch<double>(N, rowptr, col, val, X, ldx, Y, ldy, k, B, ldb, mode, s);
+}
+void launch_spmm_f32(int N, const int32_t *rowptr, const int32_t *col, const float *val,
+                     const float *X, float *Y, int k, hipStream_t s) {
+  spmm_dispatch<float>(N, rowptr, col, val, X, k, Y, k, k, nullptr, k, 0, s);
+}
+
+__global__ void k_scale_cols(int64_t n, int k, double *__restrict__ Y, const double *__restrict__ sc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Y[i] *= sc[i % k];
+}
+void launch_scale_cols(int N, int k, double *Y, const double *scale_dev, hipStream_t s) {
+  int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)),
+                       dim3(256), 0, s, n, k, Y, scale_dev);
+}
+
+__global__ void k_refine_update(int64_t n, int k, const float *__restrict__ D,
+                                const double *__restrict__ sc, double *__restrict__ X) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    X[i] += sc[i % k] * (double)D[i];
+}
+void launch_refine_update(int N, int k, const float *D, const double *scale, double *X, hipStream_t s) {
+  int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_refine_update, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)),
+                       dim3(256), 0, s, n, k, D, scale, X);
+}
+
+// ================================================================== PCG
+// I: R = B - S X, P = D^{-1} R; partials of b.b, r.r, r.z
+template <typename T, int VW, int NG>
+__global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
+                                                  const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const T *__restrict__ val,
+                                                  const T *__restrict__ diag,
+                                                  const T *__restrict__ Bm, const T *__restrict__ X,
+                                                  T *__restrict__ R, T *__restrict__ P,
+                                                  double *__restrict__ part, Control *ctl,
+                                                  ColState *cs, unsigned int *counter, double tol) {
+  __shared__ double s_red[256 * VW];
+  const RowMap m = row_map<NG>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  double abb[VW], arr[VW], arz[VW];
+  for (int v = 0; v < VW; ++v) abb[v] = arr[v] = arz[v] = 0.0;
+  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
+       row += gridDim.x * rows_per_block) {
+    const int base = row - m.slot;
+    if (base >= N) break;
+    const bool rv = m.valid && row < N;
+    T acc[VW];
+    if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, k, k, acc);
+    else {
+      for (int v = 0; v < VW; ++v) acc[v] = T(0);
+      if (NG > 1)
+        for (int off = 1; off < NG; off <<= 1)
+          for (int v = 0; v < VW; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+    }
+    if (rv && m.ng == 0 && m.cg * VW < k) {
+      T b[VW], r[VW], p[VW];
+      load_row<T, VW>(Bm, row, k, m.cg * VW, k, b);
+      const T d = diag[row];
+      for (int v = 0; v < VW; ++v) {
+        r[v] = b[v] - acc[v];
+        p[v] = r[v] / d;
+        abb[v] += (double)b[v] * (double)b[v];
+        arr[v] += (double)r[v] * (double)r[v];
+        arz[v] += (double)r[v] * (double)p[v];
+      }
+      store_row<T, VW>(R, row, k, m.cg * VW, k, r);
+      store_row<T, VW>(P, row, k, m.cg * VW, k, p);
+    }
+  }
+  block_cols<VW, NG>(abb, m, k, CG, s_red, part, 3 * k, 0);
+  block_cols<VW, NG>(arr, m, k, CG, s_red, part, 3 * k, k);
+  block_cols<VW, NG>(arz, m, k, CG, s_red, part, 3 * k, 2 * k);
+  if (last_block(counter)) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      double bb = 0.0, rr = 0.0, rz = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) {
+        bb += part[(int64_t)b * 3 * k + c];
+        rr += part[(int64_t)b * 3 * k + k + c];
+        rz += part[(int64_t)b * 3 * k + 2 * k + c];
+      }
+      ColState st;
+      st.bb = bb; st.rr = rr; st.rz = rz; st.rz_new = rz;
+      st.pq = 0.0; st.alpha = 0.0; st.beta = 0.0; st.iters = 0;
+      st.active = (bb > 0.0) && (rr > tol * tol * bb);
+      cs[c] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int any = 0;
+      for (int c = 0; c < k; ++c) any |= cs[c].active;
+      ctl->stop = !any;
+      ctl->skip = !any;
+      ctl->breakdown = 0;
+      *counter = 0u;
+    }
+  }
+}
+
+// A: Q = S P, partial p.q -> alpha
+template <typename T, int VW, int NG>
+__global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ val, const T *__restrict__ P,
+                                               T *__restrict__ Q, double *__restrict__ part,
+                                               Control *ctl, ColState *cs, unsigned int *counter) {
+  if (ctl->skip) return;
+  __shared__ double s_red[256 * VW];
+  const RowMap m = row_map<NG>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  double apq[VW];
+  for (int v = 0; v < VW; ++v) apq[v] = 0.0;
+  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
+       row += gridDim.x * rows_per_block) {
+    const int base = row - m.slot;
+    if (base >= N) break;
+    const bool rv = m.valid && row < N;
+    T acc[VW];
+    if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, P, k, k, acc);
+    else {
+      for (int v = 0; v < VW; ++v) acc[v] = T(0);
+      if (NG > 1)
+        for (int off = 1; off < NG; off <<= 1)
+          for (int v = 0; v < VW; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+    }
+    if (rv && m.ng == 0 && m.cg * VW < k) {
+      T p[VW];
+      load_row<T, VW>(P, row, k, m.cg * VW, k, p);
+      for (int v = 0; v < VW; ++v) apq[v] += (double)p[v] * (double)acc[v];
+      store_row<T, VW>(Q, row, k, m.cg * VW, k, acc);
+    }
+  }
+  block_cols<VW, NG>(apq, m, k, CG, s_red, part, k, 0);
+  if (last_block(counter)) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      double pq = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) pq += part[(int64_t)b * k + c];
+      ColState st = cs[c];
+      st.pq = pq;
+      if (st.active) {
+        if (!(pq > 0.0)) {
+          ctl->breakdown = 1;
+          st.alpha = 0.0;
+        } else {
+          st.alpha = st.rz / pq;
+        }
+      } else {
+        st.alpha = 0.0;
+      }
+      cs[c] = st;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
+// B: R -= alpha Q; partials r.z and r.r -> beta, convergence
+template <typename T, int VW>
+__global__ void __launch_bounds__(256) k_pcg_B(int N, int k, int CG, const T *__restrict__ diag,
+                                               const T *__restrict__ Q, T *__restrict__ R,
+                                               double *__restrict__ part, Control *ctl,
+                                               ColState *cs, unsigned int *counter, double tol) {
+  if (ctl->skip) return;
+  __shared__ double s_red[256 * VW];
+  __shared__ double s_alpha[MAX_K];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) s_alpha[c] = cs[c].alpha;
+  __syncthreads();
+  const RowMap m = row_map<1>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  double arz[VW], arr[VW];
+  for (int v = 0; v < VW; ++v) arz[v] = arr[v] = 0.0;
+  const int c0 = m.cg * VW;
+  T al[VW];
+  for (int v = 0; v < VW; ++v) al[v] = (c0 + v < k) ? (T)s_alpha[c0 + v] : T(0);
+  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; row < N;
+       row += gridDim.x * rows_per_block) {
+    if (!m.valid || c0 >= k) continue;
+    T q[VW], r[VW];
+    load_row<T, VW>(Q, row, k, c0, k, q);
+    load_row<T, VW>(R, row, k, c0, k, r);
+    const T d = diag[row];
+    for (int v = 0; v < VW; ++v) {
+      r[v] -= al[v] * q[v];
+      arr[v] += (double)r[v] * (double)r[v];
+      arz[v] += (double)r[v] * (double)(r[v] / d);
+    }
+    store_row<T, VW>(R, row, k, c0, k, r);
+  }
+  block_cols<VW, 1>(arz, m, k, CG, s_red, part, 2 * k, 0);
+  block_cols<VW, 1>(arr, m, k, CG, s_red, part, 2 * k, k);
+  if (last_block(counter)) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      double rz = 0.0, rr = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) {
+        rz += part[(int64_t)b * 2 * k + c];
+        rr += part[(int64_t)b * 2 * k + k + c];
+      }
+      ColState st = cs[c];
+      if (st.active) {
+        st.beta = rz / st.rz;
+        st.rz = rz;
+        st.rr = rr;
+        st.iters += 1;
+        if (!(rr > tol * tol * st.bb)) st.active = 0;
+      } else {
+        st.beta = 0.0;
+      }
+      cs[c] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int any = 0;
+      for (int c = 0; c < k; ++c) any |= cs[c].active;
+      ctl->stop = (!any) || ctl->breakdown;
+      *counter = 0u;
+    }
+  }
+}
+
+// C: X += alpha P ; P = D^{-1} R + beta P
+template <typename T, int VW>
+__global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__restrict__ diag,
+                                               const T *__restrict__ R, T *__restrict__ X,
+                                               T *__restrict__ P, Control *ctl, ColState *cs,
+                                               unsigned int *counter) {
+  if (ctl->skip) return;
+  __shared__ double s_ab[2 * MAX_K];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    s_ab[c] = cs[c].alpha;
+    s_ab[MAX_K + c] = cs[c].beta;
+  }
+  __syncthreads();
+  const RowMap m = row_map<1>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  const int c0 = m.cg * VW;
+  T al[VW], be[VW];
+  for (int v = 0; v < VW; ++v) {
+    al[v] = (c0 + v < k) ? (T)s_ab[c0 + v] : T(0);
+    be[v] = (c0 + v < k) ? (T)s_ab[MAX_K + c0 + v] : T(0);
+  }
+  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; row < N;
+       row += gridDim.x * rows_per_block) {
+    if (!m.valid || c0 >= k) continue;
+    T x[VW], p[VW], r[VW];
+    load_row<T, VW>(X, row, k, c0, k, x);
+    load_row<T, VW>(P, row, k, c0, k, p);
+    load_row<T, VW>(R, row, k, c0, k, r);
+    const T d = diag[row];
+    for (int v = 0; v < VW; ++v) {
+      x[v] += al[v] * p[v];
+      p[v] = r[v] / d + be[v] * p[v];
+    }
+    store_row<T, VW>(X, row, k, c0, k, x);
+    store_row<T, VW>(P, row, k, c0, k, p);
+  }
+  if (last_block(counter)) {
+    if (threadIdx.x == 0) {
+      ctl->skip = ctl->stop;
+      *counter = 0u;
+    }
+  }
+}
+
+template <typename T, int VW, int NG>
+static void pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
+                             const int32_t *col, const T *val, const T *diag, T *X, T *R, T *P,
+                             T *Q, double *part, Control *ctl, ColState *cs, unsigned int *cnt,
+                             double tol, int iters, hipStream_t s) {
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
+                       P, Q, part, ctl, cs, cnt);
+    hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
+                       ctl, cs, cnt + 1, tol);
+    hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
+                       cs, cnt + 2);
+  }
+}
+
+template <typename T, int VW, int NG>
+static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
+                   const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w,
+                   int *iters_out, double *relres_out, int *converged_out, int *breakdown_out,
+                   hipStream_t s) {
+  const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
+  const int RPWA = 64 / (CG * NG);
+  const int RPWE = 64 / CG;
+  const int nblkA = std::min(grid_rows(N, RPWA, 2048), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, 2048), w.nblk_max);
+  Control *ctl = reinterpret_cast<Control *>(w.state);
+  ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
+  T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
+  double *part = reinterpret_cast<double *>(w.part);
+  hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
+                     diag, B, X, R, P, part, ctl, cs, w.counter, tol);
+  std::vector<ColState> hcs(k);
+  Control hctl;
+  int done_iters = 0, chunk = 4;
+  for (;;) {
+    if (hipMemcpyAsync(&hctl, ctl, sizeof(Control), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
+    if (hipStreamSynchronize(s) != hipSuccess) return -2;
+    if (hctl.stop || done_iters >= max_iter) break;
+    int n = std::min(chunk, max_iter - done_iters);
+    pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, diag, X, R, P, Q, part, ctl,
+                                cs, w.counter + 1, tol, n, s);
+    done_iters += n;
+    chunk = std::min(chunk * 2, 32);
+  }
+  if (hipMemcpyAsync(hcs.data(), cs, sizeof(ColState) * k, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return -2;
+  if (hipStreamSynchronize(s) != hipSuccess) return -2;
+  int conv = 1;
+  for (int c = 0; c < k; ++c) {
+    if (iters_out) iters_out[c] = hcs[c].iters;
+    if (relres_out) relres_out[c] = hcs[c].bb > 0 ? sqrt(hcs[c].rr / hcs[c].bb) : 0.0;
+    if (hcs[c].active) conv = 0;
+  }
+  if (converged_out) *converged_out = conv;
+  if (breakdown_out) *breakdown_out = hctl.breakdown;
+  return 0;
+}
+
+template <typename T>
+int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
+              const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
+              double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s) {
+  if (k == 1)
+    return pcg_run<T, 1, 8>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                            relres_out, converged_out, breakdown_out, s);
+  if (k % 4 == 0)
+    return pcg_run<T, 4, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                            relres_out, converged_out, breakdown_out, s);
+  if (k % 2 == 0)
+    return pcg_run<T, 2, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                            relres_out, converged_out, breakdown_out, s);
+  return pcg_run<T, 1, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                          relres_out, converged_out, breakdown_out, s);
+}
+
+template int pcg_solve<double>(int, int, const int32_t *, const int32_t *, const double *,
+                               const double *, const double *, double *, double, int, PCGWork &,
+                               int *, double *, int *, int *, hipStream_t);
+template int pcg_solve<float>(int, int, const int32_t *, const int32_t *, const float *,
+                              const float *, const float *, float *, double, int, PCGWork &, int *,
+                              double *, int *, int *, hipStream_t);
+
+}  // namespace ks
