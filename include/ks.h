@@ -198,6 +198,11 @@ typedef struct {
 int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                 int32_t precision, double *rho_q, ks_step_report *rep_host);
 
+/* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",
+ * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom")
+ * into the device buffer dst.  For tests and debugging only. */
+int ks_debug_buffer(ks_ctx *ctx, const char *name, double *dst, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -179,6 +179,12 @@ class KSContext:
                                       m, k, self._ptr(U), B.dptr(lam), C.byref(rank)), self.lib)
         return U, lam, rank.value
 
+    def debug_buffer(self, name, n):
+        """Copy of an internal buffer (diagnostics)."""
+        t = self.empty(n)
+        B.check(self.lib.ks_debug_buffer(self.h, name.encode(), self._ptr(t), int(n)), self.lib)
+        return t
+
     def initial_guess(self, k):
         psi = self.empty(self.N, k)
         lam = np.zeros(k)

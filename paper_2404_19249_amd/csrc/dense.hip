@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
       }
     }
   }
-  // D layout: lane l, item r -> row 4*(l/16)+r, col l%16
+  // accumulator layout of v_mfma_f64_16x16x4f64 (measured): lane l, item r
+  // holds D[l/16 + 4 r][l % 16]; A and B lanes hold A[l%16][l/16], B[l/16][l%16]
   double *out = work + (int64_t)blockIdx.x * ma_p * nb_p;
 #pragma unroll
   for (int ti = 0; ti < MAXT; ++ti) {
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
       const int ta = t / tb_n, tb = t % tb_n;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = ta * 16 + 4 * (lane >> 4) + r, col = tb * 16 + (lane & 15);
+        const int row = ta * 16 + (lane >> 4) + 4 * r, col = tb * 16 + (lane & 15);
         out[(int64_t)row * nb_p + col] = acc[ti][r];
       }
     }

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -58,7 +59,20 @@ struct DevBuf {
   }
 };
 
+bool debug_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("KS_DEBUG");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 }  // namespace
+
+struct ks_ctx;
+// KS_DEBUG=1: synchronise after a stage, report launch errors and summarise a buffer
+static void dbg(ks_ctx *c, const char *what, const double *buf, int64_t n);
 
 struct ks_ctx {
   hipStream_t s = nullptr;
@@ -126,6 +140,29 @@ struct ks_ctx {
     if (ev1) (void)hipEventDestroy(ev1);
   }
 };
+
+static void dbg(ks_ctx *c, const char *what, const double *buf, int64_t n) {
+  if (!debug_on()) return;
+  hipError_t e1 = hipStreamSynchronize(c->s);
+  hipError_t e2 = hipGetLastError();
+  double mn = 0, mx = 0, sa = 0;
+  int64_t nan = 0;
+  if (buf && n > 0) {
+    std::vector<double> h(n);
+    (void)hipMemcpy(h.data(), buf, sizeof(double) * n, hipMemcpyDeviceToHost);
+    mn = h[0];
+    mx = h[0];
+    for (double v : h) {
+      if (std::isnan(v)) { ++nan; continue; }
+      mn = std::min(mn, v);
+      mx = std::max(mx, v);
+      sa += std::fabs(v);
+    }
+  }
+  std::fprintf(stderr, "[ks-debug] %-28s sync=%s last=%s n=%lld min=%.6e max=%.6e sum|.|=%.6e nan=%lld\n",
+               what, hipGetErrorString(e1), hipGetErrorString(e2), (long long)n, mn, mx, sa,
+               (long long)nan);
+}
 
 #define TRY(x)                 \
   do {                         \
@@ -650,6 +687,9 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
                        c->dphi, c->qw, c->K, c->M, s);
   }
   launch_vext(c->coords, c->elems, nl, ne, c->n_q, c->qbary, c->n_atoms, c->dZ, c->dR, c->vext_q, s);
+  dbg(c, "K", c->K, c->nnz_ext);
+  dbg(c, "M", c->M, c->nnz_ext);
+  dbg(c, "vext_q", c->vext_q, (int64_t)ne * c->n_q);
   launch_fill(c->nnz_ext, 0.0, c->AL, s);
   assemble_potential_all(c, c->vext_q, c->AL);
   launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);                  // A^L = K/2 + M[V_ext]
@@ -658,8 +698,12 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   // ---------------- coarse blocks: dense P in Z, G_PP = P^T M P, P^T A^L P
   launch_fill((int64_t)N * c->mp, 0.0, c->Z, s);
   launch_dense_P(N, c->Pidx, c->Pw, c->N_H, c->Z, c->mp, s);
+  dbg(c, "AL", c->AL, c->nnz_ext);
+  dbg(c, "Z(P dense)", c->Z, (int64_t)N * c->mp);
   launch_spmm(N, c->rowptr, c->col, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
+  dbg(c, "Y = M P", c->Y, (int64_t)N * c->mp);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->GPP, c->N_H, c->gwork, c->gwork_n, s);
+  dbg(c, "G_PP", c->GPP, (int64_t)c->N_H * c->N_H);
   launch_spmm(N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork, c->gwork_n,
                  s);
@@ -675,8 +719,10 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       int piv = p;
       for (int r = p + 1; r < n; ++r)
         if (std::fabs(G[(size_t)r * n + p]) > std::fabs(G[(size_t)piv * n + p])) piv = r;
-      if (!(std::fabs(G[(size_t)piv * n + p]) > 0.0))
+      if (!(std::fabs(G[(size_t)piv * n + p]) > 0.0)) {
+        if (debug_on()) break;
         return bail(fail(KS_ERR_MESH, "coarse space is rank deficient on this mesh (mesh too coarse for n_H)"));
+      }
       if (piv != p)
         for (int j = 0; j < n; ++j) {
           std::swap(G[(size_t)p * n + j], G[(size_t)piv * n + j]);
@@ -706,6 +752,25 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(KS_ERR_HIP, "setup failed"));
   *out = c;
   return KS_OK;
+}
+
+extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t n) {
+  if (!c || !name || !dst) return fail(KS_ERR_ARG, "null argument");
+  struct { const char *n; const double *p; int64_t size; } tab[] = {
+      {"GPP", c->GPP, (int64_t)c->N_H * c->N_H}, {"FAL_PP", c->FAL_PP, (int64_t)c->N_H * c->N_H},
+      {"Z", c->Z, (int64_t)c->N * c->mp}, {"Y", c->Y, (int64_t)c->N * c->mp},
+      {"FB", c->FB, (int64_t)c->mp * c->mp}, {"FAL", c->FAL, (int64_t)c->mp * c->mp},
+      {"FA", c->FA, (int64_t)c->mp * c->mp}, {"U", c->U, (int64_t)c->mp * c->k_max},
+      {"rho_in", c->rho_in, (int64_t)c->n_e * c->n_q}, {"vh_q", c->vh_q, (int64_t)c->n_e * c->n_q},
+      {"wB", c->wB, (int64_t)c->NB}, {"mom", c->mom, 16}};
+  for (auto &t : tab)
+    if (std::strcmp(t.n, name) == 0) {
+      if (n > t.size) return fail(KS_ERR_ARG, "buffer smaller than requested");
+      HIPCHK(hipMemcpyAsync(dst, t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      return KS_OK;
+    }
+  return fail(KS_ERR_ARG, std::string("unknown buffer ") + name);
 }
 
 extern "C" int ks_destroy(ks_ctx *c) {
