@@ -1,0 +1,187 @@
+"""Benchmark: block BVP solve of the augmented subspace step on one MI355X.
+
+A step is one iteration of Algorithm 3 (assemble S from the density,
+solve the N_occ boundary value problems, project onto the augmented space,
+nonlinear inner iteration with the small eigensolve, energies) on the
+"mixed" workload: 10 nuclei, 64^3 hexahedra -> P2 tetrahedra
+(N = 2,048,383 unknowns), N_occ = 24, moved mesh.  The headline value is
+DOF*RHS/s of the block BVP solve to a 1e-8 relative residual, measured with
+HIP events inside the timed steps; the FP64 and the mixed (FP32 PCG inside
+FP64 refinement) forms are both measured.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed|fp64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF*RHS/s of block BVP solve to 1e-8 residual; mixed vs FP64; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmm_bytes(N, nnz, k, sv):
+    """Algorithmic HBM bytes of one SpMM phase launch (q = S p with the p.q
+    reduction): matrix values + column indices + row pointers, the gathered
+    block p read once, q written once."""
+    return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * k * sv
+
+
+def cg_iteration_bytes(N, nnz, k, sv):
+    """Algorithmic bytes of one block-PCG iteration (three launches):
+    SpMM (matrix, read p, write q), r update (read r, q, write r), x/p update
+    (read x, p, r, write x, p), diagonal read twice."""
+    return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 10 * N * k * sv
+
+
+def cpu_baseline(k):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    the mixed workload's nuclei and mesh recipe at 32^3 hexahedra, one block
+    solve of the k boundary value problems to 1e-8."""
+    from threadpoolctl import threadpool_limits
+    from ks_inputs import make_workload
+    from oracle.step import KSProblem, initial_guess, block_solve
+    w = make_workload("mixed", n=32, k=k)
+    with threadpool_limits(1):
+        p = KSProblem.from_workload(w)
+        th, Psi = initial_guess(p, w.k)
+        S = (p.A_linear() + p.mu * p.M_II).tocsr()
+        t0 = time.perf_counter()
+        X, its, rr = block_solve(p, S, Psi, th, tol=1e-8)
+        dt = time.perf_counter() - t0
+    return {"value": p.N * w.k / dt, "unit": "DOF*RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"mixed workload recipe at 32^3 hexes P2 (N={p.N}, k={w.k}, nnz={p.K_II.nnz}):"
+                      f" one FP64 block Jacobi-PCG solve to 1e-8, {int(max(its))} iterations,"
+                      f" {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--workload", default="mixed")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sharded "
+              "multi-GPU path is design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from ks_inputs import make_workload
+    from paper_2404_19249_amd import KSContext
+
+    t_setup = time.perf_counter()
+    w = make_workload(args.workload, n=args.n)
+    k = w.k
+    ctx = KSContext.from_workload(w, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
+    N, nnz = ctx.N, ctx.nnz
+    log(f"[bench] {w.name}: N={N} nnz={nnz} k={k} colours={ctx.n_colours} mu={ctx.mu:.1f} "
+        f"setup {time.perf_counter() - t_setup:.1f}s")
+    psi, lam = ctx.initial_guess(k)
+    occ = w.occ
+    for i in range(args.warmup):
+        lam, rep = ctx.scf_step(psi, lam, occ, precision=args.precision)
+        log(f"[bench] warmup step {i}: inner {rep['inner_iters']} solve iters "
+            f"{max(rep['solve']['iters'])} {rep['seconds'][5]:.3f}s")
+    # ------------------------------------------------------------ timed steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solve_s, reps = 0.0, []
+    psi_in, lam_in = psi.clone(), lam.copy()
+    for i in range(args.steps):
+        lam, rep = ctx.scf_step(psi, lam, occ, precision=args.precision)
+        solve_s += rep["solve"]["seconds"]
+        reps.append(rep)
+        log(f"[bench] step {i}: E={rep['E_total']:.8f} inner={rep['inner_iters']} "
+            f"solve={rep['solve']['seconds'] * 1e3:.2f}ms iters={max(rep['solve']['iters'])} "
+            f"refine={rep['solve']['refinements']} total={rep['seconds'][5]:.3f}s")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = N * k * args.steps / solve_s
+
+    # ------------------------------------- both forms on the same inputs
+    ctx.assemble(psi_in, occ, want_fields=False)
+    forms = {}
+    for prec in ("fp64", "mixed"):
+        times, st = [], None
+        for r in range(3):
+            out, st = ctx.block_solve(psi_in, lam_in, prec)
+            times.append(st["seconds"])
+        t = float(np.median(times))
+        forms[prec] = {"dof_rhs_per_s": N * k / t, "ms": t * 1e3,
+                       "iters_max": int(max(st["iters"])), "refinements": st["refinements"],
+                       "relres_max": float(max(st["relres"]))}
+    # eigenvalue accuracy of one step in each form against a tightly solved FP64 step
+    lam_of = {}
+    for key in ("fp64", "mixed"):
+        lam_of[key], _ = ctx.scf_step(psi_in.clone(), lam_in, occ, precision=key)
+    ref_ctx = KSContext.from_workload(w, tol_solve=1e-12, tol_inner=1e-8, tol_poisson=1e-10)
+    lam_of["ref"], _ = ref_ctx.scf_step(psi_in.clone(), lam_in, occ, precision="fp64")
+    ref_ctx.close()
+    for key in ("fp64", "mixed"):
+        forms[key]["eig_err_vs_fp64_tight_Ha"] = float(np.abs(lam_of[key] - lam_of["ref"]).max())
+    forms["mixed_speedup"] = forms["fp64"]["ms"] / forms["mixed"]["ms"]
+    ctx.assemble(psi_in, occ, want_fields=False)
+
+    # ------------------------------------------- roofline of the SpMM phase
+    ctx.block_solve(psi_in, lam_in, "mixed")   # leaves the FP32 operator and workspace
+    sv = 4 if args.precision == "mixed" else 8
+    which = 3 if args.precision == "mixed" else 0
+    ms_a = ctx.time_kernel(which, k, args.reps)
+    ms_b = ctx.time_kernel(which + 1, k, args.reps)
+    ms_c = ctx.time_kernel(which + 2, k, args.reps)
+    ms_a64 = ctx.time_kernel(0, k, args.reps)
+    bytes_a = spmm_bytes(N, nnz, k, sv)
+    ach = bytes_a / (ms_a * 1e-3) / 1e9
+    roof = {"kernel": f"k_pcg_A<{'float' if sv == 4 else 'double'}> (q = S p, p.q), k={k}",
+            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": bytes_a, "ms_per_launch": ms_a}
+    it_bytes = cg_iteration_bytes(N, nnz, k, sv)
+    phases = {"spmm_ms": ms_a, "r_update_ms": ms_b, "xp_update_ms": ms_c,
+              "iteration_GBs": it_bytes / ((ms_a + ms_b + ms_c) * 1e-3) / 1e9,
+              "fp64_spmm_ms": ms_a64,
+              "fp64_spmm_GBs": spmm_bytes(N, nnz, k, 8) / (ms_a64 * 1e-3) / 1e9}
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF*RHS/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.atoms.M} nuclei, {w.mesh.n}^3 hexes P{w.mesh.order} "
+                               f"tets, moved mesh, N={N}, k={k}, nnz={nnz}",
+                   "N": N, "k": k, "nnz": nnz, "precision": args.precision, "mu": ctx.mu,
+                   "value_basis": "N*k / device time of the block solve inside each timed step"},
+        "roofline": roof,
+        "pcg_phases": phases,
+        "block_solve": forms,
+        "step": {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
+                 "inner_iters": [r["inner_iters"] for r in reps],
+                 "poisson_iters": [r["poisson_iters"] for r in reps],
+                 "seconds_split": {n: float(np.mean([r["seconds"][i] for r in reps]))
+                                   for i, n in enumerate(["assemble", "solve", "project", "inner",
+                                                          "energies", "total"])}},
+    }
+    ctx.close()
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,14 @@ typedef struct {
 int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                 int32_t precision, double *rho_q, ks_step_report *rep_host);
 
+/* Measurement: mean duration (ms, HIP events on the context stream) of
+ * `reps` back-to-back launches of one block-PCG phase in the launch
+ * configuration the solver uses, on the current operator S and workspace:
+ * which = 0 SpMM phase q = S p with the p.q reduction (FP64, k columns),
+ * 1 residual update, 2 x/p update; 3..5 the same phases in FP32 (mixed form);
+ * 6 the Hartree Poisson SpMM phase (k = 1).  Requires a prior ks_assemble. */
+int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
+
 /* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",
  * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom")
  * into the device buffer dst.  For tests and debugging only. */

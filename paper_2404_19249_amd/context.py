@@ -179,6 +179,12 @@ class KSContext:
                                       m, k, self._ptr(U), B.dptr(lam), C.byref(rank)), self.lib)
         return U, lam, rank.value
 
+    def time_kernel(self, which, k, reps=20):
+        """Mean launch duration (ms) of a block-PCG phase; see ks_time_kernel."""
+        ms = C.c_double()
+        B.check(self.lib.ks_time_kernel(self.h, int(which), int(k), int(reps), C.byref(ms)), self.lib)
+        return ms.value
+
     def debug_buffer(self, name, n):
         """Copy of an internal buffer (diagnostics)."""
         t = self.empty(n)

@@ -773,6 +773,34 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
   return fail(KS_ERR_ARG, std::string("unknown buffer ") + name);
 }
 
+extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps, double *ms_host) {
+  if (!c || !ms_host) return fail(KS_ERR_ARG, "null argument");
+  if (reps < 1 || k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "bad k or reps");
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
+  float ms = 0.f;
+  int r = 0;
+  if (which >= 0 && which <= 2) {
+    r = pcg_time_phase<double>(c->N, k, which, c->rowptr, c->col, c->S, c->diagS, c->Xv, c->pw64,
+                               reps, &ms, c->s);
+  } else if (which >= 3 && which <= 5) {
+    if (!c->have_S32) {
+      launch_to_float(c->nnz, c->S, c->S32, c->s);
+      launch_to_float(c->N, c->diagS, c->diagS32, c->s);
+      c->have_S32 = true;
+    }
+    r = pcg_time_phase<float>(c->N, k, which - 3, c->rowptr, c->col, c->S32, c->diagS32, c->X32,
+                              c->pw32, reps, &ms, c->s);
+  } else if (which == 6) {
+    r = pcg_time_phase<double>(c->N, 1, 0, c->rowptr, c->col, c->K, c->diagK, c->vh_int, c->pwP,
+                               reps, &ms, c->s);
+  } else {
+    return fail(KS_ERR_ARG, "which must be 0..6");
+  }
+  if (r < 0) return fail(KS_ERR_HIP, "timing launch failed");
+  *ms_host = ms;
+  return KS_OK;
+}
+
 extern "C" int ks_destroy(ks_ctx *c) {
   if (!c) return KS_OK;
   (void)hipStreamSynchronize(c->s);

@@ -582,6 +582,65 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   return 0;
 }
 
+// Average duration of `reps` back-to-back launches of one PCG phase
+// (0 = A: q = S p with p.q, 1 = B: r update, 2 = C: x/p update) in the
+// launch configuration pcg_solve uses, on the workspace's current contents.
+template <typename T, int VW, int NG>
+static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const int32_t *col,
+                        const T *val, const T *diag, T *X, PCGWork &w, int reps, float *ms,
+                        hipStream_t s) {
+  const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
+  const int RPWA = 64 / (CG * NG);
+  const int RPWE = 64 / CG;
+  const int nblkA = std::min(grid_rows(N, RPWA, 2048), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, 2048), w.nblk_max);
+  Control *ctl = reinterpret_cast<Control *>(w.state);
+  ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
+  T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
+  double *part = reinterpret_cast<double *>(w.part);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;
+  if (hipMemsetAsync(ctl, 0, sizeof(Control), s) != hipSuccess) return -2;
+  auto launch = [&]() {
+    if (phase == 0)
+      hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col,
+                         val, P, Q, part, ctl, cs, w.counter + 1);
+    else if (phase == 1)
+      hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
+                         ctl, cs, w.counter + 2, 0.0);
+    else
+      hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
+                         cs, w.counter + 3);
+  };
+  launch();  // warm
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(e1, s);
+  (void)hipEventSynchronize(e1);
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, e0, e1);
+  *ms = t / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // leave the solver state stopped
+  Control stop{1, 1, 0, 0};
+  (void)hipMemcpyAsync(ctl, &stop, sizeof(Control), hipMemcpyHostToDevice, s);
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
+int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
+                   const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s) {
+  if (k == 1) return time_phase_t<T, 1, 8>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
+  if (k % 4 == 0) return time_phase_t<T, 4, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
+  if (k % 2 == 0) return time_phase_t<T, 2, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
+  return time_phase_t<T, 1, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
+}
+template int pcg_time_phase<double>(int, int, int, const int32_t *, const int32_t *, const double *,
+                                    const double *, double *, PCGWork &, int, float *, hipStream_t);
+template int pcg_time_phase<float>(int, int, int, const int32_t *, const int32_t *, const float *,
+                                   const float *, float *, PCGWork &, int, float *, hipStream_t);
+
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
               const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
