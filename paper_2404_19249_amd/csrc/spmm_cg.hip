@@ -7,15 +7,15 @@
 // consecutive columns; for k = 1 (Hartree Poisson) NG lanes split the
 // nonzeros of a row instead and combine them with cross-lane shuffles.
 //
-// One PCG iteration is three launches:
-//   A  q = S p            and per-column p.q   -> alpha
-//   B  r -= alpha q       and per-column r.z, r.r  -> beta, convergence
+// One PCG iteration is three streaming launches, each followed (A, B) by a
+// one-workgroup reduction of its per-block column partials:
+//   A  q = S p                      partials p.q        -> alpha
+//   B  r -= alpha q                 partials r.z, r.r   -> beta, convergence
 //   C  x += alpha p,  p = D^{-1} r + beta p
-// Per-column scalars live on the device; the last workgroup of each launch
-// (ticket counter) combines the per-block partial sums in a fixed order, so
-// results are bitwise reproducible.  Converged columns are frozen
-// (alpha = 0).  Launches after convergence return at once; the host polls
-// the state every few iterations.
+// Per-column scalars live on the device and are combined in a fixed order
+// (bitwise-reproducible results, no device-scope fences in the streaming
+// kernels).  Converged columns are frozen (alpha = 0).  Launches after
+// convergence return at once; the host polls the state every few iterations.
 #include "common.h"
 #include "kernels.h"
 #include <vector>
@@ -30,10 +30,11 @@ struct ColState {
 };
 struct Control {
   int stop;       // set when no column is active (or breakdown)
-  int skip;       // copy of stop taken after the x/p update of the same iteration
+  int skip;       // iteration in which stop was set (its x/p update still runs)
   int breakdown;  // p^T S p <= 0 or NaN in an active column
   int pad;
 };
+constexpr int PCG_BLOCKS = 1024;  // workgroups of a streaming phase (4 per CU)
 size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
 
 template <typename T, int VW>
@@ -77,20 +78,6 @@ __device__ __forceinline__ void block_cols(const double (&acc)[VW], const RowMap
     part[(int64_t)blockIdx.x * stride + off + c] = s;
   }
   __syncthreads();
-}
-
-// Returns true in every thread of the last block to finish (after a fence).
-__device__ __forceinline__ bool last_block(unsigned int *counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(counter, 1u);
-    s_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last;
 }
 
 // ---------------------------------------------------------------- SpMM row
@@ -288,6 +275,32 @@ void launch_refine_update(int N, int k, const float *D, const double *scale, dou
 }
 
 // ================================================================== PCG
+// Every phase writes per-block column partials; a one-workgroup kernel then
+// combines them in a fixed order (deterministic, and no device-scope fences
+// inside the streaming kernels: on a multi-XCD chip those write back L2).
+constexpr int RED_THREADS = 1024;
+
+// sums[c] = sum_b part[b][c] for c < W (W <= 192), fixed order
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int nblk, int W,
+                                                double *s_sum) {
+  __shared__ double s_red[RED_THREADS];
+  const int G = max(1, RED_THREADS / W);
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  if (t < G * W) {
+    const int c = t % W, g = t / W;
+    for (int b = g; b < nblk; b += G) acc += part[(int64_t)b * W + c];
+  }
+  s_red[t] = acc;
+  __syncthreads();
+  if (t < W) {
+    double tot = 0.0;
+    for (int g = 0; g < G; ++g) tot += s_red[g * W + t];
+    s_sum[t] = tot;
+  }
+  __syncthreads();
+}
+
 // I: R = B - S X, P = D^{-1} R; partials of b.b, r.r, r.z
 template <typename T, int VW, int NG>
 __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
@@ -297,8 +310,7 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
                                                   const T *__restrict__ diag,
                                                   const T *__restrict__ Bm, const T *__restrict__ X,
                                                   T *__restrict__ R, T *__restrict__ P,
-                                                  double *__restrict__ part, Control *ctl,
-                                                  ColState *cs, unsigned int *counter, double tol) {
+                                                  double *__restrict__ part) {
   __shared__ double s_red[256 * VW];
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
@@ -335,40 +347,37 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
   block_cols<VW, NG>(abb, m, k, CG, s_red, part, 3 * k, 0);
   block_cols<VW, NG>(arr, m, k, CG, s_red, part, 3 * k, k);
   block_cols<VW, NG>(arz, m, k, CG, s_red, part, 3 * k, 2 * k);
-  if (last_block(counter)) {
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      double bb = 0.0, rr = 0.0, rz = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) {
-        bb += part[(int64_t)b * 3 * k + c];
-        rr += part[(int64_t)b * 3 * k + k + c];
-        rz += part[(int64_t)b * 3 * k + 2 * k + c];
-      }
-      ColState st;
-      st.bb = bb; st.rr = rr; st.rz = rz; st.rz_new = rz;
-      st.pq = 0.0; st.alpha = 0.0; st.beta = 0.0; st.iters = 0;
-      st.active = (bb > 0.0) && (rr > tol * tol * bb);
-      cs[c] = st;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int any = 0;
-      for (int c = 0; c < k; ++c) any |= cs[c].active;
-      ctl->stop = !any;
-      ctl->skip = !any;
-      ctl->breakdown = 0;
-      *counter = 0u;
-    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_red_init(int k, int nblk, const double *part,
+                                                          Control *ctl, ColState *cs, double tol) {
+  __shared__ double s_sum[192];
+  reduce_partials(part, nblk, 3 * k, s_sum);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    ColState st;
+    st.bb = s_sum[c]; st.rr = s_sum[k + c]; st.rz = s_sum[2 * k + c]; st.rz_new = st.rz;
+    st.pq = 0.0; st.alpha = 0.0; st.beta = 0.0; st.iters = 0;
+    st.active = (st.bb > 0.0) && (st.rr > tol * tol * st.bb);
+    cs[c] = st;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int c = 0; c < k; ++c) any |= cs[c].active;
+    ctl->stop = !any;
+    ctl->skip = -1;   // iteration in which the solver stopped (none yet)
+    ctl->breakdown = 0;
   }
 }
 
-// A: Q = S P, partial p.q -> alpha
+// A: Q = S P, partial p.q
 template <typename T, int VW, int NG>
 __global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col,
                                                const T *__restrict__ val, const T *__restrict__ P,
                                                T *__restrict__ Q, double *__restrict__ part,
-                                               Control *ctl, ColState *cs, unsigned int *counter) {
-  if (ctl->skip) return;
+                                               const Control *ctl) {
+  if (ctl->stop) return;
   __shared__ double s_red[256 * VW];
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
@@ -395,35 +404,33 @@ __global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32
     }
   }
   block_cols<VW, NG>(apq, m, k, CG, s_red, part, k, 0);
-  if (last_block(counter)) {
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      double pq = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) pq += part[(int64_t)b * k + c];
-      ColState st = cs[c];
-      st.pq = pq;
-      if (st.active) {
-        if (!(pq > 0.0)) {
-          ctl->breakdown = 1;
-          st.alpha = 0.0;
-        } else {
-          st.alpha = st.rz / pq;
-        }
-      } else {
-        st.alpha = 0.0;
-      }
-      cs[c] = st;
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_red_A(int k, int nblk, const double *part,
+                                                       Control *ctl, ColState *cs) {
+  if (ctl->stop) return;
+  __shared__ double s_sum[192];
+  reduce_partials(part, nblk, k, s_sum);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    const double pq = s_sum[c];
+    ColState st = cs[c];
+    st.pq = pq;
+    st.alpha = 0.0;
+    if (st.active) {
+      if (!(pq > 0.0)) ctl->breakdown = 1;
+      else st.alpha = st.rz / pq;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+    cs[c] = st;
   }
 }
 
-// B: R -= alpha Q; partials r.z and r.r -> beta, convergence
+// B: R -= alpha Q; partials r.z and r.r
 template <typename T, int VW>
 __global__ void __launch_bounds__(256) k_pcg_B(int N, int k, int CG, const T *__restrict__ diag,
                                                const T *__restrict__ Q, T *__restrict__ R,
-                                               double *__restrict__ part, Control *ctl,
-                                               ColState *cs, unsigned int *counter, double tol) {
-  if (ctl->skip) return;
+                                               double *__restrict__ part, const Control *ctl,
+                                               const ColState *cs) {
+  if (ctl->stop) return;
   __shared__ double s_red[256 * VW];
   __shared__ double s_alpha[MAX_K];
   for (int c = threadIdx.x; c < k; c += blockDim.x) s_alpha[c] = cs[c].alpha;
@@ -451,42 +458,46 @@ __global__ void __launch_bounds__(256) k_pcg_B(int N, int k, int CG, const T *__
   }
   block_cols<VW, 1>(arz, m, k, CG, s_red, part, 2 * k, 0);
   block_cols<VW, 1>(arr, m, k, CG, s_red, part, 2 * k, k);
-  if (last_block(counter)) {
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      double rz = 0.0, rr = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) {
-        rz += part[(int64_t)b * 2 * k + c];
-        rr += part[(int64_t)b * 2 * k + k + c];
-      }
-      ColState st = cs[c];
-      if (st.active) {
-        st.beta = rz / st.rz;
-        st.rz = rz;
-        st.rr = rr;
-        st.iters += 1;
-        if (!(rr > tol * tol * st.bb)) st.active = 0;
-      } else {
-        st.beta = 0.0;
-      }
-      cs[c] = st;
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_red_B(int k, int nblk, const double *part,
+                                                       Control *ctl, ColState *cs, double tol,
+                                                       int it) {
+  if (ctl->stop) return;
+  __shared__ double s_sum[192];
+  reduce_partials(part, nblk, 2 * k, s_sum);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    ColState st = cs[c];
+    if (st.active) {
+      const double rz = s_sum[c], rr = s_sum[k + c];
+      st.beta = rz / st.rz;
+      st.rz = rz;
+      st.rr = rr;
+      st.iters += 1;
+      if (!(rr > tol * tol * st.bb)) st.active = 0;
+    } else {
+      st.beta = 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int any = 0;
-      for (int c = 0; c < k; ++c) any |= cs[c].active;
-      ctl->stop = (!any) || ctl->breakdown;
-      *counter = 0u;
+    cs[c] = st;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int c = 0; c < k; ++c) any |= cs[c].active;
+    if (!any || ctl->breakdown) {
+      ctl->stop = 1;
+      ctl->skip = it;   // the x/p update of this iteration still runs
     }
   }
 }
 
-// C: X += alpha P ; P = D^{-1} R + beta P
+// C: X += alpha P ; P = D^{-1} R + beta P   (runs in the stopping iteration too)
 template <typename T, int VW>
 __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__restrict__ diag,
                                                const T *__restrict__ R, T *__restrict__ X,
-                                               T *__restrict__ P, Control *ctl, ColState *cs,
-                                               unsigned int *counter) {
-  if (ctl->skip) return;
+                                               T *__restrict__ P, const Control *ctl,
+                                               const ColState *cs, int it) {
+  if (ctl->stop && ctl->skip != it) return;
   __shared__ double s_ab[2 * MAX_K];
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     s_ab[c] = cs[c].alpha;
@@ -516,26 +527,22 @@ __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__
     store_row<T, VW>(X, row, k, c0, k, x);
     store_row<T, VW>(P, row, k, c0, k, p);
   }
-  if (last_block(counter)) {
-    if (threadIdx.x == 0) {
-      ctl->skip = ctl->stop;
-      *counter = 0u;
-    }
-  }
 }
 
 template <typename T, int VW, int NG>
 static void pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
                              const int32_t *col, const T *val, const T *diag, T *X, T *R, T *P,
-                             T *Q, double *part, Control *ctl, ColState *cs, unsigned int *cnt,
-                             double tol, int iters, hipStream_t s) {
-  for (int it = 0; it < iters; ++it) {
+                             T *Q, double *part, Control *ctl, ColState *cs, double tol, int it0,
+                             int iters, hipStream_t s) {
+  for (int it = it0; it < it0 + iters; ++it) {
     hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                       P, Q, part, ctl, cs, cnt);
+                       P, Q, part, ctl);
+    hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs);
     hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
-                       ctl, cs, cnt + 1, tol);
+                       ctl, cs);
+    hipLaunchKernelGGL(k_red_B, dim3(1), dim3(RED_THREADS), 0, s, k, nblkE, part, ctl, cs, tol, it);
     hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
-                       cs, cnt + 2);
+                       cs, it);
   }
 }
 
@@ -547,14 +554,15 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
-  const int nblkA = std::min(grid_rows(N, RPWA, 2048), w.nblk_max);
-  const int nblkE = std::min(grid_rows(N, RPWE, 2048), w.nblk_max);
+  const int nblkA = std::min(grid_rows(N, RPWA, PCG_BLOCKS), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
   double *part = reinterpret_cast<double *>(w.part);
   hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                     diag, B, X, R, P, part, ctl, cs, w.counter, tol);
+                     diag, B, X, R, P, part);
+  hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
   std::vector<ColState> hcs(k);
   Control hctl;
   int done_iters = 0, chunk = 4;
@@ -564,7 +572,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
     if (hctl.stop || done_iters >= max_iter) break;
     int n = std::min(chunk, max_iter - done_iters);
     pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, diag, X, R, P, Q, part, ctl,
-                                cs, w.counter + 1, tol, n, s);
+                                cs, tol, done_iters, n, s);
     done_iters += n;
     chunk = std::min(chunk * 2, 32);
   }
@@ -592,8 +600,8 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
-  const int nblkA = std::min(grid_rows(N, RPWA, 2048), w.nblk_max);
-  const int nblkE = std::min(grid_rows(N, RPWE, 2048), w.nblk_max);
+  const int nblkA = std::min(grid_rows(N, RPWA, PCG_BLOCKS), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
@@ -604,13 +612,13 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   auto launch = [&]() {
     if (phase == 0)
       hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col,
-                         val, P, Q, part, ctl, cs, w.counter + 1);
+                         val, P, Q, part, ctl);
     else if (phase == 1)
       hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
-                         ctl, cs, w.counter + 2, 0.0);
+                         ctl, cs);
     else
       hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
-                         cs, w.counter + 3);
+                         cs, 0);
   };
   launch();  // warm
   (void)hipEventRecord(e0, s);
@@ -623,7 +631,7 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // leave the solver state stopped
-  Control stop{1, 1, 0, 0};
+  Control stop{1, -1, 0, 0};
   (void)hipMemcpyAsync(ctl, &stop, sizeof(Control), hipMemcpyHostToDevice, s);
   return hipStreamSynchronize(s) == hipSuccess ? 0 : -2;
 }
