@@ -108,7 +108,7 @@ def main():
         reps.append(rep)
         log(f"[bench] step {i}: E={rep['E_total']:.8f} inner={rep['inner_iters']} "
             f"solve={rep['solve']['seconds'] * 1e3:.2f}ms iters={max(rep['solve']['iters'])} "
-            f"refine={rep['solve']['refinements']} total={rep['seconds'][5]:.3f}s")
+            f"refine={rep['solve']['refinements']} res_inner={rep['res_inner']:.2e} total={rep['seconds'][5]:.3f}s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps

@@ -34,7 +34,8 @@ struct Control {
   int breakdown;  // p^T S p <= 0 or NaN in an active column
   int pad;
 };
-constexpr int PCG_BLOCKS = 1024;  // workgroups of a streaming phase (4 per CU)
+constexpr int PCG_BLOCKS = 1024;  // workgroups of an elementwise phase (4 per CU)
+constexpr int SPMM_BLOCKS = 2048; // workgroups of the SpMM phase (8 waves per SIMD)
 size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
 
 template <typename T, int VW>
@@ -81,43 +82,48 @@ __device__ __forceinline__ void block_cols(const double (&acc)[VW], const RowMap
 }
 
 // ---------------------------------------------------------------- SpMM row
+// Nonzeros are taken U at a time: U independent (col, val) loads, then U
+// independent gathers of the VW-wide row segments, so one row costs about
+// nnz/(U*NG) dependent memory round trips.  Lanes past the row end gather the
+// row itself with weight zero (always a valid address).
+template <typename T, int VW> struct Unroll { static constexpr int U = (sizeof(T) * VW >= 32) ? 4 : 8; };
+
 template <typename T, int VW, int NG>
 __device__ __forceinline__ void row_product(int row, const RowMap &m,
                                             const int32_t *__restrict__ rowptr,
                                             const int32_t *__restrict__ col,
                                             const T *__restrict__ val, const T *__restrict__ X,
                                             int ldx, int k, T (&acc)[VW]) {
+  constexpr int U = Unroll<T, VW>::U;
   for (int v = 0; v < VW; ++v) acc[v] = T(0);
   const int c0 = m.cg * VW;
   const bool colok = c0 < k;
+  const bool vec = VW > 1 && (ldx % VW) == 0 && c0 + VW <= k;
   const int jb = rowptr[row], je = rowptr[row + 1];
-  int j = jb + m.ng;
-  // two nonzeros per trip for memory-level parallelism
-  for (; j + NG < je; j += 2 * NG) {
-    const int ca = col[j], cb = col[j + NG];
-    const T va = val[j], vb = val[j + NG];
-    if (colok) {
-      if (VW > 1 && (ldx % VW) == 0) {
-        const VecT<T, VW> xa = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)ca * ldx + c0);
-        const VecT<T, VW> xb = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)cb * ldx + c0);
-        for (int v = 0; v < VW; ++v) acc[v] += va * xa.v[v] + vb * xb.v[v];
-      } else {
-        for (int v = 0; v < VW; ++v)
-          if (c0 + v < k)
-            acc[v] += va * X[(int64_t)ca * ldx + c0 + v] + vb * X[(int64_t)cb * ldx + c0 + v];
-      }
+  for (int j = jb + m.ng; j < je; j += U * NG) {
+    int ci[U];
+    T vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int jj = j + u * NG;
+      const bool ok = jj < je;
+      ci[u] = ok ? col[jj] : row;
+      vv[u] = ok ? val[jj] : T(0);
     }
-  }
-  if (j < je) {
-    const int ca = col[j];
-    const T va = val[j];
     if (colok) {
-      if (VW > 1 && (ldx % VW) == 0) {
-        const VecT<T, VW> xa = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)ca * ldx + c0);
-        for (int v = 0; v < VW; ++v) acc[v] += va * xa.v[v];
+      if (vec) {
+        VecT<T, VW> xs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          xs[u] = *reinterpret_cast<const VecT<T, VW> *>(X + (int64_t)ci[u] * ldx + c0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          for (int v = 0; v < VW; ++v) acc[v] += vv[u] * xs[u].v[v];
       } else {
-        for (int v = 0; v < VW; ++v)
-          if (c0 + v < k) acc[v] += va * X[(int64_t)ca * ldx + c0 + v];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          for (int v = 0; v < VW; ++v)
+            if (c0 + v < k) acc[v] += vv[u] * X[(int64_t)ci[u] * ldx + c0 + v];
       }
     }
   }
@@ -554,7 +560,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
-  const int nblkA = std::min(grid_rows(N, RPWA, PCG_BLOCKS), w.nblk_max);
+  const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
   const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
@@ -600,7 +606,7 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
-  const int nblkA = std::min(grid_rows(N, RPWA, PCG_BLOCKS), w.nblk_max);
+  const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
   const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
@@ -639,6 +645,8 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
                    const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s) {
+  if (sizeof(T) == 4 && k % 8 == 0)
+    return time_phase_t<T, 8, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
   if (k == 1) return time_phase_t<T, 1, 8>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
   if (k % 4 == 0) return time_phase_t<T, 4, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
   if (k % 2 == 0) return time_phase_t<T, 2, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
@@ -653,6 +661,9 @@ template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
               const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
               double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s) {
+  if (sizeof(T) == 4 && k % 8 == 0)
+    return pcg_run<T, 8, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                            relres_out, converged_out, breakdown_out, s);
   if (k == 1)
     return pcg_run<T, 1, 8>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
