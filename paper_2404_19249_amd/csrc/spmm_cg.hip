@@ -84,8 +84,10 @@ __device__ __forceinline__ void block_cols(const double (&acc)[VW], const RowMap
 // ---------------------------------------------------------------- SpMM row
 // Nonzeros are taken U at a time: U independent (col, val) loads, then U
 // independent gathers of the VW-wide row segments, so one row costs about
-// nnz/(U*NG) dependent memory round trips.  Lanes past the row end gather the
-// row itself with weight zero (always a valid address).
+// nnz/(U*NG) dependent memory round trips.  Slots past the row end reuse the
+// chunk's first nonzero (index j < row end, so its column is a valid column
+// of this matrix, square or not) with weight zero; every load index stays in
+// [row start, row end).
 template <typename T, int VW> struct Unroll { static constexpr int U = (sizeof(T) * VW >= 32) ? 4 : 8; };
 
 template <typename T, int VW, int NG>
@@ -107,8 +109,10 @@ __device__ __forceinline__ void row_product(int row, const RowMap &m,
     for (int u = 0; u < U; ++u) {
       const int jj = j + u * NG;
       const bool ok = jj < je;
-      ci[u] = ok ? col[jj] : row;
-      vv[u] = ok ? val[jj] : T(0);
+      const int jc = ok ? jj : j;
+      ci[u] = col[jc];
+      const T vload = val[jc];
+      vv[u] = ok ? vload : T(0);
     }
     if (colok) {
       if (vec) {
@@ -661,8 +665,16 @@ template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
               const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
               double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s) {
-  if (sizeof(T) == 4 && k % 8 == 0)
+  // vector access needs VW-aligned base pointers (row strides are k)
+  auto al = [](const void *p, size_t bytes) {
+    return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+  };
+  const bool a32 = al(B, 32) && al(X, 32), a16 = al(B, 16) && al(X, 16);
+  if (sizeof(T) == 4 && k % 8 == 0 && a32)
     return pcg_run<T, 8, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+                            relres_out, converged_out, breakdown_out, s);
+  if (k != 1 && !(sizeof(T) * 4 <= 16 ? a16 : a32))
+    return pcg_run<T, 1, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
   if (k == 1)
     return pcg_run<T, 1, 8>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
