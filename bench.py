@@ -42,6 +42,25 @@ def cg_iteration_bytes(N, nnz, k, sv):
     return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 10 * N * k * sv
 
 
+def copy_probe(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB with torch's plain copy kernel: read +
+    write bytes per second (a practical HBM reference next to the 8 TB/s
+    nominal peak)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(k):
     """The oracle (single thread) on a bounded sample of the same workload:
     the mixed workload's nuclei and mesh recipe at 32^3 hexahedra, one block
@@ -73,6 +92,9 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--mode", default="step", choices=["step", "solve"],
+                    help="solve: skip the SCF steps (block solves and kernel timings only, "
+                         "for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sharded "
@@ -93,6 +115,10 @@ def main():
         f"setup {time.perf_counter() - t_setup:.1f}s")
     psi, lam = ctx.initial_guess(k)
     occ = w.occ
+    copy_gbs = copy_probe(torch)
+    log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
+    if args.mode == "solve":
+        args.warmup, args.steps = 0, 0
     for i in range(args.warmup):
         lam, rep = ctx.scf_step(psi, lam, occ, precision=args.precision)
         log(f"[bench] warmup step {i}: inner {rep['inner_iters']} solve iters "
@@ -111,8 +137,8 @@ def main():
             f"refine={rep['solve']['refinements']} res_inner={rep['res_inner']:.2e} total={rep['seconds'][5]:.3f}s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = N * k * args.steps / solve_s
+    ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    value = N * k * args.steps / solve_s if args.steps else None
 
     # ------------------------------------- both forms on the same inputs
     ctx.assemble(psi_in, occ, want_fields=False)
@@ -126,17 +152,20 @@ def main():
         forms[prec] = {"dof_rhs_per_s": N * k / t, "ms": t * 1e3,
                        "iters_max": int(max(st["iters"])), "refinements": st["refinements"],
                        "relres_max": float(max(st["relres"]))}
+    if value is None:
+        value = forms[args.precision]["dof_rhs_per_s"]
     # eigenvalue accuracy of one step in each form against a tightly solved FP64 step
-    lam_of = {}
-    for key in ("fp64", "mixed"):
-        lam_of[key], _ = ctx.scf_step(psi_in.clone(), lam_in, occ, precision=key)
-    ref_ctx = KSContext.from_workload(w, tol_solve=1e-12, tol_inner=1e-8, tol_poisson=1e-10)
-    lam_of["ref"], _ = ref_ctx.scf_step(psi_in.clone(), lam_in, occ, precision="fp64")
-    ref_ctx.close()
-    for key in ("fp64", "mixed"):
-        forms[key]["eig_err_vs_fp64_tight_Ha"] = float(np.abs(lam_of[key] - lam_of["ref"]).max())
+    if args.mode == "step":
+        lam_of = {}
+        for key in ("fp64", "mixed"):
+            lam_of[key], _ = ctx.scf_step(psi_in.clone(), lam_in, occ, precision=key)
+        ref_ctx = KSContext.from_workload(w, tol_solve=1e-12, tol_inner=1e-8, tol_poisson=1e-10)
+        lam_of["ref"], _ = ref_ctx.scf_step(psi_in.clone(), lam_in, occ, precision="fp64")
+        ref_ctx.close()
+        for key in ("fp64", "mixed"):
+            forms[key]["eig_err_vs_fp64_tight_Ha"] = float(np.abs(lam_of[key] - lam_of["ref"]).max())
+        ctx.assemble(psi_in, occ, want_fields=False)
     forms["mixed_speedup"] = forms["fp64"]["ms"] / forms["mixed"]["ms"]
-    ctx.assemble(psi_in, occ, want_fields=False)
 
     # ------------------------------------------- roofline of the SpMM phase
     ctx.block_solve(psi_in, lam_in, "mixed")   # leaves the FP32 operator and workspace
@@ -167,9 +196,10 @@ def main():
                    "N": N, "k": k, "nnz": nnz, "precision": args.precision, "mu": ctx.mu,
                    "value_basis": "N*k / device time of the block solve inside each timed step"},
         "roofline": roof,
+        "copy_probe_GBs": copy_gbs,
         "pcg_phases": phases,
         "block_solve": forms,
-        "step": {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
+        "step": {} if not reps else {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
                  "inner_iters": [r["inner_iters"] for r in reps],
                  "poisson_iters": [r["poisson_iters"] for r in reps],
                  "seconds_split": {n: float(np.mean([r["seconds"][i] for r in reps]))

@@ -34,7 +34,7 @@ struct Control {
   int breakdown;  // p^T S p <= 0 or NaN in an active column
   int pad;
 };
-constexpr int PCG_BLOCKS = 1024;  // workgroups of an elementwise phase (4 per CU)
+constexpr int PCG_BLOCKS = 2048;  // workgroups of an elementwise phase (8 per CU)
 constexpr int SPMM_BLOCKS = 2048; // workgroups of the SpMM phase (8 waves per SIMD)
 size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
 
@@ -61,6 +61,24 @@ __device__ __forceinline__ RowMap row_map(int CG) {
   m.ng = r % NG;
   m.valid = m.slot < m.RPW;
   return m;
+}
+
+// Row groups (one per workgroup iteration) are dealt to the 8 XCDs in
+// contiguous eighths: workgroup b runs on XCD b % 8 (round-robin dispatch), so
+// the workgroups of one XCD sweep one contiguous slab of rows and the gathered
+// neighbour rows of the block vector stay in that XCD's L2.
+struct GroupIter {
+  int g, end, step;
+};
+__device__ __forceinline__ GroupIter group_iter(int n_groups) {
+  const int nx = (gridDim.x >= 8 && (gridDim.x & 7) == 0) ? 8 : 1;
+  const int x = blockIdx.x % nx, lb = blockIdx.x / nx, per = gridDim.x / nx;
+  const int chunk = (n_groups + nx - 1) / nx;
+  GroupIter it;
+  it.g = x * chunk + lb;
+  it.end = min(n_groups, (x + 1) * chunk);
+  it.step = per;
+  return it;
 }
 
 // Block reduction of per-lane column partials (VW columns per lane) into
@@ -169,11 +187,10 @@ __global__ void __launch_bounds__(256) k_spmm(int N, const int32_t *__restrict__
                                               const T *__restrict__ B, int ldb, int mode) {
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
-  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
-       row += gridDim.x * rows_per_block) {
-    // uniform trip count per wave: every lane of a row group stays in the loop
-    const int base = row - m.slot;
-    if (base >= N) break;
+  // uniform trip count per workgroup: every lane of a row group stays in the loop
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
     const bool rv = m.valid && row < N;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, ldx, k, acc);
@@ -211,10 +228,14 @@ static Shape pick_shape(int k, int ld) {
   s.NG = 1;
   return s;
 }
+// workgroups for N rows at RPW rows per wave (4 waves per workgroup); a
+// multiple of 8 once there is more than one per XCD
 static int grid_rows(int N, int RPW, int cap = 4096) {
   int rows_per_block = 4 * RPW;
   int b = (N + rows_per_block - 1) / rows_per_block;
-  return std::max(1, std::min(b, cap));
+  b = std::max(1, std::min(b, cap));
+  if (b > 8) b = (b + 7) / 8 * 8;
+  return b;
 }
 
 template <typename T>
@@ -326,10 +347,9 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
   double abb[VW], arr[VW], arz[VW];
   for (int v = 0; v < VW; ++v) abb[v] = arr[v] = arz[v] = 0.0;
-  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
-       row += gridDim.x * rows_per_block) {
-    const int base = row - m.slot;
-    if (base >= N) break;
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
     const bool rv = m.valid && row < N;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, k, k, acc);
@@ -393,10 +413,9 @@ __global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
   double apq[VW];
   for (int v = 0; v < VW; ++v) apq[v] = 0.0;
-  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; ;
-       row += gridDim.x * rows_per_block) {
-    const int base = row - m.slot;
-    if (base >= N) break;
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
     const bool rv = m.valid && row < N;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, P, k, k, acc);
@@ -452,9 +471,10 @@ __global__ void __launch_bounds__(256) k_pcg_B(int N, int k, int CG, const T *__
   const int c0 = m.cg * VW;
   T al[VW];
   for (int v = 0; v < VW; ++v) al[v] = (c0 + v < k) ? (T)s_alpha[c0 + v] : T(0);
-  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; row < N;
-       row += gridDim.x * rows_per_block) {
-    if (!m.valid || c0 >= k) continue;
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
     T q[VW], r[VW];
     load_row<T, VW>(Q, row, k, c0, k, q);
     load_row<T, VW>(R, row, k, c0, k, r);
@@ -522,9 +542,10 @@ __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__
     al[v] = (c0 + v < k) ? (T)s_ab[c0 + v] : T(0);
     be[v] = (c0 + v < k) ? (T)s_ab[MAX_K + c0 + v] : T(0);
   }
-  for (int row = blockIdx.x * rows_per_block + m.wave * m.RPW + m.slot; row < N;
-       row += gridDim.x * rows_per_block) {
-    if (!m.valid || c0 >= k) continue;
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
     T x[VW], p[VW], r[VW];
     load_row<T, VW>(X, row, k, c0, k, x);
     load_row<T, VW>(P, row, k, c0, k, p);
