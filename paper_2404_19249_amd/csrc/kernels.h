@@ -77,11 +77,14 @@ void launch_lincomb(int64_t n, int nvec, const double *coef_dev, const double *c
 struct ColState;  // per-column PCG scalars, defined in spmm_cg.hip
 
 // Y = A X (mode 0) or Y = B - A X (mode 1) for [N][k] blocks, row stride ldx/ldy.
+// `ord`: device [N] schedule (permutation) in which rows are processed, or
+// nullptr for the natural order.  A spatially local schedule keeps the
+// gathered rows of X in L2; the results do not depend on it.
 void launch_spmm(int N, const int32_t *rowptr, const int32_t *col, const double *val,
                  const double *X, int ldx, double *Y, int ldy, int k, const double *B, int ldb,
-                 int mode, hipStream_t s);
+                 int mode, const int32_t *ord, hipStream_t s);
 void launch_spmm_f32(int N, const int32_t *rowptr, const int32_t *col, const float *val,
-                     const float *X, float *Y, int k, hipStream_t s);
+                     const float *X, float *Y, int k, const int32_t *ord, hipStream_t s);
 // Y[i][j] *= scale[j]
 void launch_scale_cols(int N, int k, double *Y, const double *scale_dev, hipStream_t s);
 
@@ -95,13 +98,13 @@ struct PCGWork {
   int nblk_max;
 };
 template <typename T>
-int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
-              const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
+int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
+              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
               double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s);
 size_t pcg_state_bytes(int k);
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
-                   const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s);
+                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s);
 
 // ------------------------------------------------------------------- dense
 // C[a][b] = sum_i Z[i][a] Y[i][b] for a < ma, b < nb (tall-skinny, FP64

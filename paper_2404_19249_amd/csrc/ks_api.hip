@@ -96,6 +96,7 @@ struct ks_ctx {
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
   // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
   int32_t *rowptr = nullptr, *col = nullptr, *rowptrB = nullptr, *colB = nullptr;
+  int32_t *rorder = nullptr;  // spatially local row schedule of the SpMM kernels
   double *K = nullptr, *M = nullptr, *AL = nullptr, *base = nullptr, *S = nullptr,
          *MNL = nullptr, *diagS = nullptr, *diagK = nullptr;
   float *S32 = nullptr, *diagS32 = nullptr;
@@ -249,12 +250,11 @@ static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
                        c->qw, rho, 4.0 * M_PI, c->load, c->s);
   }
   // rhs = load - K_IB wB
-  launch_spmm(c->N, c->rowptrB, c->colB, c->K + c->nnz, c->wB, 1, c->rhs, 1, 1, c->load, 1, 1,
-              c->s);
+  launch_spmm(c->N, c->rowptrB, c->colB, c->K + c->nnz, c->wB, 1, c->rhs, 1, 1, c->load, 1, 1, c->rorder, c->s);
   if (!c->vh_warm) launch_fill(c->N, 0.0, c->vh_int, c->s);
   int it[1] = {0}, conv = 0, brk = 0;
   double rr[1];
-  int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->diagK, c->rhs, c->vh_int,
+  int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->rhs, c->vh_int,
                             c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
                             c->s);
   if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
@@ -523,6 +523,40 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       }
     });
   }
+  // row schedule: interior rows in Morton (Z-curve) order of their
+  // coordinates, so the workgroups in flight sweep compact 3D regions and the
+  // neighbour rows they gather stay cached.  KS_ROW_ORDER=natural keeps the
+  // numbering order.
+  std::vector<int32_t> rorder(N);
+  {
+    const char *env = std::getenv("KS_ROW_ORDER");
+    const bool natural = env && std::strcmp(env, "natural") == 0;
+    for (int r = 0; r < N; ++r) rorder[r] = r;
+    if (!natural) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int r = 0; r < N; ++r)
+        for (int d = 0; d < 3; ++d) {
+          const double x = mesh->coords_host[3 * (int64_t)interior_nodes[r] + d];
+          lo[d] = std::min(lo[d], x);
+          hi[d] = std::max(hi[d], x);
+        }
+      std::vector<uint64_t> key(N);
+      parallel_for(N, [&](int64_t r) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; ++d) {
+          const double x = mesh->coords_host[3 * (int64_t)interior_nodes[r] + d];
+          const double t = (hi[d] > lo[d]) ? (x - lo[d]) / (hi[d] - lo[d]) : 0.0;
+          q[d] = (uint64_t)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)));
+        }
+        uint64_t k = 0;
+        for (int b = 9; b >= 0; --b)
+          for (int d = 2; d >= 0; --d) k = (k << 1) | ((q[d] >> b) & 1u);
+        key[r] = k;
+      });
+      std::stable_sort(rorder.begin(), rorder.end(),
+                       [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
+  }
   // basis tables
   std::vector<double> phi, dphi;
   basis_tables(c->order, c->n_q, quad->bary_host, phi, dphi);
@@ -559,6 +593,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(rowptr, N + 1);
   A_(col, c->nnz);
   A_(rowptrB, N + 1);
+  A_(rorder, N);
   A_(colB, std::max<int64_t>(1, c->nnzB));
   A_(K, c->nnz_ext);
   A_(M, c->nnz_ext);
@@ -664,6 +699,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   H2D(c->rowptr, rowptr.data(), N + 1);
   H2D(c->col, colI.data(), c->nnz);
   H2D(c->rowptrB, rowptrB.data(), N + 1);
+  H2D(c->rorder, rorder.data(), N);
   H2D(c->colB, colB.data(), colB.size());
   H2D(c->Pidx, Pidx.data(), Pidx.size());
   H2D(c->Pw, Pw.data(), Pw.size());
@@ -700,11 +736,11 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   launch_dense_P(N, c->Pidx, c->Pw, c->N_H, c->Z, c->mp, s);
   dbg(c, "AL", c->AL, c->nnz_ext);
   dbg(c, "Z(P dense)", c->Z, (int64_t)N * c->mp);
-  launch_spmm(N, c->rowptr, c->col, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
+  launch_spmm(N, c->rowptr, c->col, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, c->rorder, s);
   dbg(c, "Y = M P", c->Y, (int64_t)N * c->mp);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->GPP, c->N_H, c->gwork, c->gwork_n, s);
   dbg(c, "G_PP", c->GPP, (int64_t)c->N_H * c->N_H);
-  launch_spmm(N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, s);
+  launch_spmm(N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, c->rorder, s);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork, c->gwork_n,
                  s);
   {
@@ -780,7 +816,7 @@ extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps,
   float ms = 0.f;
   int r = 0;
   if (which >= 0 && which <= 2) {
-    r = pcg_time_phase<double>(c->N, k, which, c->rowptr, c->col, c->S, c->diagS, c->Xv, c->pw64,
+    r = pcg_time_phase<double>(c->N, k, which, c->rowptr, c->col, c->S, c->rorder, c->diagS, c->Xv, c->pw64,
                                reps, &ms, c->s);
   } else if (which >= 3 && which <= 5) {
     if (!c->have_S32) {
@@ -788,10 +824,10 @@ extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps,
       launch_to_float(c->N, c->diagS, c->diagS32, c->s);
       c->have_S32 = true;
     }
-    r = pcg_time_phase<float>(c->N, k, which - 3, c->rowptr, c->col, c->S32, c->diagS32, c->X32,
+    r = pcg_time_phase<float>(c->N, k, which - 3, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->X32,
                               c->pw32, reps, &ms, c->s);
   } else if (which == 6) {
-    r = pcg_time_phase<double>(c->N, 1, 0, c->rowptr, c->col, c->K, c->diagK, c->vh_int, c->pwP,
+    r = pcg_time_phase<double>(c->N, 1, 0, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->vh_int, c->pwP,
                                reps, &ms, c->s);
   } else {
     return fail(KS_ERR_ARG, "which must be 0..6");
@@ -901,7 +937,7 @@ extern "C" int ks_export_operator(ks_ctx *c, int32_t which, int32_t *row_ptr, in
 // ------------------------------------------------------------ block solve
 static int true_residual(ks_ctx *c, const double *B, const double *X, int k, double *relres,
                          bool *ok) {
-  launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->s);
+  launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->rorder, c->s);
   std::vector<double> rn(k), bn(k), tmp((size_t)256 * k);
   int nb = launch_colnorms(c->N, k, c->Wv, c->redpart, c->s);
   TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
@@ -925,7 +961,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
   HIPCHK(hipEventRecord(c->ev0, s));
   int conv = 0, brk = 0;
   if (precision == KS_PREC_FP64) {
-    int r = pcg_solve<double>(c->N, k, c->rowptr, c->col, c->S, c->diagS, B, X, tol,
+    int r = pcg_solve<double>(c->N, k, c->rowptr, c->col, c->S, c->rorder, c->diagS, B, X, tol,
                               c->opt.max_it_solve, c->pw64, loc.iters, loc.relres, &conv, &brk, s);
     if (r < 0) return fail(KS_ERR_HIP, "PCG launch failed");
     if (brk) return fail(KS_ERR_BREAKDOWN, "PCG breakdown: p^T S p <= 0 (S not positive definite; increase mu)");
@@ -945,7 +981,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
     conv = 0;
     for (int ref = 0; ref < max_ref; ++ref) {
       // FP64 residual
-      launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, s);
+      launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->rorder, s);
       nb = launch_colnorms(c->N, k, c->Wv, c->redpart, s);
       TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
       loc.refinements = ref + 1;
@@ -967,7 +1003,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
       int it[MAX_K] = {0};
       double rr[MAX_K];
       int c32 = 0;
-      int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->diagS32, c->B32, c->X32,
+      int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->B32, c->X32,
                                c->opt.mixed_inner_tol, c->opt.max_it_solve, c->pw32, it, rr, &c32,
                                &brk, s);
       if (r < 0) return fail(KS_ERR_HIP, "FP32 PCG launch failed");
@@ -1004,7 +1040,7 @@ extern "C" int ks_block_solve_rhs(ks_ctx *c, const double *B, const double *X0, 
 
 // B = M psi diag(lambda + mu)
 static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, int k, double *B) {
-  launch_spmm(c->N, c->rowptr, c->col, c->M, psi, k, B, k, k, nullptr, 0, 0, c->s);
+  launch_spmm(c->N, c->rowptr, c->col, c->M, psi, k, B, k, k, nullptr, 0, 0, c->rorder, c->s);
   double sc[MAX_K];
   for (int j = 0; j < k; ++j) sc[j] = lambda_host[j] + c->mu;
   HIPCHK(hipMemcpyAsync(c->scal, sc, sizeof(double) * k, hipMemcpyHostToDevice, c->s));
@@ -1028,7 +1064,7 @@ extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *la
 static int build_tail(ks_ctx *c, const double *psi_hat, int k) {
   hipStream_t s = c->s;
   const int N = c->N, nH = c->N_H;
-  launch_spmm(N, c->rowptr, c->col, c->M, psi_hat, k, c->Wv, k, k, nullptr, 0, 0, s);
+  launch_spmm(N, c->rowptr, c->col, c->M, psi_hat, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
   launch_gemm_tn(N, nH, k, c->Z, c->mp, c->Wv, k, c->Ctmp, k, c->gwork, c->gwork_n, s);
   launch_small_gemm(nH, k, nH, c->GPPinv, nH, c->Ctmp, k, c->Ttmp, k, 0.0, s);
   launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, -1.0, psi_hat, k, c->Z + nH, c->mp, s);
@@ -1038,13 +1074,13 @@ static int build_tail(ks_ctx *c, const double *psi_hat, int k) {
 
 // F (m x m, ld m) = Z^T H Z with the P-P block taken from PP if given
 static void project_full(ks_ctx *c, const double *H, int m, double *F) {
-  launch_spmm(c->N, c->rowptr, c->col, H, c->Z, c->mp, c->Y, c->mp, c->mp, nullptr, 0, 0, c->s);
+  launch_spmm(c->N, c->rowptr, c->col, H, c->Z, c->mp, c->Y, c->mp, c->mp, nullptr, 0, 0, c->rorder, c->s);
   launch_gemm_tn(c->N, m, m, c->Z, c->mp, c->Y, c->mp, F, m, c->gwork, c->gwork_n, c->s);
 }
 // F from the fixed P-P block and the tail columns Z^T (H psi_tilde)
 static void project_tail(ks_ctx *c, const double *H, const double *PP, int k, double *F) {
   const int m = c->N_H + k;
-  launch_spmm(c->N, c->rowptr, c->col, H, c->Z + c->N_H, c->mp, c->Wv, k, k, nullptr, 0, 0, c->s);
+  launch_spmm(c->N, c->rowptr, c->col, H, c->Z + c->N_H, c->mp, c->Wv, k, k, nullptr, 0, 0, c->rorder, c->s);
   launch_gemm_tn(c->N, m, k, c->Z, c->mp, c->Wv, k, c->Ftail, k, c->gwork, c->gwork_n, c->s);
   launch_fill_pencil(m, c->N_H, PP, c->Ftail, F, c->s);
 }

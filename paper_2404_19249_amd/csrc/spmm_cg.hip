@@ -184,14 +184,16 @@ __global__ void __launch_bounds__(256) k_spmm(int N, const int32_t *__restrict__
                                               const int32_t *__restrict__ col,
                                               const T *__restrict__ val, const T *__restrict__ X,
                                               int ldx, T *__restrict__ Y, int ldy, int k, int CG,
-                                              const T *__restrict__ B, int ldb, int mode) {
+                                              const T *__restrict__ B, int ldb, int mode,
+                                              const int32_t *__restrict__ ord) {
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
   // uniform trip count per workgroup: every lane of a row group stays in the loop
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
   for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
-    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
-    const bool rv = m.valid && row < N;
+    const int pos = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    const bool rv = m.valid && pos < N;
+    const int row = rv ? (ord ? ord[pos] : pos) : 0;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, ldx, k, acc);
     else {
@@ -241,7 +243,7 @@ static int grid_rows(int N, int RPW, int cap = 4096) {
 template <typename T>
 static void spmm_dispatch(int N, const int32_t *rowptr, const int32_t *col, const T *val, const T *X,
                           int ldx, T *Y, int ldy, int k, const T *B, int ldb, int mode,
-                          hipStream_t s) {
+                          const int32_t *ord, hipStream_t s) {
   if (N <= 0 || k <= 0) return;
   Shape sh = pick_shape(k, std::min(ldx, ldy));
   // vector loads need VW-aligned rows: drop to scalar access otherwise
@@ -258,26 +260,26 @@ static void spmm_dispatch(int N, const int32_t *rowptr, const int32_t *col, cons
   dim3 g(grid_rows(N, RPW)), b(256);
   if (sh.NG == 8)
     hipLaunchKernelGGL((k_spmm<T, 1, 8>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, 1, B,
-                       ldb, mode);
+                       ldb, mode, ord);
   else if (sh.VW == 4)
     hipLaunchKernelGGL((k_spmm<T, 4, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
-                       B, ldb, mode);
+                       B, ldb, mode, ord);
   else if (sh.VW == 2)
     hipLaunchKernelGGL((k_spmm<T, 2, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
-                       B, ldb, mode);
+                       B, ldb, mode, ord);
   else
     hipLaunchKernelGGL((k_spmm<T, 1, 1>), g, b, 0, s, N, rowptr, col, val, X, ldx, Y, ldy, k, sh.CG,
-                       B, ldb, mode);
+                       B, ldb, mode, ord);
 }
 
 void launch_spmm(int N, const int32_t *rowptr, const int32_t *col, const double *val,
                  const double *X, int ldx, double *Y, int ldy, int k, const double *B, int ldb,
-                 int mode, hipStream_t s) {
-  spmm_dispatch<double>(N, rowptr, col, val, X, ldx, Y, ldy, k, B, ldb, mode, s);
+                 int mode, const int32_t *ord, hipStream_t s) {
+  spmm_dispatch<double>(N, rowptr, col, val, X, ldx, Y, ldy, k, B, ldb, mode, ord, s);
 }
 void launch_spmm_f32(int N, const int32_t *rowptr, const int32_t *col, const float *val,
-                     const float *X, float *Y, int k, hipStream_t s) {
-  spmm_dispatch<float>(N, rowptr, col, val, X, k, Y, k, k, nullptr, k, 0, s);
+                     const float *X, float *Y, int k, const int32_t *ord, hipStream_t s) {
+  spmm_dispatch<float>(N, rowptr, col, val, X, k, Y, k, k, nullptr, k, 0, ord, s);
 }
 
 __global__ void k_scale_cols(int64_t n, int k, double *__restrict__ Y, const double *__restrict__ sc) {
@@ -341,7 +343,8 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
                                                   const T *__restrict__ diag,
                                                   const T *__restrict__ Bm, const T *__restrict__ X,
                                                   T *__restrict__ R, T *__restrict__ P,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part,
+                                                  const int32_t *__restrict__ ord) {
   __shared__ double s_red[256 * VW];
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
@@ -349,8 +352,9 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
   for (int v = 0; v < VW; ++v) abb[v] = arr[v] = arz[v] = 0.0;
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
   for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
-    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
-    const bool rv = m.valid && row < N;
+    const int pos = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    const bool rv = m.valid && pos < N;
+    const int row = rv ? (ord ? ord[pos] : pos) : 0;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, k, k, acc);
     else {
@@ -406,7 +410,8 @@ __global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32
                                                const int32_t *__restrict__ col,
                                                const T *__restrict__ val, const T *__restrict__ P,
                                                T *__restrict__ Q, double *__restrict__ part,
-                                               const Control *ctl) {
+                                               const Control *ctl,
+                                               const int32_t *__restrict__ ord) {
   if (ctl->stop) return;
   __shared__ double s_red[256 * VW];
   const RowMap m = row_map<NG>(CG);
@@ -415,8 +420,9 @@ __global__ void __launch_bounds__(256) k_pcg_A(int N, int k, int CG, const int32
   for (int v = 0; v < VW; ++v) apq[v] = 0.0;
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
   for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
-    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
-    const bool rv = m.valid && row < N;
+    const int pos = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    const bool rv = m.valid && pos < N;
+    const int row = rv ? (ord ? ord[pos] : pos) : 0;
     T acc[VW];
     if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, P, k, k, acc);
     else {
@@ -562,12 +568,13 @@ __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__
 
 template <typename T, int VW, int NG>
 static void pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
-                             const int32_t *col, const T *val, const T *diag, T *X, T *R, T *P,
+                             const int32_t *col, const T *val, const int32_t *ord, const T *diag,
+                             T *X, T *R, T *P,
                              T *Q, double *part, Control *ctl, ColState *cs, double tol, int it0,
                              int iters, hipStream_t s) {
   for (int it = it0; it < it0 + iters; ++it) {
     hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                       P, Q, part, ctl);
+                       P, Q, part, ctl, ord);
     hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs);
     hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
                        ctl, cs);
@@ -579,7 +586,7 @@ static void pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const i
 
 template <typename T, int VW, int NG>
 static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
-                   const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w,
+                   const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w,
                    int *iters_out, double *relres_out, int *converged_out, int *breakdown_out,
                    hipStream_t s) {
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
@@ -592,7 +599,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
   double *part = reinterpret_cast<double *>(w.part);
   hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                     diag, B, X, R, P, part);
+                     diag, B, X, R, P, part, ord);
   hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
   std::vector<ColState> hcs(k);
   Control hctl;
@@ -602,7 +609,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
     if (hctl.stop || done_iters >= max_iter) break;
     int n = std::min(chunk, max_iter - done_iters);
-    pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, diag, X, R, P, Q, part, ctl,
+    pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, ord, diag, X, R, P, Q, part, ctl,
                                 cs, tol, done_iters, n, s);
     done_iters += n;
     chunk = std::min(chunk * 2, 32);
@@ -626,7 +633,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
 // launch configuration pcg_solve uses, on the workspace's current contents.
 template <typename T, int VW, int NG>
 static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const int32_t *col,
-                        const T *val, const T *diag, T *X, PCGWork &w, int reps, float *ms,
+                        const T *val, const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms,
                         hipStream_t s) {
   const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
@@ -643,7 +650,7 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   auto launch = [&]() {
     if (phase == 0)
       hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col,
-                         val, P, Q, part, ctl);
+                         val, P, Q, part, ctl, ord);
     else if (phase == 1)
       hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
                          ctl, cs);
@@ -669,22 +676,22 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
 
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
-                   const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s) {
+                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s) {
   if (sizeof(T) == 4 && k % 8 == 0)
-    return time_phase_t<T, 8, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
-  if (k == 1) return time_phase_t<T, 1, 8>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
-  if (k % 4 == 0) return time_phase_t<T, 4, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
-  if (k % 2 == 0) return time_phase_t<T, 2, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
-  return time_phase_t<T, 1, 1>(N, k, phase, rowptr, col, val, diag, X, w, reps, ms, s);
+    return time_phase_t<T, 8, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
+  if (k == 1) return time_phase_t<T, 1, 8>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
+  if (k % 4 == 0) return time_phase_t<T, 4, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
+  if (k % 2 == 0) return time_phase_t<T, 2, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
+  return time_phase_t<T, 1, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
 }
 template int pcg_time_phase<double>(int, int, int, const int32_t *, const int32_t *, const double *,
-                                    const double *, double *, PCGWork &, int, float *, hipStream_t);
+                                    const int32_t *, const double *, double *, PCGWork &, int, float *, hipStream_t);
 template int pcg_time_phase<float>(int, int, int, const int32_t *, const int32_t *, const float *,
-                                   const float *, float *, PCGWork &, int, float *, hipStream_t);
+                                   const int32_t *, const float *, float *, PCGWork &, int, float *, hipStream_t);
 
 template <typename T>
-int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val, const T *diag,
-              const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
+int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
+              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
               double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s) {
   // vector access needs VW-aligned base pointers (row strides are k)
   auto al = [](const void *p, size_t bytes) {
@@ -692,29 +699,29 @@ int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *
   };
   const bool a32 = al(B, 32) && al(X, 32), a16 = al(B, 16) && al(X, 16);
   if (sizeof(T) == 4 && k % 8 == 0 && a32)
-    return pcg_run<T, 8, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+    return pcg_run<T, 8, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
   if (k != 1 && !(sizeof(T) * 4 <= 16 ? a16 : a32))
-    return pcg_run<T, 1, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+    return pcg_run<T, 1, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
   if (k == 1)
-    return pcg_run<T, 1, 8>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+    return pcg_run<T, 1, 8>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
   if (k % 4 == 0)
-    return pcg_run<T, 4, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+    return pcg_run<T, 4, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
   if (k % 2 == 0)
-    return pcg_run<T, 2, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+    return pcg_run<T, 2, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                             relres_out, converged_out, breakdown_out, s);
-  return pcg_run<T, 1, 1>(N, k, rowptr, col, val, diag, B, X, tol, max_iter, w, iters_out,
+  return pcg_run<T, 1, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
                           relres_out, converged_out, breakdown_out, s);
 }
 
 template int pcg_solve<double>(int, int, const int32_t *, const int32_t *, const double *,
-                               const double *, const double *, double *, double, int, PCGWork &,
+                               const int32_t *, const double *, const double *, double *, double, int, PCGWork &,
                                int *, double *, int *, int *, hipStream_t);
 template int pcg_solve<float>(int, int, const int32_t *, const int32_t *, const float *,
-                              const float *, const float *, float *, double, int, PCGWork &, int *,
+                              const int32_t *, const float *, const float *, float *, double, int, PCGWork &, int *,
                               double *, int *, int *, hipStream_t);
 
 }  // namespace ks
