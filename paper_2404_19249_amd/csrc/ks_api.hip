@@ -555,16 +555,6 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       });
       std::stable_sort(rorder.begin(), rorder.end(),
                        [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-      // within consecutive chunks of the curve, rows of equal length go
-      // together: a wave then runs rows with one nonzero count (P2 rows have
-      // 19..65 nonzeros and a wave lasts as long as its longest row)
-      const int chunk = 2048;
-      for (int c0 = 0; c0 < N; c0 += chunk) {
-        const int c1 = std::min(N, c0 + chunk);
-        std::stable_sort(rorder.begin() + c0, rorder.begin() + c1, [&](int32_t a, int32_t b) {
-          return (rowptr[a + 1] - rowptr[a]) < (rowptr[b + 1] - rowptr[b]);
-        });
-      }
     }
   }
   // basis tables

@@ -477,33 +477,20 @@ __global__ void __launch_bounds__(256) k_pcg_B(int N, int k, int CG, const T *__
   const int c0 = m.cg * VW;
   T al[VW];
   for (int v = 0; v < VW; ++v) al[v] = (c0 + v < k) ? (T)s_alpha[c0 + v] : T(0);
-  // two row groups per trip: all loads are issued before any arithmetic
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
-  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += 2 * gi.step) {
-    int rows[2];
-    bool ok[2];
-    T q[2][VW], r[2][VW], d[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int g = gi.g + h * gi.step;
-      rows[h] = g * rows_per_block + m.wave * m.RPW + m.slot;
-      ok[h] = m.valid && c0 < k && g < gi.end && rows[h] < N;
-      if (ok[h]) {
-        load_row<T, VW>(Q, rows[h], k, c0, k, q[h]);
-        load_row<T, VW>(R, rows[h], k, c0, k, r[h]);
-        d[h] = diag[rows[h]];
-      }
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
+    T q[VW], r[VW];
+    load_row<T, VW>(Q, row, k, c0, k, q);
+    load_row<T, VW>(R, row, k, c0, k, r);
+    const T d = diag[row];
+    for (int v = 0; v < VW; ++v) {
+      r[v] -= al[v] * q[v];
+      arr[v] += (double)r[v] * (double)r[v];
+      arz[v] += (double)r[v] * (double)(r[v] / d);
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (!ok[h]) continue;
-      for (int v = 0; v < VW; ++v) {
-        r[h][v] -= al[v] * q[h][v];
-        arr[v] += (double)r[h][v] * (double)r[h][v];
-        arz[v] += (double)r[h][v] * (double)(r[h][v] / d[h]);
-      }
-      store_row<T, VW>(R, rows[h], k, c0, k, r[h]);
-    }
+    store_row<T, VW>(R, row, k, c0, k, r);
   }
   block_cols<VW, 1>(arz, m, k, CG, s_red, part, 2 * k, 0);
   block_cols<VW, 1>(arr, m, k, CG, s_red, part, 2 * k, k);
@@ -562,32 +549,20 @@ __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__
     be[v] = (c0 + v < k) ? (T)s_ab[MAX_K + c0 + v] : T(0);
   }
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
-  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += 2 * gi.step) {
-    int rows[2];
-    bool ok[2];
-    T x[2][VW], p[2][VW], r[2][VW], d[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int g = gi.g + h * gi.step;
-      rows[h] = g * rows_per_block + m.wave * m.RPW + m.slot;
-      ok[h] = m.valid && c0 < k && g < gi.end && rows[h] < N;
-      if (ok[h]) {
-        load_row<T, VW>(X, rows[h], k, c0, k, x[h]);
-        load_row<T, VW>(P, rows[h], k, c0, k, p[h]);
-        load_row<T, VW>(R, rows[h], k, c0, k, r[h]);
-        d[h] = diag[rows[h]];
-      }
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
+    T x[VW], p[VW], r[VW];
+    load_row<T, VW>(X, row, k, c0, k, x);
+    load_row<T, VW>(P, row, k, c0, k, p);
+    load_row<T, VW>(R, row, k, c0, k, r);
+    const T d = diag[row];
+    for (int v = 0; v < VW; ++v) {
+      x[v] += al[v] * p[v];
+      p[v] = r[v] / d + be[v] * p[v];
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (!ok[h]) continue;
-      for (int v = 0; v < VW; ++v) {
-        x[h][v] += al[v] * p[h][v];
-        p[h][v] = r[h][v] / d[h] + be[v] * p[h][v];
-      }
-      store_row<T, VW>(X, rows[h], k, c0, k, x[h]);
-      store_row<T, VW>(P, rows[h], k, c0, k, p[h]);
-    }
+    store_row<T, VW>(X, row, k, c0, k, x);
+    store_row<T, VW>(P, row, k, c0, k, p);
   }
 }
 
