@@ -117,6 +117,10 @@ def main():
     occ = w.occ
     copy_gbs = copy_probe(torch)
     log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
+    ctx.assemble(psi, occ, want_fields=False)
+    tune = ctx.autotune(k, reps=10)
+    log(f"[bench] autotune: order={tune['order']} NG fp64={tune['ng_fp64']} fp32={tune['ng_fp32']} "
+        f"poisson={tune['ng_poisson']} ms={json.dumps(tune['ms'])}")
     if args.mode == "solve":
         args.warmup, args.steps = 0, 0
     for i in range(args.warmup):
@@ -197,6 +201,7 @@ def main():
                    "value_basis": "N*k / device time of the block solve inside each timed step"},
         "roofline": roof,
         "copy_probe_GBs": copy_gbs,
+        "autotune": tune,
         "pcg_phases": phases,
         "block_solve": forms,
         "step": {} if not reps else {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),

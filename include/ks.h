@@ -206,6 +206,16 @@ int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const 
  * 6 the Hartree Poisson SpMM phase (k = 1).  Requires a prior ks_assemble. */
 int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
 
+/* Autotuner of the SpMM launch shape: on the current operator S (and the
+ * Poisson operator K), times the SpMM phase of the block PCG for every row
+ * schedule (numbering order, Morton order of the node coordinates) and every
+ * split of a row's nonzeros over NG = 1, 2, 4, 8 lanes, in FP64 and FP32
+ * with k columns (Poisson: k = 1), and keeps the fastest for later solves of
+ * this context.  report_host (NULL to skip) receives 28 doubles:
+ * {order, NG fp64, NG fp32, NG Poisson, then ms[order][fp64|fp32|Poisson][NG]}.
+ * Requires a prior ks_assemble. */
+int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
+
 /* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",
  * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom")
  * into the device buffer dst.  For tests and debugging only. */

@@ -81,6 +81,7 @@ _SIGS = {
                                C.POINTER(C.c_int32)]),
     "ks_initial_guess": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
     "ks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "ks_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ks_debug_buffer": (C.c_int, [_P, C.c_char_p, _P, C.c_int64]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),

@@ -185,6 +185,18 @@ class KSContext:
         B.check(self.lib.ks_time_kernel(self.h, int(which), int(k), int(reps), C.byref(ms)), self.lib)
         return ms.value
 
+    def autotune(self, k, reps=10):
+        """ks_autotune: pick the SpMM row schedule and lanes-per-row split."""
+        rep = (C.c_double * 28)()
+        B.check(self.lib.ks_autotune(self.h, int(k), int(reps), rep), self.lib)
+        r = list(rep)
+        names = ["fp64", "fp32", "poisson"]
+        return {"order": "morton" if r[0] else "natural", "ng_fp64": int(r[1]),
+                "ng_fp32": int(r[2]), "ng_poisson": int(r[3]),
+                "ms": {("morton" if o else "natural"): {names[w]: dict(zip([1, 2, 4, 8],
+                       r[4 + o * 12 + w * 4: 8 + o * 12 + w * 4])) for w in range(3)}
+                       for o in range(2)}}
+
     def debug_buffer(self, name, n):
         """Copy of an internal buffer (diagnostics)."""
         t = self.empty(n)

@@ -99,12 +99,14 @@ struct PCGWork {
 };
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
-              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
-              double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s);
+              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter,
+              PCGWork &w, int *iters_out, double *relres_out, int *converged_out,
+              int *breakdown_out, hipStream_t s, int ng = 0);
 size_t pcg_state_bytes(int k);
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
-                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s);
+                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms,
+                   hipStream_t s, int ng = 0);
 
 // ------------------------------------------------------------------- dense
 // C[a][b] = sum_i Z[i][a] Y[i][b] for a < ma, b < nb (tall-skinny, FP64

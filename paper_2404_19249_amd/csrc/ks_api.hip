@@ -96,7 +96,9 @@ struct ks_ctx {
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
   // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
   int32_t *rowptr = nullptr, *col = nullptr, *rowptrB = nullptr, *colB = nullptr;
-  int32_t *rorder = nullptr;  // spatially local row schedule of the SpMM kernels
+  int32_t *rorder = nullptr;    // active row schedule of the SpMM kernels (nullptr = natural)
+  int32_t *rorder_m = nullptr;  // Morton schedule
+  int ng64 = 0, ng32 = 0, ngP = 0;  // lanes per row in the SpMM phase (0 = default)
   double *K = nullptr, *M = nullptr, *AL = nullptr, *base = nullptr, *S = nullptr,
          *MNL = nullptr, *diagS = nullptr, *diagK = nullptr;
   float *S32 = nullptr, *diagS32 = nullptr;
@@ -256,7 +258,7 @@ static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
   double rr[1];
   int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->rhs, c->vh_int,
                             c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
-                            c->s);
+                            c->s, c->ngP);
   if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
   if (brk) return fail(KS_ERR_BREAKDOWN, "Poisson PCG breakdown");
   c->vh_warm = true;
@@ -523,16 +525,14 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       }
     });
   }
-  // row schedule: interior rows in Morton (Z-curve) order of their
-  // coordinates, so the workgroups in flight sweep compact 3D regions and the
-  // neighbour rows they gather stay cached.  KS_ROW_ORDER=natural keeps the
-  // numbering order.
+  // candidate row schedule: interior rows in Morton (Z-curve) order of their
+  // coordinates, so the workgroups in flight sweep compact 3D regions.  The
+  // natural order is the default; ks_autotune (or KS_ROW_ORDER=morton)
+  // selects between them.
   std::vector<int32_t> rorder(N);
   {
-    const char *env = std::getenv("KS_ROW_ORDER");
-    const bool natural = env && std::strcmp(env, "natural") == 0;
     for (int r = 0; r < N; ++r) rorder[r] = r;
-    if (!natural) {
+    {
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
       for (int r = 0; r < N; ++r)
         for (int d = 0; d < 3; ++d) {
@@ -593,7 +593,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(rowptr, N + 1);
   A_(col, c->nnz);
   A_(rowptrB, N + 1);
-  A_(rorder, N);
+  A_(rorder_m, N);
   A_(colB, std::max<int64_t>(1, c->nnzB));
   A_(K, c->nnz_ext);
   A_(M, c->nnz_ext);
@@ -699,7 +699,18 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   H2D(c->rowptr, rowptr.data(), N + 1);
   H2D(c->col, colI.data(), c->nnz);
   H2D(c->rowptrB, rowptrB.data(), N + 1);
-  H2D(c->rorder, rorder.data(), N);
+  H2D(c->rorder_m, rorder.data(), N);
+  {
+    const char *env = std::getenv("KS_ROW_ORDER");
+    c->rorder = (env && std::strcmp(env, "morton") == 0) ? c->rorder_m : nullptr;
+    auto geti = [](const char *n) {
+      const char *v = std::getenv(n);
+      return v ? std::atoi(v) : 0;
+    };
+    c->ng64 = geti("KS_SPMM_NG64");
+    c->ng32 = geti("KS_SPMM_NG32");
+    c->ngP = geti("KS_SPMM_NGP");
+  }
   H2D(c->colB, colB.data(), colB.size());
   H2D(c->Pidx, Pidx.data(), Pidx.size());
   H2D(c->Pw, Pw.data(), Pw.size());
@@ -809,31 +820,84 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
   return fail(KS_ERR_ARG, std::string("unknown buffer ") + name);
 }
 
+// fp32 operator copy on demand
+static void ensure_s32(ks_ctx *c) {
+  if (!c->have_S32) {
+    launch_to_float(c->nnz, c->S, c->S32, c->s);
+    launch_to_float(c->N, c->diagS, c->diagS32, c->s);
+    c->have_S32 = true;
+  }
+}
+
+static int time_phase(ks_ctx *c, int which, int k, int reps, int ng, float *ms) {
+  if (which >= 0 && which <= 2)
+    return pcg_time_phase<double>(c->N, k, which, c->rowptr, c->col, c->S, c->rorder, c->diagS,
+                                  c->Xv, c->pw64, reps, ms, c->s, ng);
+  if (which >= 3 && which <= 5) {
+    ensure_s32(c);
+    return pcg_time_phase<float>(c->N, k, which - 3, c->rowptr, c->col, c->S32, c->rorder,
+                                 c->diagS32, c->X32, c->pw32, reps, ms, c->s, ng);
+  }
+  return pcg_time_phase<double>(c->N, 1, 0, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->vh_int,
+                                c->pwP, reps, ms, c->s, ng);
+}
+
 extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps, double *ms_host) {
   if (!c || !ms_host) return fail(KS_ERR_ARG, "null argument");
   if (reps < 1 || k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
+  if (which < 0 || which > 6) return fail(KS_ERR_ARG, "which must be 0..6");
+  const int ng = (which <= 2) ? c->ng64 : (which <= 5 ? c->ng32 : c->ngP);
   float ms = 0.f;
-  int r = 0;
-  if (which >= 0 && which <= 2) {
-    r = pcg_time_phase<double>(c->N, k, which, c->rowptr, c->col, c->S, c->rorder, c->diagS, c->Xv, c->pw64,
-                               reps, &ms, c->s);
-  } else if (which >= 3 && which <= 5) {
-    if (!c->have_S32) {
-      launch_to_float(c->nnz, c->S, c->S32, c->s);
-      launch_to_float(c->N, c->diagS, c->diagS32, c->s);
-      c->have_S32 = true;
-    }
-    r = pcg_time_phase<float>(c->N, k, which - 3, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->X32,
-                              c->pw32, reps, &ms, c->s);
-  } else if (which == 6) {
-    r = pcg_time_phase<double>(c->N, 1, 0, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->vh_int, c->pwP,
-                               reps, &ms, c->s);
-  } else {
-    return fail(KS_ERR_ARG, "which must be 0..6");
-  }
-  if (r < 0) return fail(KS_ERR_HIP, "timing launch failed");
+  if (time_phase(c, which, k, reps, ng, &ms) < 0) return fail(KS_ERR_HIP, "timing launch failed");
   *ms_host = ms;
+  return KS_OK;
+}
+
+// Autotuner: times the SpMM phase of the block PCG (FP64, FP32) and of the
+// Poisson solve on the current operator for every row schedule and lanes-
+// per-row split, and keeps the fastest for this context.
+extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_host) {
+  if (!c) return fail(KS_ERR_ARG, "null context");
+  if (k < 1 || k > c->k_max || reps < 1) return fail(KS_ERR_ARG, "bad k or reps");
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
+  const int ngs[4] = {1, 2, 4, 8};
+  double best_total = 1e300;
+  int best[4] = {0, 0, 0, 0};  // order, ng64, ng32, ngP
+  double times[2][3][4];
+  for (int ord = 0; ord < 2; ++ord) {
+    c->rorder = ord ? c->rorder_m : nullptr;
+    double bt[3] = {1e300, 1e300, 1e300};
+    int bn[3] = {1, 1, 8};
+    for (int w = 0; w < 3; ++w)
+      for (int i = 0; i < 4; ++i) {
+        const int which = w == 0 ? 0 : (w == 1 ? 3 : 6);
+        const int kk = w == 2 ? 1 : k;
+        float ms = 0.f;
+        if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0)
+          return fail(KS_ERR_HIP, "autotune timing failed");
+        times[ord][w][i] = ms;
+        if (ms < bt[w]) {
+          bt[w] = ms;
+          bn[w] = ngs[i];
+        }
+      }
+    const double total = bt[0] + bt[1];
+    if (total < best_total) {
+      best_total = total;
+      best[0] = ord; best[1] = bn[0]; best[2] = bn[1]; best[3] = bn[2];
+    }
+  }
+  c->rorder = best[0] ? c->rorder_m : nullptr;
+  c->ng64 = best[1];
+  c->ng32 = best[2];
+  c->ngP = best[3];
+  if (report_host) {
+    for (int j = 0; j < 4; ++j) report_host[j] = best[j];
+    for (int o = 0; o < 2; ++o)
+      for (int w = 0; w < 3; ++w)
+        for (int i = 0; i < 4; ++i) report_host[4 + o * 12 + w * 4 + i] = times[o][w][i];
+  }
   return KS_OK;
 }
 
@@ -962,7 +1026,8 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
   int conv = 0, brk = 0;
   if (precision == KS_PREC_FP64) {
     int r = pcg_solve<double>(c->N, k, c->rowptr, c->col, c->S, c->rorder, c->diagS, B, X, tol,
-                              c->opt.max_it_solve, c->pw64, loc.iters, loc.relres, &conv, &brk, s);
+                              c->opt.max_it_solve, c->pw64, loc.iters, loc.relres, &conv, &brk, s,
+                              c->ng64);
     if (r < 0) return fail(KS_ERR_HIP, "PCG launch failed");
     if (brk) return fail(KS_ERR_BREAKDOWN, "PCG breakdown: p^T S p <= 0 (S not positive definite; increase mu)");
     loc.refinements = 0;
@@ -1005,7 +1070,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
       int c32 = 0;
       int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->B32, c->X32,
                                c->opt.mixed_inner_tol, c->opt.max_it_solve, c->pw32, it, rr, &c32,
-                               &brk, s);
+                               &brk, s, c->ng32);
       if (r < 0) return fail(KS_ERR_HIP, "FP32 PCG launch failed");
       if (brk) return fail(KS_ERR_BREAKDOWN, "FP32 PCG breakdown");
       for (int j = 0; j < k; ++j) total_it[j] += it[j];

@@ -589,7 +589,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
                    const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w,
                    int *iters_out, double *relres_out, int *converged_out, int *breakdown_out,
                    hipStream_t s) {
-  const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
+  const int CG = (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
   const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
@@ -635,7 +635,7 @@ template <typename T, int VW, int NG>
 static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const int32_t *col,
                         const T *val, const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms,
                         hipStream_t s) {
-  const int CG = (NG > 1) ? 1 : (k + VW - 1) / VW;
+  const int CG = (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
   const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
@@ -674,54 +674,78 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   return hipStreamSynchronize(s) == hipSuccess ? 0 : -2;
 }
 
+
+
+// Vector width: 8 (FP32) / 4 / 2 / 1 values per lane, the widest that divides
+// k and fits the pointer alignment.  NG lanes share a row's nonzeros
+// (ng <= 0 picks the default: 8 for k = 1, 1 otherwise).
 template <typename T>
-int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
-                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms, hipStream_t s) {
-  if (sizeof(T) == 4 && k % 8 == 0)
-    return time_phase_t<T, 8, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
-  if (k == 1) return time_phase_t<T, 1, 8>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
-  if (k % 4 == 0) return time_phase_t<T, 4, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
-  if (k % 2 == 0) return time_phase_t<T, 2, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
-  return time_phase_t<T, 1, 1>(N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s);
+static int pick_vw(int k, const void *B, const void *X) {
+  auto al = [](const void *p, size_t bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; };
+  if (k == 1) return 1;
+  if (sizeof(T) == 4 && k % 8 == 0 && al(B, 32) && al(X, 32)) return 8;
+  if (k % 4 == 0 && al(B, 4 * sizeof(T)) && al(X, 4 * sizeof(T))) return 4;
+  if (k % 2 == 0 && al(B, 2 * sizeof(T)) && al(X, 2 * sizeof(T))) return 2;
+  return 1;
 }
-template int pcg_time_phase<double>(int, int, int, const int32_t *, const int32_t *, const double *,
-                                    const int32_t *, const double *, double *, PCGWork &, int, float *, hipStream_t);
-template int pcg_time_phase<float>(int, int, int, const int32_t *, const int32_t *, const float *,
-                                   const int32_t *, const float *, float *, PCGWork &, int, float *, hipStream_t);
+static int fit_ng(int k, int vw, int ng) {
+  if (ng <= 0) ng = (k == 1) ? 8 : 1;
+  const int cg = (k + vw - 1) / vw;
+  while (ng > 1 && cg * ng > 64) ng >>= 1;
+  return ng;
+}
+
+#define KS_PCG_DISPATCH(FN, ...)                                                 \
+  switch (vw * 16 + ng) {                                                        \
+    case 8 * 16 + 1: return FN<T, (sizeof(T) == 4 ? 8 : 4), 1>(__VA_ARGS__);     \
+    case 8 * 16 + 2: return FN<T, (sizeof(T) == 4 ? 8 : 4), 2>(__VA_ARGS__);     \
+    case 8 * 16 + 4: return FN<T, (sizeof(T) == 4 ? 8 : 4), 4>(__VA_ARGS__);     \
+    case 8 * 16 + 8: return FN<T, (sizeof(T) == 4 ? 8 : 4), 8>(__VA_ARGS__);     \
+    case 4 * 16 + 1: return FN<T, 4, 1>(__VA_ARGS__);                             \
+    case 4 * 16 + 2: return FN<T, 4, 2>(__VA_ARGS__);                             \
+    case 4 * 16 + 4: return FN<T, 4, 4>(__VA_ARGS__);                             \
+    case 4 * 16 + 8: return FN<T, 4, 8>(__VA_ARGS__);                             \
+    case 2 * 16 + 1: return FN<T, 2, 1>(__VA_ARGS__);                             \
+    case 2 * 16 + 2: return FN<T, 2, 2>(__VA_ARGS__);                             \
+    case 2 * 16 + 4: return FN<T, 2, 4>(__VA_ARGS__);                             \
+    case 2 * 16 + 8: return FN<T, 2, 8>(__VA_ARGS__);                             \
+    case 1 * 16 + 2: return FN<T, 1, 2>(__VA_ARGS__);                             \
+    case 1 * 16 + 4: return FN<T, 1, 4>(__VA_ARGS__);                             \
+    case 1 * 16 + 8: return FN<T, 1, 8>(__VA_ARGS__);                             \
+    default: return FN<T, 1, 1>(__VA_ARGS__);                                     \
+  }
 
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
-              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w, int *iters_out,
-              double *relres_out, int *converged_out, int *breakdown_out, hipStream_t s) {
-  // vector access needs VW-aligned base pointers (row strides are k)
-  auto al = [](const void *p, size_t bytes) {
-    return (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
-  };
-  const bool a32 = al(B, 32) && al(X, 32), a16 = al(B, 16) && al(X, 16);
-  if (sizeof(T) == 4 && k % 8 == 0 && a32)
-    return pcg_run<T, 8, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                            relres_out, converged_out, breakdown_out, s);
-  if (k != 1 && !(sizeof(T) * 4 <= 16 ? a16 : a32))
-    return pcg_run<T, 1, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                            relres_out, converged_out, breakdown_out, s);
-  if (k == 1)
-    return pcg_run<T, 1, 8>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                            relres_out, converged_out, breakdown_out, s);
-  if (k % 4 == 0)
-    return pcg_run<T, 4, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                            relres_out, converged_out, breakdown_out, s);
-  if (k % 2 == 0)
-    return pcg_run<T, 2, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                            relres_out, converged_out, breakdown_out, s);
-  return pcg_run<T, 1, 1>(N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                          relres_out, converged_out, breakdown_out, s);
+              const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter,
+              PCGWork &w, int *iters_out, double *relres_out, int *converged_out,
+              int *breakdown_out, hipStream_t s, int ng) {
+  const int vw = pick_vw<T>(k, B, X);
+  ng = fit_ng(k, vw, ng);
+  KS_PCG_DISPATCH(pcg_run, N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
+                  relres_out, converged_out, breakdown_out, s)
 }
 
 template int pcg_solve<double>(int, int, const int32_t *, const int32_t *, const double *,
-                               const int32_t *, const double *, const double *, double *, double, int, PCGWork &,
-                               int *, double *, int *, int *, hipStream_t);
+                               const int32_t *, const double *, const double *, double *, double, int,
+                               PCGWork &, int *, double *, int *, int *, hipStream_t, int);
 template int pcg_solve<float>(int, int, const int32_t *, const int32_t *, const float *,
-                              const int32_t *, const float *, const float *, float *, double, int, PCGWork &, int *,
-                              double *, int *, int *, hipStream_t);
+                              const int32_t *, const float *, const float *, float *, double, int,
+                              PCGWork &, int *, double *, int *, int *, hipStream_t, int);
+
+template <typename T>
+int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
+                   const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms,
+                   hipStream_t s, int ng) {
+  const int vw = pick_vw<T>(k, w.R, X);
+  ng = fit_ng(k, vw, ng);
+  KS_PCG_DISPATCH(time_phase_t, N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s)
+}
+template int pcg_time_phase<double>(int, int, int, const int32_t *, const int32_t *, const double *,
+                                    const int32_t *, const double *, double *, PCGWork &, int, float *,
+                                    hipStream_t, int);
+template int pcg_time_phase<float>(int, int, int, const int32_t *, const int32_t *, const float *,
+                                   const int32_t *, const float *, float *, PCGWork &, int, float *,
+                                   hipStream_t, int);
 
 }  // namespace ks
