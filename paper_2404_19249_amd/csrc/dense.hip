@@ -457,6 +457,331 @@ __global__ void __launch_bounds__(EIG_THREADS) k_small_eig(int m, int k, const d
   }
 }
 
+// ------------------------------------------- packed-LDS Jacobi (m <= 190)
+// The symmetric matrix (padded to even order ne with a zero row/column) is
+// kept as its packed upper triangle in LDS.  One round rotates the ne/2
+// disjoint pairs of the round-robin schedule at once: every 2x2 block
+// (pair t1 rows, pair t2 columns), t1 <= t2, is transformed by J1^T B J2 by
+// one thread, so a round has no read/write conflicts.  Eigenvectors are
+// accumulated in V (global, ld = n).  A pair is rotated while
+// |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and above an absolute floor; the sweep
+// loop stops after a sweep without rotations.
+constexpr int PJ_MAXN = 190;  // packed (190*191/2) doubles = 145 KB of the 160 KB LDS
+constexpr int PJ_PACK = (PJ_MAXN * (PJ_MAXN + 1)) / 2;
+
+__device__ __forceinline__ int pk(int i, int j, int ne) {
+  if (i > j) { int t = i; i = j; j = t; }
+  return i * ne - (i * (i - 1)) / 2 + (j - i);
+}
+
+__device__ int jacobi_packed(int n, double *sA, double *V, bool initV, int *s_top, int *s_bot,
+                             int *s_top2, int *s_bot2, double *s_c, double *s_s, int *s_p,
+                             int *s_q, int *s_cnt, double *s_red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ne = (n + 1) & ~1, h = ne / 2;
+  if (initV)
+    for (int idx = tid; idx < n * n; idx += nt) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+  double loc = 0.0;
+  for (int idx = tid; idx < ne * (ne + 1) / 2; idx += nt) loc += sA[idx] * sA[idx];
+  const double fro2 = block_sum(loc, s_red);
+  if (tid == 0) s_red[16] = sqrt(fro2);
+  for (int t = tid; t < h; t += nt) {
+    s_top[t] = 2 * t;
+    s_bot[t] = 2 * t + 1;
+  }
+  __syncthreads();
+  const double floor_abs = 1e-300 + 1e-18 * s_red[16];
+  int sweeps = 0;
+  for (; sweeps < 60; ++sweeps) {
+    if (tid == 0) *s_cnt = 0;
+    __syncthreads();
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int t = tid; t < h; t += nt) {
+        int p = s_top[t], q = s_bot[t];
+        if (p > q) { int x = p; p = q; q = x; }
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double apq = sA[pk(p, q, ne)], app = sA[pk(p, p, ne)], aqq = sA[pk(q, q, ne)];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double tt = fabs(th) > 1e150 ? 0.5 / th
+                                               : (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sn = tt * c;
+            atomicAdd(s_cnt, 1);
+          }
+        }
+        s_p[t] = p; s_q[t] = q; s_c[t] = c; s_s[t] = sn;
+      }
+      __syncthreads();
+      // 2x2 blocks of A
+      for (int idx = tid; idx < h * h; idx += nt) {
+        const int t1 = idx / h, t2 = idx % h;
+        if (t2 < t1) continue;
+        const double c1 = s_c[t1], s1 = s_s[t1], c2 = s_c[t2], s2 = s_s[t2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = s_p[t1], q1 = s_q[t1], p2 = s_p[t2], q2 = s_q[t2];
+        if (t1 == t2) {
+          const int ipp = pk(p1, p1, ne), iqq = pk(q1, q1, ne), ipq = pk(p1, q1, ne);
+          const double app = sA[ipp], aqq = sA[iqq], apq = sA[ipq];
+          sA[ipp] = c1 * c1 * app - 2.0 * c1 * s1 * apq + s1 * s1 * aqq;
+          sA[iqq] = s1 * s1 * app + 2.0 * c1 * s1 * apq + c1 * c1 * aqq;
+          sA[ipq] = 0.0;
+        } else {
+          const int i00 = pk(p1, p2, ne), i01 = pk(p1, q2, ne), i10 = pk(q1, p2, ne),
+                    i11 = pk(q1, q2, ne);
+          const double b00 = sA[i00], b01 = sA[i01], b10 = sA[i10], b11 = sA[i11];
+          // rows (p1, q1) by J1^T, then columns (p2, q2) by J2
+          const double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;
+          const double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
+          sA[i00] = c2 * r00 - s2 * r01;
+          sA[i01] = s2 * r00 + c2 * r01;
+          sA[i10] = c2 * r10 - s2 * r11;
+          sA[i11] = s2 * r10 + c2 * r11;
+        }
+      }
+      // eigenvector columns
+      for (int idx = tid; idx < h * n; idx += nt) {
+        const int t = idx / n, i = idx % n;
+        const double sn = s_s[t];
+        if (sn == 0.0) continue;
+        const int p = s_p[t], q = s_q[t];
+        const double c = s_c[t];
+        const double vp = V[i * n + p], vq = V[i * n + q];
+        V[i * n + p] = c * vp - sn * vq;
+        V[i * n + q] = sn * vp + c * vq;
+      }
+      // next round-robin arrangement (player top[0] fixed), built in parallel
+      for (int t = tid; t < h; t += nt) {
+        s_top2[t] = (t == 0) ? s_top[0] : (t == 1 ? s_bot[0] : s_top[t - 1]);
+        s_bot2[t] = (t == h - 1) ? s_top[h - 1] : s_bot[t + 1];
+      }
+      __syncthreads();
+      for (int t = tid; t < h; t += nt) {
+        s_top[t] = s_top2[t];
+        s_bot[t] = s_bot2[t];
+      }
+      __syncthreads();
+    }
+    const int cnt = *s_cnt;
+    __syncthreads();
+    if (cnt == 0) break;
+  }
+  return sweeps;
+}
+
+// Canonical orthogonalisation of F_B (once per augmented space):
+// D = diag(F_B)^{-1/2}, D F_B D = V s V^T, X = V_keep s_keep^{-1/2} (keep
+// s > 1e-12 s_max), X stored [m][r] with ld m.  info[0] = r, info[2] = 1 on a
+// non-positive diagonal, info[3] = sweeps.
+__global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__restrict__ FB, int ldfb,
+                                                      double *__restrict__ D, double *__restrict__ V,
+                                                      double *__restrict__ X, int *info) {
+  extern __shared__ double sA[];
+  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
+      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
+  __shared__ int s_cnt, s_rank, s_keep[PJ_MAXN];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ne = (m + 1) & ~1;
+  for (int i = tid; i < m; i += nt) {
+    const double b = FB[(int64_t)i * ldfb + i];
+    D[i] = b > 0.0 ? 1.0 / sqrt(b) : 0.0;
+    if (!(b > 0.0)) info[2] = 1;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ne * ne; idx += nt) {
+    const int i = idx / ne, j = idx % ne;
+    if (j < i) continue;
+    double v = 0.0;
+    if (i < m && j < m) v = D[i] * D[j] * 0.5 * (FB[(int64_t)i * ldfb + j] + FB[(int64_t)j * ldfb + i]);
+    sA[pk(i, j, ne)] = v;
+  }
+  __syncthreads();
+  const int sw = jacobi_packed(m, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q,
+                               &s_cnt, s_red);
+  for (int i = tid; i < m; i += nt) s_sv[i] = sA[pk(i, i, ne)];
+  __syncthreads();
+  if (tid == 0) {
+    double smax = 0.0;
+    for (int i = 0; i < m; ++i) smax = fmax(smax, s_sv[i]);
+    int r = 0;
+    for (int i = 0; i < m; ++i)
+      if (s_sv[i] > 1e-12 * smax) s_keep[r++] = i;
+    s_rank = r;
+  }
+  __syncthreads();
+  const int r = s_rank;
+  for (int idx = tid; idx < m * r; idx += nt) {
+    const int i = idx / r, a = idx % r;
+    const int c = s_keep[a];
+    X[(int64_t)i * m + a] = V[(int64_t)i * m + c] / sqrt(s_sv[c]);
+  }
+  if (tid == 0) {
+    info[0] = r;
+    info[3] = sw;
+  }
+}
+
+// Lowest k eigenpairs of the pencil with F_B already orthogonalised by
+// k_orth: C = X^T (D F_A D) X (r x r), optionally rotated by the previous
+// eigenvector matrix W (warm start: C <- W^T C W), Jacobi, W <- W V, ascending
+// order, U = D X W_sel with the largest-magnitude entry of each column
+// positive.  W (r x r, ld r) is in/out; theta [r].
+__global__ void __launch_bounds__(EIG_THREADS) k_reduced_eig(int m, int k, int r,
+                                                             const double *__restrict__ FA, int ldfa,
+                                                             const double *__restrict__ D,
+                                                             const double *__restrict__ X,
+                                                             double *__restrict__ W, int warm,
+                                                             double *__restrict__ T1,
+                                                             double *__restrict__ T2,
+                                                             double *__restrict__ V,
+                                                             double *__restrict__ theta,
+                                                             double *__restrict__ U, int *info) {
+  extern __shared__ double sA[];
+  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
+      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
+  __shared__ int s_cnt, s_sel[PJ_MAXN];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ne = (r + 1) & ~1;
+  // T1 = (D FA D) X   (m x r, ld r)
+  for (int idx = tid; idx < m * r; idx += nt) {
+    const int i = idx / r, a = idx % r;
+    double s = 0.0;
+    for (int j = 0; j < m; ++j)
+      s += 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]) * D[j] * X[(int64_t)j * m + a];
+    T1[idx] = D[i] * s;
+  }
+  __syncthreads();
+  // C = X^T T1 (r x r) into T2, symmetrised
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int a = idx / r, b = idx % r;
+    if (b < a) continue;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      s1 += X[(int64_t)i * m + a] * T1[i * r + b];
+      s2 += X[(int64_t)i * m + b] * T1[i * r + a];
+    }
+    T2[a * r + b] = T2[b * r + a] = 0.5 * (s1 + s2);
+  }
+  __syncthreads();
+  if (warm) {
+    // T1 = C W ; C' = W^T T1 (packed into LDS)
+    for (int idx = tid; idx < r * r; idx += nt) {
+      const int a = idx / r, b = idx % r;
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s += T2[a * r + l] * W[l * r + b];
+      T1[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < ne * ne; idx += nt) {
+      const int a = idx / ne, b = idx % ne;
+      if (b < a) continue;
+      double v = 0.0;
+      if (a < r && b < r) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int l = 0; l < r; ++l) {
+          s1 += W[l * r + a] * T1[l * r + b];
+          s2 += W[l * r + b] * T1[l * r + a];
+        }
+        v = 0.5 * (s1 + s2);
+      }
+      sA[pk(a, b, ne)] = v;
+    }
+  } else {
+    for (int idx = tid; idx < ne * ne; idx += nt) {
+      const int a = idx / ne, b = idx % ne;
+      if (b < a) continue;
+      sA[pk(a, b, ne)] = (a < r && b < r) ? T2[a * r + b] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int sw = jacobi_packed(r, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q,
+                               &s_cnt, s_red);
+  // W <- W V (or V)
+  if (warm) {
+    for (int idx = tid; idx < r * r; idx += nt) {
+      const int a = idx / r, b = idx % r;
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s += W[a * r + l] * V[l * r + b];
+      T1[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < r * r; idx += nt) W[idx] = T1[idx];
+  } else {
+    for (int idx = tid; idx < r * r; idx += nt) W[idx] = V[idx];
+  }
+  for (int i = tid; i < r; i += nt) s_sv[i] = sA[pk(i, i, ne)];
+  __syncthreads();
+  for (int i = tid; i < r; i += nt) {
+    const double v = s_sv[i];
+    int rk = 0;
+    for (int j = 0; j < r; ++j) rk += (s_sv[j] < v) || (s_sv[j] == v && j < i);
+    s_sel[rk] = i;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += nt) theta[i] = s_sv[s_sel[i]];
+  for (int idx = tid; idx < m * k; idx += nt) {
+    const int i = idx / k, j = idx % k;
+    double s = 0.0;
+    if (j < r) {
+      const int c = s_sel[j];
+      for (int a = 0; a < r; ++a) s += X[(int64_t)i * m + a] * W[a * r + c];
+    }
+    U[idx] = D[i] * s;
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += nt) {
+    int im = 0;
+    double vm = -1.0;
+    for (int i = 0; i < m; ++i) {
+      const double a = fabs(U[i * k + j]);
+      if (a > vm) { vm = a; im = i; }
+    }
+    if (U[im * k + j] < 0.0)
+      for (int i = 0; i < m; ++i) U[i * k + j] = -U[i * k + j];
+  }
+  if (tid == 0) {
+    info[0] = r;
+    info[1] = sw;
+  }
+}
+
+size_t orth_shared_bytes(int m) {
+  const int ne = (m + 1) & ~1;
+  return sizeof(double) * (size_t)ne * (ne + 1) / 2;
+}
+int packed_eig_supported(int m) { return m <= PJ_MAXN; }
+static int lds_ready = 0;
+// the packed matrix needs more than the default 64 KB of dynamic LDS
+static int enable_big_lds() {
+  if (lds_ready) return 0;
+  const int bytes = (int)orth_shared_bytes(PJ_MAXN);
+  if (hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void *)k_reduced_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          bytes) != hipSuccess)
+    return -1;
+  lds_ready = 1;
+  return 0;
+}
+int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, int *info,
+                hipStream_t s) {
+  if (enable_big_lds() < 0) return -1;
+  hipLaunchKernelGGL(k_orth, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(m), s, m, FB, ldfb, D, V, X,
+                     info);
+  return 0;
+}
+int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const double *D,
+                       const double *X, double *W, int warm, double *T1, double *T2, double *V,
+                       double *theta, double *U, int *info, hipStream_t s) {
+  if (enable_big_lds() < 0) return -1;
+  hipLaunchKernelGGL(k_reduced_eig, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, m, k, r, FA,
+                     ldfa, D, X, W, warm, T1, T2, V, theta, U, info);
+  return 0;
+}
+
 void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB, int ldfb,
                       double *work, double *theta, double *U, int *info, hipStream_t s) {
   hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(EIG_THREADS), 0, s, m, k, FA, ldfa, FB, ldfb, work,

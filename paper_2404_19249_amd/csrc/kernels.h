@@ -129,6 +129,16 @@ void launch_small_gemm(int m, int n, int p, const double *A, int lda, const doub
 void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB, int ldfb,
                       double *work, double *theta, double *U, int *info, hipStream_t s);
 size_t small_eig_work_doubles(int m);
+// Two-stage small eigensolver (m <= 190, packed symmetric matrices in LDS):
+// launch_orth once per augmented space, launch_reduced_eig per F_A.  The
+// launchers return -1 if the large-LDS attribute cannot be set.
+int packed_eig_supported(int m);
+size_t orth_shared_bytes(int m);
+int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, int *info,
+                hipStream_t s);
+int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const double *D,
+                       const double *X, double *W, int warm, double *T1, double *T2, double *V,
+                       double *theta, double *U, int *info, hipStream_t s);
 // Dense P (first n_H columns of Z) from the ELL form
 void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,
                     hipStream_t s);

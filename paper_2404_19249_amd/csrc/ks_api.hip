@@ -121,6 +121,10 @@ struct ks_ctx {
          *coef = nullptr, *redpart = nullptr;
   size_t gwork_n = 0;
   int *einfo = nullptr;
+  // two-stage eigensolver state: D, V, X (orthogonalised F_B basis), W (warm
+  // start eigenvectors), scratch T1, T2; rank r of the current F_B
+  double *eD = nullptr, *eV = nullptr, *eX = nullptr, *eW = nullptr, *eT1 = nullptr, *eT2 = nullptr;
+  int e_rank = 0, e_m = 0;
   // block vectors [N][k_max]
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
          *occ_d = nullptr, *scal = nullptr;
@@ -646,6 +650,12 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(coef, 64);
   A_(redpart, (size_t)1024 * 32);
   A_(einfo, 8);
+  A_(eD, mm);
+  A_(eV, (size_t)mm * mm);
+  A_(eX, (size_t)mm * mm);
+  A_(eW, (size_t)mm * mm);
+  A_(eT1, (size_t)mm * mm);
+  A_(eT2, (size_t)mm * mm);
   A_(Bv, (size_t)N * km);
   A_(Xv, (size_t)N * km);
   A_(Wv, (size_t)N * km);
@@ -1171,19 +1181,52 @@ extern "C" int ks_augmented_project(ks_ctx *c, const double *psi_hat, int32_t k,
 }
 
 // ---------------------------------------------------------------- eigen
-static int eig_impl(ks_ctx *c, const double *FA, const double *FB, int m, int k, double *U,
-                    std::vector<double> &theta_all, int *rank) {
+// Orthogonalise the pencil's F_B (once per augmented space); rank in c->e_rank.
+static int orth_impl(ks_ctx *c, const double *FB, int m) {
+  if (!packed_eig_supported(m)) {
+    c->e_m = 0;
+    return KS_OK;  // the one-stage fallback handles it per call
+  }
   HIPCHK(hipMemsetAsync(c->einfo, 0, 8 * sizeof(int), c->s));
-  launch_small_eig(m, k, FA, m, FB, m, c->eigwork, c->theta, U, c->einfo, c->s);
+  if (launch_orth(m, FB, m, c->eD, c->eV, c->eX, c->einfo, c->s) < 0)
+    return fail(KS_ERR_HIP, "cannot enable the LDS size of the eigensolver");
   int info[8];
-  theta_all.resize(m);
   HIPCHK(hipMemcpyAsync(info, c->einfo, sizeof(int) * 8, hipMemcpyDeviceToHost, c->s));
-  HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * m, hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
   if (info[2]) return fail(KS_ERR_EIG, "F_B has a non-positive diagonal entry");
-  if (info[0] < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(info[0]) + " < k");
-  theta_all.resize(info[0]);
-  if (rank) *rank = info[0];
+  c->e_rank = info[0];
+  c->e_m = m;
+  return KS_OK;
+}
+
+// Lowest k eigenpairs of (FA, FB) (FB orthogonalised by orth_impl); warm:
+// start from the eigenvectors of the previous call on the same F_B.
+static int eig_impl(ks_ctx *c, const double *FA, const double *FB, int m, int k, double *U,
+                    std::vector<double> &theta_all, int *rank, bool warm = false) {
+  if (!packed_eig_supported(m)) {
+    HIPCHK(hipMemsetAsync(c->einfo, 0, 8 * sizeof(int), c->s));
+    launch_small_eig(m, k, FA, m, FB, m, c->eigwork, c->theta, U, c->einfo, c->s);
+    int info[8];
+    theta_all.resize(m);
+    HIPCHK(hipMemcpyAsync(info, c->einfo, sizeof(int) * 8, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * m, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (info[2]) return fail(KS_ERR_EIG, "F_B has a non-positive diagonal entry");
+    if (info[0] < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(info[0]) + " < k");
+    theta_all.resize(info[0]);
+    if (rank) *rank = info[0];
+    return KS_OK;
+  }
+  if (c->e_m != m) TRY(orth_impl(c, FB, m));
+  const int r = c->e_rank;
+  if (r < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(r) + " < k");
+  if (launch_reduced_eig(m, k, r, FA, m, c->eD, c->eX, c->eW, warm ? 1 : 0, c->eT1, c->eT2, c->eV,
+                         c->theta, U, c->einfo + 4, c->s) < 0)
+    return fail(KS_ERR_HIP, "cannot enable the LDS size of the eigensolver");
+  theta_all.resize(r);
+  HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * r, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (rank) *rank = r;
   return KS_OK;
 }
 
@@ -1193,6 +1236,7 @@ extern "C" int ks_small_eig(ks_ctx *c, const double *FA, const double *FB, int32
   if (m < 1 || m > 256 || k < 1 || k > m || m > c->mp) return fail(KS_ERR_ARG, "bad sizes");
   std::vector<double> th;
   int rank = 0;
+  TRY(orth_impl(c, FB, m));
   TRY(eig_impl(c, FA, FB, m, k, U, th, &rank));
   for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
   if (rank_host) *rank_host = rank;
@@ -1204,6 +1248,7 @@ extern "C" int ks_initial_guess(ks_ctx *c, int32_t k, double *psi, double *lambd
   if (k < 1 || k > c->k_max || k > c->N_H) return fail(KS_ERR_ARG, "bad k");
   std::vector<double> th;
   int rank = 0;
+  TRY(orth_impl(c, c->GPP, c->N_H));
   TRY(eig_impl(c, c->FAL_PP, c->GPP, c->N_H, k, c->U, th, &rank));
   launch_ellP_times(c->N, c->Pidx, c->Pw, c->U, k, k, 1.0, nullptr, 0, psi, k, c->s);
   for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
@@ -1273,7 +1318,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   TRY(build_tail(c, c->PsiHat, k));
   project_tail(c, c->M, c->GPP, k, c->FB);
   project_tail(c, c->AL, c->FAL_PP, k, c->FAL);
-  HIPCHK(hipStreamSynchronize(s));
+  TRY(orth_impl(c, c->FB, m));
   const double t3 = now_s();
   // 4. inner nonlinear iteration
   HIPCHK(hipMemcpyAsync(c->rho_in, c->rho_l, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
@@ -1300,7 +1345,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
     } else {
       HIPCHK(hipMemcpyAsync(c->FA, c->FAL, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
     }
-    TRY(eig_impl(c, c->FA, c->FB, m, k, c->U, th, &rank));
+    TRY(eig_impl(c, c->FA, c->FB, m, k, c->U, th, &rank, it > 0));
     launch_zu(N, c->Pidx, c->Pw, nH, c->Z, c->mp, k, c->U, k, c->PsiNew, s);
     launch_density(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->PsiNew, k, k, c->occ_d,
                    c->rho_out, s);
