@@ -119,6 +119,22 @@ class KSProblem:
         self.Mext_II = fe.restrict(Mext, I, I)
         self.P = coarse_interpolation(self.coords[I], self.L, self.n_H)
 
+    def with_external(self, vext_q=None, R=None):
+        """Copy of the problem with another external potential at the
+        quadrature points (or nuclei moved to R, which also changes E_nn);
+        the mesh and everything else are shared."""
+        import copy
+        q = copy.copy(self)
+        if R is not None:
+            q.R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+            vext_q = external_potential(self.x_q, q.Z, q.R)
+        q.vext_q = np.asarray(vext_q, dtype=np.float64)
+        MVe = fe.element_matrices(self.order, self.quad, self.det, self.gl, V=q.vext_q,
+                                  kind="potential")
+        q.Mext_II = fe.restrict(fe.assemble(self.n_nodes, self.elems, MVe), self.interior,
+                                self.interior)
+        return q
+
     # --- operators --------------------------------------------------------
     @property
     def N(self):
@@ -336,7 +352,8 @@ def ks_scf_step(prob, Psi, lam, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-1
                       theta_all=th_all, U=U, FA=FA, FB=FB, FA_L=FA_L, energies=E,
                       inner_iters=inner_iters, solve_iters=its, solve_relres=rr, rank=rank,
                       extra={"S": S, "w_B": w_B, "rho_l": rho_l, "rho_in": rho_in,
-                             "Z": Z, "res_inner": res})
+                             "Z": Z, "res_inner": res, "vnl_in": VH_q + vxc_in,
+                             "G_PP": G_PP})
 
 
 def step_energy(prob, Psi, rho, rho_l, w_B, tol_poisson=1e-12):
@@ -362,3 +379,48 @@ def step_energy(prob, Psi, rho, rho_l, w_B, tol_poisson=1e-12):
     out["xc"] = prob.inner(rho, eps)
     out["KS"] = kin + out["ext"] + eh + out["xc"] + prob.E_nn()
     return out
+
+
+def step_backward(prob, res, tol=1e-13):
+    """Gradient of E_KS(Psi^{l+1}) of one step with respect to V_ext at the
+    quadrature points and the nuclear forces, the step's inputs (Psi^l,
+    lambda^l, rho^l and the boundary data) held fixed.
+
+    With the inner iteration converged, Psi^{l+1} is a stationary point of
+    E_KS over span(Z) with Psi^T M Psi = I, so (envelope theorem) only the
+    explicit V_ext term and the dependence of Z on V_ext through the BVPs
+    remain:
+      R = A Psi - M Psi Theta           (A: Hamiltonian of the final inner step)
+      dE/dZ = 2 R F U^T                 (F = diag(occupations))
+      Psi_bar_tilde = its Psi-tilde columns; Psi_bar_hat = Psi_bar_tilde
+          - M P G^{-1} P^T Psi_bar_tilde   (chain rule of the M-orthogonalisation)
+      S Y = Psi_bar_hat                 (adjoint BVPs; S symmetric)
+      dPsi_hat = -S^{-1} M[dV] Psi_hat  =>  dE = -sum_i Y_i^T M[dV] psi_hat_i
+    so  g_q = w_q |J| (rho_q - sum_i Y_i(x_q) psi_hat_i(x_q)),
+    and F_k = -sum_q g_q dV_ext(x_q)/dR_k - dE_nn/dR_k with
+    dV_ext/dR_k = -Z_k (x - R_k)/|x - R_k|^3."""
+    k = res.Psi.shape[1]
+    NH = prob.P.shape[1]
+    Psi, U, th = res.Psi, res.U, res.lam
+    A = (prob.A_linear() + prob.potential_matrix(res.extra["vnl_in"])).tocsr() \
+        if (prob.hartree or prob.xc_mode != "none") else prob.A_linear()
+    R = A @ Psi - (prob.M_II @ Psi) * th[None, :]
+    bar_t = 2.0 * (R * prob.occ[None, :]) @ U[NH:NH + k, :].T
+    G = res.extra["G_PP"]
+    bar_h = bar_t - prob.M_II @ (prob.P @ np.linalg.solve(G, prob.P.T @ bar_t))
+    Y, its, rr = jacobi_pcg(res.extra["S"], bar_h, None, tol=tol, max_iter=100000)
+    Yq = prob.at_quad(prob.to_nodes(Y))
+    Hq = prob.at_quad(prob.to_nodes(res.Psi_hat))
+    g = prob.dV * (res.rho_q - np.einsum("eqk,eqk->eq", Yq, Hq))
+    # forces
+    F = np.zeros((len(prob.Z), 3))
+    for a, (z, r) in enumerate(zip(prob.Z, prob.R)):
+        d = prob.x_q - r[None, None, :]
+        dist3 = np.sum(d * d, axis=-1) ** 1.5
+        dV = -z * d / dist3[..., None]          # dV_ext/dR_a at every point
+        F[a] = -np.einsum("eq,eqd->d", g, dV)
+        for b, (zb, rb) in enumerate(zip(prob.Z, prob.R)):
+            if b != a:
+                dr = r - rb
+                F[a] += z * zb * dr / np.linalg.norm(dr) ** 3   # -dE_nn/dR_a
+    return g, F, {"adjoint_iters": its, "R_norm": np.linalg.norm(R)}
