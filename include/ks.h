@@ -198,6 +198,30 @@ typedef struct {
 int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                 int32_t precision, double *rho_q, ks_step_report *rep_host);
 
+/* Replace the external potential: either its values at the quadrature
+ * points (device [n_elems][n_q]) or new nuclear positions R_host [n_atoms][3]
+ * (then V_ext = -sum Z_k/|x - R_k| and E_nn are recomputed).  Recomputes
+ * A^L = 1/2 K + M[V_ext] and its coarse block; a following ks_assemble is
+ * needed before solves. */
+int ks_set_external(ks_ctx *ctx, const double *vext_q, const double *R_host);
+
+/* Kohn-Sham energy (functional form of Sec. 2) of the orbitals produced by
+ * the most recent ks_scf_step, with the Hartree boundary data of that step
+ * held fixed: out_host[0..5] = {E_KS, kinetic, <V_ext, rho>, E_H^step,
+ * <rho, eps_xc>, E_nn}, E_H^step = 1/2 <rho, V_H[rho]> + 1/2 <rho - rho^l, V_bc>
+ * (V_bc: harmonic lift of the boundary data).  Two Poisson solves. */
+int ks_step_energy(ks_ctx *ctx, double *out_host);
+
+/* Adjoint of the most recent ks_scf_step (its inputs held fixed):
+ * g_q = dE * dE_KS/dV_ext at the quadrature points (device [n_elems][n_q])
+ * and forces_host = -dE * dE_KS/dR_k ([n_atoms][3], may be NULL).  Uses the
+ * stationarity of the converged inner iteration: g_q = dE w_q |J| (rho_q -
+ * sum_i Y_i(x_q) psi_hat_i(x_q)) with one adjoint block solve S Y =
+ * psi_bar_hat (CG recomputed from zero, nothing stored from the forward
+ * solve).  st_host (may be NULL) receives the adjoint solve statistics. */
+int ks_step_backward(ks_ctx *ctx, double dE, double *g_q, double *forces_host,
+                     ks_solve_stats *st_host);
+
 /* Measurement: mean duration (ms, HIP events on the context stream) of
  * `reps` back-to-back launches of one block-PCG phase in the launch
  * configuration the solver uses, on the current operator S and workspace:

@@ -82,6 +82,9 @@ _SIGS = {
     "ks_initial_guess": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
     "ks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ks_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "ks_set_external": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "ks_step_energy": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "ks_step_backward": (C.c_int, [_P, C.c_double, _P, C.POINTER(C.c_double), C.POINTER(SolveStats)]),
     "ks_debug_buffer": (C.c_int, [_P, C.c_char_p, _P, C.c_int64]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),

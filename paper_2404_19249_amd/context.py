@@ -185,6 +185,29 @@ class KSContext:
         B.check(self.lib.ks_time_kernel(self.h, int(which), int(k), int(reps), C.byref(ms)), self.lib)
         return ms.value
 
+    def set_external(self, vext_q=None, R=None):
+        """ks_set_external: new V_ext at the quadrature points or new nuclei."""
+        if R is not None:
+            self._R = _f64(np.asarray(R).reshape(-1, 3))
+            B.check(self.lib.ks_set_external(self.h, None, B.dptr(self._R)), self.lib)
+        else:
+            B.check(self.lib.ks_set_external(self.h, self._ptr(vext_q.contiguous()), None), self.lib)
+
+    def step_energy(self):
+        """ks_step_energy of the last scf_step."""
+        e = np.zeros(6)
+        B.check(self.lib.ks_step_energy(self.h, B.dptr(e)), self.lib)
+        return dict(zip(["KS", "kin", "ext", "H_step", "xc", "nn"], e))
+
+    def step_backward(self, dE=1.0, want_forces=True):
+        """ks_step_backward: (g_q device tensor, forces [n_atoms][3] numpy, stats)."""
+        g = self.empty(self.n_elems, self.n_q)
+        F = np.zeros((len(self._Z), 3)) if want_forces else None
+        st = B.SolveStats()
+        B.check(self.lib.ks_step_backward(self.h, float(dE), self._ptr(g),
+                                          None if F is None else B.dptr(F), C.byref(st)), self.lib)
+        return g, F, self._stats(st, 64)
+
     def autotune(self, k, reps=10):
         """ks_autotune: pick the SpMM row schedule and lanes-per-row split."""
         rep = (C.c_double * 28)()

@@ -166,3 +166,18 @@ void launch_fill_pencil(int m, int nH, const double *PP, const double *tail, dou
 // out = a + b  (n doubles)
 void launch_add(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
 }  // namespace ks
+
+namespace ks {
+// ------------------------------------------------------------------ adjoint
+void launch_residual_cols(int N, int k, const double *Y1, const double *Y2, const double *Y3,
+                          const double *theta, double *R, hipStream_t s);
+void launch_right_mult(int N, int k, const double *X, const double *Mk, double *Out, hipStream_t s);
+void launch_grad_q(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi,
+                   const double *w, const double *absdet, const double *A, const double *B, int k,
+                   const double *rho, double scale, double *g, hipStream_t s);
+int force_blocks(int n_e);
+void launch_force_partials(const double *coords, const int32_t *elems, int n_loc, int n_e, int n_q,
+                           const double *bary, const double *g, int a0, int na, const double *Z,
+                           const double *R, double *part, hipStream_t s);
+int launch_coldots(int N, int k, const double *X, const double *Y, double *part, hipStream_t s);
+}  // namespace ks

@@ -125,6 +125,11 @@ struct ks_ctx {
   // start eigenvectors), scratch T1, T2; rank r of the current F_B
   double *eD = nullptr, *eV = nullptr, *eX = nullptr, *eW = nullptr, *eT1 = nullptr, *eT2 = nullptr;
   int e_rank = 0, e_m = 0;
+  // state of the most recent ks_scf_step (for its energy and adjoint)
+  bool have_step = false, last_nonlinear = false;
+  int last_k = 0;
+  std::vector<double> last_theta, last_occ;
+  double *aux1 = nullptr, *aux2 = nullptr, *Rv = nullptr, *Gv = nullptr, *dMk = nullptr;
   // block vectors [N][k_max]
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
          *occ_d = nullptr, *scal = nullptr;
@@ -199,6 +204,9 @@ extern "C" int ks_options_default(ks_options *o) {
   o->deterministic = 1;
   return KS_OK;
 }
+
+static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precision, double tol,
+                      ks_solve_stats *st);
 
 // ------------------------------------------------------------ basis tables
 static void basis_tables(int order, int n_q, const double *bary, std::vector<double> &phi,
@@ -656,6 +664,11 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(eW, (size_t)mm * mm);
   A_(eT1, (size_t)mm * mm);
   A_(eT2, (size_t)mm * mm);
+  A_(aux1, nqt);
+  A_(aux2, nqt);
+  A_(Rv, (size_t)N * km);
+  A_(Gv, (size_t)N * km);
+  A_(dMk, (size_t)MAX_K * MAX_K);
   A_(Bv, (size_t)N * km);
   A_(Xv, (size_t)N * km);
   A_(Wv, (size_t)N * km);
@@ -911,6 +924,161 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
   return KS_OK;
 }
 
+// ---------------------------------------------------- external potential
+// Recompute everything that depends on V_ext: A^L, A^L + mu M and P^T A^L P.
+static int refresh_external(ks_ctx *c) {
+  hipStream_t s = c->s;
+  launch_fill(c->nnz_ext, 0.0, c->AL, s);
+  assemble_potential_all(c, c->vext_q, c->AL);
+  launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);
+  launch_combine3(c->nnz_ext, 1.0, c->AL, c->mu, c->M, 0.0, nullptr, c->base, s);
+  launch_spmm(c->N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0,
+              c->rorder, s);
+  launch_gemm_tn(c->N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork,
+                 c->gwork_n, s);
+  c->have_S = c->have_S32 = c->have_step = false;
+  HIPCHK(hipStreamSynchronize(s));
+  return KS_OK;
+}
+
+extern "C" int ks_set_external(ks_ctx *c, const double *vext_q, const double *R_host) {
+  if (!c) return fail(KS_ERR_ARG, "null context");
+  if (vext_q && R_host) return fail(KS_ERR_ARG, "give either vext_q or R_host");
+  if (R_host) {
+    if (c->n_atoms == 0) return fail(KS_ERR_ARG, "no nuclei to move");
+    c->hR.assign(R_host, R_host + 3 * c->n_atoms);
+    HIPCHK(hipMemcpyAsync(c->dR, c->hR.data(), sizeof(double) * 3 * c->n_atoms, hipMemcpyHostToDevice, c->s));
+    c->E_nn = 0.0;
+    for (int j = 0; j < c->n_atoms; ++j)
+      for (int k = 0; k < j; ++k) {
+        double dx = c->hR[3 * j] - c->hR[3 * k], dy = c->hR[3 * j + 1] - c->hR[3 * k + 1],
+               dz = c->hR[3 * j + 2] - c->hR[3 * k + 2];
+        c->E_nn += c->hZ[j] * c->hZ[k] / std::sqrt(dx * dx + dy * dy + dz * dz);
+      }
+    launch_vext(c->coords, c->elems, c->n_loc, c->n_e, c->n_q, c->qbary, c->n_atoms, c->dZ, c->dR,
+                c->vext_q, c->s);
+  } else if (vext_q) {
+    HIPCHK(hipMemcpyAsync(c->vext_q, vext_q, sizeof(double) * c->n_e * c->n_q, hipMemcpyDeviceToDevice, c->s));
+  } else {
+    return fail(KS_ERR_ARG, "nothing to set");
+  }
+  return refresh_external(c);
+}
+
+// ------------------------------------------------------ step energy E_KS
+extern "C" int ks_step_energy(ks_ctx *c, double *out) {
+  if (!c || !out) return fail(KS_ERR_ARG, "null argument");
+  if (!c->have_step) return fail(KS_ERR_STATE, "no ks_scf_step result to evaluate");
+  hipStream_t s = c->s;
+  const int k = c->last_k, N = c->N;
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  // kinetic: 1/2 sum_i f_i psi_i^T K psi_i
+  launch_spmm(N, c->rowptr, c->col, c->K, c->PsiNew, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
+  std::vector<double> kd(k);
+  const int nb = launch_coldots(N, k, c->PsiNew, c->Wv, c->redpart, s);
+  TRY(reduce_small(c, c->redpart, nb, k, kd.data()));
+  double kin = 0.0;
+  for (int j = 0; j < k; ++j) kin += 0.5 * c->last_occ[j] * kd[j];
+  double eh = 0.0, exc = 0.0, ext = 0.0;
+  {
+    const double *a[1] = {c->vext_q};
+    const double *b[1] = {c->rho_out};
+    TRY(weighted_dots(c, 1, a, b, &ext));
+  }
+  if (c->opt.hartree_mode != KS_HARTREE_OFF) {
+    // E_H^step = 1/2 <rho, V_H[rho]> + 1/2 <rho - rho^l, V_bc>, w_D frozen
+    int it = 0;
+    if (hartree_solve(c, c->rho_out, &it) < 0) return KS_ERR_BREAKDOWN;
+    HIPCHK(hipMemcpyAsync(c->aux1, c->vh_q, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
+    launch_fill(nqt, 0.0, c->aux2, s);
+    if (hartree_solve(c, c->aux2, &it) < 0) return KS_ERR_BREAKDOWN;  // V_bc
+    launch_combine3(nqt, 1.0, c->rho_out, -1.0, c->rho_l, 0.0, nullptr, c->aux2, s);
+    const double *a[2] = {c->aux1, c->vh_q};
+    const double *b[2] = {c->rho_out, c->aux2};
+    double e2[2];
+    TRY(weighted_dots(c, 2, a, b, e2));
+    eh = 0.5 * e2[0] + 0.5 * e2[1];
+    c->vh_warm = false;
+  }
+  if (c->opt.xc_mode != KS_XC_NONE) {
+    launch_xc(nqt, c->rho_out, c->opt.xc_mode, c->aux2, c->aux1, s);
+    const double *a[1] = {c->aux2};
+    const double *b[1] = {c->rho_out};
+    TRY(weighted_dots(c, 1, a, b, &exc));
+  }
+  out[1] = kin;
+  out[2] = ext;
+  out[3] = eh;
+  out[4] = exc;
+  out[5] = c->E_nn;
+  out[0] = kin + ext + eh + exc + c->E_nn;
+  return KS_OK;
+}
+
+// --------------------------------------------------------------- adjoint
+extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *forces_host,
+                                ks_solve_stats *st) {
+  if (!c || !g_q) return fail(KS_ERR_ARG, "null argument");
+  if (!c->have_step) return fail(KS_ERR_STATE, "no ks_scf_step result to differentiate");
+  hipStream_t s = c->s;
+  const int k = c->last_k, N = c->N, nH = c->N_H, m = nH + k;
+  // R = A Psi - M Psi Theta with A the Hamiltonian of the final inner iteration
+  launch_spmm(N, c->rowptr, c->col, c->AL, c->PsiNew, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
+  if (c->last_nonlinear)
+    launch_spmm(N, c->rowptr, c->col, c->MNL, c->PsiNew, k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
+  launch_spmm(N, c->rowptr, c->col, c->M, c->PsiNew, k, c->Xv, k, k, nullptr, 0, 0, c->rorder, s);
+  HIPCHK(hipMemcpyAsync(c->scal, c->last_theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+  launch_residual_cols(N, k, c->Wv, c->last_nonlinear ? c->Bv : nullptr, c->Xv, c->scal, c->Rv, s);
+  // psi_bar_tilde = R (2 F U_tail^T)
+  std::vector<double> U((size_t)m * k), Mk((size_t)k * k);
+  HIPCHK(hipMemcpyAsync(U.data(), c->U, sizeof(double) * m * k, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int l = 0; l < k; ++l)
+    for (int j = 0; j < k; ++j) Mk[(size_t)l * k + j] = 2.0 * c->last_occ[l] * U[(size_t)(nH + j) * k + l];
+  HIPCHK(hipMemcpyAsync(c->dMk, Mk.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, s));
+  launch_right_mult(N, k, c->Rv, c->dMk, c->Gv, s);
+  // psi_bar_hat = psi_bar_tilde - M P G^{-1} P^T psi_bar_tilde
+  launch_gemm_tn(N, nH, k, c->Z, c->mp, c->Gv, k, c->Ctmp, k, c->gwork, c->gwork_n, s);
+  launch_small_gemm(nH, k, nH, c->GPPinv, nH, c->Ctmp, k, c->Ttmp, k, 0.0, s);
+  launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, 1.0, nullptr, 0, c->Wv, k, s);
+  launch_spmm(N, c->rowptr, c->col, c->M, c->Wv, k, c->Xv, k, k, nullptr, 0, 0, c->rorder, s);
+  launch_combine3((int64_t)N * k, 1.0, c->Gv, -1.0, c->Xv, 0.0, nullptr, c->Rv, s);
+  // adjoint boundary value problems S Y = psi_bar_hat (from zero, FP64)
+  HIPCHK(hipMemsetAsync(c->Gv, 0, sizeof(double) * N * k, s));
+  const double tol = std::min(c->opt.tol_solve, 1e-10);
+  int r = solve_impl(c, c->Rv, c->Gv, k, KS_PREC_FP64, tol, st);
+  if (r < 0) return r;
+  // g_q = dE * w |J| (rho - sum Y psi_hat)
+  launch_grad_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, c->Gv, c->PsiHat, k,
+                c->rho_out, dE, g_q, s);
+  if (forces_host) {
+    const int nb = force_blocks(c->n_e);
+    for (int a0 = 0; a0 < c->n_atoms; a0 += 8) {
+      const int na = std::min(8, c->n_atoms - a0);
+      launch_force_partials(c->coords, c->elems, c->n_loc, c->n_e, c->n_q, c->qbary, g_q, a0, na,
+                            c->dZ, c->dR, c->redpart, s);
+      double f[24];
+      TRY(reduce_small(c, c->redpart, nb, 24, f));
+      for (int a = 0; a < na; ++a)
+        for (int d = 0; d < 3; ++d) forces_host[3 * (a0 + a) + d] = -f[3 * a + d];
+    }
+    // - dE_nn / dR_a, scaled by the seed
+    for (int a = 0; a < c->n_atoms; ++a)
+      for (int b = 0; b < c->n_atoms; ++b) {
+        if (a == b) continue;
+        double d[3], r2 = 0.0;
+        for (int t = 0; t < 3; ++t) {
+          d[t] = c->hR[3 * a + t] - c->hR[3 * b + t];
+          r2 += d[t] * d[t];
+        }
+        const double r3 = r2 * std::sqrt(r2);
+        for (int t = 0; t < 3; ++t) forces_host[3 * a + t] += dE * c->hZ[a] * c->hZ[b] * d[t] / r3;
+      }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return r;
+}
+
 extern "C" int ks_destroy(ks_ctx *c) {
   if (!c) return KS_OK;
   (void)hipStreamSynchronize(c->s);
@@ -961,6 +1129,7 @@ static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_
   launch_extract_diag(c->N, c->rowptr, c->col, c->S, c->diagS, s);
   c->have_S = true;
   c->have_S32 = false;
+  c->have_step = false;
   return KS_OK;
 }
 
@@ -1174,6 +1343,7 @@ extern "C" int ks_augmented_project(ks_ctx *c, const double *psi_hat, int32_t k,
     H = c->MNL;
   } else
     return fail(KS_ERR_ARG, "which must be 0, 1 or 2");
+  c->have_step = false;
   TRY(build_tail(c, psi_hat, k));
   project_full(c, H, c->N_H + k, F);
   HIPCHK(hipStreamSynchronize(c->s));
@@ -1236,6 +1406,7 @@ extern "C" int ks_small_eig(ks_ctx *c, const double *FA, const double *FB, int32
   if (m < 1 || m > 256 || k < 1 || k > m || m > c->mp) return fail(KS_ERR_ARG, "bad sizes");
   std::vector<double> th;
   int rank = 0;
+  c->have_step = false;
   TRY(orth_impl(c, FB, m));
   TRY(eig_impl(c, FA, FB, m, k, U, th, &rank));
   for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
@@ -1248,6 +1419,7 @@ extern "C" int ks_initial_guess(ks_ctx *c, int32_t k, double *psi, double *lambd
   if (k < 1 || k > c->k_max || k > c->N_H) return fail(KS_ERR_ARG, "bad k");
   std::vector<double> th;
   int rank = 0;
+  c->have_step = false;
   TRY(orth_impl(c, c->GPP, c->N_H));
   TRY(eig_impl(c, c->FAL_PP, c->GPP, c->N_H, k, c->U, th, &rank));
   launch_ellP_times(c->N, c->Pidx, c->Pw, c->U, k, k, 1.0, nullptr, 0, psi, k, c->s);
@@ -1437,6 +1609,11 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   R.seconds[4] = t5 - t4;
   R.seconds[5] = t5 - t0;
   if (rep) *rep = R;
+  c->have_step = true;
+  c->last_nonlinear = nonlinear;
+  c->last_k = k;
+  c->last_theta.assign(th.begin(), th.begin() + k);
+  c->last_occ.assign(occ_host, occ_host + k);
   int ret = KS_OK;
   if ((int)th.size() > k && th[k] - th[k - 1] < 1e-8) ret = KS_WARN_DEGENERATE;
   if (nonlinear && res >= c->opt.tol_inner) ret = KS_NOT_CONVERGED;

@@ -1,0 +1,95 @@
+"""GPU adjoint of one step (differentiation form): energy, dE/dV_ext at the
+quadrature points and nuclear forces against the oracle's adjoint, against
+finite differences on the GPU, and through torch.autograd."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from ks_inputs import make_workload
+from oracle.step import KSProblem, ks_scf_step, initial_guess, step_backward
+
+TIGHT = dict(tol_solve=1e-13, tol_inner=1e-12, tol_poisson=1e-13)
+DEV = "cuda:0"
+
+
+def _setup(name="small_molecule", n=5, order=1, k=2, n_H=3, mu=6.0):
+    from paper_2404_19249_amd import KSContext
+    w = make_workload(name, n=n, order=order, k=k)
+    w.n_H = n_H
+    print(f"[case] adjoint {name} n={n} order={order} k={k}", flush=True)
+    p = KSProblem.from_workload(w, mu=mu)
+    th, Psi = initial_guess(p, k)
+    for _ in range(2):
+        r = ks_scf_step(p, Psi, th, tol_solve=1e-13, tol_inner=1e-12, tol_poisson=1e-14)
+        Psi, th = r.Psi, r.lam
+    ctx = KSContext.from_workload(w, mu=mu, **TIGHT)
+    return w, p, ctx, Psi, th
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_step_energy_gradient_and_forces_match_oracle(order):
+    w, p, ctx, Psi, th = _setup(order=order, n=5 if order == 1 else 3)
+    r = ks_scf_step(p, Psi, th, tol_solve=1e-14, tol_inner=1e-13, tol_poisson=1e-14)
+    g_ref, F_ref, _ = step_backward(p, r, tol=1e-14)
+    psi = torch.tensor(Psi, device=DEV)
+    lam, rep = ctx.scf_step(psi, th, w.occ)
+    e = ctx.step_energy()
+    assert abs(e["KS"] - r.energies["KS"]) < 1e-10 * abs(r.energies["KS"])
+    g, F, st = ctx.step_backward()
+    g = g.cpu().numpy()
+    assert np.abs(g - g_ref).max() < 1e-7 * np.abs(g_ref).max()
+    assert np.abs(F - F_ref).max() < 1e-7 * np.abs(F_ref).max()
+
+
+def test_gradient_matches_gpu_finite_difference():
+    w, p, ctx, Psi, th = _setup()
+    psi0 = torch.tensor(Psi, device=DEV)
+    v0 = torch.tensor(p.vext_q, device=DEV)
+    ctx.set_external(vext_q=v0)
+    ctx.scf_step(psi0.clone(), th, w.occ)
+    g, F, _ = ctx.step_backward()
+    c = np.array([0.5, -0.3, 0.2])
+    dV = torch.tensor(np.exp(-np.sum((p.x_q - c) ** 2, -1) / 4.0), device=DEV)
+    h = 1e-4
+    E = []
+    for sgn in (1, -1):
+        ctx.set_external(vext_q=v0 + sgn * h * dV)
+        ctx.scf_step(psi0.clone(), th, w.occ)
+        E.append(ctx.step_energy()["KS"])
+    fd = (E[0] - E[1]) / (2 * h)
+    adj = float((g * dV).sum())
+    assert abs(fd - adj) < 1e-6 * abs(fd)
+
+
+def test_forces_match_gpu_finite_difference():
+    w, p, ctx, Psi, th = _setup()
+    psi0 = torch.tensor(Psi, device=DEV)
+    ctx.scf_step(psi0.clone(), th, w.occ)
+    _, F, _ = ctx.step_backward()
+    h = 1e-4
+    R0 = p.R.copy()
+    for a, d in [(0, 0), (2, 2)]:
+        E = []
+        for sgn in (1, -1):
+            R = R0.copy()
+            R[a, d] += sgn * h
+            ctx.set_external(R=R)
+            ctx.scf_step(psi0.clone(), th, w.occ)
+            E.append(ctx.step_energy()["KS"])
+        fd = -(E[0] - E[1]) / (2 * h)
+        assert abs(fd - F[a, d]) < 1e-5 * max(1.0, abs(fd)), (a, d, fd, F[a, d])
+
+
+def test_autograd_function_matches_adjoint():
+    from paper_2404_19249_amd.autograd import KSStepEnergy
+    w, p, ctx, Psi, th = _setup()
+    psi0 = torch.tensor(Psi, device=DEV)
+    v = torch.tensor(p.vext_q, device=DEV, requires_grad=True)
+    E = KSStepEnergy.apply(v, ctx, psi0, th, w.occ)
+    (gv,) = torch.autograd.grad(3.0 * E, v)
+    ctx.set_external(vext_q=v.detach())
+    ctx.scf_step(psi0.clone(), th, w.occ)
+    g, _, _ = ctx.step_backward(dE=3.0)
+    assert torch.allclose(gv, g, rtol=1e-10, atol=1e-14)
