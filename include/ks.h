@@ -222,6 +222,35 @@ int ks_step_energy(ks_ctx *ctx, double *out_host);
 int ks_step_backward(ks_ctx *ctx, double dE, double *g_q, double *forces_host,
                      ks_solve_stats *st_host);
 
+/* ---- Batched form: many independent systems in one persistent launch ----
+ * Each system is a context with an assembled operator (ks_assemble); the
+ * batch solves S_s X_s = M_s psi_s diag(lambda_s + mu_s) for every s
+ * (eq. Aux_Linear_Problem per system) in ONE persistent kernel launch,
+ * captured once in a hipGraph and replayed by every ks_batch_block_solve.
+ * Workgroups form per-system teams proportional to nnz_s k_s (grid = the
+ * resident workgroup count, or grid_req if smaller); the lanes-per-row split
+ * of each system comes from its context's autotuned choice (ks_autotune) or
+ * a rule by k.  Systems must outlive the batch and keep their operators. */
+typedef struct ks_batch ks_batch;
+typedef struct {
+  double seconds;               /* whole launch (HIP events) */
+  int32_t n;
+  double system_seconds[256];   /* device-clock completion time of each system, from launch start */
+  int32_t iters[256];           /* max PCG iterations over the columns */
+  double relres[256];           /* max recursive relative residual */
+  int32_t status[256];          /* 0 converged, 1 iteration limit */
+} ks_batch_stats;
+int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t *k_host, int32_t grid_req,
+                    ks_batch **out);
+/* grid_host: workgroups of the launch; team_host/ng_host [n] (may be NULL) */
+int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host, int32_t *ng_host);
+/* psi_old[s], psi_hat[s]: device [N_s][k_s]; lambda_host[s]: host [k_s].
+ * Host arrays of pointers. */
+int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
+                         const double *const *lambda_host, double *const *psi_hat,
+                         ks_batch_stats *st_host);
+int ks_batch_destroy(ks_batch *b);
+
 /* Measurement: mean duration (ms, HIP events on the context stream) of
  * `reps` back-to-back launches of one block-PCG phase in the launch
  * configuration the solver uses, on the current operator S and workspace:

@@ -61,6 +61,12 @@ class StepReport(C.Structure):
                 ("solve", SolveStats), ("seconds", C.c_double * 8)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("seconds", C.c_double), ("n", C.c_int32), ("system_seconds", C.c_double * 256),
+                ("iters", C.c_int32 * 256), ("relres", C.c_double * 256),
+                ("status", C.c_int32 * 256)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "ks_options_default": (C.c_int, [C.POINTER(Options)]),
@@ -86,6 +92,13 @@ _SIGS = {
     "ks_step_energy": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "ks_step_backward": (C.c_int, [_P, C.c_double, _P, C.POINTER(C.c_double), C.POINTER(SolveStats)]),
     "ks_debug_buffer": (C.c_int, [_P, C.c_char_p, _P, C.c_int64]),
+    "ks_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32,
+                                  C.POINTER(_P)]),
+    "ks_batch_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32)]),
+    "ks_batch_block_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.POINTER(C.c_double)),
+                                       C.POINTER(_P), C.POINTER(BatchStats)]),
+    "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),
 }

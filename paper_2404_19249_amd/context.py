@@ -249,3 +249,54 @@ class KSContext:
         r["seconds"] = list(rep.seconds[:6])
         r["status"] = code
         return lam_a, r
+
+
+class KSBatch:
+    """Many independent systems (each a KSContext with an assembled operator)
+    solved together: one persistent launch, captured once in a hipGraph and
+    replayed by every solve.  The contexts must outlive the batch."""
+
+    def __init__(self, contexts, ks, grid=0):
+        self.ctxs = list(contexts)
+        self.ks = [int(k) for k in ks]
+        self.lib = self.ctxs[0].lib
+        self.torch = self.ctxs[0].torch
+        n = len(self.ctxs)
+        hs = (C.c_void_p * n)(*[c.h for c in self.ctxs])
+        karr = (C.c_int32 * n)(*self.ks)
+        h = C.c_void_p()
+        B.check(self.lib.ks_batch_create(n, hs, karr, int(grid), C.byref(h)), self.lib)
+        self.h = h
+        g = C.c_int32()
+        team = (C.c_int32 * n)()
+        ng = (C.c_int32 * n)()
+        B.check(self.lib.ks_batch_info(self.h, C.byref(g), team, ng), self.lib)
+        self.grid, self.team, self.ng = g.value, list(team), list(ng)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def block_solve(self, psis, lams, outs=None):
+        """psi_hat_s = S_s^{-1} M_s psi_s diag(lam_s + mu_s) for every system s."""
+        n = len(self.ctxs)
+        assert len(psis) == n and len(lams) == n
+        outs = outs if outs is not None else [c.empty(c.N, k) for c, k in zip(self.ctxs, self.ks)]
+        lam_a = [_f64(l) for l in lams]
+        for c, p, o, l, k in zip(self.ctxs, psis, outs, lam_a, self.ks):
+            assert tuple(p.shape) == (c.N, k) and tuple(o.shape) == (c.N, k) and l.size >= k
+        pp = (C.c_void_p * n)(*[c._ptr(p).value for c, p in zip(self.ctxs, psis)])
+        oo = (C.c_void_p * n)(*[c._ptr(o).value for c, o in zip(self.ctxs, outs)])
+        ll = (C.POINTER(C.c_double) * n)(*[B.dptr(l) for l in lam_a])
+        st = B.BatchStats()
+        code = B.check(self.lib.ks_batch_block_solve(self.h, pp, ll, oo, C.byref(st)), self.lib)
+        return outs, {"status": code, "seconds": st.seconds,
+                      "system_seconds": list(st.system_seconds[:n]), "iters": list(st.iters[:n]),
+                      "relres": list(st.relres[:n]), "sys_status": list(st.status[:n])}

@@ -1,0 +1,310 @@
+// Batched block BVP solves: many independent systems of uneven size
+// (each S_s X_s = B_s with k_s columns, Jacobi-PCG per column) in ONE
+// persistent launch.
+//
+// The grid is sized to what the device keeps resident.  Workgroups are
+// dealt to systems in teams proportional to each system's work (nnz_s k_s),
+// at least one per system; a team owns contiguous row ranges of its system
+// and runs the same recurrences as the single-system solver, separated by
+// team barriers (release/acquire fences around an arrival counter and a
+// generation word).  Team reductions are done redundantly by every workgroup
+// of the team from per-workgroup partials in a fixed order, so all members
+// take identical decisions (convergence, stop) without a broadcast.  Every
+// wait is bounded: a barrier that spins past its limit sets the system's
+// status to -2 and the workgroup leaves, so the grid always drains.
+#include "common.h"
+#include "kernels.h"
+#include <algorithm>
+#include <vector>
+
+namespace ks {
+
+struct BatchSys {
+  const int32_t *rowptr, *col;
+  const double *val, *diag, *B;
+  double *X, *R, *P, *Q;
+  double *part;          // [3 phases][team][3k]
+  unsigned int *bar;     // [2]: arrival count, generation
+  int N, k, ng, team0, team, max_iter;
+  double tol;
+  int *iters;            // [k]
+  double *relres;        // [k]
+  unsigned long long *t_done;
+  int *status;           // 0 converged, 1 iteration limit, -1 breakdown, -2 barrier timeout
+};
+
+constexpr long long SPIN_LIMIT = 1LL << 24;
+
+__device__ bool team_barrier(unsigned int *bar, int team, int *status) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_ok = 1;
+    __threadfence();
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = atomicAdd(&bar[0], 1u);
+    if (arrived == (unsigned)team - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > SPIN_LIMIT) {
+          s_ok = 0;
+          atomicExch(status, -2);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// row product with k columns (one value per lane), NG lanes per row's nonzeros
+__device__ __forceinline__ double batch_row(int row, int c, int ng, int NG, const int32_t *rowptr,
+                                            const int32_t *col, const double *val, const double *X,
+                                            int k) {
+  double acc = 0.0;
+  const int jb = rowptr[row], je = rowptr[row + 1];
+  for (int j = jb + ng; j < je; j += 4 * NG) {
+    int ci[4];
+    double vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int jj = j + u * NG;
+      const bool ok = jj < je;
+      const int jc = ok ? jj : j;
+      ci[u] = col[jc];
+      const double v = val[jc];
+      vv[u] = ok ? v : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += vv[u] * X[(int64_t)ci[u] * k + c];
+  }
+  return acc;
+}
+
+// per-workgroup column sums of `a` (one column per lane group) -> out[c]
+__device__ __forceinline__ void wg_cols(double a, bool own, int c, int k, int LPR, int RPW,
+                                        double *s_red, double *out) {
+  s_red[threadIdx.x] = own ? a : 0.0;
+  __syncthreads();
+  for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+      for (int sl = 0; sl < RPW; ++sl) s += s_red[w * 64 + sl * LPR + cc * (LPR / k)];
+    out[cc] = s;
+  }
+  __syncthreads();
+}
+
+// sum of the team's partials (fixed order) for W values -> s_sum
+__device__ __forceinline__ void team_sum(const double *part, int team, int W, double *s_sum) {
+  for (int i = threadIdx.x; i < W; i += blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < team; ++t) s += part[(int64_t)t * W + i];
+    s_sum[i] = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ systems,
+                                                   const int *__restrict__ wg_sys) {
+  __shared__ double s_red[256];
+  __shared__ double s_sum[3 * MAX_K];
+  __shared__ double s_part[3 * MAX_K];
+  __shared__ double s_rz[MAX_K], s_bb[MAX_K], s_alpha[MAX_K], s_beta[MAX_K], s_rr[MAX_K];
+  __shared__ int s_active[MAX_K], s_iters[MAX_K];
+  __shared__ int s_flags[2];  // any active, breakdown
+  const int sidx = wg_sys[blockIdx.x];
+  if (sidx < 0) return;
+  const BatchSys &d = systems[sidx];
+  const int rank = blockIdx.x - d.team0, team = d.team, k = d.k, NG = d.ng;
+  const int LPR = k * NG, RPW = 64 / LPR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = lane / LPR, rem = lane % LPR, c = rem / NG, ng = rem % NG;
+  const bool valid = slot < RPW;
+  const int rows_per_iter = (blockDim.x >> 6) * RPW;
+  // contiguous row range of this workgroup
+  const int chunk = (d.N + team - 1) / team;
+  const int r0 = rank * chunk, r1 = min(d.N, r0 + chunk);
+  const int W3 = 3 * k;
+  double *partI = d.part, *partA = d.part + (int64_t)team * W3, *partB = d.part + 2 * (int64_t)team * W3;
+
+  // ---- init: R = B - S X, P = D^{-1} R; b.b, r.r, r.z
+  double abb = 0.0, arr = 0.0, arz = 0.0;
+  for (int base = r0; base < r1; base += rows_per_iter) {
+    const int row = base + wave * RPW + slot;
+    const bool rv = valid && row < r1;
+    double acc = rv ? batch_row(row, c, ng, NG, d.rowptr, d.col, d.val, d.X, k) : 0.0;
+    for (int off = 1; off < NG; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (rv && ng == 0) {
+      const int64_t ix = (int64_t)row * k + c;
+      const double b = d.B[ix], r = b - acc, p = r / d.diag[row];
+      d.R[ix] = r;
+      d.P[ix] = p;
+      abb += b * b;
+      arr += r * r;
+      arz += r * p;
+    }
+  }
+  const bool own = valid && ng == 0;
+  wg_cols(abb, own, c, k, LPR, RPW, s_red, s_part);
+  wg_cols(arr, own, c, k, LPR, RPW, s_red, s_part + k);
+  wg_cols(arz, own, c, k, LPR, RPW, s_red, s_part + 2 * k);
+  for (int i = threadIdx.x; i < W3; i += blockDim.x) partI[(int64_t)rank * W3 + i] = s_part[i];
+  if (!team_barrier(d.bar, team, d.status)) return;
+  team_sum(partI, team, W3, s_sum);
+  for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
+    s_bb[cc] = s_sum[cc];
+    s_rr[cc] = s_sum[k + cc];
+    s_rz[cc] = s_sum[2 * k + cc];
+    s_active[cc] = (s_bb[cc] > 0.0) && (s_rr[cc] > d.tol * d.tol * s_bb[cc]);
+    s_iters[cc] = 0;
+    s_alpha[cc] = s_beta[cc] = 0.0;
+  }
+  if (threadIdx.x == 0) s_flags[1] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int cc = 0; cc < k; ++cc) any |= s_active[cc];
+    s_flags[0] = any;
+  }
+  __syncthreads();
+
+  int it = 0;
+  for (; it < d.max_iter && s_flags[0] && !s_flags[1]; ++it) {
+    // ---- A: Q = S P, p.q
+    double apq = 0.0;
+    for (int base = r0; base < r1; base += rows_per_iter) {
+      const int row = base + wave * RPW + slot;
+      const bool rv = valid && row < r1;
+      double acc = rv ? batch_row(row, c, ng, NG, d.rowptr, d.col, d.val, d.P, k) : 0.0;
+      for (int off = 1; off < NG; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (rv && ng == 0) {
+        const int64_t ix = (int64_t)row * k + c;
+        d.Q[ix] = acc;
+        apq += d.P[ix] * acc;
+      }
+    }
+    wg_cols(apq, own, c, k, LPR, RPW, s_red, s_part);
+    for (int i = threadIdx.x; i < k; i += blockDim.x) partA[(int64_t)rank * W3 + i] = s_part[i];
+    if (!team_barrier(d.bar, team, d.status)) return;
+    for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
+      double pq = 0.0;
+      for (int t = 0; t < team; ++t) pq += partA[(int64_t)t * W3 + cc];
+      s_alpha[cc] = 0.0;
+      if (s_active[cc]) {
+        if (!(pq > 0.0)) s_flags[1] = 1;
+        else s_alpha[cc] = s_rz[cc] / pq;
+      }
+    }
+    __syncthreads();
+    // ---- B: R -= alpha Q ; r.z, r.r
+    double brz = 0.0, brr = 0.0;
+    for (int base = r0; base < r1; base += rows_per_iter) {
+      const int row = base + wave * RPW + slot;
+      if (!(valid && row < r1 && ng == 0)) continue;
+      const int64_t ix = (int64_t)row * k + c;
+      const double r = d.R[ix] - s_alpha[c] * d.Q[ix];
+      d.R[ix] = r;
+      brr += r * r;
+      brz += r * (r / d.diag[row]);
+    }
+    wg_cols(brz, own, c, k, LPR, RPW, s_red, s_part);
+    wg_cols(brr, own, c, k, LPR, RPW, s_red, s_part + k);
+    for (int i = threadIdx.x; i < 2 * k; i += blockDim.x) partB[(int64_t)rank * W3 + i] = s_part[i];
+    if (!team_barrier(d.bar, team, d.status)) return;
+    for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
+      double rz = 0.0, rr = 0.0;
+      for (int t = 0; t < team; ++t) {
+        rz += partB[(int64_t)t * W3 + cc];
+        rr += partB[(int64_t)t * W3 + k + cc];
+      }
+      if (s_active[cc]) {
+        s_beta[cc] = rz / s_rz[cc];
+        s_rz[cc] = rz;
+        s_rr[cc] = rr;
+        s_iters[cc] += 1;
+        if (!(rr > d.tol * d.tol * s_bb[cc])) s_active[cc] = 0;
+      } else {
+        s_beta[cc] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int any = 0;
+      for (int cc = 0; cc < k; ++cc) any |= s_active[cc];
+      s_flags[0] = any;
+    }
+    __syncthreads();
+    // ---- C: X += alpha P ; P = D^{-1} R + beta P
+    for (int base = r0; base < r1; base += rows_per_iter) {
+      const int row = base + wave * RPW + slot;
+      if (!(valid && row < r1 && ng == 0)) continue;
+      const int64_t ix = (int64_t)row * k + c;
+      const double p = d.P[ix];
+      d.X[ix] += s_alpha[c] * p;
+      d.P[ix] = d.R[ix] / d.diag[row] + s_beta[c] * p;
+    }
+    if (s_flags[0] && !s_flags[1])
+      if (!team_barrier(d.bar, team, d.status)) return;
+  }
+  if (rank == 0 && threadIdx.x == 0) {
+    for (int cc = 0; cc < k; ++cc) {
+      d.iters[cc] = s_iters[cc];
+      d.relres[cc] = s_bb[cc] > 0.0 ? sqrt(s_rr[cc] / s_bb[cc]) : 0.0;
+    }
+    int st = 0;
+    if (s_flags[1]) st = -1;
+    else if (s_flags[0]) st = 1;
+    if (atomicCAS(d.status, 0, st) != 0) { /* keep an earlier barrier timeout */ }
+    *d.t_done = wall_clock64();
+  }
+}
+
+// start of a launch: clears status and arrival counters (not the generation
+// words) and stamps the device clock
+__global__ void k_batch_reset(BatchSys *systems, int n, unsigned long long *t0) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    *systems[i].status = 0;
+    systems[i].bar[0] = 0u;
+  }
+  if (threadIdx.x == 0) *t0 = wall_clock64();
+}
+void launch_batch_reset(void *systems, int n, unsigned long long *t0, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, reinterpret_cast<BatchSys *>(systems), n, t0);
+}
+void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_pcg, dim3(grid), dim3(256), 0, s,
+                     reinterpret_cast<const BatchSys *>(systems), wg_sys);
+}
+size_t batch_sys_bytes() { return sizeof(BatchSys); }
+int batch_resident_grid() {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_pcg, 256, 0) != hipSuccess)
+    return -1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+  return per_cu * cus;
+}
+
+// Host-side description of one system (filled by the runtime), packed into
+// the device table by pack_batch.
+void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const double *val,
+                    const double *diag, const double *B, double *X, double *R, double *P, double *Q,
+                    double *part, unsigned int *bar, int N, int k, int ng, int team0, int team,
+                    int max_iter, double tol, int *iters, double *relres,
+                    unsigned long long *t_done, int *status) {
+  BatchSys s;
+  s.rowptr = rowptr; s.col = col; s.val = val; s.diag = diag; s.B = B;
+  s.X = X; s.R = R; s.P = P; s.Q = Q; s.part = part; s.bar = bar;
+  s.N = N; s.k = k; s.ng = ng; s.team0 = team0; s.team = team; s.max_iter = max_iter;
+  s.tol = tol; s.iters = iters; s.relres = relres; s.t_done = t_done; s.status = status;
+  *reinterpret_cast<BatchSys *>(dst) = s;
+}
+
+}  // namespace ks

@@ -181,3 +181,16 @@ void launch_force_partials(const double *coords, const int32_t *elems, int n_loc
                            const double *R, double *part, hipStream_t s);
 int launch_coldots(int N, int k, const double *X, const double *Y, double *part, hipStream_t s);
 }  // namespace ks
+
+namespace ks {
+// ------------------------------------------------------------------ batch
+size_t batch_sys_bytes();
+int batch_resident_grid();
+void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const double *val,
+                    const double *diag, const double *B, double *X, double *R, double *P, double *Q,
+                    double *part, unsigned int *bar, int N, int k, int ng, int team0, int team,
+                    int max_iter, double tol, int *iters, double *relres,
+                    unsigned long long *t_done, int *status);
+void launch_batch_reset(void *systems, int n, unsigned long long *t0, hipStream_t s);
+void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStream_t s);
+}  // namespace ks

@@ -1079,6 +1079,214 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
   return r;
 }
 
+// ---------------------------------------------------------------- batches
+struct ks_batch {
+  int n = 0, grid = 0;
+  hipStream_t s = nullptr;
+  std::vector<ks_ctx *> sys;
+  std::vector<int> k, team, team0, ng;
+  DevBuf mem;
+  void *table = nullptr;
+  int *wg_sys = nullptr, *iters = nullptr, *status = nullptr;
+  double *relres = nullptr, *part = nullptr;
+  unsigned int *bar = nullptr;
+  unsigned long long *t_done = nullptr, *t0 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~ks_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+  }
+  template <typename T>
+  int alloc(T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(sizeof(T) * count, 256)) != hipSuccess)
+      return fail(KS_ERR_NOMEM, "hipMalloc failed");
+    mem.ptrs.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return KS_OK;
+  }
+};
+
+extern "C" int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t *k_host,
+                               int32_t grid_req, ks_batch **out) {
+  if (n < 1 || n > 256 || !systems || !k_host || !out)
+    return fail(KS_ERR_ARG, "batch needs 1..256 systems and non-null arrays");
+  ks_batch *b = new ks_batch();
+  auto bail = [&](int code) {
+    delete b;
+    return code;
+  };
+  b->n = n;
+  // a stream of the batch's own (default priority): capture needs a
+  // non-null stream, and the contexts' streams may be the null stream
+  if (hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "stream creation failed"));
+  double total = 0.0;
+  std::vector<double> work(n);
+  for (int i = 0; i < n; ++i) {
+    ks_ctx *c = systems[i];
+    if (!c) return bail(fail(KS_ERR_ARG, "null system"));
+    if (k_host[i] < 1 || k_host[i] > c->k_max) return bail(fail(KS_ERR_ARG, "k out of range"));
+    b->sys.push_back(c);
+    b->k.push_back(k_host[i]);
+    work[i] = (double)c->nnz * k_host[i] + 1.0;
+    total += work[i];
+    // lanes per row: the system's autotuned choice, else by k
+    int ng = c->ng64 > 0 ? c->ng64 : (k_host[i] == 1 ? 8 : (k_host[i] <= 4 ? 4 : (k_host[i] <= 12 ? 2 : 1)));
+    while (ng > 1 && ng * k_host[i] > 64) ng >>= 1;
+    b->ng.push_back(ng);
+  }
+  int resident = batch_resident_grid();
+  if (resident <= 0) return bail(fail(KS_ERR_HIP, "occupancy query failed"));
+  int grid = grid_req > 0 ? std::min<int>(grid_req, resident) : resident;
+  if (grid < n) return bail(fail(KS_ERR_ARG, "more systems than resident workgroups"));
+  // teams proportional to work, at least one workgroup each
+  b->team.assign(n, 1);
+  int left = grid - n;
+  for (int i = 0; i < n; ++i) {
+    const int extra = (int)std::floor((double)left * work[i] / total);
+    b->team[i] += extra;
+  }
+  int used = 0;
+  for (int i = 0; i < n; ++i) used += b->team[i];
+  for (int i = 0; used > grid; i = (i + 1) % n)
+    if (b->team[i] > 1) { b->team[i]--; used--; }
+  b->grid = used;
+  b->team0.resize(n);
+  std::vector<int> wg(b->grid);
+  for (int i = 0, o = 0; i < n; ++i) {
+    b->team0[i] = o;
+    for (int t = 0; t < b->team[i]; ++t) wg[o++] = i;
+  }
+  size_t part_total = 0;
+  for (int i = 0; i < n; ++i) part_total += (size_t)3 * b->team[i] * 3 * b->k[i];
+  if (b->alloc(reinterpret_cast<char **>(&b->table), batch_sys_bytes() * n) < 0 ||
+      b->alloc(&b->wg_sys, b->grid) < 0 || b->alloc(&b->iters, (size_t)n * MAX_K) < 0 ||
+      b->alloc(&b->status, n) < 0 || b->alloc(&b->relres, (size_t)n * MAX_K) < 0 ||
+      b->alloc(&b->part, part_total) < 0 || b->alloc(&b->bar, (size_t)2 * n) < 0 ||
+      b->alloc(&b->t_done, n) < 0 || b->alloc(&b->t0, 1) < 0)
+    return bail(KS_ERR_NOMEM);
+  std::vector<char> tab(batch_sys_bytes() * n);
+  size_t po = 0;
+  for (int i = 0; i < n; ++i) {
+    ks_ctx *c = b->sys[i];
+    pack_batch_sys(tab.data() + batch_sys_bytes() * i, c->rowptr, c->col, c->S, c->diagS, c->Bv, c->Xv,
+                   (double *)c->pw64.R, (double *)c->pw64.P, (double *)c->pw64.Q, b->part + po,
+                   b->bar + 2 * i, c->N, b->k[i], b->ng[i], b->team0[i], b->team[i],
+                   c->opt.max_it_solve, c->opt.tol_solve, b->iters + (size_t)i * MAX_K,
+                   b->relres + (size_t)i * MAX_K, b->t_done + i, b->status + i);
+    po += (size_t)3 * b->team[i] * 3 * b->k[i];
+  }
+  hipStream_t s = b->s;
+  if (hipMemcpyAsync(b->table, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(b->wg_sys, wg.data(), sizeof(int) * b->grid, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(b->bar, 0, sizeof(unsigned) * 2 * n, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "batch upload failed"));
+  // capture the launch once; every solve replays it
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "stream capture failed"));
+  launch_batch_reset(b->table, n, b->t0, s);
+  launch_batch_pcg(b->grid, b->table, b->wg_sys, s);
+  if (hipStreamEndCapture(s, &b->graph) != hipSuccess ||
+      hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "graph instantiation failed"));
+  if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "event creation failed"));
+  *out = b;
+  return KS_OK;
+}
+
+extern "C" int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host,
+                             int32_t *ng_host) {
+  if (!b) return fail(KS_ERR_ARG, "null batch");
+  if (grid_host) *grid_host = b->grid;
+  for (int i = 0; i < b->n; ++i) {
+    if (team_host) team_host[i] = b->team[i];
+    if (ng_host) ng_host[i] = b->ng[i];
+  }
+  return KS_OK;
+}
+
+extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
+                                    const double *const *lambda_host, double *const *psi_hat,
+                                    ks_batch_stats *st) {
+  if (!b || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
+  hipStream_t s = nullptr;
+  for (int i = 0; i < b->n; ++i) {
+    ks_ctx *c = b->sys[i];
+    s = c->s;
+    if (!c->have_S) return fail(KS_ERR_STATE, "system " + std::to_string(i) + " has no assembled operator");
+    const int k = b->k[i];
+    launch_spmm(c->N, c->rowptr, c->col, c->M, psi_old[i], k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
+    std::vector<double> sc(k);
+    for (int j = 0; j < k; ++j) sc[j] = lambda_host[i][j] + c->mu;
+    HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    launch_scale_cols(c->N, k, c->Bv, c->scal, s);
+    HIPCHK(hipMemcpyAsync(c->Xv, psi_old[i], sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, s));
+    // the batch stream must see each system's right-hand side
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  s = b->s;
+  HIPCHK(hipEventRecord(b->e0, s));
+  HIPCHK(hipGraphLaunch(b->exec, s));
+  HIPCHK(hipEventRecord(b->e1, s));
+  for (int i = 0; i < b->n; ++i) {
+    ks_ctx *c = b->sys[i];
+    HIPCHK(hipMemcpyAsync(psi_hat[i], c->Xv, sizeof(double) * c->N * b->k[i], hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<int> it((size_t)b->n * MAX_K), status(b->n);
+  std::vector<double> rr((size_t)b->n * MAX_K);
+  std::vector<unsigned long long> td(b->n);
+  unsigned long long t0 = 0;
+  HIPCHK(hipMemcpyAsync(it.data(), b->iters, sizeof(int) * it.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rr.data(), b->relres, sizeof(double) * rr.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(status.data(), b->status, sizeof(int) * b->n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(td.data(), b->t_done, sizeof(unsigned long long) * b->n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&t0, b->t0, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
+  int ret = KS_OK;
+  int clk_khz = 100000;  // wall_clock64 runs at a constant 100 MHz
+  (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, 0);
+  for (int i = 0; i < b->n; ++i) {
+    if (status[i] == -2) return fail(KS_ERR_HIP, "batched solve: barrier wait limit hit (system " + std::to_string(i) + ")");
+    if (status[i] == -1) return fail(KS_ERR_BREAKDOWN, "batched solve: PCG breakdown in system " + std::to_string(i));
+    if (status[i] == 1) ret = KS_NOT_CONVERGED;
+  }
+  if (st) {
+    st->seconds = ms * 1e-3;
+    st->n = b->n;
+    for (int i = 0; i < b->n && i < 256; ++i) {
+      st->system_seconds[i] = (double)(td[i] - t0) / ((double)clk_khz * 1e3);
+      int mx = 0;
+      double rmax = 0.0;
+      for (int j = 0; j < b->k[i]; ++j) {
+        mx = std::max(mx, it[(size_t)i * MAX_K + j]);
+        rmax = std::max(rmax, rr[(size_t)i * MAX_K + j]);
+      }
+      st->iters[i] = mx;
+      st->relres[i] = rmax;
+      st->status[i] = status[i];
+    }
+  }
+  return ret;
+}
+
+extern "C" int ks_batch_destroy(ks_batch *b) {
+  if (b) {
+    (void)hipStreamSynchronize(b->s);
+    delete b;
+  }
+  return KS_OK;
+}
+
 extern "C" int ks_destroy(ks_ctx *c) {
   if (!c) return KS_OK;
   (void)hipStreamSynchronize(c->s);
