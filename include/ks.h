@@ -249,6 +249,15 @@ int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host, int
 int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
                          const double *const *lambda_host, double *const *psi_hat,
                          ks_batch_stats *st_host);
+/* Autotuner of the batch layout on these inputs (same arguments as the
+ * solve; outputs discarded).  For each candidate grid (the resident
+ * workgroup count, 3/4, 1/2 and 1/4 of it): lanes per row per system from
+ * one run at each candidate, then `rounds` feedback rounds that resize the
+ * teams so that measured completion times equalise.  Keeps the fastest
+ * layout (and re-captures the graph for its grid); best_ms (host, may be
+ * NULL) receives its launch time. */
+int ks_batch_autotune(ks_batch *b, const double *const *psi_old, const double *const *lambda_host,
+                      int32_t rounds, double *best_ms);
 int ks_batch_destroy(ks_batch *b);
 
 /* Measurement: mean duration (ms, HIP events on the context stream) of

@@ -98,6 +98,8 @@ _SIGS = {
                                 C.POINTER(C.c_int32)]),
     "ks_batch_block_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.POINTER(C.c_double)),
                                        C.POINTER(_P), C.POINTER(BatchStats)]),
+    "ks_batch_autotune": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.POINTER(C.c_double)), C.c_int32,
+                                    C.POINTER(C.c_double)]),
     "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),

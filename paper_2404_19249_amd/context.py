@@ -267,11 +267,7 @@ class KSBatch:
         h = C.c_void_p()
         B.check(self.lib.ks_batch_create(n, hs, karr, int(grid), C.byref(h)), self.lib)
         self.h = h
-        g = C.c_int32()
-        team = (C.c_int32 * n)()
-        ng = (C.c_int32 * n)()
-        B.check(self.lib.ks_batch_info(self.h, C.byref(g), team, ng), self.lib)
-        self.grid, self.team, self.ng = g.value, list(team), list(ng)
+        self._info()
 
     def close(self):
         if getattr(self, "h", None):
@@ -284,17 +280,40 @@ class KSBatch:
         except Exception:
             pass
 
+    def _info(self):
+        n = len(self.ctxs)
+        g = C.c_int32()
+        team = (C.c_int32 * n)()
+        ng = (C.c_int32 * n)()
+        B.check(self.lib.ks_batch_info(self.h, C.byref(g), team, ng), self.lib)
+        self.grid, self.team, self.ng = g.value, list(team), list(ng)
+
+    def _args(self, psis, lams):
+        n = len(self.ctxs)
+        assert len(psis) == n and len(lams) == n
+        lam_a = [_f64(l) for l in lams]
+        for c, p, l, k in zip(self.ctxs, psis, lam_a, self.ks):
+            assert tuple(p.shape) == (c.N, k) and l.size >= k
+        pp = (C.c_void_p * n)(*[c._ptr(p).value for c, p in zip(self.ctxs, psis)])
+        ll = (C.POINTER(C.c_double) * n)(*[B.dptr(l) for l in lam_a])
+        return pp, ll, lam_a
+
+    def autotune(self, psis, lams, rounds=3):
+        """ks_batch_autotune on these inputs; returns the best launch time (ms)."""
+        pp, ll, keep = self._args(psis, lams)
+        ms = C.c_double()
+        B.check(self.lib.ks_batch_autotune(self.h, pp, ll, int(rounds), C.byref(ms)), self.lib)
+        self._info()
+        return ms.value
+
     def block_solve(self, psis, lams, outs=None):
         """psi_hat_s = S_s^{-1} M_s psi_s diag(lam_s + mu_s) for every system s."""
         n = len(self.ctxs)
-        assert len(psis) == n and len(lams) == n
+        pp, ll, keep = self._args(psis, lams)
         outs = outs if outs is not None else [c.empty(c.N, k) for c, k in zip(self.ctxs, self.ks)]
-        lam_a = [_f64(l) for l in lams]
-        for c, p, o, l, k in zip(self.ctxs, psis, outs, lam_a, self.ks):
-            assert tuple(p.shape) == (c.N, k) and tuple(o.shape) == (c.N, k) and l.size >= k
-        pp = (C.c_void_p * n)(*[c._ptr(p).value for c, p in zip(self.ctxs, psis)])
+        for c, o, k in zip(self.ctxs, outs, self.ks):
+            assert tuple(o.shape) == (c.N, k)
         oo = (C.c_void_p * n)(*[c._ptr(o).value for c, o in zip(self.ctxs, outs)])
-        ll = (C.POINTER(C.c_double) * n)(*[B.dptr(l) for l in lam_a])
         st = B.BatchStats()
         code = B.check(self.lib.ks_batch_block_solve(self.h, pp, ll, oo, C.byref(st)), self.lib)
         return outs, {"status": code, "seconds": st.seconds,

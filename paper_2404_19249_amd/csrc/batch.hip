@@ -6,12 +6,23 @@
 // dealt to systems in teams proportional to each system's work (nnz_s k_s),
 // at least one per system; a team owns contiguous row ranges of its system
 // and runs the same recurrences as the single-system solver, separated by
-// team barriers (release/acquire fences around an arrival counter and a
-// generation word).  Team reductions are done redundantly by every workgroup
+// team barriers.  Team reductions are done redundantly by every workgroup
 // of the team from per-workgroup partials in a fixed order, so all members
 // take identical decisions (convergence, stop) without a broadcast.  Every
 // wait is bounded: a barrier that spins past its limit sets the system's
 // status to -2 and the workgroup leaves, so the grid always drains.
+//
+// Memory coherence.  The L2 caches of the eight XCDs are not coherent with
+// each other, and an agent-scope acquire/release fence per barrier (an L2
+// write-back plus an L2 invalidate for every workgroup) thrashes the caches
+// of every team on the XCD.  Instead, the only data one workgroup writes and
+// another reads -- the search directions P and the reduction partials --
+// are stored and loaded with agent-scope atomic (coherent) accesses, which
+// the hardware completes at the device coherence point.  Each wave waits for
+// its own accesses to complete before the barrier arrival, and a workgroup
+// issues loads of other workgroups' data only after it has observed every
+// arrival.  Everything else (the matrix, B, and the R, Q, X rows a
+// workgroup owns) uses ordinary cached accesses.
 #include "common.h"
 #include "kernels.h"
 #include <algorithm>
@@ -23,8 +34,8 @@ struct BatchSys {
   const int32_t *rowptr, *col;
   const double *val, *diag, *B;
   double *X, *R, *P, *Q;
-  double *part;          // [3 phases][team][3k]
-  unsigned int *bar;     // [2]: arrival count, generation
+  double *part;          // shared by all systems: [grid][3 phases][3 MAX_K]
+  unsigned int *bar;     // [2]: arrival count since launch start, unused
   int N, k, ng, team0, team, max_iter;
   double tol;
   int *iters;            // [k]
@@ -35,35 +46,42 @@ struct BatchSys {
 
 constexpr long long SPIN_LIMIT = 1LL << 24;
 
+__device__ __forceinline__ double ld_coh(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ bool team_barrier(unsigned int *bar, int team, int *status) {
+  // bar[0] counts arrivals since the launch started (cleared before each
+  // launch); every episode adds exactly `team` arrivals, so the episode a
+  // workgroup joins ends when the count reaches the next multiple of team.
   __shared__ int s_ok;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's coherent stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
     s_ok = 1;
-    __threadfence();
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = atomicAdd(&bar[0], 1u);
-    if (arrived == (unsigned)team - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > SPIN_LIMIT) {
-          s_ok = 0;
-          atomicExch(status, -2);
-          break;
-        }
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (arrived / (unsigned)team + 1u) * (unsigned)team;
+    long long spins = 0;
+    // relaxed polling: no cache invalidation per poll, one acquire after
+    while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT) {
+        s_ok = 0;
+        atomicExch(status, -2);
+        break;
       }
     }
-    __threadfence();
   }
   __syncthreads();
   return s_ok != 0;
 }
 
-// row product with k columns (one value per lane), NG lanes per row's nonzeros
+// row product with k columns (one value per lane), NG lanes per row's
+// nonzeros; COH: the gathered block is written by other workgroups
+template <bool COH>
 __device__ __forceinline__ double batch_row(int row, int c, int ng, int NG, const int32_t *rowptr,
                                             const int32_t *col, const double *val, const double *X,
                                             int k) {
@@ -82,7 +100,10 @@ __device__ __forceinline__ double batch_row(int row, int c, int ng, int NG, cons
       vv[u] = ok ? v : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc += vv[u] * X[(int64_t)ci[u] * k + c];
+    for (int u = 0; u < 4; ++u) {
+      const double *xp = X + (int64_t)ci[u] * k + c;
+      acc += vv[u] * (COH ? ld_coh(xp) : *xp);
+    }
   }
   return acc;
 }
@@ -105,7 +126,7 @@ __device__ __forceinline__ void wg_cols(double a, bool own, int c, int k, int LP
 __device__ __forceinline__ void team_sum(const double *part, int team, int W, double *s_sum) {
   for (int i = threadIdx.x; i < W; i += blockDim.x) {
     double s = 0.0;
-    for (int t = 0; t < team; ++t) s += part[(int64_t)t * W + i];
+    for (int t = 0; t < team; ++t) s += ld_coh(part + (int64_t)t * 9 * MAX_K + i);
     s_sum[i] = s;
   }
   __syncthreads();
@@ -131,21 +152,23 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   // contiguous row range of this workgroup
   const int chunk = (d.N + team - 1) / team;
   const int r0 = rank * chunk, r1 = min(d.N, r0 + chunk);
+  // partials of team member t (global workgroup team0 + t), phase ph
   const int W3 = 3 * k;
-  double *partI = d.part, *partA = d.part + (int64_t)team * W3, *partB = d.part + 2 * (int64_t)team * W3;
+  constexpr int PS = 9 * MAX_K;
+  double *partI = d.part + (int64_t)d.team0 * PS, *partA = partI + 3 * MAX_K, *partB = partI + 6 * MAX_K;
 
   // ---- init: R = B - S X, P = D^{-1} R; b.b, r.r, r.z
   double abb = 0.0, arr = 0.0, arz = 0.0;
   for (int base = r0; base < r1; base += rows_per_iter) {
     const int row = base + wave * RPW + slot;
     const bool rv = valid && row < r1;
-    double acc = rv ? batch_row(row, c, ng, NG, d.rowptr, d.col, d.val, d.X, k) : 0.0;
+    double acc = rv ? batch_row<false>(row, c, ng, NG, d.rowptr, d.col, d.val, d.X, k) : 0.0;
     for (int off = 1; off < NG; off <<= 1) acc += __shfl_xor(acc, off, 64);
     if (rv && ng == 0) {
       const int64_t ix = (int64_t)row * k + c;
       const double b = d.B[ix], r = b - acc, p = r / d.diag[row];
       d.R[ix] = r;
-      d.P[ix] = p;
+      st_coh(d.P + ix, p);
       abb += b * b;
       arr += r * r;
       arz += r * p;
@@ -155,7 +178,7 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   wg_cols(abb, own, c, k, LPR, RPW, s_red, s_part);
   wg_cols(arr, own, c, k, LPR, RPW, s_red, s_part + k);
   wg_cols(arz, own, c, k, LPR, RPW, s_red, s_part + 2 * k);
-  for (int i = threadIdx.x; i < W3; i += blockDim.x) partI[(int64_t)rank * W3 + i] = s_part[i];
+  for (int i = threadIdx.x; i < W3; i += blockDim.x) st_coh(partI + (int64_t)rank * PS + i, s_part[i]);
   if (!team_barrier(d.bar, team, d.status)) return;
   team_sum(partI, team, W3, s_sum);
   for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
@@ -182,20 +205,20 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     for (int base = r0; base < r1; base += rows_per_iter) {
       const int row = base + wave * RPW + slot;
       const bool rv = valid && row < r1;
-      double acc = rv ? batch_row(row, c, ng, NG, d.rowptr, d.col, d.val, d.P, k) : 0.0;
+      double acc = rv ? batch_row<true>(row, c, ng, NG, d.rowptr, d.col, d.val, d.P, k) : 0.0;
       for (int off = 1; off < NG; off <<= 1) acc += __shfl_xor(acc, off, 64);
       if (rv && ng == 0) {
         const int64_t ix = (int64_t)row * k + c;
         d.Q[ix] = acc;
-        apq += d.P[ix] * acc;
+        apq += ld_coh(d.P + ix) * acc;
       }
     }
     wg_cols(apq, own, c, k, LPR, RPW, s_red, s_part);
-    for (int i = threadIdx.x; i < k; i += blockDim.x) partA[(int64_t)rank * W3 + i] = s_part[i];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) st_coh(partA + (int64_t)rank * PS + i, s_part[i]);
     if (!team_barrier(d.bar, team, d.status)) return;
     for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
       double pq = 0.0;
-      for (int t = 0; t < team; ++t) pq += partA[(int64_t)t * W3 + cc];
+      for (int t = 0; t < team; ++t) pq += ld_coh(partA + (int64_t)t * PS + cc);
       s_alpha[cc] = 0.0;
       if (s_active[cc]) {
         if (!(pq > 0.0)) s_flags[1] = 1;
@@ -216,13 +239,13 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     }
     wg_cols(brz, own, c, k, LPR, RPW, s_red, s_part);
     wg_cols(brr, own, c, k, LPR, RPW, s_red, s_part + k);
-    for (int i = threadIdx.x; i < 2 * k; i += blockDim.x) partB[(int64_t)rank * W3 + i] = s_part[i];
+    for (int i = threadIdx.x; i < 2 * k; i += blockDim.x) st_coh(partB + (int64_t)rank * PS + i, s_part[i]);
     if (!team_barrier(d.bar, team, d.status)) return;
     for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
       double rz = 0.0, rr = 0.0;
       for (int t = 0; t < team; ++t) {
-        rz += partB[(int64_t)t * W3 + cc];
-        rr += partB[(int64_t)t * W3 + k + cc];
+        rz += ld_coh(partB + (int64_t)t * PS + cc);
+        rr += ld_coh(partB + (int64_t)t * PS + k + cc);
       }
       if (s_active[cc]) {
         s_beta[cc] = rz / s_rz[cc];
@@ -246,9 +269,9 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
       const int row = base + wave * RPW + slot;
       if (!(valid && row < r1 && ng == 0)) continue;
       const int64_t ix = (int64_t)row * k + c;
-      const double p = d.P[ix];
+      const double p = ld_coh(d.P + ix);
       d.X[ix] += s_alpha[c] * p;
-      d.P[ix] = d.R[ix] / d.diag[row] + s_beta[c] * p;
+      st_coh(d.P + ix, d.R[ix] / d.diag[row] + s_beta[c] * p);
     }
     if (s_flags[0] && !s_flags[1])
       if (!team_barrier(d.bar, team, d.status)) return;
@@ -266,8 +289,8 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   }
 }
 
-// start of a launch: clears status and arrival counters (not the generation
-// words) and stamps the device clock
+// start of a launch: clears status and arrival counters and stamps the
+// device clock
 __global__ void k_batch_reset(BatchSys *systems, int n, unsigned long long *t0) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     *systems[i].status = 0;
@@ -283,6 +306,7 @@ void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStrea
                      reinterpret_cast<const BatchSys *>(systems), wg_sys);
 }
 size_t batch_sys_bytes() { return sizeof(BatchSys); }
+size_t batch_part_stride() { return 9 * MAX_K; }
 int batch_resident_grid() {
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;

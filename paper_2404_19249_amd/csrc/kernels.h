@@ -185,6 +185,7 @@ int launch_coldots(int N, int k, const double *X, const double *Y, double *part,
 namespace ks {
 // ------------------------------------------------------------------ batch
 size_t batch_sys_bytes();
+size_t batch_part_stride();
 int batch_resident_grid();
 void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const double *val,
                     const double *diag, const double *B, double *X, double *R, double *P, double *Q,

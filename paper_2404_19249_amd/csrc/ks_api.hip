@@ -1081,10 +1081,11 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
 
 // ---------------------------------------------------------------- batches
 struct ks_batch {
-  int n = 0, grid = 0;
+  int n = 0, grid = 0, grid_max = 0;
   hipStream_t s = nullptr;
   std::vector<ks_ctx *> sys;
   std::vector<int> k, team, team0, ng;
+  std::vector<double> weight;  // relative cost per system, drives the team split
   DevBuf mem;
   void *table = nullptr;
   int *wg_sys = nullptr, *iters = nullptr, *status = nullptr;
@@ -1112,6 +1113,73 @@ struct ks_batch {
   }
 };
 
+// largest NG (lanes per row) allowed for k columns: k*NG lanes fit a wave
+static int batch_ng_cap(int k, int ng) {
+  while (ng > 1 && ng * k > 64) ng >>= 1;
+  return ng;
+}
+
+// Teams proportional to the weights (largest remainders), at least one
+// workgroup each, summing to the grid; table and workgroup map uploaded.
+static int batch_layout(ks_batch *b) {
+  const int n = b->n;
+  double total = 0.0;
+  for (double w : b->weight) total += w;
+  const int left = b->grid - n;
+  std::vector<std::pair<double, int>> rem(n);
+  int used = 0;
+  for (int i = 0; i < n; ++i) {
+    const double share = (double)left * b->weight[i] / total;
+    const int extra = (int)std::floor(share);
+    b->team[i] = 1 + extra;
+    used += b->team[i];
+    rem[i] = {share - extra, i};
+  }
+  std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+    return x.first > y.first || (x.first == y.first && x.second < y.second);
+  });
+  for (int j = 0; used < b->grid; j = (j + 1) % n, ++used) b->team[rem[j].second]++;
+  std::vector<int> wg(b->grid);
+  for (int i = 0, o = 0; i < n; ++i) {
+    b->team0[i] = o;
+    for (int t = 0; t < b->team[i]; ++t) wg[o++] = i;
+  }
+  std::vector<char> tab(batch_sys_bytes() * n);
+  for (int i = 0; i < n; ++i) {
+    ks_ctx *c = b->sys[i];
+    pack_batch_sys(tab.data() + batch_sys_bytes() * i, c->rowptr, c->col, c->S, c->diagS, c->Bv, c->Xv,
+                   (double *)c->pw64.R, (double *)c->pw64.P, (double *)c->pw64.Q, b->part,
+                   b->bar + 2 * i, c->N, b->k[i], b->ng[i], b->team0[i], b->team[i],
+                   c->opt.max_it_solve, c->opt.tol_solve, b->iters + (size_t)i * MAX_K,
+                   b->relres + (size_t)i * MAX_K, b->t_done + i, b->status + i);
+  }
+  // the launch reads these at its start: upload synchronously
+  HIPCHK(hipMemcpyAsync(b->table, tab.data(), tab.size(), hipMemcpyHostToDevice, b->s));
+  HIPCHK(hipMemcpyAsync(b->wg_sys, wg.data(), sizeof(int) * b->grid, hipMemcpyHostToDevice, b->s));
+  HIPCHK(hipStreamSynchronize(b->s));
+  return KS_OK;
+}
+
+// (re)capture the launch for the current grid; every solve replays it (the
+// table it reads is rewritten in place when the layout is retuned)
+static int batch_capture(ks_batch *b) {
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  hipStream_t s = b->s;
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  launch_batch_reset(b->table, b->n, b->t0, s);
+  launch_batch_pcg(b->grid, b->table, b->wg_sys, s);
+  HIPCHK(hipStreamEndCapture(s, &b->graph));
+  HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return KS_OK;
+}
+
 extern "C" int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t *k_host,
                                int32_t grid_req, ks_batch **out) {
   if (n < 1 || n > 256 || !systems || !k_host || !out)
@@ -1126,76 +1194,40 @@ extern "C" int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t 
   // non-null stream, and the contexts' streams may be the null stream
   if (hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(KS_ERR_HIP, "stream creation failed"));
-  double total = 0.0;
-  std::vector<double> work(n);
   for (int i = 0; i < n; ++i) {
     ks_ctx *c = systems[i];
     if (!c) return bail(fail(KS_ERR_ARG, "null system"));
     if (k_host[i] < 1 || k_host[i] > c->k_max) return bail(fail(KS_ERR_ARG, "k out of range"));
+    if (std::find(b->sys.begin(), b->sys.end(), c) != b->sys.end())
+      return bail(fail(KS_ERR_ARG, "a context appears twice in the batch"));
     b->sys.push_back(c);
     b->k.push_back(k_host[i]);
-    work[i] = (double)c->nnz * k_host[i] + 1.0;
-    total += work[i];
-    // lanes per row: the system's autotuned choice, else by k
-    int ng = c->ng64 > 0 ? c->ng64 : (k_host[i] == 1 ? 8 : (k_host[i] <= 4 ? 4 : (k_host[i] <= 12 ? 2 : 1)));
-    while (ng > 1 && ng * k_host[i] > 64) ng >>= 1;
-    b->ng.push_back(ng);
+    // initial cost model: matrix entries times columns, plus rows
+    b->weight.push_back((double)c->nnz * k_host[i] + 8.0 * c->N);
+    // lanes per row: the system's autotuned choice, else a rule by k
+    const int ng = c->ng64 > 0 ? c->ng64 : (k_host[i] == 1 ? 8 : (k_host[i] <= 4 ? 4 : (k_host[i] <= 12 ? 2 : 1)));
+    b->ng.push_back(batch_ng_cap(k_host[i], ng));
   }
-  int resident = batch_resident_grid();
+  const int resident = batch_resident_grid();
   if (resident <= 0) return bail(fail(KS_ERR_HIP, "occupancy query failed"));
-  int grid = grid_req > 0 ? std::min<int>(grid_req, resident) : resident;
-  if (grid < n) return bail(fail(KS_ERR_ARG, "more systems than resident workgroups"));
-  // teams proportional to work, at least one workgroup each
+  b->grid = grid_req > 0 ? std::min<int>(grid_req, resident) : resident;
+  if (b->grid < n) return bail(fail(KS_ERR_ARG, "more systems than resident workgroups"));
+  b->grid_max = b->grid;
   b->team.assign(n, 1);
-  int left = grid - n;
-  for (int i = 0; i < n; ++i) {
-    const int extra = (int)std::floor((double)left * work[i] / total);
-    b->team[i] += extra;
-  }
-  int used = 0;
-  for (int i = 0; i < n; ++i) used += b->team[i];
-  for (int i = 0; used > grid; i = (i + 1) % n)
-    if (b->team[i] > 1) { b->team[i]--; used--; }
-  b->grid = used;
-  b->team0.resize(n);
-  std::vector<int> wg(b->grid);
-  for (int i = 0, o = 0; i < n; ++i) {
-    b->team0[i] = o;
-    for (int t = 0; t < b->team[i]; ++t) wg[o++] = i;
-  }
-  size_t part_total = 0;
-  for (int i = 0; i < n; ++i) part_total += (size_t)3 * b->team[i] * 3 * b->k[i];
+  b->team0.assign(n, 0);
   if (b->alloc(reinterpret_cast<char **>(&b->table), batch_sys_bytes() * n) < 0 ||
       b->alloc(&b->wg_sys, b->grid) < 0 || b->alloc(&b->iters, (size_t)n * MAX_K) < 0 ||
       b->alloc(&b->status, n) < 0 || b->alloc(&b->relres, (size_t)n * MAX_K) < 0 ||
-      b->alloc(&b->part, part_total) < 0 || b->alloc(&b->bar, (size_t)2 * n) < 0 ||
+      b->alloc(&b->part, (size_t)b->grid * batch_part_stride()) < 0 || b->alloc(&b->bar, (size_t)2 * n) < 0 ||
       b->alloc(&b->t_done, n) < 0 || b->alloc(&b->t0, 1) < 0)
     return bail(KS_ERR_NOMEM);
-  std::vector<char> tab(batch_sys_bytes() * n);
-  size_t po = 0;
-  for (int i = 0; i < n; ++i) {
-    ks_ctx *c = b->sys[i];
-    pack_batch_sys(tab.data() + batch_sys_bytes() * i, c->rowptr, c->col, c->S, c->diagS, c->Bv, c->Xv,
-                   (double *)c->pw64.R, (double *)c->pw64.P, (double *)c->pw64.Q, b->part + po,
-                   b->bar + 2 * i, c->N, b->k[i], b->ng[i], b->team0[i], b->team[i],
-                   c->opt.max_it_solve, c->opt.tol_solve, b->iters + (size_t)i * MAX_K,
-                   b->relres + (size_t)i * MAX_K, b->t_done + i, b->status + i);
-    po += (size_t)3 * b->team[i] * 3 * b->k[i];
+  if (hipMemsetAsync(b->bar, 0, sizeof(unsigned) * 2 * n, b->s) != hipSuccess)
+    return bail(fail(KS_ERR_HIP, "batch clear failed"));
+  {
+    int r = batch_layout(b);
+    if (r >= 0) r = batch_capture(b);
+    if (r < 0) return bail(r);
   }
-  hipStream_t s = b->s;
-  if (hipMemcpyAsync(b->table, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(b->wg_sys, wg.data(), sizeof(int) * b->grid, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemsetAsync(b->bar, 0, sizeof(unsigned) * 2 * n, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return bail(fail(KS_ERR_HIP, "batch upload failed"));
-  // capture the launch once; every solve replays it
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return bail(fail(KS_ERR_HIP, "stream capture failed"));
-  launch_batch_reset(b->table, n, b->t0, s);
-  launch_batch_pcg(b->grid, b->table, b->wg_sys, s);
-  if (hipStreamEndCapture(s, &b->graph) != hipSuccess ||
-      hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
-    return bail(fail(KS_ERR_HIP, "graph instantiation failed"));
   if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
     return bail(fail(KS_ERR_HIP, "event creation failed"));
   *out = b;
@@ -1213,14 +1245,11 @@ extern "C" int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *tea
   return KS_OK;
 }
 
-extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
-                                    const double *const *lambda_host, double *const *psi_hat,
-                                    ks_batch_stats *st) {
-  if (!b || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
-  hipStream_t s = nullptr;
+// right-hand sides B_s = M_s psi_s diag(lambda_s + mu_s), X_s = psi_s
+static int batch_prepare(ks_batch *b, const double *const *psi_old, const double *const *lambda_host) {
   for (int i = 0; i < b->n; ++i) {
     ks_ctx *c = b->sys[i];
-    s = c->s;
+    hipStream_t s = c->s;
     if (!c->have_S) return fail(KS_ERR_STATE, "system " + std::to_string(i) + " has no assembled operator");
     const int k = b->k[i];
     launch_spmm(c->N, c->rowptr, c->col, c->M, psi_old[i], k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
@@ -1232,14 +1261,15 @@ extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
     // the batch stream must see each system's right-hand side
     HIPCHK(hipStreamSynchronize(s));
   }
-  s = b->s;
+  return KS_OK;
+}
+
+// one replay of the captured launch; per-system results into st
+static int batch_run(ks_batch *b, ks_batch_stats *st) {
+  hipStream_t s = b->s;
   HIPCHK(hipEventRecord(b->e0, s));
   HIPCHK(hipGraphLaunch(b->exec, s));
   HIPCHK(hipEventRecord(b->e1, s));
-  for (int i = 0; i < b->n; ++i) {
-    ks_ctx *c = b->sys[i];
-    HIPCHK(hipMemcpyAsync(psi_hat[i], c->Xv, sizeof(double) * c->N * b->k[i], hipMemcpyDeviceToDevice, s));
-  }
   std::vector<int> it((size_t)b->n * MAX_K), status(b->n);
   std::vector<double> rr((size_t)b->n * MAX_K);
   std::vector<unsigned long long> td(b->n);
@@ -1252,31 +1282,108 @@ extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
-  int ret = KS_OK;
-  int clk_khz = 100000;  // wall_clock64 runs at a constant 100 MHz
+  int clk_khz = 100000;  // wall_clock64 runs at a constant rate (100 MHz unless reported)
   (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, 0);
+  int ret = KS_OK;
   for (int i = 0; i < b->n; ++i) {
-    if (status[i] == -2) return fail(KS_ERR_HIP, "batched solve: barrier wait limit hit (system " + std::to_string(i) + ")");
+    if (status[i] == -2)
+      return fail(KS_ERR_HIP, "batched solve: barrier wait limit hit (system " + std::to_string(i) + ")");
     if (status[i] == -1) return fail(KS_ERR_BREAKDOWN, "batched solve: PCG breakdown in system " + std::to_string(i));
     if (status[i] == 1) ret = KS_NOT_CONVERGED;
   }
-  if (st) {
-    st->seconds = ms * 1e-3;
-    st->n = b->n;
-    for (int i = 0; i < b->n && i < 256; ++i) {
-      st->system_seconds[i] = (double)(td[i] - t0) / ((double)clk_khz * 1e3);
-      int mx = 0;
-      double rmax = 0.0;
-      for (int j = 0; j < b->k[i]; ++j) {
-        mx = std::max(mx, it[(size_t)i * MAX_K + j]);
-        rmax = std::max(rmax, rr[(size_t)i * MAX_K + j]);
-      }
-      st->iters[i] = mx;
-      st->relres[i] = rmax;
-      st->status[i] = status[i];
+  std::memset(st, 0, sizeof(*st));
+  st->seconds = ms * 1e-3;
+  st->n = b->n;
+  for (int i = 0; i < b->n; ++i) {
+    st->system_seconds[i] = (double)(td[i] - t0) / ((double)clk_khz * 1e3);
+    int mx = 0;
+    double rmax = 0.0;
+    for (int j = 0; j < b->k[i]; ++j) {
+      mx = std::max(mx, it[(size_t)i * MAX_K + j]);
+      rmax = std::max(rmax, rr[(size_t)i * MAX_K + j]);
     }
+    st->iters[i] = mx;
+    st->relres[i] = rmax;
+    st->status[i] = status[i];
   }
   return ret;
+}
+
+extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
+                                    const double *const *lambda_host, double *const *psi_hat,
+                                    ks_batch_stats *st) {
+  if (!b || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
+  TRY(batch_prepare(b, psi_old, lambda_host));
+  ks_batch_stats loc;
+  const int ret = batch_run(b, &loc);
+  if (ret < 0) return ret;
+  for (int i = 0; i < b->n; ++i) {
+    ks_ctx *c = b->sys[i];
+    HIPCHK(hipMemcpyAsync(psi_hat[i], c->Xv, sizeof(double) * c->N * b->k[i], hipMemcpyDeviceToDevice, b->s));
+  }
+  HIPCHK(hipStreamSynchronize(b->s));
+  if (st) *st = loc;
+  return ret;
+}
+
+// Autotuner of the batch layout on the given inputs.  For each candidate
+// grid (the resident workgroup count and fractions of it): (1) lanes per
+// row, per system, from one run at each candidate; (2) team sizes by
+// feedback: the weight of a system becomes its measured time times its
+// team, so the next split equalises completion times.  Keeps the fastest
+// layout seen.
+extern "C" int ks_batch_autotune(ks_batch *b, const double *const *psi_old,
+                                 const double *const *lambda_host, int32_t rounds, double *best_ms) {
+  if (!b || !psi_old || !lambda_host) return fail(KS_ERR_ARG, "null argument");
+  ks_batch_stats st;
+  const int n = b->n;
+  const std::vector<double> w0 = b->weight;
+  double best = 1e300;
+  int best_grid = b->grid;
+  std::vector<int> best_ng = b->ng;
+  std::vector<double> best_w = b->weight;
+  auto run = [&]() -> int {
+    TRY(batch_layout(b));
+    TRY(batch_prepare(b, psi_old, lambda_host));
+    const int r = batch_run(b, &st);
+    return r < 0 ? r : KS_OK;
+  };
+  for (int frac : {4, 3, 2, 1}) {
+    const int g = b->grid_max * frac / 4;
+    if (g < n) continue;
+    b->grid = g;
+    TRY(batch_capture(b));
+    b->weight = w0;
+    std::vector<double> t_best(n, 1e300);
+    std::vector<int> ng_best(b->ng);
+    for (int ng : {1, 2, 4, 8}) {
+      for (int i = 0; i < n; ++i) b->ng[i] = batch_ng_cap(b->k[i], ng);
+      TRY(run());
+      for (int i = 0; i < n; ++i)
+        if (st.system_seconds[i] < t_best[i]) {
+          t_best[i] = st.system_seconds[i];
+          ng_best[i] = b->ng[i];
+        }
+    }
+    b->ng = ng_best;
+    for (int r = 0; r < std::max(1, (int)rounds); ++r) {
+      TRY(run());
+      if (st.seconds < best) {
+        best = st.seconds;
+        best_grid = g;
+        best_ng = b->ng;
+        best_w = b->weight;
+      }
+      for (int i = 0; i < n; ++i) b->weight[i] = std::max(st.system_seconds[i], 1e-7) * b->team[i];
+    }
+  }
+  b->grid = best_grid;
+  b->ng = best_ng;
+  b->weight = best_w;
+  TRY(batch_layout(b));
+  TRY(batch_capture(b));
+  if (best_ms) *best_ms = best * 1e3;
+  return KS_OK;
 }
 
 extern "C" int ks_batch_destroy(ks_batch *b) {

@@ -53,6 +53,10 @@ def test_batched_solve_matches_single_solves(grid):
     b = KSBatch(ctxs, [w.k for w in ws], grid=grid)
     print(f"[case] grid={b.grid} teams={b.team} ng={b.ng}", flush=True)
     assert b.grid == (grid if grid else b.grid) and sum(b.team) == b.grid
+    if grid == 0:
+        ms = b.autotune(psis, lams, rounds=2)
+        print(f"[case] tuned {ms:.3f} ms teams={b.team} ng={b.ng}", flush=True)
+        assert ms > 0 and sum(b.team) == b.grid and min(b.team) >= 1
     for rep in range(3):
         outs, st = b.block_solve(psis, lams)
         assert st["status"] == 0 and all(s == 0 for s in st["sys_status"])
