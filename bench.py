@@ -82,6 +82,51 @@ def cpu_baseline(k):
                       f" {dt:.2f} s"}
 
 
+def batched_leg(torch, np, reps=3):
+    """The batched workload: 48 independent systems of uneven size (P1/P2,
+    12^3..40^3 hexes, k = 1..12) solved together in one persistent launch
+    replayed from a hipGraph, after the layout autotuner; against the same
+    systems solved one after another with the single-system solver."""
+    from ks_inputs.workloads import batched_systems
+    from paper_2404_19249_amd import KSContext, KSBatch
+    t0 = time.perf_counter()
+    ws = batched_systems(48)
+    ctxs, psis, lams = [], [], []
+    for w in ws:
+        c = KSContext.from_workload(w, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
+        psi, lam = c.initial_guess(w.k)
+        c.assemble(psi, w.occ, want_fields=False)
+        ctxs.append(c); psis.append(psi); lams.append(lam)
+    setup = time.perf_counter() - t0
+    seq = []
+    for c, p, l in zip(ctxs, psis, lams):
+        c.block_solve(p, l)
+    for c, p, l in zip(ctxs, psis, lams):
+        seq.append(c.block_solve(p, l)[1]["seconds"])
+    b = KSBatch(ctxs, [w.k for w in ws])
+    tuned_ms = b.autotune(psis, lams, rounds=4)
+    launches, st = [], None
+    for r in range(reps):
+        outs, st = b.block_solve(psis, lams)
+        launches.append(st["seconds"])
+    t = float(np.median(launches))
+    ss = np.array(st["system_seconds"]) * 1e3
+    dofs = sum(c.N * w.k for c, w in zip(ctxs, ws))
+    its = st["iters"]
+    byt = sum(i * cg_iteration_bytes(c.N, c.nnz, w.k, 8) for i, c, w in zip(its, ctxs, ws))
+    out = {"systems": len(ws), "sum_N_k": dofs, "launch_ms": t * 1e3,
+           "dof_rhs_per_s": dofs / t, "p50_system_ms": float(np.percentile(ss, 50)),
+           "p99_system_ms": float(np.percentile(ss, 99)), "max_system_ms": float(ss.max()),
+           "sequential_device_ms": sum(seq) * 1e3, "speedup_vs_sequential": sum(seq) / t,
+           "grid": b.grid, "autotune_best_ms": tuned_ms,
+           "iteration_GBs": byt / t / 1e9, "relres_max": float(max(st["relres"])),
+           "setup_s": setup}
+    b.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +137,7 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--mode", default="step", choices=["step", "solve"],
                     help="solve: skip the SCF steps (block solves and kernel timings only, "
                          "for profiling)")
@@ -212,6 +258,13 @@ def main():
                                                           "energies", "total"])}},
     }
     ctx.close()
+    if not args.no_batched:
+        log("[bench] batched form ...")
+        try:
+            forms["batched"] = batched_leg(torch, np)
+            log(f"[bench] batched: {json.dumps(forms['batched'])}")
+        except Exception as e:  # reported, never hides the headline
+            forms["batched"] = {"error": repr(e)}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(k)

@@ -427,6 +427,34 @@ __global__ void k_add(int64_t n, const double *__restrict__ a, const double *__r
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = a[i] + b[i];
 }
+// Row permutations between the API's natural numbering and the storage
+// order: to storage dst[r] = src[int2nat[r]]; to API dst[int2nat[r]] = src[r]
+// (k contiguous values per row).
+__global__ void k_rows_perm(int N, int k, const double *__restrict__ src, double *__restrict__ dst,
+                            const int32_t *__restrict__ int2nat, int to_api) {
+  const int64_t n = (int64_t)N * k;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / k, c = i - r * k;
+    const int64_t o = (int64_t)int2nat[r] * k + c;
+    if (to_api) dst[o] = src[i];
+    else dst[i] = src[o];
+  }
+}
+void launch_rows_to_storage(int N, int k, const double *src_api, double *dst, const int32_t *int2nat,
+                            hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_rows_perm, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
+                       s, N, k, src_api, dst, int2nat, 0);
+}
+void launch_rows_to_api(int N, int k, const double *src, double *dst_api, const int32_t *int2nat,
+                        hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  if (n > 0)
+    hipLaunchKernelGGL(k_rows_perm, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
+                       s, N, k, src, dst_api, int2nat, 1);
+}
+
 void launch_add(int64_t n, const double *a, const double *b, double *out, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_add, grid_for(n), dim3(256), 0, s, n, a, b, out);
 }

@@ -165,6 +165,10 @@ void launch_fill_pencil(int m, int nH, const double *PP, const double *tail, dou
                         hipStream_t s);
 // out = a + b  (n doubles)
 void launch_add(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+void launch_rows_to_storage(int N, int k, const double *src_api, double *dst, const int32_t *int2nat,
+                            hipStream_t s);
+void launch_rows_to_api(int N, int k, const double *src, double *dst_api, const int32_t *int2nat,
+                        hipStream_t s);
 }  // namespace ks
 
 namespace ks {

@@ -96,8 +96,10 @@ struct ks_ctx {
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
   // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
   int32_t *rowptr = nullptr, *col = nullptr, *rowptrB = nullptr, *colB = nullptr;
-  int32_t *rorder = nullptr;    // active row schedule of the SpMM kernels (nullptr = natural)
-  int32_t *rorder_m = nullptr;  // Morton schedule
+  int32_t *rorder = nullptr;    // active row schedule of the SpMM kernels (nullptr = storage order)
+  int32_t *rorder_m = nullptr;  // Morton schedule of the rows
+  int32_t *int2nat = nullptr;   // natural (API) index of each stored unknown
+  std::vector<int32_t> h_int2nat;
   int ng64 = 0, ng32 = 0, ngP = 0;  // lanes per row in the SpMM phase (0 = default)
   double *K = nullptr, *M = nullptr, *AL = nullptr, *base = nullptr, *S = nullptr,
          *MNL = nullptr, *diagS = nullptr, *diagK = nullptr;
@@ -133,6 +135,7 @@ struct ks_ctx {
   // block vectors [N][k_max]
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
          *occ_d = nullptr, *scal = nullptr;
+  double *PsiIn = nullptr, *Xs = nullptr;  // API-order inputs in storage order; solve output
   float *B32 = nullptr, *X32 = nullptr;
   PCGWork pw64{}, pw32{}, pwP{};
   unsigned int *counters = nullptr;
@@ -367,20 +370,55 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   const int32_t *el = mesh->elems_host;
   for (int64_t i = 0; i < (int64_t)ne * nl; ++i)
     if (el[i] < 0 || el[i] >= nn) return bail(fail(KS_ERR_MESH, "element node id out of range"));
-  // interior / boundary numbering
-  std::vector<int32_t> node2int(nn, -1), node2bnd(nn, -1), bnodes;
-  int N = 0;
+  // interior / boundary numbering.  The unknowns are stored in Morton
+  // (Z-curve) order of their node coordinates, so that consecutive rows are
+  // spatial neighbours (compact row blocks, short gather distances); the API
+  // numbers them by ascending node id ("natural" index) and every DOF-indexed
+  // argument is permuted at the boundary (int2nat).  KS_DOF_ORDER=natural
+  // keeps the natural order inside too.
+  std::vector<int32_t> node2int(nn, -1), node2bnd(nn, -1), bnodes, nat_nodes;
   for (int i = 0; i < nn; ++i) {
     if (mesh->dirichlet_host[i]) {
       node2bnd[i] = (int)bnodes.size();
       bnodes.push_back(i);
     } else {
-      node2int[i] = N++;
+      nat_nodes.push_back(i);
     }
   }
+  const int N = (int)nat_nodes.size();
   c->N = N;
   c->NB = (int)bnodes.size();
   if (N == 0) return bail(fail(KS_ERR_MESH, "mesh has no interior node"));
+  c->h_int2nat.resize(N);
+  for (int r = 0; r < N; ++r) c->h_int2nat[r] = r;
+  {
+    const char *env = std::getenv("KS_DOF_ORDER");
+    if (!(env && std::strcmp(env, "natural") == 0)) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int r = 0; r < N; ++r)
+        for (int d = 0; d < 3; ++d) {
+          const double x = mesh->coords_host[3 * (int64_t)nat_nodes[r] + d];
+          lo[d] = std::min(lo[d], x);
+          hi[d] = std::max(hi[d], x);
+        }
+      std::vector<uint64_t> key(N);
+      parallel_for(N, [&](int64_t r) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; ++d) {
+          const double x = mesh->coords_host[3 * (int64_t)nat_nodes[r] + d];
+          const double t = (hi[d] > lo[d]) ? (x - lo[d]) / (hi[d] - lo[d]) : 0.0;
+          q[d] = (uint64_t)std::min(1048575.0, std::max(0.0, std::floor(t * 1048576.0)));
+        }
+        uint64_t k = 0;
+        for (int b = 19; b >= 0; --b)
+          for (int d = 2; d >= 0; --d) k = (k << 1) | ((q[d] >> b) & 1u);
+        key[r] = k;
+      });
+      std::stable_sort(c->h_int2nat.begin(), c->h_int2nat.end(),
+                       [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+    }
+  }
+  for (int r = 0; r < N; ++r) node2int[nat_nodes[c->h_int2nat[r]]] = r;
   std::vector<int32_t> edof((size_t)ne * nl);
   for (int64_t i = 0; i < (int64_t)ne * nl; ++i) edof[i] = node2int[el[i]];
   // node -> element adjacency
@@ -673,6 +711,9 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(Xv, (size_t)N * km);
   A_(Wv, (size_t)N * km);
   A_(PsiHat, (size_t)N * km);
+  A_(PsiIn, (size_t)N * km);
+  A_(Xs, (size_t)N * km);
+  A_(int2nat, N);
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
   A_(scal, 64);
@@ -723,6 +764,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   H2D(c->col, colI.data(), c->nnz);
   H2D(c->rowptrB, rowptrB.data(), N + 1);
   H2D(c->rorder_m, rorder.data(), N);
+  H2D(c->int2nat, c->h_int2nat.data(), N);
   {
     const char *env = std::getenv("KS_ROW_ORDER");
     c->rorder = (env && std::strcmp(env, "morton") == 0) ? c->rorder_m : nullptr;
@@ -836,7 +878,9 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
   for (auto &t : tab)
     if (std::strcmp(t.n, name) == 0) {
       if (n > t.size) return fail(KS_ERR_ARG, "buffer smaller than requested");
-      HIPCHK(hipMemcpyAsync(dst, t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
+      const bool rows = (t.p == c->Z || t.p == c->Y) && n == t.size;
+      if (rows) launch_rows_to_api(c->N, c->mp, t.p, dst, c->int2nat, c->s);  // API row order
+      else HIPCHK(hipMemcpyAsync(dst, t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
       HIPCHK(hipStreamSynchronize(c->s));
       return KS_OK;
     }
@@ -1252,12 +1296,13 @@ static int batch_prepare(ks_batch *b, const double *const *psi_old, const double
     hipStream_t s = c->s;
     if (!c->have_S) return fail(KS_ERR_STATE, "system " + std::to_string(i) + " has no assembled operator");
     const int k = b->k[i];
-    launch_spmm(c->N, c->rowptr, c->col, c->M, psi_old[i], k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
+    launch_rows_to_storage(c->N, k, psi_old[i], c->PsiIn, c->int2nat, s);
+    launch_spmm(c->N, c->rowptr, c->col, c->M, c->PsiIn, k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
     std::vector<double> sc(k);
     for (int j = 0; j < k; ++j) sc[j] = lambda_host[i][j] + c->mu;
     HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     launch_scale_cols(c->N, k, c->Bv, c->scal, s);
-    HIPCHK(hipMemcpyAsync(c->Xv, psi_old[i], sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->Xv, c->PsiIn, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, s));
     // the batch stream must see each system's right-hand side
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -1319,7 +1364,7 @@ extern "C" int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
   if (ret < 0) return ret;
   for (int i = 0; i < b->n; ++i) {
     ks_ctx *c = b->sys[i];
-    HIPCHK(hipMemcpyAsync(psi_hat[i], c->Xv, sizeof(double) * c->N * b->k[i], hipMemcpyDeviceToDevice, b->s));
+    launch_rows_to_api(c->N, b->k[i], c->Xv, psi_hat[i], c->int2nat, b->s);
   }
   HIPCHK(hipStreamSynchronize(b->s));
   if (st) *st = loc;
@@ -1453,7 +1498,8 @@ extern "C" int ks_assemble(ks_ctx *c, const double *psi, int32_t k, const double
   if (!c) return fail(KS_ERR_ARG, "null context");
   if (psi && (k < 1 || k > c->k_max || !occ_host)) return fail(KS_ERR_ARG, "k must be in 1..k_max with occupations");
   int piters = 0;
-  TRY(assemble_impl(c, psi, k, occ_host, &piters));
+  if (psi) launch_rows_to_storage(c->N, k, psi, c->PsiIn, c->int2nat, c->s);
+  TRY(assemble_impl(c, psi ? c->PsiIn : nullptr, k, occ_host, &piters));
   const int64_t nqt = (int64_t)c->n_e * c->n_q;
   if (rho_q) HIPCHK(hipMemcpyAsync(rho_q, c->rho_l, sizeof(double) * nqt, hipMemcpyDeviceToDevice, c->s));
   if (veff_q) launch_combine3(nqt, 1.0, c->vext_q, 1.0, c->vh_q, 1.0, c->vxc_q, veff_q, c->s);
@@ -1485,9 +1531,35 @@ extern "C" int ks_export_operator(ks_ctx *c, int32_t which, int32_t *row_ptr, in
     case 4: src = c->MNL; break;
     default: return fail(KS_ERR_ARG, "which must be 0..4");
   }
-  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, c->rowptr, sizeof(int32_t) * (c->N + 1), hipMemcpyDeviceToDevice, c->s));
-  if (colp) HIPCHK(hipMemcpyAsync(colp, c->col, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToDevice, c->s));
-  if (val) HIPCHK(hipMemcpyAsync(val, src, sizeof(double) * c->nnz, hipMemcpyDeviceToDevice, c->s));
+  // stored rows/columns are in storage order: rebuild the CSR in the API's
+  // natural numbering on the host (inspection only, not a hot path)
+  const int N = c->N;
+  std::vector<int32_t> rp(N + 1), cl(c->nnz), nrp(N + 1, 0), ncl(c->nnz);
+  std::vector<double> vl(c->nnz), nvl(c->nnz);
+  HIPCHK(hipMemcpyAsync(rp.data(), c->rowptr, sizeof(int32_t) * (N + 1), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(cl.data(), c->col, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(vl.data(), src, sizeof(double) * c->nnz, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  const std::vector<int32_t> &i2n = c->h_int2nat;
+  std::vector<int32_t> n2i(N);
+  for (int r = 0; r < N; ++r) n2i[i2n[r]] = r;
+  for (int i = 0; i < N; ++i) nrp[i + 1] = nrp[i] + (rp[n2i[i] + 1] - rp[n2i[i]]);
+  parallel_for(N, [&](int64_t i) {
+    const int r = n2i[i];
+    std::vector<std::pair<int32_t, double>> e;
+    e.reserve(rp[r + 1] - rp[r]);
+    for (int j = rp[r]; j < rp[r + 1]; ++j) e.push_back({i2n[cl[j]], vl[j]});
+    std::sort(e.begin(), e.end(), [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+      return x.first < y.first;
+    });
+    for (size_t t = 0; t < e.size(); ++t) {
+      ncl[nrp[i] + t] = e[t].first;
+      nvl[nrp[i] + t] = e[t].second;
+    }
+  });
+  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, nrp.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, c->s));
+  if (colp) HIPCHK(hipMemcpyAsync(colp, ncl.data(), sizeof(int32_t) * c->nnz, hipMemcpyHostToDevice, c->s));
+  if (val) HIPCHK(hipMemcpyAsync(val, nvl.data(), sizeof(double) * c->nnz, hipMemcpyHostToDevice, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
   return KS_OK;
 }
@@ -1592,9 +1664,14 @@ extern "C" int ks_block_solve_rhs(ks_ctx *c, const double *B, const double *X0, 
   if (!c || !B || !X) return fail(KS_ERR_ARG, "null argument");
   if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
   if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
-  if (X0) HIPCHK(hipMemcpyAsync(X, X0, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
-  else HIPCHK(hipMemsetAsync(X, 0, sizeof(double) * c->N * k, c->s));
-  return solve_impl(c, B, X, k, precision, tol > 0 ? tol : c->opt.tol_solve, st);
+  launch_rows_to_storage(c->N, k, B, c->Bv, c->int2nat, c->s);
+  if (X0) launch_rows_to_storage(c->N, k, X0, c->Xs, c->int2nat, c->s);
+  else HIPCHK(hipMemsetAsync(c->Xs, 0, sizeof(double) * c->N * k, c->s));
+  const int r = solve_impl(c, c->Bv, c->Xs, k, precision, tol > 0 ? tol : c->opt.tol_solve, st);
+  if (r < 0) return r;
+  launch_rows_to_api(c->N, k, c->Xs, X, c->int2nat, c->s);
+  HIPCHK(hipStreamSynchronize(c->s));
+  return r;
 }
 
 // B = M psi diag(lambda + mu)
@@ -1612,10 +1689,14 @@ extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *la
   if (!c || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
   if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
   if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
-  TRY(build_rhs(c, psi_old, lambda_host, k, c->Bv));
-  if (psi_hat != psi_old)
-    HIPCHK(hipMemcpyAsync(psi_hat, psi_old, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
-  return solve_impl(c, c->Bv, psi_hat, k, precision, c->opt.tol_solve, st);
+  launch_rows_to_storage(c->N, k, psi_old, c->PsiIn, c->int2nat, c->s);
+  TRY(build_rhs(c, c->PsiIn, lambda_host, k, c->Bv));
+  HIPCHK(hipMemcpyAsync(c->Xs, c->PsiIn, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
+  const int r = solve_impl(c, c->Bv, c->Xs, k, precision, c->opt.tol_solve, st);
+  if (r < 0) return r;
+  launch_rows_to_api(c->N, k, c->Xs, psi_hat, c->int2nat, c->s);
+  HIPCHK(hipStreamSynchronize(c->s));
+  return r;
 }
 
 // -------------------------------------------------------- augmented basis
@@ -1659,7 +1740,8 @@ extern "C" int ks_augmented_project(ks_ctx *c, const double *psi_hat, int32_t k,
   } else
     return fail(KS_ERR_ARG, "which must be 0, 1 or 2");
   c->have_step = false;
-  TRY(build_tail(c, psi_hat, k));
+  launch_rows_to_storage(c->N, k, psi_hat, c->PsiIn, c->int2nat, c->s);
+  TRY(build_tail(c, c->PsiIn, k));
   project_full(c, H, c->N_H + k, F);
   HIPCHK(hipStreamSynchronize(c->s));
   return KS_OK;
@@ -1737,7 +1819,8 @@ extern "C" int ks_initial_guess(ks_ctx *c, int32_t k, double *psi, double *lambd
   c->have_step = false;
   TRY(orth_impl(c, c->GPP, c->N_H));
   TRY(eig_impl(c, c->FAL_PP, c->GPP, c->N_H, k, c->U, th, &rank));
-  launch_ellP_times(c->N, c->Pidx, c->Pw, c->U, k, k, 1.0, nullptr, 0, psi, k, c->s);
+  launch_ellP_times(c->N, c->Pidx, c->Pw, c->U, k, k, 1.0, nullptr, 0, c->Xs, k, c->s);
+  launch_rows_to_api(c->N, k, c->Xs, psi, c->int2nat, c->s);
   for (int j = 0; j < k; ++j) lambda_host[j] = th[j];
   HIPCHK(hipStreamSynchronize(c->s));
   return KS_OK;
@@ -1791,12 +1874,13 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   const bool nonlinear = hartree || c->opt.xc_mode != KS_XC_NONE;
   // 1. S of the input density (w_D frozen from here on)
   int piters = 0;
-  TRY(assemble_impl(c, psi, k, occ_host, &piters));
+  launch_rows_to_storage(N, k, psi, c->PsiIn, c->int2nat, s);
+  TRY(assemble_impl(c, c->PsiIn, k, occ_host, &piters));
   HIPCHK(hipStreamSynchronize(s));
   const double t1 = now_s();
   // 2. BVPs
-  TRY(build_rhs(c, psi, lambda_host, k, c->Bv));
-  HIPCHK(hipMemcpyAsync(c->PsiHat, psi, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
+  TRY(build_rhs(c, c->PsiIn, lambda_host, k, c->Bv));
+  HIPCHK(hipMemcpyAsync(c->PsiHat, c->PsiIn, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
   int st = solve_impl(c, c->Bv, c->PsiHat, k, precision, c->opt.tol_solve, &R.solve);
   if (st < 0) return st;
   R.status_solve = st;
@@ -1895,7 +1979,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   R.rank = rank;
   const double t4 = now_s();
   // 5. outputs and energies
-  HIPCHK(hipMemcpyAsync(psi, c->PsiNew, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
+  launch_rows_to_api(N, k, c->PsiNew, psi, c->int2nat, s);
   if (rho_q) HIPCHK(hipMemcpyAsync(rho_q, c->rho_out, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
   double band = 0.0;
   for (int j = 0; j < k; ++j) {
