@@ -165,8 +165,7 @@ def main():
     log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
     ctx.assemble(psi, occ, want_fields=False)
     tune = ctx.autotune(k, reps=10)
-    log(f"[bench] autotune: order={tune['order']} NG fp64={tune['ng_fp64']} fp32={tune['ng_fp32']} "
-        f"poisson={tune['ng_poisson']} ms={json.dumps(tune['ms'])}")
+    log(f"[bench] autotune: {json.dumps(tune)}")
     if args.mode == "solve":
         args.warmup, args.steps = 0, 0
     for i in range(args.warmup):

@@ -268,14 +268,17 @@ int ks_batch_destroy(ks_batch *b);
  * 6 the Hartree Poisson SpMM phase (k = 1).  Requires a prior ks_assemble. */
 int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
 
-/* Autotuner of the SpMM launch shape: on the current operator S (and the
- * Poisson operator K), times the SpMM phase of the block PCG for every row
- * schedule (numbering order, Morton order of the node coordinates) and every
- * split of a row's nonzeros over NG = 1, 2, 4, 8 lanes, in FP64 and FP32
- * with k columns (Poisson: k = 1), and keeps the fastest for later solves of
- * this context.  report_host (NULL to skip) receives 28 doubles:
- * {order, NG fp64, NG fp32, NG Poisson, then ms[order][fp64|fp32|Poisson][NG]}.
- * Requires a prior ks_assemble. */
+/* Autotuner of the SpMM phase: on the current operator S (and the Poisson
+ * operator K), times the SpMM phase of the block PCG for every kernel
+ * candidate -- the row kernel with a row's nonzeros split over NG = 1, 2, 4,
+ * 8 lanes, and the LDS-staged halo-tile kernel with row blocks of 16, 32,
+ * 64, 128, 256 rows and 16 or 32 bytes of columns per lane -- in FP64 and
+ * FP32 with k columns (Poisson: k = 1), and keeps the fastest for later
+ * solves of this context.  report_host (NULL to skip) receives 48 doubles:
+ * {NG fp64, NG fp32, NG Poisson, tile rows fp64, fp32, Poisson (0 = row
+ * kernel chosen, negative = 32-byte form), then row-kernel ms[fp64|fp32|
+ * Poisson][NG], then tile-kernel ms[fp64|fp32|Poisson][rows][16|32 bytes]
+ * (-1: not available for this shape)}.  Requires a prior ks_assemble. */
 int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 
 /* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",

@@ -209,16 +209,21 @@ class KSContext:
         return g, F, self._stats(st, 64)
 
     def autotune(self, k, reps=10):
-        """ks_autotune: pick the SpMM row schedule and lanes-per-row split."""
-        rep = (C.c_double * 28)()
+        """ks_autotune: pick the SpMM phase kernel (row kernel lanes-per-row
+        split, or halo-tile row-block size) per solver."""
+        rep = (C.c_double * 48)()
         B.check(self.lib.ks_autotune(self.h, int(k), int(reps), rep), self.lib)
         r = list(rep)
         names = ["fp64", "fp32", "poisson"]
-        return {"order": "morton" if r[0] else "natural", "ng_fp64": int(r[1]),
-                "ng_fp32": int(r[2]), "ng_poisson": int(r[3]),
-                "ms": {("morton" if o else "natural"): {names[w]: dict(zip([1, 2, 4, 8],
-                       r[4 + o * 12 + w * 4: 8 + o * 12 + w * 4])) for w in range(3)}
-                       for o in range(2)}}
+        out = {}
+        for w, n in enumerate(names):
+            out[f"ng_{n}"] = int(r[w])
+            out[f"tile_{n}"] = int(r[3 + w])
+            out[f"row_ms_{n}"] = dict(zip([1, 2, 4, 8], r[6 + 4 * w: 10 + 4 * w]))
+            t = r[18 + 10 * w: 28 + 10 * w]
+            out[f"tile_ms_{n}"] = {f"{br}{'w' if d else ''}": t[2 * i + d]
+                                   for i, br in enumerate([16, 32, 64, 128, 256]) for d in (0, 1)}
+        return out
 
     def debug_buffer(self, name, n):
         """Copy of an internal buffer (diagnostics)."""

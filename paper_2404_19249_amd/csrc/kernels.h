@@ -90,12 +90,30 @@ void launch_scale_cols(int N, int k, double *Y, const double *scale_dev, hipStre
 
 // PCG driver (device-side per-column scalars; host polls every `chunk`
 // iterations).  Solves S X = B for k columns from X (in/out) to tol.
+// Halo tiling of a CSR pattern for the LDS-staged SpMM: row block b is
+// rows [b*BR, min(N, (b+1)*BR)); its halo is the sorted set of columns its
+// rows reference (halo_col[halo_ptr[b] .. halo_ptr[b+1])), and lcol[j] is
+// the position of col[j] in its row block's halo.
+struct Tiling {
+  int BR = 0, nblk = 0, max_halo = 0, max_nnz = 0;  // max_nnz: most nonzeros in one block
+  int32_t *halo_ptr = nullptr, *halo_col = nullptr;
+  int32_t *hself = nullptr;  // [nblk] position of the block's first row in its halo
+  uint16_t *lcol = nullptr;
+};
+// LDS bytes the tiled SpMM needs for k columns of elem-byte values (0 if the
+// tiling cannot serve this shape).  The kernel reads the value and index
+// arrays in whole 16-byte chunks: each must extend 16 bytes past its last
+// entry.
+size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem);
+
 struct PCGWork {
   void *R, *P, *Q;       // [N][k] of T
   void *part;            // block partials [nblk][2k] doubles
   void *state;           // device ColState[k] + control
   unsigned int *counter; // last-block counters
   int nblk_max;
+  const Tiling *til;     // SpMM phase: LDS-staged halo tiles (nullptr = row kernel)
+  bool til_wide;         // tiled kernel with 32 bytes of columns per lane (else 16)
 };
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,

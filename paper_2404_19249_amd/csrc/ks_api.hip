@@ -138,6 +138,11 @@ struct ks_ctx {
   double *PsiIn = nullptr, *Xs = nullptr;  // API-order inputs in storage order; solve output
   float *B32 = nullptr, *X32 = nullptr;
   PCGWork pw64{}, pw32{}, pwP{};
+  // halo tilings of the CSR pattern for the LDS-staged SpMM, row blocks of
+  // TILE_BR[i] rows; chosen tiling per solver (-1 = row kernel)
+  static constexpr int NTILE = 5;
+  Tiling til[NTILE];
+  int tile64 = -1, tile32 = -1, tileP = -1;
   unsigned int *counters = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
@@ -314,6 +319,26 @@ static int weighted_dots(ks_ctx *c, int nd, const double *const *a, const double
 }
 
 // ------------------------------------------------------------------- create
+// row-block sizes of the halo tilings
+static const int TILE_BR[ks_ctx::NTILE] = {16, 32, 64, 128, 256};
+static int tile_index(int br) {
+  for (int i = 0; i < ks_ctx::NTILE; ++i)
+    if (TILE_BR[i] == br) return i;
+  return -1;
+}
+// tile choice code: 2 * tiling index + wide flag (32 bytes of columns per
+// lane), -1 = row kernel
+static void apply_tiles(ks_ctx *c) {
+  auto set = [&](PCGWork &w, int code) {
+    const int i = code >= 0 ? code / 2 : -1;
+    w.til = (i >= 0 && c->til[i].nblk) ? &c->til[i] : nullptr;
+    w.til_wide = code >= 0 && (code & 1);
+  };
+  set(c->pw64, c->tile64);
+  set(c->pw32, c->tile32);
+  set(c->pwP, c->tileP);
+}
+
 extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
                          const ks_atoms_desc *atoms, const ks_options *opt, hipStream_t stream,
                          ks_ctx **out) {
@@ -480,6 +505,62 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
     std::copy(ci.begin(), ci.end(), colI.begin() + rowptr[r]);
     std::copy(cb.begin(), cb.end(), colB.begin() + rowptrB[r]);
   });
+  // halo tilings (row blocks of consecutive rows in the Morton storage order)
+  std::vector<int32_t> t_hptr[ks_ctx::NTILE], t_hcol[ks_ctx::NTILE], t_hself[ks_ctx::NTILE];
+  std::vector<uint16_t> t_lcol[ks_ctx::NTILE];
+  for (int ti = 0; ti < ks_ctx::NTILE; ++ti) {
+    const int BR = TILE_BR[ti];
+    const int nblk = (N + BR - 1) / BR;
+    std::vector<std::vector<int32_t>> halos(nblk);
+    t_lcol[ti].assign(c->nnz, 0);
+    std::vector<int> ok(nblk, 1);
+    parallel_for(nblk, [&](int64_t b) {
+      const int r0 = (int)b * BR, r1 = std::min(N, r0 + BR);
+      std::vector<int32_t> &h = halos[b];
+      h.assign(colI.begin() + rowptr[r0], colI.begin() + rowptr[r1]);
+      std::sort(h.begin(), h.end());
+      h.erase(std::unique(h.begin(), h.end()), h.end());
+      if (h.size() > 65535) {
+        ok[b] = 0;
+        return;
+      }
+      for (int64_t j = rowptr[r0]; j < rowptr[r1]; ++j)
+        t_lcol[ti][j] = (uint16_t)(std::lower_bound(h.begin(), h.end(), colI[j]) - h.begin());
+    });
+    bool all = true;
+    for (int b = 0; b < nblk; ++b) all = all && ok[b];
+    if (!all) continue;  // halo too large for 16-bit local indices: tiling unused
+    t_hptr[ti].assign(nblk + 1, 0);
+    int mx = 0;
+    for (int b = 0; b < nblk; ++b) {
+      t_hptr[ti][b + 1] = t_hptr[ti][b] + (int32_t)halos[b].size();
+      mx = std::max(mx, (int)halos[b].size());
+    }
+    int mnz = 0;
+    t_hself[ti].resize(nblk);
+    for (int b = 0; b < nblk; ++b) {
+      mnz = std::max(mnz, rowptr[std::min(N, (b + 1) * BR)] - rowptr[b * BR]);
+      // every row has its diagonal, so the block's rows form one run of the
+      // sorted halo; hself = where it starts
+      const int r0 = b * BR, nr = std::min(BR, N - r0);
+      const int hs = (int)(std::lower_bound(halos[b].begin(), halos[b].end(), r0) - halos[b].begin());
+      t_hself[ti][b] = hs;
+      for (int rr = 0; rr < nr; ++rr)
+        if (hs + rr >= (int)halos[b].size() || halos[b][hs + rr] != r0 + rr) all = false;
+    }
+    if (!all) {  // a row without its diagonal entry: tiling unused
+      c->til[ti] = Tiling();
+      continue;
+    }
+    c->til[ti].max_nnz = mnz;
+    t_hcol[ti].resize(t_hptr[ti][nblk]);
+    parallel_for(nblk, [&](int64_t b) {
+      std::copy(halos[b].begin(), halos[b].end(), t_hcol[ti].begin() + t_hptr[ti][b]);
+    });
+    c->til[ti].BR = BR;
+    c->til[ti].nblk = nblk;
+    c->til[ti].max_halo = mx;
+  }
   // element -> value slot map (interior rows only)
   std::vector<int32_t> slot((size_t)ne * nl * nl, -1);
   parallel_for(ne, [&](int64_t e) {
@@ -645,15 +726,15 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(rowptrB, N + 1);
   A_(rorder_m, N);
   A_(colB, std::max<int64_t>(1, c->nnzB));
-  A_(K, c->nnz_ext);
+  A_(K, c->nnz_ext + 2);  // + 16 bytes: chunked reads of the tiled SpMM
   A_(M, c->nnz_ext);
   A_(AL, c->nnz_ext);
   A_(base, c->nnz_ext);
-  A_(S, c->nnz_ext);
+  A_(S, c->nnz_ext + 2);
   A_(MNL, c->nnz_ext);
   A_(diagS, N);
   A_(diagK, N);
-  A_(S32, c->nnz);
+  A_(S32, c->nnz + 8);  // 16-byte chunk reads past the end (tiled SpMM)
   A_(diagS32, N);
   A_(vext_q, nqt);
   A_(rho_l, nqt);
@@ -714,6 +795,13 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(PsiIn, (size_t)N * km);
   A_(Xs, (size_t)N * km);
   A_(int2nat, N);
+  for (int ti = 0; ti < ks_ctx::NTILE; ++ti)
+    if (c->til[ti].nblk) {
+      A_(til[ti].halo_ptr, t_hptr[ti].size());
+      A_(til[ti].halo_col, t_hcol[ti].size() + 8);  // 16-byte chunk reads past the end
+      A_(til[ti].hself, t_hself[ti].size());
+      A_(til[ti].lcol, t_lcol[ti].size() + 16);  // 16-byte chunk reads past the end
+    }
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
   A_(scal, 64);
@@ -765,6 +853,13 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   H2D(c->rowptrB, rowptrB.data(), N + 1);
   H2D(c->rorder_m, rorder.data(), N);
   H2D(c->int2nat, c->h_int2nat.data(), N);
+  for (int ti = 0; ti < ks_ctx::NTILE; ++ti)
+    if (c->til[ti].nblk) {
+      H2D(c->til[ti].halo_ptr, t_hptr[ti].data(), t_hptr[ti].size());
+      if (!t_hcol[ti].empty()) H2D(c->til[ti].halo_col, t_hcol[ti].data(), t_hcol[ti].size());
+      H2D(c->til[ti].hself, t_hself[ti].data(), t_hself[ti].size());
+      if (!t_lcol[ti].empty()) H2D(c->til[ti].lcol, t_lcol[ti].data(), t_lcol[ti].size());
+    }
   {
     const char *env = std::getenv("KS_ROW_ORDER");
     c->rorder = (env && std::strcmp(env, "morton") == 0) ? c->rorder_m : nullptr;
@@ -775,6 +870,17 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
     c->ng64 = geti("KS_SPMM_NG64");
     c->ng32 = geti("KS_SPMM_NG32");
     c->ngP = geti("KS_SPMM_NGP");
+    // SpMM phase kernel before any autotuning: halo tiles of 64 rows (FP64),
+    // 128 (FP32), 256 (Poisson, one column); KS_TILE64/32/P = rows, 0 = row kernel
+    auto tile_env = [&](const char *n, int dflt) {
+      const char *v = std::getenv(n);
+      const int i = tile_index(v ? std::atoi(v) : dflt);
+      return i >= 0 ? 2 * i : -1;
+    };
+    c->tile64 = tile_env("KS_TILE64", 16);
+    c->tile32 = tile_env("KS_TILE32", 32);
+    c->tileP = tile_env("KS_TILEP", 64);
+    apply_tiles(c);
   }
   H2D(c->colB, colB.data(), colB.size());
   H2D(c->Pidx, Pidx.data(), Pidx.size());
@@ -922,48 +1028,77 @@ extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps,
 }
 
 // Autotuner: times the SpMM phase of the block PCG (FP64, FP32) and of the
-// Poisson solve on the current operator for every row schedule and lanes-
-// per-row split, and keeps the fastest for this context.
+// Poisson solve on the current operator for every kernel candidate -- the
+// row kernel with NG = 1, 2, 4, 8 lanes per row and the LDS-staged halo
+// kernel with row blocks of 32, 64, 128, 256 rows -- and keeps the fastest
+// for this context.
 extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_host) {
   if (!c) return fail(KS_ERR_ARG, "null context");
   if (k < 1 || k > c->k_max || reps < 1) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
   const int ngs[4] = {1, 2, 4, 8};
-  double best_total = 1e300;
-  int best[4] = {0, 0, 0, 0};  // order, ng64, ng32, ngP
-  double times[2][3][4];
-  for (int ord = 0; ord < 2; ++ord) {
-    c->rorder = ord ? c->rorder_m : nullptr;
-    double bt[3] = {1e300, 1e300, 1e300};
-    int bn[3] = {1, 1, 8};
-    for (int w = 0; w < 3; ++w)
-      for (int i = 0; i < 4; ++i) {
-        const int which = w == 0 ? 0 : (w == 1 ? 3 : 6);
-        const int kk = w == 2 ? 1 : k;
-        float ms = 0.f;
-        if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0)
-          return fail(KS_ERR_HIP, "autotune timing failed");
-        times[ord][w][i] = ms;
-        if (ms < bt[w]) {
-          bt[w] = ms;
-          bn[w] = ngs[i];
-        }
+  double t_row[3][4], t_til[3][2 * ks_ctx::NTILE];
+  int best_ng[3] = {1, 1, 8}, best_tile[3] = {-1, -1, -1};
+  PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
+  c->rorder = nullptr;
+  for (int w = 0; w < 3; ++w) {
+    const int which = w == 0 ? 0 : (w == 1 ? 3 : 6);
+    const int kk = w == 2 ? 1 : k;
+    double bt = 1e300;
+    const Tiling *keep = ws[w]->til;
+    const bool keep_db = ws[w]->til_wide;
+    ws[w]->til = nullptr;
+    for (int i = 0; i < 4; ++i) {
+      float ms = 0.f;
+      if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0) {
+        ws[w]->til = keep;
+        ws[w]->til_wide = keep_db;
+        return fail(KS_ERR_HIP, "autotune timing failed");
       }
-    const double total = bt[0] + bt[1];
-    if (total < best_total) {
-      best_total = total;
-      best[0] = ord; best[1] = bn[0]; best[2] = bn[1]; best[3] = bn[2];
+      t_row[w][i] = ms;
+      if (ms < bt) {
+        bt = ms;
+        best_ng[w] = ngs[i];
+        best_tile[w] = -1;
+      }
     }
+    for (int code = 0; code < 2 * ks_ctx::NTILE; ++code) {
+      const int i = code / 2;
+      t_til[w][code] = -1.0;
+      if (!c->til[i].nblk) continue;
+      ws[w]->til = &c->til[i];
+      ws[w]->til_wide = code & 1;
+      float ms = 0.f;
+      const int r = time_phase(c, which, kk, reps, 0, &ms);
+      if (r == -3) continue;  // does not fit in LDS for this shape
+      if (r < 0) {
+        ws[w]->til = keep;
+        ws[w]->til_wide = keep_db;
+        return fail(KS_ERR_HIP, "autotune timing failed");
+      }
+      t_til[w][code] = ms;
+      if (ms < bt) {
+        bt = ms;
+        best_tile[w] = code;
+      }
+    }
+    ws[w]->til = keep;
+    ws[w]->til_wide = keep_db;
   }
-  c->rorder = best[0] ? c->rorder_m : nullptr;
-  c->ng64 = best[1];
-  c->ng32 = best[2];
-  c->ngP = best[3];
+  c->ng64 = best_ng[0];
+  c->ng32 = best_ng[1];
+  c->ngP = best_ng[2];
+  c->tile64 = best_tile[0];
+  c->tile32 = best_tile[1];
+  c->tileP = best_tile[2];
+  apply_tiles(c);
   if (report_host) {
-    for (int j = 0; j < 4; ++j) report_host[j] = best[j];
-    for (int o = 0; o < 2; ++o)
-      for (int w = 0; w < 3; ++w)
-        for (int i = 0; i < 4; ++i) report_host[4 + o * 12 + w * 4 + i] = times[o][w][i];
+    for (int w = 0; w < 3; ++w) {
+      report_host[w] = best_ng[w];
+      report_host[3 + w] = best_tile[w] >= 0 ? TILE_BR[best_tile[w] / 2] * ((best_tile[w] & 1) ? -1 : 1) : 0;
+      for (int i = 0; i < 4; ++i) report_host[6 + w * 4 + i] = t_row[w][i];
+      for (int i = 0; i < 2 * ks_ctx::NTILE; ++i) report_host[18 + w * 2 * ks_ctx::NTILE + i] = t_til[w][i];
+    }
   }
   return KS_OK;
 }

@@ -307,6 +307,223 @@ void launch_refine_update(int N, int k, const float *D, const double *scale, dou
                        dim3(256), 0, s, n, k, D, scale, X);
 }
 
+
+// ============================================================ tiled SpMM
+// q = S p for one block of BR consecutive rows at a time.  Everything the
+// block reads is first copied into LDS with direct global->LDS loads (each
+// lane moves one 16-byte chunk, a wave fills 64 consecutive chunks): the rows
+// of p the block references (its halo, typically 2.5-6x BR rows) as a
+// row-major [halo][k] image, and the block's contiguous runs of matrix values
+// and 16-bit local column indices.  Then every (row, VW-column group) lane
+// walks its row's nonzeros entirely in LDS.  The matrix is streamed once,
+// the block vector is read from HBM about once (neighbouring blocks of one
+// XCD share halo rows in L2), and no gather goes through the vector L1.
+// Several workgroups per CU overlap one block's copies with another's math.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef const __attribute__((address_space(1))) void gbl_void_t;
+
+// nchunks CB-byte chunks (CB = 16 or 4): chunk c comes from src_of(c) and
+// lands at lds + CB c
+template <int CB, typename F>
+__device__ __forceinline__ void dma(int nchunks, unsigned char *lds, F src_of) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c0 = wave * 64; c0 < nchunks; c0 += nw * 64) {
+    const int c = c0 + lane;
+    if (c < nchunks) {
+      lds_void_t *d = (lds_void_t *)(lds + (size_t)c0 * CB);
+      if constexpr (CB == 16) __builtin_amdgcn_global_load_lds((gbl_void_t *)src_of(c), d, 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds((gbl_void_t *)src_of(c), d, 4, 0, 0);
+    }
+  }
+}
+
+// LDS layout of one block: halo image, values, local indices; every region
+// a whole number of 1 KB wave fills.  Several workgroups per CU overlap one
+// block's copies with another block's arithmetic.
+struct TLayout {
+  int halo, vals, idx;  // byte offsets
+  int total;
+};
+__host__ __device__ __forceinline__ int round_kb(int b) { return (b + 1023) / 1024 * 1024; }
+__host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nnz, int rowbytes, int elem) {
+  TLayout L;
+  L.halo = 0;
+  L.vals = round_kb(max_halo * rowbytes);
+  L.idx = L.vals + round_kb(max_nnz * elem + 32);
+  L.total = L.idx + round_kb(max_nnz * 2 + 32);
+  return L;
+}
+
+// Q = S P for the rows of the tiling, partial p.q per workgroup.  VW columns
+// per lane (k % VW == 0); halo rows copied in HCB-byte chunks, HCB = 16 when
+// k * sizeof(T) % 16 == 0, else 4; N * k * sizeof(T) < 2^32 (byte offsets
+// into P are 32-bit).  All checked by the host.
+template <typename T, int VW, int HCB>
+__global__ void __launch_bounds__(256) k_tpcg_A(int N, int k, int BR, int nblk, int max_halo, int max_nnz,
+                                                const int32_t *__restrict__ halo_ptr,
+                                                const int32_t *__restrict__ halo_col,
+                                                const int32_t *__restrict__ hself,
+                                                const int32_t *__restrict__ rowptr,
+                                                const uint16_t *__restrict__ lcol,
+                                                const T *__restrict__ val, const T *__restrict__ P,
+                                                T *__restrict__ Q, double *__restrict__ part,
+                                                const Control *ctl) {
+  if (ctl && ctl->stop) return;
+  extern __shared__ __align__(16) unsigned char t_smem[];
+  __shared__ double s_red[256 * VW];
+  const int CG = k / VW;
+  const unsigned rowbytes = (unsigned)k * sizeof(T);
+  const int CH = (int)rowbytes / HCB;
+  const TLayout L = tile_layout(max_halo, max_nnz, (int)rowbytes, (int)sizeof(T));
+  // fixed (row slot, column group) per thread: RPP rows per pass
+  const int RPP = (int)blockDim.x / CG;
+  const int cg = threadIdx.x % CG, rslot = threadIdx.x / CG;
+  const bool active = rslot < RPP;
+  // halo copy: this lane's first chunk (h0c, ch0c) and the per-pass stride
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, per = (int)blockDim.x;
+  const int h0c = (wave * 64 + lane) / CH, ch0c = (wave * 64 + lane) - h0c * CH;
+  const int dh = per / CH, dch = per - dh * CH;
+  double apq[VW];
+  for (int v = 0; v < VW; ++v) apq[v] = 0.0;
+  const unsigned char *Pb = reinterpret_cast<const unsigned char *>(P);
+  const unsigned char *Vb = reinterpret_cast<const unsigned char *>(val);
+  const unsigned char *Ib = reinterpret_cast<const unsigned char *>(lcol);
+  for (GroupIter gi = group_iter(nblk); gi.g < gi.end; gi.g += gi.step) {
+    const int b = gi.g;
+    const int hb0 = halo_ptr[b], nh = halo_ptr[b + 1] - hb0;
+    const int r0 = b * BR, nr = min(BR, N - r0);
+    const int j0 = rowptr[r0], j1 = rowptr[r0 + nr];
+    __syncthreads();  // the previous block is done with the LDS image
+    {
+      const int32_t *hl = halo_col + hb0;
+      const int total = nh * CH;
+      int h = h0c, ch = ch0c;
+      for (int c0 = wave * 64; c0 < total; c0 += per) {
+        if (c0 + lane < total) {
+          const unsigned off = (unsigned)hl[h] * rowbytes + (unsigned)(ch * HCB);
+          lds_void_t *d = (lds_void_t *)(t_smem + L.halo + (unsigned)c0 * HCB);
+          if constexpr (HCB == 16) __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 16, 0, 0);
+          else __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 4, 0, 0);
+        }
+        h += dh;
+        ch += dch;
+        if (ch >= CH) {
+          ch -= CH;
+          h += 1;
+        }
+      }
+    }
+    const int64_t va = ((int64_t)j0 * sizeof(T)) & ~(int64_t)15;
+    const int64_t vb = ((int64_t)j1 * sizeof(T) + 15) & ~(int64_t)15;
+    dma<16>((int)((vb - va) / 16), t_smem + L.vals, [&](int c) { return Vb + va + (int64_t)c * 16; });
+    const int64_t ia = ((int64_t)j0 * 2) & ~(int64_t)15;
+    const int64_t ib = ((int64_t)j1 * 2 + 15) & ~(int64_t)15;
+    dma<16>((int)((ib - ia) / 16), t_smem + L.idx, [&](int c) { return Ib + ia + (int64_t)c * 16; });
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    __syncthreads();                // ... and every wave's
+    const T *xs = reinterpret_cast<const T *>(t_smem + L.halo) + cg * VW;
+    const T *vs = reinterpret_cast<const T *>(t_smem + L.vals + ((int64_t)j0 * sizeof(T) - va)) - j0;
+    const uint16_t *is = reinterpret_cast<const uint16_t *>(t_smem + L.idx + ((int64_t)j0 * 2 - ia)) - j0;
+    const int hs = hself[b];  // halo position of row r0; rows r0.. are consecutive there
+    for (int rr = rslot; active && rr < nr; rr += RPP) {
+      const int row = r0 + rr;
+      T acc[VW];
+      for (int v = 0; v < VW; ++v) acc[v] = T(0);
+      const int jb = rowptr[row], je = rowptr[row + 1];
+      int j = jb;
+      constexpr int U = (VW * sizeof(T) > 16) ? 4 : 8;
+      for (; j + U <= je; j += U) {
+        int li[U];
+        T vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          li[u] = is[j + u];
+          vv[u] = vs[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + li[u] * k);
+          for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
+        }
+      }
+      for (; j < je; ++j) {
+        const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + (int)is[j] * k);
+        const T w = vs[j];
+        for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
+      }
+      const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + (hs + rr) * k);
+      for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
+      store_row<T, VW>(Q, row, k, cg * VW, k, acc);
+    }
+  }
+  // per-workgroup column partials (fixed order): thread t holds columns
+  // [(t % CG) VW, (t % CG) VW + VW) of its rows
+  __syncthreads();
+  for (int v = 0; v < VW; ++v) s_red[threadIdx.x * VW + v] = active ? apq[v] : 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    const int g = c / VW, v = c % VW;
+    double sum = 0.0;
+    for (int t = g; t < RPP * CG; t += CG) sum += s_red[t * VW + v];
+    part[(int64_t)blockIdx.x * k + c] = sum;
+  }
+}
+
+size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem) {
+  if (!t.nblk || (k * elem) % 4 != 0) return 0;
+  return (size_t)tile_layout(t.max_halo, t.max_nnz, k * (int)elem, (int)elem).total;
+}
+
+// launch shape of the tiled SpMM for this operator: VW, halo chunk, grid, LDS
+struct TShape {
+  int VW = 1, HCB = 16, grid = 0;
+  size_t lds = 0;
+};
+constexpr size_t TILE_LDS_MAX = 160 * 1024 - 256 * sizeof(double) * 8 - 512;
+// wide: 32 bytes of columns per lane instead of 16 (when k allows)
+template <typename T>
+static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, bool wide) {
+  TShape sh;
+  const int vw16 = 16 / (int)sizeof(T);
+  if (wide && k % (2 * vw16) == 0) sh.VW = 2 * vw16;
+  else if (!wide && k % vw16 == 0) sh.VW = vw16;
+  else if (!wide) sh.VW = 1;
+  else return sh;  // no wide form for this k
+  sh.HCB = ((k * sizeof(T)) % 16 == 0) ? 16 : 4;
+  sh.lds = tiled_lds_bytes(t, k, sizeof(T));
+  if (sh.lds == 0 || sh.lds > TILE_LDS_MAX || (double)N * k * sizeof(T) >= 4294967296.0) return sh;
+  const int per_cu = std::max(1, std::min(8, (int)(TILE_LDS_MAX / sh.lds)));
+  int g = std::min(t.nblk, 256 * per_cu);
+  if (g > 8) g = g / 8 * 8;
+  sh.grid = std::max(1, std::min(g, nblk_max));
+  return sh;
+}
+
+template <typename T, int VW, int HCB>
+static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
+                           const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)TILE_LDS_MAX) != hipSuccess)
+      return -1;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB>), dim3(sh.grid), dim3(256), sh.lds, s, N, k, t.BR, t.nblk,
+                     t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, val, P, Q, part,
+                     ctl);
+  return 0;
+}
+template <typename T>
+static int launch_tpcg_A(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
+                         const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
+  constexpr int V16 = 16 / sizeof(T);
+  if (sh.VW == 2 * V16) return launch_tpcg_A_t<T, 2 * V16, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  return launch_tpcg_A_t<T, 1, 4>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+}
+
 // ================================================================== PCG
 // Every phase writes per-block column partials; a one-workgroup kernel then
 // combines them in a fixed order (deterministic, and no device-scope fences
@@ -567,21 +784,27 @@ __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__
 }
 
 template <typename T, int VW, int NG>
-static void pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
+static int pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
                              const int32_t *col, const T *val, const int32_t *ord, const T *diag,
                              T *X, T *R, T *P,
                              T *Q, double *part, Control *ctl, ColState *cs, double tol, int it0,
-                             int iters, hipStream_t s) {
+                             int iters, hipStream_t s, const Tiling *til, const TShape &tsh) {
   for (int it = it0; it < it0 + iters; ++it) {
-    hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                       P, Q, part, ctl, ord);
-    hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs);
+    if (til) {
+      if (launch_tpcg_A<T>(N, k, *til, tsh, rowptr, val, P, Q, part, ctl, s) < 0) return -1;
+      hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, tsh.grid, part, ctl, cs);
+    } else {
+      hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
+                         P, Q, part, ctl, ord);
+      hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs);
+    }
     hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
                        ctl, cs);
     hipLaunchKernelGGL(k_red_B, dim3(1), dim3(RED_THREADS), 0, s, k, nblkE, part, ctl, cs, tol, it);
     hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
                        cs, it);
   }
+  return 0;
 }
 
 template <typename T, int VW, int NG>
@@ -598,6 +821,12 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
   double *part = reinterpret_cast<double *>(w.part);
+  TShape tsh;
+  const Tiling *til = nullptr;
+  if (w.til) {
+    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_wide);
+    if (tsh.grid > 0) til = w.til;
+  }
   hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
                      diag, B, X, R, P, part, ord);
   hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
@@ -609,8 +838,9 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
     if (hctl.stop || done_iters >= max_iter) break;
     int n = std::min(chunk, max_iter - done_iters);
-    pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, ord, diag, X, R, P, Q, part, ctl,
-                                cs, tol, done_iters, n, s);
+    if (pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, ord, diag, X, R, P, Q, part,
+                                    ctl, cs, tol, done_iters, n, s, til, tsh) < 0)
+      return -1;
     done_iters += n;
     chunk = std::min(chunk * 2, 32);
   }
@@ -644,11 +874,20 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
   double *part = reinterpret_cast<double *>(w.part);
+  TShape tsh;
+  const Tiling *til = nullptr;
+  if (w.til) {
+    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_wide);
+    if (tsh.grid > 0) til = w.til;
+    else return -3;  // this tiling cannot serve k columns of T
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;
   if (hipMemsetAsync(ctl, 0, sizeof(Control), s) != hipSuccess) return -2;
   auto launch = [&]() {
-    if (phase == 0)
+    if (phase == 0 && til)
+      (void)launch_tpcg_A<T>(N, k, *til, tsh, rowptr, val, P, Q, part, ctl, s);
+    else if (phase == 0)
       hipLaunchKernelGGL((k_pcg_A<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col,
                          val, P, Q, part, ctl, ord);
     else if (phase == 1)
