@@ -370,7 +370,6 @@ __global__ void __launch_bounds__(256) k_tpcg_A(int N, int k, int BR, int nblk, 
                                                 const Control *ctl) {
   if (ctl && ctl->stop) return;
   extern __shared__ __align__(16) unsigned char t_smem[];
-  __shared__ double s_red[256 * VW];
   const int CG = k / VW;
   const unsigned rowbytes = (unsigned)k * sizeof(T);
   const int CH = (int)rowbytes / HCB;
@@ -442,23 +441,24 @@ __global__ void __launch_bounds__(256) k_tpcg_A(int N, int k, int BR, int nblk, 
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + li[u] * k);
+          const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], k));
           for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
         }
       }
       for (; j < je; ++j) {
-        const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + (int)is[j] * k);
+        const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(is[j], k));
         const T w = vs[j];
         for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
       }
-      const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + (hs + rr) * k);
+      const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
       for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
       store_row<T, VW>(Q, row, k, cg * VW, k, acc);
     }
   }
   // per-workgroup column partials (fixed order): thread t holds columns
-  // [(t % CG) VW, (t % CG) VW + VW) of its rows
+  // [(t % CG) VW, (t % CG) VW + VW) of its rows; the LDS image is free now
   __syncthreads();
+  double *s_red = reinterpret_cast<double *>(t_smem);
   for (int v = 0; v < VW; ++v) s_red[threadIdx.x * VW + v] = active ? apq[v] : 0.0;
   __syncthreads();
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
@@ -479,7 +479,7 @@ struct TShape {
   int VW = 1, HCB = 16, grid = 0;
   size_t lds = 0;
 };
-constexpr size_t TILE_LDS_MAX = 160 * 1024 - 256 * sizeof(double) * 8 - 512;
+constexpr size_t TILE_LDS_MAX = 160 * 1024 - 512;
 // wide: 32 bytes of columns per lane instead of 16 (when k allows)
 template <typename T>
 static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, bool wide) {
@@ -491,6 +491,7 @@ static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, bool wide
   else return sh;  // no wide form for this k
   sh.HCB = ((k * sizeof(T)) % 16 == 0) ? 16 : 4;
   sh.lds = tiled_lds_bytes(t, k, sizeof(T));
+  if (sh.lds) sh.lds = std::max(sh.lds, (size_t)256 * sh.VW * sizeof(double));  // final column reduction
   if (sh.lds == 0 || sh.lds > TILE_LDS_MAX || (double)N * k * sizeof(T) >= 4294967296.0) return sh;
   const int per_cu = std::max(1, std::min(8, (int)(TILE_LDS_MAX / sh.lds)));
   int g = std::min(t.nblk, 256 * per_cu);
