@@ -127,6 +127,58 @@ def batched_leg(torch, np, reps=3):
     return out
 
 
+def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
+    """The differentiation workload: 20 nuclei, 96^3 hexes -> P1 tetrahedra
+    (N = 857,375), N_occ = 40.  One step forward (with E_KS) and its adjoint
+    backward (dE/dV_ext at the quadrature points and the nuclear forces),
+    timed; the force on one nuclear coordinate is checked against a central
+    finite difference of E_KS with step h (Bohr), both steps started from the
+    same orbitals."""
+    import torch
+    from ks_inputs import make_workload
+    from paper_2404_19249_amd import KSContext
+    w = make_workload("differentiation")
+    ctx = KSContext.from_workload(w, tol_solve=1e-11, tol_inner=1e-11, tol_poisson=1e-12,
+                                  max_it_inner=80)
+    psi, lam = ctx.initial_guess(w.k)
+    for i in range(warm_steps):
+        lam, rep = ctx.scf_step(psi, lam, w.occ)
+        log(f"[bench] differentiation warm step {i}: inner {rep['inner_iters']} "
+            f"{rep['seconds'][5]:.2f}s")
+    psi0, lam0 = psi.clone(), lam.copy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = psi0.clone()
+    _, rep = ctx.scf_step(p, lam0, w.occ)
+    e = ctx.step_energy()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, F, st = ctx.step_backward(dE=1.0, want_forces=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    R0 = np.array(w.atoms.R, dtype=np.float64)
+    E = []
+    for sgn in (1, -1):
+        R = R0.copy()
+        R[atom, axis] += sgn * h
+        ctx.set_external(R=R)
+        p = psi0.clone()
+        ctx.scf_step(p, lam0, w.occ)
+        E.append(ctx.step_energy()["KS"])
+    ctx.set_external(R=R0)
+    f_fd = -(E[0] - E[1]) / (2 * h)
+    f_adj = float(F[atom, axis])
+    out = {"N": ctx.N, "k": w.k, "n_atoms": int(len(R0)), "forward_step_s": t1 - t0,
+           "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+           "adjoint_solve_iters_max": int(max(st["iters"][:w.k])),
+           "E_KS": e["KS"], "inner_iters": rep["inner_iters"], "res_inner": rep["res_inner"],
+           "force_check": {"atom": atom, "axis": axis, "h": h, "adjoint": f_adj, "central_fd": f_fd,
+                           "rel_err": abs(f_adj - f_fd) / max(abs(f_fd), 1e-300)},
+           "grad_q_values": int(g.numel())}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +190,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default SpMM kernels (for profiling one configuration)")
+    ap.add_argument("--differentiation", action="store_true",
+                    help="also run the differentiation workload (forward + adjoint, FD check)")
     ap.add_argument("--mode", default="step", choices=["step", "solve"],
                     help="solve: skip the SCF steps (block solves and kernel timings only, "
                          "for profiling)")
@@ -164,7 +220,7 @@ def main():
     copy_gbs = copy_probe(torch)
     log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
     ctx.assemble(psi, occ, want_fields=False)
-    tune = ctx.autotune(k, reps=10)
+    tune = None if args.no_autotune else ctx.autotune(k, reps=10)
     log(f"[bench] autotune: {json.dumps(tune)}")
     if args.mode == "solve":
         args.warmup, args.steps = 0, 0
@@ -264,6 +320,13 @@ def main():
             log(f"[bench] batched: {json.dumps(forms['batched'])}")
         except Exception as e:  # reported, never hides the headline
             forms["batched"] = {"error": repr(e)}
+    if args.differentiation:
+        log("[bench] differentiation form ...")
+        try:
+            out["differentiation"] = differentiation_leg(np)
+            log(f"[bench] differentiation: {json.dumps(out['differentiation'])}")
+        except Exception as e:  # reported, never hides the headline
+            out["differentiation"] = {"error": repr(e)}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(k)
