@@ -42,6 +42,20 @@ def cg_iteration_bytes(N, nnz, k, sv):
     return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 10 * N * k * sv
 
 
+def profiled_traffic(key):
+    """HBM bytes per launch of the kernel configuration `key`, from the rocprofv3
+    counter summaries committed under profiles/ (None if that configuration was
+    not profiled)."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch ") and ":" in line:
+                k, v = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+                if k.strip() == key:
+                    return float(v)
+    return None
+
+
 def copy_probe(torch, nbytes=1 << 30, reps=10):
     """Device-to-device copy of 1 GiB with torch's plain copy kernel: read +
     write bytes per second (a practical HBM reference next to the 8 TB/s
@@ -282,10 +296,20 @@ def main():
     ms_a64 = ctx.time_kernel(0, k, args.reps)
     bytes_a = spmm_bytes(N, nnz, k, sv)
     ach = bytes_a / (ms_a * 1e-3) / 1e9
-    roof = {"kernel": f"k_pcg_A<{'float' if sv == 4 else 'double'}> (q = S p, p.q), k={k}",
-            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_launch": bytes_a, "ms_per_launch": ms_a}
+    cfg = ctx.spmm_config()
+    tile = cfg["tile_fp32" if sv == 4 else "tile_fp64"]
+    tname = "float" if sv == 4 else "double"
+    if tile > 0:
+        kname = f"k_tpcg_A<{tname},{16 // sv},16>"
+        kdesc = f"k_tpcg_A<{tname}> halo-tile SpMM, {tile}-row blocks (q = S p, p.q), k={k}"
+    else:
+        kname, kdesc = f"k_pcg_A<{tname}>", f"k_pcg_A<{tname}> row kernel (q = S p, p.q), k={k}"
+    traffic = profiled_traffic(f"{kname} tile={tile} N={N} k={k}")
+    roof = {"kernel": kdesc, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic / 1e9,
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
+            "bytes_per_launch": bytes_a, "ms_per_launch": ms_a, "spmm_config": cfg}
     it_bytes = cg_iteration_bytes(N, nnz, k, sv)
     phases = {"spmm_ms": ms_a, "r_update_ms": ms_b, "xp_update_ms": ms_c,
               "iteration_GBs": it_bytes / ((ms_a + ms_b + ms_c) * 1e-3) / 1e9,

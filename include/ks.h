@@ -281,6 +281,12 @@ int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *
  * (-1: not available for this shape)}.  Requires a prior ks_assemble. */
 int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 
+/* SpMM-phase kernels in use: out_host[0..5] = {NG fp64, NG fp32, NG Poisson
+ * (row kernel lanes per row), tile rows fp64, fp32, Poisson (0 = row kernel,
+ * negative = 32-byte lane form)}.  The tiled kernel is used only where its
+ * LDS image fits for the solve's k. */
+int ks_spmm_config(const ks_ctx *ctx, int32_t *out_host);
+
 /* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",
  * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom")
  * into the device buffer dst.  For tests and debugging only. */

@@ -86,6 +86,7 @@ _SIGS = {
     "ks_small_eig": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                C.POINTER(C.c_int32)]),
     "ks_initial_guess": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
+    "ks_spmm_config": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "ks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ks_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ks_set_external": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),

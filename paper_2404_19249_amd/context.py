@@ -208,6 +208,13 @@ class KSContext:
                                           None if F is None else B.dptr(F), C.byref(st)), self.lib)
         return g, F, self._stats(st, 64)
 
+    def spmm_config(self):
+        """ks_spmm_config: the SpMM-phase kernel of each solver."""
+        o = (C.c_int32 * 6)()
+        B.check(self.lib.ks_spmm_config(self.h, o), self.lib)
+        return {"ng_fp64": o[0], "ng_fp32": o[1], "ng_poisson": o[2], "tile_fp64": o[3],
+                "tile_fp32": o[4], "tile_poisson": o[5]}
+
     def autotune(self, k, reps=10):
         """ks_autotune: pick the SpMM phase kernel (row kernel lanes-per-row
         split, or halo-tile row-block size) per solver."""

@@ -1015,6 +1015,16 @@ static int time_phase(ks_ctx *c, int which, int k, int reps, int ng, float *ms) 
                                 c->pwP, reps, ms, c->s, ng);
 }
 
+extern "C" int ks_spmm_config(const ks_ctx *c, int32_t *out_host) {
+  if (!c || !out_host) return fail(KS_ERR_ARG, "null argument");
+  out_host[0] = c->ng64;
+  out_host[1] = c->ng32;
+  out_host[2] = c->ngP;
+  const PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
+  for (int w = 0; w < 3; ++w) out_host[3 + w] = ws[w]->til ? ws[w]->til->BR * (ws[w]->til_wide ? -1 : 1) : 0;
+  return KS_OK;
+}
+
 extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps, double *ms_host) {
   if (!c || !ms_host) return fail(KS_ERR_ARG, "null argument");
   if (reps < 1 || k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "bad k or reps");
