@@ -42,6 +42,39 @@ def cg_iteration_bytes(N, nnz, k, sv):
     return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 10 * N * k * sv
 
 
+def phase_rooflines(ctx, k, reps=10, with_projection=True):
+    """Per-phase device time (HIP events, ks_time_kernel) and throughput against
+    the algorithmic bytes / flops of each phase (per unit of work as defined
+    for the hot path): potential-matrix assembly (a4), density and LDA at the
+    quadrature points (a2), projection onto the augmented basis (a6/a7) and
+    its FP64 MFMA GEMM."""
+    ne, nq, nl, nnz, N = ctx.n_elems, ctx.n_q, ctx.n_loc, ctx.nnz, ctx.N
+    m = ctx.N_H + k
+    out = {}
+    ms = ctx.time_kernel(7, k, reps)
+    b = ne * nq * 8 + ne * nl * 4 + 80 * ne + 8 * nnz
+    f = 2 * ne * nq * nl * (nl + 1) // 2
+    out["a4_potential_assembly"] = {"ms": ms, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS,
+                                    "GFLOPs": f / ms / 1e6, "bytes": b, "flops": f}
+    ms = ctx.time_kernel(8, k, reps)
+    b = ctx.n_nodes * k * 8 + ne * nl * 4 + ne * nq * 8
+    out["a2_density"] = {"ms": ms, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS, "bytes": b}
+    ms = ctx.time_kernel(9, k, reps)
+    b = 3 * ne * nq * 8
+    out["a2_lda"] = {"ms": ms, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS, "bytes": b}
+    if with_projection:
+        ms = ctx.time_kernel(10, k, reps)
+        b = 12 * nnz + 4 * (N + 1) + 8 * N * m
+        f = 2 * nnz * m + 2 * N * m * m
+        out["a6_projection"] = {"ms": ms, "m": m, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS,
+                                "TFLOPs": f / ms / 1e9, "bytes": b, "flops": f}
+        ms = ctx.time_kernel(11, k, reps)
+        f = 2 * N * m * m
+        out["a6_gemm_mfma_f64"] = {"ms": ms, "TFLOPs": f / ms / 1e9,
+                                   "frac_mfma_f64": f / ms / 1e9 / 78.6, "flops": f}
+    return out
+
+
 def profiled_traffic(key):
     """HBM bytes per launch of the kernel configuration `key`, from the rocprofv3
     counter summaries committed under profiles/ (None if that configuration was
@@ -258,19 +291,30 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     value = N * k * args.steps / solve_s if args.steps else None
+    # per-phase rooflines on the state the last step left (assembly, fields, projection)
+    phases_other = phase_rooflines(ctx, k, with_projection=args.steps > 0)
+    log(f"[bench] phases: {json.dumps(phases_other)}")
 
     # ------------------------------------- both forms on the same inputs
     ctx.assemble(psi_in, occ, want_fields=False)
     forms = {}
     for prec in ("fp64", "mixed"):
         times, st = [], None
-        for r in range(3):
+        for r in range(5):
             out, st = ctx.block_solve(psi_in, lam_in, prec)
             times.append(st["seconds"])
         t = float(np.median(times))
+        its = int(max(st["iters"]))
+        # whole-solve algorithmic bytes: iterations x B_it (+ the FP64 residual
+        # SpMMs b - S x of the refinement loop in the mixed form)
+        if prec == "fp64":
+            sb = its * cg_iteration_bytes(N, nnz, k, 8)
+        else:
+            sb = its * cg_iteration_bytes(N, nnz, k, 4) + st["refinements"] * (nnz * 12 + 4 * (N + 1) + 3 * N * k * 8)
         forms[prec] = {"dof_rhs_per_s": N * k / t, "ms": t * 1e3,
-                       "iters_max": int(max(st["iters"])), "refinements": st["refinements"],
-                       "relres_max": float(max(st["relres"]))}
+                       "iters_max": its, "refinements": st["refinements"],
+                       "relres_max": float(max(st["relres"])),
+                       "solve_GBs": sb / t / 1e9, "solve_frac_hbm": sb / t / 1e9 / HBM_PEAK_GBS}
     if value is None:
         value = forms[args.precision]["dof_rhs_per_s"]
     # eigenvalue accuracy of one step in each form against a tightly solved FP64 step
@@ -300,8 +344,9 @@ def main():
     tile = cfg["tile_fp32" if sv == 4 else "tile_fp64"]
     tname = "float" if sv == 4 else "double"
     if tile > 0:
-        kname = f"k_tpcg_A<{tname},{16 // sv},16>"
-        kdesc = f"k_tpcg_A<{tname}> halo-tile SpMM, {tile}-row blocks (q = S p, p.q), k={k}"
+        tb = cfg["tile_threads_fp32" if sv == 4 else "tile_threads_fp64"]
+        kname = f"k_tpcg_A<{tname},{16 // sv},16,{tb}>"
+        kdesc = f"k_tpcg_A<{tname}> halo-tile SpMM, {tile}-row blocks, {tb} threads (q = S p, p.q), k={k}"
     else:
         kname, kdesc = f"k_pcg_A<{tname}>", f"k_pcg_A<{tname}> row kernel (q = S p, p.q), k={k}"
     traffic = profiled_traffic(f"{kname} tile={tile} N={N} k={k}")
@@ -328,6 +373,7 @@ def main():
         "copy_probe_GBs": copy_gbs,
         "autotune": tune,
         "pcg_phases": phases,
+        "phases": phases_other,
         "block_solve": forms,
         "step": {} if not reps else {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
                  "inner_iters": [r["inner_iters"] for r in reps],

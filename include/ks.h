@@ -261,29 +261,36 @@ int ks_batch_autotune(ks_batch *b, const double *const *psi_old, const double *c
 int ks_batch_destroy(ks_batch *b);
 
 /* Measurement: mean duration (ms, HIP events on the context stream) of
- * `reps` back-to-back launches of one block-PCG phase in the launch
- * configuration the solver uses, on the current operator S and workspace:
- * which = 0 SpMM phase q = S p with the p.q reduction (FP64, k columns),
- * 1 residual update, 2 x/p update; 3..5 the same phases in FP32 (mixed form);
- * 6 the Hartree Poisson SpMM phase (k = 1).  Requires a prior ks_assemble. */
+ * `reps` back-to-back launches of one hot-path operation on the current
+ * state.  which = 0 SpMM phase q = S p with the p.q reduction (FP64, k
+ * columns, the kernel the solver uses), 1 residual update, 2 x/p update;
+ * 3..5 the same phases in FP32 (mixed form); 6 the Hartree Poisson SpMM phase
+ * (k = 1); 7 potential-matrix assembly M[V] over all colours; 8 density at the
+ * quadrature points from the k orbitals of the last ks_assemble; 9 LDA
+ * energy density and potential at the quadrature points; 10 projection
+ * F = Z^T M[V] Z over the augmented basis of the last step (m = N_H + k;
+ * SpMM + FP64 MFMA GEMM); 11 that GEMM alone.  7..11 overwrite work buffers
+ * (a following ks_step_backward needs a new ks_scf_step).  Requires a prior
+ * ks_assemble (10, 11: a prior ks_scf_step or ks_augmented_project). */
 int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
 
 /* Autotuner of the SpMM phase: on the current operator S (and the Poisson
  * operator K), times the SpMM phase of the block PCG for every kernel
  * candidate -- the row kernel with a row's nonzeros split over NG = 1, 2, 4,
  * 8 lanes, and the LDS-staged halo-tile kernel with row blocks of 16, 32,
- * 64, 128, 256 rows and 16 or 32 bytes of columns per lane -- in FP64 and
+ * 64, 128, 256 rows and 256-, 512- or 1024-thread workgroups -- in FP64 and
  * FP32 with k columns (Poisson: k = 1), and keeps the fastest for later
- * solves of this context.  report_host (NULL to skip) receives 48 doubles:
+ * solves of this context.  report_host (NULL to skip) receives 66 doubles:
  * {NG fp64, NG fp32, NG Poisson, tile rows fp64, fp32, Poisson (0 = row
- * kernel chosen, negative = 32-byte form), then row-kernel ms[fp64|fp32|
- * Poisson][NG], then tile-kernel ms[fp64|fp32|Poisson][rows][16|32 bytes]
- * (-1: not available for this shape)}.  Requires a prior ks_assemble. */
+ * kernel chosen), tile threads fp64, fp32, Poisson, then row-kernel
+ * ms[fp64|fp32|Poisson][NG], then tile-kernel ms[fp64|fp32|Poisson][rows]
+ * [256|512|1024 threads] (-1: not available for this shape)}.  Requires a
+ * prior ks_assemble. */
 int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 
-/* SpMM-phase kernels in use: out_host[0..5] = {NG fp64, NG fp32, NG Poisson
- * (row kernel lanes per row), tile rows fp64, fp32, Poisson (0 = row kernel,
- * negative = 32-byte lane form)}.  The tiled kernel is used only where its
+/* SpMM-phase kernels in use: out_host[0..8] = {NG fp64, NG fp32, NG Poisson
+ * (row kernel lanes per row), tile rows fp64, fp32, Poisson (0 = row
+ * kernel), tile workgroup threads fp64, fp32, Poisson}.  The tiled kernel is used only where its
  * LDS image fits for the solve's k. */
 int ks_spmm_config(const ks_ctx *ctx, int32_t *out_host);
 

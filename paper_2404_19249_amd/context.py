@@ -210,15 +210,16 @@ class KSContext:
 
     def spmm_config(self):
         """ks_spmm_config: the SpMM-phase kernel of each solver."""
-        o = (C.c_int32 * 6)()
+        o = (C.c_int32 * 9)()
         B.check(self.lib.ks_spmm_config(self.h, o), self.lib)
         return {"ng_fp64": o[0], "ng_fp32": o[1], "ng_poisson": o[2], "tile_fp64": o[3],
-                "tile_fp32": o[4], "tile_poisson": o[5]}
+                "tile_fp32": o[4], "tile_poisson": o[5], "tile_threads_fp64": o[6],
+                "tile_threads_fp32": o[7], "tile_threads_poisson": o[8]}
 
     def autotune(self, k, reps=10):
         """ks_autotune: pick the SpMM phase kernel (row kernel lanes-per-row
-        split, or halo-tile row-block size) per solver."""
-        rep = (C.c_double * 48)()
+        split, or halo-tile row-block size and workgroup size) per solver."""
+        rep = (C.c_double * 66)()
         B.check(self.lib.ks_autotune(self.h, int(k), int(reps), rep), self.lib)
         r = list(rep)
         names = ["fp64", "fp32", "poisson"]
@@ -226,10 +227,12 @@ class KSContext:
         for w, n in enumerate(names):
             out[f"ng_{n}"] = int(r[w])
             out[f"tile_{n}"] = int(r[3 + w])
-            out[f"row_ms_{n}"] = dict(zip([1, 2, 4, 8], r[6 + 4 * w: 10 + 4 * w]))
-            t = r[18 + 10 * w: 28 + 10 * w]
-            out[f"tile_ms_{n}"] = {f"{br}{'w' if d else ''}": t[2 * i + d]
-                                   for i, br in enumerate([16, 32, 64, 128, 256]) for d in (0, 1)}
+            out[f"tile_threads_{n}"] = int(r[6 + w])
+            out[f"row_ms_{n}"] = dict(zip([1, 2, 4, 8], r[9 + 4 * w: 13 + 4 * w]))
+            t = r[21 + 15 * w: 36 + 15 * w]
+            out[f"tile_ms_{n}"] = {f"{br}x{tb}": t[3 * i + j]
+                                   for i, br in enumerate([16, 32, 64, 128, 256])
+                                   for j, tb in enumerate([256, 512, 1024])}
         return out
 
     def debug_buffer(self, name, n):

@@ -146,49 +146,57 @@ void launch_assemble_KM(const int32_t *list, int count, int n_loc, int n_q, cons
 
 // ------------------------------------------------------------ M[V]
 // pairtab[q][p] = phi_qa phi_qb for the p-th pair (a <= b) in row-major
-// upper-triangle order.
+// upper-triangle order.  One lane per (element, pair): EPW = 64 / NP
+// elements per wave (6 for P1, 1 for P2); the lanes of an element read its
+// quadrature weights w_q |J| V_q as broadcasts and their own pair column of
+// the table from LDS, and add the entry into its two CSR slots (elements of
+// one colour share no node, so no two lanes of a launch touch one slot).
 template <int NLOC, int NQ>
 __global__ void __launch_bounds__(256) k_assemble_potential(
     const int32_t *__restrict__ list, int count, const int32_t *__restrict__ slot,
     const double *__restrict__ absdet, const double *__restrict__ pairtab,
     const double *__restrict__ w, const double *__restrict__ V, double *__restrict__ out) {
   constexpr int NP = NLOC * (NLOC + 1) / 2;
+  constexpr int EPW = 64 / NP;
   __shared__ double s_pt[NQ * NP];
   __shared__ double s_w[NQ];
+  __shared__ unsigned char s_a[NP], s_b[NP];
   for (int i = threadIdx.x; i < NQ * NP; i += blockDim.x) s_pt[i] = pairtab[i];
   for (int i = threadIdx.x; i < NQ; i += blockDim.x) s_w[i] = w[i];
+  if (threadIdx.x == 0) {
+    int p = 0;
+    for (int a = 0; a < NLOC; ++a)
+      for (int b = a; b < NLOC; ++b, ++p) {
+        s_a[p] = (unsigned char)a;
+        s_b[p] = (unsigned char)b;
+      }
+  }
   __syncthreads();
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int es = lane / NP, p = lane - es * NP;
+  const int t = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * EPW + es;
+  if (es >= EPW || t >= count) return;
   const int e = list[t];
   const double dj = absdet[e];
-  double c[NQ];
   const double *Ve = V + (int64_t)e * NQ;
+  double m = 0.0;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) c[q] = s_w[q] * dj * Ve[q];
+  for (int q = 0; q < NQ; ++q) m += (s_w[q] * dj * Ve[q]) * s_pt[q * NP + p];
+  const int a = s_a[p], b = s_b[p];
   const int32_t *sl = slot + (int64_t)e * NLOC * NLOC;
-  int p = 0;
-#pragma unroll
-  for (int a = 0; a < NLOC; ++a) {
-#pragma unroll
-    for (int b = a; b < NLOC; ++b, ++p) {
-      const int s_ab = sl[a * NLOC + b];
-      const int s_ba = sl[b * NLOC + a];
-      if (s_ab < 0 && s_ba < 0) continue;  // both rows on the boundary
-      double m = 0.0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) m += c[q] * s_pt[q * NP + p];
-      if (s_ab >= 0) out[s_ab] += m;
-      if (b != a && s_ba >= 0) out[s_ba] += m;
-    }
-  }
+  const int s_ab = sl[a * NLOC + b];
+  const int s_ba = sl[b * NLOC + a];
+  if (s_ab >= 0) out[s_ab] += m;
+  if (b != a && s_ba >= 0) out[s_ba] += m;
 }
 
 void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_q,
                                const int32_t *slot, const double *absdet, const double *pairtab,
                                const double *w, const double *V_q, double *out, hipStream_t s) {
   if (count <= 0) return;
-  dim3 g((count + 255) / 256), b(256);
+  const int np = n_loc * (n_loc + 1) / 2, epw = 64 / np;
+  const int per_block = 4 * epw;  // elements per 256-thread workgroup
+  dim3 g((count + per_block - 1) / per_block), b(256);
   if (n_loc == 4 && n_q == 8)
     hipLaunchKernelGGL((k_assemble_potential<4, 8>), g, b, 0, s, list, count, slot, absdet,
                        pairtab, w, V_q, out);

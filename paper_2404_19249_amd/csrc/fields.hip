@@ -43,53 +43,62 @@ void launch_vext(const double *coords, const int32_t *elems, int n_loc, int n_e,
                        n_loc, n_e, n_q, bary, n_atoms, Z, R, out);
 }
 
-// rho_q = sum_i occ_i psi_i(x_q)^2, one element per thread
+// rho_q = sum_i f_i (sum_a phi_qa X[dof_a][i])^2.  One lane per (element,
+// orbital): LPE = the next power of two >= k lanes per element (the orbital
+// rows of a node are contiguous, so the gathers of an element are coalesced),
+// EPW = 64 / LPE elements per wave; the per-point sums over orbitals are
+// butterfly shuffles inside each lane group, in a fixed order.
 template <int NLOC, int NQ>
 __global__ void __launch_bounds__(256) k_density(const int32_t *__restrict__ edof, int n_e,
                                                  const double *__restrict__ phi,
                                                  const double *__restrict__ X, int ldx, int k,
                                                  const double *__restrict__ occ,
-                                                 double *__restrict__ rho) {
+                                                 double *__restrict__ rho, int LPE) {
   __shared__ double s_phi[NQ * NLOC];
   for (int i = threadIdx.x; i < NQ * NLOC; i += blockDim.x) s_phi[i] = phi[i];
   __syncthreads();
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_e) return;
-  int dof[NLOC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int EPW = 64 / LPE;
+  const int es = lane / LPE, i = lane - es * LPE;
+  const int e = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * EPW + es;
+  const bool ok = e < n_e;                 // uniform across a lane group
+  const bool own = ok && i < k;
+  double xa[NLOC];
 #pragma unroll
-  for (int a = 0; a < NLOC; ++a) dof[a] = edof[(int64_t)e * NLOC + a];
-  double r[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) r[q] = 0.0;
-  for (int i = 0; i < k; ++i) {
-    double xa[NLOC];
-#pragma unroll
-    for (int a = 0; a < NLOC; ++a) xa[a] = dof[a] >= 0 ? X[(int64_t)dof[a] * ldx + i] : 0.0;
-    const double f = occ[i];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double v = 0.0;
-#pragma unroll
-      for (int a = 0; a < NLOC; ++a) v += s_phi[q * NLOC + a] * xa[a];
-      r[q] += f * v * v;
-    }
+  for (int a = 0; a < NLOC; ++a) {
+    const int d = ok ? edof[(int64_t)e * NLOC + a] : -1;
+    xa[a] = (own && d >= 0) ? X[(int64_t)d * ldx + i] : 0.0;
   }
+  const double f = own ? occ[i] : 0.0;
+  double mine = 0.0;  // lane i < NQ keeps point i's sum
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) rho[(int64_t)e * NQ + q] = r[q];
+  for (int q = 0; q < NQ; ++q) {
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < NLOC; ++a) v += s_phi[q * NLOC + a] * xa[a];
+    double r = f * v * v;
+    for (int off = LPE >> 1; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+    if (i == q) mine = r;
+  }
+  if (ok && i < NQ) rho[(int64_t)e * NQ + i] = mine;
 }
 void launch_density(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi,
                     const double *X, int ldx, int k, const double *occ, double *rho,
                     hipStream_t s) {
   if (n_e <= 0) return;
-  dim3 g((n_e + 255) / 256), b(256);
+  int LPE = 1;
+  while (LPE < k || LPE < n_q) LPE <<= 1;  // every point needs a writer lane
+  if (LPE > 64) return;                    // k <= 64 and n_q <= 27 always hold
+  const int per_block = 4 * (64 / LPE);
+  dim3 g((n_e + per_block - 1) / per_block), b(256);
   if (n_loc == 4 && n_q == 8)
-    hipLaunchKernelGGL((k_density<4, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho);
+    hipLaunchKernelGGL((k_density<4, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
   else if (n_loc == 10 && n_q == 27)
-    hipLaunchKernelGGL((k_density<10, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho);
+    hipLaunchKernelGGL((k_density<10, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
   else if (n_loc == 4 && n_q == 27)
-    hipLaunchKernelGGL((k_density<4, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho);
+    hipLaunchKernelGGL((k_density<4, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
   else if (n_loc == 10 && n_q == 8)
-    hipLaunchKernelGGL((k_density<10, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho);
+    hipLaunchKernelGGL((k_density<10, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
 }
 
 // u_q = sum_a phi_qa U[node_a] for a nodal field over all nodes

@@ -113,7 +113,7 @@ struct PCGWork {
   unsigned int *counter; // last-block counters
   int nblk_max;
   const Tiling *til;     // SpMM phase: LDS-staged halo tiles (nullptr = row kernel)
-  bool til_wide;         // tiled kernel with 32 bytes of columns per lane (else 16)
+  int til_tb;            // threads per workgroup of the tiled kernel (256, 512, 1024)
 };
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,

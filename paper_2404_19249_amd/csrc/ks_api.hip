@@ -326,13 +326,14 @@ static int tile_index(int br) {
     if (TILE_BR[i] == br) return i;
   return -1;
 }
-// tile choice code: 2 * tiling index + wide flag (32 bytes of columns per
-// lane), -1 = row kernel
+// tile choice code: 3 * tiling index + workgroup size index (256, 512,
+// 1024 threads), -1 = row kernel
+static const int TILE_TB[3] = {256, 512, 1024};
 static void apply_tiles(ks_ctx *c) {
   auto set = [&](PCGWork &w, int code) {
-    const int i = code >= 0 ? code / 2 : -1;
+    const int i = code >= 0 ? code / 3 : -1;
     w.til = (i >= 0 && c->til[i].nblk) ? &c->til[i] : nullptr;
-    w.til_wide = code >= 0 && (code & 1);
+    w.til_tb = TILE_TB[code >= 0 ? code % 3 : 0];
   };
   set(c->pw64, c->tile64);
   set(c->pw32, c->tile32);
@@ -875,11 +876,11 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
     auto tile_env = [&](const char *n, int dflt) {
       const char *v = std::getenv(n);
       const int i = tile_index(v ? std::atoi(v) : dflt);
-      return i >= 0 ? 2 * i : -1;
+      return i >= 0 ? 3 * i + 1 : -1;  // 512 threads
     };
-    c->tile64 = tile_env("KS_TILE64", 16);
-    c->tile32 = tile_env("KS_TILE32", 32);
-    c->tileP = tile_env("KS_TILEP", 64);
+    c->tile64 = tile_env("KS_TILE64", 64);
+    c->tile32 = tile_env("KS_TILE32", 64);
+    c->tileP = tile_env("KS_TILEP", 128);
     apply_tiles(c);
   }
   H2D(c->colB, colB.data(), colB.size());
@@ -1015,13 +1016,54 @@ static int time_phase(ks_ctx *c, int which, int k, int reps, int ng, float *ms) 
                                 c->pwP, reps, ms, c->s, ng);
 }
 
-extern "C" int ks_spmm_config(const ks_ctx *c, int32_t *out_host) {
+extern "C" int ks_spmm_config(const ks_ctx *c, int32_t *out_host) {  // 9 values
   if (!c || !out_host) return fail(KS_ERR_ARG, "null argument");
   out_host[0] = c->ng64;
   out_host[1] = c->ng32;
   out_host[2] = c->ngP;
   const PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
-  for (int w = 0; w < 3; ++w) out_host[3 + w] = ws[w]->til ? ws[w]->til->BR * (ws[w]->til_wide ? -1 : 1) : 0;
+  for (int w = 0; w < 3; ++w) out_host[3 + w] = ws[w]->til ? ws[w]->til->BR : 0;
+  for (int w = 0; w < 3; ++w) out_host[6 + w] = ws[w]->til ? ws[w]->til_tb : 0;
+  return KS_OK;
+}
+
+static void project_full(ks_ctx *c, const double *H, int m, double *F);
+
+// mean duration of `reps` back-to-back runs of one of the other hot-path
+// operations (see ks_time_kernel), on the context's current state
+static int time_op(ks_ctx *c, int which, int k, int reps, float *ms) {
+  hipStream_t s = c->s;
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  const int m = c->N_H + k;
+  auto op = [&]() {
+    switch (which) {
+      case 7:  // potential matrix M[V_nl] over all colours (a4)
+        launch_fill(c->nnz_ext, 0.0, c->MNL, s);
+        assemble_potential_all(c, c->vnl_q, c->MNL);
+        break;
+      case 8:  // density at the quadrature points (a2)
+        launch_density(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->PsiIn, k, k, c->occ_d, c->aux1, s);
+        break;
+      case 9:  // LDA energy density and potential (a2)
+        launch_xc(nqt, c->rho_l, c->opt.xc_mode == KS_XC_NONE ? KS_XC_X_PZ81 : c->opt.xc_mode, c->aux1, c->aux2, s);
+        break;
+      case 10:  // projection F = Z^T (M[V_nl] Z) over the augmented basis (a6/a7): SpMM + MFMA GEMM
+        project_full(c, c->MNL, m, c->Ctmp);
+        break;
+      default:  // 11: the tall-skinny GEMM Z^T Y alone (FP64 MFMA)
+        launch_gemm_tn(c->N, m, m, c->Z, c->mp, c->Y, c->mp, c->Ctmp, m, c->gwork, c->gwork_n, s);
+        break;
+    }
+  };
+  op();  // warm
+  HIPCHK(hipEventRecord(c->ev0, s));
+  for (int r = 0; r < reps; ++r) op();
+  HIPCHK(hipEventRecord(c->ev1, s));
+  HIPCHK(hipEventSynchronize(c->ev1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, c->ev0, c->ev1));
+  *ms = t / reps;
+  c->have_step = false;  // MNL / work buffers were overwritten
   return KS_OK;
 }
 
@@ -1029,7 +1071,13 @@ extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps,
   if (!c || !ms_host) return fail(KS_ERR_ARG, "null argument");
   if (reps < 1 || k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
-  if (which < 0 || which > 6) return fail(KS_ERR_ARG, "which must be 0..6");
+  if (which < 0 || which > 11) return fail(KS_ERR_ARG, "which must be 0..11");
+  if (which >= 7) {
+    float ms = 0.f;
+    TRY(time_op(c, which, k, reps, &ms));
+    *ms_host = ms;
+    return KS_OK;
+  }
   const int ng = (which <= 2) ? c->ng64 : (which <= 5 ? c->ng32 : c->ngP);
   float ms = 0.f;
   if (time_phase(c, which, k, reps, ng, &ms) < 0) return fail(KS_ERR_HIP, "timing launch failed");
@@ -1047,7 +1095,7 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
   if (k < 1 || k > c->k_max || reps < 1) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
   const int ngs[4] = {1, 2, 4, 8};
-  double t_row[3][4], t_til[3][2 * ks_ctx::NTILE];
+  double t_row[3][4], t_til[3][3 * ks_ctx::NTILE];
   int best_ng[3] = {1, 1, 8}, best_tile[3] = {-1, -1, -1};
   PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
   c->rorder = nullptr;
@@ -1056,13 +1104,13 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
     const int kk = w == 2 ? 1 : k;
     double bt = 1e300;
     const Tiling *keep = ws[w]->til;
-    const bool keep_db = ws[w]->til_wide;
+    const int keep_db = ws[w]->til_tb;
     ws[w]->til = nullptr;
     for (int i = 0; i < 4; ++i) {
       float ms = 0.f;
       if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0) {
         ws[w]->til = keep;
-        ws[w]->til_wide = keep_db;
+        ws[w]->til_tb = keep_db;
         return fail(KS_ERR_HIP, "autotune timing failed");
       }
       t_row[w][i] = ms;
@@ -1072,18 +1120,18 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
         best_tile[w] = -1;
       }
     }
-    for (int code = 0; code < 2 * ks_ctx::NTILE; ++code) {
-      const int i = code / 2;
+    for (int code = 0; code < 3 * ks_ctx::NTILE; ++code) {
+      const int i = code / 3;
       t_til[w][code] = -1.0;
       if (!c->til[i].nblk) continue;
       ws[w]->til = &c->til[i];
-      ws[w]->til_wide = code & 1;
+      ws[w]->til_tb = TILE_TB[code % 3];
       float ms = 0.f;
       const int r = time_phase(c, which, kk, reps, 0, &ms);
       if (r == -3) continue;  // does not fit in LDS for this shape
       if (r < 0) {
         ws[w]->til = keep;
-        ws[w]->til_wide = keep_db;
+        ws[w]->til_tb = keep_db;
         return fail(KS_ERR_HIP, "autotune timing failed");
       }
       t_til[w][code] = ms;
@@ -1093,7 +1141,7 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
       }
     }
     ws[w]->til = keep;
-    ws[w]->til_wide = keep_db;
+    ws[w]->til_tb = keep_db;
   }
   c->ng64 = best_ng[0];
   c->ng32 = best_ng[1];
@@ -1105,9 +1153,10 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
   if (report_host) {
     for (int w = 0; w < 3; ++w) {
       report_host[w] = best_ng[w];
-      report_host[3 + w] = best_tile[w] >= 0 ? TILE_BR[best_tile[w] / 2] * ((best_tile[w] & 1) ? -1 : 1) : 0;
-      for (int i = 0; i < 4; ++i) report_host[6 + w * 4 + i] = t_row[w][i];
-      for (int i = 0; i < 2 * ks_ctx::NTILE; ++i) report_host[18 + w * 2 * ks_ctx::NTILE + i] = t_til[w][i];
+      report_host[3 + w] = best_tile[w] >= 0 ? TILE_BR[best_tile[w] / 3] : 0;
+      report_host[6 + w] = best_tile[w] >= 0 ? TILE_TB[best_tile[w] % 3] : 0;
+      for (int i = 0; i < 4; ++i) report_host[9 + w * 4 + i] = t_row[w][i];
+      for (int i = 0; i < 3 * ks_ctx::NTILE; ++i) report_host[21 + w * 3 * ks_ctx::NTILE + i] = t_til[w][i];
     }
   }
   return KS_OK;

@@ -358,8 +358,8 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // per lane (k % VW == 0); halo rows copied in HCB-byte chunks, HCB = 16 when
 // k * sizeof(T) % 16 == 0, else 4; N * k * sizeof(T) < 2^32 (byte offsets
 // into P are 32-bit).  All checked by the host.
-template <typename T, int VW, int HCB>
-__global__ void __launch_bounds__(256) k_tpcg_A(int N, int k, int BR, int nblk, int max_halo, int max_nnz,
+template <typename T, int VW, int HCB, int TB>
+__global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, int max_halo, int max_nnz,
                                                 const int32_t *__restrict__ halo_ptr,
                                                 const int32_t *__restrict__ halo_col,
                                                 const int32_t *__restrict__ hself,
@@ -476,41 +476,39 @@ size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem) {
 
 // launch shape of the tiled SpMM for this operator: VW, halo chunk, grid, LDS
 struct TShape {
-  int VW = 1, HCB = 16, grid = 0;
+  int VW = 1, HCB = 16, grid = 0, TB = 256;
   size_t lds = 0;
 };
 constexpr size_t TILE_LDS_MAX = 160 * 1024 - 512;
-// wide: 32 bytes of columns per lane instead of 16 (when k allows)
+// tb: threads per workgroup (256, 512 or 1024; the waves share one block)
 template <typename T>
-static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, bool wide) {
+static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb) {
   TShape sh;
   const int vw16 = 16 / (int)sizeof(T);
-  if (wide && k % (2 * vw16) == 0) sh.VW = 2 * vw16;
-  else if (!wide && k % vw16 == 0) sh.VW = vw16;
-  else if (!wide) sh.VW = 1;
-  else return sh;  // no wide form for this k
+  sh.VW = (k % vw16 == 0) ? vw16 : 1;
+  sh.TB = (tb == 512 || tb == 1024) ? tb : 256;
   sh.HCB = ((k * sizeof(T)) % 16 == 0) ? 16 : 4;
   sh.lds = tiled_lds_bytes(t, k, sizeof(T));
-  if (sh.lds) sh.lds = std::max(sh.lds, (size_t)256 * sh.VW * sizeof(double));  // final column reduction
+  if (sh.lds) sh.lds = std::max(sh.lds, (size_t)sh.TB * sh.VW * sizeof(double));  // final column reduction
   if (sh.lds == 0 || sh.lds > TILE_LDS_MAX || (double)N * k * sizeof(T) >= 4294967296.0) return sh;
-  const int per_cu = std::max(1, std::min(8, (int)(TILE_LDS_MAX / sh.lds)));
+  const int per_cu = std::max(1, std::min(2048 / sh.TB, (int)(TILE_LDS_MAX / sh.lds)));
   int g = std::min(t.nblk, 256 * per_cu);
   if (g > 8) g = g / 8 * 8;
   sh.grid = std::max(1, std::min(g, nblk_max));
   return sh;
 }
 
-template <typename T, int VW, int HCB>
+template <typename T, int VW, int HCB, int TB>
 static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
                            const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)TILE_LDS_MAX) != hipSuccess)
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB>), dim3(sh.grid), dim3(256), sh.lds, s, N, k, t.BR, t.nblk,
+  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, t.BR, t.nblk,
                      t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, val, P, Q, part,
                      ctl);
   return 0;
@@ -519,10 +517,19 @@ template <typename T>
 static int launch_tpcg_A(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
                          const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
   constexpr int V16 = 16 / sizeof(T);
-  if (sh.VW == 2 * V16) return launch_tpcg_A_t<T, 2 * V16, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  return launch_tpcg_A_t<T, 1, 4>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  if (sh.TB == 1024) {
+    if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+    if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+    return launch_tpcg_A_t<T, 1, 4, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  }
+  if (sh.TB == 512) {
+    if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+    if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+    return launch_tpcg_A_t<T, 1, 4, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  }
+  if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  return launch_tpcg_A_t<T, 1, 4, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
 }
 
 // ================================================================== PCG
@@ -825,7 +832,7 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   TShape tsh;
   const Tiling *til = nullptr;
   if (w.til) {
-    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_wide);
+    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_tb);
     if (tsh.grid > 0) til = w.til;
   }
   hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
@@ -878,7 +885,7 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   TShape tsh;
   const Tiling *til = nullptr;
   if (w.til) {
-    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_wide);
+    tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_tb);
     if (tsh.grid > 0) til = w.til;
     else return -3;  // this tiling cannot serve k columns of T
   }
