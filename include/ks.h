@@ -277,10 +277,10 @@ int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *
 /* Autotuner of the SpMM phase: on the current operator S (and the Poisson
  * operator K), times the SpMM phase of the block PCG for every kernel
  * candidate -- the row kernel with a row's nonzeros split over NG = 1, 2, 4,
- * 8 lanes, and the LDS-staged halo-tile kernel with row blocks of 16, 32,
- * 64, 128, 256 rows and 256-, 512- or 1024-thread workgroups -- in FP64 and
- * FP32 with k columns (Poisson: k = 1), and keeps the fastest for later
- * solves of this context.  report_host (NULL to skip) receives 66 doubles:
+ * 8 lanes, and the LDS-staged halo-tile kernel with row blocks of 32, 64,
+ * 85, 128, 170, 256 rows and 256-, 512- or 1024-thread workgroups -- in FP64
+ * and FP32 with k columns (Poisson: k = 1), and keeps the fastest for later
+ * solves of this context.  report_host (NULL to skip) receives 75 doubles:
  * {NG fp64, NG fp32, NG Poisson, tile rows fp64, fp32, Poisson (0 = row
  * kernel chosen), tile threads fp64, fp32, Poisson, then row-kernel
  * ms[fp64|fp32|Poisson][NG], then tile-kernel ms[fp64|fp32|Poisson][rows]

@@ -219,7 +219,7 @@ class KSContext:
     def autotune(self, k, reps=10):
         """ks_autotune: pick the SpMM phase kernel (row kernel lanes-per-row
         split, or halo-tile row-block size and workgroup size) per solver."""
-        rep = (C.c_double * 66)()
+        rep = (C.c_double * 75)()
         B.check(self.lib.ks_autotune(self.h, int(k), int(reps), rep), self.lib)
         r = list(rep)
         names = ["fp64", "fp32", "poisson"]
@@ -229,9 +229,9 @@ class KSContext:
             out[f"tile_{n}"] = int(r[3 + w])
             out[f"tile_threads_{n}"] = int(r[6 + w])
             out[f"row_ms_{n}"] = dict(zip([1, 2, 4, 8], r[9 + 4 * w: 13 + 4 * w]))
-            t = r[21 + 15 * w: 36 + 15 * w]
+            t = r[21 + 18 * w: 39 + 18 * w]
             out[f"tile_ms_{n}"] = {f"{br}x{tb}": t[3 * i + j]
-                                   for i, br in enumerate([16, 32, 64, 128, 256])
+                                   for i, br in enumerate([32, 64, 85, 128, 170, 256])
                                    for j, tb in enumerate([256, 512, 1024])}
         return out
 

@@ -140,7 +140,7 @@ struct ks_ctx {
   PCGWork pw64{}, pw32{}, pwP{};
   // halo tilings of the CSR pattern for the LDS-staged SpMM, row blocks of
   // TILE_BR[i] rows; chosen tiling per solver (-1 = row kernel)
-  static constexpr int NTILE = 5;
+  static constexpr int NTILE = 6;
   Tiling til[NTILE];
   int tile64 = -1, tile32 = -1, tileP = -1;
   unsigned int *counters = nullptr;
@@ -320,7 +320,8 @@ static int weighted_dots(ks_ctx *c, int nd, const double *const *a, const double
 
 // ------------------------------------------------------------------- create
 // row-block sizes of the halo tilings
-static const int TILE_BR[ks_ctx::NTILE] = {16, 32, 64, 128, 256};
+// (85 and 170 rows fill one pass of 512 / 1024 threads at 6 or 12 lanes per row)
+static const int TILE_BR[ks_ctx::NTILE] = {32, 64, 85, 128, 170, 256};
 static int tile_index(int br) {
   for (int i = 0; i < ks_ctx::NTILE; ++i)
     if (TILE_BR[i] == br) return i;
@@ -871,16 +872,20 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
     c->ng64 = geti("KS_SPMM_NG64");
     c->ng32 = geti("KS_SPMM_NG32");
     c->ngP = geti("KS_SPMM_NGP");
-    // SpMM phase kernel before any autotuning: halo tiles of 64 rows (FP64),
-    // 128 (FP32), 256 (Poisson, one column); KS_TILE64/32/P = rows, 0 = row kernel
-    auto tile_env = [&](const char *n, int dflt) {
+    // SpMM phase kernel before any autotuning: halo tiles of 85 rows with
+    // 1024 threads (FP64), 85 rows with 512 threads (FP32), 128 rows with 512
+    // threads (Poisson, one column); KS_TILE64/32/P = rows (0 = row kernel),
+    // KS_TILE64_TB/32_TB/P_TB = threads
+    auto tile_env = [&](const char *n, int dflt, const char *ntb, int dtb) {
       const char *v = std::getenv(n);
+      const char *vt = std::getenv(ntb);
       const int i = tile_index(v ? std::atoi(v) : dflt);
-      return i >= 0 ? 3 * i + 1 : -1;  // 512 threads
+      const int tb = vt ? std::atoi(vt) : dtb;
+      return i >= 0 ? 3 * i + (tb == 1024 ? 2 : (tb == 512 ? 1 : 0)) : -1;
     };
-    c->tile64 = tile_env("KS_TILE64", 64);
-    c->tile32 = tile_env("KS_TILE32", 64);
-    c->tileP = tile_env("KS_TILEP", 128);
+    c->tile64 = tile_env("KS_TILE64", 85, "KS_TILE64_TB", 1024);
+    c->tile32 = tile_env("KS_TILE32", 85, "KS_TILE32_TB", 512);
+    c->tileP = tile_env("KS_TILEP", 128, "KS_TILEP_TB", 512);
     apply_tiles(c);
   }
   H2D(c->colB, colB.data(), colB.size());
