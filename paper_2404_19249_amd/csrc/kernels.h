@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace ks {
 
@@ -216,4 +217,18 @@ void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const 
                     unsigned long long *t_done, int *status);
 void launch_batch_reset(void *systems, int n, unsigned long long *t0, hipStream_t s);
 void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStream_t s);
+}  // namespace ks
+
+namespace ks {
+// ------------------------------------------------------------ multigrid
+struct Multigrid;
+void kuhn_interp(const double *x, double L, int nH, int32_t *idx, double *w);
+Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d,
+                    const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
+                    const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
+                    hipStream_t s);
+void mg_destroy(Multigrid *mg);
+int mg_levels(const Multigrid *mg);
+int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *red,
+           int *iters, double *relres, hipStream_t s);
 }  // namespace ks

@@ -141,6 +141,8 @@ struct ks_ctx {
   // halo tilings of the CSR pattern for the LDS-staged SpMM, row blocks of
   // TILE_BR[i] rows; chosen tiling per solver (-1 = row kernel)
   static constexpr int NTILE = 6;
+  Multigrid *mg = nullptr;  // V-cycle hierarchy of the Poisson operator (nullptr: Jacobi-PCG)
+  int mg_iters_last = 0;
   Tiling til[NTILE];
   int tile64 = -1, tile32 = -1, tileP = -1;
   unsigned int *counters = nullptr;
@@ -156,6 +158,7 @@ struct ks_ctx {
     return KS_OK;
   }
   ~ks_ctx() {
+    if (mg) mg_destroy(mg);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -276,11 +279,20 @@ static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
   if (!c->vh_warm) launch_fill(c->N, 0.0, c->vh_int, c->s);
   int it[1] = {0}, conv = 0, brk = 0;
   double rr[1];
-  int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->rhs, c->vh_int,
-                            c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
-                            c->s, c->ngP);
-  if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
-  if (brk) return fail(KS_ERR_BREAKDOWN, "Poisson PCG breakdown");
+  if (c->mg) {
+    // CG preconditioned by one multigrid V-cycle per iteration
+    const int r = mg_pcg(c->mg, c->rhs, c->vh_int, c->opt.tol_poisson, c->opt.max_it_poisson, c->redpart,
+                         c->mom + 64, it, rr, c->s);
+    if (r == -1) return fail(KS_ERR_HIP, "Poisson MG-PCG failed");
+    if (r == -2) return fail(KS_ERR_BREAKDOWN, "Poisson MG-PCG breakdown");
+    conv = (r == 0);
+  } else {
+    int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->rhs, c->vh_int,
+                              c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
+                              c->s, c->ngP);
+    if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
+    if (brk) return fail(KS_ERR_BREAKDOWN, "Poisson PCG breakdown");
+  }
   c->vh_warm = true;
   if (iters) *iters += it[0];
   launch_scatter_nodes(c->n_nodes, c->node2int, c->node2bnd, c->vh_int, c->wB, c->vh_nodes, c->s);
@@ -973,6 +985,25 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return bail(fail(KS_ERR_HIP, "event creation failed"));
+  // multigrid hierarchy for the Hartree Poisson solves (KS_POISSON=jacobi: none)
+  {
+    const char *env = std::getenv("KS_POISSON");
+    const bool want = c->opt.hartree_mode != KS_HARTREE_OFF && !(env && std::strcmp(env, "jacobi") == 0);
+    if (want) {
+      std::vector<double> Kh(c->nnz), X((size_t)N * 3);
+      if (hipMemcpyAsync(Kh.data(), c->K, sizeof(double) * c->nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(KS_ERR_HIP, "download failed"));
+      for (int r = 0; r < N; ++r)
+        for (int d = 0; d < 3; ++d) X[3 * (size_t)r + d] = mesh->coords_host[3 * (int64_t)interior_nodes[r] + d];
+      // cells per side of the first coarse level: the fine mesh's vertex
+      // lattice for P2 (P1 on the same vertices), half of it for P1
+      const int side = (int)std::lround(std::cbrt((double)nn));
+      const int nfine = std::max(1, (side - 1) / c->order);
+      const int n1 = c->order == 2 ? nfine : nfine / 2;
+      c->mg = mg_build(N, c->rowptr, c->col, c->K, rowptr, colI, Kh, X, c->L, n1, s);
+    }
+  }
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(KS_ERR_HIP, "setup failed"));
   *out = c;
   return KS_OK;

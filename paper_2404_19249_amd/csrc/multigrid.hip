@@ -1,0 +1,516 @@
+// Multigrid-preconditioned CG for the Hartree Poisson problem K_II v = f.
+//
+// The paper solves its Poisson and boundary value problems with
+// algebraic-multigrid-preconditioned Krylov methods (PETSc GAMG).  Here the
+// coarse spaces are the P1 spaces of uniform Kuhn (Freudenthal) meshes of the
+// same box, each with half the cells per side of the level above; the
+// interpolation of a level's nodes into the next coarser mesh is closed-form
+// point location (the coarse tetrahedron containing a point follows from the
+// ordering of its cell-local coordinates), which is exact for nested uniform
+// levels and a smooth (non-nested) transfer from the moved fine mesh.  Coarse
+// operators are Galerkin products A_l = P_l^T A_{l-1} P_l, formed once per
+// mesh on the host; the coarsest (at most 512 unknowns) is inverted densely.
+//
+// Preconditioner: one symmetric V-cycle with Chebyshev smoothing (degree 2,
+// Jacobi-scaled, interval [lambda_max / 8, 1.1 lambda_max] of D^-1 A from a
+// power iteration), the same polynomial before and after the coarse
+// correction, so the preconditioner is symmetric positive definite.
+#include "common.h"
+#include "kernels.h"
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+namespace ks {
+
+namespace {
+
+template <typename F>
+void par_for(int64_t n, F f) {
+  const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 4096 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=]() {
+      for (int64_t i = a; i < b; ++i) f(i);
+    });
+  }
+  for (auto &x : th) x.join();
+}
+
+struct HostCSR {
+  int n = 0, m = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+
+// y = A x
+void host_spmv(const HostCSR &A, const std::vector<double> &x, std::vector<double> &y) {
+  y.assign(A.n, 0.0);
+  par_for(A.n, [&](int64_t i) {
+    double s = 0.0;
+    for (int j = A.rp[i]; j < A.rp[i + 1]; ++j) s += A.v[j] * x[A.ci[j]];
+    y[i] = s;
+  });
+}
+
+// C = P^T A P with P given as ELL-4 (idx -1 = unused), A square n x n, P n x nc
+HostCSR galerkin(const HostCSR &A, const std::vector<int32_t> &Pi, const std::vector<double> &Pw, int nc) {
+  const int n = A.n;
+  // AP row by row (sparse, coarse columns)
+  std::vector<std::vector<std::pair<int32_t, double>>> AP(n);
+  par_for(n, [&](int64_t i) {
+    std::vector<std::pair<int32_t, double>> &row = AP[i];
+    for (int j = A.rp[i]; j < A.rp[i + 1]; ++j) {
+      const int c = A.ci[j];
+      for (int t = 0; t < 4; ++t)
+        if (Pi[4 * (size_t)c + t] >= 0) row.push_back({Pi[4 * (size_t)c + t], A.v[j] * Pw[4 * (size_t)c + t]});
+    }
+    std::sort(row.begin(), row.end(), [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+      return a.first < b.first;
+    });
+    size_t o = 0;
+    for (size_t t = 0; t < row.size(); ++t) {
+      if (o > 0 && row[o - 1].first == row[t].first) row[o - 1].second += row[t].second;
+      else row[o++] = row[t];
+    }
+    row.resize(o);
+  });
+  // transpose of P: coarse row -> (fine row, weight)
+  std::vector<int32_t> tp(nc + 1, 0);
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < 4; ++t)
+      if (Pi[4 * (size_t)i + t] >= 0) tp[Pi[4 * (size_t)i + t] + 1]++;
+  for (int a = 0; a < nc; ++a) tp[a + 1] += tp[a];
+  std::vector<int32_t> tf(tp[nc]);
+  std::vector<double> tw(tp[nc]);
+  {
+    std::vector<int32_t> pos(tp.begin(), tp.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < 4; ++t) {
+        const int a = Pi[4 * (size_t)i + t];
+        if (a >= 0) {
+          tf[pos[a]] = i;
+          tw[pos[a]++] = Pw[4 * (size_t)i + t];
+        }
+      }
+  }
+  // C rows: sum over fine rows i of P_ia * AP_i
+  std::vector<std::vector<std::pair<int32_t, double>>> C(nc);
+  par_for(nc, [&](int64_t a) {
+    std::vector<std::pair<int32_t, double>> acc;
+    for (int t = tp[a]; t < tp[a + 1]; ++t) {
+      const double w = tw[t];
+      for (const auto &e : AP[tf[t]]) acc.push_back({e.first, w * e.second});
+    }
+    std::sort(acc.begin(), acc.end(), [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+      return x.first < y.first;
+    });
+    size_t o = 0;
+    for (size_t u = 0; u < acc.size(); ++u) {
+      if (o > 0 && acc[o - 1].first == acc[u].first) acc[o - 1].second += acc[u].second;
+      else acc[o++] = acc[u];
+    }
+    acc.resize(o);
+    C[a].swap(acc);
+  });
+  HostCSR out;
+  out.n = out.m = nc;
+  out.rp.assign(nc + 1, 0);
+  for (int a = 0; a < nc; ++a) out.rp[a + 1] = out.rp[a] + (int32_t)C[a].size();
+  out.ci.resize(out.rp[nc]);
+  out.v.resize(out.rp[nc]);
+  par_for(nc, [&](int64_t a) {
+    int o = out.rp[a];
+    for (const auto &e : C[a]) {
+      out.ci[o] = e.first;
+      out.v[o++] = e.second;
+    }
+  });
+  return out;
+}
+
+// largest eigenvalue of D^-1 A (power iteration from a fixed start)
+double lambda_max_jacobi(const HostCSR &A) {
+  std::vector<double> d(A.n, 1.0), x(A.n), y;
+  for (int i = 0; i < A.n; ++i) {
+    for (int j = A.rp[i]; j < A.rp[i + 1]; ++j)
+      if (A.ci[j] == i) d[i] = A.v[j];
+    x[i] = 1.0 + 0.37 * std::sin(0.91 * i);  // deterministic, not an eigenvector
+  }
+  double lam = 1.0;
+  for (int it = 0; it < 20; ++it) {
+    host_spmv(A, x, y);
+    double nx = 0.0, ny = 0.0, xy = 0.0;
+    for (int i = 0; i < A.n; ++i) {
+      y[i] /= d[i];
+      nx += x[i] * x[i];
+      xy += x[i] * y[i];
+      ny += y[i] * y[i];
+    }
+    lam = xy / nx;
+    const double s = 1.0 / std::sqrt(ny);
+    for (int i = 0; i < A.n; ++i) x[i] = y[i] * s;
+  }
+  return lam;
+}
+
+}  // namespace
+
+// point location in the uniform Kuhn mesh of [-L, L]^3 with nH cells per
+// side: the (up to 4) interior vertices of the tetrahedron containing x and
+// their barycentric weights; vertex id = (i-1) + ni ((j-1) + ni (k-1)),
+// ni = nH - 1; boundary vertices are dropped (zero Dirichlet values).
+void kuhn_interp(const double *x, double L, int nH, int32_t *idx, double *w) {
+  const int ni = nH - 1;
+  const double h = 2.0 * L / nH;
+  int cell[3];
+  double xi[3];
+  for (int d = 0; d < 3; ++d) {
+    const double t = (x[d] + L) / h;
+    int ci = (int)std::floor(t);
+    ci = std::max(0, std::min(nH - 1, ci));
+    cell[d] = ci;
+    xi[d] = std::min(1.0, std::max(0.0, t - ci));
+  }
+  int ord[3] = {0, 1, 2};
+  std::sort(ord, ord + 3, [&](int a, int b) { return xi[a] > xi[b] || (xi[a] == xi[b] && a < b); });
+  const double lam[4] = {1.0 - xi[ord[0]], xi[ord[0]] - xi[ord[1]], xi[ord[1]] - xi[ord[2]], xi[ord[2]]};
+  int v[3] = {cell[0], cell[1], cell[2]};
+  int cnt = 0;
+  for (int t = 0; t < 4; ++t) idx[t] = -1, w[t] = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    if (j > 0) v[ord[j - 1]] += 1;
+    bool inner = true;
+    for (int d = 0; d < 3; ++d)
+      if (v[d] <= 0 || v[d] >= nH) inner = false;
+    if (!inner || lam[j] == 0.0) continue;
+    idx[cnt] = (v[0] - 1) + ni * ((v[1] - 1) + ni * (v[2] - 1));
+    w[cnt] = lam[j];
+    ++cnt;
+  }
+}
+
+// ------------------------------------------------------------ device
+__global__ void k_cheb(int n, const double *__restrict__ r, const double *__restrict__ dinv, double c1,
+                       double c2, double *__restrict__ d, double *__restrict__ x, int first) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double di = (first ? 0.0 : c1 * d[i]) + c2 * dinv[i] * r[i];
+    d[i] = di;
+    x[i] = (first == 2 ? 0.0 : x[i]) + di;
+  }
+}
+static void launch_cheb(int n, const double *r, const double *dinv, double c1, double c2, double *d,
+                        double *x, int first, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_cheb, dim3(std::min(4096, (n + 255) / 256)), dim3(256), 0, s, n, r, dinv, c1, c2, d,
+                       x, first);
+}
+__global__ void k_invert(int n, const double *__restrict__ a, double *__restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = 1.0 / a[i];
+}
+
+struct MGLevel {
+  int n = 0;
+  const int32_t *rp = nullptr, *ci = nullptr;  // operator (level 0: the context's CSR)
+  const double *val = nullptr;
+  double *dinv = nullptr;
+  double lmax = 2.0;
+  // transfer to the next coarser level: restriction R = P^T (CSR, rows =
+  // coarse nodes) and prolongation P (ELL-4, rows = this level's nodes)
+  int32_t *Rrp = nullptr, *Rci = nullptr, *Pidx = nullptr;
+  double *Rv = nullptr, *Pw = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr;
+};
+
+struct Multigrid {
+  std::vector<MGLevel> lv;
+  double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
+  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;  // PCG vectors (level 0)
+  std::vector<void *> mem;
+  ~Multigrid() {
+    for (void *p : mem) (void)hipFree(p);
+  }
+  template <typename T>
+  bool alloc(T **p, size_t n) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n * sizeof(T), 256)) != hipSuccess) return false;
+    mem.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return true;
+  }
+};
+
+void mg_destroy(Multigrid *mg) { delete mg; }
+int mg_levels(const Multigrid *mg) { return mg ? (int)mg->lv.size() : 0; }
+
+// Build the hierarchy.  Level 0 is the given operator (device CSR plus its
+// host copy for the Galerkin products); coords: the level-0 unknowns'
+// coordinates [n][3]; L: half side of the box; n1: cells per side of the
+// first coarse level.  Returns nullptr when no coarse level fits.
+Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d,
+                    const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
+                    const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
+                    hipStream_t s) {
+  if (n1 < 2) return nullptr;
+  Multigrid *mg = new Multigrid();
+  auto bail = [&]() {
+    delete mg;
+    return (Multigrid *)nullptr;
+  };
+  HostCSR A;
+  A.n = A.m = n0;
+  A.rp = rp_h;
+  A.ci = ci_h;
+  A.v = val_h;
+  std::vector<double> X = coords;  // this level's node coordinates
+  int n_cells = n1;
+  {
+    MGLevel l0;
+    l0.n = n0;
+    l0.rp = rp_d;
+    l0.ci = ci_d;
+    l0.val = val_d;
+    mg->lv.push_back(l0);
+  }
+  std::vector<HostCSR> ops;
+  ops.push_back(A);
+  while (true) {
+    MGLevel &f = mg->lv.back();
+    const HostCSR &Af = ops.back();
+    f.lmax = lambda_max_jacobi(Af);
+    const int ni = n_cells - 1;
+    const int nc = ni * ni * ni;
+    if (nc < 1) break;
+    // interpolation of this level's nodes from the coarse mesh
+    std::vector<int32_t> Pi((size_t)f.n * 4);
+    std::vector<double> Pw((size_t)f.n * 4);
+    par_for(f.n, [&](int64_t i) { kuhn_interp(&X[3 * i], L, n_cells, &Pi[4 * i], &Pw[4 * i]); });
+    HostCSR Ac = galerkin(Af, Pi, Pw, nc);
+    // a coarse node no fine node interpolates from leaves a zero row: the
+    // hierarchy is then unusable (the caller keeps the Jacobi-PCG solver)
+    for (int a = 0; a < nc; ++a) {
+      bool has = false;
+      for (int j = Ac.rp[a]; j < Ac.rp[a + 1]; ++j) has = has || (Ac.ci[j] == a && Ac.v[j] > 0.0);
+      if (!has) return bail();
+    }
+    // restriction CSR = P^T
+    std::vector<int32_t> Rrp(nc + 1, 0), Rci;
+    std::vector<double> Rv;
+    for (int i = 0; i < f.n; ++i)
+      for (int t = 0; t < 4; ++t)
+        if (Pi[4 * (size_t)i + t] >= 0) Rrp[Pi[4 * (size_t)i + t] + 1]++;
+    for (int a = 0; a < nc; ++a) Rrp[a + 1] += Rrp[a];
+    Rci.resize(Rrp[nc]);
+    Rv.resize(Rrp[nc]);
+    {
+      std::vector<int32_t> pos(Rrp.begin(), Rrp.end() - 1);
+      for (int i = 0; i < f.n; ++i)
+        for (int t = 0; t < 4; ++t) {
+          const int a = Pi[4 * (size_t)i + t];
+          if (a >= 0) {
+            Rci[pos[a]] = i;
+            Rv[pos[a]++] = Pw[4 * (size_t)i + t];
+          }
+        }
+    }
+    if (!mg->alloc(&f.Rrp, nc + 1) || !mg->alloc(&f.Rci, Rci.size()) || !mg->alloc(&f.Rv, Rv.size()) ||
+        !mg->alloc(&f.Pidx, Pi.size()) || !mg->alloc(&f.Pw, Pw.size()))
+      return bail();
+    if (hipMemcpyAsync(f.Rrp, Rrp.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f.Rci, Rci.data(), sizeof(int32_t) * Rci.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f.Rv, Rv.data(), sizeof(double) * Rv.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f.Pidx, Pi.data(), sizeof(int32_t) * Pi.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(f.Pw, Pw.data(), sizeof(double) * Pw.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail();
+    // the coarse level
+    MGLevel cl;
+    cl.n = nc;
+    int32_t *crp, *cci;
+    double *cv;
+    if (!mg->alloc(&crp, nc + 1) || !mg->alloc(&cci, Ac.ci.size()) || !mg->alloc(&cv, Ac.v.size())) return bail();
+    if (hipMemcpyAsync(crp, Ac.rp.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(cci, Ac.ci.data(), sizeof(int32_t) * Ac.ci.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(cv, Ac.v.data(), sizeof(double) * Ac.v.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail();
+    cl.rp = crp;
+    cl.ci = cci;
+    cl.val = cv;
+    // node coordinates of the coarse level (interior lattice vertices)
+    std::vector<double> Xc((size_t)nc * 3);
+    const double h = 2.0 * L / n_cells;
+    for (int kz = 0; kz < ni; ++kz)
+      for (int jy = 0; jy < ni; ++jy)
+        for (int ix = 0; ix < ni; ++ix) {
+          const size_t a = ix + (size_t)ni * (jy + (size_t)ni * kz);
+          Xc[3 * a] = -L + h * (ix + 1);
+          Xc[3 * a + 1] = -L + h * (jy + 1);
+          Xc[3 * a + 2] = -L + h * (kz + 1);
+        }
+    mg->lv.push_back(cl);
+    ops.push_back(std::move(Ac));
+    X.swap(Xc);
+    if (nc <= 512 || n_cells < 4) break;  // coarsest: dense
+    n_cells /= 2;
+  }
+  if (mg->lv.size() < 2) return bail();
+  // dense inverse of the coarsest operator
+  {
+    const HostCSR &Ac = ops.back();
+    const int n = Ac.n;
+    std::vector<double> G((size_t)n * n, 0.0), I((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a)
+      for (int j = Ac.rp[a]; j < Ac.rp[a + 1]; ++j) G[(size_t)a * n + Ac.ci[j]] = Ac.v[j];
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int p = 0; p < n; ++p) {
+      int piv = p;
+      for (int r = p + 1; r < n; ++r)
+        if (std::fabs(G[(size_t)r * n + p]) > std::fabs(G[(size_t)piv * n + p])) piv = r;
+      if (!(std::fabs(G[(size_t)piv * n + p]) > 0.0)) return bail();
+      if (piv != p)
+        for (int j = 0; j < n; ++j) {
+          std::swap(G[(size_t)p * n + j], G[(size_t)piv * n + j]);
+          std::swap(I[(size_t)p * n + j], I[(size_t)piv * n + j]);
+        }
+      const double dd = 1.0 / G[(size_t)p * n + p];
+      for (int j = 0; j < n; ++j) {
+        G[(size_t)p * n + j] *= dd;
+        I[(size_t)p * n + j] *= dd;
+      }
+      for (int r = 0; r < n; ++r) {
+        if (r == p) continue;
+        const double fct = G[(size_t)r * n + p];
+        if (fct == 0.0) continue;
+        for (int j = 0; j < n; ++j) {
+          G[(size_t)r * n + j] -= fct * G[(size_t)p * n + j];
+          I[(size_t)r * n + j] -= fct * I[(size_t)p * n + j];
+        }
+      }
+    }
+    if (!mg->alloc(&mg->coarse_inv, (size_t)n * n)) return bail();
+    if (hipMemcpyAsync(mg->coarse_inv, I.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s) != hipSuccess)
+      return bail();
+  }
+  // work vectors and inverse diagonals
+  if (!mg->alloc(&mg->pr, n0) || !mg->alloc(&mg->pz, n0) || !mg->alloc(&mg->pp, n0) || !mg->alloc(&mg->pq, n0))
+    return bail();
+  for (size_t l = 0; l < mg->lv.size(); ++l) {
+    MGLevel &v = mg->lv[l];
+    if (!mg->alloc(&v.b, v.n) || !mg->alloc(&v.x, v.n) || !mg->alloc(&v.r, v.n) || !mg->alloc(&v.d, v.n) ||
+        !mg->alloc(&v.dinv, v.n))
+      return bail();
+    std::vector<double> dh(v.n, 1.0);
+    const HostCSR &Al = ops[l];
+    for (int i = 0; i < Al.n; ++i)
+      for (int j = Al.rp[i]; j < Al.rp[i + 1]; ++j)
+        if (Al.ci[j] == i) dh[i] = 1.0 / Al.v[j];
+    if (hipMemcpyAsync(v.dinv, dh.data(), sizeof(double) * v.n, hipMemcpyHostToDevice, s) != hipSuccess)
+      return bail();
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return bail();
+  return mg;
+}
+
+// Chebyshev smoothing (degree 2) of A x = b on level l; zero_init: x = 0 in
+static void mg_smooth(MGLevel &v, const double *b, bool zero_init, hipStream_t s) {
+  const double lo = v.lmax / 8.0, hi = 1.1 * v.lmax;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  // d_1 = D^-1 r / theta, x += d_1
+  if (zero_init) {
+    launch_cheb(v.n, b, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 2, s);
+  } else {
+    launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);
+    launch_cheb(v.n, v.r, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 1, s);
+  }
+  const double rho0 = 1.0 / sigma;
+  const double rho1 = 1.0 / (2.0 * sigma - rho0);
+  launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);  // r = b - A x
+  launch_cheb(v.n, v.r, v.dinv, rho1 * rho0, 2.0 * rho1 / delta, v.d, v.x, 0, s);
+}
+
+// one V-cycle: x_0 = M^-1 b_0 on level 0 (b, x: level-0 vectors)
+static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s) {
+  MGLevel &v = mg->lv[l];
+  if (l + 1 == (int)mg->lv.size()) {
+    launch_small_gemm(v.n, 1, v.n, mg->coarse_inv, v.n, b, 1, x, 1, 0.0, s);
+    return;
+  }
+  double *xs = v.x;
+  v.x = x;  // smooth in place in the caller's vector
+  mg_smooth(v, b, true, s);
+  launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);  // r = b - A x
+  MGLevel &c = mg->lv[l + 1];
+  launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);  // b_c = P^T r
+  vcycle(mg, l + 1, c.b, c.x, s);
+  launch_ellP_times(v.n, v.Pidx, v.Pw, c.x, 1, 1, 1.0, v.x, 1, v.x, 1, s);  // x += P x_c
+  mg_smooth(v, b, false, s);
+  v.x = xs;
+}
+
+void mg_apply(Multigrid *mg, const double *b, double *x, hipStream_t s) { vcycle(mg, 0, b, x, s); }
+
+// a . b over n values, to the host (fixed-order block partials)
+static int dot(int n, const double *a, const double *b, double *part, double *red, double *out, hipStream_t s) {
+  const int nb = launch_coldots(n, 1, a, b, part, s);
+  launch_reduce_cols(part, nb, 1, red, s);
+  if (hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  return 0;
+}
+
+// CG preconditioned by one V-cycle per iteration on level 0's operator:
+// A x = f from the warm start x, stopped at ||f - A x||_2 <= tol ||f||_2.
+// part / red: device scratch for the dot products.  Returns 0 converged,
+// 1 iteration limit, -1 launch failure, -2 breakdown (p.Ap <= 0).
+int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *red,
+           int *iters, double *relres, hipStream_t s) {
+  MGLevel &v = mg->lv[0];
+  const int n = v.n;
+  double bb = 0.0, rr = 0.0, rz = 0.0, pq = 0.0;
+  if (dot(n, f, f, part, red, &bb, s) < 0) return -1;
+  launch_spmm(n, v.rp, v.ci, v.val, x, 1, mg->pr, 1, 1, f, 1, 1, nullptr, s);  // r = f - A x
+  if (dot(n, mg->pr, mg->pr, part, red, &rr, s) < 0) return -1;
+  *iters = 0;
+  if (!(bb > 0.0)) {
+    launch_fill(n, 0.0, x, s);
+    *relres = 0.0;
+    return 0;
+  }
+  if (rr <= tol * tol * bb) {
+    *relres = std::sqrt(rr / bb);
+    return 0;
+  }
+  vcycle(mg, 0, mg->pr, mg->pz, s);
+  if (hipMemcpyAsync(mg->pp, mg->pz, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
+  if (dot(n, mg->pr, mg->pz, part, red, &rz, s) < 0) return -1;
+  for (int it = 1; it <= max_it; ++it) {
+    launch_spmm(n, v.rp, v.ci, v.val, mg->pp, 1, mg->pq, 1, 1, nullptr, 0, 0, nullptr, s);  // q = A p
+    if (dot(n, mg->pp, mg->pq, part, red, &pq, s) < 0) return -1;
+    if (!(pq > 0.0)) return -2;
+    const double alpha = rz / pq;
+    launch_axpby(n, alpha, mg->pp, 1.0, x, s);
+    launch_axpby(n, -alpha, mg->pq, 1.0, mg->pr, s);
+    if (dot(n, mg->pr, mg->pr, part, red, &rr, s) < 0) return -1;
+    *iters = it;
+    *relres = std::sqrt(rr / bb);
+    if (rr <= tol * tol * bb) return 0;
+    vcycle(mg, 0, mg->pr, mg->pz, s);
+    double rz_new = 0.0;
+    if (dot(n, mg->pr, mg->pz, part, red, &rz_new, s) < 0) return -1;
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    launch_axpby(n, 1.0, mg->pz, beta, mg->pp, s);  // p = z + beta p
+  }
+  return 1;
+}
+
+}  // namespace ks
