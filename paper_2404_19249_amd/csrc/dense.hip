@@ -782,6 +782,123 @@ int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const do
   return 0;
 }
 
+// ---------------------------------------- reduced eigensolve, split form
+// The dense products around the Jacobi iteration (r <= 190) run as
+// one-thread-per-entry kernels over many workgroups; only the Jacobi
+// iteration itself is one workgroup.
+
+// C = op(A) op(B) + beta C, op = transpose when t* != 0 (row-major, small)
+__global__ void k_gemm_small(int m, int n, int p, const double *__restrict__ A, int lda, int ta,
+                             const double *__restrict__ B, int ldb, int tb, double *__restrict__ C,
+                             int ldc, double beta) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int i = idx / n, j = idx % n;
+  double s = 0.0;
+  for (int l = 0; l < p; ++l) {
+    const double a = ta ? A[(int64_t)l * lda + i] : A[(int64_t)i * lda + l];
+    const double b = tb ? B[(int64_t)j * ldb + l] : B[(int64_t)l * ldb + j];
+    s += a * b;
+  }
+  C[(int64_t)i * ldc + j] = beta != 0.0 ? s + beta * C[(int64_t)i * ldc + j] : s;
+}
+static void gemm_small(int m, int n, int p, const double *A, int lda, int ta, const double *B, int ldb, int tb,
+                       double *C, int ldc, hipStream_t s) {
+  if (m * n > 0)
+    hipLaunchKernelGGL(k_gemm_small, dim3((m * n + 127) / 128), dim3(128), 0, s, m, n, p, A, lda, ta, B, ldb, tb,
+                       C, ldc, 0.0);
+}
+// S = D sym(FA) D  (m x m, ld m)
+__global__ void k_scale_sym(int m, const double *__restrict__ FA, int ldfa, const double *__restrict__ D,
+                            double *__restrict__ S) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int i = idx / m, j = idx % m;
+  S[idx] = D[i] * D[j] * 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]);
+}
+// eigenvalues (unsorted, lam) and eigenvectors V (r x r) of the symmetric C
+__global__ void __launch_bounds__(EIG_THREADS) k_jacobi_only(int r, const double *__restrict__ C,
+                                                             double *__restrict__ V, double *__restrict__ lam,
+                                                             int *info) {
+  extern __shared__ double sA[];
+  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
+      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32];
+  __shared__ int s_cnt;
+  const int ne = (r + 1) & ~1;
+  for (int idx = threadIdx.x; idx < ne * ne; idx += blockDim.x) {
+    const int a = idx / ne, b = idx % ne;
+    if (b < a) continue;
+    sA[pk(a, b, ne)] = (a < r && b < r) ? 0.5 * (C[a * r + b] + C[b * r + a]) : 0.0;
+  }
+  __syncthreads();
+  const int sw = jacobi_packed(r, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q, &s_cnt, s_red);
+  for (int i = threadIdx.x; i < r; i += blockDim.x) lam[i] = sA[pk(i, i, ne)];
+  if (threadIdx.x == 0) {
+    info[0] = r;
+    info[1] = sw;
+  }
+}
+// ascending theta; U[:, j] = D .* XW[:, sel_j] for the k lowest, largest-
+// magnitude entry of each column positive (one workgroup)
+__global__ void __launch_bounds__(256) k_eig_select(int m, int k, int r, const double *__restrict__ lam,
+                                                    const double *__restrict__ XW, const double *__restrict__ D,
+                                                    double *__restrict__ theta, double *__restrict__ U) {
+  __shared__ int s_sel[PJ_MAXN];
+  for (int i = threadIdx.x; i < r; i += blockDim.x) {
+    const double v = lam[i];
+    int rk = 0;
+    for (int j = 0; j < r; ++j) rk += (lam[j] < v) || (lam[j] == v && j < i);
+    s_sel[rk] = i;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < r; i += blockDim.x) theta[i] = lam[s_sel[i]];
+  for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) {
+    const int i = idx / k, j = idx % k;
+    U[idx] = j < r ? D[i] * XW[(int64_t)i * r + s_sel[j]] : 0.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    int im = 0;
+    double vm = -1.0;
+    for (int i = 0; i < m; ++i) {
+      const double a = fabs(U[i * k + j]);
+      if (a > vm) { vm = a; im = i; }
+    }
+    if (U[im * k + j] < 0.0)
+      for (int i = 0; i < m; ++i) U[i * k + j] = -U[i * k + j];
+  }
+}
+int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, const double *D, const double *X,
+                             double *W, int warm, double *S, double *T1, double *T2, double *V, double *lam,
+                             double *theta, double *U, int *info, hipStream_t s) {
+  if (enable_big_lds() < 0) return -1;
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void *)k_jacobi_only, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)orth_shared_bytes(PJ_MAXN)) != hipSuccess)
+      return -1;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_scale_sym, dim3((m * m + 255) / 256), dim3(256), 0, s, m, FA, ldfa, D, S);
+  gemm_small(m, r, m, S, m, 0, X, m, 0, T1, r, s);   // T1 = S X      (m x r)
+  gemm_small(r, r, m, X, m, 1, T1, r, 0, T2, r, s);  // T2 = X^T T1   (r x r)
+  if (warm) {
+    gemm_small(r, r, r, T2, r, 0, W, r, 0, T1, r, s);  // T1 = C W
+    gemm_small(r, r, r, W, r, 1, T1, r, 0, T2, r, s);  // T2 = W^T C W
+  }
+  hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, r, T2, V, lam, info);
+  if (warm) {
+    gemm_small(r, r, r, W, r, 0, V, r, 0, T1, r, s);  // W <- W V
+    if (hipMemcpyAsync(W, T1, sizeof(double) * r * r, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
+  } else if (hipMemcpyAsync(W, V, sizeof(double) * r * r, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+    return -1;
+  }
+  gemm_small(m, r, r, X, m, 0, W, r, 0, T1, r, s);  // X W (m x r)
+  hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(256), 0, s, m, k, r, lam, T1, D, theta, U);
+  return 0;
+}
+
 void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB, int ldfb,
                       double *work, double *theta, double *U, int *info, hipStream_t s) {
   hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(EIG_THREADS), 0, s, m, k, FA, ldfa, FB, ldfb, work,

@@ -106,6 +106,10 @@ struct Tiling {
 // arrays in whole 16-byte chunks: each must extend 16 bytes past its last
 // entry.
 size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem);
+// Y = S X (B null) or Y = B - S X through the halo tiles (FP64); -1 when the
+// tiling cannot serve k columns (the caller uses launch_spmm)
+int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
+                      const double *X, double *Y, const double *B, hipStream_t s);
 
 struct PCGWork {
   void *R, *P, *Q;       // [N][k] of T
@@ -158,6 +162,11 @@ int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double 
 int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const double *D,
                        const double *X, double *W, int warm, double *T1, double *T2, double *V,
                        double *theta, double *U, int *info, hipStream_t s);
+// the same with the dense products as multi-workgroup kernels; S (m x m),
+// T1 (m x r), T2 (r x r), V (r x r), lam [r] are work buffers
+int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, const double *D, const double *X,
+                             double *W, int warm, double *S, double *T1, double *T2, double *V, double *lam,
+                             double *theta, double *U, int *info, hipStream_t s);
 // Dense P (first n_H columns of Z) from the ELL form
 void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,
                     hipStream_t s);
@@ -223,11 +232,13 @@ namespace ks {
 // ------------------------------------------------------------ multigrid
 struct Multigrid;
 void kuhn_interp(const double *x, double L, int nH, int32_t *idx, double *w);
-Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d,
+Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d, const Tiling *til0,
+                    int tb0,
                     const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
                     const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
                     hipStream_t s);
 void mg_destroy(Multigrid *mg);
+void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0);
 int mg_levels(const Multigrid *mg);
 int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *red,
            int *iters, double *relres, hipStream_t s);

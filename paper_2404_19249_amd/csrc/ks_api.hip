@@ -125,7 +125,7 @@ struct ks_ctx {
   int *einfo = nullptr;
   // two-stage eigensolver state: D, V, X (orthogonalised F_B basis), W (warm
   // start eigenvectors), scratch T1, T2; rank r of the current F_B
-  double *eD = nullptr, *eV = nullptr, *eX = nullptr, *eW = nullptr, *eT1 = nullptr, *eT2 = nullptr;
+  double *eD = nullptr, *eV = nullptr, *eX = nullptr, *eW = nullptr, *eT1 = nullptr, *eT2 = nullptr, *eS = nullptr, *eLam = nullptr;
   int e_rank = 0, e_m = 0;
   // state of the most recent ks_scf_step (for its energy and adjoint)
   bool have_step = false, last_nonlinear = false;
@@ -351,6 +351,7 @@ static void apply_tiles(ks_ctx *c) {
   set(c->pw64, c->tile64);
   set(c->pw32, c->tile32);
   set(c->pwP, c->tileP);
+  mg_set_tiling(c->mg, c->pwP.til, c->pwP.til_tb);
 }
 
 extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
@@ -797,6 +798,8 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(eW, (size_t)mm * mm);
   A_(eT1, (size_t)mm * mm);
   A_(eT2, (size_t)mm * mm);
+  A_(eS, (size_t)mm * mm);
+  A_(eLam, mm);
   A_(aux1, nqt);
   A_(aux2, nqt);
   A_(Rv, (size_t)N * km);
@@ -1001,7 +1004,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       const int side = (int)std::lround(std::cbrt((double)nn));
       const int nfine = std::max(1, (side - 1) / c->order);
       const int n1 = c->order == 2 ? nfine : nfine / 2;
-      c->mg = mg_build(N, c->rowptr, c->col, c->K, rowptr, colI, Kh, X, c->L, n1, s);
+      c->mg = mg_build(N, c->rowptr, c->col, c->K, c->pwP.til, c->pwP.til_tb, rowptr, colI, Kh, X, c->L, n1, s);
     }
   }
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(KS_ERR_HIP, "setup failed"));
@@ -2017,8 +2020,8 @@ static int eig_impl(ks_ctx *c, const double *FA, const double *FB, int m, int k,
   if (c->e_m != m) TRY(orth_impl(c, FB, m));
   const int r = c->e_rank;
   if (r < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(r) + " < k");
-  if (launch_reduced_eig(m, k, r, FA, m, c->eD, c->eX, c->eW, warm ? 1 : 0, c->eT1, c->eT2, c->eV,
-                         c->theta, U, c->einfo + 4, c->s) < 0)
+  if (launch_reduced_eig_split(m, k, r, FA, m, c->eD, c->eX, c->eW, warm ? 1 : 0, c->eS, c->eT1, c->eT2,
+                               c->eV, c->eLam, c->theta, U, c->einfo + 4, c->s) < 0)
     return fail(KS_ERR_HIP, "cannot enable the LDS size of the eigensolver");
   theta_all.resize(r);
   HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * r, hipMemcpyDeviceToHost, c->s));

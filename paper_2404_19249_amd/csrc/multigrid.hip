@@ -232,6 +232,8 @@ struct MGLevel {
 
 struct Multigrid {
   std::vector<MGLevel> lv;
+  const Tiling *til0 = nullptr;  // halo tiles of the level-0 operator (nullptr: row kernel)
+  int tb0 = 256;
   double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;  // PCG vectors (level 0)
   std::vector<void *> mem;
@@ -249,18 +251,27 @@ struct Multigrid {
 };
 
 void mg_destroy(Multigrid *mg) { delete mg; }
+void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0) {
+  if (mg) {
+    mg->til0 = til0;
+    mg->tb0 = tb0;
+  }
+}
 int mg_levels(const Multigrid *mg) { return mg ? (int)mg->lv.size() : 0; }
 
 // Build the hierarchy.  Level 0 is the given operator (device CSR plus its
 // host copy for the Galerkin products); coords: the level-0 unknowns'
 // coordinates [n][3]; L: half side of the box; n1: cells per side of the
 // first coarse level.  Returns nullptr when no coarse level fits.
-Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d,
+Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d, const Tiling *til0,
+                    int tb0,
                     const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
                     const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
                     hipStream_t s) {
   if (n1 < 2) return nullptr;
   Multigrid *mg = new Multigrid();
+  mg->til0 = til0;
+  mg->tb0 = tb0;
   auto bail = [&]() {
     delete mg;
     return (Multigrid *)nullptr;
@@ -420,20 +431,29 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
   return mg;
 }
 
+// y = A x (b null) or y = b - A x on one level (halo tiles on level 0)
+static void lv_spmv(const Multigrid *mg, const MGLevel &v, const double *x, double *y, const double *b,
+                    hipStream_t s) {
+  if (&v == &mg->lv[0] && mg->til0 &&
+      launch_spmm_tiled(v.n, 1, *mg->til0, mg->tb0, v.rp, v.val, x, y, b, s) == 0)
+    return;
+  launch_spmm(v.n, v.rp, v.ci, v.val, x, 1, y, 1, 1, b, 1, b ? 1 : 0, nullptr, s);
+}
+
 // Chebyshev smoothing (degree 2) of A x = b on level l; zero_init: x = 0 in
-static void mg_smooth(MGLevel &v, const double *b, bool zero_init, hipStream_t s) {
+static void mg_smooth(const Multigrid *mg, MGLevel &v, const double *b, bool zero_init, hipStream_t s) {
   const double lo = v.lmax / 8.0, hi = 1.1 * v.lmax;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   // d_1 = D^-1 r / theta, x += d_1
   if (zero_init) {
     launch_cheb(v.n, b, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 2, s);
   } else {
-    launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);
+    lv_spmv(mg, v, v.x, v.r, b, s);
     launch_cheb(v.n, v.r, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 1, s);
   }
   const double rho0 = 1.0 / sigma;
   const double rho1 = 1.0 / (2.0 * sigma - rho0);
-  launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);  // r = b - A x
+  lv_spmv(mg, v, v.x, v.r, b, s);  // r = b - A x
   launch_cheb(v.n, v.r, v.dinv, rho1 * rho0, 2.0 * rho1 / delta, v.d, v.x, 0, s);
 }
 
@@ -446,13 +466,13 @@ static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t
   }
   double *xs = v.x;
   v.x = x;  // smooth in place in the caller's vector
-  mg_smooth(v, b, true, s);
-  launch_spmm(v.n, v.rp, v.ci, v.val, v.x, 1, v.r, 1, 1, b, 1, 1, nullptr, s);  // r = b - A x
+  mg_smooth(mg, v, b, true, s);
+  lv_spmv(mg, v, v.x, v.r, b, s);  // r = b - A x
   MGLevel &c = mg->lv[l + 1];
   launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);  // b_c = P^T r
   vcycle(mg, l + 1, c.b, c.x, s);
   launch_ellP_times(v.n, v.Pidx, v.Pw, c.x, 1, 1, 1.0, v.x, 1, v.x, 1, s);  // x += P x_c
-  mg_smooth(v, b, false, s);
+  mg_smooth(mg, v, b, false, s);
   v.x = xs;
 }
 
@@ -477,7 +497,7 @@ int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, do
   const int n = v.n;
   double bb = 0.0, rr = 0.0, rz = 0.0, pq = 0.0;
   if (dot(n, f, f, part, red, &bb, s) < 0) return -1;
-  launch_spmm(n, v.rp, v.ci, v.val, x, 1, mg->pr, 1, 1, f, 1, 1, nullptr, s);  // r = f - A x
+  lv_spmv(mg, v, x, mg->pr, f, s);  // r = f - A x
   if (dot(n, mg->pr, mg->pr, part, red, &rr, s) < 0) return -1;
   *iters = 0;
   if (!(bb > 0.0)) {
@@ -493,7 +513,7 @@ int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, do
   if (hipMemcpyAsync(mg->pp, mg->pz, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
   if (dot(n, mg->pr, mg->pz, part, red, &rz, s) < 0) return -1;
   for (int it = 1; it <= max_it; ++it) {
-    launch_spmm(n, v.rp, v.ci, v.val, mg->pp, 1, mg->pq, 1, 1, nullptr, 0, 0, nullptr, s);  // q = A p
+    lv_spmv(mg, v, mg->pp, mg->pq, nullptr, s);  // q = A p
     if (dot(n, mg->pp, mg->pq, part, red, &pq, s) < 0) return -1;
     if (!(pq > 0.0)) return -2;
     const double alpha = rz / pq;

@@ -358,7 +358,9 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // per lane (k % VW == 0); halo rows copied in HCB-byte chunks, HCB = 16 when
 // k * sizeof(T) % 16 == 0, else 4; N * k * sizeof(T) < 2^32 (byte offsets
 // into P are 32-bit).  All checked by the host.
-template <typename T, int VW, int HCB, int TB>
+// MODE 0: the PCG phase (Q = S P, p.q partials, skipped once the solver
+// stopped); MODE 1: Q = S P; MODE 2: Q = B - S P.
+template <typename T, int VW, int HCB, int TB, int MODE>
 __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, int max_halo, int max_nnz,
                                                 const int32_t *__restrict__ halo_ptr,
                                                 const int32_t *__restrict__ halo_col,
@@ -367,8 +369,8 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
                                                 const uint16_t *__restrict__ lcol,
                                                 const T *__restrict__ val, const T *__restrict__ P,
                                                 T *__restrict__ Q, double *__restrict__ part,
-                                                const Control *ctl) {
-  if (ctl && ctl->stop) return;
+                                                const Control *ctl, const T *__restrict__ Bm) {
+  if (MODE == 0 && ctl && ctl->stop) return;
   extern __shared__ __align__(16) unsigned char t_smem[];
   const int CG = k / VW;
   const unsigned rowbytes = (unsigned)k * sizeof(T);
@@ -450,11 +452,18 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
         const T w = vs[j];
         for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
       }
-      const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
-      for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
+      if constexpr (MODE == 0) {
+        const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
+        for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
+      } else if constexpr (MODE == 2) {
+        T b[VW];
+        load_row<T, VW>(Bm, row, k, cg * VW, k, b);
+        for (int v = 0; v < VW; ++v) acc[v] = b[v] - acc[v];
+      }
       store_row<T, VW>(Q, row, k, cg * VW, k, acc);
     }
   }
+  if constexpr (MODE != 0) return;
   // per-workgroup column partials (fixed order): thread t holds columns
   // [(t % CG) VW, (t % CG) VW + VW) of its rows; the LDS image is free now
   __syncthreads();
@@ -498,38 +507,58 @@ static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb) {
   return sh;
 }
 
-template <typename T, int VW, int HCB, int TB>
+template <typename T, int VW, int HCB, int TB, int MODE>
 static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
-                           const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
+                           const T *val, const T *P, T *Q, double *part, const Control *ctl, const T *Bm,
+                           hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)TILE_LDS_MAX) != hipSuccess)
+    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB, MODE>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)TILE_LDS_MAX) != hipSuccess)
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, t.BR, t.nblk,
+  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, t.BR, t.nblk,
                      t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, val, P, Q, part,
-                     ctl);
+                     ctl, Bm);
   return 0;
+}
+template <typename T, int MODE>
+static int launch_tpcg_A_m(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
+                           const T *val, const T *P, T *Q, double *part, const Control *ctl, const T *Bm,
+                           hipStream_t s) {
+  constexpr int V16 = 16 / sizeof(T);
+#define KS_TL(VW, HCB, TB) \
+  return launch_tpcg_A_t<T, VW, HCB, TB, MODE>(N, k, t, sh, rowptr, val, P, Q, part, ctl, Bm, s)
+  if (sh.TB == 1024) {
+    if (sh.VW == V16) KS_TL(V16, 16, 1024);
+    if (sh.HCB == 16) KS_TL(1, 16, 1024);
+    KS_TL(1, 4, 1024);
+  }
+  if (sh.TB == 512) {
+    if (sh.VW == V16) KS_TL(V16, 16, 512);
+    if (sh.HCB == 16) KS_TL(1, 16, 512);
+    KS_TL(1, 4, 512);
+  }
+  if (sh.VW == V16) KS_TL(V16, 16, 256);
+  if (sh.HCB == 16) KS_TL(1, 16, 256);
+  KS_TL(1, 4, 256);
+#undef KS_TL
 }
 template <typename T>
 static int launch_tpcg_A(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
                          const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
-  constexpr int V16 = 16 / sizeof(T);
-  if (sh.TB == 1024) {
-    if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-    if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-    return launch_tpcg_A_t<T, 1, 4, 1024>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  }
-  if (sh.TB == 512) {
-    if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-    if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-    return launch_tpcg_A_t<T, 1, 4, 512>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  }
-  if (sh.VW == V16) return launch_tpcg_A_t<T, V16, 16, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  if (sh.HCB == 16) return launch_tpcg_A_t<T, 1, 16, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
-  return launch_tpcg_A_t<T, 1, 4, 256>(N, k, t, sh, rowptr, val, P, Q, part, ctl, s);
+  return launch_tpcg_A_m<T, 0>(N, k, t, sh, rowptr, val, P, Q, part, ctl, nullptr, s);
+}
+
+// Y = S X (B == nullptr) or Y = B - S X with the halo-tile kernel (FP64, X
+// and Y row-major [N][k]); -1 when the tiling cannot serve this k
+int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
+                      const double *X, double *Y, const double *B, hipStream_t s) {
+  const TShape sh = tiled_shape<double>(t, k, N, 1 << 30, tb);
+  if (sh.grid <= 0) return -1;
+  if (B) return launch_tpcg_A_m<double, 2>(N, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, B, s);
+  return launch_tpcg_A_m<double, 1>(N, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
 }
 
 // ================================================================== PCG
