@@ -267,7 +267,9 @@ static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out) {
 
 // V_H at the quadrature points for density rho with the frozen boundary
 // data c->wB (Sec. 3.1): K_II V_I = 4 pi <rho, phi_I> - K_IB w_B.
-static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
+// tol <= 0: the context's tol_poisson
+static int hartree_solve(ks_ctx *c, const double *rho, int *iters, double tol = 0.0) {
+  if (!(tol > 0.0)) tol = c->opt.tol_poisson;
   launch_fill(c->N, 0.0, c->load, c->s);
   for (int col = 0; col < c->n_colours; ++col) {
     const int a = c->colour_off[col], b = c->colour_off[col + 1];
@@ -281,14 +283,14 @@ static int hartree_solve(ks_ctx *c, const double *rho, int *iters) {
   double rr[1];
   if (c->mg) {
     // CG preconditioned by one multigrid V-cycle per iteration
-    const int r = mg_pcg(c->mg, c->rhs, c->vh_int, c->opt.tol_poisson, c->opt.max_it_poisson, c->redpart,
+    const int r = mg_pcg(c->mg, c->rhs, c->vh_int, tol, c->opt.max_it_poisson, c->redpart,
                          c->mom + 64, it, rr, c->s);
     if (r == -1) return fail(KS_ERR_HIP, "Poisson MG-PCG failed");
     if (r == -2) return fail(KS_ERR_BREAKDOWN, "Poisson MG-PCG breakdown");
     conv = (r == 0);
   } else {
     int r = pcg_solve<double>(c->N, 1, c->rowptr, c->col, c->K, c->rorder, c->diagK, c->rhs, c->vh_int,
-                              c->opt.tol_poisson, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
+                              tol, c->opt.max_it_poisson, c->pwP, it, rr, &conv, &brk,
                               c->s, c->ngP);
     if (r < 0) return fail(KS_ERR_HIP, "Poisson PCG failed");
     if (brk) return fail(KS_ERR_BREAKDOWN, "Poisson PCG breakdown");
@@ -2135,7 +2137,9 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   for (it = 0; it < c->opt.max_it_inner; ++it) {
     if (nonlinear) {
       if (hartree) {
-        int r = hartree_solve(c, c->rho_in, &piters);
+        // the inner fixed point cannot settle below the error the inexact
+        // Poisson solves leave in V_H: tie their tolerance to tol_inner
+        int r = hartree_solve(c, c->rho_in, &piters, std::min(c->opt.tol_poisson, 1e-4 * c->opt.tol_inner));
         if (r < 0) return r;
       } else {
         launch_fill(nqt, 0.0, c->vh_q, s);
@@ -2173,6 +2177,12 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
     int nb = launch_anderson_gram(nqt, c->n_q, c->absdet, c->qw, Fm, nh, Fj, c->redpart, s);
     TRY(reduce_small(c, c->redpart, nb, 21, g));
     res = std::sqrt(std::max(g[0], 0.0));
+    if (std::getenv("KS_TRACE_INNER")) {
+      int info[8] = {0};
+      (void)hipMemcpy(info, c->einfo, sizeof(int) * 8, hipMemcpyDeviceToHost);
+      std::fprintf(stderr, "[ks-inner] it %d res %.3e jacobi_sweeps %d poisson_iters %d\n", it, res, info[5],
+                   piters);
+    }
     if (res < c->opt.tol_inner) {
       it += 1;
       break;
