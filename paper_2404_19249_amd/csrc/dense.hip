@@ -459,11 +459,13 @@ __global__ void __launch_bounds__(EIG_THREADS) k_small_eig(int m, int k, const d
 
 // ------------------------------------------- packed-LDS Jacobi (m <= 190)
 // The symmetric matrix (padded to even order ne with a zero row/column) is
-// kept as its packed upper triangle in LDS.  One round rotates the ne/2
-// disjoint pairs of the round-robin schedule at once: every 2x2 block
-// (pair t1 rows, pair t2 columns), t1 <= t2, is transformed by J1^T B J2 by
-// one thread, so a round has no read/write conflicts.  Eigenvectors are
-// accumulated in V (global, ld = n).  A pair is rotated while
+// kept as its packed upper triangle in LDS.  A sweep is ne - 1 rounds of the
+// circle method (player ne - 1 stays, the others turn), each round rotating
+// ne/2 disjoint pairs at once: every 2x2 block (pair t1 rows, pair t2
+// columns), t1 <= t2, is transformed by J1^T B J2 by one thread, so a round
+// has no read/write conflicts.  Eigenvectors are accumulated as the ROWS of
+// Vt (global, ld = n; Vt[p][i] = entry i of eigenvector p), so a rotation
+// updates two contiguous rows.  A pair is rotated while
 // |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and above an absolute floor; the sweep
 // loop stops after a sweep without rotations.
 constexpr int PJ_MAXN = 190;  // packed (190*191/2) doubles = 145 KB of the 160 KB LDS
@@ -474,21 +476,34 @@ __device__ __forceinline__ int pk(int i, int j, int ne) {
   return i * ne - (i * (i - 1)) / 2 + (j - i);
 }
 
-__device__ int jacobi_packed(int n, double *sA, double *V, bool initV, int *s_top, int *s_bot,
-                             int *s_top2, int *s_bot2, double *s_c, double *s_s, int *s_p,
+// pair t of round rho of the circle method over ne players (p < q)
+__device__ __forceinline__ void circle_pair(int t, int rho, int ne, int &p, int &q) {
+  const int M = ne - 1;
+  int x, y;
+  if (t == 0) {
+    x = rho;
+    y = M;
+  } else {
+    x = rho + t;
+    if (x >= M) x -= M;
+    y = rho - t;
+    if (y < 0) y += M;
+  }
+  p = min(x, y);
+  q = max(x, y);
+}
+
+constexpr int VB = 12;  // eigenvector entries per thread and batch (h n <= 95 * 190 = 12 * 1504)
+__device__ int jacobi_packed(int n, double *sA, double *Vt, bool initV, double *s_c, double *s_s, int *s_p,
                              int *s_q, int *s_cnt, double *s_red) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int ne = (n + 1) & ~1, h = ne / 2;
+  const int ne = (n + 1) & ~1, h = ne / 2, nblk2 = h * (h + 1) / 2;
   if (initV)
-    for (int idx = tid; idx < n * n; idx += nt) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+    for (int idx = tid; idx < n * n; idx += nt) Vt[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   double loc = 0.0;
   for (int idx = tid; idx < ne * (ne + 1) / 2; idx += nt) loc += sA[idx] * sA[idx];
   const double fro2 = block_sum(loc, s_red);
   if (tid == 0) s_red[16] = sqrt(fro2);
-  for (int t = tid; t < h; t += nt) {
-    s_top[t] = 2 * t;
-    s_bot[t] = 2 * t + 1;
-  }
   __syncthreads();
   const double floor_abs = 1e-300 + 1e-18 * s_red[16];
   int sweeps = 0;
@@ -496,9 +511,10 @@ __device__ int jacobi_packed(int n, double *sA, double *V, bool initV, int *s_to
     if (tid == 0) *s_cnt = 0;
     __syncthreads();
     for (int round = 0; round < ne - 1; ++round) {
+      // rotation of each pair of this round
       for (int t = tid; t < h; t += nt) {
-        int p = s_top[t], q = s_bot[t];
-        if (p > q) { int x = p; p = q; q = x; }
+        int p, q;
+        circle_pair(t, round, ne, p, q);
         double c = 1.0, sn = 0.0;
         if (q < n) {
           const double apq = sA[pk(p, q, ne)], app = sA[pk(p, p, ne)], aqq = sA[pk(q, q, ne)];
@@ -514,10 +530,12 @@ __device__ int jacobi_packed(int n, double *sA, double *V, bool initV, int *s_to
         s_p[t] = p; s_q[t] = q; s_c[t] = c; s_s[t] = sn;
       }
       __syncthreads();
-      // 2x2 blocks of A
-      for (int idx = tid; idx < h * h; idx += nt) {
-        const int t1 = idx / h, t2 = idx % h;
-        if (t2 < t1) continue;
+      // 2x2 blocks (t1 <= t2) of A, enumerated over the upper triangle
+      for (int idx = tid; idx < nblk2; idx += nt) {
+        int t2 = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);  // fixed up below
+        while (t2 * (t2 + 1) / 2 > idx) --t2;
+        while ((t2 + 1) * (t2 + 2) / 2 <= idx) ++t2;
+        const int t1 = idx - t2 * (t2 + 1) / 2;
         const double c1 = s_c[t1], s1 = s_s[t1], c2 = s_c[t2], s2 = s_s[t2];
         if (s1 == 0.0 && s2 == 0.0) continue;
         const int p1 = s_p[t1], q1 = s_q[t1], p2 = s_p[t2], q2 = s_q[t2];
@@ -540,26 +558,34 @@ __device__ int jacobi_packed(int n, double *sA, double *V, bool initV, int *s_to
           sA[i11] = s2 * r10 + c2 * r11;
         }
       }
-      // eigenvector columns
-      for (int idx = tid; idx < h * n; idx += nt) {
-        const int t = idx / n, i = idx % n;
-        const double sn = s_s[t];
-        if (sn == 0.0) continue;
-        const int p = s_p[t], q = s_q[t];
-        const double c = s_c[t];
-        const double vp = V[i * n + p], vq = V[i * n + q];
-        V[i * n + p] = c * vp - sn * vq;
-        V[i * n + q] = sn * vp + c * vq;
-      }
-      // next round-robin arrangement (player top[0] fixed), built in parallel
-      for (int t = tid; t < h; t += nt) {
-        s_top2[t] = (t == 0) ? s_top[0] : (t == 1 ? s_bot[0] : s_top[t - 1]);
-        s_bot2[t] = (t == h - 1) ? s_top[h - 1] : s_bot[t + 1];
-      }
-      __syncthreads();
-      for (int t = tid; t < h; t += nt) {
-        s_top[t] = s_top2[t];
-        s_bot[t] = s_bot2[t];
+      // eigenvector rows p and q of each rotated pair (contiguous); all of a
+      // thread's loads are issued before its stores, so one round costs one
+      // memory latency, not one per entry
+      for (int base = tid; base < h * n; base += VB * nt) {
+        double vp[VB], vq[VB];
+        int ip[VB], iq[VB];
+#pragma unroll
+        for (int u = 0; u < VB; ++u) {
+          const int idx = base + u * nt;
+          ip[u] = -1;
+          if (idx < h * n) {
+            const int t = idx / n, i = idx - t * n;
+            if (s_s[t] != 0.0) {
+              ip[u] = s_p[t] * n + i;
+              iq[u] = s_q[t] * n + i;
+              vp[u] = Vt[ip[u]];
+              vq[u] = Vt[iq[u]];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < VB; ++u) {
+          if (ip[u] < 0) continue;
+          const int t = (base + u * nt) / n;
+          const double c = s_c[t], sn = s_s[t];
+          Vt[ip[u]] = c * vp[u] - sn * vq[u];
+          Vt[iq[u]] = sn * vp[u] + c * vq[u];
+        }
       }
       __syncthreads();
     }
@@ -578,8 +604,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__res
                                                       double *__restrict__ D, double *__restrict__ V,
                                                       double *__restrict__ X, int *info) {
   extern __shared__ double sA[];
-  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
-      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
   __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
   __shared__ int s_cnt, s_rank, s_keep[PJ_MAXN];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -598,8 +623,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__res
     sA[pk(i, j, ne)] = v;
   }
   __syncthreads();
-  const int sw = jacobi_packed(m, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q,
-                               &s_cnt, s_red);
+  const int sw = jacobi_packed(m, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
   for (int i = tid; i < m; i += nt) s_sv[i] = sA[pk(i, i, ne)];
   __syncthreads();
   if (tid == 0) {
@@ -615,7 +639,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__res
   for (int idx = tid; idx < m * r; idx += nt) {
     const int i = idx / r, a = idx % r;
     const int c = s_keep[a];
-    X[(int64_t)i * m + a] = V[(int64_t)i * m + c] / sqrt(s_sv[c]);
+    X[(int64_t)i * m + a] = V[(int64_t)c * m + i] / sqrt(s_sv[c]);
   }
   if (tid == 0) {
     info[0] = r;
@@ -639,8 +663,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_reduced_eig(int m, int k, int r
                                                              double *__restrict__ theta,
                                                              double *__restrict__ U, int *info) {
   extern __shared__ double sA[];
-  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
-      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
   __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
   __shared__ int s_cnt, s_sel[PJ_MAXN];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -697,20 +720,19 @@ __global__ void __launch_bounds__(EIG_THREADS) k_reduced_eig(int m, int k, int r
     }
   }
   __syncthreads();
-  const int sw = jacobi_packed(r, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q,
-                               &s_cnt, s_red);
-  // W <- W V (or V)
+  const int sw = jacobi_packed(r, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
+  // W <- W V (or V); V holds the eigenvectors as rows
   if (warm) {
     for (int idx = tid; idx < r * r; idx += nt) {
       const int a = idx / r, b = idx % r;
       double s = 0.0;
-      for (int l = 0; l < r; ++l) s += W[a * r + l] * V[l * r + b];
+      for (int l = 0; l < r; ++l) s += W[a * r + l] * V[b * r + l];
       T1[idx] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < r * r; idx += nt) W[idx] = T1[idx];
   } else {
-    for (int idx = tid; idx < r * r; idx += nt) W[idx] = V[idx];
+    for (int idx = tid; idx < r * r; idx += nt) W[idx] = V[(idx % r) * r + idx / r];
   }
   for (int i = tid; i < r; i += nt) s_sv[i] = sA[pk(i, i, ne)];
   __syncthreads();
@@ -816,13 +838,17 @@ __global__ void k_scale_sym(int m, const double *__restrict__ FA, int ldfa, cons
   const int i = idx / m, j = idx % m;
   S[idx] = D[i] * D[j] * 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]);
 }
-// eigenvalues (unsorted, lam) and eigenvectors V (r x r) of the symmetric C
+// W = V^T (r x r)
+__global__ void k_transpose_small(int r, const double *__restrict__ V, double *__restrict__ W) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < r * r) W[idx] = V[(idx % r) * r + idx / r];
+}
+// eigenvalues (unsorted, lam) and eigenvectors (rows of V, r x r) of the symmetric C
 __global__ void __launch_bounds__(EIG_THREADS) k_jacobi_only(int r, const double *__restrict__ C,
                                                              double *__restrict__ V, double *__restrict__ lam,
                                                              int *info) {
   extern __shared__ double sA[];
-  __shared__ int s_top[PJ_MAXN / 2 + 1], s_bot[PJ_MAXN / 2 + 1], s_top2[PJ_MAXN / 2 + 1],
-      s_bot2[PJ_MAXN / 2 + 1], s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
+  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
   __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32];
   __shared__ int s_cnt;
   const int ne = (r + 1) & ~1;
@@ -832,7 +858,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_jacobi_only(int r, const double
     sA[pk(a, b, ne)] = (a < r && b < r) ? 0.5 * (C[a * r + b] + C[b * r + a]) : 0.0;
   }
   __syncthreads();
-  const int sw = jacobi_packed(r, sA, V, true, s_top, s_bot, s_top2, s_bot2, s_c, s_s, s_p, s_q, &s_cnt, s_red);
+  const int sw = jacobi_packed(r, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
   for (int i = threadIdx.x; i < r; i += blockDim.x) lam[i] = sA[pk(i, i, ne)];
   if (threadIdx.x == 0) {
     info[0] = r;
@@ -887,12 +913,13 @@ int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, co
     gemm_small(r, r, r, T2, r, 0, W, r, 0, T1, r, s);  // T1 = C W
     gemm_small(r, r, r, W, r, 1, T1, r, 0, T2, r, s);  // T2 = W^T C W
   }
+  // V: eigenvectors as rows
   hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, r, T2, V, lam, info);
   if (warm) {
-    gemm_small(r, r, r, W, r, 0, V, r, 0, T1, r, s);  // W <- W V
+    gemm_small(r, r, r, W, r, 0, V, r, 1, T1, r, s);  // W <- W V^T
     if (hipMemcpyAsync(W, T1, sizeof(double) * r * r, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
-  } else if (hipMemcpyAsync(W, V, sizeof(double) * r * r, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-    return -1;
+  } else {
+    hipLaunchKernelGGL(k_transpose_small, dim3((r * r + 255) / 256), dim3(256), 0, s, r, V, W);
   }
   gemm_small(m, r, r, X, m, 0, W, r, 0, T1, r, s);  // X W (m x r)
   hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(256), 0, s, m, k, r, lam, T1, D, theta, U);

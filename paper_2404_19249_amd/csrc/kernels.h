@@ -100,6 +100,9 @@ struct Tiling {
   int32_t *halo_ptr = nullptr, *halo_col = nullptr;
   int32_t *hself = nullptr;  // [nblk] position of the block's first row in its halo
   uint16_t *lcol = nullptr;
+  // [N] slot -> row offset inside its block, rows with more nonzeros first,
+  // so that the rows one wavefront walks together have similar lengths
+  uint8_t *rperm = nullptr;
 };
 // LDS bytes the tiled SpMM needs for k columns of elem-byte values (0 if the
 // tiling cannot serve this shape).  The kernel reads the value and index
@@ -240,6 +243,7 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
 void mg_destroy(Multigrid *mg);
 void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0);
 int mg_levels(const Multigrid *mg);
-int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *red,
+// part: >= 256 doubles of device scratch; sc: >= 5 device doubles (CG scalars)
+int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
            int *iters, double *relres, hipStream_t s);
 }  // namespace ks

@@ -249,6 +249,15 @@ static void basis_tables(int order, int n_q, const double *bary, std::vector<dou
 }
 
 // ---------------------------------------------------------------- helpers
+// Y = A X (B null) or Y = B - A X for an operator on the interior pattern
+// (S, M, K, ...), X, Y, B row-major [N][k]: the halo tiles of the FP64 block
+// solve when they serve k, else the row kernel
+static void spmm_op(ks_ctx *c, const double *val, const double *X, int k, double *Y, const double *B) {
+  if (c->pw64.til && launch_spmm_tiled(c->N, k, *c->pw64.til, c->pw64.til_tb, c->rowptr, val, X, Y, B, c->s) == 0)
+    return;
+  launch_spmm(c->N, c->rowptr, c->col, val, X, k, Y, k, k, B, k, B ? 1 : 0, c->rorder, c->s);
+}
+
 static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *out_host) {
   launch_reduce_cols(part, nblk, nvals, c->mom + 64, c->s);
   HIPCHK(hipMemcpyAsync(out_host, c->mom + 64, sizeof(double) * nvals, hipMemcpyDeviceToHost, c->s));
@@ -525,6 +534,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   // halo tilings (row blocks of consecutive rows in the Morton storage order)
   std::vector<int32_t> t_hptr[ks_ctx::NTILE], t_hcol[ks_ctx::NTILE], t_hself[ks_ctx::NTILE];
   std::vector<uint16_t> t_lcol[ks_ctx::NTILE];
+  std::vector<uint8_t> t_rperm[ks_ctx::NTILE];
   for (int ti = 0; ti < ks_ctx::NTILE; ++ti) {
     const int BR = TILE_BR[ti];
     const int nblk = (N + BR - 1) / BR;
@@ -570,6 +580,17 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       continue;
     }
     c->til[ti].max_nnz = mnz;
+    // within each block: longest rows first (stable), so that a wavefront's
+    // rows have similar nonzero counts
+    t_rperm[ti].resize(N);
+    parallel_for(nblk, [&](int64_t b) {
+      const int r0 = (int)b * BR, nr = std::min(BR, N - r0);
+      uint8_t *o = t_rperm[ti].data() + r0;
+      for (int rr = 0; rr < nr; ++rr) o[rr] = (uint8_t)rr;
+      std::stable_sort(o, o + nr, [&](uint8_t x, uint8_t y) {
+        return rowptr[r0 + x + 1] - rowptr[r0 + x] > rowptr[r0 + y + 1] - rowptr[r0 + y];
+      });
+    });
     t_hcol[ti].resize(t_hptr[ti][nblk]);
     parallel_for(nblk, [&](int64_t b) {
       std::copy(halos[b].begin(), halos[b].end(), t_hcol[ti].begin() + t_hptr[ti][b]);
@@ -820,6 +841,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       A_(til[ti].halo_col, t_hcol[ti].size() + 8);  // 16-byte chunk reads past the end
       A_(til[ti].hself, t_hself[ti].size());
       A_(til[ti].lcol, t_lcol[ti].size() + 16);  // 16-byte chunk reads past the end
+      A_(til[ti].rperm, t_rperm[ti].size());
     }
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
@@ -878,6 +900,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       if (!t_hcol[ti].empty()) H2D(c->til[ti].halo_col, t_hcol[ti].data(), t_hcol[ti].size());
       H2D(c->til[ti].hself, t_hself[ti].data(), t_hself[ti].size());
       if (!t_lcol[ti].empty()) H2D(c->til[ti].lcol, t_lcol[ti].data(), t_lcol[ti].size());
+      H2D(c->til[ti].rperm, t_rperm[ti].data(), t_rperm[ti].size());
     }
   {
     const char *env = std::getenv("KS_ROW_ORDER");
@@ -1252,7 +1275,7 @@ extern "C" int ks_step_energy(ks_ctx *c, double *out) {
   const int k = c->last_k, N = c->N;
   const int64_t nqt = (int64_t)c->n_e * c->n_q;
   // kinetic: 1/2 sum_i f_i psi_i^T K psi_i
-  launch_spmm(N, c->rowptr, c->col, c->K, c->PsiNew, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
+  spmm_op(c, c->K, c->PsiNew, k, c->Wv, nullptr);
   std::vector<double> kd(k);
   const int nb = launch_coldots(N, k, c->PsiNew, c->Wv, c->redpart, s);
   TRY(reduce_small(c, c->redpart, nb, k, kd.data()));
@@ -1302,10 +1325,10 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
   hipStream_t s = c->s;
   const int k = c->last_k, N = c->N, nH = c->N_H, m = nH + k;
   // R = A Psi - M Psi Theta with A the Hamiltonian of the final inner iteration
-  launch_spmm(N, c->rowptr, c->col, c->AL, c->PsiNew, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
+  spmm_op(c, c->AL, c->PsiNew, k, c->Wv, nullptr);
   if (c->last_nonlinear)
-    launch_spmm(N, c->rowptr, c->col, c->MNL, c->PsiNew, k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
-  launch_spmm(N, c->rowptr, c->col, c->M, c->PsiNew, k, c->Xv, k, k, nullptr, 0, 0, c->rorder, s);
+    spmm_op(c, c->MNL, c->PsiNew, k, c->Bv, nullptr);
+  spmm_op(c, c->M, c->PsiNew, k, c->Xv, nullptr);
   HIPCHK(hipMemcpyAsync(c->scal, c->last_theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
   launch_residual_cols(N, k, c->Wv, c->last_nonlinear ? c->Bv : nullptr, c->Xv, c->scal, c->Rv, s);
   // psi_bar_tilde = R (2 F U_tail^T)
@@ -1320,7 +1343,7 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
   launch_gemm_tn(N, nH, k, c->Z, c->mp, c->Gv, k, c->Ctmp, k, c->gwork, c->gwork_n, s);
   launch_small_gemm(nH, k, nH, c->GPPinv, nH, c->Ctmp, k, c->Ttmp, k, 0.0, s);
   launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, 1.0, nullptr, 0, c->Wv, k, s);
-  launch_spmm(N, c->rowptr, c->col, c->M, c->Wv, k, c->Xv, k, k, nullptr, 0, 0, c->rorder, s);
+  spmm_op(c, c->M, c->Wv, k, c->Xv, nullptr);
   launch_combine3((int64_t)N * k, 1.0, c->Gv, -1.0, c->Xv, 0.0, nullptr, c->Rv, s);
   // adjoint boundary value problems S Y = psi_bar_hat (from zero, FP64)
   HIPCHK(hipMemsetAsync(c->Gv, 0, sizeof(double) * N * k, s));
@@ -1532,7 +1555,7 @@ static int batch_prepare(ks_batch *b, const double *const *psi_old, const double
     if (!c->have_S) return fail(KS_ERR_STATE, "system " + std::to_string(i) + " has no assembled operator");
     const int k = b->k[i];
     launch_rows_to_storage(c->N, k, psi_old[i], c->PsiIn, c->int2nat, s);
-    launch_spmm(c->N, c->rowptr, c->col, c->M, c->PsiIn, k, c->Bv, k, k, nullptr, 0, 0, c->rorder, s);
+    spmm_op(c, c->M, c->PsiIn, k, c->Bv, nullptr);
     std::vector<double> sc(k);
     for (int j = 0; j < k; ++j) sc[j] = lambda_host[i][j] + c->mu;
     HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
@@ -1802,8 +1825,8 @@ extern "C" int ks_export_operator(ks_ctx *c, int32_t which, int32_t *row_ptr, in
 // ------------------------------------------------------------ block solve
 static int true_residual(ks_ctx *c, const double *B, const double *X, int k, double *relres,
                          bool *ok) {
-  launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->rorder, c->s);
-  std::vector<double> rn(k), bn(k), tmp((size_t)256 * k);
+  spmm_op(c, c->S, X, k, c->Wv, B);
+  std::vector<double> rn(k), bn(k);
   int nb = launch_colnorms(c->N, k, c->Wv, c->redpart, c->s);
   TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
   nb = launch_colnorms(c->N, k, B, c->redpart, c->s);
@@ -1847,7 +1870,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
     conv = 0;
     for (int ref = 0; ref < max_ref; ++ref) {
       // FP64 residual
-      launch_spmm(c->N, c->rowptr, c->col, c->S, X, k, c->Wv, k, k, B, k, 1, c->rorder, s);
+      spmm_op(c, c->S, X, k, c->Wv, B);
       nb = launch_colnorms(c->N, k, c->Wv, c->redpart, s);
       TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
       loc.refinements = ref + 1;
@@ -1911,7 +1934,7 @@ extern "C" int ks_block_solve_rhs(ks_ctx *c, const double *B, const double *X0, 
 
 // B = M psi diag(lambda + mu)
 static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, int k, double *B) {
-  launch_spmm(c->N, c->rowptr, c->col, c->M, psi, k, B, k, k, nullptr, 0, 0, c->rorder, c->s);
+  spmm_op(c, c->M, psi, k, B, nullptr);
   double sc[MAX_K];
   for (int j = 0; j < k; ++j) sc[j] = lambda_host[j] + c->mu;
   HIPCHK(hipMemcpyAsync(c->scal, sc, sizeof(double) * k, hipMemcpyHostToDevice, c->s));
@@ -1939,7 +1962,7 @@ extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *la
 static int build_tail(ks_ctx *c, const double *psi_hat, int k) {
   hipStream_t s = c->s;
   const int N = c->N, nH = c->N_H;
-  launch_spmm(N, c->rowptr, c->col, c->M, psi_hat, k, c->Wv, k, k, nullptr, 0, 0, c->rorder, s);
+  spmm_op(c, c->M, psi_hat, k, c->Wv, nullptr);
   launch_gemm_tn(N, nH, k, c->Z, c->mp, c->Wv, k, c->Ctmp, k, c->gwork, c->gwork_n, s);
   launch_small_gemm(nH, k, nH, c->GPPinv, nH, c->Ctmp, k, c->Ttmp, k, 0.0, s);
   launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, -1.0, psi_hat, k, c->Z + nH, c->mp, s);

@@ -217,6 +217,19 @@ __global__ void k_invert(int n, const double *__restrict__ a, double *__restrict
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = 1.0 / a[i];
 }
 
+// x = G b for the dense n x n matrix G (row-major): one wavefront per row,
+// lanes striding the row (coalesced), butterfly sum across the wavefront
+__global__ void __launch_bounds__(256) k_dense_matvec(int n, const double *__restrict__ G,
+                                                     const double *__restrict__ b, double *__restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double *g = G + (int64_t)row * n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += g[j] * b[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) x[row] = s;
+}
+
 struct MGLevel {
   int n = 0;
   const int32_t *rp = nullptr, *ci = nullptr;  // operator (level 0: the context's CSR)
@@ -461,7 +474,7 @@ static void mg_smooth(const Multigrid *mg, MGLevel &v, const double *b, bool zer
 static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s) {
   MGLevel &v = mg->lv[l];
   if (l + 1 == (int)mg->lv.size()) {
-    launch_small_gemm(v.n, 1, v.n, mg->coarse_inv, v.n, b, 1, x, 1, 0.0, s);
+    hipLaunchKernelGGL(k_dense_matvec, dim3((v.n + 3) / 4), dim3(256), 0, s, v.n, mg->coarse_inv, b, x);
     return;
   }
   double *xs = v.x;
@@ -478,57 +491,102 @@ static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t
 
 void mg_apply(Multigrid *mg, const double *b, double *x, hipStream_t s) { vcycle(mg, 0, b, x, s); }
 
-// a . b over n values, to the host (fixed-order block partials)
-static int dot(int n, const double *a, const double *b, double *part, double *red, double *out, hipStream_t s) {
-  const int nb = launch_coldots(n, 1, a, b, part, s);
-  launch_reduce_cols(part, nb, 1, red, s);
-  if (hipMemcpyAsync(out, red, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-  if (hipStreamSynchronize(s) != hipSuccess) return -1;
-  return 0;
+// ------------------------------------------------------------ MG-PCG
+// The CG scalars live on the device (sc[]); the host reads back one pair
+// (p.q, r.r) per iteration for the breakdown and stopping tests.
+// sc layout: [0] p.q, [1] r.r, [2] f.f, [3], [4] alternating r.z slots.
+constexpr int MG_NB = 256;  // partial-sum blocks of the vector kernels
+
+// a . b per block (fixed order)
+__global__ void __launch_bounds__(256) k_mg_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                               double *__restrict__ part) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v += a[i] * b[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+// alpha = sc[irz] / sc[0]; x += alpha p; r -= alpha q; per-block r.r
+__global__ void __launch_bounds__(256) k_mg_xr(int n, const double *__restrict__ p, const double *__restrict__ q,
+                                              double *__restrict__ x, double *__restrict__ r,
+                                              const double *__restrict__ sc, int irz, double *__restrict__ part) {
+  __shared__ double sh[16];
+  const double alpha = sc[irz] / sc[0];
+  double v = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v += ri * ri;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+// p = z + (sc[inew] / sc[iold]) p
+__global__ void k_mg_p(int n, const double *__restrict__ z, double *__restrict__ p, const double *__restrict__ sc,
+                       int inew, int iold) {
+  const double beta = sc[inew] / sc[iold];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+}
+static int mg_nb(int n) { return std::max(1, std::min(MG_NB, (n + 255) / 256)); }
+// sc[slot] = a . b (device)
+static void dot_dev(int n, const double *a, const double *b, double *part, double *sc, int slot, hipStream_t s) {
+  const int nb = mg_nb(n);
+  hipLaunchKernelGGL(k_mg_dot, dim3(nb), dim3(256), 0, s, n, a, b, part);
+  launch_reduce_cols(part, nb, 1, sc + slot, s);
+}
+static int read_back(const double *sc, int slot, int cnt, double *h, hipStream_t s) {
+  if (hipMemcpyAsync(h, sc + slot, sizeof(double) * cnt, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : -1;
 }
 
 // CG preconditioned by one V-cycle per iteration on level 0's operator:
 // A x = f from the warm start x, stopped at ||f - A x||_2 <= tol ||f||_2.
-// part / red: device scratch for the dot products.  Returns 0 converged,
-// 1 iteration limit, -1 launch failure, -2 breakdown (p.Ap <= 0).
-int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *red,
+// part: device scratch (>= 256 doubles); sc: device scalars (>= 5 doubles).
+// Returns 0 converged, 1 iteration limit, -1 launch failure, -2 breakdown
+// (p.Ap <= 0).
+int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
            int *iters, double *relres, hipStream_t s) {
   MGLevel &v = mg->lv[0];
-  const int n = v.n;
-  double bb = 0.0, rr = 0.0, rz = 0.0, pq = 0.0;
-  if (dot(n, f, f, part, red, &bb, s) < 0) return -1;
+  const int n = v.n, nb = mg_nb(n);
+  double h[2] = {0.0, 0.0};
   lv_spmv(mg, v, x, mg->pr, f, s);  // r = f - A x
-  if (dot(n, mg->pr, mg->pr, part, red, &rr, s) < 0) return -1;
+  dot_dev(n, f, f, part, sc, 2, s);
+  dot_dev(n, mg->pr, mg->pr, part, sc, 1, s);
+  double bb = 0.0;
+  if (read_back(sc, 1, 2, h, s) < 0) return -1;
+  double rr = h[0];
+  bb = h[1];
   *iters = 0;
   if (!(bb > 0.0)) {
     launch_fill(n, 0.0, x, s);
     *relres = 0.0;
     return 0;
   }
-  if (rr <= tol * tol * bb) {
-    *relres = std::sqrt(rr / bb);
-    return 0;
-  }
+  *relres = std::sqrt(rr / bb);
+  if (rr <= tol * tol * bb) return 0;
   vcycle(mg, 0, mg->pr, mg->pz, s);
   if (hipMemcpyAsync(mg->pp, mg->pz, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
-  if (dot(n, mg->pr, mg->pz, part, red, &rz, s) < 0) return -1;
+  int irz = 3;
+  dot_dev(n, mg->pr, mg->pz, part, sc, irz, s);
   for (int it = 1; it <= max_it; ++it) {
     lv_spmv(mg, v, mg->pp, mg->pq, nullptr, s);  // q = A p
-    if (dot(n, mg->pp, mg->pq, part, red, &pq, s) < 0) return -1;
-    if (!(pq > 0.0)) return -2;
-    const double alpha = rz / pq;
-    launch_axpby(n, alpha, mg->pp, 1.0, x, s);
-    launch_axpby(n, -alpha, mg->pq, 1.0, mg->pr, s);
-    if (dot(n, mg->pr, mg->pr, part, red, &rr, s) < 0) return -1;
+    dot_dev(n, mg->pp, mg->pq, part, sc, 0, s);
+    hipLaunchKernelGGL(k_mg_xr, dim3(nb), dim3(256), 0, s, n, mg->pp, mg->pq, x, mg->pr, sc, irz, part);
+    launch_reduce_cols(part, nb, 1, sc + 1, s);
+    if (read_back(sc, 0, 2, h, s) < 0) return -1;  // p.q, r.r
+    // on breakdown x and r already took the (meaningless) step: the caller
+    // treats -2 as a failed solve
+    if (!(h[0] > 0.0)) return -2;
+    rr = h[1];
     *iters = it;
     *relres = std::sqrt(rr / bb);
     if (rr <= tol * tol * bb) return 0;
     vcycle(mg, 0, mg->pr, mg->pz, s);
-    double rz_new = 0.0;
-    if (dot(n, mg->pr, mg->pz, part, red, &rz_new, s) < 0) return -1;
-    const double beta = rz_new / rz;
-    rz = rz_new;
-    launch_axpby(n, 1.0, mg->pz, beta, mg->pp, s);  // p = z + beta p
+    const int inew = 7 - irz;  // the other r.z slot (3 <-> 4)
+    dot_dev(n, mg->pr, mg->pz, part, sc, inew, s);
+    hipLaunchKernelGGL(k_mg_p, dim3(nb), dim3(256), 0, s, n, mg->pz, mg->pp, sc, inew, irz);
+    irz = inew;
   }
   return 1;
 }

@@ -367,6 +367,7 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
                                                 const int32_t *__restrict__ hself,
                                                 const int32_t *__restrict__ rowptr,
                                                 const uint16_t *__restrict__ lcol,
+                                                const uint8_t *__restrict__ rperm,
                                                 const T *__restrict__ val, const T *__restrict__ P,
                                                 T *__restrict__ Q, double *__restrict__ part,
                                                 const Control *ctl, const T *__restrict__ Bm) {
@@ -426,7 +427,8 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
     const T *vs = reinterpret_cast<const T *>(t_smem + L.vals + ((int64_t)j0 * sizeof(T) - va)) - j0;
     const uint16_t *is = reinterpret_cast<const uint16_t *>(t_smem + L.idx + ((int64_t)j0 * 2 - ia)) - j0;
     const int hs = hself[b];  // halo position of row r0; rows r0.. are consecutive there
-    for (int rr = rslot; active && rr < nr; rr += RPP) {
+    for (int rs = rslot; active && rs < nr; rs += RPP) {
+      const int rr = rperm[r0 + rs];  // longest rows first
       const int row = r0 + rr;
       T acc[VW];
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
@@ -519,7 +521,7 @@ static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, cons
     attr = true;
   }
   hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, t.BR, t.nblk,
-                     t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, val, P, Q, part,
+                     t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, t.rperm, val, P, Q, part,
                      ctl, Bm);
   return 0;
 }
