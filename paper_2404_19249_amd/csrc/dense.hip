@@ -34,7 +34,24 @@ size_t gemm_tn_work_doubles(int N, int ma, int nb) {
 // work[blk][ma_p][nb_p] = sum over the block's rows of Z^T Y.  Wave w owns
 // the 16x16 output tiles w, w + 8, ...; MAXT bounds the tiles per wave so
 // the accumulators stay in registers (static indexing after unrolling).
-template <int MAXT>
+// SYM: Z^T Y is symmetric (Y = H Z for a symmetric H): only the tiles on and
+// above the diagonal are computed
+__device__ __forceinline__ void gemm_tile(int t, int tb_n, bool sym, int &ta, int &tb) {
+  if (!sym) {
+    ta = t / tb_n;
+    tb = t - ta * tb_n;
+    return;
+  }
+  // t-th tile of the upper triangle, row by row: row ta holds tb_n - ta tiles
+  ta = 0;
+  int rem = t;
+  while (rem >= tb_n - ta) {
+    rem -= tb_n - ta;
+    ++ta;
+  }
+  tb = ta + rem;
+}
+template <int MAXT, bool SYM>
 __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, int ma_p, int nb_p,
                                                        const double *__restrict__ Z, int ldz,
                                                        const double *__restrict__ Y, int ldy,
@@ -43,7 +60,7 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
   double *sZ = sm;                       // [GT_ROWS][ma_p]
   double *sY = sm + GT_ROWS * ma_p;      // [GT_ROWS][nb_p]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = GT_THREADS / 64;
-  const int tb_n = nb_p / 16, ntiles = (ma_p / 16) * tb_n;
+  const int tb_n = nb_p / 16, ntiles = SYM ? tb_n * (tb_n + 1) / 2 : (ma_p / 16) * tb_n;
   f64x4 acc[MAXT];
 #pragma unroll
   for (int ti = 0; ti < MAXT; ++ti) acc[ti] = (f64x4){0.0, 0.0, 0.0, 0.0};
@@ -64,7 +81,8 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
     for (int ti = 0; ti < MAXT; ++ti) {
       const int t = wave + ti * nwaves;
       if (t < ntiles) {
-        const int ta = t / tb_n, tb = t % tb_n;
+        int ta, tb;
+        gemm_tile(t, tb_n, SYM, ta, tb);
         f64x4 c = acc[ti];
 #pragma unroll
         for (int kk = 0; kk < GT_ROWS; kk += 4) {
@@ -84,7 +102,8 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
   for (int ti = 0; ti < MAXT; ++ti) {
     const int t = wave + ti * nwaves;
     if (t < ntiles) {
-      const int ta = t / tb_n, tb = t % tb_n;
+      int ta, tb;
+      gemm_tile(t, tb_n, SYM, ta, tb);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = ta * 16 + (lane >> 4) + 4 * r, col = tb * 16 + (lane & 15);
@@ -94,37 +113,53 @@ __global__ void __launch_bounds__(GT_THREADS) k_gemm_tn(int N, int ma, int nb, i
   }
 }
 
+// sym: entries below the diagonal tiles come from their mirror
 __global__ void k_gemm_reduce(int nblk, int ma, int nb, int ma_p, int nb_p,
-                              const double *__restrict__ work, double *__restrict__ C, int ldc) {
+                              const double *__restrict__ work, double *__restrict__ C, int ldc, int sym) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ma * nb) return;
-  const int a = idx / nb, b = idx % nb;
+  int a = idx / nb, b = idx % nb;
+  const int ca = a, cb = b;
+  if (sym && a / 16 > b / 16) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
   double s = 0.0;
   for (int k = 0; k < nblk; ++k) s += work[(int64_t)k * ma_p * nb_p + a * nb_p + b];
-  C[(int64_t)a * ldc + b] = s;
+  C[(int64_t)ca * ldc + cb] = s;
 }
 
-void launch_gemm_tn(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy,
-                    double *C, int ldc, double *work, size_t work_doubles, hipStream_t s) {
+template <bool SYM>
+static void gemm_tn_t(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy, double *C,
+                      int ldc, double *work, hipStream_t s) {
   const int ma_p = pad16(ma), nb_p = pad16(nb);
   const int nblk = gemm_blocks(N);
   int rows_per_blk = (N + nblk - 1) / nblk;
   rows_per_blk = (rows_per_blk + GT_ROWS - 1) / GT_ROWS * GT_ROWS;
   const size_t shm = sizeof(double) * GT_ROWS * (ma_p + nb_p);
-  const int per_wave = ((ma_p / 16) * (nb_p / 16) + 7) / 8;
+  const int tn = nb_p / 16, ntiles = SYM ? tn * (tn + 1) / 2 : (ma_p / 16) * tn;
+  const int per_wave = (ntiles + 7) / 8;
   dim3 g(nblk), b(GT_THREADS);
-  if (per_wave <= 2)
-    hipLaunchKernelGGL(k_gemm_tn<2>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
-  else if (per_wave <= 4)
-    hipLaunchKernelGGL(k_gemm_tn<4>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
-  else if (per_wave <= 8)
-    hipLaunchKernelGGL(k_gemm_tn<8>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
-  else if (per_wave <= 16)
-    hipLaunchKernelGGL(k_gemm_tn<16>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
-  else
-    hipLaunchKernelGGL(k_gemm_tn<32>, g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk);
+#define KS_GT(T) \
+  hipLaunchKernelGGL((k_gemm_tn<T, SYM>), g, b, shm, s, N, ma, nb, ma_p, nb_p, Z, ldz, Y, ldy, work, rows_per_blk)
+  if (per_wave <= 2) KS_GT(2);
+  else if (per_wave <= 4) KS_GT(4);
+  else if (per_wave <= 8) KS_GT(8);
+  else if (per_wave <= 16) KS_GT(16);
+  else KS_GT(32);
+#undef KS_GT
   hipLaunchKernelGGL(k_gemm_reduce, dim3((ma * nb + 255) / 256), dim3(256), 0, s, nblk, ma, nb, ma_p,
-                     nb_p, work, C, ldc);
+                     nb_p, work, C, ldc, SYM ? 1 : 0);
+}
+void launch_gemm_tn(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy,
+                    double *C, int ldc, double *work, size_t work_doubles, hipStream_t s) {
+  (void)work_doubles;
+  gemm_tn_t<false>(N, ma, nb, Z, ldz, Y, ldy, C, ldc, work, s);
+}
+void launch_gemm_tn_sym(int N, int m, const double *Z, int ldz, const double *Y, int ldy, double *C, int ldc,
+                        double *work, hipStream_t s) {
+  gemm_tn_t<true>(N, m, m, Z, ldz, Y, ldy, C, ldc, work, s);
 }
 
 // ------------------------------------------------------------ ELL-4 P
@@ -167,12 +202,51 @@ __global__ void k_zu(int N, const int32_t *__restrict__ Pidx, const double *__re
   for (int a = 0; a < kt; ++a) s += zr[a] * U[(int64_t)(n_H + a) * k + j];
   Psi[t] = s;
 }
+// The same with U staged in LDS and four output columns per lane (k % 4 == 0,
+// (n_H + kt) k doubles <= 64 KB): the Z row a lane group shares is read once
+// per four columns.
+__global__ void __launch_bounds__(256) k_zu4(int N, const int32_t *__restrict__ Pidx, const double *__restrict__ Pw,
+                                             int n_H, const double *__restrict__ Z, int ldz, int kt,
+                                             const double *__restrict__ U, int k, double *__restrict__ Psi) {
+  extern __shared__ double s_u[];  // [(n_H + kt)][k]
+  const int m = n_H + kt;
+  for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) s_u[idx] = U[idx];
+  __syncthreads();
+  const int CG = k / 4;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * CG) return;
+  const int i = (int)(t / CG), c0 = (int)(t - (int64_t)i * CG) * 4;
+  f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int id = Pidx[4 * (int64_t)i + c];
+    if (id >= 0) {
+      const double w = Pw[4 * (int64_t)i + c];
+      const f64x4 u = *reinterpret_cast<const f64x4 *>(s_u + id * k + c0);
+      acc += w * u;
+    }
+  }
+  const double *zr = Z + (int64_t)i * ldz + n_H;
+  for (int a = 0; a < kt; ++a) {
+    const double z = zr[a];
+    const f64x4 u = *reinterpret_cast<const f64x4 *>(s_u + (n_H + a) * k + c0);
+    acc += z * u;
+  }
+  *reinterpret_cast<f64x4 *>(Psi + (int64_t)i * k + c0) = acc;
+}
 void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const double *Z, int ldz, int kt,
                const double *U, int k, double *Psi, hipStream_t s) {
   int64_t n = (int64_t)N * k;
-  if (n > 0)
-    hipLaunchKernelGGL(k_zu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, Pidx, Pw, n_H, Z,
-                       ldz, kt, U, k, Psi);
+  if (n <= 0) return;
+  const size_t lds = sizeof(double) * (size_t)(n_H + kt) * k;
+  if (k % 4 == 0 && lds <= 65536) {
+    const int64_t nt = (int64_t)N * (k / 4);
+    hipLaunchKernelGGL(k_zu4, dim3((unsigned)((nt + 255) / 256)), dim3(256), lds, s, N, Pidx, Pw, n_H, Z, ldz,
+                       kt, U, k, Psi);
+    return;
+  }
+  hipLaunchKernelGGL(k_zu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, Pidx, Pw, n_H, Z,
+                     ldz, kt, U, k, Psi);
 }
 
 __global__ void k_small_gemm(int m, int n, int p, const double *__restrict__ A, int lda,
@@ -463,13 +537,22 @@ __global__ void __launch_bounds__(EIG_THREADS) k_small_eig(int m, int k, const d
 // circle method (player ne - 1 stays, the others turn), each round rotating
 // ne/2 disjoint pairs at once: every 2x2 block (pair t1 rows, pair t2
 // columns), t1 <= t2, is transformed by J1^T B J2 by one thread, so a round
-// has no read/write conflicts.  Eigenvectors are accumulated as the ROWS of
-// Vt (global, ld = n; Vt[p][i] = entry i of eigenvector p), so a rotation
-// updates two contiguous rows.  A pair is rotated while
+// has no read/write conflicts.  The eigenvectors are not accumulated here:
+// each round's (cos, sin) per pair goes to a log in global memory (written,
+// never read back by this kernel), and k_apply_rot replays the log on the
+// rows of a matrix over many workgroups.  A pair is rotated while
 // |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and above an absolute floor; the sweep
 // loop stops after a sweep without rotations.
 constexpr int PJ_MAXN = 190;  // packed (190*191/2) doubles = 145 KB of the 160 KB LDS
 constexpr int PJ_PACK = (PJ_MAXN * (PJ_MAXN + 1)) / 2;
+constexpr int JAC_MAX_SWEEPS = 60;
+
+// doubles of the rotation log for order n: (cos, sin) per pair, round, sweep
+__host__ __device__ inline size_t jacobi_log_doubles(int n) {
+  const size_t ne = (size_t)((n + 1) & ~1);
+  return 2 * (size_t)JAC_MAX_SWEEPS * (ne - 1) * (ne / 2);
+}
+size_t jacobi_work_doubles(int m) { return jacobi_log_doubles(m) + 2 * (size_t)m + 64; }
 
 __device__ __forceinline__ int pk(int i, int j, int ne) {
   if (i > j) { int t = i; i = j; j = t; }
@@ -493,24 +576,53 @@ __device__ __forceinline__ void circle_pair(int t, int rho, int ne, int &p, int 
   q = max(x, y);
 }
 
-constexpr int VB = 12;  // eigenvector entries per thread and batch (h n <= 95 * 190 = 12 * 1504)
-__device__ int jacobi_packed(int n, double *sA, double *Vt, bool initV, double *s_c, double *s_s, int *s_p,
-                             int *s_q, int *s_cnt, double *s_red) {
+// a rotation of pair (p, q) is due: |a_pq| above the relative threshold and
+// the absolute floor
+__device__ __forceinline__ bool rot_due(double apq, double app, double aqq, double floor_abs) {
+  return fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs;
+}
+
+// Returns the number of sweeps run (all of them rotated and are in the log).
+// Before each sweep every pair is tested at once: a sweep starting with no
+// pair due would rotate nothing, so the loop ends there without running it.
+constexpr int JB_MAX = 5;  // 2x2 blocks per thread of the 1024-thread workgroup
+static_assert((PJ_MAXN / 2) * (PJ_MAXN / 2 + 1) / 2 <= JB_MAX * EIG_THREADS, "2x2 blocks per thread");
+__device__ int jacobi_packed(int n, double *sA, double2 *__restrict__ rot, double2 *s_cs, int2 *s_pq, int *s_cnt,
+                             double *s_red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ne = (n + 1) & ~1, h = ne / 2, nblk2 = h * (h + 1) / 2;
-  if (initV)
-    for (int idx = tid; idx < n * n; idx += nt) Vt[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   double loc = 0.0;
   for (int idx = tid; idx < ne * (ne + 1) / 2; idx += nt) loc += sA[idx] * sA[idx];
   const double fro2 = block_sum(loc, s_red);
   if (tid == 0) s_red[16] = sqrt(fro2);
+  // this thread's 2x2 blocks (t1 <= t2), enumerated over the upper triangle
+  int nb = 0, bt1[JB_MAX], bt2[JB_MAX];
+  for (int idx = tid; idx < nblk2 && nb < JB_MAX; idx += nt) {
+    int t2 = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);  // fixed up below
+    while (t2 * (t2 + 1) / 2 > idx) --t2;
+    while ((t2 + 1) * (t2 + 2) / 2 <= idx) ++t2;
+    bt1[nb] = idx - t2 * (t2 + 1) / 2;
+    bt2[nb] = t2;
+    ++nb;
+  }
   __syncthreads();
   const double floor_abs = 1e-300 + 1e-18 * s_red[16];
   int sweeps = 0;
-  for (; sweeps < 60; ++sweeps) {
+  for (; sweeps < JAC_MAX_SWEEPS; ++sweeps) {
+    // any pair due?
     if (tid == 0) *s_cnt = 0;
     __syncthreads();
+    bool any = false;
+    for (int idx = tid; idx < n * n && !any; idx += nt) {
+      const int p = idx / n, q = idx - p * n;
+      if (q > p) any = rot_due(sA[pk(p, q, ne)], sA[pk(p, p, ne)], sA[pk(q, q, ne)], floor_abs);
+    }
+    if (any) *s_cnt = 1;
+    __syncthreads();
+    const int cnt = *s_cnt;
+    if (cnt == 0) break;
     for (int round = 0; round < ne - 1; ++round) {
+      double2 *lg = rot + ((size_t)sweeps * (ne - 1) + round) * h;
       // rotation of each pair of this round
       for (int t = tid; t < h; t += nt) {
         int p, q;
@@ -518,27 +630,26 @@ __device__ int jacobi_packed(int n, double *sA, double *Vt, bool initV, double *
         double c = 1.0, sn = 0.0;
         if (q < n) {
           const double apq = sA[pk(p, q, ne)], app = sA[pk(p, p, ne)], aqq = sA[pk(q, q, ne)];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) {
+          if (rot_due(apq, app, aqq, floor_abs)) {
             const double th = (aqq - app) / (2.0 * apq);
             const double tt = fabs(th) > 1e150 ? 0.5 / th
                                                : (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
             sn = tt * c;
-            atomicAdd(s_cnt, 1);
           }
         }
-        s_p[t] = p; s_q[t] = q; s_c[t] = c; s_s[t] = sn;
+        s_cs[t] = make_double2(c, sn);
+        s_pq[t] = make_int2(p, q);
+        lg[t] = make_double2(c, sn);
       }
       __syncthreads();
-      // 2x2 blocks (t1 <= t2) of A, enumerated over the upper triangle
-      for (int idx = tid; idx < nblk2; idx += nt) {
-        int t2 = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);  // fixed up below
-        while (t2 * (t2 + 1) / 2 > idx) --t2;
-        while ((t2 + 1) * (t2 + 2) / 2 <= idx) ++t2;
-        const int t1 = idx - t2 * (t2 + 1) / 2;
-        const double c1 = s_c[t1], s1 = s_s[t1], c2 = s_c[t2], s2 = s_s[t2];
+      for (int b = 0; b < nb; ++b) {
+        const int t1 = bt1[b], t2 = bt2[b];
+        const double2 r1 = s_cs[t1], r2 = s_cs[t2];
+        const int2 i1 = s_pq[t1], i2 = s_pq[t2];
+        const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
         if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p1 = s_p[t1], q1 = s_q[t1], p2 = s_p[t2], q2 = s_q[t2];
+        const int p1 = i1.x, q1 = i1.y, p2 = i2.x, q2 = i2.y;
         if (t1 == t2) {
           const int ipp = pk(p1, p1, ne), iqq = pk(q1, q1, ne), ipq = pk(p1, q1, ne);
           const double app = sA[ipp], aqq = sA[iqq], apq = sA[ipq];
@@ -558,55 +669,77 @@ __device__ int jacobi_packed(int n, double *sA, double *Vt, bool initV, double *
           sA[i11] = s2 * r10 + c2 * r11;
         }
       }
-      // eigenvector rows p and q of each rotated pair (contiguous); all of a
-      // thread's loads are issued before its stores, so one round costs one
-      // memory latency, not one per entry
-      for (int base = tid; base < h * n; base += VB * nt) {
-        double vp[VB], vq[VB];
-        int ip[VB], iq[VB];
-#pragma unroll
-        for (int u = 0; u < VB; ++u) {
-          const int idx = base + u * nt;
-          ip[u] = -1;
-          if (idx < h * n) {
-            const int t = idx / n, i = idx - t * n;
-            if (s_s[t] != 0.0) {
-              ip[u] = s_p[t] * n + i;
-              iq[u] = s_q[t] * n + i;
-              vp[u] = Vt[ip[u]];
-              vq[u] = Vt[iq[u]];
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < VB; ++u) {
-          if (ip[u] < 0) continue;
-          const int t = (base + u * nt) / n;
-          const double c = s_c[t], sn = s_s[t];
-          Vt[ip[u]] = c * vp[u] - sn * vq[u];
-          Vt[iq[u]] = sn * vp[u] + c * vq[u];
-        }
-      }
       __syncthreads();
     }
-    const int cnt = *s_cnt;
-    __syncthreads();
-    if (cnt == 0) break;
   }
   return sweeps;
 }
 
+// W <- W J_1 J_2 ... : the first nsw logged sweeps of rotations, in order,
+// applied to the columns of W (n x n, row-major; the identity first when
+// init).  Rows are independent, so each workgroup rotates its own block of
+// R = 1024 / (ne/2) rows in LDS; per round, thread (row slot, pair) updates
+// two entries, and the next round's (cos, sin) is loaded ahead.
+constexpr int AR_THREADS = 1024;
+__global__ void __launch_bounds__(AR_THREADS) k_apply_rot(int n, const int *__restrict__ nsw_ptr,
+                                                          const double2 *__restrict__ rot, double *__restrict__ W,
+                                                          int init) {
+  __shared__ double sW[2 * AR_THREADS];  // R n <= (1024 / h) 2h
+  const int ne = (n + 1) & ~1, h = ne / 2, R = AR_THREADS / h;
+  const int row0 = blockIdx.x * R, tid = threadIdx.x;
+  for (int idx = tid; idx < R * n; idx += blockDim.x) {
+    const int i = row0 + idx / n, j = idx % n;
+    double v = 0.0;
+    if (i < n) v = init ? (i == j ? 1.0 : 0.0) : W[(int64_t)i * n + j];
+    sW[idx] = v;
+  }
+  __syncthreads();
+  const int slot = tid / h, t = tid - slot * h;
+  const bool act = slot < R && row0 + slot < n;
+  const int nrounds = min(*nsw_ptr, JAC_MAX_SWEEPS) * (ne - 1);
+  double *w = sW + slot * n;
+  double2 cs = make_double2(1.0, 0.0);
+  if (act && nrounds > 0) cs = rot[t];
+  int round = 0;
+  for (int g = 0; g < nrounds; ++g) {
+    double2 nx = make_double2(1.0, 0.0);
+    if (act && g + 1 < nrounds) nx = rot[(size_t)(g + 1) * h + t];
+    if (act && cs.y != 0.0) {
+      int p, q;
+      circle_pair(t, round, ne, p, q);  // q < n whenever the sine is nonzero
+      const double wp = w[p], wq = w[q];
+      w[p] = cs.x * wp - cs.y * wq;
+      w[q] = cs.y * wp + cs.x * wq;
+    }
+    __syncthreads();
+    cs = nx;
+    if (++round == ne - 1) round = 0;
+  }
+  for (int idx = tid; idx < R * n; idx += blockDim.x) {
+    const int i = row0 + idx / n;
+    if (i < n) W[(int64_t)i * n + idx % n] = sW[idx];
+  }
+}
+static void apply_rot(int n, const int *nsw, const double *rot, double *W, int init, hipStream_t s) {
+  const int h = ((n + 1) & ~1) / 2, R = AR_THREADS / h;
+  hipLaunchKernelGGL(k_apply_rot, dim3((n + R - 1) / R), dim3(AR_THREADS), 0, s, n, nsw,
+                     reinterpret_cast<const double2 *>(rot), W, init);
+}
+
 // Canonical orthogonalisation of F_B (once per augmented space):
 // D = diag(F_B)^{-1/2}, D F_B D = V s V^T, X = V_keep s_keep^{-1/2} (keep
-// s > 1e-12 s_max), X stored [m][r] with ld m.  info[0] = r, info[2] = 1 on a
-// non-positive diagonal, info[3] = sweeps.
+// s > 1e-12 s_max), X stored [m][r] with ld m.  k_orth (one workgroup) runs
+// the Jacobi and selects the kept pairs (s and the kept indices to the tail
+// of work); k_apply_rot forms V; k_orth_x forms X.  info[0] = r, info[2] = 1
+// on a non-positive diagonal, info[3] = sweeps.
 __global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__restrict__ FB, int ldfb,
-                                                      double *__restrict__ D, double *__restrict__ V,
-                                                      double *__restrict__ X, int *info) {
+                                                      double *__restrict__ D, double *__restrict__ work,
+                                                      int *info) {
   extern __shared__ double sA[];
-  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
-  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
-  __shared__ int s_cnt, s_rank, s_keep[PJ_MAXN];
+  __shared__ double2 s_cs[PJ_MAXN / 2 + 1];
+  __shared__ int2 s_pq[PJ_MAXN / 2 + 1];
+  __shared__ double s_red[32], s_sv[PJ_MAXN];
+  __shared__ int s_cnt;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ne = (m + 1) & ~1;
   for (int i = tid; i < m; i += nt) {
@@ -623,151 +756,32 @@ __global__ void __launch_bounds__(EIG_THREADS) k_orth(int m, const double *__res
     sA[pk(i, j, ne)] = v;
   }
   __syncthreads();
-  const int sw = jacobi_packed(m, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
+  const int sw = jacobi_packed(m, sA, reinterpret_cast<double2 *>(work), s_cs, s_pq, &s_cnt, s_red);
   for (int i = tid; i < m; i += nt) s_sv[i] = sA[pk(i, i, ne)];
   __syncthreads();
+  double *sv = work + jacobi_log_doubles(m);
+  int *keep = reinterpret_cast<int *>(sv + m);
+  for (int i = tid; i < m; i += nt) sv[i] = s_sv[i];
   if (tid == 0) {
     double smax = 0.0;
     for (int i = 0; i < m; ++i) smax = fmax(smax, s_sv[i]);
     int r = 0;
     for (int i = 0; i < m; ++i)
-      if (s_sv[i] > 1e-12 * smax) s_keep[r++] = i;
-    s_rank = r;
-  }
-  __syncthreads();
-  const int r = s_rank;
-  for (int idx = tid; idx < m * r; idx += nt) {
-    const int i = idx / r, a = idx % r;
-    const int c = s_keep[a];
-    X[(int64_t)i * m + a] = V[(int64_t)c * m + i] / sqrt(s_sv[c]);
-  }
-  if (tid == 0) {
+      if (s_sv[i] > 1e-12 * smax) keep[r++] = i;
     info[0] = r;
     info[3] = sw;
   }
 }
-
-// Lowest k eigenpairs of the pencil with F_B already orthogonalised by
-// k_orth: C = X^T (D F_A D) X (r x r), optionally rotated by the previous
-// eigenvector matrix W (warm start: C <- W^T C W), Jacobi, W <- W V, ascending
-// order, U = D X W_sel with the largest-magnitude entry of each column
-// positive.  W (r x r, ld r) is in/out; theta [r].
-__global__ void __launch_bounds__(EIG_THREADS) k_reduced_eig(int m, int k, int r,
-                                                             const double *__restrict__ FA, int ldfa,
-                                                             const double *__restrict__ D,
-                                                             const double *__restrict__ X,
-                                                             double *__restrict__ W, int warm,
-                                                             double *__restrict__ T1,
-                                                             double *__restrict__ T2,
-                                                             double *__restrict__ V,
-                                                             double *__restrict__ theta,
-                                                             double *__restrict__ U, int *info) {
-  extern __shared__ double sA[];
-  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
-  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32], s_sv[PJ_MAXN];
-  __shared__ int s_cnt, s_sel[PJ_MAXN];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int ne = (r + 1) & ~1;
-  // T1 = (D FA D) X   (m x r, ld r)
-  for (int idx = tid; idx < m * r; idx += nt) {
-    const int i = idx / r, a = idx % r;
-    double s = 0.0;
-    for (int j = 0; j < m; ++j)
-      s += 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]) * D[j] * X[(int64_t)j * m + a];
-    T1[idx] = D[i] * s;
-  }
-  __syncthreads();
-  // C = X^T T1 (r x r) into T2, symmetrised
-  for (int idx = tid; idx < r * r; idx += nt) {
-    const int a = idx / r, b = idx % r;
-    if (b < a) continue;
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < m; ++i) {
-      s1 += X[(int64_t)i * m + a] * T1[i * r + b];
-      s2 += X[(int64_t)i * m + b] * T1[i * r + a];
-    }
-    T2[a * r + b] = T2[b * r + a] = 0.5 * (s1 + s2);
-  }
-  __syncthreads();
-  if (warm) {
-    // T1 = C W ; C' = W^T T1 (packed into LDS)
-    for (int idx = tid; idx < r * r; idx += nt) {
-      const int a = idx / r, b = idx % r;
-      double s = 0.0;
-      for (int l = 0; l < r; ++l) s += T2[a * r + l] * W[l * r + b];
-      T1[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += nt) {
-      const int a = idx / ne, b = idx % ne;
-      if (b < a) continue;
-      double v = 0.0;
-      if (a < r && b < r) {
-        double s1 = 0.0, s2 = 0.0;
-        for (int l = 0; l < r; ++l) {
-          s1 += W[l * r + a] * T1[l * r + b];
-          s2 += W[l * r + b] * T1[l * r + a];
-        }
-        v = 0.5 * (s1 + s2);
-      }
-      sA[pk(a, b, ne)] = v;
-    }
-  } else {
-    for (int idx = tid; idx < ne * ne; idx += nt) {
-      const int a = idx / ne, b = idx % ne;
-      if (b < a) continue;
-      sA[pk(a, b, ne)] = (a < r && b < r) ? T2[a * r + b] : 0.0;
-    }
-  }
-  __syncthreads();
-  const int sw = jacobi_packed(r, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
-  // W <- W V (or V); V holds the eigenvectors as rows
-  if (warm) {
-    for (int idx = tid; idx < r * r; idx += nt) {
-      const int a = idx / r, b = idx % r;
-      double s = 0.0;
-      for (int l = 0; l < r; ++l) s += W[a * r + l] * V[b * r + l];
-      T1[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < r * r; idx += nt) W[idx] = T1[idx];
-  } else {
-    for (int idx = tid; idx < r * r; idx += nt) W[idx] = V[(idx % r) * r + idx / r];
-  }
-  for (int i = tid; i < r; i += nt) s_sv[i] = sA[pk(i, i, ne)];
-  __syncthreads();
-  for (int i = tid; i < r; i += nt) {
-    const double v = s_sv[i];
-    int rk = 0;
-    for (int j = 0; j < r; ++j) rk += (s_sv[j] < v) || (s_sv[j] == v && j < i);
-    s_sel[rk] = i;
-  }
-  __syncthreads();
-  for (int i = tid; i < r; i += nt) theta[i] = s_sv[s_sel[i]];
-  for (int idx = tid; idx < m * k; idx += nt) {
-    const int i = idx / k, j = idx % k;
-    double s = 0.0;
-    if (j < r) {
-      const int c = s_sel[j];
-      for (int a = 0; a < r; ++a) s += X[(int64_t)i * m + a] * W[a * r + c];
-    }
-    U[idx] = D[i] * s;
-  }
-  __syncthreads();
-  for (int j = tid; j < k; j += nt) {
-    int im = 0;
-    double vm = -1.0;
-    for (int i = 0; i < m; ++i) {
-      const double a = fabs(U[i * k + j]);
-      if (a > vm) { vm = a; im = i; }
-    }
-    if (U[im * k + j] < 0.0)
-      for (int i = 0; i < m; ++i) U[i * k + j] = -U[i * k + j];
-  }
-  if (tid == 0) {
-    info[0] = r;
-    info[1] = sw;
-  }
+// X[i][a] = V[i][keep[a]] / sqrt(s[keep[a]]) for a < r = info[0]
+__global__ void k_orth_x(int m, const double *__restrict__ V, const double *__restrict__ work,
+                         const int *__restrict__ info, double *__restrict__ X) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = info[0];
+  if (idx >= m * r) return;
+  const double *sv = work + jacobi_log_doubles(m);
+  const int *keep = reinterpret_cast<const int *>(sv + m);
+  const int i = idx / r, a = idx % r, c = keep[a];
+  X[(int64_t)i * m + a] = V[(int64_t)i * m + c] / sqrt(sv[c]);
 }
 
 size_t orth_shared_bytes(int m) {
@@ -781,33 +795,25 @@ static int enable_big_lds() {
   if (lds_ready) return 0;
   const int bytes = (int)orth_shared_bytes(PJ_MAXN);
   if (hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
-          hipSuccess ||
-      hipFuncSetAttribute((const void *)k_reduced_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          bytes) != hipSuccess)
+      hipSuccess)
     return -1;
   lds_ready = 1;
   return 0;
 }
-int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, int *info,
+int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, double *work, int *info,
                 hipStream_t s) {
   if (enable_big_lds() < 0) return -1;
-  hipLaunchKernelGGL(k_orth, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(m), s, m, FB, ldfb, D, V, X,
-                     info);
-  return 0;
-}
-int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const double *D,
-                       const double *X, double *W, int warm, double *T1, double *T2, double *V,
-                       double *theta, double *U, int *info, hipStream_t s) {
-  if (enable_big_lds() < 0) return -1;
-  hipLaunchKernelGGL(k_reduced_eig, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, m, k, r, FA,
-                     ldfa, D, X, W, warm, T1, T2, V, theta, U, info);
+  hipLaunchKernelGGL(k_orth, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(m), s, m, FB, ldfb, D, work, info);
+  apply_rot(m, info + 3, work, V, 1, s);
+  hipLaunchKernelGGL(k_orth_x, dim3((m * m + 255) / 256), dim3(256), 0, s, m, V, work, info, X);
   return 0;
 }
 
 // ---------------------------------------- reduced eigensolve, split form
 // The dense products around the Jacobi iteration (r <= 190) run as
-// one-thread-per-entry kernels over many workgroups; only the Jacobi
-// iteration itself is one workgroup.
+// one-thread-per-entry kernels over many workgroups, the eigenvector
+// accumulation as the rotation replay; only the Jacobi iteration on the
+// matrix itself is one workgroup.
 
 // C = op(A) op(B) + beta C, op = transpose when t* != 0 (row-major, small)
 __global__ void k_gemm_small(int m, int n, int p, const double *__restrict__ A, int lda, int ta,
@@ -838,18 +844,14 @@ __global__ void k_scale_sym(int m, const double *__restrict__ FA, int ldfa, cons
   const int i = idx / m, j = idx % m;
   S[idx] = D[i] * D[j] * 0.5 * (FA[(int64_t)i * ldfa + j] + FA[(int64_t)j * ldfa + i]);
 }
-// W = V^T (r x r)
-__global__ void k_transpose_small(int r, const double *__restrict__ V, double *__restrict__ W) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < r * r) W[idx] = V[(idx % r) * r + idx / r];
-}
-// eigenvalues (unsorted, lam) and eigenvectors (rows of V, r x r) of the symmetric C
+// eigenvalues (unsorted, lam) of the symmetric C; rotations to the log
 __global__ void __launch_bounds__(EIG_THREADS) k_jacobi_only(int r, const double *__restrict__ C,
-                                                             double *__restrict__ V, double *__restrict__ lam,
+                                                             double *__restrict__ rot, double *__restrict__ lam,
                                                              int *info) {
   extern __shared__ double sA[];
-  __shared__ int s_p[PJ_MAXN / 2 + 1], s_q[PJ_MAXN / 2 + 1];
-  __shared__ double s_c[PJ_MAXN / 2 + 1], s_s[PJ_MAXN / 2 + 1], s_red[32];
+  __shared__ double2 s_cs[PJ_MAXN / 2 + 1];
+  __shared__ int2 s_pq[PJ_MAXN / 2 + 1];
+  __shared__ double s_red[32];
   __shared__ int s_cnt;
   const int ne = (r + 1) & ~1;
   for (int idx = threadIdx.x; idx < ne * ne; idx += blockDim.x) {
@@ -858,7 +860,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_jacobi_only(int r, const double
     sA[pk(a, b, ne)] = (a < r && b < r) ? 0.5 * (C[a * r + b] + C[b * r + a]) : 0.0;
   }
   __syncthreads();
-  const int sw = jacobi_packed(r, sA, V, true, s_c, s_s, s_p, s_q, &s_cnt, s_red);
+  const int sw = jacobi_packed(r, sA, reinterpret_cast<double2 *>(rot), s_cs, s_pq, &s_cnt, s_red);
   for (int i = threadIdx.x; i < r; i += blockDim.x) lam[i] = sA[pk(i, i, ne)];
   if (threadIdx.x == 0) {
     info[0] = r;
@@ -896,7 +898,7 @@ __global__ void __launch_bounds__(256) k_eig_select(int m, int k, int r, const d
   }
 }
 int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, const double *D, const double *X,
-                             double *W, int warm, double *S, double *T1, double *T2, double *V, double *lam,
+                             double *W, int warm, double *S, double *T1, double *T2, double *work, double *lam,
                              double *theta, double *U, int *info, hipStream_t s) {
   if (enable_big_lds() < 0) return -1;
   static bool attr = false;
@@ -913,14 +915,8 @@ int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, co
     gemm_small(r, r, r, T2, r, 0, W, r, 0, T1, r, s);  // T1 = C W
     gemm_small(r, r, r, W, r, 1, T1, r, 0, T2, r, s);  // T2 = W^T C W
   }
-  // V: eigenvectors as rows
-  hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, r, T2, V, lam, info);
-  if (warm) {
-    gemm_small(r, r, r, W, r, 0, V, r, 1, T1, r, s);  // W <- W V^T
-    if (hipMemcpyAsync(W, T1, sizeof(double) * r * r, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
-  } else {
-    hipLaunchKernelGGL(k_transpose_small, dim3((r * r + 255) / 256), dim3(256), 0, s, r, V, W);
-  }
+  hipLaunchKernelGGL(k_jacobi_only, dim3(1), dim3(EIG_THREADS), orth_shared_bytes(r), s, r, T2, work, lam, info);
+  apply_rot(r, info + 1, work, W, warm ? 0 : 1, s);  // W <- W V (or V)
   gemm_small(m, r, r, X, m, 0, W, r, 0, T1, r, s);  // X W (m x r)
   hipLaunchKernelGGL(k_eig_select, dim3(1), dim3(256), 0, s, m, k, r, lam, T1, D, theta, U);
   return 0;

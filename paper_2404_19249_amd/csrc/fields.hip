@@ -43,62 +43,68 @@ void launch_vext(const double *coords, const int32_t *elems, int n_loc, int n_e,
                        n_loc, n_e, n_q, bary, n_atoms, Z, R, out);
 }
 
-// rho_q = sum_i f_i (sum_a phi_qa X[dof_a][i])^2.  One lane per (element,
-// orbital): LPE = the next power of two >= k lanes per element (the orbital
-// rows of a node are contiguous, so the gathers of an element are coalesced),
-// EPW = 64 / LPE elements per wave; the per-point sums over orbitals are
-// butterfly shuffles inside each lane group, in a fixed order.
-template <int NLOC, int NQ>
+// rho_q = sum_i f_i (sum_a phi_qa X[node_a][i])^2, one lane per (element,
+// quadrature point): a block first stages its elements' nodal rows (all k
+// orbitals of each node, coalesced) in LDS; each lane then runs over the
+// orbitals with the element's values read as LDS broadcasts.  LPE lanes per
+// element (>= NQ), EPB = 256 / LPE elements per block.
+template <int NLOC, int NQ, int LPE>
 __global__ void __launch_bounds__(256) k_density(const int32_t *__restrict__ edof, int n_e,
                                                  const double *__restrict__ phi,
                                                  const double *__restrict__ X, int ldx, int k,
                                                  const double *__restrict__ occ,
-                                                 double *__restrict__ rho, int LPE) {
-  __shared__ double s_phi[NQ * NLOC];
-  for (int i = threadIdx.x; i < NQ * NLOC; i += blockDim.x) s_phi[i] = phi[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int EPW = 64 / LPE;
-  const int es = lane / LPE, i = lane - es * LPE;
-  const int e = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * EPW + es;
-  const bool ok = e < n_e;                 // uniform across a lane group
-  const bool own = ok && i < k;
-  double xa[NLOC];
-#pragma unroll
-  for (int a = 0; a < NLOC; ++a) {
-    const int d = ok ? edof[(int64_t)e * NLOC + a] : -1;
-    xa[a] = (own && d >= 0) ? X[(int64_t)d * ldx + i] : 0.0;
+                                                 double *__restrict__ rho) {
+  constexpr int EPB = 256 / LPE;
+  extern __shared__ double s_x[];  // [EPB][NLOC][k], then occ [k]
+  const int nk = NLOC * k;
+  const int e0 = blockIdx.x * EPB;
+  for (int idx = threadIdx.x; idx < EPB * nk; idx += blockDim.x) {
+    const int el = idx / nk, r = idx - el * nk, a = r / k, i = r - a * k;
+    const int e = e0 + el;
+    double v = 0.0;
+    if (e < n_e) {
+      const int d = edof[(int64_t)e * NLOC + a];
+      if (d >= 0) v = X[(int64_t)d * ldx + i];
+    }
+    s_x[idx] = v;
   }
-  const double f = own ? occ[i] : 0.0;
-  double mine = 0.0;  // lane i < NQ keeps point i's sum
+  double *s_occ = s_x + EPB * nk;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) s_occ[i] = occ[i];
+  __syncthreads();
+  const int el = threadIdx.x / LPE, q = threadIdx.x - el * LPE, e = e0 + el;
+  if (q >= NQ || e >= n_e) return;
+  double ph[NLOC];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int a = 0; a < NLOC; ++a) ph[a] = phi[q * NLOC + a];
+  const double *xe = s_x + el * nk;
+  double r = 0.0;
+  for (int i = 0; i < k; ++i) {
     double v = 0.0;
 #pragma unroll
-    for (int a = 0; a < NLOC; ++a) v += s_phi[q * NLOC + a] * xa[a];
-    double r = f * v * v;
-    for (int off = LPE >> 1; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
-    if (i == q) mine = r;
+    for (int a = 0; a < NLOC; ++a) v += ph[a] * xe[a * k + i];
+    r += s_occ[i] * v * v;
   }
-  if (ok && i < NQ) rho[(int64_t)e * NQ + i] = mine;
+  rho[(int64_t)e * NQ + q] = r;
+}
+template <int NLOC, int NQ>
+static void density_t(const int32_t *edof, int n_e, const double *phi, const double *X, int ldx, int k,
+                      const double *occ, double *rho, hipStream_t s) {
+  // 32 lanes per element for the 27-point rule or 10-node elements (keeps the
+  // staged block <= 40 KB at k = 64), else 16
+  constexpr int LPE = (NQ > 16 || NLOC == 10) ? 32 : 16;
+  constexpr int EPB = 256 / LPE;
+  const size_t lds = sizeof(double) * ((size_t)EPB * NLOC * k + k);
+  hipLaunchKernelGGL((k_density<NLOC, NQ, LPE>), dim3((n_e + EPB - 1) / EPB), dim3(256), lds, s, edof, n_e, phi,
+                     X, ldx, k, occ, rho);
 }
 void launch_density(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi,
                     const double *X, int ldx, int k, const double *occ, double *rho,
                     hipStream_t s) {
-  if (n_e <= 0) return;
-  int LPE = 1;
-  while (LPE < k || LPE < n_q) LPE <<= 1;  // every point needs a writer lane
-  if (LPE > 64) return;                    // k <= 64 and n_q <= 27 always hold
-  const int per_block = 4 * (64 / LPE);
-  dim3 g((n_e + per_block - 1) / per_block), b(256);
-  if (n_loc == 4 && n_q == 8)
-    hipLaunchKernelGGL((k_density<4, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
-  else if (n_loc == 10 && n_q == 27)
-    hipLaunchKernelGGL((k_density<10, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
-  else if (n_loc == 4 && n_q == 27)
-    hipLaunchKernelGGL((k_density<4, 27>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
-  else if (n_loc == 10 && n_q == 8)
-    hipLaunchKernelGGL((k_density<10, 8>), g, b, 0, s, edof, n_e, phi, X, ldx, k, occ, rho, LPE);
+  if (n_e <= 0 || k < 1 || k > 64) return;
+  if (n_loc == 4 && n_q == 8) density_t<4, 8>(edof, n_e, phi, X, ldx, k, occ, rho, s);
+  else if (n_loc == 10 && n_q == 27) density_t<10, 27>(edof, n_e, phi, X, ldx, k, occ, rho, s);
+  else if (n_loc == 4 && n_q == 27) density_t<4, 27>(edof, n_e, phi, X, ldx, k, occ, rho, s);
+  else if (n_loc == 10 && n_q == 8) density_t<10, 8>(edof, n_e, phi, X, ldx, k, occ, rho, s);
 }
 
 // u_q = sum_a phi_qa U[node_a] for a nodal field over all nodes
@@ -378,29 +384,64 @@ int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s) 
 struct FjArgs {
   const double *f[4];
 };
+// NH history differences (compile-time, so the accumulators stay in
+// registers); part[b][21]: [0] <F,F>, [1 + j] <D_j,F>, [5 + 4j + l] <D_j,D_l>
+template <int NH>
 __global__ void __launch_bounds__(256) k_anderson_gram(int64_t npts, int n_q,
                                                        const double *__restrict__ absdet,
                                                        const double *__restrict__ w,
-                                                       const double *__restrict__ Fm, int nh,
-                                                       FjArgs fj, double *__restrict__ part) {
+                                                       const double *__restrict__ Fm, FjArgs fj,
+                                                       double *__restrict__ part) {
   __shared__ double sh[16];
-  double acc[21];
-  for (int j = 0; j < 21; ++j) acc[j] = 0.0;
+  double a0 = 0.0, a1[NH > 0 ? NH : 1], a2[NH > 0 ? NH * NH : 1];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) a1[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < NH * NH; ++j) a2[j] = 0.0;
+  const bool small = npts < 2147483647LL;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npts;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double dv = absdet[i / n_q] * w[i % n_q];
+    int64_t e;
+    int q;
+    if (small) {
+      const unsigned ui = (unsigned)i, un = (unsigned)n_q;
+      e = ui / un;
+      q = (int)(ui - (unsigned)e * un);
+    } else {
+      e = i / n_q;
+      q = (int)(i - e * n_q);
+    }
+    const double dv = absdet[e] * w[q];
     const double fm = Fm[i];
-    double d[4];
-    for (int j = 0; j < 4; ++j) d[j] = j < nh ? fm - fj.f[j][i] : 0.0;
-    acc[0] += dv * fm * fm;
-    for (int j = 0; j < nh; ++j) {
-      acc[1 + j] += dv * d[j] * fm;
-      for (int l = 0; l < nh; ++l) acc[5 + 4 * j + l] += dv * d[j] * d[l];
+    double d[NH > 0 ? NH : 1];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) d[j] = fm - fj.f[j][i];
+    a0 += dv * fm * fm;
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+      const double dj = dv * d[j];
+      a1[j] += dj * fm;
+#pragma unroll
+      for (int l = 0; l < NH; ++l) a2[j * NH + l] += dj * d[l];
     }
   }
-  for (int j = 0; j < 21; ++j) {
-    double s = block_sum(acc[j], sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 21 + j] = s;
+  double s = block_sum(a0, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 21] = s;
+  for (int j = 0; j < 4; ++j) {
+    double v = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < NH; ++jj) if (jj == j) v = a1[jj];
+    s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 21 + 1 + j] = s;
+    for (int l = 0; l < 4; ++l) {
+      double u = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NH; ++jj)
+#pragma unroll
+        for (int ll = 0; ll < NH; ++ll) if (jj == j && ll == l) u = a2[jj * NH + ll];
+      s = block_sum(u, sh);
+      if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 21 + 5 + 4 * j + l] = s;
+    }
   }
 }
 int launch_anderson_gram(int64_t npts, int n_q, const double *absdet, const double *w,
@@ -409,8 +450,13 @@ int launch_anderson_gram(int64_t npts, int n_q, const double *absdet, const doub
   FjArgs a;
   for (int j = 0; j < 4; ++j) a.f[j] = j < nh ? Fj[j] : nullptr;
   int nb = wdot_blocks(npts);
-  hipLaunchKernelGGL(k_anderson_gram, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, nh, a,
-                     part);
+  switch (nh) {
+    case 0: hipLaunchKernelGGL(k_anderson_gram<0>, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, a, part); break;
+    case 1: hipLaunchKernelGGL(k_anderson_gram<1>, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, a, part); break;
+    case 2: hipLaunchKernelGGL(k_anderson_gram<2>, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, a, part); break;
+    case 3: hipLaunchKernelGGL(k_anderson_gram<3>, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, a, part); break;
+    default: hipLaunchKernelGGL(k_anderson_gram<4>, dim3(nb), dim3(256), 0, s, npts, n_q, absdet, w, Fm, a, part); break;
+  }
   return nb;
 }
 

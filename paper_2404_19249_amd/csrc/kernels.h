@@ -113,6 +113,10 @@ size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem);
 // tiling cannot serve k columns (the caller uses launch_spmm)
 int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
                       const double *X, double *Y, const double *B, hipStream_t s);
+// the same over column chunks of width kc, X / Y / B with row pitches ldx / ldy
+// (B: ldy); -1 (nothing launched) when the tiling cannot serve a chunk
+int launch_spmm_tiled_cols(int N, int k, int ldx, int ldy, int kc, const Tiling &t, int tb, const int32_t *rowptr,
+                           const double *val, const double *X, double *Y, const double *B, hipStream_t s);
 
 struct PCGWork {
   void *R, *P, *Q;       // [N][k] of T
@@ -139,6 +143,10 @@ int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t
 // MFMA), Z row stride ldz, Y row stride ldy, C row stride ldc.
 void launch_gemm_tn(int N, int ma, int nb, const double *Z, int ldz, const double *Y, int ldy,
                     double *C, int ldc, double *work, size_t work_doubles, hipStream_t s);
+// the same for a symmetric product (Y = H Z, H symmetric; m x m): only the
+// 16x16 tiles on and above the diagonal are computed, the rest mirrored
+void launch_gemm_tn_sym(int N, int m, const double *Z, int ldz, const double *Y, int ldy, double *C, int ldc,
+                        double *work, hipStream_t s);
 size_t gemm_tn_work_doubles(int N, int ma, int nb);
 // Out[i][j] = sum_{c<4} Pw[i][c] T[Pidx[i][c]][j] (+ Y[i][j] if Y) ; T row stride ldt
 void launch_ellP_times(int N, const int32_t *Pidx, const double *Pw, const double *T, int ldt,
@@ -156,19 +164,18 @@ void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB
                       double *work, double *theta, double *U, int *info, hipStream_t s);
 size_t small_eig_work_doubles(int m);
 // Two-stage small eigensolver (m <= 190, packed symmetric matrices in LDS):
-// launch_orth once per augmented space, launch_reduced_eig per F_A.  The
+// launch_orth once per augmented space, launch_reduced_eig_split per F_A.
+// work: jacobi_work_doubles(m) device doubles (the Jacobi rotation log).  The
 // launchers return -1 if the large-LDS attribute cannot be set.
 int packed_eig_supported(int m);
 size_t orth_shared_bytes(int m);
-int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, int *info,
+size_t jacobi_work_doubles(int m);
+int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double *X, double *work, int *info,
                 hipStream_t s);
-int launch_reduced_eig(int m, int k, int r, const double *FA, int ldfa, const double *D,
-                       const double *X, double *W, int warm, double *T1, double *T2, double *V,
-                       double *theta, double *U, int *info, hipStream_t s);
-// the same with the dense products as multi-workgroup kernels; S (m x m),
-// T1 (m x r), T2 (r x r), V (r x r), lam [r] are work buffers
+// the dense products run as multi-workgroup kernels; S (m x m), T1 (m x r),
+// T2 (r x r), lam [r] are work buffers
 int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, const double *D, const double *X,
-                             double *W, int warm, double *S, double *T1, double *T2, double *V, double *lam,
+                             double *W, int warm, double *S, double *T1, double *T2, double *work, double *lam,
                              double *theta, double *U, int *info, hipStream_t s);
 // Dense P (first n_H columns of Z) from the ELL form
 void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,

@@ -79,6 +79,9 @@ struct ks_ctx {
   ks_options opt;
   int order = 1, n_loc = 4, n_nodes = 0, n_e = 0, n_q = 0, N = 0, NB = 0, N_H = 0, n_H = 0;
   int k_max = 0, mp = 0;  // leading dimension of Z
+  // halo tiles of the many-column products (projection): row block, column
+  // chunk, threads
+  int proj_br = 128, proj_kc = 16, proj_tb = 1024;
   double L = 0.0, mu = 0.0;
   int n_atoms = 0;
   std::vector<double> hZ, hR;
@@ -125,6 +128,7 @@ struct ks_ctx {
   int *einfo = nullptr;
   // two-stage eigensolver state: D, V, X (orthogonalised F_B basis), W (warm
   // start eigenvectors), scratch T1, T2; rank r of the current F_B
+  double *eRot = nullptr;  // Jacobi rotation log
   double *eD = nullptr, *eV = nullptr, *eX = nullptr, *eW = nullptr, *eT1 = nullptr, *eT2 = nullptr, *eS = nullptr, *eLam = nullptr;
   int e_rank = 0, e_m = 0;
   // state of the most recent ks_scf_step (for its energy and adjoint)
@@ -256,6 +260,18 @@ static void spmm_op(ks_ctx *c, const double *val, const double *X, int k, double
   if (c->pw64.til && launch_spmm_tiled(c->N, k, *c->pw64.til, c->pw64.til_tb, c->rowptr, val, X, Y, B, c->s) == 0)
     return;
   launch_spmm(c->N, c->rowptr, c->col, val, X, k, Y, k, k, B, k, B ? 1 : 0, c->rorder, c->s);
+}
+
+static int tile_index(int br);
+// Y = A X over ncols columns, X and Y with row pitches ldx, ldy (elements):
+// halo tiles over column chunks, else the row kernel
+static void spmm_cols(ks_ctx *c, const double *val, const double *X, int ldx, double *Y, int ldy, int ncols) {
+  const int ti = tile_index(c->proj_br);
+  if (ti >= 0 && c->til[ti].nblk &&
+      launch_spmm_tiled_cols(c->N, ncols, ldx, ldy, c->proj_kc, c->til[ti], c->proj_tb, c->rowptr, val, X, Y,
+                             nullptr, c->s) == 0)
+    return;
+  launch_spmm(c->N, c->rowptr, c->col, val, X, ldx, Y, ldy, ncols, nullptr, 0, 0, c->rorder, c->s);
 }
 
 static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *out_host) {
@@ -817,6 +833,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(einfo, 8);
   A_(eD, mm);
   A_(eV, (size_t)mm * mm);
+  A_(eRot, jacobi_work_doubles(std::min(mm, 190)));
   A_(eX, (size_t)mm * mm);
   A_(eW, (size_t)mm * mm);
   A_(eT1, (size_t)mm * mm);
@@ -923,6 +940,15 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       const int tb = vt ? std::atoi(vt) : dtb;
       return i >= 0 ? 3 * i + (tb == 1024 ? 2 : (tb == 512 ? 1 : 0)) : -1;
     };
+    // KS_PROJ_TILE = "rows,columns,threads" of the projection products
+    if (const char *v = std::getenv("KS_PROJ_TILE")) {
+      int br = 0, kc = 0, tb = 0;
+      if (std::sscanf(v, "%d,%d,%d", &br, &kc, &tb) == 3) {
+        c->proj_br = br;
+        c->proj_kc = kc;
+        c->proj_tb = tb;
+      }
+    }
     c->tile64 = tile_env("KS_TILE64", 85, "KS_TILE64_TB", 1024);
     c->tile32 = tile_env("KS_TILE32", 85, "KS_TILE32_TB", 512);
     c->tileP = tile_env("KS_TILEP", 128, "KS_TILEP_TB", 512);
@@ -964,11 +990,11 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   launch_dense_P(N, c->Pidx, c->Pw, c->N_H, c->Z, c->mp, s);
   dbg(c, "AL", c->AL, c->nnz_ext);
   dbg(c, "Z(P dense)", c->Z, (int64_t)N * c->mp);
-  launch_spmm(N, c->rowptr, c->col, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, c->rorder, s);
+  spmm_cols(c, c->M, c->Z, c->mp, c->Y, c->mp, c->N_H);
   dbg(c, "Y = M P", c->Y, (int64_t)N * c->mp);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->GPP, c->N_H, c->gwork, c->gwork_n, s);
   dbg(c, "G_PP", c->GPP, (int64_t)c->N_H * c->N_H);
-  launch_spmm(N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0, c->rorder, s);
+  spmm_cols(c, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H);
   launch_gemm_tn(N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork, c->gwork_n,
                  s);
   {
@@ -1115,7 +1141,7 @@ static int time_op(ks_ctx *c, int which, int k, int reps, float *ms) {
         project_full(c, c->MNL, m, c->Ctmp);
         break;
       default:  // 11: the tall-skinny GEMM Z^T Y alone (FP64 MFMA)
-        launch_gemm_tn(c->N, m, m, c->Z, c->mp, c->Y, c->mp, c->Ctmp, m, c->gwork, c->gwork_n, s);
+        launch_gemm_tn_sym(c->N, m, c->Z, c->mp, c->Y, c->mp, c->Ctmp, m, c->gwork, s);
         break;
     }
   };
@@ -1234,8 +1260,7 @@ static int refresh_external(ks_ctx *c) {
   assemble_potential_all(c, c->vext_q, c->AL);
   launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);
   launch_combine3(c->nnz_ext, 1.0, c->AL, c->mu, c->M, 0.0, nullptr, c->base, s);
-  launch_spmm(c->N, c->rowptr, c->col, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H, nullptr, 0, 0,
-              c->rorder, s);
+  spmm_cols(c, c->AL, c->Z, c->mp, c->Y, c->mp, c->N_H);
   launch_gemm_tn(c->N, c->N_H, c->N_H, c->Z, c->mp, c->Y, c->mp, c->FAL_PP, c->N_H, c->gwork,
                  c->gwork_n, s);
   c->have_S = c->have_S32 = c->have_step = false;
@@ -1972,13 +1997,14 @@ static int build_tail(ks_ctx *c, const double *psi_hat, int k) {
 
 // F (m x m, ld m) = Z^T H Z with the P-P block taken from PP if given
 static void project_full(ks_ctx *c, const double *H, int m, double *F) {
-  launch_spmm(c->N, c->rowptr, c->col, H, c->Z, c->mp, c->Y, c->mp, c->mp, nullptr, 0, 0, c->rorder, c->s);
-  launch_gemm_tn(c->N, m, m, c->Z, c->mp, c->Y, c->mp, F, m, c->gwork, c->gwork_n, c->s);
+  // columns m.. of Z are zero: an even count keeps two-column vector lanes
+  spmm_cols(c, H, c->Z, c->mp, c->Y, c->mp, std::min(c->mp, (m + 1) & ~1));
+  launch_gemm_tn_sym(c->N, m, c->Z, c->mp, c->Y, c->mp, F, m, c->gwork, c->s);
 }
 // F from the fixed P-P block and the tail columns Z^T (H psi_tilde)
 static void project_tail(ks_ctx *c, const double *H, const double *PP, int k, double *F) {
   const int m = c->N_H + k;
-  launch_spmm(c->N, c->rowptr, c->col, H, c->Z + c->N_H, c->mp, c->Wv, k, k, nullptr, 0, 0, c->rorder, c->s);
+  spmm_cols(c, H, c->Z + c->N_H, c->mp, c->Wv, k, k);
   launch_gemm_tn(c->N, m, k, c->Z, c->mp, c->Wv, k, c->Ftail, k, c->gwork, c->gwork_n, c->s);
   launch_fill_pencil(m, c->N_H, PP, c->Ftail, F, c->s);
 }
@@ -2013,7 +2039,7 @@ static int orth_impl(ks_ctx *c, const double *FB, int m) {
     return KS_OK;  // the one-stage fallback handles it per call
   }
   HIPCHK(hipMemsetAsync(c->einfo, 0, 8 * sizeof(int), c->s));
-  if (launch_orth(m, FB, m, c->eD, c->eV, c->eX, c->einfo, c->s) < 0)
+  if (launch_orth(m, FB, m, c->eD, c->eV, c->eX, c->eRot, c->einfo, c->s) < 0)
     return fail(KS_ERR_HIP, "cannot enable the LDS size of the eigensolver");
   int info[8];
   HIPCHK(hipMemcpyAsync(info, c->einfo, sizeof(int) * 8, hipMemcpyDeviceToHost, c->s));
@@ -2046,7 +2072,7 @@ static int eig_impl(ks_ctx *c, const double *FA, const double *FB, int m, int k,
   const int r = c->e_rank;
   if (r < k) return fail(KS_ERR_EIG, "augmented space has rank " + std::to_string(r) + " < k");
   if (launch_reduced_eig_split(m, k, r, FA, m, c->eD, c->eX, c->eW, warm ? 1 : 0, c->eS, c->eT1, c->eT2,
-                               c->eV, c->eLam, c->theta, U, c->einfo + 4, c->s) < 0)
+                               c->eRot, c->eLam, c->theta, U, c->einfo + 4, c->s) < 0)
     return fail(KS_ERR_HIP, "cannot enable the LDS size of the eigensolver");
   theta_all.resize(r);
   HIPCHK(hipMemcpyAsync(theta_all.data(), c->theta, sizeof(double) * r, hipMemcpyDeviceToHost, c->s));

@@ -361,7 +361,8 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // MODE 0: the PCG phase (Q = S P, p.q partials, skipped once the solver
 // stopped); MODE 1: Q = S P; MODE 2: Q = B - S P.
 template <typename T, int VW, int HCB, int TB, int MODE>
-__global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, int max_halo, int max_nnz,
+__global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, int BR, int nblk, int max_halo,
+                                                int max_nnz,
                                                 const int32_t *__restrict__ halo_ptr,
                                                 const int32_t *__restrict__ halo_col,
                                                 const int32_t *__restrict__ hself,
@@ -374,7 +375,8 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
   if (MODE == 0 && ctl && ctl->stop) return;
   extern __shared__ __align__(16) unsigned char t_smem[];
   const int CG = k / VW;
-  const unsigned rowbytes = (unsigned)k * sizeof(T);
+  const unsigned rowbytes = (unsigned)k * sizeof(T);   // one halo row in LDS
+  const unsigned pitch = (unsigned)ldp * sizeof(T);     // one row of P in memory
   const int CH = (int)rowbytes / HCB;
   const TLayout L = tile_layout(max_halo, max_nnz, (int)rowbytes, (int)sizeof(T));
   // fixed (row slot, column group) per thread: RPP rows per pass
@@ -402,7 +404,7 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
       int h = h0c, ch = ch0c;
       for (int c0 = wave * 64; c0 < total; c0 += per) {
         if (c0 + lane < total) {
-          const unsigned off = (unsigned)hl[h] * rowbytes + (unsigned)(ch * HCB);
+          const unsigned off = (unsigned)hl[h] * pitch + (unsigned)(ch * HCB);
           lds_void_t *d = (lds_void_t *)(t_smem + L.halo + (unsigned)c0 * HCB);
           if constexpr (HCB == 16) __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 16, 0, 0);
           else __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 4, 0, 0);
@@ -459,10 +461,10 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int BR, int nblk, i
         for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
       } else if constexpr (MODE == 2) {
         T b[VW];
-        load_row<T, VW>(Bm, row, k, cg * VW, k, b);
+        load_row<T, VW>(Bm, row, ldq, cg * VW, k, b);
         for (int v = 0; v < VW; ++v) acc[v] = b[v] - acc[v];
       }
-      store_row<T, VW>(Q, row, k, cg * VW, k, acc);
+      store_row<T, VW>(Q, row, ldq, cg * VW, k, acc);
     }
   }
   if constexpr (MODE != 0) return;
@@ -492,16 +494,19 @@ struct TShape {
 };
 constexpr size_t TILE_LDS_MAX = 160 * 1024 - 512;
 // tb: threads per workgroup (256, 512 or 1024; the waves share one block)
+// ld: row pitch (elements) of the gathered operand; a16: its base address and
+// pitch allow 16-byte halo chunks
 template <typename T>
-static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb) {
+static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb, int ld = 0, bool a16 = true) {
   TShape sh;
+  if (ld <= 0) ld = k;
   const int vw16 = 16 / (int)sizeof(T);
   sh.VW = (k % vw16 == 0) ? vw16 : 1;
   sh.TB = (tb == 512 || tb == 1024) ? tb : 256;
-  sh.HCB = ((k * sizeof(T)) % 16 == 0) ? 16 : 4;
+  sh.HCB = ((k * sizeof(T)) % 16 == 0 && (ld * sizeof(T)) % 16 == 0 && a16) ? 16 : 4;
   sh.lds = tiled_lds_bytes(t, k, sizeof(T));
   if (sh.lds) sh.lds = std::max(sh.lds, (size_t)sh.TB * sh.VW * sizeof(double));  // final column reduction
-  if (sh.lds == 0 || sh.lds > TILE_LDS_MAX || (double)N * k * sizeof(T) >= 4294967296.0) return sh;
+  if (sh.lds == 0 || sh.lds > TILE_LDS_MAX || (double)N * ld * sizeof(T) >= 4294967296.0) return sh;
   const int per_cu = std::max(1, std::min(2048 / sh.TB, (int)(TILE_LDS_MAX / sh.lds)));
   int g = std::min(t.nblk, 256 * per_cu);
   if (g > 8) g = g / 8 * 8;
@@ -510,9 +515,9 @@ static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb) {
 }
 
 template <typename T, int VW, int HCB, int TB, int MODE>
-static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
-                           const T *val, const T *P, T *Q, double *part, const Control *ctl, const T *Bm,
-                           hipStream_t s) {
+static int launch_tpcg_A_t(int N, int k, int ldp, int ldq, const Tiling &t, const TShape &sh,
+                           const int32_t *rowptr, const T *val, const T *P, T *Q, double *part, const Control *ctl,
+                           const T *Bm, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB, MODE>,
@@ -520,18 +525,19 @@ static int launch_tpcg_A_t(int N, int k, const Tiling &t, const TShape &sh, cons
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, t.BR, t.nblk,
+  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, ldp, ldq, t.BR,
+                     t.nblk,
                      t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, t.rperm, val, P, Q, part,
                      ctl, Bm);
   return 0;
 }
 template <typename T, int MODE>
-static int launch_tpcg_A_m(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
-                           const T *val, const T *P, T *Q, double *part, const Control *ctl, const T *Bm,
-                           hipStream_t s) {
+static int launch_tpcg_A_m(int N, int k, int ldp, int ldq, const Tiling &t, const TShape &sh,
+                           const int32_t *rowptr, const T *val, const T *P, T *Q, double *part, const Control *ctl,
+                           const T *Bm, hipStream_t s) {
   constexpr int V16 = 16 / sizeof(T);
 #define KS_TL(VW, HCB, TB) \
-  return launch_tpcg_A_t<T, VW, HCB, TB, MODE>(N, k, t, sh, rowptr, val, P, Q, part, ctl, Bm, s)
+  return launch_tpcg_A_t<T, VW, HCB, TB, MODE>(N, k, ldp, ldq, t, sh, rowptr, val, P, Q, part, ctl, Bm, s)
   if (sh.TB == 1024) {
     if (sh.VW == V16) KS_TL(V16, 16, 1024);
     if (sh.HCB == 16) KS_TL(1, 16, 1024);
@@ -550,7 +556,7 @@ static int launch_tpcg_A_m(int N, int k, const Tiling &t, const TShape &sh, cons
 template <typename T>
 static int launch_tpcg_A(int N, int k, const Tiling &t, const TShape &sh, const int32_t *rowptr,
                          const T *val, const T *P, T *Q, double *part, const Control *ctl, hipStream_t s) {
-  return launch_tpcg_A_m<T, 0>(N, k, t, sh, rowptr, val, P, Q, part, ctl, nullptr, s);
+  return launch_tpcg_A_m<T, 0>(N, k, k, k, t, sh, rowptr, val, P, Q, part, ctl, nullptr, s);
 }
 
 // Y = S X (B == nullptr) or Y = B - S X with the halo-tile kernel (FP64, X
@@ -559,8 +565,33 @@ int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowp
                       const double *X, double *Y, const double *B, hipStream_t s) {
   const TShape sh = tiled_shape<double>(t, k, N, 1 << 30, tb);
   if (sh.grid <= 0) return -1;
-  if (B) return launch_tpcg_A_m<double, 2>(N, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, B, s);
-  return launch_tpcg_A_m<double, 1>(N, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
+  if (B) return launch_tpcg_A_m<double, 2>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, B, s);
+  return launch_tpcg_A_m<double, 1>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
+}
+
+// The same over column chunks of width kc: X, Y (and B) with row pitches
+// ldx, ldy (elements); -1 (nothing launched) when the tiling cannot serve a
+// chunk
+int launch_spmm_tiled_cols(int N, int k, int ldx, int ldy, int kc, const Tiling &t, int tb, const int32_t *rowptr,
+                           const double *val, const double *X, double *Y, const double *B, hipStream_t s) {
+  if (kc < 1 || ldx < k || ldy < k) return -1;
+  auto shape = [&](int c0) {
+    const int w = std::min(kc, k - c0);
+    const bool a16 = ((c0 * sizeof(double)) % 16 == 0) && ((uintptr_t)X % 16 == 0);
+    return tiled_shape<double>(t, w, N, 1 << 30, tb, ldx, a16);
+  };
+  for (int c0 = 0; c0 < k; c0 += kc)
+    if (shape(c0).grid <= 0) return -1;
+  for (int c0 = 0; c0 < k; c0 += kc) {
+    const int w = std::min(kc, k - c0);
+    const TShape sh = shape(c0);
+    const int r = B ? launch_tpcg_A_m<double, 2>(N, w, ldx, ldy, t, sh, rowptr, val, X + c0, Y + c0, nullptr,
+                                                 nullptr, B + c0, s)
+                    : launch_tpcg_A_m<double, 1>(N, w, ldx, ldy, t, sh, rowptr, val, X + c0, Y + c0, nullptr,
+                                                 nullptr, nullptr, s);
+    if (r < 0) return -1;
+  }
+  return 0;
 }
 
 // ================================================================== PCG
