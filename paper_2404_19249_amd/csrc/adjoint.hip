@@ -167,23 +167,8 @@ void launch_force_partials(const double *coords, const int32_t *elems, int n_loc
 }
 
 // per-column dot products of two [N][k] blocks: part[blk][k]
-__global__ void __launch_bounds__(256) k_coldots(int N, int k, const double *__restrict__ X,
-                                                 const double *__restrict__ Y,
-                                                 double *__restrict__ part) {
-  __shared__ double sh[16];
-  for (int c = 0; c < k; ++c) {
-    double a = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
-      a += X[(int64_t)i * k + c] * Y[(int64_t)i * k + c];
-    const double s = block_sum(a, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + c] = s;
-  }
-}
 int launch_coldots(int N, int k, const double *X, const double *Y, double *part, hipStream_t s) {
-  int nb = (N + 255) / 256;
-  nb = nb > 256 ? 256 : (nb < 1 ? 1 : nb);
-  hipLaunchKernelGGL(k_coldots, dim3(nb), dim3(256), 0, s, N, k, X, Y, part);
-  return nb;
+  return launch_colsums(N, k, X, Y, part, s);
 }
 
 }  // namespace ks

@@ -361,24 +361,39 @@ void launch_lincomb(int64_t n, int nvec, const double *coef_dev, const double *c
 }  // namespace ks
 
 namespace ks {
-__global__ void __launch_bounds__(256) k_colnorms(int N, int k, const double *__restrict__ X,
-                                                  double *__restrict__ part) {
-  __shared__ double sh[16];
-  for (int c = 0; c < k; ++c) {
-    double a = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
-      const double v = X[(int64_t)i * k + c];
-      a += v * v;
+// Per-column sums of X[i][c] * Y[i][c] over [N][k] row-major blocks (Y null:
+// squares of X), per block of rows: thread t owns column t % k of rows
+// t / k, t / k + R, ... (R = 256 / k rows per pass), so the reads of a pass are
+// one contiguous, coalesced run; the R partial sums of a column are added in a
+// fixed order.  k <= 256.
+__global__ void __launch_bounds__(256) k_colsums(int N, int k, const double *__restrict__ X,
+                                                 const double *__restrict__ Y, double *__restrict__ part) {
+  __shared__ double s[256];
+  const int R = 256 / k, t = threadIdx.x, c = t % k, r0 = t / k;
+  double a = 0.0;
+  if (r0 < R) {
+    for (int64_t i = (int64_t)blockIdx.x * R + r0; i < N; i += (int64_t)gridDim.x * R) {
+      const double x = X[i * k + c];
+      a += x * (Y ? Y[i * k + c] : x);
     }
-    double s = block_sum(a, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + c] = s;
+  }
+  s[t] = a;
+  __syncthreads();
+  if (t < k) {
+    double sum = 0.0;
+    for (int r = 0; r < R; ++r) sum += s[r * k + t];
+    part[(int64_t)blockIdx.x * k + t] = sum;
   }
 }
-int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s) {
-  int nb = (N + 255) / 256;
+int launch_colsums(int N, int k, const double *X, const double *Y, double *part, hipStream_t s) {
+  const int R = 256 / k;
+  int nb = (N + R - 1) / R;
   nb = nb > 256 ? 256 : (nb < 1 ? 1 : nb);
-  hipLaunchKernelGGL(k_colnorms, dim3(nb), dim3(256), 0, s, N, k, X, part);
+  hipLaunchKernelGGL(k_colsums, dim3(nb), dim3(256), 0, s, N, k, X, Y, part);
   return nb;
+}
+int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s) {
+  return launch_colsums(N, k, X, nullptr, part, s);
 }
 
 struct FjArgs {

@@ -126,12 +126,13 @@ struct PCGWork {
   int nblk_max;
   const Tiling *til;     // SpMM phase: LDS-staged halo tiles (nullptr = row kernel)
   int til_tb;            // threads per workgroup of the tiled kernel (256, 512, 1024)
+  int last_iters = 0;    // iterations of the previous solve (first host poll)
 };
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
               const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter,
               PCGWork &w, int *iters_out, double *relres_out, int *converged_out,
-              int *breakdown_out, hipStream_t s, int ng = 0);
+              int *breakdown_out, hipStream_t s, int ng = 0, int x_zero = 0);  // x_zero: X is 0 on entry
 size_t pcg_state_bytes(int k);
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
@@ -189,6 +190,9 @@ void launch_zero_cols(int N, int c0, int c1, double *Z, int ldz, hipStream_t s);
 
 namespace ks {
 // per-column sums of squares of an [N][k] block: part[blk][k]; returns nblk
+// per-column sums of X .* Y (Y null: X .* X) over [N][k] rows, k <= 256:
+// part[blk][k]; returns the number of blocks
+int launch_colsums(int N, int k, const double *X, const double *Y, double *part, hipStream_t s);
 int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s);
 // X[i][j] += scale[j] * (double)D[i][j]   (mixed-precision refinement update)
 void launch_refine_update(int N, int k, const float *D, const double *scale, double *X, hipStream_t s);

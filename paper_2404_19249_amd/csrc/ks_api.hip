@@ -1919,7 +1919,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
       int c32 = 0;
       int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->B32, c->X32,
                                c->opt.mixed_inner_tol, c->opt.max_it_solve, c->pw32, it, rr, &c32,
-                               &brk, s, c->ng32);
+                               &brk, s, c->ng32, 1);
       if (r < 0) return fail(KS_ERR_HIP, "FP32 PCG launch failed");
       if (brk) return fail(KS_ERR_BREAKDOWN, "FP32 PCG breakdown");
       for (int j = 0; j < k; ++j) total_it[j] += it[j];

@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
                                                   const T *__restrict__ Bm, const T *__restrict__ X,
                                                   T *__restrict__ R, T *__restrict__ P,
                                                   double *__restrict__ part,
-                                                  const int32_t *__restrict__ ord) {
+                                                  const int32_t *__restrict__ ord, int have_r) {
   __shared__ double s_red[256 * VW];
   const RowMap m = row_map<NG>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
@@ -643,7 +643,10 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
     const bool rv = m.valid && pos < N;
     const int row = rv ? (ord ? ord[pos] : pos) : 0;
     T acc[VW];
-    if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, k, k, acc);
+    if (have_r) {
+      // R already holds b - S x (halo-tile kernel), or x = 0: no S x needed
+      for (int v = 0; v < VW; ++v) acc[v] = T(0);
+    } else if (rv) row_product<T, VW, NG>(row, m, rowptr, col, val, X, k, k, acc);
     else {
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
       if (NG > 1)
@@ -653,9 +656,10 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
     if (rv && m.ng == 0 && m.cg * VW < k) {
       T b[VW], r[VW], p[VW];
       load_row<T, VW>(Bm, row, k, m.cg * VW, k, b);
+      if (have_r == 1) load_row<T, VW>(R, row, k, m.cg * VW, k, r);
       const T d = diag[row];
       for (int v = 0; v < VW; ++v) {
-        r[v] = b[v] - acc[v];
+        if (have_r != 1) r[v] = b[v] - acc[v];  // acc = 0 when x = 0 (have_r == 2)
         p[v] = r[v] / d;
         abb[v] += (double)b[v] * (double)b[v];
         arr[v] += (double)r[v] * (double)r[v];
@@ -881,7 +885,7 @@ template <typename T, int VW, int NG>
 static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
                    const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter, PCGWork &w,
                    int *iters_out, double *relres_out, int *converged_out, int *breakdown_out,
-                   hipStream_t s) {
+                   hipStream_t s, int x_zero) {
   const int CG = (k + VW - 1) / VW;
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
@@ -897,12 +901,24 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
     tsh = tiled_shape<T>(*w.til, k, N, w.nblk_max, w.til_tb);
     if (tsh.grid > 0) til = w.til;
   }
+  int have_r = 0;
+  if (x_zero) {
+    have_r = 2;  // r = b
+  } else if (til) {  // R = B - S X through the halo tiles
+    if (launch_tpcg_A_m<T, 2>(N, k, k, k, *til, tsh, rowptr, val, X, R, nullptr, nullptr, B, s) < 0) return -1;
+    have_r = 1;
+  }
   hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                     diag, B, X, R, P, part, ord);
+                     diag, B, X, R, P, part, ord, have_r);
   hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
   std::vector<ColState> hcs(k);
   Control hctl;
-  int done_iters = 0, chunk = 4;
+  // host polls of the stop flag: the first after about as many iterations as
+  // the previous solve took, then every 2 (iterations launched after
+  // convergence return at once, but still cost a launch each); without a
+  // history, after 4, 8, 16, 32, ... iterations
+  const bool hist = w.last_iters > 0;
+  int done_iters = 0, chunk = hist ? std::max(2, w.last_iters - 1) : 4;
   for (;;) {
     if (hipMemcpyAsync(&hctl, ctl, sizeof(Control), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
@@ -912,12 +928,14 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
                                     ctl, cs, tol, done_iters, n, s, til, tsh) < 0)
       return -1;
     done_iters += n;
-    chunk = std::min(chunk * 2, 32);
+    chunk = hist ? 2 : std::min(chunk * 2, 32);
   }
   if (hipMemcpyAsync(hcs.data(), cs, sizeof(ColState) * k, hipMemcpyDeviceToHost, s) != hipSuccess)
     return -2;
   if (hipStreamSynchronize(s) != hipSuccess) return -2;
-  int conv = 1;
+  int conv = 1, itmax = 0;
+  for (int c = 0; c < k; ++c) itmax = std::max(itmax, hcs[c].iters);
+  w.last_iters = itmax;
   for (int c = 0; c < k; ++c) {
     if (iters_out) iters_out[c] = hcs[c].iters;
     if (relres_out) relres_out[c] = hcs[c].bb > 0 ? sqrt(hcs[c].rr / hcs[c].bb) : 0.0;
@@ -1028,19 +1046,19 @@ template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
               const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter,
               PCGWork &w, int *iters_out, double *relres_out, int *converged_out,
-              int *breakdown_out, hipStream_t s, int ng) {
+              int *breakdown_out, hipStream_t s, int ng, int x_zero) {
   const int vw = pick_vw<T>(k, B, X);
   ng = fit_ng(k, vw, ng);
   KS_PCG_DISPATCH(pcg_run, N, k, rowptr, col, val, ord, diag, B, X, tol, max_iter, w, iters_out,
-                  relres_out, converged_out, breakdown_out, s)
+                  relres_out, converged_out, breakdown_out, s, x_zero)
 }
 
 template int pcg_solve<double>(int, int, const int32_t *, const int32_t *, const double *,
                                const int32_t *, const double *, const double *, double *, double, int,
-                               PCGWork &, int *, double *, int *, int *, hipStream_t, int);
+                               PCGWork &, int *, double *, int *, int *, hipStream_t, int, int);
 template int pcg_solve<float>(int, int, const int32_t *, const int32_t *, const float *,
                               const int32_t *, const float *, const float *, float *, double, int,
-                              PCGWork &, int *, double *, int *, int *, hipStream_t, int);
+                              PCGWork &, int *, double *, int *, int *, hipStream_t, int, int);
 
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
