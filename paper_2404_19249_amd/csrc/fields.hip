@@ -372,7 +372,19 @@ __global__ void __launch_bounds__(256) k_colsums(int N, int k, const double *__r
   const int R = 256 / k, t = threadIdx.x, c = t % k, r0 = t / k;
   double a = 0.0;
   if (r0 < R) {
-    for (int64_t i = (int64_t)blockIdx.x * R + r0; i < N; i += (int64_t)gridDim.x * R) {
+    // four passes in flight per iteration
+    const int64_t step = (int64_t)gridDim.x * R;
+    int64_t i = (int64_t)blockIdx.x * R + r0;
+    for (; i + 3 * step < N; i += 4 * step) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = X[(i + u * step) * k + c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = Y ? Y[(i + u * step) * k + c] : x[u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a += x[u] * y[u];
+    }
+    for (; i < N; i += step) {
       const double x = X[i * k + c];
       a += x * (Y ? Y[i * k + c] : x);
     }
@@ -388,7 +400,7 @@ __global__ void __launch_bounds__(256) k_colsums(int N, int k, const double *__r
 int launch_colsums(int N, int k, const double *X, const double *Y, double *part, hipStream_t s) {
   const int R = 256 / k;
   int nb = (N + R - 1) / R;
-  nb = nb > 256 ? 256 : (nb < 1 ? 1 : nb);
+  nb = nb > 512 ? 512 : (nb < 1 ? 1 : nb);  // part: <= 512 k doubles
   hipLaunchKernelGGL(k_colsums, dim3(nb), dim3(256), 0, s, N, k, X, Y, part);
   return nb;
 }

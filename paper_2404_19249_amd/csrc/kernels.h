@@ -189,10 +189,10 @@ void launch_zero_cols(int N, int c0, int c1, double *Z, int ldz, hipStream_t s);
 }  // namespace ks
 
 namespace ks {
-// per-column sums of squares of an [N][k] block: part[blk][k]; returns nblk
 // per-column sums of X .* Y (Y null: X .* X) over [N][k] rows, k <= 256:
-// part[blk][k]; returns the number of blocks
+// part[blk][k] with at most 512 blocks; returns the number of blocks
 int launch_colsums(int N, int k, const double *X, const double *Y, double *part, hipStream_t s);
+// per-column sums of squares (launch_colsums with Y null)
 int launch_colnorms(int N, int k, const double *X, double *part, hipStream_t s);
 // X[i][j] += scale[j] * (double)D[i][j]   (mixed-precision refinement update)
 void launch_refine_update(int N, int k, const float *D, const double *scale, double *X, hipStream_t s);

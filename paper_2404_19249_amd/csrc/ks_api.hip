@@ -1232,6 +1232,10 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
     }
     ws[w]->til = keep;
     ws[w]->til_tb = keep_db;
+    // keep the configuration in use unless another is more than 3% faster:
+    // closer timings are within the run-to-run noise
+    const int cur = w == 0 ? c->tile64 : (w == 1 ? c->tile32 : c->tileP);
+    if (cur >= 0 && t_til[w][cur] > 0.0 && t_til[w][cur] <= 1.03 * bt) best_tile[w] = cur;
   }
   c->ng64 = best_ng[0];
   c->ng32 = best_ng[1];
