@@ -186,6 +186,7 @@ typedef struct {
   int32_t status_solve;
   ks_solve_stats solve;
   double seconds[8];     /* assemble, block solve, project, inner SCF, energies, total */
+  double res_outer;      /* ||rho^{l+1} - rho^l||_0: the step's output density against its input */
 } ks_step_report;
 
 /* One iteration of Algorithm 3: assemble S from the density of psi, solve
@@ -197,6 +198,22 @@ typedef struct {
  * rho_q (device [n_elems][n_q], may be NULL) receives the new density. */
 int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                 int32_t precision, double *rho_q, ks_step_report *rep_host);
+
+/* Algorithm 3 to convergence: ks_scf_step repeated (in place on psi,
+ * lambda_host) until ||rho^{l+1} - rho^l||_0 < tol_outer (the quadrature L2
+ * norm of the density change; Alg. 3's stopping rule) or max_steps steps,
+ * then ks_step_energy for E_KS of the last step.  Returns KS_NOT_CONVERGED
+ * if max_steps was reached, KS_WARN_DEGENERATE as ks_scf_step; rep_host may
+ * be NULL. */
+typedef struct {
+  int32_t steps, converged;
+  int32_t inner_iters, poisson_iters;  /* totals over the steps */
+  double res_outer;                    /* of the last step */
+  double E_total, E_KS;                /* of the last step; equal at outer convergence */
+  double seconds;
+} ks_run_report;
+int ks_scf_run(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
+               int32_t precision, double tol_outer, int32_t max_steps, double *rho_q, ks_run_report *rep_host);
 
 /* Replace the external potential: either its values at the quadrature
  * points (device [n_elems][n_q]) or new nuclear positions R_host [n_atoms][3]

@@ -58,7 +58,13 @@ class StepReport(C.Structure):
                 ("E_xc", C.c_double), ("E_vxc", C.c_double), ("E_nn", C.c_double),
                 ("res_inner", C.c_double), ("inner_iters", C.c_int32),
                 ("poisson_iters", C.c_int32), ("rank", C.c_int32), ("status_solve", C.c_int32),
-                ("solve", SolveStats), ("seconds", C.c_double * 8)]
+                ("solve", SolveStats), ("seconds", C.c_double * 8), ("res_outer", C.c_double)]
+
+
+class RunReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("converged", C.c_int32), ("inner_iters", C.c_int32),
+                ("poisson_iters", C.c_int32), ("res_outer", C.c_double), ("E_total", C.c_double),
+                ("E_KS", C.c_double), ("seconds", C.c_double)]
 
 
 class BatchStats(C.Structure):
@@ -104,6 +110,8 @@ _SIGS = {
     "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),
+    "ks_scf_run": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                             C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(RunReport)]),
 }
 
 _lib = None

@@ -259,9 +259,24 @@ class KSContext:
                                             C.byref(rep)), self.lib)
         r = {f: getattr(rep, f) for f in ("E_total", "E_band", "E_H", "E_xc", "E_vxc", "E_nn",
                                           "res_inner", "inner_iters", "poisson_iters", "rank",
-                                          "status_solve")}
+                                          "status_solve", "res_outer")}
         r["solve"] = self._stats(rep.solve, k)
         r["seconds"] = list(rep.seconds[:6])
+        r["status"] = code
+        return lam_a, r
+
+    def scf_run(self, psi, lam, occ, tol, max_steps=100, precision="fp64", rho_out=None):
+        """Algorithm 3 to convergence (ks_scf_run): steps in place on psi until
+        the density changes by less than tol (quadrature L2 norm)."""
+        k = psi.shape[1]
+        lam_a = _f64(lam).copy()
+        occ_a = _f64(occ)
+        rep = B.RunReport()
+        code = B.check(self.lib.ks_scf_run(self.h, self._ptr(psi), B.dptr(lam_a), k, B.dptr(occ_a),
+                                           B.PREC[precision], float(tol), int(max_steps),
+                                           self._ptr(rho_out), C.byref(rep)), self.lib)
+        r = {f: getattr(rep, f) for f in ("steps", "converged", "inner_iters", "poisson_iters",
+                                          "res_outer", "E_total", "E_KS", "seconds")}
         r["status"] = code
         return lam_a, r
 

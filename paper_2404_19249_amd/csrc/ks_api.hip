@@ -110,7 +110,7 @@ struct ks_ctx {
   bool have_S = false, have_S32 = false;
   // quadrature fields [n_e][n_q]
   double *vext_q = nullptr, *rho_l = nullptr, *rho_in = nullptr, *rho_out = nullptr,
-         *vh_q = nullptr, *vxc_q = nullptr, *exc_q = nullptr, *vnl_q = nullptr;
+         *vh_q = nullptr, *vxc_q = nullptr, *exc_q = nullptr, *vnl_q = nullptr, *drho = nullptr;
   double *hist_in[5] = {}, *hist_F[5] = {};
   // Hartree
   double *vh_int = nullptr, *vh_nodes = nullptr, *wB = nullptr, *load = nullptr, *rhs = nullptr,
@@ -794,6 +794,7 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(rho_l, nqt);
   A_(rho_in, nqt);
   A_(rho_out, nqt);
+  A_(drho, nqt);
   A_(vh_q, nqt);
   A_(vxc_q, nqt);
   A_(exc_q, nqt);
@@ -2295,6 +2296,14 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   }
   R.E_total = R.E_band - R.E_H - R.E_vxc + R.E_xc + R.E_nn;
   R.poisson_iters = piters;
+  {
+    // ||rho^{l+1} - rho^l||_0, the outer stopping quantity of Algorithm 3
+    launch_combine3(nqt, 1.0, c->rho_out, -1.0, c->rho_l, 0.0, nullptr, c->drho, s);
+    const double *d[1] = {c->drho};
+    double v = 0.0;
+    TRY(weighted_dots(c, 1, d, d, &v));
+    R.res_outer = std::sqrt(std::max(v, 0.0));
+  }
   HIPCHK(hipStreamSynchronize(s));
   const double t5 = now_s();
   R.seconds[0] = t1 - t0;
@@ -2314,4 +2323,40 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   if (nonlinear && res >= c->opt.tol_inner) ret = KS_NOT_CONVERGED;
   if (st == KS_NOT_CONVERGED) ret = KS_NOT_CONVERGED;
   return ret;
+}
+
+// Algorithm 3 run to convergence: repeat ks_scf_step until
+// ||rho^{l+1} - rho^l||_0 < tol_outer or max_steps steps; then E_KS of the
+// last step (ks_step_energy).
+extern "C" int ks_scf_run(ks_ctx *c, double *psi, double *lambda_host, int32_t k, const double *occ_host,
+                          int32_t precision, double tol_outer, int32_t max_steps, double *rho_q,
+                          ks_run_report *rep_host) {
+  if (!c || !psi || !lambda_host || !occ_host) return fail(KS_ERR_ARG, "null argument");
+  if (!(tol_outer > 0.0) || max_steps < 1) return fail(KS_ERR_ARG, "tol_outer must be > 0, max_steps >= 1");
+  ks_run_report R;
+  std::memset(&R, 0, sizeof(R));
+  const double t0 = now_s();
+  int st = KS_OK;
+  for (int l = 0; l < max_steps; ++l) {
+    ks_step_report sr;
+    st = ks_scf_step(c, psi, lambda_host, k, occ_host, precision, rho_q, &sr);
+    if (st < 0) return st;
+    R.steps = l + 1;
+    R.inner_iters += sr.inner_iters;
+    R.poisson_iters += sr.poisson_iters;
+    R.res_outer = sr.res_outer;
+    R.E_total = sr.E_total;
+    if (sr.res_outer < tol_outer) {
+      R.converged = 1;
+      break;
+    }
+  }
+  double e[6];
+  const int se = ks_step_energy(c, e);
+  if (se < 0) return se;
+  R.E_KS = e[0];
+  R.seconds = now_s() - t0;
+  if (rep_host) *rep_host = R;
+  if (!R.converged) return KS_NOT_CONVERGED;
+  return st == KS_WARN_DEGENERATE ? KS_WARN_DEGENERATE : KS_OK;
 }
