@@ -211,6 +211,78 @@ void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_
                        pairtab, w, V_q, out);
 }
 
+// Gather form.  emat[i][p] = sum_q w_q |J_e| V_eq phi_a(q) phi_b(q) for
+// e = eord[i] and pair p = (a <= b): one lane per (element, pair), every
+// element in one launch (no colouring: nothing is scattered here).
+template <int NLOC, int NQ>
+__global__ void __launch_bounds__(256) k_elem_potential(const int32_t *__restrict__ eord, int n,
+                                                        const double *__restrict__ absdet,
+                                                        const double *__restrict__ pairtab,
+                                                        const double *__restrict__ w,
+                                                        const double *__restrict__ V, double *__restrict__ emat) {
+  constexpr int NP = NLOC * (NLOC + 1) / 2;
+  constexpr int EPW = 64 / NP;
+  constexpr int NC = EPW * NQ;  // weights per wave
+  __shared__ double s_pt[NQ * NP];
+  __shared__ double s_c[4][NC];  // per wave: w_q |J| V_q of its elements
+  for (int i = threadIdx.x; i < NQ * NP; i += blockDim.x) s_pt[i] = pairtab[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * EPW;
+  // weight l of the wave: point l % NQ of element l / NQ (coalesced loads)
+  for (int l = lane; l < NC; l += 64) {
+    const int el = l / NQ, q = l - el * NQ;
+    double cq = 0.0;
+    if (i0 + el < n) {
+      const int e = eord[i0 + el];
+      cq = w[q] * absdet[e] * V[(int64_t)e * NQ + q];
+    }
+    s_c[wave][l] = cq;
+  }
+  __syncthreads();
+  const int es = lane / NP, p = lane - es * NP;
+  const int i = i0 + es;
+  if (es >= EPW || i >= n) return;
+  const double *c = s_c[wave] + es * NQ;
+  double m = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) m += c[q] * s_pt[q * NP + p];
+  emat[(int64_t)i * NP + p] = m;
+}
+void launch_elem_potential(const int32_t *eord, int n, int n_loc, int n_q, const double *absdet,
+                           const double *pairtab, const double *w, const double *V_q, double *emat, hipStream_t s) {
+  if (n <= 0) return;
+  const int np = n_loc * (n_loc + 1) / 2, epw = 64 / np;
+  dim3 g((n + 4 * epw - 1) / (4 * epw)), b(256);
+  if (n_loc == 4 && n_q == 8)
+    hipLaunchKernelGGL((k_elem_potential<4, 8>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
+  else if (n_loc == 10 && n_q == 27)
+    hipLaunchKernelGGL((k_elem_potential<10, 27>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
+  else if (n_loc == 4 && n_q == 27)
+    hipLaunchKernelGGL((k_elem_potential<4, 27>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
+  else if (n_loc == 10 && n_q == 8)
+    hipLaunchKernelGGL((k_elem_potential<10, 8>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
+}
+// out[s] = base[s] (0 if base is null) + the pair values that belong to
+// value slot s, added in ascending order (a fixed order: bitwise
+// reproducible)
+__global__ void k_gather_slots(int64_t nslots, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
+                               const double *__restrict__ emat, const double *__restrict__ base,
+                               double *__restrict__ out) {
+  for (int64_t sidx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sidx < nslots;
+       sidx += (int64_t)gridDim.x * blockDim.x) {
+    const int j0 = cptr[sidx], j1 = cptr[sidx + 1];
+    double v = base ? base[sidx] : 0.0;
+    for (int j = j0; j < j1; ++j) v += emat[cidx[j]];
+    out[sidx] = v;
+  }
+}
+void launch_gather_slots(int64_t nslots, const int32_t *cptr, const int32_t *cidx, const double *emat,
+                         const double *base, double *out, hipStream_t s) {
+  if (nslots <= 0) return;
+  const int64_t b = std::min<int64_t>((nslots + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_gather_slots, dim3((unsigned)b), dim3(256), 0, s, nslots, cptr, cidx, emat, base, out);
+}
+
 // ------------------------------------------------------------ load vector
 template <int NLOC, int NQ>
 __global__ void __launch_bounds__(256) k_load_vector(const int32_t *__restrict__ list, int count,

@@ -95,6 +95,13 @@ struct ks_ctx {
   double *coords = nullptr;
   int32_t *elems = nullptr, *edof = nullptr, *slot = nullptr, *node2int = nullptr,
           *node2bnd = nullptr, *bnodes = nullptr, *elem_perm = nullptr;
+  // gather form of the potential-matrix assembly: elements in the order of
+  // the first storage row they touch (g_eord), their pair values (g_emat
+  // [n][n_pairs]), and per value slot the pair values that add into it
+  // (g_cidx[g_cptr[s] .. g_cptr[s+1]), ascending)
+  int32_t *g_eord = nullptr, *g_cptr = nullptr, *g_cidx = nullptr;
+  double *g_emat = nullptr;
+  int g_nE = 0;
   double *absdet = nullptr, *gl = nullptr, *phi = nullptr, *dphi = nullptr, *pairtab = nullptr,
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
   // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
@@ -282,7 +289,16 @@ static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *ou
 }
 
 // colour loop helpers
-static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out) {
+// out = base + M[V] over the extended pattern (base null: out = M[V])
+static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out, const double *base = nullptr) {
+  if (c->g_nE) {  // element pair values, then one gather per value slot
+    launch_elem_potential(c->g_eord, c->g_nE, c->n_loc, c->n_q, c->absdet, c->pairtab, c->qw, Vq, c->g_emat,
+                          c->s);
+    launch_gather_slots(c->nnz_ext, c->g_cptr, c->g_cidx, c->g_emat, base, out, c->s);
+    return;
+  }
+  if (base) launch_axpby(c->nnz_ext, 1.0, base, 0.0, out, c->s);
+  else launch_fill(c->nnz_ext, 0.0, out, c->s);
   for (int col = 0; col < c->n_colours; ++col) {
     const int a = c->colour_off[col], b = c->colour_off[col + 1];
     launch_assemble_potential(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->slot, c->absdet,
@@ -638,6 +654,57 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
       }
     }
   });
+  // gather form of the potential assembly (see g_eord): elements touching an
+  // interior row, ordered by the first (Morton) storage row they touch, so
+  // that the pair values one row block gathers sit close together
+  std::vector<int32_t> g_eord, g_cptr, g_cidx;
+  {
+    const int np = nl * (nl + 1) / 2;
+    std::vector<int32_t> ekey(ne);
+    parallel_for(ne, [&](int64_t e) {
+      int32_t k = INT32_MAX;
+      for (int a2 = 0; a2 < nl; ++a2) {
+        const int32_t d = edof[e * nl + a2];
+        if (d >= 0) k = std::min(k, d);
+      }
+      ekey[e] = k;
+    });
+    for (int e = 0; e < ne; ++e)
+      if (ekey[e] != INT32_MAX) g_eord.push_back(e);
+    std::stable_sort(g_eord.begin(), g_eord.end(), [&](int32_t x, int32_t y) { return ekey[x] < ekey[y]; });
+    const int64_t nslots = c->nnz_ext;
+    g_cptr.assign(nslots + 1, 0);
+    for (size_t i = 0; i < g_eord.size(); ++i) {
+      const int64_t e = g_eord[i];
+      for (int a2 = 0; a2 < nl * nl; ++a2) {
+        const int32_t sl = slot[e * nl * nl + a2];
+        if (sl >= 0) g_cptr[sl + 1]++;
+      }
+    }
+    int64_t total = 0;
+    for (int64_t sidx = 0; sidx < nslots; ++sidx) total += g_cptr[sidx + 1];
+    if (total < INT32_MAX)
+      for (int64_t sidx = 0; sidx < nslots; ++sidx) g_cptr[sidx + 1] += g_cptr[sidx];
+    if ((int64_t)g_eord.size() * np < INT32_MAX && total > 0 && total < INT32_MAX) {
+      g_cidx.resize(g_cptr[nslots]);
+      std::vector<int32_t> pos(g_cptr.begin(), g_cptr.end() - 1);
+      for (size_t i = 0; i < g_eord.size(); ++i) {
+        const int64_t e = g_eord[i];
+        for (int a2 = 0; a2 < nl; ++a2)
+          for (int b2 = 0; b2 < nl; ++b2) {
+            const int32_t sl = slot[(e * nl + a2) * nl + b2];
+            if (sl < 0) continue;
+            const int lo = std::min(a2, b2), hi = std::max(a2, b2);
+            const int pidx = lo * nl - (lo * (lo - 1)) / 2 + (hi - lo);  // pair (lo, hi), lo <= hi
+            g_cidx[pos[sl]++] = (int32_t)(i * np + pidx);
+          }
+      }
+      c->g_nE = (int)g_eord.size();
+    } else {
+      g_eord.clear();
+      g_cptr.clear();
+    }
+  }
   // greedy element colouring: no two elements of one colour share a node
   std::vector<int16_t> colour(ne, -1);
   int ncol = 0;
@@ -762,6 +829,12 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   A_(elems, (size_t)ne * nl);
   A_(edof, (size_t)ne * nl);
   A_(slot, (size_t)ne * nl * nl);
+  if (c->g_nE) {
+    A_(g_eord, g_eord.size());
+    A_(g_cptr, g_cptr.size());
+    A_(g_cidx, g_cidx.size());
+    A_(g_emat, (size_t)c->g_nE * (nl * (nl + 1) / 2));
+  }
   A_(node2int, nn);
   A_(node2bnd, nn);
   A_(bnodes, std::max(1, c->NB));
@@ -894,6 +967,11 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   H2D(c->elems, el, (size_t)ne * nl);
   H2D(c->edof, edof.data(), edof.size());
   H2D(c->slot, slot.data(), slot.size());
+  if (c->g_nE) {
+    H2D(c->g_eord, g_eord.data(), g_eord.size());
+    H2D(c->g_cptr, g_cptr.data(), g_cptr.size());
+    H2D(c->g_cidx, g_cidx.data(), g_cidx.size());
+  }
   H2D(c->node2int, node2int.data(), nn);
   H2D(c->node2bnd, node2bnd.data(), nn);
   if (c->NB) H2D(c->bnodes, bnodes.data(), c->NB);
@@ -981,7 +1059,6 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   dbg(c, "K", c->K, c->nnz_ext);
   dbg(c, "M", c->M, c->nnz_ext);
   dbg(c, "vext_q", c->vext_q, (int64_t)ne * c->n_q);
-  launch_fill(c->nnz_ext, 0.0, c->AL, s);
   assemble_potential_all(c, c->vext_q, c->AL);
   launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);                  // A^L = K/2 + M[V_ext]
   launch_combine3(c->nnz_ext, 1.0, c->AL, c->mu, c->M, 0.0, nullptr, c->base, s);  // + mu M
@@ -1129,7 +1206,6 @@ static int time_op(ks_ctx *c, int which, int k, int reps, float *ms) {
   auto op = [&]() {
     switch (which) {
       case 7:  // potential matrix M[V_nl] over all colours (a4)
-        launch_fill(c->nnz_ext, 0.0, c->MNL, s);
         assemble_potential_all(c, c->vnl_q, c->MNL);
         break;
       case 8:  // density at the quadrature points (a2)
@@ -1261,7 +1337,6 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
 // Recompute everything that depends on V_ext: A^L, A^L + mu M and P^T A^L P.
 static int refresh_external(ks_ctx *c) {
   hipStream_t s = c->s;
-  launch_fill(c->nnz_ext, 0.0, c->AL, s);
   assemble_potential_all(c, c->vext_q, c->AL);
   launch_axpby(c->nnz_ext, 0.5, c->K, 1.0, c->AL, s);
   launch_combine3(c->nnz_ext, 1.0, c->AL, c->mu, c->M, 0.0, nullptr, c->base, s);
@@ -1772,8 +1847,8 @@ static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_
   }
   launch_xc(nqt, c->rho_l, psi ? c->opt.xc_mode : KS_XC_NONE, c->exc_q, c->vxc_q, s);
   launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
-  launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
-  if (nonlinear) assemble_potential_all(c, c->vnl_q, c->S);
+  if (nonlinear) assemble_potential_all(c, c->vnl_q, c->S, c->base);  // S = A^L + mu M + M[V_nl]
+  else launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
   launch_extract_diag(c->N, c->rowptr, c->col, c->S, c->diagS, s);
   c->have_S = true;
   c->have_S32 = false;
@@ -2023,7 +2098,6 @@ extern "C" int ks_augmented_project(ks_ctx *c, const double *psi_hat, int32_t k,
   else if (which == 1) H = c->AL;
   else if (which == 2) {
     if (!c->have_S) return fail(KS_ERR_STATE, "no assembly");
-    launch_fill(c->nnz_ext, 0.0, c->MNL, c->s);
     assemble_potential_all(c, c->vnl_q, c->MNL);
     H = c->MNL;
   } else
@@ -2200,7 +2274,6 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
       }
       launch_xc(nqt, c->rho_in, c->opt.xc_mode, c->exc_q, c->vxc_q, s);
       launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
-      launch_fill(c->nnz_ext, 0.0, c->MNL, s);
       assemble_potential_all(c, c->vnl_q, c->MNL);
       project_full(c, c->MNL, m, c->Ctmp);
       launch_combine3((int64_t)m * m, 1.0, c->FAL, 1.0, c->Ctmp, 0.0, nullptr, c->FA, s);
