@@ -120,6 +120,10 @@ size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem);
 // tiling cannot serve k columns (the caller uses launch_spmm)
 int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
                       const double *X, double *Y, const double *B, hipStream_t s);
+// FP32 values and vectors; tiled_fits_f32: whether the tiling serves k FP32 columns
+int launch_spmm_tiled_f32(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const float *val,
+                          const float *X, float *Y, const float *B, hipStream_t s);
+bool tiled_fits_f32(int N, int k, const Tiling &t, int tb);
 // the same over column chunks of width kc, X / Y / B with row pitches ldx / ldy
 // (B: ldy); -1 (nothing launched) when the tiling cannot serve a chunk
 int launch_spmm_tiled_cols(int N, int k, int ldx, int ldy, int kc, const Tiling &t, int tb, const int32_t *rowptr,
@@ -261,7 +265,7 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
 void mg_destroy(Multigrid *mg);
 void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0);
 int mg_levels(const Multigrid *mg);
-// part: >= 256 doubles of device scratch; sc: >= 5 device doubles (CG scalars)
+// part: >= 256 doubles of device scratch; sc: >= 6 device doubles (CG scalars)
 int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
            int *iters, double *relres, hipStream_t s);
 }  // namespace ks

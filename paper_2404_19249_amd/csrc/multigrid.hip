@@ -18,6 +18,8 @@
 #include "common.h"
 #include "kernels.h"
 #include <algorithm>
+#include <cstring>
+#include <climits>
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -213,6 +215,36 @@ static void launch_cheb(int n, const double *r, const double *dinv, double c1, d
     hipLaunchKernelGGL(k_cheb, dim3(std::min(4096, (n + 255) / 256)), dim3(256), 0, s, n, r, dinv, c1, c2, d,
                        x, first);
 }
+// the Chebyshev update in FP32
+__global__ void k_cheb32(int n, const float *__restrict__ r, const float *__restrict__ dinv, float c1, float c2,
+                         float *__restrict__ d, float *__restrict__ x, int first) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float di = (first ? 0.0f : c1 * d[i]) + c2 * dinv[i] * r[i];
+    d[i] = di;
+    x[i] = (first == 2 ? 0.0f : x[i]) + di;
+  }
+}
+static void launch_cheb32(int n, const float *r, const float *dinv, double c1, double c2, float *d, float *x,
+                          int first, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_cheb32, dim3(std::min(4096, (n + 255) / 256)), dim3(256), 0, s, n, r, dinv, (float)c1,
+                       (float)c2, d, x, first);
+}
+__global__ void k_f2d(int n, const float *__restrict__ a, double *__restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = (double)a[i];
+}
+// x32 += P xc (P: ELL-4 interpolation from the next coarser level)
+__global__ void k_prolong_add32(int n, const int32_t *__restrict__ Pidx, const double *__restrict__ Pw,
+                                const double *__restrict__ xc, float *__restrict__ x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const int id = Pidx[4 * (int64_t)i + c];
+      if (id >= 0) v += Pw[4 * (int64_t)i + c] * xc[id];
+    }
+    x[i] += (float)v;
+  }
+}
 __global__ void k_invert(int n, const double *__restrict__ a, double *__restrict__ out) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = 1.0 / a[i];
 }
@@ -249,6 +281,10 @@ struct Multigrid {
   int tb0 = 256;
   double *coarse_inv = nullptr;  // dense inverse of the coarsest operator
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;  // PCG vectors (level 0)
+  // FP32 smoothing on level 0 (the V-cycle is a preconditioner; the outer
+  // CG stays FP64): operator values, 1/diag and the level's vectors in FP32
+  bool f32 = false;
+  float *val32 = nullptr, *dinv32 = nullptr, *x32 = nullptr, *r32 = nullptr, *d32 = nullptr, *b32 = nullptr;
   std::vector<void *> mem;
   ~Multigrid() {
     for (void *p : mem) (void)hipFree(p);
@@ -268,6 +304,8 @@ void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0) {
   if (mg) {
     mg->til0 = til0;
     mg->tb0 = tb0;
+    // the FP32 level 0 needs halo tiles that serve one FP32 column
+    if (mg->val32) mg->f32 = til0 && tiled_fits_f32(mg->lv[0].n, 1, *til0, tb0);
   }
 }
 int mg_levels(const Multigrid *mg) { return mg ? (int)mg->lv.size() : 0; }
@@ -440,6 +478,20 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
     if (hipMemcpyAsync(v.dinv, dh.data(), sizeof(double) * v.n, hipMemcpyHostToDevice, s) != hipSuccess)
       return bail();
   }
+  {
+    // FP32 level 0 (KS_MG_FP32=0 keeps it FP64)
+    const char *env = std::getenv("KS_MG_FP32");
+    const int64_t nnz0 = rp_h[n0];
+    if (!(env && std::strcmp(env, "0") == 0) && nnz0 > 0 && nnz0 < INT32_MAX) {
+      MGLevel &v0 = mg->lv[0];
+      if (mg->alloc(&mg->val32, (size_t)nnz0 + 8) && mg->alloc(&mg->dinv32, n0) && mg->alloc(&mg->x32, n0) &&
+          mg->alloc(&mg->r32, n0) && mg->alloc(&mg->d32, n0) && mg->alloc(&mg->b32, n0)) {
+        launch_to_float(nnz0, val_d, mg->val32, s);
+        launch_to_float(n0, v0.dinv, mg->dinv32, s);
+        mg->f32 = til0 && tiled_fits_f32(n0, 1, *til0, tb0);
+      }
+    }
+  }
   if (hipStreamSynchronize(s) != hipSuccess) return bail();
   return mg;
 }
@@ -470,8 +522,51 @@ static void mg_smooth(const Multigrid *mg, MGLevel &v, const double *b, bool zer
   launch_cheb(v.n, v.r, v.dinv, rho1 * rho0, 2.0 * rho1 / delta, v.d, v.x, 0, s);
 }
 
+static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s);
+
+// r32 = b32 - A x32 on level 0 (FP32 halo tiles); false if they cannot serve
+static bool spmv0_f32(const Multigrid *mg, hipStream_t s) {
+  const MGLevel &v = mg->lv[0];
+  return mg->til0 &&
+         launch_spmm_tiled_f32(v.n, 1, *mg->til0, mg->tb0, v.rp, mg->val32, mg->x32, mg->r32, mg->b32, s) == 0;
+}
+
+// The V-cycle with level 0 smoothed in FP32: the same Chebyshev steps as
+// mg_smooth, the residual restricted and the correction prolonged through
+// FP64 coarse levels
+static void vcycle0_f32(Multigrid *mg, const double *b, double *x, hipStream_t s) {
+  MGLevel &v = mg->lv[0];
+  const int n = v.n;
+  const double lo = v.lmax / 8.0, hi = 1.1 * v.lmax;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  const int g = std::min(4096, (n + 255) / 256);
+  launch_to_float(n, b, mg->b32, s);
+  // pre-smoothing from zero
+  launch_cheb32(n, mg->b32, mg->dinv32, 0.0, 1.0 / theta, mg->d32, mg->x32, 2, s);
+  spmv0_f32(mg, s);
+  launch_cheb32(n, mg->r32, mg->dinv32, rho1 * rho0, 2.0 * rho1 / delta, mg->d32, mg->x32, 0, s);
+  // residual to the next level
+  spmv0_f32(mg, s);
+  hipLaunchKernelGGL(k_f2d, dim3(g), dim3(256), 0, s, n, mg->r32, v.r);
+  MGLevel &c = mg->lv[1];
+  launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);  // b_c = P^T r
+  vcycle(mg, 1, c.b, c.x, s);
+  hipLaunchKernelGGL(k_prolong_add32, dim3(g), dim3(256), 0, s, n, v.Pidx, v.Pw, c.x, mg->x32);
+  // post-smoothing
+  spmv0_f32(mg, s);
+  launch_cheb32(n, mg->r32, mg->dinv32, 0.0, 1.0 / theta, mg->d32, mg->x32, 1, s);
+  spmv0_f32(mg, s);
+  launch_cheb32(n, mg->r32, mg->dinv32, rho1 * rho0, 2.0 * rho1 / delta, mg->d32, mg->x32, 0, s);
+  hipLaunchKernelGGL(k_f2d, dim3(g), dim3(256), 0, s, n, mg->x32, x);
+}
+
 // one V-cycle: x_0 = M^-1 b_0 on level 0 (b, x: level-0 vectors)
 static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s) {
+  if (l == 0 && mg->f32 && mg->lv.size() > 1) {
+    vcycle0_f32(mg, b, x, s);
+    return;
+  }
   MGLevel &v = mg->lv[l];
   if (l + 1 == (int)mg->lv.size()) {
     hipLaunchKernelGGL(k_dense_matvec, dim3((v.n + 3) / 4), dim3(256), 0, s, v.n, mg->coarse_inv, b, x);
@@ -494,7 +589,8 @@ void mg_apply(Multigrid *mg, const double *b, double *x, hipStream_t s) { vcycle
 // ------------------------------------------------------------ MG-PCG
 // The CG scalars live on the device (sc[]); the host reads back one pair
 // (p.q, r.r) per iteration for the breakdown and stopping tests.
-// sc layout: [0] p.q, [1] r.r, [2] f.f, [3], [4] alternating r.z slots.
+// sc layout: [0] p.q, [1] r.r, [2] f.f, [3], [4] alternating r.z slots,
+// [5] r_new . z_old.
 constexpr int MG_NB = 256;  // partial-sum blocks of the vector kernels
 
 // a . b per block (fixed order)
@@ -522,10 +618,10 @@ __global__ void __launch_bounds__(256) k_mg_xr(int n, const double *__restrict__
   v = block_sum(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
-// p = z + (sc[inew] / sc[iold]) p
+// p = z + beta p, beta = (sc[inew] - sc[5]) / sc[iold] = r_new . (z_new - z_old) / (r_old . z_old)
 __global__ void k_mg_p(int n, const double *__restrict__ z, double *__restrict__ p, const double *__restrict__ sc,
                        int inew, int iold) {
-  const double beta = sc[inew] / sc[iold];
+  const double beta = (sc[inew] - sc[5]) / sc[iold];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
 }
 static int mg_nb(int n) { return std::max(1, std::min(MG_NB, (n + 255) / 256)); }
@@ -542,7 +638,7 @@ static int read_back(const double *sc, int slot, int cnt, double *h, hipStream_t
 
 // CG preconditioned by one V-cycle per iteration on level 0's operator:
 // A x = f from the warm start x, stopped at ||f - A x||_2 <= tol ||f||_2.
-// part: device scratch (>= 256 doubles); sc: device scalars (>= 5 doubles).
+// part: device scratch (>= 256 doubles); sc: device scalars (>= 6 doubles).
 // Returns 0 converged, 1 iteration limit, -1 launch failure, -2 breakdown
 // (p.Ap <= 0).
 int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
@@ -582,6 +678,9 @@ int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, do
     *iters = it;
     *relres = std::sqrt(rr / bb);
     if (rr <= tol * tol * bb) return 0;
+    // flexible (Polak-Ribiere) beta: the FP32 level-0 smoothing makes the
+    // preconditioner vary at rounding level between iterations
+    dot_dev(n, mg->pr, mg->pz, part, sc, 5, s);  // r_new . z_old
     vcycle(mg, 0, mg->pr, mg->pz, s);
     const int inew = 7 - irz;  // the other r.z slot (3 <-> 4)
     dot_dev(n, mg->pr, mg->pz, part, sc, inew, s);

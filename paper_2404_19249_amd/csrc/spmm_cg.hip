@@ -569,6 +569,17 @@ int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowp
   return launch_tpcg_A_m<double, 1>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
 }
 
+// FP32 form (Y = S X or Y = B - S X, [N][k] row-major); -1 when the tiling
+// cannot serve k FP32 columns
+int launch_spmm_tiled_f32(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const float *val,
+                          const float *X, float *Y, const float *B, hipStream_t s) {
+  const TShape sh = tiled_shape<float>(t, k, N, 1 << 30, tb);
+  if (sh.grid <= 0) return -1;
+  if (B) return launch_tpcg_A_m<float, 2>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, B, s);
+  return launch_tpcg_A_m<float, 1>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
+}
+bool tiled_fits_f32(int N, int k, const Tiling &t, int tb) { return tiled_shape<float>(t, k, N, 1 << 30, tb).grid > 0; }
+
 // The same over column chunks of width kc: X, Y (and B) with row pitches
 // ldx, ldy (elements); -1 (nothing launched) when the tiling cannot serve a
 // chunk
