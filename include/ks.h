@@ -108,6 +108,18 @@ int ks_options_default(ks_options *o);
  * KS_ERR_NOMEM, KS_ERR_HIP. */
 int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad, const ks_atoms_desc *atoms,
               const ks_options *opt, hipStream_t stream, ks_ctx **out);
+
+/* The same with the coarse space S_H on a given P1 tetrahedral mesh T_H that
+ * need not be nested in the fine mesh (Sec. 3.2): I_H^h interpolates the
+ * coarse P1 functions at the fine nodes by Algorithm 1 (nearest coarse
+ * vertex from a bucket grid, then a barycentric walk to the containing
+ * element).  coarse->dirichlet_host marks the coarse boundary vertices,
+ * which carry no basis function; N_H = the number of the others (N_H + k_max
+ * <= 256); opt->n_H is ignored.  Fine nodes outside T_H take the weights of
+ * the last element of their walk, projected onto it.  coarse == NULL is
+ * ks_create. */
+int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc *coarse, const ks_quad_desc *quad,
+                        const ks_atoms_desc *atoms, const ks_options *opt, hipStream_t stream, ks_ctx **out);
 int ks_destroy(ks_ctx *ctx);
 const char *ks_last_error(void);
 

@@ -163,3 +163,22 @@ def move_nodes_toward_nuclei(mesh: Mesh, R, a: float = 0.5, s: float = 2.0,
                         dirichlet=mesh.dirichlet, moved=True, info=info)
         amp *= 0.5
     raise RuntimeError("could not find a valid moving-map amplitude")
+
+
+def jittered_coarse_mesh(n_H: int, L: float, amp: float = 0.25, seed: int = 7) -> Mesh:
+    """A P1 Kuhn mesh of the box with n_H hexahedra per side whose interior
+    vertices are moved by seeded uniform offsets of up to amp * h per axis
+    (h = 2L / n_H; amp < 0.5 keeps every element positively oriented, which is
+    checked): a coarse mesh that is not nested in any fine lattice mesh."""
+    base = freudenthal_mesh(n_H, L, 1)
+    rng = np.random.default_rng(seed)
+    h = 2.0 * L / n_H
+    off = rng.uniform(-amp * h, amp * h, size=base.coords.shape)
+    off[base.dirichlet == 1] = 0.0
+    coords = base.coords + off
+    if np.any(_signed_volumes6(coords, base.elems) <= 0.0):
+        raise RuntimeError("jitter inverted an element; use a smaller amp")
+    info = dict(base.info)
+    info["jitter"] = amp
+    return Mesh(order=1, n=n_H, L=L, coords=coords, elems=base.elems, dirichlet=base.dirichlet,
+                moved=True, info=info)

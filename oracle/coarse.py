@@ -39,3 +39,31 @@ def coarse_interpolation(x_fine, L, n_H):
             cid = (vv[0] - 1) + ni * ((vv[1] - 1) + ni * (vv[2] - 1))
             P[a, cid] += lv
     return P
+
+
+def interpolation_in_mesh(x_fine, coarse_coords, coarse_tets, coarse_dirichlet):
+    """Dense P [n_fine][n_inner] for a general coarse P1 tetrahedral mesh, by
+    the definition: for every fine point, the coarse element that contains it
+    (brute force over all elements: the one whose smallest barycentric
+    coordinate is largest), and its barycentric coordinates as the values of
+    that element's vertex basis functions.  Coarse vertices with a Dirichlet
+    flag carry no basis function; the others are numbered by ascending id."""
+    cv = np.asarray(coarse_coords, dtype=np.float64)
+    T = np.asarray(coarse_tets, dtype=np.int64)
+    inner = np.flatnonzero(np.asarray(coarse_dirichlet) == 0)
+    cid = -np.ones(cv.shape[0], dtype=np.int64)
+    cid[inner] = np.arange(inner.size)
+    X0 = cv[T[:, 0]]
+    J = np.stack([cv[T[:, 1]] - X0, cv[T[:, 2]] - X0, cv[T[:, 3]] - X0], axis=2)  # [n_t][3][3]
+    Jinv = np.linalg.inv(J)
+    x = np.asarray(x_fine, dtype=np.float64)
+    P = np.zeros((x.shape[0], inner.size))
+    for a in range(x.shape[0]):
+        l123 = np.einsum("tij,tj->ti", Jinv, x[a][None, :] - X0)
+        lam = np.concatenate([1.0 - l123.sum(axis=1, keepdims=True), l123], axis=1)
+        t = int(np.argmax(lam.min(axis=1)))
+        for j in range(4):
+            c = cid[T[t, j]]
+            if c >= 0:
+                P[a, c] += lam[t, j]
+    return P

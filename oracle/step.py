@@ -48,7 +48,7 @@ from . import fe
 from .xc import lda_xc
 from .hartree import density_moments, multipole_boundary
 from .solvers import jacobi_pcg
-from .coarse import coarse_interpolation
+from .coarse import coarse_interpolation, interpolation_in_mesh
 
 
 @dataclass
@@ -68,6 +68,7 @@ class KSProblem:
     hartree: bool = True
     xc_mode: str = "x_pz81"
     quad_factor: float = 0.5
+    coarse: object = None        # a nonnested coarse P1 mesh (None: uniform n_H)
     # derived
     n_nodes: int = 0
     interior: np.ndarray = None
@@ -88,12 +89,12 @@ class KSProblem:
     extra: dict = field(default_factory=dict)
 
     @classmethod
-    def from_workload(cls, w, mu=None, quad_factor=0.5):
+    def from_workload(cls, w, mu=None, quad_factor=0.5, coarse=None):
         p = cls(order=w.mesh.order, coords=w.mesh.coords, elems=w.mesh.elems,
                 dirichlet=w.mesh.dirichlet, quad=w.quad, Z=w.atoms.Z, R=w.atoms.R,
                 occ=w.occ, L=w.mesh.L, n_H=w.n_H,
                 mu=w.mu_paper if mu is None else mu, hartree=w.hartree,
-                xc_mode="x_pz81" if w.xc else "none", quad_factor=quad_factor)
+                xc_mode="x_pz81" if w.xc else "none", quad_factor=quad_factor, coarse=coarse)
         p.setup()
         return p
 
@@ -117,7 +118,11 @@ class KSProblem:
         self.K_IB = fe.restrict(self.K, I, B)
         self.M_II = fe.restrict(self.M, I, I)
         self.Mext_II = fe.restrict(Mext, I, I)
-        self.P = coarse_interpolation(self.coords[I], self.L, self.n_H)
+        if self.coarse is None:
+            self.P = coarse_interpolation(self.coords[I], self.L, self.n_H)
+        else:  # Sec. 3.2: coarse space on a nonnested mesh
+            self.P = interpolation_in_mesh(self.coords[I], self.coarse.coords, self.coarse.elems,
+                                           self.coarse.dirichlet)
 
     def with_external(self, vext_q=None, R=None):
         """Copy of the problem with another external potential at the

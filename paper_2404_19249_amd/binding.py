@@ -78,6 +78,8 @@ _SIGS = {
     "ks_options_default": (C.c_int, [C.POINTER(Options)]),
     "ks_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(QuadDesc), C.POINTER(AtomsDesc),
                             C.POINTER(Options), _P, C.POINTER(_P)]),
+    "ks_create_nonnested": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(MeshDesc), C.POINTER(QuadDesc),
+                                      C.POINTER(AtomsDesc), C.POINTER(Options), _P, C.POINTER(_P)]),
     "ks_destroy": (C.c_int, [_P]),
     "ks_last_error": (C.c_char_p, []),
     "ks_get_sizes": (C.c_int, [_P, C.POINTER(C.c_double)]),

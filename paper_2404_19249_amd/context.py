@@ -25,7 +25,10 @@ class KSContext:
                  mu=None, xc="x_pz81", hartree="multipole", k_max=8, tol_solve=1e-8,
                  tol_inner=1e-8, tol_poisson=1e-10, max_it_solve=5000, max_it_inner=50,
                  max_it_poisson=20000, anderson_depth=5, anderson_beta=0.7,
-                 mixed_inner_tol=1e-5, device=0, stream=None):
+                 mixed_inner_tol=1e-5, device=0, stream=None, coarse=None):
+        """coarse: optional nonnested coarse P1 mesh (an object with coords,
+        elems, dirichlet, L), giving S_H on that mesh (ks_create_nonnested)
+        instead of the uniform n_H mesh."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("KSContext needs a ROCm GPU; none is visible")
@@ -62,9 +65,19 @@ class KSContext:
         opt.mixed_inner_tol = mixed_inner_tol
         self.opt = opt
         h = C.c_void_p()
+        cmesh = None
+        if coarse is not None:
+            self._c_coords = _f64(coarse.coords)
+            self._c_elems = _i32(coarse.elems)
+            self._c_dir = np.ascontiguousarray(coarse.dirichlet, dtype=np.uint8)
+            cmesh = B.MeshDesc(self._c_coords.shape[0], self._c_elems.shape[0], 1,
+                               self._c_coords.ctypes.data_as(C.POINTER(C.c_double)),
+                               self._c_elems.ctypes.data_as(C.POINTER(C.c_int32)),
+                               self._c_dir.ctypes.data_as(C.POINTER(C.c_uint8)), float(coarse.L))
         with torch.cuda.device(self.device):
-            B.check(self.lib.ks_create(C.byref(mesh), C.byref(quad), C.byref(atoms), C.byref(opt),
-                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)), self.lib)
+            B.check(self.lib.ks_create_nonnested(C.byref(mesh), C.byref(cmesh) if cmesh is not None else None,
+                                                 C.byref(quad), C.byref(atoms), C.byref(opt),
+                                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)), self.lib)
         self.h = h
         sz = (C.c_double * 10)()
         B.check(self.lib.ks_get_sizes(self.h, sz))

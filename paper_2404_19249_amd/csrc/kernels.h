@@ -81,6 +81,15 @@ void launch_wdots(int64_t npts, int n_q, const double *absdet, const double *w, 
 void launch_lincomb(int64_t n, int nvec, const double *coef_dev, const double *const *x,
                     double *out, hipStream_t s);
 
+// ------------------------------------------------------ nonnested meshes
+// Interpolation weights of npts points in a coarse P1 tetrahedral mesh
+// (Algorithm 1, host): vid/w [npts][4] = the containing element's vertices
+// and barycentric coordinates.  Returns 0, -1 on a bad mesh, -2 if some
+// point could not be placed (its weights are then those of the nearest
+// element's projection).
+int nonnested_weights(int ncv, const double *cv, int nct, const int32_t *ctet, int npts, const double *pts,
+                      int32_t *vid, double *w);
+
 // ------------------------------------------------------------- sparse / CG
 struct ColState;  // per-column PCG scalars, defined in spmm_cg.hip
 

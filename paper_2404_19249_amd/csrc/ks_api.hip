@@ -400,7 +400,16 @@ static void apply_tiles(ks_ctx *c) {
 extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
                          const ks_atoms_desc *atoms, const ks_options *opt, hipStream_t stream,
                          ks_ctx **out) {
+  return ks_create_nonnested(mesh, nullptr, quad, atoms, opt, stream, out);
+}
+
+extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc *coarse,
+                                   const ks_quad_desc *quad, const ks_atoms_desc *atoms, const ks_options *opt,
+                                   hipStream_t stream, ks_ctx **out) {
   if (!mesh || !quad || !atoms || !out) return fail(KS_ERR_ARG, "null argument");
+  if (coarse && (coarse->order != 1 || coarse->n_nodes < 4 || coarse->n_elems < 1 || !coarse->coords_host ||
+                 !coarse->elems_host || !coarse->dirichlet_host))
+    return fail(KS_ERR_ARG, "coarse mesh: P1 tetrahedra with coordinates, elements and Dirichlet flags");
   if (!mesh->coords_host || !mesh->elems_host || !mesh->dirichlet_host)
     return fail(KS_ERR_ARG, "mesh arrays missing");
   if (mesh->order != 1 && mesh->order != 2) return fail(KS_ERR_ARG, "order must be 1 or 2");
@@ -433,6 +442,16 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
   c->L = mesh->L;
   c->n_H = o.n_H;
   c->N_H = (o.n_H - 1) * (o.n_H - 1) * (o.n_H - 1);
+  std::vector<int32_t> cint;  // coarse vertex -> coarse unknown (-1 on the coarse boundary)
+  if (coarse) {
+    cint.assign(coarse->n_nodes, -1);
+    int nh = 0;
+    for (int v = 0; v < coarse->n_nodes; ++v)
+      if (!coarse->dirichlet_host[v]) cint[v] = nh++;
+    if (nh < 1) return bail(fail(KS_ERR_MESH, "coarse mesh has no interior vertex"));
+    c->n_H = 0;
+    c->N_H = nh;
+  }
   c->k_max = o.k_max;
   if (c->N_H + c->k_max > 256) return bail(fail(KS_ERR_ARG, "N_H + k_max must be <= 256"));
   c->mp = (c->N_H + c->k_max + 15) / 16 * 16;
@@ -741,10 +760,30 @@ extern "C" int ks_create(const ks_mesh_desc *mesh, const ks_quad_desc *quad,
     std::vector<int> pos(c->colour_off.begin(), c->colour_off.end() - 1);
     for (int e = 0; e < ne; ++e) perm[pos[colour[e]]++] = e;
   }
-  // coarse interpolation (closed-form location in the uniform Kuhn mesh)
+  // coarse interpolation (closed-form location in the uniform Kuhn mesh, or
+  // Algorithm 1 in a given nonnested coarse mesh)
   std::vector<int32_t> Pidx((size_t)N * 4, -1);
   std::vector<double> Pw((size_t)N * 4, 0.0);
-  {
+  if (coarse) {
+    std::vector<double> pts((size_t)N * 3);
+    for (int r = 0; r < N; ++r)
+      for (int d = 0; d < 3; ++d) pts[3 * (size_t)r + d] = mesh->coords_host[3 * (int64_t)interior_nodes[r] + d];
+    std::vector<int32_t> vid((size_t)N * 4);
+    std::vector<double> wv((size_t)N * 4);
+    const int rc = nonnested_weights(coarse->n_nodes, coarse->coords_host, coarse->n_elems, coarse->elems_host, N,
+                                     pts.data(), vid.data(), wv.data());
+    if (rc == -1) return bail(fail(KS_ERR_MESH, "coarse mesh: bad element vertex ids"));
+    for (int r = 0; r < N; ++r) {
+      int cnt = 0;
+      for (int j = 0; j < 4; ++j) {
+        const int ci = cint[vid[4 * (size_t)r + j]];
+        if (ci < 0 || wv[4 * (size_t)r + j] == 0.0) continue;  // coarse boundary vertex: no basis function
+        Pidx[4 * (size_t)r + cnt] = ci;
+        Pw[4 * (size_t)r + cnt] = wv[4 * (size_t)r + j];
+        ++cnt;
+      }
+    }
+  } else {
     const int nH = c->n_H, ni = nH - 1;
     const double h = 2.0 * c->L / nH;
     parallel_for(N, [&](int64_t r) {
