@@ -1,0 +1,59 @@
+"""Edge cases on the GPU: the largest block (k = 64 right-hand sides, every
+kernel shape at its widest), odd and single-column blocks, a mesh whose row
+count fills no tile exactly, and argument errors on a live context."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from ks_inputs import make_workload
+from paper_2404_19249_amd.binding import KSError
+
+DEV = "cuda:0"
+
+
+def _ctx(w, **kw):
+    from paper_2404_19249_amd import KSContext
+    print(f"[case] {w.name} order={w.mesh.order} n={w.mesh.n} k={w.k} {kw}", flush=True)
+    return KSContext.from_workload(w, **kw)
+
+
+def _csr(ctx, which):
+    rp, cl, vl = ctx.export_operator(which)
+    return sp.csr_matrix((vl, cl, rp), shape=(ctx.N, ctx.N))
+
+
+@pytest.mark.parametrize("k", [1, 7, 64])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_block_solve_widths_reach_tolerance(k, prec):
+    """S X = B for seeded B of width k (1, odd, the maximum 64); the relative
+    residual of every column is recomputed on the host from the exported S."""
+    w = make_workload("small_molecule", n=5)            # N = 729: no tile size divides it
+    ctx = _ctx(w, k_max=64, tol_solve=1e-10)
+    psi, lam = ctx.initial_guess(w.k)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    S = _csr(ctx, 0)
+    rng = np.random.default_rng(100 + k)
+    Bh = rng.standard_normal((ctx.N, k))
+    Bd = torch.tensor(Bh, device=DEV)
+    X, st = ctx.block_solve_rhs(Bd, precision=prec)
+    Xh = X.cpu().numpy()
+    rel = np.linalg.norm(Bh - S @ Xh, axis=0) / np.linalg.norm(Bh, axis=0)
+    assert st["converged"]
+    assert rel.max() <= 1e-10 * 1.0001, (k, prec, rel.max())
+
+
+def test_live_context_rejects_bad_widths():
+    w = make_workload("small_molecule", n=4)
+    ctx = _ctx(w, k_max=8)
+    psi, lam = ctx.initial_guess(w.k)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    for k in (0, 9):
+        Bd = torch.zeros(ctx.N, max(k, 1), dtype=torch.float64, device=DEV)[:, :k].contiguous()
+        with pytest.raises(KSError) as e:
+            ctx.block_solve_rhs(Bd)
+        assert e.value.code == -1
+    with pytest.raises(KSError):
+        ctx.scf_run(psi, lam, w.occ, tol=0.0)
