@@ -113,12 +113,20 @@ void launch_scale_cols(int N, int k, double *Y, const double *scale_dev, hipStre
 // the position of col[j] in its row block's halo.
 struct Tiling {
   int BR = 0, nblk = 0, max_halo = 0, max_nnz = 0;  // max_nnz: most nonzeros in one block
+  int max_pnz = 0;           // most padded local indices in one block
   int32_t *halo_ptr = nullptr, *halo_col = nullptr;
   int32_t *hself = nullptr;  // [nblk] position of the block's first row in its halo
+  // local (halo) column indices, each row's run padded with index 0 to a
+  // multiple of 8 entries, so that every run starts on a 16-byte boundary;
+  // pptr [nblk + 1]: start of each block's runs
   uint16_t *lcol = nullptr;
-  // [N] slot -> row offset inside its block, rows with more nonzeros first,
-  // so that the rows one wavefront walks together have similar lengths
-  uint8_t *rperm = nullptr;
+  int32_t *pptr = nullptr;
+  // [N][2] per row slot of each block, rows with more nonzeros first (so
+  // that the rows one wavefront walks together have similar lengths): word 0
+  // bits 0-15 the row's first nonzero relative to the block's first, 16-23
+  // its nonzero count, 24-31 its offset inside the block; word 1 the start of
+  // its padded index run relative to the block's
+  uint32_t *rmeta = nullptr;
 };
 // LDS bytes the tiled SpMM needs for k columns of elem-byte values (0 if the
 // tiling cannot serve this shape).  The kernel reads the value and index

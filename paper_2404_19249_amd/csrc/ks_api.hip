@@ -585,12 +585,16 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   // halo tilings (row blocks of consecutive rows in the Morton storage order)
   std::vector<int32_t> t_hptr[ks_ctx::NTILE], t_hcol[ks_ctx::NTILE], t_hself[ks_ctx::NTILE];
   std::vector<uint16_t> t_lcol[ks_ctx::NTILE];
-  std::vector<uint8_t> t_rperm[ks_ctx::NTILE];
+  std::vector<int32_t> t_pptr[ks_ctx::NTILE];
+  // padded index runs: row r's local indices start at prp[r], a multiple of 8
+  std::vector<int64_t> prp(N + 1, 0);
+  for (int r = 0; r < N; ++r) prp[r + 1] = prp[r] + (rowptr[r + 1] - rowptr[r] + 7) / 8 * 8;
+  std::vector<uint32_t> t_rmeta[ks_ctx::NTILE];
   for (int ti = 0; ti < ks_ctx::NTILE; ++ti) {
     const int BR = TILE_BR[ti];
     const int nblk = (N + BR - 1) / BR;
     std::vector<std::vector<int32_t>> halos(nblk);
-    t_lcol[ti].assign(c->nnz, 0);
+    t_lcol[ti].assign((size_t)prp[N], 0);
     std::vector<int> ok(nblk, 1);
     parallel_for(nblk, [&](int64_t b) {
       const int r0 = (int)b * BR, r1 = std::min(N, r0 + BR);
@@ -602,8 +606,10 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
         ok[b] = 0;
         return;
       }
-      for (int64_t j = rowptr[r0]; j < rowptr[r1]; ++j)
-        t_lcol[ti][j] = (uint16_t)(std::lower_bound(h.begin(), h.end(), colI[j]) - h.begin());
+      for (int r = r0; r < r1; ++r)
+        for (int64_t j = rowptr[r]; j < rowptr[r + 1]; ++j)
+          t_lcol[ti][prp[r] + (j - rowptr[r])] =
+              (uint16_t)(std::lower_bound(h.begin(), h.end(), colI[j]) - h.begin());
     });
     bool all = true;
     for (int b = 0; b < nblk; ++b) all = all && ok[b];
@@ -630,17 +636,38 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       c->til[ti] = Tiling();
       continue;
     }
+    // the packed row slots need block nonzero offsets below 2^16 and rows
+    // of at most 255 nonzeros
+    bool fits = mnz < 65536 && prp[N] < ((int64_t)1 << 31);
+    for (int r = 0; r < N && fits; ++r) fits = rowptr[r + 1] - rowptr[r] <= 255;
+    if (!fits) {
+      c->til[ti] = Tiling();
+      continue;
+    }
     c->til[ti].max_nnz = mnz;
+    t_pptr[ti].assign(nblk + 1, 0);
+    int mpz = 0;
+    for (int b = 0; b <= nblk; ++b) t_pptr[ti][b] = (int32_t)prp[std::min(N, b * BR)];
+    for (int b = 0; b < nblk; ++b) mpz = std::max(mpz, t_pptr[ti][b + 1] - t_pptr[ti][b]);
+    c->til[ti].max_pnz = mpz;
     // within each block: longest rows first (stable), so that a wavefront's
-    // rows have similar nonzero counts
-    t_rperm[ti].resize(N);
+    // rows have similar nonzero counts; each slot packs the row's offset in
+    // the block, its nonzero count and its first nonzero (block-relative)
+    t_rmeta[ti].resize((size_t)2 * N);
     parallel_for(nblk, [&](int64_t b) {
       const int r0 = (int)b * BR, nr = std::min(BR, N - r0);
-      uint8_t *o = t_rperm[ti].data() + r0;
-      for (int rr = 0; rr < nr; ++rr) o[rr] = (uint8_t)rr;
-      std::stable_sort(o, o + nr, [&](uint8_t x, uint8_t y) {
+      std::vector<int> o(nr);
+      for (int rr = 0; rr < nr; ++rr) o[rr] = rr;
+      std::stable_sort(o.begin(), o.end(), [&](int x, int y) {
         return rowptr[r0 + x + 1] - rowptr[r0 + x] > rowptr[r0 + y + 1] - rowptr[r0 + y];
       });
+      for (int s = 0; s < nr; ++s) {
+        const int rr = o[s];
+        const uint32_t rel = (uint32_t)(rowptr[r0 + rr] - rowptr[r0]);
+        const uint32_t len = (uint32_t)(rowptr[r0 + rr + 1] - rowptr[r0 + rr]);
+        t_rmeta[ti][2 * (size_t)(r0 + s)] = rel | (len << 16) | ((uint32_t)rr << 24);
+        t_rmeta[ti][2 * (size_t)(r0 + s) + 1] = (uint32_t)(prp[r0 + rr] - prp[r0]);
+      }
     });
     t_hcol[ti].resize(t_hptr[ti][nblk]);
     parallel_for(nblk, [&](int64_t b) {
@@ -971,7 +998,8 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       A_(til[ti].halo_col, t_hcol[ti].size() + 8);  // 16-byte chunk reads past the end
       A_(til[ti].hself, t_hself[ti].size());
       A_(til[ti].lcol, t_lcol[ti].size() + 16);  // 16-byte chunk reads past the end
-      A_(til[ti].rperm, t_rperm[ti].size());
+      A_(til[ti].pptr, t_pptr[ti].size());
+      A_(til[ti].rmeta, t_rmeta[ti].size());
     }
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
@@ -1035,7 +1063,8 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       if (!t_hcol[ti].empty()) H2D(c->til[ti].halo_col, t_hcol[ti].data(), t_hcol[ti].size());
       H2D(c->til[ti].hself, t_hself[ti].data(), t_hself[ti].size());
       if (!t_lcol[ti].empty()) H2D(c->til[ti].lcol, t_lcol[ti].data(), t_lcol[ti].size());
-      H2D(c->til[ti].rperm, t_rperm[ti].data(), t_rperm[ti].size());
+      H2D(c->til[ti].pptr, t_pptr[ti].data(), t_pptr[ti].size());
+      H2D(c->til[ti].rmeta, t_rmeta[ti].data(), t_rmeta[ti].size());
     }
   {
     const char *env = std::getenv("KS_ROW_ORDER");

@@ -345,12 +345,13 @@ struct TLayout {
   int total;
 };
 __host__ __device__ __forceinline__ int round_kb(int b) { return (b + 1023) / 1024 * 1024; }
-__host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nnz, int rowbytes, int elem) {
+__host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nnz, int max_pnz, int rowbytes,
+                                                        int elem) {
   TLayout L;
   L.halo = 0;
   L.vals = round_kb(max_halo * rowbytes);
   L.idx = L.vals + round_kb(max_nnz * elem + 32);
-  L.total = L.idx + round_kb(max_nnz * 2 + 32);
+  L.total = L.idx + round_kb(max_pnz * 2 + 32);
   return L;
 }
 
@@ -360,101 +361,180 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // into P are 32-bit).  All checked by the host.
 // MODE 0: the PCG phase (Q = S P, p.q partials, skipped once the solver
 // stopped); MODE 1: Q = S P; MODE 2: Q = B - S P.
+//
+// Every address a block's copies need is in registers before the block
+// starts: while block i is computed from LDS, each lane fetches the halo
+// list entries of its first PC copy chunks of block i+1 (and that block's
+// CSR range and its first row slot), so that the copies of block i+1 issue
+// back to back instead of one dependent index load each.
 template <typename T, int VW, int HCB, int TB, int MODE>
 __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, int BR, int nblk, int max_halo,
-                                                int max_nnz,
+                                                int max_nnz, int max_pnz,
                                                 const int32_t *__restrict__ halo_ptr,
                                                 const int32_t *__restrict__ halo_col,
                                                 const int32_t *__restrict__ hself,
                                                 const int32_t *__restrict__ rowptr,
                                                 const uint16_t *__restrict__ lcol,
-                                                const uint8_t *__restrict__ rperm,
+                                                const int32_t *__restrict__ pptr,
+                                                const uint32_t *__restrict__ rmeta,
                                                 const T *__restrict__ val, const T *__restrict__ P,
                                                 T *__restrict__ Q, double *__restrict__ part,
                                                 const Control *ctl, const T *__restrict__ Bm) {
   if (MODE == 0 && ctl && ctl->stop) return;
   extern __shared__ __align__(16) unsigned char t_smem[];
+  constexpr int PC = 8;  // copy chunks per lane whose halo rows are fetched one block ahead
   const int CG = k / VW;
   const unsigned rowbytes = (unsigned)k * sizeof(T);   // one halo row in LDS
   const unsigned pitch = (unsigned)ldp * sizeof(T);     // one row of P in memory
   const int CH = (int)rowbytes / HCB;
-  const TLayout L = tile_layout(max_halo, max_nnz, (int)rowbytes, (int)sizeof(T));
+  const TLayout L = tile_layout(max_halo, max_nnz, max_pnz, (int)rowbytes, (int)sizeof(T));
   // fixed (row slot, column group) per thread: RPP rows per pass
   const int RPP = (int)blockDim.x / CG;
   const int cg = threadIdx.x % CG, rslot = threadIdx.x / CG;
   const bool active = rslot < RPP;
-  // halo copy: this lane's first chunk (h0c, ch0c) and the per-pass stride
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, per = (int)blockDim.x;
-  const int h0c = (wave * 64 + lane) / CH, ch0c = (wave * 64 + lane) - h0c * CH;
-  const int dh = per / CH, dch = per - dh * CH;
+  // copy chunk c = wave 64 + lane + i TB of a block is byte (c % CH) HCB of
+  // halo row c / CH; for i < PC: hpb[i] = (c / CH) << 10 | (c % CH) HCB
+  // (a halo row is at most 512 bytes)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned hpb[PC];
+#pragma unroll
+  for (int i = 0; i < PC; ++i) {
+    const int c = wave * 64 + lane + i * TB;
+    const int h = c / CH;
+    hpb[i] = ((unsigned)h << 10) | (unsigned)((c - h * CH) * HCB);
+  }
+  // chunks from i = PC on (rare: halos above PC TB / CH rows) walk on from here
+  const int cr = wave * 64 + lane + PC * TB;
+  const int hr0 = cr / CH, chr0 = cr - hr0 * CH;
+  const int dh = TB / CH, dch = TB - dh * CH;
   double apq[VW];
   for (int v = 0; v < VW; ++v) apq[v] = 0.0;
   const unsigned char *Pb = reinterpret_cast<const unsigned char *>(P);
   const unsigned char *Vb = reinterpret_cast<const unsigned char *>(val);
   const unsigned char *Ib = reinterpret_cast<const unsigned char *>(lcol);
-  for (GroupIter gi = group_iter(nblk); gi.g < gi.end; gi.g += gi.step) {
-    const int b = gi.g;
-    const int hb0 = halo_ptr[b], nh = halo_ptr[b + 1] - hb0;
+  const GroupIter gi = group_iter(nblk);
+  // the block about to be copied: halo list start and size, CSR range,
+  // padded index range, halo rows of this lane's first PC chunks, first row
+  // slot of this lane
+  int hb0 = 0, nh = 0, j0 = 0, j1 = 0, p0 = 0, p1 = 0;
+  int hrow[PC];
+  uint2 rm0 = make_uint2(0u, 0u);
+  const uint2 *rm2 = reinterpret_cast<const uint2 *>(rmeta);
+  if (gi.g < gi.end) {
+    const int b = gi.g, r0 = b * BR, nr = min(BR, N - r0);
+    hb0 = halo_ptr[b];
+    nh = halo_ptr[b + 1] - hb0;
+    j0 = rowptr[r0];
+    j1 = rowptr[r0 + nr];
+    p0 = pptr[b];
+    p1 = pptr[b + 1];
+#pragma unroll
+    for (int i = 0; i < PC; ++i) {
+      const int h = (int)(hpb[i] >> 10);
+      hrow[i] = halo_col[hb0 + (h < nh ? h : 0)];  // unconditional loads: one wait covers all
+    }
+    if (active && rslot < nr) rm0 = rm2[r0 + rslot];
+  }
+  for (int b = gi.g; b < gi.end; b += gi.step) {
     const int r0 = b * BR, nr = min(BR, N - r0);
-    const int j0 = rowptr[r0], j1 = rowptr[r0 + nr];
-    __syncthreads();  // the previous block is done with the LDS image
+    const int hs = hself[b];  // halo position of row r0; rows r0.. are consecutive there
+    __syncthreads();          // the previous block is done with the LDS image
+    // the fetched halo rows are in (one wait here, none between the copies)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     {
-      const int32_t *hl = halo_col + hb0;
-      const int total = nh * CH;
-      int h = h0c, ch = ch0c;
-      for (int c0 = wave * 64; c0 < total; c0 += per) {
-        if (c0 + lane < total) {
-          const unsigned off = (unsigned)hl[h] * pitch + (unsigned)(ch * HCB);
-          lds_void_t *d = (lds_void_t *)(t_smem + L.halo + (unsigned)c0 * HCB);
+      unsigned char *dst = t_smem + L.halo + (unsigned)(wave * 64) * HCB;
+#pragma unroll
+      for (int i = 0; i < PC; ++i) {
+        if ((int)(hpb[i] >> 10) < nh) {
+          const unsigned off = (unsigned)hrow[i] * pitch + (hpb[i] & 1023u);
+          lds_void_t *d = (lds_void_t *)(dst + (unsigned)(i * TB) * HCB);
           if constexpr (HCB == 16) __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 16, 0, 0);
           else __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 4, 0, 0);
         }
-        h += dh;
-        ch += dch;
-        if (ch >= CH) {
-          ch -= CH;
-          h += 1;
+      }
+      const int total = nh * CH;
+      if (wave * 64 + PC * TB < total) {
+        const int32_t *hl = halo_col + hb0;
+        int h = hr0, ch = chr0;
+        for (int c0 = wave * 64 + PC * TB; c0 < total; c0 += TB) {
+          if (c0 + lane < total) {
+            const unsigned off = (unsigned)hl[h] * pitch + (unsigned)(ch * HCB);
+            lds_void_t *d = (lds_void_t *)(t_smem + L.halo + (unsigned)c0 * HCB);
+            if constexpr (HCB == 16) __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 16, 0, 0);
+            else __builtin_amdgcn_global_load_lds((gbl_void_t *)(Pb + off), d, 4, 0, 0);
+          }
+          h += dh;
+          ch += dch;
+          if (ch >= CH) {
+            ch -= CH;
+            h += 1;
+          }
         }
       }
     }
     const int64_t va = ((int64_t)j0 * sizeof(T)) & ~(int64_t)15;
     const int64_t vb = ((int64_t)j1 * sizeof(T) + 15) & ~(int64_t)15;
     dma<16>((int)((vb - va) / 16), t_smem + L.vals, [&](int c) { return Vb + va + (int64_t)c * 16; });
-    const int64_t ia = ((int64_t)j0 * 2) & ~(int64_t)15;
-    const int64_t ib = ((int64_t)j1 * 2 + 15) & ~(int64_t)15;
-    dma<16>((int)((ib - ia) / 16), t_smem + L.idx, [&](int c) { return Ib + ia + (int64_t)c * 16; });
+    // padded index runs: 16-byte aligned at both ends
+    dma<16>((p1 - p0) / 8, t_smem + L.idx, [&](int c) { return Ib + (int64_t)p0 * 2 + (int64_t)c * 16; });
+    // this block's values in LDS, addressed from its first nonzero; its
+    // index runs from the image start
+    const T *vs = reinterpret_cast<const T *>(t_smem + L.vals + ((int64_t)j0 * sizeof(T) - va));
+    const uint16_t *is = reinterpret_cast<const uint16_t *>(t_smem + L.idx);
+    const uint2 m0 = rm0;
+    // the next block's list range and CSR range (scalar loads, land with the copies)
+    const int bn = b + gi.step;
+    const bool more = bn < gi.end;
+    int r0n = 0, nrn = 0;
+    if (more) {
+      r0n = bn * BR;
+      nrn = min(BR, N - r0n);
+      hb0 = halo_ptr[bn];
+      nh = halo_ptr[bn + 1] - hb0;
+      j0 = rowptr[r0n];
+      j1 = rowptr[r0n + nrn];
+      p0 = pptr[bn];
+      p1 = pptr[bn + 1];
+    }
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
     __syncthreads();                // ... and every wave's
+    // the next block's halo rows and first row slot, in flight while this
+    // block is computed
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < PC; ++i) {
+        const int h = (int)(hpb[i] >> 10);
+        hrow[i] = halo_col[hb0 + (h < nh ? h : 0)];
+      }
+      rm0 = (active && rslot < nrn) ? rm2[r0n + rslot] : make_uint2(0u, 0u);
+    }
     const T *xs = reinterpret_cast<const T *>(t_smem + L.halo) + cg * VW;
-    const T *vs = reinterpret_cast<const T *>(t_smem + L.vals + ((int64_t)j0 * sizeof(T) - va)) - j0;
-    const uint16_t *is = reinterpret_cast<const uint16_t *>(t_smem + L.idx + ((int64_t)j0 * 2 - ia)) - j0;
-    const int hs = hself[b];  // halo position of row r0; rows r0.. are consecutive there
     for (int rs = rslot; active && rs < nr; rs += RPP) {
-      const int rr = rperm[r0 + rs];  // longest rows first
+      const uint2 m = rs == rslot ? m0 : rm2[r0 + rs];
+      const int rr = (int)(m.x >> 24);  // longest rows first
       const int row = r0 + rr;
+      const int jb = (int)(m.x & 0xffffu), len = (int)((m.x >> 16) & 0xffu);
+      const uint16_t *ir = is + m.y;  // this row's index run, 16-byte aligned
       T acc[VW];
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
-      const int jb = rowptr[row], je = rowptr[row + 1];
-      int j = jb;
-      constexpr int U = (VW * sizeof(T) > 16) ? 4 : 8;
-      for (; j + U <= je; j += U) {
-        int li[U];
-        T vv[U];
+      // eight nonzeros per step: one aligned 16-byte read of their local
+      // indices (the run's padding points at halo row 0 with weight 0)
+      for (int j = 0; j < len; j += 8) {
+        const uint4 iw = *reinterpret_cast<const uint4 *>(ir + j);
+        const int li[8] = {(int)(iw.x & 0xffffu), (int)(iw.x >> 16), (int)(iw.y & 0xffffu), (int)(iw.y >> 16),
+                           (int)(iw.z & 0xffffu), (int)(iw.z >> 16), (int)(iw.w & 0xffffu), (int)(iw.w >> 16)};
+        // the weights past the row's end are read (inside the LDS image)
+        // and replaced by zero
+        T vv[8];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          li[u] = is[j + u];
-          vv[u] = vs[j + u];
-        }
+        for (int u = 0; u < 8; ++u) vv[u] = vs[jb + j + u];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < 8; ++u) vv[u] = (j + u < len) ? vv[u] : T(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
           const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], k));
           for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
         }
-      }
-      for (; j < je; ++j) {
-        const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(is[j], k));
-        const T w = vs[j];
-        for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
       }
       if constexpr (MODE == 0) {
         const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
@@ -484,7 +564,7 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
 
 size_t tiled_lds_bytes(const Tiling &t, int k, size_t elem) {
   if (!t.nblk || (k * elem) % 4 != 0) return 0;
-  return (size_t)tile_layout(t.max_halo, t.max_nnz, k * (int)elem, (int)elem).total;
+  return (size_t)tile_layout(t.max_halo, t.max_nnz, t.max_pnz, k * (int)elem, (int)elem).total;
 }
 
 // launch shape of the tiled SpMM for this operator: VW, halo chunk, grid, LDS
@@ -527,7 +607,8 @@ static int launch_tpcg_A_t(int N, int k, int ldp, int ldq, const Tiling &t, cons
   }
   hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, ldp, ldq, t.BR,
                      t.nblk,
-                     t.max_halo, t.max_nnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, t.rperm, val, P, Q, part,
+                     t.max_halo, t.max_nnz, t.max_pnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, t.pptr, t.rmeta,
+                     val, P, Q, part,
                      ctl, Bm);
   return 0;
 }
@@ -619,8 +700,16 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
   const int t = threadIdx.x;
   double acc = 0.0;
   if (t < G * W) {
+    // partials b = g, g + G, g + 2G, ... added in that order; eight loads
+    // in flight per step
     const int c = t % W, g = t / W;
-    for (int b = g; b < nblk; b += G) acc += part[(int64_t)b * W + c];
+    for (int b = g; b < nblk; b += 8 * G) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (b + u * G < nblk) ? part[(int64_t)(b + u * G) * W + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
   }
   s_red[t] = acc;
   __syncthreads();
