@@ -1077,7 +1077,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     c->ng32 = geti("KS_SPMM_NG32");
     c->ngP = geti("KS_SPMM_NGP");
     // SpMM phase kernel before any autotuning: halo tiles of 85 rows with
-    // 1024 threads (FP64), 85 rows with 512 threads (FP32), 128 rows with 512
+    // 1024 threads (FP64), 85 rows with 512 threads (FP32), 128 rows with 256
     // threads (Poisson, one column); KS_TILE64/32/P = rows (0 = row kernel),
     // KS_TILE64_TB/32_TB/P_TB = threads
     auto tile_env = [&](const char *n, int dflt, const char *ntb, int dtb) {
@@ -1098,7 +1098,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     }
     c->tile64 = tile_env("KS_TILE64", 85, "KS_TILE64_TB", 1024);
     c->tile32 = tile_env("KS_TILE32", 85, "KS_TILE32_TB", 512);
-    c->tileP = tile_env("KS_TILEP", 128, "KS_TILEP_TB", 512);
+    c->tileP = tile_env("KS_TILEP", 128, "KS_TILEP_TB", 256);
     apply_tiles(c);
   }
   H2D(c->colB, colB.data(), colB.size());

@@ -2,6 +2,12 @@
 
     python -m paper_2404_19249_amd.profiling stats <dir>/run_kernel_trace.csv [--top N]
     python -m paper_2404_19249_amd.profiling pmc <dir>/run_counter_collection.csv [--regex R]
+    python -m paper_2404_19249_amd.profiling traffic <fetch.csv> --write <write.csv> --regex R
+
+`traffic` gives the HBM bytes per launch of the kernels matching R as
+FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB x 1024, medians over dispatches): on
+this device a plain 1 GiB device copy reads back FETCH_SIZE = half the bytes
+it copies and WRITE_SIZE = all of them.
 
 Kernel launches of the block PCG that return at once (issued after the
 solver converged, between two host polls) last a few microseconds; the
@@ -45,15 +51,28 @@ def pmc(path, regex=None):
         print(f"{c:>14} {g:>8} {len(v):5d} {statistics.median(v):12.4g} {max(v):12.4g}  {k}")
 
 
+def traffic(fetch_path, write_path, regex):
+    def med(path, counter):
+        v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+             if r["Counter_Name"] == counter and re.search(regex, r["Kernel_Name"])]
+        return statistics.median(v), len(v)
+    (f, nf), (w, nw) = med(fetch_path, "FETCH_SIZE"), med(write_path, "WRITE_SIZE")
+    print(f"FETCH_SIZE median {f:.6g} KiB ({nf} dispatches), WRITE_SIZE median {w:.6g} KiB ({nw} dispatches)")
+    print(f"traffic per launch: {int(round((2 * f + w) * 1024))} bytes")
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "pmc"])
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic"])
     ap.add_argument("path")
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--regex", default=None)
     ap.add_argument("--active-us", type=float, default=20.0)
+    ap.add_argument("--write", default=None)
     a = ap.parse_args()
     if a.mode == "stats":
         stats(a.path, a.top, a.active_us)
-    else:
+    elif a.mode == "pmc":
         pmc(a.path, a.regex)
+    else:
+        traffic(a.path, a.write, a.regex)
