@@ -116,10 +116,15 @@ struct Tiling {
   int max_pnz = 0;           // most padded local indices in one block
   int32_t *halo_ptr = nullptr, *halo_col = nullptr;
   int32_t *hself = nullptr;  // [nblk] position of the block's first row in its halo
-  // local (halo) column indices, each row's run padded with index 0 to a
-  // multiple of 8 entries, so that every run starts on a 16-byte boundary;
-  // pptr [nblk + 1]: start of each block's runs
+  // local (halo) column indices, each row's run padded to a multiple of 8
+  // entries with index max_halo (a halo row the kernel keeps at zero), so
+  // that every run starts on a 16-byte boundary; pptr [nblk + 1]: start of
+  // each block's runs
   uint16_t *lcol = nullptr;
+  // the same runs as LDS byte offsets lcol[j] * lb_rowbytes, for halo rows
+  // of lb_rowbytes bytes (present when max_halo * lb_rowbytes < 2^16)
+  uint16_t *lbyte = nullptr;
+  int lb_rowbytes = 0;
   int32_t *pptr = nullptr;
   // [N][2] per row slot of each block, rows with more nonzeros first (so
   // that the rows one wavefront walks together have similar lengths): word 0

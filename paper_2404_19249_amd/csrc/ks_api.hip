@@ -584,7 +584,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   });
   // halo tilings (row blocks of consecutive rows in the Morton storage order)
   std::vector<int32_t> t_hptr[ks_ctx::NTILE], t_hcol[ks_ctx::NTILE], t_hself[ks_ctx::NTILE];
-  std::vector<uint16_t> t_lcol[ks_ctx::NTILE];
+  std::vector<uint16_t> t_lcol[ks_ctx::NTILE], t_lbyte[ks_ctx::NTILE];
   std::vector<int32_t> t_pptr[ks_ctx::NTILE];
   // padded index runs: row r's local indices start at prp[r], a multiple of 8
   std::vector<int64_t> prp(N + 1, 0);
@@ -602,7 +602,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       h.assign(colI.begin() + rowptr[r0], colI.begin() + rowptr[r1]);
       std::sort(h.begin(), h.end());
       h.erase(std::unique(h.begin(), h.end()), h.end());
-      if (h.size() > 65535) {
+      if (h.size() > 65534) {  // local indices and the zero row index fit 16 bits
         ok[b] = 0;
         return;
       }
@@ -620,6 +620,11 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       t_hptr[ti][b + 1] = t_hptr[ti][b] + (int32_t)halos[b].size();
       mx = std::max(mx, (int)halos[b].size());
     }
+    // padding slots of every index run point at halo row mx, which the
+    // kernel keeps at zero: the padded nonzeros add exact zeros
+    parallel_for(N, [&](int64_t r) {
+      for (int64_t q = prp[r] + (rowptr[r + 1] - rowptr[r]); q < prp[r + 1]; ++q) t_lcol[ti][q] = (uint16_t)mx;
+    });
     int mnz = 0;
     t_hself[ti].resize(nblk);
     for (int b = 0; b < nblk; ++b) {
@@ -998,6 +1003,12 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       A_(til[ti].halo_col, t_hcol[ti].size() + 8);  // 16-byte chunk reads past the end
       A_(til[ti].hself, t_hself[ti].size());
       A_(til[ti].lcol, t_lcol[ti].size() + 16);  // 16-byte chunk reads past the end
+      // byte-offset runs for FP32 halo rows of k_max columns
+      const int rb = km * (int)sizeof(float);
+      if ((int64_t)c->til[ti].max_halo * rb < 65536 && rb % 16 == 0) {
+        c->til[ti].lb_rowbytes = rb;
+        A_(til[ti].lbyte, t_lcol[ti].size() + 16);
+      }
       A_(til[ti].pptr, t_pptr[ti].size());
       A_(til[ti].rmeta, t_rmeta[ti].size());
     }
@@ -1063,6 +1074,12 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       if (!t_hcol[ti].empty()) H2D(c->til[ti].halo_col, t_hcol[ti].data(), t_hcol[ti].size());
       H2D(c->til[ti].hself, t_hself[ti].data(), t_hself[ti].size());
       if (!t_lcol[ti].empty()) H2D(c->til[ti].lcol, t_lcol[ti].data(), t_lcol[ti].size());
+      if (c->til[ti].lbyte && !t_lcol[ti].empty()) {
+        const int rb = c->til[ti].lb_rowbytes;
+        t_lbyte[ti].resize(t_lcol[ti].size());
+        parallel_for((int64_t)t_lcol[ti].size(), [&](int64_t q) { t_lbyte[ti][q] = (uint16_t)(t_lcol[ti][q] * rb); });
+        H2D(c->til[ti].lbyte, t_lbyte[ti].data(), t_lbyte[ti].size());
+      }
       H2D(c->til[ti].pptr, t_pptr[ti].data(), t_pptr[ti].size());
       H2D(c->til[ti].rmeta, t_rmeta[ti].data(), t_rmeta[ti].size());
     }

@@ -337,9 +337,10 @@ __device__ __forceinline__ void dma(int nchunks, unsigned char *lds, F src_of) {
   }
 }
 
-// LDS layout of one block: halo image, values, local indices; every region
-// a whole number of 1 KB wave fills.  Several workgroups per CU overlap one
-// block's copies with another block's arithmetic.
+// LDS layout of one block: halo image (max_halo rows, then one row of zeros
+// that the index runs' padding points at), values, local indices; every
+// region a whole number of 1 KB wave fills.  Several workgroups per CU
+// overlap one block's copies with another block's arithmetic.
 struct TLayout {
   int halo, vals, idx;  // byte offsets
   int total;
@@ -349,7 +350,7 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
                                                         int elem) {
   TLayout L;
   L.halo = 0;
-  L.vals = round_kb(max_halo * rowbytes);
+  L.vals = round_kb((max_halo + 1) * rowbytes);
   L.idx = L.vals + round_kb(max_nnz * elem + 32);
   L.total = L.idx + round_kb(max_pnz * 2 + 32);
   return L;
@@ -361,13 +362,15 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // into P are 32-bit).  All checked by the host.
 // MODE 0: the PCG phase (Q = S P, p.q partials, skipped once the solver
 // stopped); MODE 1: Q = S P; MODE 2: Q = B - S P.
+// SC: lcol holds LDS byte offsets of the halo rows (local index x rowbytes)
+// instead of local indices, which saves one address instruction per nonzero.
 //
 // Every address a block's copies need is in registers before the block
 // starts: while block i is computed from LDS, each lane fetches the halo
 // list entries of its first PC copy chunks of block i+1 (and that block's
 // CSR range and its first row slot), so that the copies of block i+1 issue
 // back to back instead of one dependent index load each.
-template <typename T, int VW, int HCB, int TB, int MODE>
+template <typename T, int VW, int HCB, int TB, int MODE, bool SC>
 __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, int BR, int nblk, int max_halo,
                                                 int max_nnz, int max_pnz,
                                                 const int32_t *__restrict__ halo_ptr,
@@ -413,6 +416,12 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
   const unsigned char *Vb = reinterpret_cast<const unsigned char *>(val);
   const unsigned char *Ib = reinterpret_cast<const unsigned char *>(lcol);
   const GroupIter gi = group_iter(nblk);
+  // the zero halo row, and the value region (read up to 7 entries past a
+  // row's end, always finite after this)
+  for (unsigned o = threadIdx.x * 4; o < rowbytes; o += TB * 4)
+    *reinterpret_cast<float *>(t_smem + L.halo + (unsigned)max_halo * rowbytes + o) = 0.f;
+  for (int o = threadIdx.x * 16; o < L.idx - L.vals; o += TB * 16)
+    *reinterpret_cast<uint4 *>(t_smem + L.vals + o) = make_uint4(0u, 0u, 0u, 0u);
   // the block about to be copied: halo list start and size, CSR range,
   // padded index range, halo rows of this lane's first PC chunks, first row
   // slot of this lane
@@ -509,6 +518,7 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
       rm0 = (active && rslot < nrn) ? rm2[r0n + rslot] : make_uint2(0u, 0u);
     }
     const T *xs = reinterpret_cast<const T *>(t_smem + L.halo) + cg * VW;
+    const unsigned char *xsb = t_smem + L.halo + cg * VW * sizeof(T);
     for (int rs = rslot; active && rs < nr; rs += RPP) {
       const uint2 m = rs == rslot ? m0 : rm2[r0 + rs];
       const int rr = (int)(m.x >> 24);  // longest rows first
@@ -518,21 +528,20 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
       T acc[VW];
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
       // eight nonzeros per step: one aligned 16-byte read of their local
-      // indices (the run's padding points at halo row 0 with weight 0)
+      // indices.  Slots past the row's end point at the zero halo row; their
+      // weights (the following entries of the LDS value image, finite) then
+      // add exact zeros.
       for (int j = 0; j < len; j += 8) {
         const uint4 iw = *reinterpret_cast<const uint4 *>(ir + j);
-        const int li[8] = {(int)(iw.x & 0xffffu), (int)(iw.x >> 16), (int)(iw.y & 0xffffu), (int)(iw.y >> 16),
-                           (int)(iw.z & 0xffffu), (int)(iw.z >> 16), (int)(iw.w & 0xffffu), (int)(iw.w >> 16)};
-        // the weights past the row's end are read (inside the LDS image)
-        // and replaced by zero
+        const unsigned li[8] = {iw.x & 0xffffu, iw.x >> 16, iw.y & 0xffffu, iw.y >> 16,
+                                iw.z & 0xffffu, iw.z >> 16, iw.w & 0xffffu, iw.w >> 16};
         T vv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) vv[u] = vs[jb + j + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = (j + u < len) ? vv[u] : T(0);
-#pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const VecT<T, VW> x = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], k));
+          const VecT<T, VW> x = SC ? *reinterpret_cast<const VecT<T, VW> *>(xsb + li[u])
+                                   : *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], (unsigned)k));
           for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
         }
       }
@@ -594,23 +603,26 @@ static TShape tiled_shape(const Tiling &t, int k, int N, int nblk_max, int tb, i
   return sh;
 }
 
-template <typename T, int VW, int HCB, int TB, int MODE>
+template <typename T, int VW, int HCB, int TB, int MODE, bool SC = false>
 static int launch_tpcg_A_t(int N, int k, int ldp, int ldq, const Tiling &t, const TShape &sh,
                            const int32_t *rowptr, const T *val, const T *P, T *Q, double *part, const Control *ctl,
                            const T *Bm, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB, MODE>,
+    if (hipFuncSetAttribute((const void *)k_tpcg_A<T, VW, HCB, TB, MODE, SC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)TILE_LDS_MAX) != hipSuccess)
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, ldp, ldq, t.BR,
-                     t.nblk,
-                     t.max_halo, t.max_nnz, t.max_pnz, t.halo_ptr, t.halo_col, t.hself, rowptr, t.lcol, t.pptr, t.rmeta,
-                     val, P, Q, part,
-                     ctl, Bm);
+  hipLaunchKernelGGL((k_tpcg_A<T, VW, HCB, TB, MODE, SC>), dim3(sh.grid), dim3(TB), sh.lds, s, N, k, ldp, ldq,
+                     t.BR, t.nblk, t.max_halo, t.max_nnz, t.max_pnz, t.halo_ptr, t.halo_col, t.hself, rowptr,
+                     SC ? t.lbyte : t.lcol, t.pptr, t.rmeta, val, P, Q, part, ctl, Bm);
   return 0;
+}
+// the byte-offset index runs serve FP32 halo rows of exactly lb_rowbytes
+template <typename T>
+static bool use_lbyte(const Tiling &t, const TShape &sh, int k) {
+  return sizeof(T) == 4 && sh.VW == 4 && sh.HCB == 16 && t.lbyte && k * (int)sizeof(T) == t.lb_rowbytes;
 }
 template <typename T, int MODE>
 static int launch_tpcg_A_m(int N, int k, int ldp, int ldq, const Tiling &t, const TShape &sh,
@@ -619,6 +631,16 @@ static int launch_tpcg_A_m(int N, int k, int ldp, int ldq, const Tiling &t, cons
   constexpr int V16 = 16 / sizeof(T);
 #define KS_TL(VW, HCB, TB) \
   return launch_tpcg_A_t<T, VW, HCB, TB, MODE>(N, k, ldp, ldq, t, sh, rowptr, val, P, Q, part, ctl, Bm, s)
+#define KS_TLS(TB) \
+  return launch_tpcg_A_t<T, V16, 16, TB, MODE, true>(N, k, ldp, ldq, t, sh, rowptr, val, P, Q, part, ctl, Bm, s)
+  if constexpr (sizeof(T) == 4) {
+    if (use_lbyte<T>(t, sh, k)) {
+      if (sh.TB == 1024) KS_TLS(1024);
+      if (sh.TB == 512) KS_TLS(512);
+      KS_TLS(256);
+    }
+  }
+#undef KS_TLS
   if (sh.TB == 1024) {
     if (sh.VW == V16) KS_TL(V16, 16, 1024);
     if (sh.HCB == 16) KS_TL(1, 16, 1024);
