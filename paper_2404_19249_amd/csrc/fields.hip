@@ -244,18 +244,39 @@ void launch_moments(const double *coords, const int32_t *elems, int n_loc, int n
                      n_e, n_q, bary, w, absdet, rho, center, part, nvals);
 }
 
-__global__ void __launch_bounds__(256) k_reduce_cols(const double *__restrict__ part, int nblk,
-                                                     int nvals, double *__restrict__ out) {
-  __shared__ double sh[16];
-  for (int j = 0; j < nvals; ++j) {
+// out[j] = sum_b part[b][j]: all columns at once (threads t = g W + c take
+// rows b = g, g + G, ... of column c, eight loads in flight), then the G
+// group sums of each column in order; W = min(nvals, 1024) columns per pass
+__global__ void __launch_bounds__(1024) k_reduce_cols(const double *__restrict__ part, int nblk,
+                                                      int nvals, double *__restrict__ out) {
+  __shared__ double sh[1024];
+  const int t = threadIdx.x;
+  for (int c0 = 0; c0 < nvals; c0 += 1024) {
+    const int W = min(1024, nvals - c0);
+    const int G = 1024 / W;
     double a = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) a += part[(int64_t)b * nvals + j];
-    double s = block_sum(a, sh);
-    if (threadIdx.x == 0) out[j] = s;
+    if (t < G * W) {
+      const int c = c0 + t % W, g = t / W;
+      for (int b = g; b < nblk; b += 8 * G) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (b + u * G < nblk) ? part[(int64_t)(b + u * G) * nvals + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += v[u];
+      }
+    }
+    sh[t] = a;
+    __syncthreads();
+    if (t < W) {
+      double tot = 0.0;
+      for (int g = 0; g < G; ++g) tot += sh[g * W + t];
+      out[c0 + t] = tot;
+    }
+    __syncthreads();
   }
 }
 void launch_reduce_cols(const double *part, int nblk, int nvals, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, s, part, nblk, nvals, out);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(1024), 0, s, part, nblk, nvals, out);
 }
 
 // w_D = Q/|d| + p.d/|d|^3 + f sum q_ij (3 d_i d_j - delta_ij |d|^2)/|d|^5  (eq. bd)

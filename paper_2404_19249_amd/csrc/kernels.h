@@ -153,6 +153,7 @@ int launch_spmm_tiled_cols(int N, int k, int ldx, int ldy, int kc, const Tiling 
 
 struct PCGWork {
   void *R, *P, *Q;       // [N][k] of T
+  void *P2;              // [N][k] of T: directions alternate between P and P2
   void *part;            // block partials [nblk][2k] doubles
   void *state;           // device ColState[k] + control
   unsigned int *counter; // last-block counters
@@ -160,12 +161,26 @@ struct PCGWork {
   const Tiling *til;     // SpMM phase: LDS-staged halo tiles (nullptr = row kernel)
   int til_tb;            // threads per workgroup of the tiled kernel (256, 512, 1024)
   int last_iters = 0;    // iterations of the previous solve (first host poll)
+  int prep_nblk = 0;     // partial rows written by launch_refine_prep
 };
 template <typename T>
 int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *val,
               const int32_t *ord, const T *diag, const T *B, T *X, double tol, int max_iter,
               PCGWork &w, int *iters_out, double *relres_out, int *converged_out,
-              int *breakdown_out, hipStream_t s, int ng = 0, int x_zero = 0);  // x_zero: X is 0 on entry
+              int *breakdown_out, hipStream_t s, int ng = 0, int x_zero = 0);
+// x_zero: 1 = X is 0 on entry; 2 = R, P, X and the start partials were
+// written by launch_refine_prep (B unused)
+// FP32 correction-solve start of the mixed-precision refinement from the
+// FP64 residual W [N][k] and column scales sc (device, [k]): R = float(W sc),
+// P = D^{-1} R, X = 0 and the start partials, in w; then pcg_solve<float>
+// with x_zero = 2
+int launch_refine_prep(int N, int k, const double *W, const double *sc, const float *diag, float *X, PCGWork &w,
+                       hipStream_t s);
+// Y = B - S X through the halo tiles with per-workgroup column partials of
+// the squared residual in part [returned count][k]; -1 when the tiling
+// cannot serve k (nothing launched)
+int launch_residual_tiled_norms(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
+                                const double *X, double *Y, const double *B, double *part, hipStream_t s);
 size_t pcg_state_bytes(int k);
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,

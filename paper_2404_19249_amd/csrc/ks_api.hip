@@ -147,7 +147,7 @@ struct ks_ctx {
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
          *occ_d = nullptr, *scal = nullptr;
   double *PsiIn = nullptr, *Xs = nullptr;  // API-order inputs in storage order; solve output
-  float *B32 = nullptr, *X32 = nullptr;
+  float *X32 = nullptr;
   PCGWork pw64{}, pw32{}, pwP{};
   // halo tilings of the CSR pattern for the LDS-staged SpMM, row blocks of
   // TILE_BR[i] rows; chosen tiling per solver (-1 = row kernel)
@@ -1015,19 +1015,19 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
   A_(scal, 64);
-  A_(B32, (size_t)N * km);
   A_(X32, (size_t)N * km);
   A_(counters, 16);
   {
     const int nblk = 2048;
     auto mk = [&](PCGWork &w, size_t elem, int k, int cidx) -> int {
-      void *r, *p, *q, *part, *st;
+      void *r, *p, *p2, *q, *part, *st;
       if (c->alloc(reinterpret_cast<char **>(&r), elem * N * k) < 0) return -1;
       if (c->alloc(reinterpret_cast<char **>(&p), elem * N * k) < 0) return -1;
+      if (c->alloc(reinterpret_cast<char **>(&p2), elem * N * k) < 0) return -1;
       if (c->alloc(reinterpret_cast<char **>(&q), elem * N * k) < 0) return -1;
       if (c->alloc(reinterpret_cast<double **>(&part), (size_t)nblk * 3 * k) < 0) return -1;
       if (c->alloc(reinterpret_cast<char **>(&st), pcg_state_bytes(k)) < 0) return -1;
-      w.R = r; w.P = p; w.Q = q; w.part = part; w.state = st;
+      w.R = r; w.P = p; w.P2 = p2; w.Q = q; w.part = part; w.state = st;
       w.counter = c->counters + cidx;
       w.nblk_max = nblk;
       return 0;
@@ -2059,10 +2059,18 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
     int total_it[MAX_K] = {0};
     conv = 0;
     for (int ref = 0; ref < max_ref; ++ref) {
-      // FP64 residual
-      spmm_op(c, c->S, X, k, c->Wv, B);
-      nb = launch_colnorms(c->N, k, c->Wv, c->redpart, s);
-      TRY(reduce_small(c, c->redpart, nb, k, rn.data()));
+      // FP64 residual and its column norms (one pass through the halo
+      // tiles when they serve k; the FP64 PCG workspace holds the partials)
+      double *npart = reinterpret_cast<double *>(c->pw64.part);
+      nb = c->pw64.til ? launch_residual_tiled_norms(c->N, k, *c->pw64.til, c->pw64.til_tb, c->rowptr, c->S, X,
+                                                     c->Wv, B, npart, s)
+                       : -1;
+      if (nb < 0) {
+        spmm_op(c, c->S, X, k, c->Wv, B);
+        npart = c->redpart;
+        nb = launch_colnorms(c->N, k, c->Wv, npart, s);
+      }
+      TRY(reduce_small(c, npart, nb, k, rn.data()));
       loc.refinements = ref + 1;
       bool all = true;
       for (int j = 0; j < k; ++j) {
@@ -2074,17 +2082,18 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
         conv = 1;
         break;
       }
-      // scaled FP32 right-hand side, FP32 PCG from zero
+      // FP32 PCG from zero on the scaled residual: one pass writes its
+      // right-hand side (the start residual), first direction, X = 0 and
+      // start partials
       HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-      launch_scale_cols(c->N, k, c->Wv, c->scal, s);
-      launch_to_float((int64_t)c->N * k, c->Wv, c->B32, s);
-      HIPCHK(hipMemsetAsync(c->X32, 0, sizeof(float) * c->N * k, s));
+      if (launch_refine_prep(c->N, k, c->Wv, c->scal, c->diagS32, c->X32, c->pw32, s) < 0)
+        return fail(KS_ERR_ARG, "FP32 correction start: unsupported k");
       int it[MAX_K] = {0};
       double rr[MAX_K];
       int c32 = 0;
-      int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, c->B32, c->X32,
+      int r = pcg_solve<float>(c->N, k, c->rowptr, c->col, c->S32, c->rorder, c->diagS32, nullptr, c->X32,
                                c->opt.mixed_inner_tol, c->opt.max_it_solve, c->pw32, it, rr, &c32,
-                               &brk, s, c->ng32, 1);
+                               &brk, s, c->ng32, 2);
       if (r < 0) return fail(KS_ERR_HIP, "FP32 PCG launch failed");
       if (brk) return fail(KS_ERR_BREAKDOWN, "FP32 PCG breakdown");
       for (int j = 0; j < k; ++j) total_it[j] += it[j];

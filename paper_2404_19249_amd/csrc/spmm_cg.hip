@@ -26,6 +26,7 @@ namespace ks {
 // per-column scalars and control words
 struct ColState {
   double rz, pq, alpha, beta, rr, bb, rz_new;
+  double alpha_prev;  // the previous iteration's alpha (its x update is deferred to this one)
   int active, iters;
 };
 struct Control {
@@ -34,7 +35,19 @@ struct Control {
   int breakdown;  // p^T S p <= 0 or NaN in an active column
   int pad;
 };
-constexpr int PCG_BLOCKS = 2048;  // workgroups of an elementwise phase (8 per CU)
+// workgroups of an elementwise phase: 512 (2 per CU, each sweeping many row
+// groups) unless KS_PCG_BLOCKS (a multiple of 8 in 256..2048) says
+// otherwise.  On the 2M-row, 24-column FP32 solve 512 streams as fast as
+// 2048 and leaves a quarter of the column partials for the one-workgroup
+// reductions between phases.
+static int pcg_blocks() {
+  static const int nb = [] {
+    const char *e = std::getenv("KS_PCG_BLOCKS");
+    const int v = e ? std::atoi(e) : 512;
+    return (v >= 256 && v <= 2048 && v % 8 == 0) ? v : 512;
+  }();
+  return nb;
+}
 constexpr int SPMM_BLOCKS = 2048; // workgroups of the SpMM phase (8 waves per SIMD)
 size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
 
@@ -361,7 +374,8 @@ __host__ __device__ __forceinline__ TLayout tile_layout(int max_halo, int max_nn
 // k * sizeof(T) % 16 == 0, else 4; N * k * sizeof(T) < 2^32 (byte offsets
 // into P are 32-bit).  All checked by the host.
 // MODE 0: the PCG phase (Q = S P, p.q partials, skipped once the solver
-// stopped); MODE 1: Q = S P; MODE 2: Q = B - S P.
+// stopped); MODE 1: Q = S P; MODE 2: Q = B - S P, with per-workgroup column
+// partials of the squared residual when part is given.
 // SC: lcol holds LDS byte offsets of the halo rows (local index x rowbytes)
 // instead of local indices, which saves one address instruction per nonzero.
 //
@@ -552,11 +566,12 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
         T b[VW];
         load_row<T, VW>(Bm, row, ldq, cg * VW, k, b);
         for (int v = 0; v < VW; ++v) acc[v] = b[v] - acc[v];
+        for (int v = 0; v < VW; ++v) apq[v] += (double)acc[v] * (double)acc[v];
       }
       store_row<T, VW>(Q, row, ldq, cg * VW, k, acc);
     }
   }
-  if constexpr (MODE != 0) return;
+  if (MODE == 1 || part == nullptr) return;
   // per-workgroup column partials (fixed order): thread t holds columns
   // [(t % CG) VW, (t % CG) VW + VW) of its rows; the LDS image is free now
   __syncthreads();
@@ -672,6 +687,17 @@ int launch_spmm_tiled(int N, int k, const Tiling &t, int tb, const int32_t *rowp
   return launch_tpcg_A_m<double, 1>(N, k, k, k, t, sh, rowptr, val, X, Y, nullptr, nullptr, nullptr, s);
 }
 
+// Y = B - S X through the halo tiles with per-workgroup column partials of
+// sum_i Y[i][c]^2 in part[b][c] (FP64, [N][k]); returns the number of
+// partial rows, or -1 (nothing launched) when the tiling cannot serve k
+int launch_residual_tiled_norms(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
+                                const double *X, double *Y, const double *B, double *part, hipStream_t s) {
+  const TShape sh = tiled_shape<double>(t, k, N, 1 << 30, tb);
+  if (sh.grid <= 0 || !B || !part) return -1;
+  if (launch_tpcg_A_m<double, 2>(N, k, k, k, t, sh, rowptr, val, X, Y, part, nullptr, B, s) < 0) return -1;
+  return sh.grid;
+}
+
 // FP32 form (Y = S X or Y = B - S X, [N][k] row-major); -1 when the tiling
 // cannot serve k FP32 columns
 int launch_spmm_tiled_f32(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const float *val,
@@ -722,15 +748,15 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
   const int t = threadIdx.x;
   double acc = 0.0;
   if (t < G * W) {
-    // partials b = g, g + G, g + 2G, ... added in that order; eight loads
-    // in flight per step
+    // partials b = g, g + G, g + 2G, ... added in that order; sixteen
+    // loads in flight per step
     const int c = t % W, g = t / W;
-    for (int b = g; b < nblk; b += 8 * G) {
-      double v[8];
+    for (int b = g; b < nblk; b += 16 * G) {
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (b + u * G < nblk) ? part[(int64_t)(b + u * G) * W + c] : 0.0;
+      for (int u = 0; u < 16; ++u) v[u] = (b + u * G < nblk) ? part[(int64_t)(b + u * G) * W + c] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += v[u];
+      for (int u = 0; u < 16; ++u) acc += v[u];
     }
   }
   s_red[t] = acc;
@@ -796,6 +822,65 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
   block_cols<VW, NG>(arz, m, k, CG, s_red, part, 3 * k, 2 * k);
 }
 
+// Start of the FP32 correction solve of the mixed-precision refinement,
+// from the FP64 residual W and the column scales sc: R = float(W sc) (the
+// right-hand side; the correction starts from X = 0), P = D^{-1} R, X = 0,
+// and the b.b, r.r, r.z partials in k_pcg_init's layout.
+template <int VW>
+__global__ void __launch_bounds__(256) k_refine_prep(int N, int k, int CG, const double *__restrict__ W,
+                                                     const double *__restrict__ sc, const float *__restrict__ diag,
+                                                     float *__restrict__ R, float *__restrict__ P,
+                                                     float *__restrict__ X, double *__restrict__ part) {
+  __shared__ double s_red[256 * VW];
+  const RowMap m = row_map<1>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  const int c0 = m.cg * VW;
+  double sv[VW], arr[VW], arz[VW];
+  for (int v = 0; v < VW; ++v) {
+    sv[v] = (c0 + v < k) ? sc[c0 + v] : 0.0;
+    arr[v] = arz[v] = 0.0;
+  }
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
+    double w[VW];
+    load_row<double, VW>(W, row, k, c0, k, w);
+    const float d = diag[row];
+    float r[VW], p[VW], z[VW];
+    for (int v = 0; v < VW; ++v) {
+      r[v] = (float)(w[v] * sv[v]);
+      p[v] = r[v] / d;
+      z[v] = 0.f;
+      arr[v] += (double)r[v] * (double)r[v];
+      arz[v] += (double)r[v] * (double)p[v];
+    }
+    store_row<float, VW>(R, row, k, c0, k, r);
+    store_row<float, VW>(P, row, k, c0, k, p);
+    store_row<float, VW>(X, row, k, c0, k, z);
+  }
+  block_cols<VW, 1>(arr, m, k, CG, s_red, part, 3 * k, 0);
+  block_cols<VW, 1>(arr, m, k, CG, s_red, part, 3 * k, k);
+  block_cols<VW, 1>(arz, m, k, CG, s_red, part, 3 * k, 2 * k);
+}
+
+int launch_refine_prep(int N, int k, const double *W, const double *sc, const float *diag, float *X, PCGWork &w,
+                       hipStream_t s) {
+  if (N <= 0 || k <= 0 || k > MAX_K) return -1;
+  const int VW = (k % 4 == 0) ? 4 : 1;
+  const int CG = k / VW;
+  if (CG > 64) return -1;
+  const int nb = std::min(grid_rows(N, 64 / CG, pcg_blocks()), w.nblk_max);
+  float *R = reinterpret_cast<float *>(w.R), *P = reinterpret_cast<float *>(w.P);
+  double *part = reinterpret_cast<double *>(w.part);
+  if (VW == 4)
+    hipLaunchKernelGGL(k_refine_prep<4>, dim3(nb), dim3(256), 0, s, N, k, CG, W, sc, diag, R, P, X, part);
+  else
+    hipLaunchKernelGGL(k_refine_prep<1>, dim3(nb), dim3(256), 0, s, N, k, CG, W, sc, diag, R, P, X, part);
+  w.prep_nblk = nb;
+  return 0;
+}
+
 __global__ void __launch_bounds__(RED_THREADS) k_red_init(int k, int nblk, const double *part,
                                                           Control *ctl, ColState *cs, double tol) {
   __shared__ double s_sum[192];
@@ -803,7 +888,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_red_init(int k, int nblk, const
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     ColState st;
     st.bb = s_sum[c]; st.rr = s_sum[k + c]; st.rz = s_sum[2 * k + c]; st.rz_new = st.rz;
-    st.pq = 0.0; st.alpha = 0.0; st.beta = 0.0; st.iters = 0;
+    st.pq = 0.0; st.alpha = 0.0; st.alpha_prev = 0.0; st.beta = 0.0; st.iters = 0;
     st.active = (st.bb > 0.0) && (st.rr > tol * tol * st.bb);
     cs[c] = st;
   }
@@ -863,6 +948,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_red_A(int k, int nblk, const do
     const double pq = s_sum[c];
     ColState st = cs[c];
     st.pq = pq;
+    st.alpha_prev = st.alpha;
     st.alpha = 0.0;
     if (st.active) {
       if (!(pq > 0.0)) ctl->breakdown = 1;
@@ -941,51 +1027,94 @@ __global__ void __launch_bounds__(RED_THREADS) k_red_B(int k, int nblk, const do
 }
 
 // C: X += alpha P ; P = D^{-1} R + beta P   (runs in the stopping iteration too)
+// The directions alternate between two buffers: iteration it reads p_it from
+// Pc and writes p_{it+1} to Pn.  The x update of an even iteration is
+// deferred to the next one, which reads p_{it-1} from Pn (before overwriting
+// it) and applies both terms in order: one pass over X per two iterations.
+// An even iteration that stops the solver applies its own term.
 template <typename T, int VW>
 __global__ void __launch_bounds__(256) k_pcg_C(int N, int k, int CG, const T *__restrict__ diag,
                                                const T *__restrict__ R, T *__restrict__ X,
-                                               T *__restrict__ P, const Control *ctl,
-                                               const ColState *cs, int it) {
+                                               const T *__restrict__ Pc, T *__restrict__ Pn,
+                                               const Control *ctl, const ColState *cs, int it) {
   if (ctl->stop && ctl->skip != it) return;
-  __shared__ double s_ab[2 * MAX_K];
+  const bool odd = it & 1;
+  const bool upd_x = odd || ctl->stop;  // an even iteration updates X only when it is the last
+  __shared__ double s_ab[3 * MAX_K];
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     s_ab[c] = cs[c].alpha;
     s_ab[MAX_K + c] = cs[c].beta;
+    s_ab[2 * MAX_K + c] = cs[c].alpha_prev;
   }
   __syncthreads();
   const RowMap m = row_map<1>(CG);
   const int rows_per_block = (blockDim.x >> 6) * m.RPW;
   const int c0 = m.cg * VW;
-  T al[VW], be[VW];
+  T al[VW], be[VW], ap[VW];
   for (int v = 0; v < VW; ++v) {
     al[v] = (c0 + v < k) ? (T)s_ab[c0 + v] : T(0);
     be[v] = (c0 + v < k) ? (T)s_ab[MAX_K + c0 + v] : T(0);
+    ap[v] = (c0 + v < k) ? (T)s_ab[2 * MAX_K + c0 + v] : T(0);
   }
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
   for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
     const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
     if (!m.valid || c0 >= k || row >= N) continue;
-    T x[VW], p[VW], r[VW];
-    load_row<T, VW>(X, row, k, c0, k, x);
-    load_row<T, VW>(P, row, k, c0, k, p);
+    T p[VW], r[VW];
+    load_row<T, VW>(Pc, row, k, c0, k, p);
     load_row<T, VW>(R, row, k, c0, k, r);
-    const T d = diag[row];
-    for (int v = 0; v < VW; ++v) {
-      x[v] += al[v] * p[v];
-      p[v] = r[v] / d + be[v] * p[v];
+    if (upd_x) {
+      T x[VW];
+      load_row<T, VW>(X, row, k, c0, k, x);
+      if (odd) {
+        T q[VW];
+        load_row<T, VW>(Pn, row, k, c0, k, q);
+        for (int v = 0; v < VW; ++v) x[v] += ap[v] * q[v];
+      }
+      for (int v = 0; v < VW; ++v) x[v] += al[v] * p[v];
+      store_row<T, VW>(X, row, k, c0, k, x);
     }
+    const T d = diag[row];
+    for (int v = 0; v < VW; ++v) p[v] = r[v] / d + be[v] * p[v];
+    store_row<T, VW>(Pn, row, k, c0, k, p);
+  }
+}
+
+// After the last launched iteration it (even) when the solver did not stop:
+// its deferred X += alpha p_it
+template <typename T, int VW>
+__global__ void __launch_bounds__(256) k_pcg_flush(int N, int k, int CG, T *__restrict__ X,
+                                                   const T *__restrict__ Pc, const Control *ctl,
+                                                   const ColState *cs) {
+  if (ctl->stop) return;
+  __shared__ double s_a[MAX_K];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) s_a[c] = cs[c].alpha;
+  __syncthreads();
+  const RowMap m = row_map<1>(CG);
+  const int rows_per_block = (blockDim.x >> 6) * m.RPW;
+  const int c0 = m.cg * VW;
+  T al[VW];
+  for (int v = 0; v < VW; ++v) al[v] = (c0 + v < k) ? (T)s_a[c0 + v] : T(0);
+  const int n_groups = (N + rows_per_block - 1) / rows_per_block;
+  for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
+    const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
+    if (!m.valid || c0 >= k || row >= N) continue;
+    T x[VW], p[VW];
+    load_row<T, VW>(X, row, k, c0, k, x);
+    load_row<T, VW>(Pc, row, k, c0, k, p);
+    for (int v = 0; v < VW; ++v) x[v] += al[v] * p[v];
     store_row<T, VW>(X, row, k, c0, k, x);
-    store_row<T, VW>(P, row, k, c0, k, p);
   }
 }
 
 template <typename T, int VW, int NG>
 static int pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const int32_t *rowptr,
                              const int32_t *col, const T *val, const int32_t *ord, const T *diag,
-                             T *X, T *R, T *P,
+                             T *X, T *R, T *P0, T *P1,
                              T *Q, double *part, Control *ctl, ColState *cs, double tol, int it0,
                              int iters, hipStream_t s, const Tiling *til, const TShape &tsh) {
   for (int it = it0; it < it0 + iters; ++it) {
+    T *P = (it & 1) ? P1 : P0, *Pn = (it & 1) ? P0 : P1;
     if (til) {
       if (launch_tpcg_A<T>(N, k, *til, tsh, rowptr, val, P, Q, part, ctl, s) < 0) return -1;
       hipLaunchKernelGGL(k_red_A, dim3(1), dim3(RED_THREADS), 0, s, k, tsh.grid, part, ctl, cs);
@@ -997,7 +1126,7 @@ static int pcg_launch_iters(int N, int k, int CG, int nblkA, int nblkE, const in
     hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
                        ctl, cs);
     hipLaunchKernelGGL(k_red_B, dim3(1), dim3(RED_THREADS), 0, s, k, nblkE, part, ctl, cs, tol, it);
-    hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
+    hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, Pn, ctl,
                        cs, it);
   }
   return 0;
@@ -1012,10 +1141,11 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
   const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
-  const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, pcg_blocks()), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
+  T *P2 = reinterpret_cast<T *>(w.P2);
   double *part = reinterpret_cast<double *>(w.part);
   TShape tsh;
   const Tiling *til = nullptr;
@@ -1024,34 +1154,46 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
     if (tsh.grid > 0) til = w.til;
   }
   int have_r = 0;
-  if (x_zero) {
-    have_r = 2;  // r = b
-  } else if (til) {  // R = B - S X through the halo tiles
-    if (launch_tpcg_A_m<T, 2>(N, k, k, k, *til, tsh, rowptr, val, X, R, nullptr, nullptr, B, s) < 0) return -1;
-    have_r = 1;
+  if (x_zero == 2) {
+    // R, P, X and the start partials written by launch_refine_prep
+    hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, w.prep_nblk, part, ctl, cs, tol);
+  } else {
+    if (x_zero) {
+      have_r = 2;  // r = b
+    } else if (til) {  // R = B - S X through the halo tiles
+      if (launch_tpcg_A_m<T, 2>(N, k, k, k, *til, tsh, rowptr, val, X, R, nullptr, nullptr, B, s) < 0) return -1;
+      have_r = 1;
+    }
+    hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
+                       diag, B, X, R, P, part, ord, have_r);
+    hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
   }
-  hipLaunchKernelGGL((k_pcg_init<T, VW, NG>), dim3(nblkA), dim3(256), 0, s, N, k, CG, rowptr, col, val,
-                     diag, B, X, R, P, part, ord, have_r);
-  hipLaunchKernelGGL(k_red_init, dim3(1), dim3(RED_THREADS), 0, s, k, nblkA, part, ctl, cs, tol);
   std::vector<ColState> hcs(k);
-  Control hctl;
+  Control hctl{};
   // host polls of the stop flag: the first after about as many iterations as
   // the previous solve took, then every 2 (iterations launched after
   // convergence return at once, but still cost a launch each); without a
   // history, after 4, 8, 16, 32, ... iterations
+  // (the first chunk goes out unpolled: a start that already meets the
+  // tolerance costs only launches that return at once)
   const bool hist = w.last_iters > 0;
   int done_iters = 0, chunk = hist ? std::max(2, w.last_iters - 1) : 4;
   for (;;) {
-    if (hipMemcpyAsync(&hctl, ctl, sizeof(Control), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
-    if (hipStreamSynchronize(s) != hipSuccess) return -2;
+    if (done_iters > 0) {
+      if (hipMemcpyAsync(&hctl, ctl, sizeof(Control), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
+      if (hipStreamSynchronize(s) != hipSuccess) return -2;
+    }
     if (hctl.stop || done_iters >= max_iter) break;
     int n = std::min(chunk, max_iter - done_iters);
-    if (pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, ord, diag, X, R, P, Q, part,
+    if (pcg_launch_iters<T, VW, NG>(N, k, CG, nblkA, nblkE, rowptr, col, val, ord, diag, X, R, P, P2, Q, part,
                                     ctl, cs, tol, done_iters, n, s, til, tsh) < 0)
       return -1;
     done_iters += n;
     chunk = hist ? 2 : std::min(chunk * 2, 32);
   }
+  // iteration limit reached after an even iteration: its deferred x update
+  if (!hctl.stop && done_iters > 0 && ((done_iters - 1) & 1) == 0)
+    hipLaunchKernelGGL((k_pcg_flush<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, X, P, ctl, cs);
   if (hipMemcpyAsync(hcs.data(), cs, sizeof(ColState) * k, hipMemcpyDeviceToHost, s) != hipSuccess)
     return -2;
   if (hipStreamSynchronize(s) != hipSuccess) return -2;
@@ -1079,10 +1221,11 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
   const int RPWA = 64 / (CG * NG);
   const int RPWE = 64 / CG;
   const int nblkA = std::min(grid_rows(N, RPWA, SPMM_BLOCKS), w.nblk_max);
-  const int nblkE = std::min(grid_rows(N, RPWE, PCG_BLOCKS), w.nblk_max);
+  const int nblkE = std::min(grid_rows(N, RPWE, pcg_blocks()), w.nblk_max);
   Control *ctl = reinterpret_cast<Control *>(w.state);
   ColState *cs = reinterpret_cast<ColState *>(reinterpret_cast<char *>(w.state) + sizeof(Control));
   T *R = reinterpret_cast<T *>(w.R), *P = reinterpret_cast<T *>(w.P), *Q = reinterpret_cast<T *>(w.Q);
+  T *P2 = reinterpret_cast<T *>(w.P2);
   double *part = reinterpret_cast<double *>(w.part);
   TShape tsh;
   const Tiling *til = nullptr;
@@ -1091,6 +1234,7 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
     if (tsh.grid > 0) til = w.til;
     else return -3;  // this tiling cannot serve k columns of T
   }
+  int nc = 0;  // C launches alternate even and odd iterations (the average cost)
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;
   if (hipMemsetAsync(ctl, 0, sizeof(Control), s) != hipSuccess) return -2;
@@ -1103,9 +1247,11 @@ static int time_phase_t(int N, int k, int phase, const int32_t *rowptr, const in
     else if (phase == 1)
       hipLaunchKernelGGL((k_pcg_B<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, Q, R, part,
                          ctl, cs);
-    else
-      hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, P, ctl,
-                         cs, 0);
+    else {
+      const int it = nc++;
+      hipLaunchKernelGGL((k_pcg_C<T, VW>), dim3(nblkE), dim3(256), 0, s, N, k, CG, diag, R, X, (it & 1) ? P2 : P,
+                         (it & 1) ? P : P2, ctl, cs, it);
+    }
   };
   launch();  // warm
   (void)hipEventRecord(e0, s);

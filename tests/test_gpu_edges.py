@@ -57,3 +57,45 @@ def test_live_context_rejects_bad_widths():
         assert e.value.code == -1
     with pytest.raises(KSError):
         ctx.scf_run(psi, lam, w.occ, tol=0.0)
+
+
+def _jacobi_pcg(S, b, m):
+    """m iterations of Jacobi-preconditioned CG from x = 0, column by column
+    (the textbook recurrences, FP64)."""
+    d = S.diagonal()
+    X = np.zeros_like(b)
+    for c in range(b.shape[1]):
+        x = np.zeros(b.shape[0])
+        r = b[:, c].copy()
+        z = r / d
+        p = z.copy()
+        rz = r @ z
+        for _ in range(m):
+            q = S @ p
+            a = rz / (p @ q)
+            x += a * p
+            r -= a * q
+            z = r / d
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        X[:, c] = x
+    return X
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_block_solve_stops_at_iteration_limit(m):
+    """A block PCG cut off after m iterations (odd and even m: the x update of
+    an even iteration is deferred to the next) returns the m-th CG iterate."""
+    w = make_workload("small_molecule", n=5)
+    ctx = _ctx(w, k_max=8, tol_solve=1e-14, max_it_solve=m)
+    psi, lam = ctx.initial_guess(w.k)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    S = _csr(ctx, 0)
+    rng = np.random.default_rng(7 + m)
+    Bh = rng.standard_normal((ctx.N, 3))
+    X, st = ctx.block_solve_rhs(torch.tensor(Bh, device=DEV), precision="fp64")
+    ref = _jacobi_pcg(S, Bh, m)
+    assert not st["converged"]
+    err = np.abs(X.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, (m, err)
