@@ -19,6 +19,7 @@
 #include "common.h"
 #include "kernels.h"
 #include <vector>
+#include <type_traits>
 #include <algorithm>
 
 namespace ks {
@@ -542,23 +543,35 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
       T acc[VW];
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
       // eight nonzeros per step: one aligned 16-byte read of their local
-      // indices.  Slots past the row's end point at the zero halo row; their
-      // weights (the following entries of the LDS value image, finite) then
-      // add exact zeros.
-      for (int j = 0; j < len; j += 8) {
-        const uint4 iw = *reinterpret_cast<const uint4 *>(ir + j);
-        const unsigned li[8] = {iw.x & 0xffffu, iw.x >> 16, iw.y & 0xffffu, iw.y >> 16,
-                                iw.z & 0xffffu, iw.z >> 16, iw.w & 0xffffu, iw.w >> 16};
-        T vv[8];
+      // indices; a tail of at most four takes one four-wide step (8-byte
+      // index read).  Slots past the row's end point at the zero halo row;
+      // their weights (the following entries of the LDS value image, finite)
+      // then add exact zeros.
+      auto step = [&](auto nu, int j) {
+        constexpr int NU = decltype(nu)::value;
+        unsigned li[NU];
+        if constexpr (NU == 8) {
+          const uint4 iw = *reinterpret_cast<const uint4 *>(ir + j);
+          li[0] = iw.x & 0xffffu; li[1] = iw.x >> 16; li[2] = iw.y & 0xffffu; li[3] = iw.y >> 16;
+          li[4] = iw.z & 0xffffu; li[5] = iw.z >> 16; li[6] = iw.w & 0xffffu; li[7] = iw.w >> 16;
+        } else {
+          const uint2 iw = *reinterpret_cast<const uint2 *>(ir + j);
+          li[0] = iw.x & 0xffffu; li[1] = iw.x >> 16; li[2] = iw.y & 0xffffu; li[3] = iw.y >> 16;
+        }
+        T vv[NU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) vv[u] = vs[jb + j + u];
+        for (int u = 0; u < NU; ++u) vv[u] = vs[jb + j + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NU; ++u) {
           const VecT<T, VW> x = SC ? *reinterpret_cast<const VecT<T, VW> *>(xsb + li[u])
                                    : *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], (unsigned)k));
           for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
         }
-      }
+      };
+      int j = 0;
+      for (; j + 8 <= len; j += 8) step(std::integral_constant<int, 8>{}, j);
+      if (len - j > 4) step(std::integral_constant<int, 8>{}, j);
+      else if (len - j > 0) step(std::integral_constant<int, 4>{}, j);
       if constexpr (MODE == 0) {
         const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
         for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
