@@ -37,9 +37,11 @@ def spmm_bytes(N, nnz, k, sv):
 
 def cg_iteration_bytes(N, nnz, k, sv):
     """Algorithmic bytes of one block-PCG iteration (three launches):
-    SpMM (matrix, read p, write q), r update (read r, q, write r), x/p update
-    (read x, p, r, write x, p), diagonal read twice."""
-    return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 10 * N * k * sv
+    SpMM (matrix, read p, write q), r update (read r, q, write r), p update
+    (read p, r, write p) and the x update x += alpha p, which is applied for
+    two iterations in one pass (read x and both directions, write x): on
+    average 9.5 [N][k] vector passes; diagonal read twice."""
+    return nnz * (sv + 4) + 4 * (N + 1) + 2 * N * sv + 19 * N * k * sv // 2
 
 
 def phase_rooflines(ctx, k, reps=10, with_projection=True):

@@ -264,23 +264,25 @@ void launch_elem_potential(const int32_t *eord, int n, int n_loc, int n_q, const
 }
 // out[s] = base[s] (0 if base is null) + the pair values that belong to
 // value slot s, added in ascending order (a fixed order: bitwise
-// reproducible)
+// reproducible); out32[s] = (float)out[s] for s < n32 when out32 is given
 __global__ void k_gather_slots(int64_t nslots, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
                                const double *__restrict__ emat, const double *__restrict__ base,
-                               double *__restrict__ out) {
+                               double *__restrict__ out, float *__restrict__ out32, int64_t n32) {
   for (int64_t sidx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sidx < nslots;
        sidx += (int64_t)gridDim.x * blockDim.x) {
     const int j0 = cptr[sidx], j1 = cptr[sidx + 1];
     double v = base ? base[sidx] : 0.0;
     for (int j = j0; j < j1; ++j) v += emat[cidx[j]];
     out[sidx] = v;
+    if (out32 && sidx < n32) out32[sidx] = (float)v;
   }
 }
 void launch_gather_slots(int64_t nslots, const int32_t *cptr, const int32_t *cidx, const double *emat,
-                         const double *base, double *out, hipStream_t s) {
+                         const double *base, double *out, hipStream_t s, float *out32, int64_t n32) {
   if (nslots <= 0) return;
   const int64_t b = std::min<int64_t>((nslots + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather_slots, dim3((unsigned)b), dim3(256), 0, s, nslots, cptr, cidx, emat, base, out);
+  hipLaunchKernelGGL(k_gather_slots, dim3((unsigned)b), dim3(256), 0, s, nslots, cptr, cidx, emat, base, out,
+                     out32, n32);
 }
 
 // ------------------------------------------------------------ load vector

@@ -29,8 +29,10 @@ void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_
 // launch; then out[s] = base[s] (0: base null) + sum_{j in [cptr[s], cptr[s+1])} emat[cidx[j]].
 void launch_elem_potential(const int32_t *eord, int n, int n_loc, int n_q, const double *absdet,
                            const double *pairtab, const double *w, const double *V_q, double *emat, hipStream_t s);
+// With out32: also (float)out[s] for s < n32 (the FP32 operator copy).
 void launch_gather_slots(int64_t nslots, const int32_t *cptr, const int32_t *cidx, const double *emat,
-                         const double *base, double *out, hipStream_t s);
+                         const double *base, double *out, hipStream_t s, float *out32 = nullptr,
+                         int64_t n32 = 0);
 // out[dof_a] += sum_q w_q |J| f_q phi_a (one colour; dof = interior index or -1).
 void launch_load_vector(const int32_t *list, int count, int n_loc, int n_q,
                         const int32_t *edof, const double *absdet, const double *phi,

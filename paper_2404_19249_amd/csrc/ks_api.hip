@@ -289,12 +289,14 @@ static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *ou
 }
 
 // colour loop helpers
-// out = base + M[V] over the extended pattern (base null: out = M[V])
-static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out, const double *base = nullptr) {
+// out = base + M[V] over the extended pattern (base null: out = M[V]);
+// out32: the FP32 copy of the interior values as well (nullptr: none)
+static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out, const double *base = nullptr,
+                                   float *out32 = nullptr) {
   if (c->g_nE) {  // element pair values, then one gather per value slot
     launch_elem_potential(c->g_eord, c->g_nE, c->n_loc, c->n_q, c->absdet, c->pairtab, c->qw, Vq, c->g_emat,
                           c->s);
-    launch_gather_slots(c->nnz_ext, c->g_cptr, c->g_cidx, c->g_emat, base, out, c->s);
+    launch_gather_slots(c->nnz_ext, c->g_cptr, c->g_cidx, c->g_emat, base, out, c->s, out32, c->nnz);
     return;
   }
   if (base) launch_axpby(c->nnz_ext, 1.0, base, 0.0, out, c->s);
@@ -1911,7 +1913,9 @@ extern "C" int ks_get_sizes(const ks_ctx *c, double *o) {
 
 // --------------------------------------------------------------- assemble
 // rho_l, w_B, V_H, V_xc of the density of psi; S = base + M[V_H + V_xc].
-static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_host, int *p_iters) {
+// want_s32: also the FP32 copy of S (the step solves in the mixed form)
+static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_host, int *p_iters,
+                         bool want_s32 = false) {
   hipStream_t s = c->s;
   const int64_t nqt = (int64_t)c->n_e * c->n_q;
   const bool nonlinear = psi && (c->opt.hartree_mode != KS_HARTREE_OFF || c->opt.xc_mode != KS_XC_NONE);
@@ -1932,11 +1936,18 @@ static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_
   }
   launch_xc(nqt, c->rho_l, psi ? c->opt.xc_mode : KS_XC_NONE, c->exc_q, c->vxc_q, s);
   launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
-  if (nonlinear) assemble_potential_all(c, c->vnl_q, c->S, c->base);  // S = A^L + mu M + M[V_nl]
-  else launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
-  launch_extract_diag(c->N, c->rowptr, c->col, c->S, c->diagS, s);
-  c->have_S = true;
+  // the mixed form's FP32 copy of S comes out of the same pass
+  const bool mixed = want_s32;
   c->have_S32 = false;
+  if (nonlinear) {  // S = A^L + mu M + M[V_nl]
+    assemble_potential_all(c, c->vnl_q, c->S, c->base, mixed && c->g_nE ? c->S32 : nullptr);
+    c->have_S32 = mixed && c->g_nE;
+  } else {
+    launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
+  }
+  launch_extract_diag(c->N, c->rowptr, c->col, c->S, c->diagS, s);
+  if (c->have_S32) launch_to_float(c->N, c->diagS, c->diagS32, s);
+  c->have_S = true;
   c->have_step = false;
   return KS_OK;
 }
@@ -2332,7 +2343,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   // 1. S of the input density (w_D frozen from here on)
   int piters = 0;
   launch_rows_to_storage(N, k, psi, c->PsiIn, c->int2nat, s);
-  TRY(assemble_impl(c, c->PsiIn, k, occ_host, &piters));
+  TRY(assemble_impl(c, c->PsiIn, k, occ_host, &piters, precision == KS_PREC_MIXED));
   HIPCHK(hipStreamSynchronize(s));
   const double t1 = now_s();
   // 2. BVPs
