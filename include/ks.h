@@ -324,8 +324,11 @@ int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 int ks_spmm_config(const ks_ctx *ctx, int32_t *out_host);
 
 /* Diagnostics: copy n doubles of an internal buffer (by name: "GPP",
- * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom")
- * into the device buffer dst.  For tests and debugging only. */
+ * "FAL_PP", "Z", "Y", "FB", "FAL", "FA", "U", "rho_in", "vh_q", "wB", "mom",
+ * "S": the interior operator values in storage order) into the device buffer
+ * dst.  "S32" copies the mixed form's FP32 operator copy (nnz floats, packed
+ * into the first ceil(nnz / 2) doubles of dst; KS_ERR_STATE when there is
+ * none).  For tests and debugging only. */
 int ks_debug_buffer(ks_ctx *ctx, const char *name, double *dst, int64_t n);
 
 #ifdef __cplusplus

@@ -1236,7 +1236,15 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
       {"FB", c->FB, (int64_t)c->mp * c->mp}, {"FAL", c->FAL, (int64_t)c->mp * c->mp},
       {"FA", c->FA, (int64_t)c->mp * c->mp}, {"U", c->U, (int64_t)c->mp * c->k_max},
       {"rho_in", c->rho_in, (int64_t)c->n_e * c->n_q}, {"vh_q", c->vh_q, (int64_t)c->n_e * c->n_q},
-      {"wB", c->wB, (int64_t)c->NB}, {"mom", c->mom, 16}};
+      {"wB", c->wB, (int64_t)c->NB}, {"mom", c->mom, 16}, {"S", c->S, (int64_t)c->nnz}};
+  // "S32": the FP32 operator copy, nnz floats packed into ceil(nnz / 2) doubles
+  if (std::strcmp(name, "S32") == 0) {
+    if (!c->have_S32) return fail(KS_ERR_STATE, "no FP32 operator copy");
+    if (n < ((int64_t)c->nnz + 1) / 2) return fail(KS_ERR_ARG, "buffer smaller than requested");
+    HIPCHK(hipMemcpyAsync(dst, c->S32, sizeof(float) * c->nnz, hipMemcpyDeviceToDevice, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    return KS_OK;
+  }
   for (auto &t : tab)
     if (std::strcmp(t.n, name) == 0) {
       if (n > t.size) return fail(KS_ERR_ARG, "buffer smaller than requested");

@@ -99,3 +99,24 @@ def test_block_solve_stops_at_iteration_limit(m):
     assert not st["converged"]
     err = np.abs(X.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err < 1e-11, (m, err)
+
+
+def test_fp32_operator_copy_is_the_rounded_operator():
+    """The mixed form's FP32 copy of S, whether written by the assembly of a
+    mixed-precision step or made on demand before a mixed solve, is S rounded
+    to FP32 value by value."""
+    w = make_workload("small_molecule", n=5)
+    ctx = _ctx(w, k_max=8)
+    psi, lam = ctx.initial_guess(w.k)
+    half = (ctx.nnz + 1) // 2
+    lam, rep = ctx.scf_step(psi, lam, w.occ, precision="mixed")
+    S = ctx.debug_buffer("S", ctx.nnz)
+    S32 = ctx.debug_buffer("S32", half).view(torch.float32)[:ctx.nnz]
+    assert torch.equal(S32, S.float())
+    ctx.assemble(psi, w.occ, want_fields=False)
+    with pytest.raises(KSError):
+        ctx.debug_buffer("S32", half)
+    ctx.block_solve(psi, lam, "mixed")
+    S = ctx.debug_buffer("S", ctx.nnz)
+    S32 = ctx.debug_buffer("S32", half).view(torch.float32)[:ctx.nnz]
+    assert torch.equal(S32, S.float())
