@@ -58,6 +58,44 @@ def test_correlation_branch_gap_at_rs_one_is_as_printed():
     assert np.isfinite(lo)
 
 
+def _golden_pz81():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "lda_pz81_constants.txt")
+    vals = {}
+    for line in open(path):
+        line = line.split("#")[0].split()
+        if len(line) == 2:
+            vals[line[0]] = float(line[1])
+    return vals
+
+
+def test_correlation_uses_the_printed_constants():
+    """The oracle's correlation energy at r_s = 0.5 (first branch) and r_s = 4
+    (second branch) equals the paper's formulas with the constants read from
+    the golden file (Sec. 3.1), and the low-density branch's energy and
+    potential approach zero like gamma / (beta_2 r_s) as r_s grows."""
+    g = _golden_pz81()
+    assert len(g) == 7
+
+    def ec_vc(rs):
+        rho = 3.0 / (4.0 * np.pi * rs ** 3)
+        e, v = lda_xc(np.array([rho]))
+        ex, vx = lda_xc(np.array([rho]), "x_only")
+        return (e - ex)[0], (v - vx)[0]
+
+    rs = 0.5
+    ec, _ = ec_vc(rs)
+    assert abs(ec - (g["A"] * np.log(rs) + g["B"] + g["C"] * rs * np.log(rs) + g["D"] * rs)) < 1e-15
+    rs = 4.0
+    ec, vc = ec_vc(rs)
+    den = 1 + g["beta_1"] * np.sqrt(rs) + g["beta_2"] * rs
+    assert abs(ec - g["gamma"] / den) < 1e-15
+    rs = 1e8
+    ec, vc = ec_vc(rs)
+    assert abs(ec * g["beta_2"] * rs / g["gamma"] - 1) < 1e-3
+    assert abs(vc * g["beta_2"] * rs / g["gamma"] - 4.0 / 3.0) < 1e-3
+
+
 def test_xc_vanishes_at_zero_density():
     e, v = lda_xc(np.array([0.0, 1e-31, -1e-5]))
     assert np.all(e == 0) and np.all(v == 0)
