@@ -156,7 +156,7 @@ int launch_spmm_tiled_cols(int N, int k, int ldx, int ldy, int kc, const Tiling 
 struct PCGWork {
   void *R, *P, *Q;       // [N][k] of T
   void *P2;              // [N][k] of T: directions alternate between P and P2
-  void *part;            // block partials [nblk][2k] doubles
+  void *part;            // block partials, up to [nblk_max][3k] doubles
   void *state;           // device ColState[k] + control
   unsigned int *counter; // last-block counters
   int nblk_max;
