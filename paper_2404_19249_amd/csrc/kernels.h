@@ -173,7 +173,8 @@ int pcg_solve(int N, int k, const int32_t *rowptr, const int32_t *col, const T *
 // x_zero: 1 = X is 0 on entry; 2 = R, P, X and the start partials were
 // written by launch_refine_prep (B unused)
 // FP32 correction-solve start of the mixed-precision refinement from the
-// FP64 residual W [N][k] and column scales sc (device, [k]): R = float(W sc),
+// FP64 residual W [N][k] and column scales sc (device, [2k]: the scales,
+// then per-column factors >= 1 on the solve's tolerance): R = float(W sc),
 // P = D^{-1} R, X = 0 and the start partials, in w; then pcg_solve<float>
 // with x_zero = 2
 int launch_refine_prep(int N, int k, const double *W, const double *sc, const float *diag, float *X, PCGWork &w,

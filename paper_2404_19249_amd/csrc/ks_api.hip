@@ -1016,7 +1016,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     }
   A_(PsiNew, (size_t)N * km);
   A_(occ_d, 64);
-  A_(scal, 64);
+  A_(scal, 128);
   A_(X32, (size_t)N * km);
   A_(counters, 16);
   {
@@ -2092,10 +2092,15 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
       TRY(reduce_small(c, npart, nb, k, rn.data()));
       loc.refinements = ref + 1;
       bool all = true;
+      // inexact refinement: column j's FP32 solve stops once its residual
+      // is below half of what the outer tolerance still asks of it (never
+      // tighter than the inner tolerance): factor max(1, tol/(2 inner rel))
+      sc.resize(2 * k);
       for (int j = 0; j < k; ++j) {
         const double rel = bn[j] > 0 ? std::sqrt(rn[j] / bn[j]) : 0.0;
         if (rel > tol) all = false;
         sc[j] = rn[j] > 0 ? 1.0 / std::sqrt(rn[j]) : 0.0;
+        sc[k + j] = rel > 0 ? std::max(1.0, 0.5 * tol / (rel * c->opt.mixed_inner_tol)) : 1.0;
       }
       if (all) {
         conv = 1;
@@ -2104,7 +2109,7 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
       // FP32 PCG from zero on the scaled residual: one pass writes its
       // right-hand side (the start residual), first direction, X = 0 and
       // start partials
-      HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(c->scal, sc.data(), sizeof(double) * 2 * k, hipMemcpyHostToDevice, s));
       if (launch_refine_prep(c->N, k, c->Wv, c->scal, c->diagS32, c->X32, c->pw32, s) < 0)
         return fail(KS_ERR_ARG, "FP32 correction start: unsupported k");
       int it[MAX_K] = {0};

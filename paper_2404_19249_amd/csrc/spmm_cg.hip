@@ -838,7 +838,9 @@ __global__ void __launch_bounds__(256) k_pcg_init(int N, int k, int CG,
 // Start of the FP32 correction solve of the mixed-precision refinement,
 // from the FP64 residual W and the column scales sc: R = float(W sc) (the
 // right-hand side; the correction starts from X = 0), P = D^{-1} R, X = 0,
-// and the b.b, r.r, r.z partials in k_pcg_init's layout.
+// and the b.b, r.r, r.z partials in k_pcg_init's layout.  sc[k + c] >= 1
+// relaxes column c's stopping test: b.b is recorded times sc[k + c]^2, so
+// the column stops at relative residual tol sc[k + c].
 template <int VW>
 __global__ void __launch_bounds__(256) k_refine_prep(int N, int k, int CG, const double *__restrict__ W,
                                                      const double *__restrict__ sc, const float *__restrict__ diag,
@@ -853,6 +855,8 @@ __global__ void __launch_bounds__(256) k_refine_prep(int N, int k, int CG, const
     sv[v] = (c0 + v < k) ? sc[c0 + v] : 0.0;
     arr[v] = arz[v] = 0.0;
   }
+  double rx[VW];
+  for (int v = 0; v < VW; ++v) rx[v] = (c0 + v < k) ? sc[k + c0 + v] * sc[k + c0 + v] : 1.0;
   const int n_groups = (N + rows_per_block - 1) / rows_per_block;
   for (GroupIter gi = group_iter(n_groups); gi.g < gi.end; gi.g += gi.step) {
     const int row = gi.g * rows_per_block + m.wave * m.RPW + m.slot;
@@ -872,7 +876,9 @@ __global__ void __launch_bounds__(256) k_refine_prep(int N, int k, int CG, const
     store_row<float, VW>(P, row, k, c0, k, p);
     store_row<float, VW>(X, row, k, c0, k, z);
   }
-  block_cols<VW, 1>(arr, m, k, CG, s_red, part, 3 * k, 0);
+  double abb[VW];
+  for (int v = 0; v < VW; ++v) abb[v] = arr[v] * rx[v];
+  block_cols<VW, 1>(abb, m, k, CG, s_red, part, 3 * k, 0);
   block_cols<VW, 1>(arr, m, k, CG, s_red, part, 3 * k, k);
   block_cols<VW, 1>(arz, m, k, CG, s_red, part, 3 * k, 2 * k);
 }
