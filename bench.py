@@ -448,12 +448,21 @@ def main():
             "frac": ach / HBM_PEAK_GBS,
             "traffic": None if traffic is None else traffic / 1e9,
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
-            "bytes_per_launch": bytes_a, "ms_per_launch": ms_a, "spmm_config": cfg}
+            "bytes_per_launch": bytes_a, "ms_per_launch": ms_a, "spmm_config": cfg,
+            # against the copy probe of the same run, and algorithmic / measured bytes
+            "frac_probe": ach / copy_gbs,
+            "algorithmic_over_traffic": None if not traffic else bytes_a / traffic}
     it_bytes = cg_iteration_bytes(N, nnz, k, sv)
+    it_gbs = it_bytes / ((ms_a + ms_b + ms_c) * 1e-3) / 1e9
     phases = {"spmm_ms": ms_a, "r_update_ms": ms_b, "xp_update_ms": ms_c,
-              "iteration_GBs": it_bytes / ((ms_a + ms_b + ms_c) * 1e-3) / 1e9,
+              "iteration_GBs": it_gbs, "iteration_frac_probe": it_gbs / copy_gbs,
               "fp64_spmm_ms": ms_a64,
               "fp64_spmm_GBs": spmm_bytes(N, nnz, k, 8) / (ms_a64 * 1e-3) / 1e9}
+    for ph in phases_other.values():
+        if "GBs" in ph:
+            ph["frac_probe"] = ph["GBs"] / copy_gbs
+    for key in ("fp64", "mixed"):
+        forms[key]["solve_frac_probe"] = forms[key]["solve_GBs"] / copy_gbs
     out = {
         "metric": METRIC, "value": value, "unit": "DOF*RHS/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
