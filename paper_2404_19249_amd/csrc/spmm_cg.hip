@@ -1189,14 +1189,14 @@ static int pcg_run(int N, int k, const int32_t *rowptr, const int32_t *col, cons
   }
   std::vector<ColState> hcs(k);
   Control hctl{};
-  // host polls of the stop flag: the first after about as many iterations as
-  // the previous solve took, then every 2 (iterations launched after
+  // host polls of the stop flag: the first after as many iterations as the
+  // previous solve took, then every 2 (iterations launched after
   // convergence return at once, but still cost a launch each); without a
   // history, after 4, 8, 16, 32, ... iterations
   // (the first chunk goes out unpolled: a start that already meets the
   // tolerance costs only launches that return at once)
   const bool hist = w.last_iters > 0;
-  int done_iters = 0, chunk = hist ? std::max(2, w.last_iters - 1) : 4;
+  int done_iters = 0, chunk = hist ? std::max(2, w.last_iters) : 4;
   for (;;) {
     if (done_iters > 0) {
       if (hipMemcpyAsync(&hctl, ctl, sizeof(Control), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
