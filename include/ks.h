@@ -20,6 +20,10 @@
  *    the calling thread.  Positive values are usable results with a warning.
  *  - A context is not thread safe; separate contexts on separate streams may
  *    be used concurrently.
+ *  - Two environment variables print diagnostics and change no result:
+ *    KS_DEBUG=1 synchronises after each stage and reports launch errors and
+ *    buffer summaries on stderr; KS_TRACE_INNER=1 prints the residual of
+ *    every inner (nonlinear) iteration of ks_scf_step.
  */
 #ifndef KS_H
 #define KS_H
@@ -97,6 +101,14 @@ typedef struct {
 
 /* Fill *o with the defaults above. */
 int ks_options_default(ks_options *o);
+
+/* Replace the options of a live context (the next calls use them): the
+ * tolerances, iteration limits, Anderson depth (at most the depth given at
+ * ks_create) and beta, and the mixed form's inner tolerance.  mu, n_H,
+ * xc_mode, hartree_mode and k_max fix the context's data and must equal the
+ * values given at ks_create (KS_ERR_ARG otherwise; the context is then
+ * unchanged). */
+int ks_set_options(ks_ctx *ctx, const ks_options *o);
 
 /* Per-mesh setup (not part of a step): interior numbering, CSR pattern,
  * element colouring, geometry, stiffness and mass matrices, the external
@@ -207,7 +219,11 @@ typedef struct {
  * (Hartree boundary data w_D frozen at the step's input density), and write
  * the new orbitals and eigenvalues back in place.
  * psi: device [N][k] in/out; lambda_host [k] in/out; occ_host [k];
- * rho_q (device [n_elems][n_q], may be NULL) receives the new density. */
+ * rho_q (device [n_elems][n_q], may be NULL) receives the new density.
+ * Returns KS_NOT_CONVERGED when the inner iteration stops at max_it_inner
+ * with ||rho_out - rho_in||_0 >= tol_inner (rep_host->res_inner) or the BVP
+ * solve at max_it_solve; the outputs are then those of the last inner pass,
+ * and its energies use the input density that built that pass's potentials. */
 int ks_scf_step(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                 int32_t precision, double *rho_q, ks_step_report *rep_host);
 
@@ -247,7 +263,9 @@ int ks_step_energy(ks_ctx *ctx, double *out_host);
  * stationarity of the converged inner iteration: g_q = dE w_q |J| (rho_q -
  * sum_i Y_i(x_q) psi_hat_i(x_q)) with one adjoint block solve S Y =
  * psi_bar_hat (CG recomputed from zero, nothing stored from the forward
- * solve).  st_host (may be NULL) receives the adjoint solve statistics. */
+ * solve).  st_host (may be NULL) receives the adjoint solve statistics.
+ * KS_ERR_STATE when there is no step, or when its inner iteration stopped at
+ * max_it_inner above tol_inner (no stationary point to differentiate). */
 int ks_step_backward(ks_ctx *ctx, double dE, double *g_q, double *forces_host,
                      ks_solve_stats *st_host);
 

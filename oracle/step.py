@@ -337,7 +337,9 @@ def ks_scf_step(prob, Psi, lam, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-1
         Psi_new = Z @ U
         rho_out = prob.density(Psi_new)
         res = np.sqrt(max(prob.inner(rho_out - rho_in, rho_out - rho_in), 0.0))
-        if not nonlinear or res < tol_inner:
+        # the last permitted pass mixes nothing: the energies below pair
+        # rho_in with the potentials it produced (Sec. 3.1)
+        if not nonlinear or res < tol_inner or it == max_inner - 1:
             break
         hist_in.append(rho_in)
         hist_out.append(rho_out)

@@ -76,6 +76,7 @@ class BatchStats(C.Structure):
 _P = C.c_void_p
 _SIGS = {
     "ks_options_default": (C.c_int, [C.POINTER(Options)]),
+    "ks_set_options": (C.c_int, [_P, C.POINTER(Options)]),
     "ks_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(QuadDesc), C.POINTER(AtomsDesc),
                             C.POINTER(Options), _P, C.POINTER(_P)]),
     "ks_create_nonnested": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(MeshDesc), C.POINTER(QuadDesc),

@@ -86,6 +86,21 @@ class KSContext:
         self.mu = float(sz[9])
         self.k_max = k_max
 
+    _SETTABLE = ("tol_solve", "tol_inner", "tol_poisson", "max_it_solve", "max_it_inner",
+                 "max_it_poisson", "anderson_depth", "anderson_beta", "mixed_inner_tol")
+
+    def set_options(self, **kw):
+        """Change tolerances, iteration limits or Anderson parameters of the
+        live context (ks_set_options); other options are fixed at creation."""
+        opt = B.Options()
+        C.memmove(C.byref(opt), C.byref(self.opt), C.sizeof(B.Options))
+        for key, v in kw.items():
+            if key not in self._SETTABLE:
+                raise KeyError(f"option {key} cannot change after creation")
+            setattr(opt, key, v)
+        B.check(self.lib.ks_set_options(self.h, C.byref(opt)), self.lib)
+        self.opt = opt
+
     @classmethod
     def from_workload(cls, w, **kw):
         kw.setdefault("n_H", w.n_H)

@@ -119,6 +119,7 @@ struct ks_ctx {
   double *vext_q = nullptr, *rho_l = nullptr, *rho_in = nullptr, *rho_out = nullptr,
          *vh_q = nullptr, *vxc_q = nullptr, *exc_q = nullptr, *vnl_q = nullptr, *drho = nullptr;
   double *hist_in[5] = {}, *hist_F[5] = {};
+  int hist_alloc = 0;  // Anderson history slots allocated at ks_create
   // Hartree
   double *vh_int = nullptr, *vh_nodes = nullptr, *wB = nullptr, *load = nullptr, *rhs = nullptr,
          *mom = nullptr, *mpart = nullptr;
@@ -140,6 +141,7 @@ struct ks_ctx {
   int e_rank = 0, e_m = 0;
   // state of the most recent ks_scf_step (for its energy and adjoint)
   bool have_step = false, last_nonlinear = false;
+  bool last_inner_converged = false;  // the last step's inner iteration met tol_inner
   int last_k = 0;
   std::vector<double> last_theta, last_occ;
   double *aux1 = nullptr, *aux2 = nullptr, *Rv = nullptr, *Gv = nullptr, *dMk = nullptr;
@@ -224,6 +226,21 @@ extern "C" int ks_options_default(ks_options *o) {
   o->anderson_beta = 0.7;
   o->mixed_inner_tol = 1e-5;
   o->deterministic = 1;
+  return KS_OK;
+}
+
+extern "C" int ks_set_options(ks_ctx *c, const ks_options *o) {
+  if (!c || !o) return fail(KS_ERR_ARG, "null argument");
+  const ks_options &p = c->opt;
+  if (o->mu != p.mu || o->n_H != p.n_H || o->xc_mode != p.xc_mode || o->hartree_mode != p.hartree_mode ||
+      o->k_max != p.k_max)
+    return fail(KS_ERR_ARG, "mu, n_H, xc_mode, hartree_mode and k_max are fixed at ks_create");
+  if (o->anderson_depth < 1 || o->anderson_depth > c->hist_alloc)
+    return fail(KS_ERR_ARG, "anderson_depth must be in 1..(the depth given at ks_create)");
+  if (!(o->tol_solve > 0.0) || !(o->tol_inner > 0.0) || !(o->tol_poisson > 0.0) || !(o->mixed_inner_tol > 0.0) ||
+      o->max_it_solve < 1 || o->max_it_inner < 1 || o->max_it_poisson < 1)
+    return fail(KS_ERR_ARG, "tolerances must be > 0 and iteration limits >= 1");
+  c->opt = *o;
   return KS_OK;
 }
 
@@ -478,8 +495,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   // (Z-curve) order of their node coordinates, so that consecutive rows are
   // spatial neighbours (compact row blocks, short gather distances); the API
   // numbers them by ascending node id ("natural" index) and every DOF-indexed
-  // argument is permuted at the boundary (int2nat).  KS_DOF_ORDER=natural
-  // keeps the natural order inside too.
+  // argument is permuted at the boundary (int2nat).
   std::vector<int32_t> node2int(nn, -1), node2bnd(nn, -1), bnodes, nat_nodes;
   for (int i = 0; i < nn; ++i) {
     if (mesh->dirichlet_host[i]) {
@@ -496,8 +512,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   c->h_int2nat.resize(N);
   for (int r = 0; r < N; ++r) c->h_int2nat[r] = r;
   {
-    const char *env = std::getenv("KS_DOF_ORDER");
-    if (!(env && std::strcmp(env, "natural") == 0)) {
+    {
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
       for (int r = 0; r < N; ++r)
         for (int d = 0; d < 3; ++d) {
@@ -852,8 +867,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   }
   // candidate row schedule: interior rows in Morton (Z-curve) order of their
   // coordinates, so the workgroups in flight sweep compact 3D regions.  The
-  // natural order is the default; ks_autotune (or KS_ROW_ORDER=morton)
-  // selects between them.
+  // natural order is the default; ks_autotune selects between them.
   std::vector<int32_t> rorder(N);
   {
     for (int r = 0; r < N; ++r) rorder[r] = r;
@@ -949,6 +963,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     A_(hist_in[j], nqt);
     A_(hist_F[j], nqt);
   }
+  c->hist_alloc = o.anderson_depth;
   A_(vh_int, N);
   A_(vh_nodes, nn);
   A_(wB, std::max(1, c->NB));
@@ -1086,38 +1101,18 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       H2D(c->til[ti].rmeta, t_rmeta[ti].data(), t_rmeta[ti].size());
     }
   {
-    const char *env = std::getenv("KS_ROW_ORDER");
-    c->rorder = (env && std::strcmp(env, "morton") == 0) ? c->rorder_m : nullptr;
-    auto geti = [](const char *n) {
-      const char *v = std::getenv(n);
-      return v ? std::atoi(v) : 0;
-    };
-    c->ng64 = geti("KS_SPMM_NG64");
-    c->ng32 = geti("KS_SPMM_NG32");
-    c->ngP = geti("KS_SPMM_NGP");
+    c->rorder = nullptr;
+    c->ng64 = c->ng32 = c->ngP = 0;
     // SpMM phase kernel before any autotuning: halo tiles of 85 rows with
     // 1024 threads (FP64), 85 rows with 512 threads (FP32), 128 rows with 256
-    // threads (Poisson, one column); KS_TILE64/32/P = rows (0 = row kernel),
-    // KS_TILE64_TB/32_TB/P_TB = threads
-    auto tile_env = [&](const char *n, int dflt, const char *ntb, int dtb) {
-      const char *v = std::getenv(n);
-      const char *vt = std::getenv(ntb);
-      const int i = tile_index(v ? std::atoi(v) : dflt);
-      const int tb = vt ? std::atoi(vt) : dtb;
+    // threads (Poisson, one column)
+    auto tile_of = [&](int rows, int tb) {
+      const int i = tile_index(rows);
       return i >= 0 ? 3 * i + (tb == 1024 ? 2 : (tb == 512 ? 1 : 0)) : -1;
     };
-    // KS_PROJ_TILE = "rows,columns,threads" of the projection products
-    if (const char *v = std::getenv("KS_PROJ_TILE")) {
-      int br = 0, kc = 0, tb = 0;
-      if (std::sscanf(v, "%d,%d,%d", &br, &kc, &tb) == 3) {
-        c->proj_br = br;
-        c->proj_kc = kc;
-        c->proj_tb = tb;
-      }
-    }
-    c->tile64 = tile_env("KS_TILE64", 85, "KS_TILE64_TB", 1024);
-    c->tile32 = tile_env("KS_TILE32", 85, "KS_TILE32_TB", 512);
-    c->tileP = tile_env("KS_TILEP", 128, "KS_TILEP_TB", 256);
+    c->tile64 = tile_of(85, 1024);
+    c->tile32 = tile_of(85, 512);
+    c->tileP = tile_of(128, 256);
     apply_tiles(c);
   }
   H2D(c->colB, colB.data(), colB.size());
@@ -1204,11 +1199,9 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return bail(fail(KS_ERR_HIP, "event creation failed"));
-  // multigrid hierarchy for the Hartree Poisson solves (KS_POISSON=jacobi: none)
+  // multigrid hierarchy for the Hartree Poisson solves
   {
-    const char *env = std::getenv("KS_POISSON");
-    const bool want = c->opt.hartree_mode != KS_HARTREE_OFF && !(env && std::strcmp(env, "jacobi") == 0);
-    if (want) {
+    if (c->opt.hartree_mode != KS_HARTREE_OFF) {
       std::vector<double> Kh(c->nnz), X((size_t)N * 3);
       if (hipMemcpyAsync(Kh.data(), c->K, sizeof(double) * c->nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
@@ -1522,6 +1515,11 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
                                 ks_solve_stats *st) {
   if (!c || !g_q) return fail(KS_ERR_ARG, "null argument");
   if (!c->have_step) return fail(KS_ERR_STATE, "no ks_scf_step result to differentiate");
+  // the adjoint uses the stationarity of the converged inner iteration; an
+  // inner iteration stopped at its limit has no such point
+  if (!c->last_inner_converged)
+    return fail(KS_ERR_STATE, "the last ks_scf_step's inner iteration did not reach tol_inner; "
+                              "its gradient is not defined");
   hipStream_t s = c->s;
   const int k = c->last_k, N = c->N, nH = c->N_H, m = nH + k;
   // R = A Psi - M Psi Theta with A the Hamiltonian of the final inner iteration
@@ -2428,7 +2426,9 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
       std::fprintf(stderr, "[ks-inner] it %d res %.3e jacobi_sweeps %d poisson_iters %d\n", it, res, info[5],
                    piters);
     }
-    if (res < c->opt.tol_inner) {
+    // converged, or the last permitted pass: no mixing, so the energies
+    // below pair rho_in with the potentials it produced (Sec. 3.1)
+    if (res < c->opt.tol_inner || it + 1 == c->opt.max_it_inner) {
       it += 1;
       break;
     }
@@ -2506,6 +2506,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   if (rep) *rep = R;
   c->have_step = true;
   c->last_nonlinear = nonlinear;
+  c->last_inner_converged = !nonlinear || res < c->opt.tol_inner;
   c->last_k = k;
   c->last_theta.assign(th.begin(), th.begin() + k);
   c->last_occ.assign(occ_host, occ_host + k);

@@ -479,10 +479,9 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
       return bail();
   }
   {
-    // FP32 level 0 (KS_MG_FP32=0 keeps it FP64)
-    const char *env = std::getenv("KS_MG_FP32");
+    // FP32 level 0 (smoothing and residuals of the finest level)
     const int64_t nnz0 = rp_h[n0];
-    if (!(env && std::strcmp(env, "0") == 0) && nnz0 > 0 && nnz0 < INT32_MAX) {
+    if (nnz0 > 0 && nnz0 < INT32_MAX) {
       MGLevel &v0 = mg->lv[0];
       if (mg->alloc(&mg->val32, (size_t)nnz0 + 8) && mg->alloc(&mg->dinv32, n0) && mg->alloc(&mg->x32, n0) &&
           mg->alloc(&mg->r32, n0) && mg->alloc(&mg->d32, n0) && mg->alloc(&mg->b32, n0)) {

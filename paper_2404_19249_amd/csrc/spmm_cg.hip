@@ -37,18 +37,10 @@ struct Control {
   int pad;
 };
 // workgroups of an elementwise phase: 512 (2 per CU, each sweeping many row
-// groups) unless KS_PCG_BLOCKS (a multiple of 8 in 256..2048) says
-// otherwise.  On the 2M-row, 24-column FP32 solve 512 streams as fast as
-// 2048 and leaves a quarter of the column partials for the one-workgroup
+// groups).  On the 2M-row, 24-column FP32 solve 512 streams as fast as 2048
+// and leaves a quarter of the column partials for the one-workgroup
 // reductions between phases.
-static int pcg_blocks() {
-  static const int nb = [] {
-    const char *e = std::getenv("KS_PCG_BLOCKS");
-    const int v = e ? std::atoi(e) : 512;
-    return (v >= 256 && v <= 2048 && v % 8 == 0) ? v : 512;
-  }();
-  return nb;
-}
+static int pcg_blocks() { return 512; }
 constexpr int SPMM_BLOCKS = 2048; // workgroups of the SpMM phase (8 waves per SIMD)
 size_t pcg_state_bytes(int k) { return sizeof(Control) + sizeof(ColState) * (size_t)k + 64; }
 

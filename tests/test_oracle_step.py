@@ -159,3 +159,36 @@ def test_converged_augmented_iteration_equals_direct_scf():
     # at outer convergence the two energy expressions coincide
     E = r.energies
     assert abs(E["total"] - E["KS"]) < 1e-8
+
+
+def test_inner_iteration_cap_keeps_energy_density_pairing():
+    """When the inner iteration stops at its limit, the reported energies and
+    the final pencil belong to one input density: nothing is mixed after the
+    last pass.  With a limit of one pass that density is rho^l itself, and the
+    Hartree energy 1/2 <V_H, rho_in> must equal the frozen-boundary form
+    1/2 <rho, V_0[rho]> + <rho, V_bc> - 1/2 <rho^l, V_bc> at rho = rho^l, which
+    is computed from two separate Poisson problems (zero-Dirichlet and
+    harmonic lift)."""
+    from oracle.step import step_energy
+    p = _tiny_nonlinear(order=1, n=6)
+    th0, Psi = initial_guess(p, 5)
+    r1 = ks_scf_step(p, Psi, th0, tol_solve=1e-13, tol_inner=1e-14, tol_poisson=1e-14,
+                     max_inner=1)
+    assert r1.inner_iters == 1 and r1.extra["res_inner"] > 1e-14
+    rho_l = r1.extra["rho_l"]
+    assert np.array_equal(r1.extra["rho_in"], rho_l)
+    e = step_energy(p, Psi, rho_l, rho_l, r1.extra["w_B"], tol_poisson=1e-14)
+    assert abs(r1.energies["H_in"] - e["H_step"]) < 1e-10 * abs(e["H_step"])
+    eps, vxc = lda_xc(rho_l, p.xc_mode)
+    assert abs(r1.energies["xc_in"] - p.inner(eps, rho_l)) < 1e-12 * abs(r1.energies["xc_in"])
+    # a later cap: the final pencil was built from the returned rho_in
+    r3 = ks_scf_step(p, Psi, th0, tol_solve=1e-13, tol_inner=1e-14, tol_poisson=1e-14,
+                     max_inner=3)
+    assert r3.inner_iters == 3
+    rin = r3.extra["rho_in"]
+    VH, _ = p.hartree_nodes(rin, r3.extra["w_B"], 1e-14)
+    _, vxc = lda_xc(rin, p.xc_mode)
+    Z = r3.extra["Z"]
+    FA = r3.FA_L + Z.T @ (p.potential_matrix(p.at_quad(VH) + vxc) @ Z)
+    assert np.abs(FA - r3.FA).max() < 1e-9 * np.abs(r3.FA).max()
+    assert abs(r3.energies["H_in"] - 0.5 * p.inner(p.at_quad(VH), rin)) < 1e-10 * abs(r3.energies["H_in"])
