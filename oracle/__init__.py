@@ -24,7 +24,7 @@ self-consistency properties ("parity unpinned" for its absolute energy).
 from .fe import (basis_tables, element_geometry, quad_points, assemble, restrict,
                  eval_at_quad, density_at_quad)
 from .xc import lda_xc
-from .hartree import density_moments, multipole_boundary, poisson_solve, hartree_potential
+from .hartree import density_moments, multipole_boundary
 from .solvers import jacobi_pcg
 from .coarse import coarse_interpolation
 from .step import (KSProblem, ks_scf_step, initial_guess, block_solve, small_eig, anderson_mix,
@@ -33,7 +33,7 @@ from .step import (KSProblem, ks_scf_step, initial_guess, block_solve, small_eig
 __all__ = [
     "basis_tables", "element_geometry", "quad_points", "assemble", "restrict",
     "eval_at_quad", "density_at_quad", "lda_xc", "density_moments",
-    "multipole_boundary", "poisson_solve", "hartree_potential", "jacobi_pcg",
+    "multipole_boundary", "jacobi_pcg",
     "coarse_interpolation", "KSProblem", "ks_scf_step", "initial_guess",
     "block_solve", "small_eig", "anderson_mix", "step_backward",
 ]

@@ -10,13 +10,12 @@ gives (1/2) sum q_ij (3 d_i d_j - delta_ij |d|^2) / |d|^5; the paper prints
 no 1/2, kept as the option ``quad_factor=1``.  The dipole p vanishes about
 the charge centre but is computed anyway.
 
-The Galerkin problem on interior nodes I with boundary nodes B fixed to w_D:
+The Galerkin problem on interior nodes I with boundary nodes B fixed to w_D,
     K_II V_I = 4 pi b_I - K_IB w_B,   b_a = <rho, phi_a>
-(K the stiffness matrix without the 1/2 of the kinetic term).
+(K the stiffness matrix without the 1/2 of the kinetic term), is solved by
+KSProblem.hartree_nodes in step.py.
 """
 import numpy as np
-
-from .solvers import jacobi_pcg
 
 
 def density_moments(rho_q, x_q, dV):
@@ -38,21 +37,3 @@ def multipole_boundary(points, Q, c, p, q, quad_factor=0.5):
     dip = (d @ p) / (r2 * r)
     quad = (3.0 * np.einsum("ni,ij,nj->n", d, q, d) - np.trace(q) * r2) / (r2 * r2 * r)
     return mono + dip + quad_factor * quad
-
-
-def poisson_solve(K_II, K_IB, load_I, w_B, tol=1e-12, x0=None, max_iter=100000):
-    """Interior values of V with K_II V_I = 4 pi load_I - K_IB w_B."""
-    rhs = 4.0 * np.pi * load_I - K_IB @ w_B
-    V, it, rr = jacobi_pcg(K_II, rhs, x0, tol=tol, max_iter=max_iter)
-    return V, int(it[0])
-
-
-def hartree_potential(prob, rho_q, w_B, tol=1e-12):
-    """Nodal V_H over all nodes for density rho_q and boundary data w_B."""
-    from .fe import load_vector
-    load = load_vector(prob.order, prob.quad, prob.elems, prob.det, prob.n_nodes, rho_q)
-    VI, it = poisson_solve(prob.K_II, prob.K_IB, load[prob.interior], w_B, tol=tol)
-    V = np.zeros(prob.n_nodes)
-    V[prob.interior] = VI
-    V[prob.boundary] = w_B
-    return V, it

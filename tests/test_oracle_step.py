@@ -192,3 +192,36 @@ def test_inner_iteration_cap_keeps_energy_density_pairing():
     FA = r3.FA_L + Z.T @ (p.potential_matrix(p.at_quad(VH) + vxc) @ Z)
     assert np.abs(FA - r3.FA).max() < 1e-9 * np.abs(r3.FA).max()
     assert abs(r3.energies["H_in"] - 0.5 * p.inner(p.at_quad(VH), rin)) < 1e-10 * abs(r3.energies["H_in"])
+
+
+def test_initial_guess_on_nested_mesh_is_the_coarse_mesh_problem():
+    """With V_ext = 0 (a zero nuclear charge) and a fine mesh that refines
+    the coarse Kuhn mesh T_H, span(I_H^h) is the coarse P1 space itself, so
+    the Ritz pairs of initial_guess are the eigenpairs of (1/2 K_H, M_H)
+    assembled on T_H (eq. st5: A_H = I^T A_h I) and every orbital is a
+    coarse eigenvector interpolated to the fine nodes.  A wrong operator,
+    basis or ordering in initial_guess fails this."""
+    from ks_inputs.mesh import freudenthal_mesh
+    from ks_inputs.quadrature import rule_for_order
+    L, nH, k = 4.0, 3, 4
+    coarse = freudenthal_mesh(nH, L, 1)
+    pc = KSProblem(order=1, coords=coarse.coords, elems=coarse.elems, dirichlet=coarse.dirichlet,
+                   quad=rule_for_order(1), Z=np.array([0.0]), R=np.full((1, 3), 0.1),
+                   occ=np.ones(k), L=L, n_H=nH, mu=1.0, hartree=False, xc_mode="none")
+    pc.setup()
+    lam_H = sla.eigh(0.5 * pc.K_II.toarray(), pc.M_II.toarray(), eigvals_only=True)[:k]
+    for order in (1, 2):
+        fine = freudenthal_mesh(2 * nH, L, order)
+        pf = KSProblem(order=order, coords=fine.coords, elems=fine.elems, dirichlet=fine.dirichlet,
+                       quad=rule_for_order(order), Z=np.array([0.0]), R=np.full((1, 3), 0.1),
+                       occ=np.ones(k), L=L, n_H=nH, mu=1.0, hartree=False, xc_mode="none")
+        pf.setup()
+        assert np.abs(pf.vext_q).max() == 0.0
+        th, Psi = initial_guess(pf, k)
+        assert np.abs(th - lam_H).max() < 1e-10 * np.abs(lam_H).max()
+        # the orbitals are coarse functions solving the coarse problem
+        U = np.linalg.lstsq(pf.P, Psi, rcond=None)[0]
+        assert np.abs(pf.P @ U - Psi).max() < 1e-10
+        Kc, Mc = 0.5 * pc.K_II.toarray(), pc.M_II.toarray()
+        assert np.abs(Kc @ U - (Mc @ U) * th[None, :]).max() < 1e-10
+        assert np.abs(Psi.T @ (pf.M_II @ Psi) - np.eye(k)).max() < 1e-10
