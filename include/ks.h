@@ -196,6 +196,20 @@ int ks_augmented_project(ks_ctx *ctx, const double *psi_hat, int32_t k, int32_t 
 int ks_small_eig(ks_ctx *ctx, const double *FA, const double *FB, int32_t m, int32_t k,
                  double *U, double *lambda_host, int32_t *rank_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * eigensolve as ks_small_eig without a context.  FA, FB device [m][m]
+ * row-major (ld m), U device [m][k], lambda_host [k], rank_host may be NULL;
+ * work is enqueued on `stream`, which is synchronised twice (the rank of F_B
+ * sizes the second stage) before the call returns.  Every work buffer lives
+ * in one fixed 19 MiB device array per GPU, held until the process ends:
+ * the call itself allocates nothing.  Limits: 1 <= k <= m <= 190
+ * (KS_ERR_ARG beyond).  Calls that overlap on one GPU (several host
+ * threads, or several streams before the first returns) share that array
+ * and race; results are undefined then. */
+int ks_small_eig_noalloc(const double *FA, const double *FB, int32_t m, int32_t k, double *U,
+                         double *lambda_host, int32_t *rank_host, hipStream_t stream);
+
 /* Initial guess: Ritz pairs of (1/2 K + M[V_ext], M) in span(I_H^h).
  * psi device [N][k], lambda_host [k]. */
 int ks_initial_guess(ks_ctx *ctx, int32_t k, double *psi, double *lambda_host);

@@ -94,6 +94,8 @@ _SIGS = {
     "ks_augmented_project": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P]),
     "ks_small_eig": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
                                C.POINTER(C.c_int32)]),
+    "ks_small_eig_noalloc": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32), _P]),
     "ks_initial_guess": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
     "ks_spmm_config": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "ks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),

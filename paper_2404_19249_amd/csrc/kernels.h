@@ -229,6 +229,8 @@ int launch_orth(int m, const double *FB, int ldfb, double *D, double *V, double 
 int launch_reduced_eig_split(int m, int k, int r, const double *FA, int ldfa, const double *D, const double *X,
                              double *W, int warm, double *S, double *T1, double *T2, double *work, double *lam,
                              double *theta, double *U, int *info, hipStream_t s);
+// Record msg as ks_last_error() of the calling thread; returns code.
+int set_error(int code, const char *msg);
 // Dense P (first n_H columns of Z) from the ELL form
 void launch_dense_P(int N, const int32_t *Pidx, const double *Pw, int n_H, double *Z, int ldz,
                     hipStream_t s);

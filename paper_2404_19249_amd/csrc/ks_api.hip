@@ -23,6 +23,8 @@ static int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
 }
+// the same error channel for entry points defined in other source files
+int ks::set_error(int code, const char *msg) { return fail(code, msg); }
 #define HIPCHK(x)                                                                     \
   do {                                                                                \
     hipError_t e_ = (x);                                                              \
