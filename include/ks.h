@@ -135,9 +135,10 @@ int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc *coarse, co
 int ks_destroy(ks_ctx *ctx);
 const char *ks_last_error(void);
 
-/* Sizes: out_host[0..9] = N (interior unknowns), n_nodes, n_elems, n_q,
+/* Sizes: out_host[0..10] = N (interior unknowns), n_nodes, n_elems, n_q,
  * N_H (coarse unknowns), nnz of the interior CSR pattern, n_loc, number of
- * element colours, leading dimension of the augmented basis Z, mu. */
+ * element colours, leading dimension of the augmented basis Z, mu, levels
+ * of the Hartree solver's multigrid hierarchy (0: Jacobi-PCG). */
 int ks_get_sizes(const ks_ctx *ctx, double *out_host);
 
 /* Assemble the Hamiltonian of the density of psi (Sec. 3.1 and 3.3):

@@ -79,11 +79,12 @@ class KSContext:
                                                  C.byref(quad), C.byref(atoms), C.byref(opt),
                                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)), self.lib)
         self.h = h
-        sz = (C.c_double * 10)()
+        sz = (C.c_double * 11)()
         B.check(self.lib.ks_get_sizes(self.h, sz))
         self.N, self.n_nodes, self.n_elems, self.n_q, self.N_H, self.nnz, self.n_loc, \
             self.n_colours, self.ld_z = [int(v) for v in sz[:9]]
         self.mu = float(sz[9])
+        self.mg_levels = int(sz[10])
         self.k_max = k_max
 
     _SETTABLE = ("tol_solve", "tol_inner", "tol_poisson", "max_it_solve", "max_it_inner",

@@ -1916,6 +1916,7 @@ extern "C" int ks_get_sizes(const ks_ctx *c, double *o) {
   o[7] = c->n_colours;
   o[8] = c->mp;
   o[9] = c->mu;
+  o[10] = mg_levels(c->mg);
   return KS_OK;
 }
 
