@@ -5,9 +5,12 @@ solve the N_occ boundary value problems, project onto the augmented space,
 nonlinear inner iteration with the small eigensolve, energies) on the
 "mixed" workload: 10 nuclei, 64^3 hexahedra -> P2 tetrahedra
 (N = 2,048,383 unknowns), N_occ = 24, moved mesh.  The headline value is
-DOF*RHS/s of the block BVP solve to a 1e-8 relative residual, measured with
-HIP events inside the timed steps; the FP64 and the mixed (FP32 PCG inside
-FP64 refinement) forms are both measured.
+DOF*RHS/s of the block BVP solve, measured with HIP events inside the timed
+steps.  The timed solves run to a 1e-9 relative residual (inside the metric's
+1e-8 bound: at 1e-8 the step's eigenvalues still move by up to ~2e-8 Ha, at
+1e-9 they stay within 1e-8 Ha of a tightly solved step); both tolerances are
+reported, in the FP64 and the mixed (FP32 PCG inside FP64 refinement) forms,
+with the eigenvalue and energy errors of each.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed|fp64]
 """
@@ -164,25 +167,77 @@ def copy_probe(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(k):
-    """The oracle (single thread) on a bounded sample of the same workload:
-    the mixed workload's nuclei and mesh recipe at 32^3 hexahedra, one block
-    solve of the k boundary value problems to 1e-8."""
+def cpu_info():
+    """CPU model and logical CPU count of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(k, tol, n=24, n_inner=None, N_full=None):
+    """The oracle, single thread, on a bounded sample of the same workload:
+    the mixed workload's nuclei and mesh recipe at n^3 hexahedra (n = 24:
+    N = 103,823), the BVP operator S = 1/2 K + M[V_ext + V_H + V_xc] + mu M
+    of the initial guess's density (Hartree and LDA included, as on the
+    GPU).  Timed legs: the assembly of S, the block solve of the k BVPs to
+    `tol` (the value), one projection (F_B, F_A^L) and one inner iteration
+    (Poisson, LDA, M[V_nl], its projection, the small eigensolve, the new
+    density).  The whole step at full size is extrapolated from these legs,
+    linear in N, with the GPU step's inner iteration count."""
+    import numpy as np
     from threadpoolctl import threadpool_limits
     from ks_inputs import make_workload
-    from oracle.step import KSProblem, initial_guess, block_solve
-    w = make_workload("mixed", n=32, k=k)
+    from oracle.step import KSProblem, initial_guess, block_solve, small_eig
+    from oracle.xc import lda_xc
+    w = make_workload("mixed", n=n, k=k)
+    legs = {}
     with threadpool_limits(1):
         p = KSProblem.from_workload(w)
         th, Psi = initial_guess(p, w.k)
-        S = (p.A_linear() + p.mu * p.M_II).tocsr()
+        rho = p.density(Psi)
+        wB = p.boundary_data(rho)
+        VH, _ = p.hartree_nodes(rho, wB, 1e-10)
         t0 = time.perf_counter()
-        X, its, rr = block_solve(p, S, Psi, th, tol=1e-8)
+        _, vxc = lda_xc(rho, p.xc_mode)
+        veff = p.vext_q + p.at_quad(VH) + vxc
+        S = (0.5 * p.K_II + p.potential_matrix(veff) + p.mu * p.M_II).tocsr()
+        legs["assembly_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        X, its, rr = block_solve(p, S, Psi, th, tol=tol)
         dt = time.perf_counter() - t0
-    return {"value": p.N * w.k / dt, "unit": "DOF*RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"mixed workload recipe at 32^3 hexes P2 (N={p.N}, k={w.k}, nnz={p.K_II.nnz}):"
-                      f" one FP64 block Jacobi-PCG solve to 1e-8, {int(max(its))} iterations,"
-                      f" {dt:.2f} s"}
+        legs["block_solve_s"] = dt
+        t0 = time.perf_counter()
+        G = p.P.T @ (p.M_II @ p.P)
+        T = np.linalg.solve(G, p.P.T @ (p.M_II @ X))
+        Z = np.hstack([p.P, X - p.P @ T])
+        FB = Z.T @ (p.M_II @ Z)
+        FAL = Z.T @ (p.A_linear() @ Z)
+        legs["projection_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        VHi, _ = p.hartree_nodes(rho, wB, 1e-12)
+        _, vx = lda_xc(rho, p.xc_mode)
+        FA = FAL + Z.T @ (p.potential_matrix(p.at_quad(VHi) + vx) @ Z)
+        _, U, _, _ = small_eig(FA, FB, w.k)
+        p.density(Z @ U)
+        legs["inner_iteration_s"] = time.perf_counter() - t0
+    model, nproc = cpu_info()
+    out = {"value": p.N * w.k / dt, "unit": "DOF*RHS/s", "cores": 1, "kind": "oracle",
+           "sample": f"mixed workload recipe at {n}^3 hexes P2 (N={p.N}, k={w.k}, nnz={p.K_II.nnz}),"
+                     f" S with Hartree and LDA from the initial guess's density: one FP64 block"
+                     f" Jacobi-PCG solve to {tol:g}, {int(max(its))} iterations, {dt:.2f} s",
+           "cpu_model": model, "nproc": nproc, "legs": legs, "N": int(p.N)}
+    if n_inner and N_full:
+        per = legs["assembly_s"] + legs["block_solve_s"] + legs["projection_s"] + n_inner * legs["inner_iteration_s"]
+        out["step_extrapolated_s"] = per * N_full / p.N
+        out["step_extrapolation"] = (f"(assembly + solve + projection + {n_inner} inner iterations) at N={p.N},"
+                                     f" scaled linearly to N={N_full}")
+    return out
 
 
 def batched_leg(torch, np, reps=3):
@@ -295,11 +350,72 @@ def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
     out = {"N": ctx.N, "k": w.k, "n_atoms": int(len(R0)), "forward_step_s": t1 - t0,
            "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
            "adjoint_solve_iters_max": int(max(st["iters"][:w.k])),
-           "E_KS": e["KS"], "inner_iters": rep["inner_iters"], "res_inner": rep["res_inner"],
+           "E_KS": e["KS"], "status": rep["status"], "inner_iters": rep["inner_iters"],
+           "res_inner": rep["res_inner"], "adjoint_converged": bool(st["converged"]),
            "force_check": {"atom": atom, "axis": axis, "h": h, "adjoint": f_adj, "central_fd": f_fd,
                            "rel_err": abs(f_adj - f_fd) / max(abs(f_fd), 1e-300)},
            "grad_q_values": int(g.numel())}
     ctx.close()
+    return out
+
+
+def solve_forms(ctx, k, psi, lam, occ, tols, reps=5):
+    """Both forms of the block solve on the operator assembled from psi, at
+    each tolerance: median device time, iterations, refinements, final
+    relative residual and the whole solve's algorithmic bandwidth."""
+    import numpy as np
+    N, nnz = ctx.N, ctx.nnz
+    ctx.assemble(psi, occ, want_fields=False)
+    out = {}
+    for tol in tols:
+        ctx.set_options(tol_solve=tol)
+        res = {}
+        for prec in ("fp64", "mixed"):
+            times, st = [], None
+            for _ in range(reps):
+                _, st = ctx.block_solve(psi, lam, prec)
+                times.append(st["seconds"])
+            t = float(np.median(times))
+            its = int(max(st["iters"]))
+            # whole-solve algorithmic bytes: iterations x B_it (+ the FP64
+            # residual SpMMs b - S x of the refinement loop in the mixed form)
+            if prec == "fp64":
+                sb = its * cg_iteration_bytes(N, nnz, k, 8)
+            else:
+                sb = its * cg_iteration_bytes(N, nnz, k, 4) + st["refinements"] * (nnz * 12 + 4 * (N + 1) + 3 * N * k * 8)
+            res[prec] = {"dof_rhs_per_s": N * k / t, "ms": t * 1e3, "iters_max": its,
+                         "refinements": st["refinements"], "converged": bool(st["converged"]),
+                         "relres_max": float(max(st["relres"])),
+                         "solve_GBs": sb / t / 1e9, "solve_frac_hbm": sb / t / 1e9 / HBM_PEAK_GBS}
+        res["mixed_speedup"] = res["fp64"]["ms"] / res["mixed"]["ms"]
+        out[f"tol_{tol:g}"] = res
+    return out
+
+
+def eig_accuracy(w, ctx, psi, lam, occ, tols):
+    """Eigenvalues and E_total of one step from (psi, lam) in each form and
+    at each solve tolerance against the same step with the BVPs solved to
+    1e-12 in FP64; all inner iterations to 1e-11.  Every step's status is
+    kept: an error is only meaningful when both steps converged."""
+    import numpy as np
+    from paper_2404_19249_amd import KSContext
+    ref_ctx = KSContext.from_workload(w, tol_solve=1e-12, tol_inner=1e-11, tol_poisson=1e-12,
+                                      max_it_inner=100)
+    lam_ref, rr = ref_ctx.scf_step(psi.clone(), lam, occ, precision="fp64")
+    ref_ctx.close()
+    out = {"reference": {"status": rr["status"], "inner_iters": rr["inner_iters"],
+                         "res_inner": rr["res_inner"], "solve_iters_max": int(max(rr["solve"]["iters"])),
+                         "tol_solve": 1e-12, "tol_inner": 1e-11}}
+    for tol in tols:
+        ctx.set_options(tol_solve=tol, tol_inner=1e-11, tol_poisson=1e-12, max_it_inner=100)
+        for prec in ("fp64", "mixed"):
+            l2, r2 = ctx.scf_step(psi.clone(), lam, occ, precision=prec)
+            out[f"{prec}_tol_{tol:g}"] = {
+                "status": r2["status"], "res_inner": r2["res_inner"],
+                "relres_max": float(max(r2["solve"]["relres"])),
+                "eig_err_Ha": float(np.abs(l2 - lam_ref).max()),
+                "E_total_err_Ha": abs(r2["E_total"] - rr["E_total"]),
+                "both_converged": rr["status"] == 0 and r2["status"] == 0}
     return out
 
 
@@ -308,6 +424,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol-solve", type=float, default=1e-9,
+                    help="relative residual of the timed block solves (the metric's bound is 1e-8; "
+                         "1e-9 keeps every eigenvalue of the step within 1e-8 Ha)")
     ap.add_argument("--no-shift-leg", action="store_true",
                     help="skip the secondary solve with mu' = -lambda_1 + 1")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
@@ -318,8 +437,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default SpMM kernels (for profiling one configuration)")
-    ap.add_argument("--differentiation", action="store_true",
-                    help="also run the differentiation workload (forward + adjoint, FD check)")
+    ap.add_argument("--no-differentiation", action="store_true",
+                    help="skip the differentiation workload (forward + adjoint, FD check)")
     ap.add_argument("--scf-run", action="store_true",
                     help="also run Algorithm 3 to convergence (density change < 2e-4) from the "
                          "coarse initial guess on the bench workload")
@@ -340,43 +459,46 @@ def main():
     t_setup = time.perf_counter()
     w = make_workload(args.workload, n=args.n)
     k = w.k
-    ctx = KSContext.from_workload(w, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
+    tol = args.tol_solve
+    ctx = KSContext.from_workload(w, tol_solve=tol, tol_inner=1e-8, tol_poisson=1e-10)
     N, nnz = ctx.N, ctx.nnz
     log(f"[bench] {w.name}: N={N} nnz={nnz} k={k} colours={ctx.n_colours} mu={ctx.mu:.1f} "
         f"setup {time.perf_counter() - t_setup:.1f}s")
-    # the step-0 state (initial guess): every warm-up and timed step, and the
-    # solve comparisons, start from it
-    psi0, lam0 = ctx.initial_guess(k)
-    psi, lam = psi0.clone(), lam0.copy()
     occ = w.occ
+    psi0, lam0 = ctx.initial_guess(k)
     copy_gbs = copy_probe(torch)
     log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
-    ctx.assemble(psi, occ, want_fields=False)
+    ctx.assemble(psi0, occ, want_fields=False)
     tune = None if args.no_autotune else ctx.autotune(k, reps=10)
     log(f"[bench] autotune: {json.dumps(tune)}")
     if args.mode == "solve":
         args.warmup, args.steps = 0, 0
-    # the state after one step from step 0 (psi1, lam1): its inner iteration
-    # converges, so the eigenvalue accuracy of the two forms is compared there
-    psi1, lam1 = None, None
-    for i in range(max(args.warmup, 1) if args.mode == "step" else 0):
-        psi.copy_(psi0)
-        lam, rep = ctx.scf_step(psi, lam0.copy(), occ, precision=args.precision)
-        if psi1 is None:
-            psi1, lam1 = psi.clone(), lam.copy()
-        log(f"[bench] warmup step {i}: inner {rep['inner_iters']} solve iters "
+    # The timed state: one step from the coarse Ritz guess (step 0).  From the
+    # guess itself the inner iteration does not converge on this workload
+    # (the augmented space's gap at the 24th level is a few mHa and the
+    # Anderson iteration oscillates, as the oracle's does on the 32^3 mesh),
+    # so every timed step starts from the state after it, where it converges.
+    psi1, lam1 = psi0.clone(), lam0.copy()
+    lam1, rep0 = ctx.scf_step(psi1, lam1, occ, precision=args.precision)
+    step0 = {"status": rep0["status"], "inner_iters": rep0["inner_iters"], "res_inner": rep0["res_inner"],
+             "solve_iters_max": int(max(rep0["solve"]["iters"])), "seconds": rep0["seconds"][5]}
+    log(f"[bench] step 0 (prepares the timed state): {json.dumps(step0)}")
+    psi = psi1.clone()
+    for i in range(args.warmup):
+        psi.copy_(psi1)
+        lam, rep = ctx.scf_step(psi, lam1.copy(), occ, precision=args.precision)
+        log(f"[bench] warmup step {i}: status {rep['status']} inner {rep['inner_iters']} solve iters "
             f"{max(rep['solve']['iters'])} {rep['seconds'][5]:.3f}s")
     # ------------------------------------------------------------ timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solve_s, reps = 0.0, []
-    psi_in, lam_in = psi0, lam0
     for i in range(args.steps):
-        psi.copy_(psi0)   # one pass of the step over the same step-0 input
-        lam, rep = ctx.scf_step(psi, lam0.copy(), occ, precision=args.precision)
+        psi.copy_(psi1)   # one pass of the step over the same input state
+        lam, rep = ctx.scf_step(psi, lam1.copy(), occ, precision=args.precision)
         solve_s += rep["solve"]["seconds"]
         reps.append(rep)
-        log(f"[bench] step {i}: E={rep['E_total']:.8f} inner={rep['inner_iters']} "
+        log(f"[bench] step {i}: status={rep['status']} E={rep['E_total']:.8f} inner={rep['inner_iters']} "
             f"solve={rep['solve']['seconds'] * 1e3:.2f}ms iters={max(rep['solve']['iters'])} "
             f"refine={rep['solve']['refinements']} res_inner={rep['res_inner']:.2e} total={rep['seconds'][5]:.3f}s")
     torch.cuda.synchronize()
@@ -388,44 +510,21 @@ def main():
     log(f"[bench] phases: {json.dumps(phases_other)}")
 
     # ------------------------------------- both forms on the same inputs
-    ctx.assemble(psi_in, occ, want_fields=False)
-    forms = {}
-    for prec in ("fp64", "mixed"):
-        times, st = [], None
-        for r in range(5):
-            out, st = ctx.block_solve(psi_in, lam_in, prec)
-            times.append(st["seconds"])
-        t = float(np.median(times))
-        its = int(max(st["iters"]))
-        # whole-solve algorithmic bytes: iterations x B_it (+ the FP64 residual
-        # SpMMs b - S x of the refinement loop in the mixed form)
-        if prec == "fp64":
-            sb = its * cg_iteration_bytes(N, nnz, k, 8)
-        else:
-            sb = its * cg_iteration_bytes(N, nnz, k, 4) + st["refinements"] * (nnz * 12 + 4 * (N + 1) + 3 * N * k * 8)
-        forms[prec] = {"dof_rhs_per_s": N * k / t, "ms": t * 1e3,
-                       "iters_max": its, "refinements": st["refinements"],
-                       "relres_max": float(max(st["relres"])),
-                       "solve_GBs": sb / t / 1e9, "solve_frac_hbm": sb / t / 1e9 / HBM_PEAK_GBS}
+    tols = sorted({tol, 1e-8})
+    forms = solve_forms(ctx, k, psi1, lam1, occ, tols)
+    forms["state"] = "after one step from the coarse Ritz guess (the timed steps' input)"
+    forms["step0_state"] = solve_forms(ctx, k, psi0, lam0, occ, tols)
+    ctx.set_options(tol_solve=tol, tol_inner=1e-8, tol_poisson=1e-10, max_it_inner=50)
     if value is None:
-        value = forms[args.precision]["dof_rhs_per_s"]
-    # eigenvalue accuracy of one step in each form against a tightly solved FP64 step
+        value = forms[f"tol_{tol:g}"][args.precision]["dof_rhs_per_s"]
     if args.mode == "step":
-        lam_of = {}
-        for key in ("fp64", "mixed"):
-            lam_of[key], _ = ctx.scf_step(psi1.clone(), lam1, occ, precision=key)
-        ref_ctx = KSContext.from_workload(w, tol_solve=1e-12, tol_inner=1e-8, tol_poisson=1e-10)
-        lam_of["ref"], _ = ref_ctx.scf_step(psi1.clone(), lam1, occ, precision="fp64")
-        ref_ctx.close()
-        for key in ("fp64", "mixed"):
-            forms[key]["eig_err_vs_fp64_tight_Ha"] = float(np.abs(lam_of[key] - lam_of["ref"]).max())
-        # the two forms at the same solve tolerance
-        forms["eig_diff_mixed_vs_fp64_Ha"] = float(np.abs(lam_of["mixed"] - lam_of["fp64"]).max())
-        ctx.assemble(psi_in, occ, want_fields=False)
-    forms["mixed_speedup"] = forms["fp64"]["ms"] / forms["mixed"]["ms"]
+        forms["eig_accuracy"] = eig_accuracy(w, ctx, psi1, lam1, occ, tols)
+        log(f"[bench] eigenvalue accuracy: {json.dumps(forms['eig_accuracy'])}")
+        ctx.set_options(tol_solve=tol, tol_inner=1e-8, tol_poisson=1e-10, max_it_inner=50)
 
     # ------------------------------------------- roofline of the SpMM phase
-    ctx.block_solve(psi_in, lam_in, "mixed")   # leaves the FP32 operator and workspace
+    ctx.assemble(psi1, occ, want_fields=False)
+    ctx.block_solve(psi1, lam1, "mixed")   # leaves the FP32 operator and workspace
     sv = 4 if args.precision == "mixed" else 8
     which = 3 if args.precision == "mixed" else 0
     ms_a = ctx.time_kernel(which, k, args.reps)
@@ -461,8 +560,11 @@ def main():
     for ph in phases_other.values():
         if "GBs" in ph:
             ph["frac_probe"] = ph["GBs"] / copy_gbs
-    for key in ("fp64", "mixed"):
-        forms[key]["solve_frac_probe"] = forms[key]["solve_GBs"] / copy_gbs
+    for key, res in forms.items():
+        if key.startswith("tol_"):
+            for prec in ("fp64", "mixed"):
+                res[prec]["solve_frac_probe"] = res[prec]["solve_GBs"] / copy_gbs
+    statuses = [r["status"] for r in reps]
     out = {
         "metric": METRIC, "value": value, "unit": "DOF*RHS/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -471,20 +573,28 @@ def main():
         "config": {"workload": f"{w.name}: {w.atoms.M} nuclei, {w.mesh.n}^3 hexes P{w.mesh.order} "
                                f"tets, moved mesh, N={N}, k={k}, nnz={nnz}",
                    "N": N, "k": k, "nnz": nnz, "precision": args.precision, "mu": ctx.mu,
+                   "tol_solve": tol, "tol_inner": 1e-8,
                    "value_basis": "N*k / device time of the block solve inside each timed step "
-                                   "(every step from the step-0 state: initial guess psi0, lambda0)"},
+                                   "(every step from the state after one step from the coarse "
+                                   "Ritz guess)"},
         "roofline": roof,
         "copy_probe_GBs": copy_gbs,
         "autotune": tune,
         "pcg_phases": phases,
         "phases": phases_other,
         "block_solve": forms,
-        "step": {} if not reps else {"dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
-                 "inner_iters": [r["inner_iters"] for r in reps],
-                 "poisson_iters": [r["poisson_iters"] for r in reps],
-                 "seconds_split": {n: float(np.mean([r["seconds"][i] for r in reps]))
-                                   for i, n in enumerate(["assemble", "solve", "project", "inner",
-                                                          "energies", "total"])}},
+        "step0": step0,
+        "step": {} if not reps else {
+            "dof_rhs_per_s": N * k / (ms_per_step * 1e-3),
+            "status": statuses, "all_converged": all(s == 0 for s in statuses),
+            "res_inner": [r["res_inner"] for r in reps],
+            "inner_iters": [r["inner_iters"] for r in reps],
+            "solve_iters_max": [int(max(r["solve"]["iters"])) for r in reps],
+            "solve_relres_max": [float(max(r["solve"]["relres"])) for r in reps],
+            "poisson_iters": [r["poisson_iters"] for r in reps],
+            "seconds_split": {n: float(np.mean([r["seconds"][i] for r in reps]))
+                              for i, n in enumerate(["assemble", "solve", "project", "inner",
+                                                     "energies", "total"])}},
     }
     vmin = None
     if not args.no_shift_leg and args.mode == "step":
@@ -511,7 +621,7 @@ def main():
             log(f"[bench] scf_run: {json.dumps(out['scf_run'])}")
         except Exception as e:  # reported, never hides the headline
             out["scf_run"] = {"error": repr(e)}
-    if args.differentiation:
+    if not args.no_differentiation and args.mode == "step":
         log("[bench] differentiation form ...")
         try:
             out["differentiation"] = differentiation_leg(np)
@@ -520,7 +630,10 @@ def main():
             out["differentiation"] = {"error": repr(e)}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(k)
+        n_inner = int(np.median([r["inner_iters"] for r in reps])) if reps else None
+        out["cpu_baseline"] = cpu_baseline(k, tol, n_inner=n_inner, N_full=N)
+        if reps:
+            out["cpu_baseline"]["step_gpu_over_cpu"] = out["cpu_baseline"]["step_extrapolated_s"] / (ms_per_step * 1e-3)
     print(json.dumps(out), flush=True)
 
 

@@ -201,24 +201,45 @@ def test_mixed_precision_solve_reaches_fp64_accuracy():
     assert d < 1e-6
 
 
-def test_mixed_precision_step_eigenvalues_within_1e8():
-    """Eigenvalue accuracy of the step against a tightly solved FP64 reference:
-    with the BVPs solved to 1e-10, the FP64 form and the FP32-in-FP64
-    refinement form both give every eigenvalue within 1e-8 Ha."""
-    w = make_workload("small_molecule", n=6)
+# The solve tolerance the benchmark times.  The eigenvalues of one step move
+# to first order with the BVP solution error, with a coefficient set by the
+# eigen-residual of the step's input: on the bench workload, from the state
+# after one step, 1.8e-8 Ha at a 1e-8 relative residual and 2.3e-9 Ha at
+# 1e-9; from the coarse Ritz guess itself the coefficient is about 15 times
+# larger.  The timed solves run to 1e-9, inside the metric's 1e-8 bound, and
+# every timed step starts from the state after one step.
+BENCH_TOL_SOLVE = 1e-9
+
+
+@pytest.mark.parametrize("name,kw", [("small_molecule", dict(n=6)), ("mixed", dict(n=5, k=6))])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_step_at_bench_tolerance_matches_tight_oracle_step(name, kw, prec):
+    """One step with the BVPs solved to the benchmark's tolerance, in the
+    FP32-in-FP64 refinement form and in FP64, against the oracle's step
+    with tightly solved sub-problems, both from the oracle's state after one
+    step from the coarse Ritz guess (the benchmark's timed input is such a
+    state): every eigenvalue within 1e-8 Ha, and E_total within
+    sum_i f_i 1e-8 Ha."""
+    w = make_workload(name, **kw)
     p = KSProblem.from_workload(w)
-    th, Psi = initial_guess(p, w.k)
-    lams = {}
-    for key, tol, prec in [("ref", 1e-13, "fp64"), ("fp64", 1e-10, "fp64"), ("mixed", 1e-10, "mixed")]:
-        ctx = _ctx(w, tol_solve=tol, tol_inner=1e-11, tol_poisson=1e-12)
-        psi = torch.tensor(Psi, device=DEV)
-        lams[key], rep = ctx.scf_step(psi, th, w.occ, precision=prec)
-        if prec == "mixed":
-            assert rep["solve"]["refinements"] >= 2
-        ctx.close()
-    print({k: np.abs(v - lams["ref"]).max() for k, v in lams.items()})
-    assert np.abs(lams["fp64"] - lams["ref"]).max() < 1e-8
-    assert np.abs(lams["mixed"] - lams["ref"]).max() < 1e-8
+    th0, Psi0 = initial_guess(p, w.k)
+    tight = dict(tol_solve=1e-13, tol_inner=1e-11, tol_poisson=1e-13, want_eks=False)
+    s1 = ks_scf_step(p, Psi0, th0, **tight)
+    Psi, th = s1.Psi, s1.lam
+    ref = ks_scf_step(p, Psi, th, **tight)
+    ctx = _ctx(w, tol_solve=BENCH_TOL_SOLVE, tol_inner=1e-11, tol_poisson=1e-12)
+    psi = torch.tensor(Psi, device=DEV)
+    lam, rep = ctx.scf_step(psi, th, w.occ, precision=prec)
+    assert rep["status"] == 0 and rep["solve"]["converged"]
+    assert max(rep["solve"]["relres"]) <= BENCH_TOL_SOLVE
+    if prec == "mixed":
+        assert rep["solve"]["refinements"] >= 2
+    err = np.abs(lam - ref.lam).max()
+    e_err = abs(rep["E_total"] - ref.energies["total"])
+    print(f"{name} {prec}: eig err {err:.2e} Ha, E_total err {e_err:.2e} Ha")
+    assert err < 1e-8
+    assert e_err < 1e-8 * float(np.sum(w.occ))
+    ctx.close()
 
 
 def _direct_dense_scf(p, k, tol=1e-12, beta=0.5, max_it=400):
