@@ -211,78 +211,127 @@ void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_
                        pairtab, w, V_q, out);
 }
 
-// Gather form.  emat[i][p] = sum_q w_q |J_e| V_eq phi_a(q) phi_b(q) for
-// e = eord[i] and pair p = (a <= b): one lane per (element, pair), every
-// element in one launch (no colouring: nothing is scattered here).
+// Row form.  One thread per interior row, one workgroup per block of
+// blockDim.x consecutive storage rows, whose CSR values are contiguous and
+// accumulate in LDS.  The thread of row r walks the incidences (e, a) of r
+// (the elements in which r is local node a, ascending element order) and,
+// for every local node b whose column is interior, adds
+//     sum_q w_q |J_e| V_eq phi_a(q) phi_b(q)
+// to the slot at off[b] of its own row.  Every value slot is summed by one
+// thread in a fixed order: no atomics, bitwise reproducible.  The rows of a
+// block are visited longest incidence list first (rperm), so that the rows
+// of one wavefront have similar trip counts.  out = base + M[V] over the
+// interior pattern (base may be null), out32 = (float) out (may be null).
 template <int NLOC, int NQ>
-__global__ void __launch_bounds__(256) k_elem_potential(const int32_t *__restrict__ eord, int n,
-                                                        const double *__restrict__ absdet,
-                                                        const double *__restrict__ pairtab,
-                                                        const double *__restrict__ w,
-                                                        const double *__restrict__ V, double *__restrict__ emat) {
-  constexpr int NP = NLOC * (NLOC + 1) / 2;
-  constexpr int EPW = 64 / NP;
-  constexpr int NC = EPW * NQ;  // weights per wave
-  __shared__ double s_pt[NQ * NP];
-  __shared__ double s_c[4][NC];  // per wave: w_q |J| V_q of its elements
-  for (int i = threadIdx.x; i < NQ * NP; i += blockDim.x) s_pt[i] = pairtab[i];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * EPW;
-  // weight l of the wave: point l % NQ of element l / NQ (coalesced loads)
-  for (int l = lane; l < NC; l += 64) {
-    const int el = l / NQ, q = l - el * NQ;
-    double cq = 0.0;
-    if (i0 + el < n) {
-      const int e = eord[i0 + el];
-      cq = w[q] * absdet[e] * V[(int64_t)e * NQ + q];
+__global__ void __launch_bounds__(ASM_ROWS) k_assemble_rows(int N, const int32_t *__restrict__ rowptr,
+                                                            const int32_t *__restrict__ incptr,
+                                                            const IncRec<NLOC> *__restrict__ inc,
+                                                            const uint8_t *__restrict__ rperm,
+                                                            const double *__restrict__ absdet,
+                                                            const double *__restrict__ phiq,
+                                                            const double *__restrict__ phib,
+                                                            const double *__restrict__ w,
+                                                            const double *__restrict__ V,
+                                                            const double *__restrict__ base,
+                                                            double *__restrict__ out, float *__restrict__ out32) {
+  extern __shared__ double s_acc[];
+  __shared__ double s_wphi[NQ * NLOC];  // w_q phi_a(q)
+  const int r0 = blockIdx.x * ASM_ROWS;
+  const int nr = min(ASM_ROWS, N - r0);
+  const int v0 = rowptr[r0], nv = rowptr[r0 + nr] - v0;
+  for (int i = threadIdx.x; i < nv; i += ASM_ROWS) s_acc[i] = base ? base[v0 + i] : 0.0;
+  for (int i = threadIdx.x; i < NQ * NLOC; i += ASM_ROWS) s_wphi[i] = w[i / NLOC] * phiq[i];
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    const int row = r0 + rperm[r0 + threadIdx.x];
+    double *acc = s_acc + (rowptr[row] - v0);
+    const int jb = incptr[row], j1 = incptr[row + 1];
+    // two-deep pipeline: while incidence j is computed, the values of j + 1
+    // (|J|, V at the points) and the record of j + 2 are in flight
+    IncRec<NLOC> rc, rn;
+    double dj = 0.0, vq[NQ];
+    if (jb < j1) {
+      rc = inc[jb];
+      if (jb + 1 < j1) rn = inc[jb + 1];
+      const int e = (int)(rc.ea >> 4);
+      dj = absdet[e];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) vq[q] = V[(int64_t)e * NQ + q];
     }
-    s_c[wave][l] = cq;
+    for (int j = jb; j < j1; ++j) {
+      const int a = (int)(rc.ea & 15u);
+      unsigned off[NLOC];
+#pragma unroll
+      for (int b = 0; b < NLOC; ++b) off[b] = rc.off[b];
+      // d_q = w_q |J| V_q phi_a(q); then v_b = sum_q d_q phi_b(q), b by b,
+      // each sum in three independent chains (phi_b(q) is uniform over the
+      // workgroup: scalar operands)
+      double d[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) d[q] = dj * vq[q] * s_wphi[q * NLOC + a];
+      if (j + 1 < j1) {
+        rc = rn;
+        if (j + 2 < j1) rn = inc[j + 2];
+        const int e = (int)(rc.ea >> 4);
+        dj = absdet[e];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) vq[q] = V[(int64_t)e * NQ + q];
+      }
+#pragma unroll 1
+      for (int b = 0; b < NLOC; ++b) {
+        const double *pb = phib + b * NQ;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q + 2 < NQ; q += 3) {
+          s0 += d[q] * pb[q];
+          s1 += d[q + 1] * pb[q + 1];
+          s2 += d[q + 2] * pb[q + 2];
+        }
+        if constexpr (NQ % 3 >= 1) s0 += d[NQ - NQ % 3] * pb[NQ - NQ % 3];
+        if constexpr (NQ % 3 == 2) s1 += d[NQ - 1] * pb[NQ - 1];
+        const double v = (s0 + s1) + s2;
+        unsigned o = off[0];
+#pragma unroll
+        for (int t = 1; t < NLOC; ++t)
+          if (b == t) o = off[t];
+        if (o != 255u) acc[o] += v;
+      }
+    }
   }
   __syncthreads();
-  const int es = lane / NP, p = lane - es * NP;
-  const int i = i0 + es;
-  if (es >= EPW || i >= n) return;
-  const double *c = s_c[wave] + es * NQ;
-  double m = 0.0;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) m += c[q] * s_pt[q * NP + p];
-  emat[(int64_t)i * NP + p] = m;
-}
-void launch_elem_potential(const int32_t *eord, int n, int n_loc, int n_q, const double *absdet,
-                           const double *pairtab, const double *w, const double *V_q, double *emat, hipStream_t s) {
-  if (n <= 0) return;
-  const int np = n_loc * (n_loc + 1) / 2, epw = 64 / np;
-  dim3 g((n + 4 * epw - 1) / (4 * epw)), b(256);
-  if (n_loc == 4 && n_q == 8)
-    hipLaunchKernelGGL((k_elem_potential<4, 8>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
-  else if (n_loc == 10 && n_q == 27)
-    hipLaunchKernelGGL((k_elem_potential<10, 27>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
-  else if (n_loc == 4 && n_q == 27)
-    hipLaunchKernelGGL((k_elem_potential<4, 27>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
-  else if (n_loc == 10 && n_q == 8)
-    hipLaunchKernelGGL((k_elem_potential<10, 8>), g, b, 0, s, eord, n, absdet, pairtab, w, V_q, emat);
-}
-// out[s] = base[s] (0 if base is null) + the pair values that belong to
-// value slot s, added in ascending order (a fixed order: bitwise
-// reproducible); out32[s] = (float)out[s] for s < n32 when out32 is given
-__global__ void k_gather_slots(int64_t nslots, const int32_t *__restrict__ cptr, const int32_t *__restrict__ cidx,
-                               const double *__restrict__ emat, const double *__restrict__ base,
-                               double *__restrict__ out, float *__restrict__ out32, int64_t n32) {
-  for (int64_t sidx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sidx < nslots;
-       sidx += (int64_t)gridDim.x * blockDim.x) {
-    const int j0 = cptr[sidx], j1 = cptr[sidx + 1];
-    double v = base ? base[sidx] : 0.0;
-    for (int j = j0; j < j1; ++j) v += emat[cidx[j]];
-    out[sidx] = v;
-    if (out32 && sidx < n32) out32[sidx] = (float)v;
+  for (int i = threadIdx.x; i < nv; i += ASM_ROWS) {
+    const double v = s_acc[i];
+    out[v0 + i] = v;
+    if (out32) out32[v0 + i] = (float)v;
   }
 }
-void launch_gather_slots(int64_t nslots, const int32_t *cptr, const int32_t *cidx, const double *emat,
-                         const double *base, double *out, hipStream_t s, float *out32, int64_t n32) {
-  if (nslots <= 0) return;
-  const int64_t b = std::min<int64_t>((nslots + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_gather_slots, dim3((unsigned)b), dim3(256), 0, s, nslots, cptr, cidx, emat, base, out,
-                     out32, n32);
+size_t assemble_rows_lds_limit() { return 160 * 1024 - 27 * 10 * sizeof(double) - 1024; }
+int launch_assemble_rows(int N, int n_loc, int n_q, const int32_t *rowptr, const int32_t *incptr, const void *inc,
+                         const uint8_t *rperm, size_t lds_bytes, const double *absdet, const double *phi,
+                         const double *phib, const double *w, const double *V_q, const double *base, double *out,
+                         float *out32, hipStream_t s) {
+  if (N <= 0) return 0;
+  dim3 g((N + ASM_ROWS - 1) / ASM_ROWS), b(ASM_ROWS);
+#define KS_AR(NL, NQ)                                                                                           \
+  do {                                                                                                          \
+    static bool attr = false;                                                                                   \
+    if (!attr) {                                                                                                \
+      if (hipFuncSetAttribute((const void *)k_assemble_rows<NL, NQ>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)assemble_rows_lds_limit()) != hipSuccess)                                    \
+        return -1;                                                                                              \
+      attr = true;                                                                                              \
+    }                                                                                                           \
+    hipLaunchKernelGGL((k_assemble_rows<NL, NQ>), g, b, lds_bytes, s, N, rowptr, incptr,                        \
+                       static_cast<const IncRec<NL> *>(inc), rperm, absdet, phi, phib, w, V_q, base, out,    \
+                       out32);     \
+    return 0;                                                                                                   \
+  } while (0)
+  if (n_loc == 4 && n_q == 8) KS_AR(4, 8);
+  if (n_loc == 10 && n_q == 27) KS_AR(10, 27);
+  if (n_loc == 4 && n_q == 27) KS_AR(4, 27);
+  if (n_loc == 10 && n_q == 8) KS_AR(10, 8);
+#undef KS_AR
+  return -1;
 }
 
 // ------------------------------------------------------------ load vector

@@ -24,15 +24,26 @@ void launch_assemble_KM(const int32_t *list, int count, int n_loc, int n_q,
 void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_q,
                                const int32_t *slot, const double *absdet, const double *pairtab,
                                const double *w, const double *V_q, double *out, hipStream_t s);
-// Gather form of the potential assembly: emat[i][p] = sum_q w_q |J| V_q
-// phi_a phi_b for element eord[i] and pair p (a <= b), all elements in one
-// launch; then out[s] = base[s] (0: base null) + sum_{j in [cptr[s], cptr[s+1])} emat[cidx[j]].
-void launch_elem_potential(const int32_t *eord, int n, int n_loc, int n_q, const double *absdet,
-                           const double *pairtab, const double *w, const double *V_q, double *emat, hipStream_t s);
-// With out32: also (float)out[s] for s < n32 (the FP32 operator copy).
-void launch_gather_slots(int64_t nslots, const int32_t *cptr, const int32_t *cidx, const double *emat,
-                         const double *base, double *out, hipStream_t s, float *out32 = nullptr,
-                         int64_t n32 = 0);
+// Row form of the potential assembly: one record per incidence (element e,
+// local node a) of an interior row, grouped by row (incptr) in ascending
+// element order: ea = e << 4 | a, off[b] = position of local node b's
+// column in the row's CSR column list (255: a boundary column, skipped).
+constexpr int ASM_ROWS = 128;  // rows (threads) per workgroup of the row-form assembly
+template <int NLOC> struct IncRec;
+template <> struct __align__(16) IncRec<10> { uint32_t ea; uint8_t off[12]; };
+template <> struct __align__(8) IncRec<4> { uint32_t ea; uint8_t off[4]; };
+// out = base + M[V] over the interior pattern (base may be null; out32 =
+// (float) out, may be null).  Row blocks of ASM_ROWS rows: rperm [N] holds each
+// block's local rows in visiting order; lds_bytes = 8 x the largest block's
+// value count (<= assemble_rows_lds_limit()).  Returns -1 when the shape has
+// no kernel or the LDS attribute cannot be set.
+size_t assemble_rows_lds_limit();
+// phi: [n_q][n_loc] basis values at the quadrature points; phib: the same
+// table b-major [n_loc][n_q]
+int launch_assemble_rows(int N, int n_loc, int n_q, const int32_t *rowptr, const int32_t *incptr, const void *inc,
+                         const uint8_t *rperm, size_t lds_bytes, const double *absdet, const double *phi,
+                         const double *phib, const double *w, const double *V_q, const double *base, double *out,
+                         float *out32, hipStream_t s);
 // out[dof_a] += sum_q w_q |J| f_q phi_a (one colour; dof = interior index or -1).
 void launch_load_vector(const int32_t *list, int count, int n_loc, int n_q,
                         const int32_t *edof, const double *absdet, const double *phi,

@@ -97,13 +97,14 @@ struct ks_ctx {
   double *coords = nullptr;
   int32_t *elems = nullptr, *edof = nullptr, *slot = nullptr, *node2int = nullptr,
           *node2bnd = nullptr, *bnodes = nullptr, *elem_perm = nullptr;
-  // gather form of the potential-matrix assembly: elements in the order of
-  // the first storage row they touch (g_eord), their pair values (g_emat
-  // [n][n_pairs]), and per value slot the pair values that add into it
-  // (g_cidx[g_cptr[s] .. g_cptr[s+1]), ascending)
-  int32_t *g_eord = nullptr, *g_cptr = nullptr, *g_cidx = nullptr;
-  double *g_emat = nullptr;
-  int g_nE = 0;
+  // row form of the potential-matrix assembly: per storage row its incidence
+  // records (element, local node, column offsets; IncRec) from r_incptr,
+  // each row block's visiting order r_perm, and its LDS size (0: the
+  // colour-scatter path is used instead)
+  int32_t *r_incptr = nullptr;
+  uint8_t *r_inc = nullptr, *r_perm = nullptr;
+  size_t r_lds = 0;
+  double *phib = nullptr;  // basis values b-major [n_loc][n_q] (row-form assembly)
   double *absdet = nullptr, *gl = nullptr, *phi = nullptr, *dphi = nullptr, *pairtab = nullptr,
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
   // CSR (interior rows; columns [0,nnz) interior, extension [nnz, nnz_ext) = K_IB part)
@@ -307,17 +308,17 @@ static int reduce_small(ks_ctx *c, double *part, int nblk, int nvals, double *ou
   return KS_OK;
 }
 
-// colour loop helpers
-// out = base + M[V] over the extended pattern (base null: out = M[V]);
-// out32: the FP32 copy of the interior values as well (nullptr: none)
-static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out, const double *base = nullptr,
+// out = base + M[V] (eq. st4) over the interior pattern (base null: out =
+// M[V]); out32: the FP32 copy of the values as well (nullptr: none).  The
+// colour-scatter path, used when the row form does not fit, covers the
+// extended pattern.
+// Returns true when out32 was written.
+static bool assemble_potential_all(ks_ctx *c, const double *Vq, double *out, const double *base = nullptr,
                                    float *out32 = nullptr) {
-  if (c->g_nE) {  // element pair values, then one gather per value slot
-    launch_elem_potential(c->g_eord, c->g_nE, c->n_loc, c->n_q, c->absdet, c->pairtab, c->qw, Vq, c->g_emat,
-                          c->s);
-    launch_gather_slots(c->nnz_ext, c->g_cptr, c->g_cidx, c->g_emat, base, out, c->s, out32, c->nnz);
-    return;
-  }
+  if (c->r_lds &&  // one thread per row sums its own slots
+      launch_assemble_rows(c->N, c->n_loc, c->n_q, c->rowptr, c->r_incptr, c->r_inc, c->r_perm, c->r_lds,
+                           c->absdet, c->phi, c->phib, c->qw, Vq, base, out, out32, c->s) == 0)
+    return out32 != nullptr;
   if (base) launch_axpby(c->nnz_ext, 1.0, base, 0.0, out, c->s);
   else launch_fill(c->nnz_ext, 0.0, out, c->s);
   for (int col = 0; col < c->n_colours; ++col) {
@@ -325,6 +326,7 @@ static void assemble_potential_all(ks_ctx *c, const double *Vq, double *out, con
     launch_assemble_potential(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->slot, c->absdet,
                               c->pairtab, c->qw, Vq, out, c->s);
   }
+  return false;
 }
 
 // V_H at the quadrature points for density rho with the frozen boundary
@@ -724,55 +726,50 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       }
     }
   });
-  // gather form of the potential assembly (see g_eord): elements touching an
-  // interior row, ordered by the first (Morton) storage row they touch, so
-  // that the pair values one row block gathers sit close together
-  std::vector<int32_t> g_eord, g_cptr, g_cidx;
+  // row form of the potential assembly (see r_incptr): the incidences of
+  // every storage row in ascending element order, and per row block its rows
+  // ordered by incidence count (longest first)
+  std::vector<int32_t> r_incptr;
+  std::vector<uint8_t> r_inc, r_perm;
+  size_t r_lds = 0;
   {
-    const int np = nl * (nl + 1) / 2;
-    std::vector<int32_t> ekey(ne);
-    parallel_for(ne, [&](int64_t e) {
-      int32_t k = INT32_MAX;
-      for (int a2 = 0; a2 < nl; ++a2) {
-        const int32_t d = edof[e * nl + a2];
-        if (d >= 0) k = std::min(k, d);
-      }
-      ekey[e] = k;
-    });
-    for (int e = 0; e < ne; ++e)
-      if (ekey[e] != INT32_MAX) g_eord.push_back(e);
-    std::stable_sort(g_eord.begin(), g_eord.end(), [&](int32_t x, int32_t y) { return ekey[x] < ekey[y]; });
-    const int64_t nslots = c->nnz_ext;
-    g_cptr.assign(nslots + 1, 0);
-    for (size_t i = 0; i < g_eord.size(); ++i) {
-      const int64_t e = g_eord[i];
-      for (int a2 = 0; a2 < nl * nl; ++a2) {
-        const int32_t sl = slot[e * nl * nl + a2];
-        if (sl >= 0) g_cptr[sl + 1]++;
-      }
-    }
-    int64_t total = 0;
-    for (int64_t sidx = 0; sidx < nslots; ++sidx) total += g_cptr[sidx + 1];
-    if (total < INT32_MAX)
-      for (int64_t sidx = 0; sidx < nslots; ++sidx) g_cptr[sidx + 1] += g_cptr[sidx];
-    if ((int64_t)g_eord.size() * np < INT32_MAX && total > 0 && total < INT32_MAX) {
-      g_cidx.resize(g_cptr[nslots]);
-      std::vector<int32_t> pos(g_cptr.begin(), g_cptr.end() - 1);
-      for (size_t i = 0; i < g_eord.size(); ++i) {
-        const int64_t e = g_eord[i];
-        for (int a2 = 0; a2 < nl; ++a2)
-          for (int b2 = 0; b2 < nl; ++b2) {
-            const int32_t sl = slot[(e * nl + a2) * nl + b2];
-            if (sl < 0) continue;
-            const int lo = std::min(a2, b2), hi = std::max(a2, b2);
-            const int pidx = lo * nl - (lo * (lo - 1)) / 2 + (hi - lo);  // pair (lo, hi), lo <= hi
-            g_cidx[pos[sl]++] = (int32_t)(i * np + pidx);
+    const int RS = nl == 10 ? 16 : 8;  // bytes per record (IncRec)
+    int maxlen = 0;
+    for (int r = 0; r < N; ++r) maxlen = std::max(maxlen, rowptr[r + 1] - rowptr[r]);
+    size_t blk = 0;
+    for (int r0 = 0; r0 < N; r0 += ASM_ROWS)
+      blk = std::max(blk, (size_t)(rowptr[std::min(N, r0 + ASM_ROWS)] - rowptr[r0]) * sizeof(double));
+    if ((nl == 4 || nl == 10) && (c->n_q == 8 || c->n_q == 27) && ne < (1 << 27) && maxlen < 255 && (int64_t)ne * nl < INT32_MAX &&
+        blk <= assemble_rows_lds_limit()) {
+      r_incptr.assign(N + 1, 0);
+      for (int64_t x = 0; x < (int64_t)ne * nl; ++x)
+        if (edof[x] >= 0) r_incptr[edof[x] + 1]++;
+      for (int r = 0; r < N; ++r) r_incptr[r + 1] += r_incptr[r];
+      r_inc.assign((size_t)r_incptr[N] * RS, 0);
+      std::vector<int32_t> pos(r_incptr.begin(), r_incptr.end() - 1);
+      for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < nl; ++a) {
+          const int r = edof[e * nl + a];
+          if (r < 0) continue;
+          uint8_t *rec = r_inc.data() + (size_t)pos[r]++ * RS;
+          const uint32_t ea = (uint32_t)e << 4 | (uint32_t)a;
+          std::memcpy(rec, &ea, 4);
+          for (int b = 0; b < nl; ++b) {
+            const int32_t sl = slot[(e * nl + a) * nl + b];
+            rec[4 + b] = (sl >= 0 && sl < c->nnz) ? (uint8_t)(sl - rowptr[r]) : (uint8_t)255;
           }
-      }
-      c->g_nE = (int)g_eord.size();
-    } else {
-      g_eord.clear();
-      g_cptr.clear();
+        }
+      r_perm.resize(N);
+      parallel_for((N + ASM_ROWS - 1) / ASM_ROWS, [&](int64_t bk) {
+        const int r0 = (int)bk * ASM_ROWS, nr = std::min(ASM_ROWS, N - r0);
+        std::vector<int> ord(nr);
+        for (int t = 0; t < nr; ++t) ord[t] = t;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+          return r_incptr[r0 + x + 1] - r_incptr[r0 + x] > r_incptr[r0 + y + 1] - r_incptr[r0 + y];
+        });
+        for (int t = 0; t < nr; ++t) r_perm[r0 + t] = (uint8_t)ord[t];
+      });
+      r_lds = std::max<size_t>(blk, 8);
     }
   }
   // greedy element colouring: no two elements of one colour share a node
@@ -918,11 +915,10 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   A_(elems, (size_t)ne * nl);
   A_(edof, (size_t)ne * nl);
   A_(slot, (size_t)ne * nl * nl);
-  if (c->g_nE) {
-    A_(g_eord, g_eord.size());
-    A_(g_cptr, g_cptr.size());
-    A_(g_cidx, g_cidx.size());
-    A_(g_emat, (size_t)c->g_nE * (nl * (nl + 1) / 2));
+  if (r_lds) {
+    A_(r_incptr, r_incptr.size());
+    A_(r_inc, r_inc.size());
+    A_(r_perm, r_perm.size());
   }
   A_(node2int, nn);
   A_(node2bnd, nn);
@@ -933,6 +929,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   A_(phi, phi.size());
   A_(dphi, dphi.size());
   A_(pairtab, pairtab.size());
+  A_(phib, phi.size());
   A_(qw, c->n_q);
   A_(qbary, 4 * c->n_q);
   A_(dZ, std::max(1, c->n_atoms));
@@ -1064,10 +1061,11 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   H2D(c->elems, el, (size_t)ne * nl);
   H2D(c->edof, edof.data(), edof.size());
   H2D(c->slot, slot.data(), slot.size());
-  if (c->g_nE) {
-    H2D(c->g_eord, g_eord.data(), g_eord.size());
-    H2D(c->g_cptr, g_cptr.data(), g_cptr.size());
-    H2D(c->g_cidx, g_cidx.data(), g_cidx.size());
+  if (r_lds) {
+    H2D(c->r_incptr, r_incptr.data(), r_incptr.size());
+    H2D(c->r_inc, r_inc.data(), r_inc.size());
+    H2D(c->r_perm, r_perm.data(), r_perm.size());
+    c->r_lds = r_lds;
   }
   H2D(c->node2int, node2int.data(), nn);
   H2D(c->node2bnd, node2bnd.data(), nn);
@@ -1076,6 +1074,10 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   H2D(c->phi, phi.data(), phi.size());
   H2D(c->dphi, dphi.data(), dphi.size());
   H2D(c->pairtab, pairtab.data(), pairtab.size());
+  std::vector<double> phib_h(phi.size());
+  for (int q = 0; q < c->n_q; ++q)
+    for (int a = 0; a < nl; ++a) phib_h[(size_t)a * c->n_q + q] = phi[(size_t)q * nl + a];
+  H2D(c->phib, phib_h.data(), phib_h.size());
   H2D(c->qw, quad->w_host, c->n_q);
   H2D(c->qbary, quad->bary_host, 4 * c->n_q);
   if (c->n_atoms) {
@@ -1949,8 +1951,7 @@ static int assemble_impl(ks_ctx *c, const double *psi, int k, const double *occ_
   const bool mixed = want_s32;
   c->have_S32 = false;
   if (nonlinear) {  // S = A^L + mu M + M[V_nl]
-    assemble_potential_all(c, c->vnl_q, c->S, c->base, mixed && c->g_nE ? c->S32 : nullptr);
-    c->have_S32 = mixed && c->g_nE;
+    c->have_S32 = assemble_potential_all(c, c->vnl_q, c->S, c->base, mixed ? c->S32 : nullptr);
   } else {
     launch_axpby(c->nnz_ext, 1.0, c->base, 0.0, c->S, s);
   }
