@@ -258,6 +258,34 @@ typedef struct {
 int ks_scf_run(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                int32_t precision, double tol_outer, int32_t max_steps, double *rho_q, ks_run_report *rep_host);
 
+/* The "direct" method that Sec. 4 compares Algorithm 3 with: the
+ * self-consistent field iteration on the whole fine space.  Every pass
+ * builds H(rho_in) = 1/2 K + M[V_ext + V_H(rho_in) + V_xc(rho_in)] (Sec. 3.1;
+ * the multipole boundary data w_D of eq. bd recomputed from rho_in), takes
+ * the lowest k eigenpairs of (H, M) by block LOBPCG (Jacobi preconditioner
+ * of 1/2 K + tau M, warm-started from the previous pass, to a relative
+ * residual ||H x - lambda M x|| / ||M x|| of max(tol_eig, min(1e-3,
+ * 0.1 x the last density residual))), and mixes the density by the Anderson
+ * scheme of Sec. 4 (the context's depth and beta), until ||rho_out -
+ * rho_in||_0 < tol with the last eigensolve at tol_eig, or max_scf passes.
+ * psi: device [N][k] in (the start orbitals) / out; lambda_host [k] in
+ * (used for the first preconditioner shift) / out; occ_host [k]; rho_q
+ * (device [n_elems][n_q], may be NULL) receives the last output density.
+ * The energy is that of Sec. 3.1 on the density that built the final H.
+ * Requires k <= min(k_max, 48).  Allocates its LOBPCG work space (about
+ * 11 N k_max doubles and one operator) on the first call.  Returns
+ * KS_NOT_CONVERGED at max_scf. */
+typedef struct {
+  int32_t scf_iters, eig_iters, poisson_iters, converged;
+  double res;                          /* final ||rho_out - rho_in||_0 */
+  double eig_res;                      /* largest relative eigen-residual of the last pass */
+  double E_total, E_band, E_H, E_xc, E_vxc, E_nn;
+  double seconds;
+} ks_direct_report;
+int ks_direct_scf(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
+                  double tol, int32_t max_scf, double tol_eig, int32_t max_eig, double *rho_q,
+                  ks_direct_report *rep_host);
+
 /* Replace the external potential: either its values at the quadrature
  * points (device [n_elems][n_q]) or new nuclear positions R_host [n_atoms][3]
  * (then V_ext = -sum Z_k/|x - R_k| and E_nn are recomputed).  Recomputes

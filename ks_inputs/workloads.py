@@ -17,6 +17,9 @@ replaces them.
                    k~U{1..min(12, sum Z // 2)}, moved, n_H = 4 if n < 24 else 6
   differentiation  P1, 96^3, [-12,12]^3, seed 5: 20 nuclei Z~U{1..6} with
                    sum Z >= 80, R~U[-6,6]^3 spacing >= 1.5, unmoved, k=40, n_H=6
+  lih, ch4, c6h6   the paper's molecules (positions and charges from Sec. 4),
+                   [-10,10]^3, P1 by default, n^3 hexes moved toward the
+                   nuclei, k = 2, 5, 21, LDA, n_H = 4 if n < 24 else 6
 """
 from dataclasses import dataclass, field
 import numpy as np
@@ -46,7 +49,7 @@ class Workload:
         return 8.0 * self.atoms.M * float(np.sum(self.atoms.Z ** 2))
 
 
-WORKLOADS = ("hydrogen", "small_molecule", "mixed", "batched", "differentiation")
+WORKLOADS = ("hydrogen", "small_molecule", "mixed", "batched", "differentiation", "lih", "ch4", "c6h6")
 
 _FULL_N = {"hydrogen": 16, "small_molecule": 32, "mixed": 64, "differentiation": 96}
 
@@ -89,6 +92,12 @@ def make_workload(name: str, n: int = None, k: int = None, system: int = 0,
         kk = k or 40
         return _build(name, order or 1, n or 96, 12.0, atoms, kk, [2.0] * kk, 6, True, True,
                       False, 5)
+    if name in ("lih", "ch4", "c6h6"):
+        from .molecules import molecule, BOX_HALF
+        atoms, kk = molecule(name)
+        kk = k or kk
+        return _build(name, order or 1, n or 32, BOX_HALF, atoms, kk, [2.0] * kk,
+                      4 if (n or 32) < 24 else 6, True, True, True, 0)
     if name == "batched":
         s = int(system)
         rng = np.random.default_rng(4000 + s)

@@ -67,6 +67,14 @@ class RunReport(C.Structure):
                 ("E_KS", C.c_double), ("seconds", C.c_double)]
 
 
+class DirectReport(C.Structure):
+    _fields_ = [("scf_iters", C.c_int32), ("eig_iters", C.c_int32), ("poisson_iters", C.c_int32),
+                ("converged", C.c_int32), ("res", C.c_double), ("eig_res", C.c_double),
+                ("E_total", C.c_double), ("E_band", C.c_double), ("E_H", C.c_double),
+                ("E_xc", C.c_double), ("E_vxc", C.c_double), ("E_nn", C.c_double),
+                ("seconds", C.c_double)]
+
+
 class BatchStats(C.Structure):
     _fields_ = [("seconds", C.c_double), ("n", C.c_int32), ("system_seconds", C.c_double * 256),
                 ("iters", C.c_int32 * 256), ("relres", C.c_double * 256),
@@ -115,6 +123,8 @@ _SIGS = {
     "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),
+    "ks_direct_scf": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                                C.c_double, C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(DirectReport)]),
     "ks_scf_run": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                              C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(RunReport)]),
 }

@@ -310,6 +310,22 @@ class KSContext:
         return lam_a, r
 
 
+    def direct_scf(self, psi, lam, occ, tol=1e-8, max_scf=200, tol_eig=1e-9, max_eig=500, rho_out=None):
+        """The direct SCF on the fine space (ks_direct_scf), in place on psi:
+        LOBPCG eigensolves and Anderson-mixed densities until the density
+        changes by less than tol."""
+        k = psi.shape[1]
+        lam_a = _f64(lam).copy()
+        occ_a = _f64(occ)
+        rep = B.DirectReport()
+        code = B.check(self.lib.ks_direct_scf(self.h, self._ptr(psi), B.dptr(lam_a), k, B.dptr(occ_a),
+                                              float(tol), int(max_scf), float(tol_eig), int(max_eig),
+                                              self._ptr(rho_out), C.byref(rep)), self.lib)
+        r = {f: getattr(rep, f) for f, _ in B.DirectReport._fields_}
+        r["status"] = code
+        return lam_a, r
+
+
 class KSBatch:
     """Many independent systems (each a KSContext with an assembled operator)
     solved together: one persistent launch, captured once in a hipGraph and

@@ -249,6 +249,95 @@ void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const doub
                      ldz, kt, U, k, Psi);
 }
 
+// Out[i][j] (row stride ldo) = sum_{a < m} S[i][a] C[a][j] for j < k: a tall
+// block times a small matrix, C (m x k, row-major) staged in LDS, four output
+// columns per lane when k % 4 == 0.
+__global__ void __launch_bounds__(256) k_tsmm(int N, int m, const double *__restrict__ S, int lds,
+                                              const double *__restrict__ C, int k, double *__restrict__ Out,
+                                              int ldo) {
+  extern __shared__ double s_c[];  // [m][k]
+  for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) s_c[idx] = C[idx];
+  __syncthreads();
+  const int VW = (k % 4 == 0) ? 4 : 1, CG = k / VW;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * CG) return;
+  const int i = (int)(t / CG), c0 = (int)(t - (int64_t)i * CG) * VW;
+  const double *sr = S + (int64_t)i * lds;
+  if (VW == 4) {
+    f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < m; ++a) acc += sr[a] * *reinterpret_cast<const f64x4 *>(s_c + a * k + c0);
+    double *o = Out + (int64_t)i * ldo + c0;
+    o[0] = acc.x; o[1] = acc.y; o[2] = acc.z; o[3] = acc.w;
+  } else {
+    double acc = 0.0;
+    for (int a = 0; a < m; ++a) acc += sr[a] * s_c[a * k + c0];
+    Out[(int64_t)i * ldo + c0] = acc;
+  }
+}
+int launch_tsmm(int N, int m, const double *S, int lds, const double *C, int k, double *Out, int ldo,
+                hipStream_t s) {
+  const size_t lb = sizeof(double) * (size_t)m * k;
+  if (lb > 64 * 1024) return -1;
+  const int CG = (k % 4 == 0) ? k / 4 : k;
+  const int64_t nt = (int64_t)N * CG;
+  if (nt > 0)
+    hipLaunchKernelGGL(k_tsmm, dim3((unsigned)((nt + 255) / 256)), dim3(256), lb, s, N, m, S, lds, C, k, Out, ldo);
+  return 0;
+}
+
+// LOBPCG residual block (rows of stride ld): R = HX - MX diag(theta); W =
+// D^-1 R (stride ldw); per-block column sums of R^2 (part[b][j]) and MX^2
+// (part[b][k + j]) in a fixed order.  blockDim = (256 / k) k threads: thread
+// t owns column t % k of every (256 / k)-th row of the block's rows.
+__global__ void __launch_bounds__(256) k_lobpcg_resid(int N, int k, int ld, const double *__restrict__ HX,
+                                                      const double *__restrict__ MX,
+                                                      const double *__restrict__ theta,
+                                                      const double *__restrict__ dinv, double *__restrict__ W,
+                                                      int ldw, double *__restrict__ part) {
+  __shared__ double s_r[256], s_m[256];
+  const int rpi = blockDim.x / k;
+  const int j = threadIdx.x % k, r0 = threadIdx.x / k;
+  const double th = theta[j];
+  double sr = 0.0, sm = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * rpi + r0; i < N; i += (int64_t)gridDim.x * rpi) {
+    const double mx = MX[i * ld + j];
+    const double r = HX[i * ld + j] - th * mx;
+    W[i * ldw + j] = r * dinv[i];
+    sr += r * r;
+    sm += mx * mx;
+  }
+  s_r[threadIdx.x] = sr;
+  s_m[threadIdx.x] = sm;
+  __syncthreads();
+  if ((int)threadIdx.x < k) {
+    double a = 0.0, b = 0.0;
+    for (int u = 0; u < rpi; ++u) {
+      a += s_r[u * k + threadIdx.x];
+      b += s_m[u * k + threadIdx.x];
+    }
+    part[(int64_t)blockIdx.x * 2 * k + threadIdx.x] = a;
+    part[(int64_t)blockIdx.x * 2 * k + k + threadIdx.x] = b;
+  }
+}
+int launch_lobpcg_resid(int N, int k, int ld, const double *HX, const double *MX, const double *theta,
+                        const double *dinv, double *W, int ldw, double *part, int max_blocks, hipStream_t s) {
+  if (k < 1 || k > 256) return -1;
+  const int rpi = 256 / k, tpb = rpi * k;
+  int nb = (int)std::min<int64_t>(((int64_t)N + rpi - 1) / rpi, max_blocks);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_lobpcg_resid, dim3(nb), dim3(tpb), 0, s, N, k, ld, HX, MX, theta, dinv, W, ldw, part);
+  return nb;
+}
+// dinv[i] = 1 / (a dK[i] + b dM[i])
+__global__ void k_prec_diag(int N, double a, const double *__restrict__ dK, double b, const double *__restrict__ dM,
+                            double *__restrict__ dinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dinv[i] = 1.0 / (a * dK[i] + b * dM[i]);
+}
+void launch_prec_diag(int N, double a, const double *dK, double b, const double *dM, double *dinv, hipStream_t s) {
+  if (N > 0) hipLaunchKernelGGL(k_prec_diag, dim3((N + 255) / 256), dim3(256), 0, s, N, a, dK, b, dM, dinv);
+}
+
 __global__ void k_small_gemm(int m, int n, int p, const double *__restrict__ A, int lda,
                              const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
                              double beta) {

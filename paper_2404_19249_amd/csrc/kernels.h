@@ -218,6 +218,17 @@ void launch_ellP_times(int N, const int32_t *Pidx, const double *Pw, const doubl
 // Psi[i][j] = sum_c Pw Ut[Pidx][j] + sum_a Zt[i][a] Ut2[a][j]  (Zt: tail block of Z)
 void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const double *Z, int ldz,
                int kt, const double *U, int k, double *Psi, hipStream_t s);
+// Out[i][j] (row stride ldo) = sum_{a < m} S[i][a] C[a][j], j < k (S row stride
+// lds, C m x k row-major, m k doubles <= 64 KB; -1 otherwise)
+int launch_tsmm(int N, int m, const double *S, int lds, const double *C, int k, double *Out, int ldo,
+                hipStream_t s);
+// LOBPCG residual block: R = HX - MX diag(theta) (row stride ld), W = D^-1 R
+// (row stride ldw), per-block column sums of R^2 and MX^2 in part[b][2k];
+// returns the number of blocks (<= max_blocks), -1 if k > 256
+int launch_lobpcg_resid(int N, int k, int ld, const double *HX, const double *MX, const double *theta,
+                        const double *dinv, double *W, int ldw, double *part, int max_blocks, hipStream_t s);
+// dinv = 1 / (a dK + b dM)
+void launch_prec_diag(int N, double a, const double *dK, double b, const double *dM, double *dinv, hipStream_t s);
 // C (m x n) = A (m x p) * B (p x n), small dense, row-major
 void launch_small_gemm(int m, int n, int p, const double *A, int lda, const double *B, int ldb,
                        double *C, int ldc, double beta, hipStream_t s);
