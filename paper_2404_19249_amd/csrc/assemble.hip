@@ -236,7 +236,13 @@ __global__ void __launch_bounds__(ASM_ROWS) k_assemble_rows(int N, const int32_t
                                                             double *__restrict__ out, float *__restrict__ out32) {
   extern __shared__ double s_acc[];
   __shared__ double s_wphi[NQ * NLOC];  // w_q phi_a(q)
-  const int r0 = blockIdx.x * ASM_ROWS;
+  // workgroups are dealt to the 8 XCDs round robin: give each XCD a
+  // contiguous eighth of the row blocks, so that neighbouring blocks (which
+  // share elements) meet in one L2
+  const int nblk = (N + ASM_ROWS - 1) / ASM_ROWS, per = (nblk + 7) / 8;
+  const int blk = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (blk >= nblk) return;
+  const int r0 = blk * ASM_ROWS;
   const int nr = min(ASM_ROWS, N - r0);
   const int v0 = rowptr[r0], nv = rowptr[r0 + nr] - v0;
   for (int i = threadIdx.x; i < nv; i += ASM_ROWS) s_acc[i] = base ? base[v0 + i] : 0.0;
@@ -311,7 +317,8 @@ int launch_assemble_rows(int N, int n_loc, int n_q, const int32_t *rowptr, const
                          const double *phib, const double *w, const double *V_q, const double *base, double *out,
                          float *out32, hipStream_t s) {
   if (N <= 0) return 0;
-  dim3 g((N + ASM_ROWS - 1) / ASM_ROWS), b(ASM_ROWS);
+  const int nblk = (N + ASM_ROWS - 1) / ASM_ROWS;
+  dim3 g(8 * ((nblk + 7) / 8)), b(ASM_ROWS);
 #define KS_AR(NL, NQ)                                                                                           \
   do {                                                                                                          \
     static bool attr = false;                                                                                   \
