@@ -122,15 +122,24 @@ def phase_rooflines(ctx, k, reps=10, with_projection=True):
     b = 3 * ne * nq * 8
     out["a2_lda"] = {"ms": ms, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS, "bytes": b}
     if with_projection:
-        ms = ctx.time_kernel(10, k, reps)
+        # the unit of a6: the projection onto the m-column basis (its bytes and
+        # flops as the dense formulation defines them), in the form the inner
+        # iteration runs (coarse blocks from the ELL interpolation, T^T H T on
+        # the matrix cores) and in the dense form
         b = 12 * nnz + 4 * (N + 1) + 8 * N * m
         f = 2 * nnz * m + 2 * N * m * m
-        out["a6_projection"] = {"ms": ms, "m": m, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS,
-                                "TFLOPs": f / ms / 1e9, "bytes": b, "flops": f}
+        for key, which in (("a6_projection", 10), ("a6_projection_dense", 12)):
+            ms = ctx.time_kernel(which, k, reps)
+            out[key] = {"ms": ms, "m": m, "GBs": b / ms / 1e6, "frac_hbm": b / ms / 1e6 / HBM_PEAK_GBS,
+                        "TFLOPs": f / ms / 1e9, "bytes": b, "flops": f}
+        # MFMA fraction from the flops the kernel executes: 16x16 tiles on
+        # and above the diagonal of the padded k x k product
+        tb = (k + 15) // 16
+        f_exec = 2 * N * 256 * tb * (tb + 1) // 2
         ms = ctx.time_kernel(11, k, reps)
-        f = 2 * N * m * m
-        out["a6_gemm_mfma_f64"] = {"ms": ms, "TFLOPs": f / ms / 1e9,
-                                   "frac_mfma_f64": f / ms / 1e9 / 78.6, "flops": f}
+        out["a6_gemm_mfma_f64"] = {"ms": ms, "executed_flops": f_exec, "TFLOPs": f_exec / ms / 1e9,
+                                   "frac_mfma_f64": f_exec / ms / 1e9 / 78.6,
+                                   "product": f"T^T (H T), N x {k}"}
     return out
 
 

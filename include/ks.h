@@ -358,10 +358,13 @@ int ks_batch_destroy(ks_batch *b);
  * (k = 1); 7 potential-matrix assembly M[V] over all colours; 8 density at the
  * quadrature points from the k orbitals of the last ks_assemble; 9 LDA
  * energy density and potential at the quadrature points; 10 projection
- * F = Z^T M[V] Z over the augmented basis of the last step (m = N_H + k;
- * SpMM + FP64 MFMA GEMM); 11 that GEMM alone.  7..11 overwrite work buffers
- * (a following ks_step_backward needs a new ks_scf_step).  Requires a prior
- * ks_assemble (10, 11: a prior ks_scf_step or ks_augmented_project). */
+ * F = Z^T M[V] Z over the augmented basis of the last step (m = N_H + k) as
+ * the inner iteration computes it (coarse blocks from the ELL form of I_H^h,
+ * T^T M[V] T on the FP64 matrix cores); 11 that T^T (M[V] T) GEMM alone;
+ * 12 the dense projection over all m columns of Z (SpMM + FP64 MFMA GEMM).
+ * 7..12 overwrite work buffers (a following ks_step_backward needs a new
+ * ks_scf_step).  Requires a prior ks_assemble (10..12: a prior ks_scf_step
+ * or ks_augmented_project). */
 int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
 
 /* Autotuner of the SpMM phase: on the current operator S (and the Poisson

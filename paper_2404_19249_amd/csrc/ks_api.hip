@@ -97,6 +97,15 @@ struct ks_ctx {
   double *coords = nullptr;
   int32_t *elems = nullptr, *edof = nullptr, *slot = nullptr, *node2int = nullptr,
           *node2bnd = nullptr, *bnodes = nullptr, *elem_perm = nullptr;
+  // coarse blocks of the inner iteration's projection (launch_proj_coarse):
+  // per CP_ROWS-row block its own / neighbour coarse index lists, partial
+  // offsets, and per output the partials that sum into it (cp_ok = 0: the
+  // dense projection is used)
+  int cp_ok = 0, cp_nblk = 0, cp_ldt = 0;
+  int32_t *cp_uoff = nullptr, *cp_ulist = nullptr, *cp_noff = nullptr, *cp_nlist = nullptr,
+          *cp_gpp_ptr = nullptr, *cp_gpt_ptr = nullptr;
+  int64_t *cp_ppoff = nullptr, *cp_ptoff = nullptr, *cp_gpp_idx = nullptr, *cp_gpt_idx = nullptr;
+  double *cp_pp = nullptr, *cp_pt = nullptr;
   // direct SCF (ks_direct_scf): LOBPCG blocks S = [X | W | P], H S, M S
   // ([N][3 k_d], row-major), two [N][k_d] temporaries, the operator H, the
   // Jacobi preconditioner, Gram matrices and the Ritz coefficients
@@ -870,6 +879,73 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       }
     });
   }
+  // coarse blocks of the projection (launch_proj_coarse): own and neighbour
+  // coarse index lists per block of CP_ROWS rows, partial offsets and the
+  // gather lists of every output (blocks in ascending order)
+  std::vector<int32_t> cp_uoff, cp_ulist, cp_noff, cp_nlist, cp_gpp_ptr, cp_gpt_ptr;
+  std::vector<int64_t> cp_ppoff, cp_ptoff, cp_gpp_idx, cp_gpt_idx;
+  int cp_ok = 0, cp_ldt = 0;
+  const int cp_nblk = (N + CP_ROWS - 1) / CP_ROWS;
+  if (c->N_H <= 256) {
+    std::vector<std::vector<int32_t>> own(cp_nblk), nbr(cp_nblk);
+    parallel_for(cp_nblk, [&](int64_t b) {
+      const int r0 = (int)b * CP_ROWS, r1 = std::min(N, r0 + CP_ROWS);
+      for (int r = r0; r < r1; ++r) {
+        for (int cc = 0; cc < 4; ++cc)
+          if (Pidx[4 * (size_t)r + cc] >= 0) own[b].push_back(Pidx[4 * (size_t)r + cc]);
+        for (int jj = rowptr[r]; jj < rowptr[r + 1]; ++jj)
+          for (int cc = 0; cc < 4; ++cc)
+            if (Pidx[4 * (size_t)colI[jj] + cc] >= 0) nbr[b].push_back(Pidx[4 * (size_t)colI[jj] + cc]);
+      }
+      for (auto *v : {&own[b], &nbr[b]}) {
+        std::sort(v->begin(), v->end());
+        v->erase(std::unique(v->begin(), v->end()), v->end());
+      }
+    });
+    cp_ok = 1;
+    for (int b = 0; b < cp_nblk; ++b) {
+      if (own[b].size() > 127) cp_ok = 0;
+      cp_ldt = std::max(cp_ldt, (int)nbr[b].size());
+    }
+    cp_ldt = std::max(cp_ldt, 1);
+    if (sizeof(double) * (size_t)CP_ROWS * cp_ldt > 48 * 1024) cp_ok = 0;
+    if (cp_ok) {
+      const int nH = c->N_H, km = c->k_max;
+      cp_uoff.assign(cp_nblk + 1, 0);
+      cp_noff.assign(cp_nblk + 1, 0);
+      cp_ppoff.assign(cp_nblk + 1, 0);
+      cp_ptoff.assign(cp_nblk + 1, 0);
+      for (int b = 0; b < cp_nblk; ++b) {
+        cp_uoff[b + 1] = cp_uoff[b] + (int)own[b].size();
+        cp_noff[b + 1] = cp_noff[b] + (int)nbr[b].size();
+        cp_ppoff[b + 1] = cp_ppoff[b] + (int64_t)own[b].size() * nbr[b].size();
+        cp_ptoff[b + 1] = cp_ptoff[b] + (int64_t)own[b].size() * km;
+        cp_ulist.insert(cp_ulist.end(), own[b].begin(), own[b].end());
+        cp_nlist.insert(cp_nlist.end(), nbr[b].begin(), nbr[b].end());
+      }
+      // gather lists: (I, J) of the P^T H P block and I of the P^T Y block
+      cp_gpp_ptr.assign((size_t)nH * nH + 1, 0);
+      cp_gpt_ptr.assign(nH + 1, 0);
+      for (int b = 0; b < cp_nblk; ++b)
+        for (int I : own[b]) {
+          cp_gpt_ptr[I + 1]++;
+          for (int J : nbr[b]) cp_gpp_ptr[(size_t)I * nH + J + 1]++;
+        }
+      for (size_t o = 0; o < (size_t)nH * nH; ++o) cp_gpp_ptr[o + 1] += cp_gpp_ptr[o];
+      for (int I = 0; I < nH; ++I) cp_gpt_ptr[I + 1] += cp_gpt_ptr[I];
+      cp_gpp_idx.resize(cp_gpp_ptr[(size_t)nH * nH]);
+      cp_gpt_idx.resize(cp_gpt_ptr[nH]);
+      std::vector<int32_t> fpp(cp_gpp_ptr.begin(), cp_gpp_ptr.end() - 1), fpt(cp_gpt_ptr.begin(), cp_gpt_ptr.end() - 1);
+      for (int b = 0; b < cp_nblk; ++b) {
+        const int nv = (int)nbr[b].size();
+        for (int u = 0; u < (int)own[b].size(); ++u) {
+          const int I = own[b][u];
+          cp_gpt_idx[fpt[I]++] = cp_ptoff[b] + (int64_t)u * km;
+          for (int v = 0; v < nv; ++v) cp_gpp_idx[fpp[(size_t)I * nH + nbr[b][v]]++] = cp_ppoff[b] + (int64_t)u * nv + v;
+        }
+      }
+    }
+  }
   // candidate row schedule: interior rows in Morton (Z-curve) order of their
   // coordinates, so the workgroups in flight sweep compact 3D regions.  The
   // natural order is the default; ks_autotune selects between them.
@@ -978,6 +1054,20 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   A_(mpart, (size_t)moments_blocks(ne) * 16);
   A_(Pidx, (size_t)N * 4);
   A_(Pw, (size_t)N * 4);
+  if (cp_ok) {
+    A_(cp_uoff, cp_uoff.size());
+    A_(cp_ulist, std::max<size_t>(1, cp_ulist.size()));
+    A_(cp_noff, cp_noff.size());
+    A_(cp_nlist, std::max<size_t>(1, cp_nlist.size()));
+    A_(cp_ppoff, cp_ppoff.size());
+    A_(cp_ptoff, cp_ptoff.size());
+    A_(cp_gpp_ptr, cp_gpp_ptr.size());
+    A_(cp_gpp_idx, std::max<size_t>(1, cp_gpp_idx.size()));
+    A_(cp_gpt_ptr, cp_gpt_ptr.size());
+    A_(cp_gpt_idx, std::max<size_t>(1, cp_gpt_idx.size()));
+    A_(cp_pp, std::max<int64_t>(1, cp_ppoff.back()));
+    A_(cp_pt, std::max<int64_t>(1, cp_ptoff.back()));
+  }
   A_(Z, (size_t)N * c->mp);
   A_(Y, (size_t)N * c->mp);
   // small dense blocks: the augmented pencil (m <= mp) and the direct SCF's
@@ -1130,6 +1220,21 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   H2D(c->colB, colB.data(), colB.size());
   H2D(c->Pidx, Pidx.data(), Pidx.size());
   H2D(c->Pw, Pw.data(), Pw.size());
+  if (cp_ok) {
+    H2D(c->cp_uoff, cp_uoff.data(), cp_uoff.size());
+    if (!cp_ulist.empty()) H2D(c->cp_ulist, cp_ulist.data(), cp_ulist.size());
+    H2D(c->cp_noff, cp_noff.data(), cp_noff.size());
+    if (!cp_nlist.empty()) H2D(c->cp_nlist, cp_nlist.data(), cp_nlist.size());
+    H2D(c->cp_ppoff, cp_ppoff.data(), cp_ppoff.size());
+    H2D(c->cp_ptoff, cp_ptoff.data(), cp_ptoff.size());
+    H2D(c->cp_gpp_ptr, cp_gpp_ptr.data(), cp_gpp_ptr.size());
+    if (!cp_gpp_idx.empty()) H2D(c->cp_gpp_idx, cp_gpp_idx.data(), cp_gpp_idx.size());
+    H2D(c->cp_gpt_ptr, cp_gpt_ptr.data(), cp_gpt_ptr.size());
+    if (!cp_gpt_idx.empty()) H2D(c->cp_gpt_idx, cp_gpt_idx.data(), cp_gpt_idx.size());
+    c->cp_ok = 1;
+    c->cp_nblk = cp_nblk;
+    c->cp_ldt = cp_ldt;
+  }
 #undef H2D
   if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned int), s) != hipSuccess)
     return bail(fail(KS_ERR_HIP, "memset failed"));
@@ -1296,6 +1401,7 @@ extern "C" int ks_spmm_config(const ks_ctx *c, int32_t *out_host) {  // 9 values
 }
 
 static void project_full(ks_ctx *c, const double *H, int m, double *F);
+static void project_nl(ks_ctx *c, const double *H, int k, double *F);
 
 // mean duration of `reps` back-to-back runs of one of the other hot-path
 // operations (see ks_time_kernel), on the context's current state
@@ -1314,11 +1420,14 @@ static int time_op(ks_ctx *c, int which, int k, int reps, float *ms) {
       case 9:  // LDA energy density and potential (a2)
         launch_xc(nqt, c->rho_l, c->opt.xc_mode == KS_XC_NONE ? KS_XC_X_PZ81 : c->opt.xc_mode, c->aux1, c->aux2, s);
         break;
-      case 10:  // projection F = Z^T (M[V_nl] Z) over the augmented basis (a6/a7): SpMM + MFMA GEMM
-        project_full(c, c->MNL, m, c->Ctmp);
+      case 10:  // projection F = Z^T (M[V_nl] Z) as the inner iteration runs it (a6/a7)
+        project_nl(c, c->MNL, k, c->Ctmp);
         break;
-      default:  // 11: the tall-skinny GEMM Z^T Y alone (FP64 MFMA)
-        launch_gemm_tn_sym(c->N, m, c->Z, c->mp, c->Y, c->mp, c->Ctmp, m, c->gwork, s);
+      case 11:  // its tall-skinny GEMM T^T (H T) alone (FP64 MFMA)
+        launch_gemm_tn_sym(c->N, k, c->Z + c->N_H, c->mp, c->Wv, k, c->Ttmp, k, c->gwork, s);
+        break;
+      default:  // 12: the dense projection over all m columns of Z (SpMM + MFMA GEMM)
+        project_full(c, c->MNL, m, c->Ctmp);
         break;
     }
   };
@@ -1338,7 +1447,7 @@ extern "C" int ks_time_kernel(ks_ctx *c, int32_t which, int32_t k, int32_t reps,
   if (!c || !ms_host) return fail(KS_ERR_ARG, "null argument");
   if (reps < 1 || k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
-  if (which < 0 || which > 11) return fail(KS_ERR_ARG, "which must be 0..11");
+  if (which < 0 || which > 12) return fail(KS_ERR_ARG, "which must be 0..12");
   if (which >= 7) {
     float ms = 0.f;
     TRY(time_op(c, which, k, reps, &ms));
@@ -2209,6 +2318,25 @@ static void project_full(ks_ctx *c, const double *H, int m, double *F) {
   spmm_cols(c, H, c->Z, c->mp, c->Y, c->mp, std::min(c->mp, (m + 1) & ~1));
   launch_gemm_tn_sym(c->N, m, c->Z, c->mp, c->Y, c->mp, F, m, c->gwork, c->s);
 }
+// F (m x m, ld m) = Z^T H Z for the inner iteration's H = M[V_nl]: the
+// blocks P^T H P and P^T H T from the ELL form of P (launch_proj_coarse),
+// T^T H T on the FP64 matrix cores; the dense product over all of Z where
+// the coarse blocks do not fit
+static void project_nl(ks_ctx *c, const double *H, int k, double *F) {
+  const int m = c->N_H + k, nH = c->N_H;
+  if (c->cp_ok) {
+    spmm_cols(c, H, c->Z + nH, c->mp, c->Wv, k, k);  // Y = H T
+    launch_gemm_tn_sym(c->N, k, c->Z + nH, c->mp, c->Wv, k, c->Ttmp, k, c->gwork, c->s);
+    if (launch_proj_coarse(c->N, nH, k, c->k_max, c->cp_nblk, c->cp_ldt, c->rowptr, c->col, H, c->Pidx, c->Pw,
+                           c->Wv, c->cp_uoff, c->cp_ulist, c->cp_noff, c->cp_nlist, c->cp_ppoff, c->cp_ptoff,
+                           c->cp_pp, c->cp_pt, c->cp_gpp_ptr, c->cp_gpp_idx, c->cp_gpt_ptr, c->cp_gpt_idx, F, m,
+                           c->s) == 0) {
+      launch_copy_cols(k, k, c->Ttmp, k, F + (size_t)nH * m, m, nH, c->s);  // T^T H T
+      return;
+    }
+  }
+  project_full(c, H, m, F);
+}
 // F from the fixed P-P block and the tail columns Z^T (H psi_tilde)
 static void project_tail(ks_ctx *c, const double *H, const double *PP, int k, double *F) {
   const int m = c->N_H + k;
@@ -2468,7 +2596,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
       launch_xc(nqt, c->rho_in, c->opt.xc_mode, c->exc_q, c->vxc_q, s);
       launch_add(nqt, c->vh_q, c->vxc_q, c->vnl_q, s);
       assemble_potential_all(c, c->vnl_q, c->MNL);
-      project_full(c, c->MNL, m, c->Ctmp);
+      project_nl(c, c->MNL, k, c->Ctmp);
       launch_combine3((int64_t)m * m, 1.0, c->FAL, 1.0, c->Ctmp, 0.0, nullptr, c->FA, s);
     } else {
       HIPCHK(hipMemcpyAsync(c->FA, c->FAL, sizeof(double) * m * m, hipMemcpyDeviceToDevice, s));
