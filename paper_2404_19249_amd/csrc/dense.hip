@@ -359,43 +359,61 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
                                                          const int32_t *__restrict__ nlist,
                                                          const int64_t *__restrict__ ppoff,
                                                          const int64_t *__restrict__ ptoff, double *__restrict__ pp,
-                                                         double *__restrict__ pt, int ldt) {
-  extern __shared__ double s_t[];       // [CP_ROWS][ldt]: (H P)[i][nbr_v]
-  __shared__ int16_t s_map[256];        // coarse index -> position in nbr (-1)
-  __shared__ int8_t s_u[CP_ROWS][4];    // own position of row i's P entries (-1)
-  __shared__ double s_w[CP_ROWS][4];
+                                                         double *__restrict__ pt, int ldt, int ldo) {
+  extern __shared__ double s_dyn[];
+  double *s_t = s_dyn;                           // [CP_ROWS][ldt]: (H P)[i][nbr_v]
+  double *s_p = s_dyn + CP_ROWS * ldt;           // [CP_ROWS][ldo]: P[i][own_u]
+  double *s_y = s_p + CP_ROWS * ldo;             // [CP_ROWS][k]: Y[i][j]
+  __shared__ int16_t s_map[256];                 // coarse index -> position in nbr (-1)
+  __shared__ int16_t s_umap[256];                // coarse index -> position in own (-1)
   const int b = blockIdx.x, r0 = b * CP_ROWS, nr = min(CP_ROWS, N - r0);
   const int u0 = uoff[b], nu = uoff[b + 1] - u0, v0 = noff[b], nv = noff[b + 1] - v0;
   const int t = threadIdx.x;
-  for (int i = t; i < n_H; i += CP_ROWS) s_map[i] = -1;
+  for (int i = t; i < n_H; i += CP_ROWS) {
+    s_map[i] = -1;
+    s_umap[i] = -1;
+  }
+  for (int i = t; i < CP_ROWS * (ldt + ldo); i += CP_ROWS) s_dyn[i] = 0.0;
   __syncthreads();
   for (int v = t; v < nv; v += CP_ROWS) s_map[nlist[v0 + v]] = (int16_t)v;
-  for (int i = t; i < CP_ROWS * ldt; i += CP_ROWS) s_t[i] = 0.0;
+  for (int u = t; u < nu; u += CP_ROWS) s_umap[ulist[u0 + u]] = (int16_t)u;
+  // Y rows of the block (coalesced)
+  for (int i = t; i < nr * k; i += CP_ROWS) s_y[i] = Y[(int64_t)r0 * k + i];
   __syncthreads();
   if (t < nr) {
     const int i = r0 + t;
     for (int c = 0; c < 4; ++c) {
       const int I = Pidx[4 * (int64_t)i + c];
-      int u = -1;
-      if (I >= 0)
-        for (int a = 0; a < nu; ++a)
-          if (ulist[u0 + a] == I) u = a;
-      s_u[t][c] = (int8_t)u;
-      s_w[t][c] = I >= 0 ? Pw[4 * (int64_t)i + c] : 0.0;
+      if (I >= 0) s_p[t * ldo + s_umap[I]] = Pw[4 * (int64_t)i + c];
     }
     double *ti = s_t + t * ldt;
-    for (int jj = rowptr[i]; jj < rowptr[i + 1]; ++jj) {
-      const int j = col[jj];
-      const double h = H[jj];
-      for (int c = 0; c < 4; ++c) {
-        const int J = Pidx[4 * (int64_t)j + c];
-        if (J >= 0) ti[s_map[J]] += h * Pw[4 * (int64_t)j + c];
+    const int jb = rowptr[i], je = rowptr[i + 1];
+    // four nonzeros at a time: their columns, values and P rows are loaded
+    // before any of them is accumulated
+    for (int jj = jb; jj < je; jj += 4) {
+      int j4[4];
+      double h4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = jj + u < je;
+        j4[u] = ok ? col[jj + u] : i;
+        h4[u] = ok ? H[jj + u] : 0.0;
       }
-    }
-  } else if (t < CP_ROWS) {
-    for (int c = 0; c < 4; ++c) {
-      s_u[t][c] = -1;
-      s_w[t][c] = 0.0;
+      int4 pi[4];
+      double2 pa[4], pb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pi[u] = *reinterpret_cast<const int4 *>(Pidx + 4 * (int64_t)j4[u]);
+        pa[u] = *reinterpret_cast<const double2 *>(Pw + 4 * (int64_t)j4[u]);
+        pb[u] = *reinterpret_cast<const double2 *>(Pw + 4 * (int64_t)j4[u] + 2);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pi[u].x >= 0) ti[s_map[pi[u].x]] += h4[u] * pa[u].x;
+        if (pi[u].y >= 0) ti[s_map[pi[u].y]] += h4[u] * pa[u].y;
+        if (pi[u].z >= 0) ti[s_map[pi[u].z]] += h4[u] * pb[u].x;
+        if (pi[u].w >= 0) ti[s_map[pi[u].w]] += h4[u] * pb[u].y;
+      }
     }
   }
   __syncthreads();
@@ -403,52 +421,57 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
   for (int o = t; o < nu * nv; o += CP_ROWS) {
     const int u = o / nv, v = o - u * nv;
     double acc = 0.0;
-    for (int r = 0; r < nr; ++r)
-      for (int c = 0; c < 4; ++c)
-        if (s_u[r][c] == u) acc += s_w[r][c] * s_t[r * ldt + v];
+    for (int r = 0; r < nr; ++r) acc += s_p[r * ldo + u] * s_t[r * ldt + v];
     ppb[o] = acc;
   }
   double *ptb = pt + ptoff[b];
   for (int o = t; o < nu * k; o += CP_ROWS) {
     const int u = o / k, j = o - u * k;
     double acc = 0.0;
-    for (int r = 0; r < nr; ++r)
-      for (int c = 0; c < 4; ++c)
-        if (s_u[r][c] == u) acc += s_w[r][c] * Y[(int64_t)(r0 + r) * k + j];
+    for (int r = 0; r < nr; ++r) acc += s_p[r * ldo + u] * s_y[r * k + j];
     ptb[u * kmax + j] = acc;
   }
 }
 // F[I][J] = sum of the pp partials listed for (I, J), ascending; F[I][n_H + j]
-// = F[n_H + j][I] = sum of the pt partials listed for I (at offset j)
-__global__ void k_proj_gather(int n_H, int k, int m, const int32_t *__restrict__ gpp_ptr,
-                              const int64_t *__restrict__ gpp_idx, const double *__restrict__ pp,
-                              const int32_t *__restrict__ gpt_ptr, const int64_t *__restrict__ gpt_idx,
-                              const double *__restrict__ pt, double *__restrict__ F) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+// = F[n_H + j][I] = sum of the pt partials listed for I (at offset j).  One
+// wavefront per output: lane l sums the entries l, l + 64, ... in order, then
+// a fixed butterfly combines the lanes.
+__global__ void __launch_bounds__(256) k_proj_gather(int n_H, int k, int m, const int32_t *__restrict__ gpp_ptr,
+                                                     const int64_t *__restrict__ gpp_idx,
+                                                     const double *__restrict__ pp,
+                                                     const int32_t *__restrict__ gpt_ptr,
+                                                     const int64_t *__restrict__ gpt_idx,
+                                                     const double *__restrict__ pt, double *__restrict__ F) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o < n_H * n_H) {
     double acc = 0.0;
-    for (int q = gpp_ptr[o]; q < gpp_ptr[o + 1]; ++q) acc += pp[gpp_idx[q]];
-    F[(int64_t)(o / n_H) * m + (o % n_H)] = acc;
+    for (int q = gpp_ptr[o] + lane; q < gpp_ptr[o + 1]; q += 64) acc += pp[gpp_idx[q]];
+    acc = wave_sum(acc);
+    if (lane == 0) F[(int64_t)(o / n_H) * m + (o % n_H)] = acc;
   } else if (o < n_H * n_H + n_H * k) {
     const int p = o - n_H * n_H, I = p / k, j = p - I * k;
     double acc = 0.0;
-    for (int q = gpt_ptr[I]; q < gpt_ptr[I + 1]; ++q) acc += pt[gpt_idx[q] + j];
-    F[(int64_t)I * m + n_H + j] = acc;
-    F[(int64_t)(n_H + j) * m + I] = acc;
+    for (int q = gpt_ptr[I] + lane; q < gpt_ptr[I + 1]; q += 64) acc += pt[gpt_idx[q] + j];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      F[(int64_t)I * m + n_H + j] = acc;
+      F[(int64_t)(n_H + j) * m + I] = acc;
+    }
   }
 }
-int launch_proj_coarse(int N, int n_H, int k, int kmax, int nblk, int ldt, const int32_t *rowptr, const int32_t *col,
+int launch_proj_coarse(int N, int n_H, int k, int kmax, int nblk, int ldt, int ldo, const int32_t *rowptr,
+                       const int32_t *col,
                        const double *H, const int32_t *Pidx, const double *Pw, const double *Y, const int32_t *uoff,
                        const int32_t *ulist, const int32_t *noff, const int32_t *nlist, const int64_t *ppoff,
                        const int64_t *ptoff, double *pp, double *pt, const int32_t *gpp_ptr, const int64_t *gpp_idx,
                        const int32_t *gpt_ptr, const int64_t *gpt_idx, double *F, int m, hipStream_t s) {
   if (n_H > 256 || k > kmax) return -1;
-  const size_t lds = sizeof(double) * (size_t)CP_ROWS * ldt;
-  if (lds > 48 * 1024) return -1;
+  const size_t lds = sizeof(double) * (size_t)CP_ROWS * (ldt + ldo + k);
+  if (lds > 60 * 1024) return -1;
   hipLaunchKernelGGL(k_proj_coarse, dim3(nblk), dim3(CP_ROWS), lds, s, N, n_H, k, kmax, rowptr, col, H, Pidx, Pw,
-                     Y, uoff, ulist, noff, nlist, ppoff, ptoff, pp, pt, ldt);
+                     Y, uoff, ulist, noff, nlist, ppoff, ptoff, pp, pt, ldt, ldo);
   const int nout = n_H * n_H + n_H * k;
-  hipLaunchKernelGGL(k_proj_gather, dim3((nout + 255) / 256), dim3(256), 0, s, n_H, k, m, gpp_ptr, gpp_idx, pp,
+  hipLaunchKernelGGL(k_proj_gather, dim3((nout + 3) / 4), dim3(256), 0, s, n_H, k, m, gpp_ptr, gpp_idx, pp,
                      gpt_ptr, gpt_idx, pt, F);
   return 0;
 }

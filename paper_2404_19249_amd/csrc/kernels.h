@@ -232,10 +232,12 @@ void launch_prec_diag(int N, double a, const double *dK, double b, const double 
 // Coarse blocks of the projection F = Z^T H Z with Z = [P | T] (P in ELL
 // form): F[:n_H][:n_H] = P^T H P and F[:n_H][n_H:] = P^T Y (mirrored), Y = H T
 // [N][k], from per-row-block partials (pp, pt; blocks of CP_ROWS rows, own and
-// neighbour coarse index lists) gathered in a fixed order.  ldt >= the
-// largest neighbour list; -1 when n_H > 256, k > kmax or the LDS does not fit.
+// neighbour coarse index lists) gathered in a fixed order.  ldt, ldo >= the
+// largest neighbour / own list; -1 when n_H > 256, k > kmax or the LDS does
+// not fit.  Pidx / Pw rows are 16- / 32-byte aligned (4 entries per row).
 constexpr int CP_ROWS = 64;
-int launch_proj_coarse(int N, int n_H, int k, int kmax, int nblk, int ldt, const int32_t *rowptr, const int32_t *col,
+int launch_proj_coarse(int N, int n_H, int k, int kmax, int nblk, int ldt, int ldo, const int32_t *rowptr,
+                       const int32_t *col,
                        const double *H, const int32_t *Pidx, const double *Pw, const double *Y, const int32_t *uoff,
                        const int32_t *ulist, const int32_t *noff, const int32_t *nlist, const int64_t *ppoff,
                        const int64_t *ptoff, double *pp, double *pt, const int32_t *gpp_ptr, const int64_t *gpp_idx,

@@ -101,7 +101,7 @@ struct ks_ctx {
   // per CP_ROWS-row block its own / neighbour coarse index lists, partial
   // offsets, and per output the partials that sum into it (cp_ok = 0: the
   // dense projection is used)
-  int cp_ok = 0, cp_nblk = 0, cp_ldt = 0;
+  int cp_ok = 0, cp_nblk = 0, cp_ldt = 0, cp_ldo = 0;
   int32_t *cp_uoff = nullptr, *cp_ulist = nullptr, *cp_noff = nullptr, *cp_nlist = nullptr,
           *cp_gpp_ptr = nullptr, *cp_gpt_ptr = nullptr;
   int64_t *cp_ppoff = nullptr, *cp_ptoff = nullptr, *cp_gpp_idx = nullptr, *cp_gpt_idx = nullptr;
@@ -884,7 +884,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
   // gather lists of every output (blocks in ascending order)
   std::vector<int32_t> cp_uoff, cp_ulist, cp_noff, cp_nlist, cp_gpp_ptr, cp_gpt_ptr;
   std::vector<int64_t> cp_ppoff, cp_ptoff, cp_gpp_idx, cp_gpt_idx;
-  int cp_ok = 0, cp_ldt = 0;
+  int cp_ok = 0, cp_ldt = 0, cp_ldo = 0;
   const int cp_nblk = (N + CP_ROWS - 1) / CP_ROWS;
   if (c->N_H <= 256) {
     std::vector<std::vector<int32_t>> own(cp_nblk), nbr(cp_nblk);
@@ -904,11 +904,12 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     });
     cp_ok = 1;
     for (int b = 0; b < cp_nblk; ++b) {
-      if (own[b].size() > 127) cp_ok = 0;
+      cp_ldo = std::max(cp_ldo, (int)own[b].size());
       cp_ldt = std::max(cp_ldt, (int)nbr[b].size());
     }
     cp_ldt = std::max(cp_ldt, 1);
-    if (sizeof(double) * (size_t)CP_ROWS * cp_ldt > 48 * 1024) cp_ok = 0;
+    cp_ldo = std::max(cp_ldo, 1);
+    if (sizeof(double) * (size_t)CP_ROWS * (cp_ldt + cp_ldo + c->k_max) > 60 * 1024) cp_ok = 0;
     if (cp_ok) {
       const int nH = c->N_H, km = c->k_max;
       cp_uoff.assign(cp_nblk + 1, 0);
@@ -1234,6 +1235,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     c->cp_ok = 1;
     c->cp_nblk = cp_nblk;
     c->cp_ldt = cp_ldt;
+    c->cp_ldo = cp_ldo;
   }
 #undef H2D
   if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned int), s) != hipSuccess)
@@ -2327,8 +2329,8 @@ static void project_nl(ks_ctx *c, const double *H, int k, double *F) {
   if (c->cp_ok) {
     spmm_cols(c, H, c->Z + nH, c->mp, c->Wv, k, k);  // Y = H T
     launch_gemm_tn_sym(c->N, k, c->Z + nH, c->mp, c->Wv, k, c->Ttmp, k, c->gwork, c->s);
-    if (launch_proj_coarse(c->N, nH, k, c->k_max, c->cp_nblk, c->cp_ldt, c->rowptr, c->col, H, c->Pidx, c->Pw,
-                           c->Wv, c->cp_uoff, c->cp_ulist, c->cp_noff, c->cp_nlist, c->cp_ppoff, c->cp_ptoff,
+    if (launch_proj_coarse(c->N, nH, k, c->k_max, c->cp_nblk, c->cp_ldt, c->cp_ldo, c->rowptr, c->col, H, c->Pidx,
+                           c->Pw, c->Wv, c->cp_uoff, c->cp_ulist, c->cp_noff, c->cp_nlist, c->cp_ppoff, c->cp_ptoff,
                            c->cp_pp, c->cp_pt, c->cp_gpp_ptr, c->cp_gpp_idx, c->cp_gpt_ptr, c->cp_gpt_idx, F, m,
                            c->s) == 0) {
       launch_copy_cols(k, k, c->Ttmp, k, F + (size_t)nH * m, m, nH, c->s);  // T^T H T
