@@ -315,46 +315,80 @@ def scf_run_leg(np, w, precision, tol=2e-4, max_steps=60):
     return out
 
 
-def compare_leg(np, molecules=("lih", "ch4", "c6h6"), sizes=(16, 32, 48), tol=2e-4, max_steps=200):
-    """Algorithm 3 against the direct method on the paper's molecules
-    (Sec. 4, Tables 1-3: LiH, CH4, C6H6 in (-10, 10)^3, P1 elements) on
-    meshes of n^3 hexahedra moved toward the nuclei: both from the coarse
-    Ritz guess of the same context until the density changes by less than
-    tol (the tolerance Sec. 4 sets for Algorithm 3); Algorithm 3 with the
-    paper's shift mu = 8 M sum Z^2 and the BVPs to 1e-8, the direct SCF with
-    LOBPCG eigensolves to a relative residual of 1e-6.  Wall time,
-    iterations and E_total of each."""
+COMPARE_SIZES = {"lih": (12, 14, 16, 20, 24, 28, 34, 44), "ch4": (12, 14, 16, 20, 26, 34, 44, 56),
+                 "c6h6": (14, 16, 20, 24, 32, 44, 56)}
+
+
+def compare_leg(np, molecules=("lih", "ch4", "c6h6"), k_asm=4, tol=2e-4, max_steps=300, precision="mixed"):
+    """Algorithm 3 against the direct method along a mesh sequence, as
+    Algorithm 2 runs them (Sec. 3.3; Sec. 4, Tables 1-3: LiH, CH4, C6H6 in
+    (-10, 10)^3, P1 elements, cumulative time against the element count).
+
+    The meshes are n^3 hexahedra moved toward the nuclei for the n in
+    COMPARE_SIZES (1.0e4 .. 1.1e6 elements; the paper's tables span 9e3 ..
+    2.8e6); a mesh is not adapted to the density.  Level 1 starts from the
+    coarse Ritz guess; every later level starts from the previous level's
+    orbitals carried over by Algorithm 1 (ks_interpolate, then
+    M-orthonormalised) and its eigenvalues.  The first k_asm levels use the
+    direct SCF (Algorithm 2's threshold K_asm = 4); after them three chains
+    go on from the same state: the direct SCF (LOBPCG to a relative residual
+    of 1e-6), Algorithm 3 with the paper's shift mu = 8 M sum Z^2, and
+    Algorithm 3 with mu = 2 (1 - lambda_1) from the previous level's lowest
+    eigenvalue (H~ + mu M stays positive definite while lambda_1 moves by less
+    than 1 - lambda_1); BVPs to 1e-8, each until the density changes by less
+    than tol.  Per level: element count, iterations, seconds (interpolation
+    included, mesh set-up not), E_total; the cumulative seconds of each
+    chain."""
     import torch
     from ks_inputs import make_workload
     from paper_2404_19249_amd import KSContext
-    rows = []
+    chains = ("direct", "algorithm3", "algorithm3_small_mu")
+    out = {"tol": tol, "k_asm": k_asm, "precision": precision, "molecules": []}
     for name in molecules:
-        for n in sizes:
+        carry = dict.fromkeys(chains)
+        cum = dict.fromkeys(chains, 0.0)
+        levels = []
+        for lev, n in enumerate(COMPARE_SIZES[name]):
             w = make_workload(name, n=n)
-            ctx = KSContext.from_workload(w, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
-            psi0, lam0 = ctx.initial_guess(w.k)
-            ctx.assemble(psi0, w.occ, want_fields=False)
-            row = {"molecule": name, "n": n, "elements": ctx.n_elems, "N": ctx.N, "k": w.k, "mu": ctx.mu}
-            for method in ("algorithm3", "direct"):
-                psi = psi0.clone()
+            row = {"level": lev + 1, "n": n}
+            for method in (("direct",) if lev < k_asm else chains):
+                prev = carry[method]
+                mu = None
+                if method == "algorithm3_small_mu":
+                    mu = 2.0 * (1.0 - float(prev[2][0]))
+                ctx = KSContext.from_workload(w, mu=mu, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
+                row.update(elements=ctx.n_elems, N=ctx.N)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                if method == "algorithm3":
-                    lam, rep = ctx.scf_run(psi, lam0, w.occ, tol=tol, max_steps=max_steps, precision="fp64")
-                    it = {"steps": rep["steps"], "inner_iters": rep["inner_iters"]}
+                if prev is None:
+                    psi, lam = ctx.initial_guess(w.k)
                 else:
-                    lam, rep = ctx.direct_scf(psi, lam0, w.occ, tol=tol, max_scf=max_steps, tol_eig=1e-6,
+                    psi = ctx.interpolate(prev[0], prev[1], orthonormalize=True)
+                    lam = prev[2].copy()
+                if method == "direct":
+                    lam, rep = ctx.direct_scf(psi, lam, w.occ, tol=tol, max_scf=max_steps, tol_eig=1e-6,
                                               max_eig=3000)
                     it = {"scf_iters": rep["scf_iters"], "eig_iters": rep["eig_iters"]}
+                else:
+                    lam, rep = ctx.scf_run(psi, lam, w.occ, tol=tol, max_steps=max_steps, precision=precision)
+                    it = {"steps": rep["steps"], "inner_iters": rep["inner_iters"], "mu": ctx.mu}
                 torch.cuda.synchronize()
-                row[method] = dict(it, seconds=time.perf_counter() - t0, converged=bool(rep["converged"]),
-                                   E_total=rep["E_total"], lambda_1=float(lam[0]),
-                                   res=rep.get("res_outer", rep.get("res")))
-            row["direct_over_algorithm3"] = row["direct"]["seconds"] / row["algorithm3"]["seconds"]
-            log(f"[bench] compare {json.dumps(row)}")
-            rows.append(row)
-            ctx.close()
-    return {"tol": tol, "rows": rows}
+                dt = time.perf_counter() - t0
+                ctx.close()
+                row[method] = dict(it, seconds=dt, converged=bool(rep["converged"]), E_total=rep["E_total"],
+                                   lambda_1=float(lam[0]))
+                if lev < k_asm:
+                    for ch in chains:
+                        carry[ch] = (w.mesh, psi, lam)
+                        cum[ch] += dt
+                else:
+                    carry[method] = (w.mesh, psi, lam)
+                    cum[method] += dt
+            row["cumulative_s"] = dict(cum)
+            log(f"[bench] compare {name} {json.dumps(row)}")
+            levels.append(row)
+        out["molecules"].append({"molecule": name, "k": w.k, "levels": levels})
+    return out
 
 
 def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
@@ -491,14 +525,14 @@ def main():
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the differentiation workload (forward + adjoint, FD check)")
     ap.add_argument("--compare", action="store_true",
-                    help="also run Algorithm 3 against the direct SCF on the paper's molecules "
-                         "(LiH, CH4, C6H6) on several mesh sizes")
+                    help="also run Algorithm 3 against the direct SCF along a mesh sequence on "
+                         "the paper's molecules (LiH, CH4, C6H6)")
     ap.add_argument("--scf-run", action="store_true",
                     help="also run Algorithm 3 to convergence (density change < 2e-4) from the "
                          "coarse initial guess on the bench workload")
-    ap.add_argument("--mode", default="step", choices=["step", "solve"],
+    ap.add_argument("--mode", default="step", choices=["step", "solve", "compare"],
                     help="solve: skip the SCF steps (block solves and kernel timings only, "
-                         "for profiling)")
+                         "for profiling); compare: only the mesh-sequence comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sharded "
@@ -510,6 +544,9 @@ def main():
     from ks_inputs import make_workload
     from paper_2404_19249_amd import KSContext
 
+    if args.mode == "compare":
+        print(json.dumps({"compare": compare_leg(np)}), flush=True)
+        return
     t_setup = time.perf_counter()
     w = make_workload(args.workload, n=args.n)
     k = w.k

@@ -258,6 +258,23 @@ typedef struct {
 int ks_scf_run(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const double *occ_host,
                int32_t precision, double tol_outer, int32_t max_steps, double *rho_q, ks_run_report *rep_host);
 
+/* Algorithm 1 (Sec. 3.2) between two meshes, as Algorithm 2 uses it to
+ * carry the orbitals to the next mesh: every interior node of this context's
+ * mesh is located in the P1 tetrahedral mesh src (nearest vertex from a
+ * bucket grid, then a barycentric walk; a node outside src takes the
+ * weights of the last element of its walk, projected onto it) and the
+ * orbitals, P1 on src and zero on its Dirichlet nodes, are interpolated
+ * there.  psi_src: device [N_src][k], rows = src's non-Dirichlet nodes in
+ * ascending order (the orbital layout of a context on src); psi: device
+ * [N][k] on this context.  The location runs on the host; two small device
+ * buffers are allocated for the call.  orthonormalize != 0: the
+ * interpolated columns are then made M-orthonormal on this mesh in column
+ * order (Cholesky of Psi^T M Psi), as an SCF started from them expects;
+ * KS_ERR_EIG if they are linearly dependent.  KS_ERR_ARG for a P2 source or
+ * k outside 1..k_max. */
+int ks_interpolate(ks_ctx *ctx, const ks_mesh_desc *src, const double *psi_src, int32_t k, int32_t orthonormalize,
+                   double *psi);
+
 /* The "direct" method that Sec. 4 compares Algorithm 3 with: the
  * self-consistent field iteration on the whole fine space.  Every pass
  * builds H(rho_in) = 1/2 K + M[V_ext + V_H(rho_in) + V_xc(rho_in)] (Sec. 3.1;

@@ -310,6 +310,20 @@ class KSContext:
         return lam_a, r
 
 
+    def interpolate(self, src_mesh, psi_src, orthonormalize=False):
+        """ks_interpolate: orbitals P1 on src_mesh (coords, elems, dirichlet,
+        order 1) carried to this context's interior nodes by Algorithm 1,
+        optionally made M-orthonormal there (Cholesky, column order)."""
+        k = psi_src.shape[1]
+        co, el, di = _f64(src_mesh.coords), _i32(src_mesh.elems), np.ascontiguousarray(src_mesh.dirichlet, np.uint8)
+        md = B.MeshDesc(co.shape[0], el.shape[0], int(getattr(src_mesh, "order", 1)),
+                        co.ctypes.data_as(C.POINTER(C.c_double)), el.ctypes.data_as(C.POINTER(C.c_int32)),
+                        di.ctypes.data_as(C.POINTER(C.c_uint8)), float(getattr(src_mesh, "L", 0.0)))
+        out = self.empty(self.N, k)
+        B.check(self.lib.ks_interpolate(self.h, C.byref(md), self._ptr(psi_src.contiguous()), k,
+                                        int(bool(orthonormalize)), self._ptr(out)), self.lib)
+        return out
+
     def direct_scf(self, psi, lam, occ, tol=1e-8, max_scf=200, tol_eig=1e-9, max_eig=500, rho_out=None):
         """The direct SCF on the fine space (ks_direct_scf), in place on psi:
         LOBPCG eigensolves and Anderson-mixed densities until the density

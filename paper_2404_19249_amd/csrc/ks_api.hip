@@ -1348,7 +1348,11 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
       {"FB", c->FB, (int64_t)c->mp * c->mp}, {"FAL", c->FAL, (int64_t)c->mp * c->mp},
       {"FA", c->FA, (int64_t)c->mp * c->mp}, {"U", c->U, (int64_t)c->mp * c->k_max},
       {"rho_in", c->rho_in, (int64_t)c->n_e * c->n_q}, {"vh_q", c->vh_q, (int64_t)c->n_e * c->n_q},
-      {"wB", c->wB, (int64_t)c->NB}, {"mom", c->mom, 16}, {"S", c->S, (int64_t)c->nnz}};
+      {"wB", c->wB, (int64_t)c->NB}, {"mom", c->mom, 16}, {"S", c->S, (int64_t)c->nnz},
+      // LOBPCG blocks of the direct SCF ([N][3 k] storage order; Gram matrices m x m)
+      {"dS", c->dS, c->d_k ? (int64_t)c->N * 3 * c->d_k : 0}, {"dHS", c->dHS, c->d_k ? (int64_t)c->N * 3 * c->d_k : 0},
+      {"dMS", c->dMS, c->d_k ? (int64_t)c->N * 3 * c->d_k : 0}, {"dGM", c->dGM, (int64_t)9 * c->d_k * c->d_k},
+      {"dGH", c->dGH, (int64_t)9 * c->d_k * c->d_k}};
   // "S32": the FP32 operator copy, nnz floats packed into ceil(nnz / 2) doubles
   if (std::strcmp(name, "S32") == 0) {
     if (!c->have_S32) return fail(KS_ERR_STATE, "no FP32 operator copy");
@@ -1359,7 +1363,7 @@ extern "C" int ks_debug_buffer(ks_ctx *c, const char *name, double *dst, int64_t
   }
   for (auto &t : tab)
     if (std::strcmp(t.n, name) == 0) {
-      if (n > t.size) return fail(KS_ERR_ARG, "buffer smaller than requested");
+      if (n > t.size || !t.p) return fail(KS_ERR_ARG, "buffer smaller than requested");
       const bool rows = (t.p == c->Z || t.p == c->Y) && n == t.size;
       if (rows) launch_rows_to_api(c->N, c->mp, t.p, dst, c->int2nat, c->s);  // API row order
       else HIPCHK(hipMemcpyAsync(dst, t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s));
@@ -2681,6 +2685,117 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   return ret;
 }
 
+// ------------------------------------------------------ mesh to mesh
+// Algorithm 1 (Sec. 3.2) between two meshes: this context's interior nodes
+// located in a P1 source mesh (bucket-grid nearest vertex, barycentric
+// walk), the orbitals interpolated with the barycentric weights.
+extern "C" int ks_interpolate(ks_ctx *c, const ks_mesh_desc *src, const double *psi_src, int32_t k,
+                              int32_t orthonormalize, double *psi) {
+  if (!c || !src || !psi_src || !psi || !src->coords_host || !src->elems_host || !src->dirichlet_host)
+    return fail(KS_ERR_ARG, "null argument");
+  if (src->order != 1) return fail(KS_ERR_ARG, "the source mesh must be P1");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (src->n_nodes < 4 || src->n_elems < 1) return fail(KS_ERR_ARG, "empty source mesh");
+  for (int64_t i = 0; i < (int64_t)src->n_elems * 4; ++i)
+    if (src->elems_host[i] < 0 || src->elems_host[i] >= src->n_nodes) return fail(KS_ERR_MESH, "source node id out of range");
+  hipStream_t s = c->s;
+  const int N = c->N;
+  // this mesh's interior node coordinates in storage order
+  std::vector<int32_t> n2i(c->n_nodes);
+  std::vector<double> xyz((size_t)c->n_nodes * 3);
+  HIPCHK(hipMemcpyAsync(n2i.data(), c->node2int, sizeof(int32_t) * c->n_nodes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(xyz.data(), c->coords, sizeof(double) * xyz.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<double> pts((size_t)N * 3);
+  for (int v = 0; v < c->n_nodes; ++v)
+    if (n2i[v] >= 0)
+      for (int d = 0; d < 3; ++d) pts[3 * (size_t)n2i[v] + d] = xyz[3 * (size_t)v + d];
+  // source unknowns: the non-Dirichlet nodes in ascending order
+  std::vector<int32_t> sint(src->n_nodes, -1);
+  int ns = 0;
+  for (int v = 0; v < src->n_nodes; ++v)
+    if (!src->dirichlet_host[v]) sint[v] = ns++;
+  std::vector<int32_t> vid((size_t)N * 4);
+  std::vector<double> wv((size_t)N * 4);
+  if (nonnested_weights(src->n_nodes, src->coords_host, src->n_elems, src->elems_host, N, pts.data(), vid.data(),
+                        wv.data()) < 0)
+    return fail(KS_ERR_MESH, "source mesh: bad element vertex ids");
+  std::vector<int32_t> idx((size_t)N * 4, -1);
+  std::vector<double> w((size_t)N * 4, 0.0);
+  for (size_t a = 0; a < idx.size(); ++a) {
+    const int u = sint[vid[a]];
+    if (u >= 0 && wv[a] != 0.0) {
+      idx[a] = u;
+      w[a] = wv[a];
+    }
+  }
+  int32_t *didx = nullptr;
+  double *dw = nullptr, *dg = nullptr;
+  const size_t kk = (size_t)k * k;
+  if (hipMalloc(&didx, sizeof(int32_t) * idx.size()) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  if (hipMalloc(&dw, sizeof(double) * (w.size() + 2 * kk)) != hipSuccess) {
+    (void)hipFree(didx);
+    return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  }
+  dg = dw + w.size();
+  int rc = KS_OK;
+  hipError_t e = hipMemcpyAsync(didx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dw, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_ellP_times(N, didx, dw, psi_src, k, k, 1.0, nullptr, 0, c->Xs, k, s);
+    double *out = c->Xs;
+    if (orthonormalize) {
+      // G = X^T M X = R^T R (Cholesky, in column order) and X <- X R^-1
+      spmm_cols(c, c->M, c->Xs, k, c->PsiNew, k, k);
+      launch_gemm_tn_sym(N, k, c->Xs, k, c->PsiNew, k, dg, k, c->gwork, s);
+      std::vector<double> G(kk), Ri(kk, 0.0);
+      e = hipMemcpyAsync(G.data(), dg, sizeof(double) * kk, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess) {
+        // in place: lower triangle of G becomes L with G = L L^T (R = L^T)
+        for (int j = 0; j < k && rc == KS_OK; ++j) {
+          double d = G[(size_t)j * k + j];
+          for (int p = 0; p < j; ++p) d -= G[(size_t)j * k + p] * G[(size_t)j * k + p];
+          if (!(d > 0.0)) {
+            rc = fail(KS_ERR_EIG, "interpolated orbitals are linearly dependent");
+            break;
+          }
+          const double ljj = std::sqrt(d);
+          G[(size_t)j * k + j] = ljj;
+          for (int i = j + 1; i < k; ++i) {
+            double t = G[(size_t)i * k + j];
+            for (int p = 0; p < j; ++p) t -= G[(size_t)i * k + p] * G[(size_t)j * k + p];
+            G[(size_t)i * k + j] = t / ljj;
+          }
+        }
+        // R^-1 = (L^T)^-1, upper triangular: columns by back substitution
+        for (int col = 0; col < k && rc == KS_OK; ++col)
+          for (int i = col; i >= 0; --i) {
+            double t = (i == col) ? 1.0 : 0.0;
+            for (int p = i + 1; p <= col; ++p) t -= G[(size_t)p * k + i] * Ri[(size_t)p * k + col];
+            Ri[(size_t)i * k + col] = t / G[(size_t)i * k + i];
+          }
+        if (rc == KS_OK) {
+          e = hipMemcpyAsync(dg + kk, Ri.data(), sizeof(double) * kk, hipMemcpyHostToDevice, s);
+          if (e == hipSuccess && launch_tsmm(N, k, c->Xs, k, dg + kk, k, c->PsiNew, k, s) < 0)
+            rc = fail(KS_ERR_ARG, "k too large for the orthonormalisation");
+          out = c->PsiNew;
+        }
+      }
+    }
+    if (e == hipSuccess && rc == KS_OK) {
+      launch_rows_to_api(N, k, out, psi, c->int2nat, s);
+      e = hipStreamSynchronize(s);
+    }
+  }
+  (void)hipFree(didx);
+  (void)hipFree(dw);
+  if (e != hipSuccess) return fail(KS_ERR_HIP, hipGetErrorString(e));
+  if (rc != KS_OK) return rc;
+  c->have_step = false;
+  return KS_OK;
+}
+
 // ------------------------------------------------------------ direct SCF
 // LOBPCG work space for up to k_max orbitals (allocated on first use)
 static int direct_alloc(ks_ctx *c) {
@@ -2715,24 +2830,51 @@ static int direct_alloc(ks_ctx *c) {
 // vectors, ascending theta); H X and M X in c->dHS, c->dMS.  Stops when
 // every column's ||H x - theta M x||_2 / ||M x||_2 <= tol or after max_it
 // iterations; *resmax receives the largest of those ratios.
+//
+// H X, M X and H P, M P are carried by the same linear combinations as X and
+// P.  When those combinations cancel (P nearly dependent on [X | W]) the
+// carried products drift from the true ones, so: they are recomputed every
+// LOBPCG_REFRESH iterations, before a stop is accepted, and when a
+// Rayleigh-Ritz step fails (a Gram matrix with a non-positive diagonal); if
+// the step still fails, P is dropped for that iteration.
+constexpr int LOBPCG_REFRESH = 16;
 static int lobpcg(ks_ctx *c, const double *H, int k, double tol, int max_it, std::vector<double> &theta,
                   int *iters, double *resmax) {
   const int N = c->N, L = 3 * k;
   hipStream_t s = c->s;
   double *S = c->dS, *HS = c->dHS, *MS = c->dMS;
-  spmm_cols(c, H, S, L, HS, L, k);
-  spmm_cols(c, c->M, S, L, MS, L, k);
-  const int maxb = std::min(512, (1024 * 32) / (2 * k));
-  std::vector<double> sums(2 * k);
-  int m = k;
-  *iters = 0;
-  for (int it = 0;; ++it) {
-    // Rayleigh-Ritz on the active columns [0, m)
+  auto refresh = [&](int ncols) {
+    spmm_cols(c, H, S, L, HS, L, ncols);
+    spmm_cols(c, c->M, S, L, MS, L, ncols);
+  };
+  auto rayleigh_ritz = [&](int m) {
     launch_gemm_tn_sym(N, m, S, L, HS, L, c->dGH, m, c->gwork, s);
     launch_gemm_tn_sym(N, m, S, L, MS, L, c->dGM, m, c->gwork, s);
-    TRY(orth_impl(c, c->dGM, m));
+    int r = orth_impl(c, c->dGM, m);
+    if (r < 0) return r;
     int rank = 0;
-    TRY(eig_impl(c, c->dGH, c->dGM, m, k, c->dC, theta, &rank));
+    return eig_impl(c, c->dGH, c->dGM, m, k, c->dC, theta, &rank);
+  };
+  refresh(k);
+  const int maxb = std::min(512, (1024 * 32) / (2 * k));
+  std::vector<double> sums(2 * k);
+  int m = k, since_refresh = 0;
+  *iters = 0;
+  for (int it = 0;; ++it) {
+    if (m > k && ++since_refresh >= LOBPCG_REFRESH) {
+      refresh(m);
+      since_refresh = 0;
+    }
+    // Rayleigh-Ritz on the active columns [0, m)
+    if (rayleigh_ritz(m) < 0) {
+      refresh(m);
+      since_refresh = 0;
+      if (rayleigh_ritz(m) < 0) {
+        if (m != 3 * k) return KS_ERR_EIG;
+        m = 2 * k;
+        TRY(rayleigh_ritz(m));
+      }
+    }
     // P <- [W | P] C[k:m];  X <- [X | W | P] C  (and the same for H S, M S)
     for (double *B : {S, HS, MS}) {
       if (m > k && launch_tsmm(N, m - k, B + k, L, c->dC + (size_t)k * k, k, c->dT1, k, s) < 0)
@@ -2745,11 +2887,17 @@ static int lobpcg(ks_ctx *c, const double *H, int k, double tol, int max_it, std
     const bool haveP = m > k;
     // residuals; the preconditioned ones become W (columns [k, 2k))
     HIPCHK(hipMemcpyAsync(c->dTheta, theta.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    const int nb = launch_lobpcg_resid(N, k, L, HS, MS, c->dTheta, c->dDinv, S + k, L, c->redpart, maxb, s);
-    if (nb < 0) return fail(KS_ERR_ARG, "k too large for the LOBPCG residual");
-    TRY(reduce_small(c, c->redpart, nb, 2 * k, sums.data()));
     double rmax = 0.0;
-    for (int j = 0; j < k; ++j) rmax = std::max(rmax, std::sqrt(sums[j] / std::max(sums[k + j], 1e-300)));
+    for (int pass = 0; pass < 2; ++pass) {
+      const int nb = launch_lobpcg_resid(N, k, L, HS, MS, c->dTheta, c->dDinv, S + k, L, c->redpart, maxb, s);
+      if (nb < 0) return fail(KS_ERR_ARG, "k too large for the LOBPCG residual");
+      TRY(reduce_small(c, c->redpart, nb, 2 * k, sums.data()));
+      rmax = 0.0;
+      for (int j = 0; j < k; ++j) rmax = std::max(rmax, std::sqrt(sums[j] / std::max(sums[k + j], 1e-300)));
+      // a stop is accepted on residuals from freshly computed H X and M X
+      if (rmax > tol || it >= max_it || !haveP) break;
+      refresh(k);
+    }
     *resmax = rmax;
     *iters = it;
     if (rmax <= tol || it >= max_it) break;
