@@ -176,6 +176,29 @@ def copy_probe(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def stream_probes(nbytes=1 << 32, reps=10):
+    """Hand-written HBM streaming probes (ks_stream_probe, nontemporal
+    16-byte vector streams): read, copy and triad bandwidth, and the write
+    bandwidth implied by read and copy (a copy moves one read and one write
+    stream: 2 / copy = 1 / read + 1 / write)."""
+    from paper_2404_19249_amd import stream_probe
+    out = {kind: stream_probe(kind, nbytes, nontemporal=True, reps=reps) for kind in ("read", "copy", "triad")}
+    inv_w = 2.0 / out["copy"] - 1.0 / out["read"]
+    out["write_implied"] = 1.0 / inv_w if inv_w > 0 else None
+    out["buffer_bytes"] = nbytes
+    return out
+
+
+def mix_ceiling(probes, read_bytes, write_bytes):
+    """Streaming ceiling (GB/s) for a kernel that reads read_bytes and writes
+    write_bytes: the time of those streams at the probes' read and implied
+    write bandwidth."""
+    if not probes.get("write_implied"):
+        return probes["copy"]
+    t = read_bytes / probes["read"] + write_bytes / probes["write_implied"]
+    return (read_bytes + write_bytes) / t
+
+
 def cpu_info():
     """CPU model and logical CPU count of this host."""
     model = "unknown"
@@ -558,7 +581,8 @@ def main():
     occ = w.occ
     psi0, lam0 = ctx.initial_guess(k)
     copy_gbs = copy_probe(torch)
-    log(f"[bench] device copy probe: {copy_gbs:.0f} GB/s")
+    probes = stream_probes()
+    log(f"[bench] device copy probe (torch): {copy_gbs:.0f} GB/s; streaming probes: {json.dumps(probes)}")
     ctx.assemble(psi0, occ, want_fields=False)
     tune = None if args.no_autotune else ctx.autotune(k, reps=10)
     log(f"[bench] autotune: {json.dumps(tune)}")
@@ -639,8 +663,11 @@ def main():
             "traffic": None if traffic is None else traffic / 1e9,
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
             "bytes_per_launch": bytes_a, "ms_per_launch": ms_a, "spmm_config": cfg,
-            # against the copy probe of the same run, and algorithmic / measured bytes
-            "frac_probe": ach / copy_gbs,
+            # against the streaming ceiling for this kernel's read/write mix (hand-written
+            # probes of the same run), against torch's copy, and algorithmic / measured bytes
+            "probe_ceiling_GBs": mix_ceiling(probes, bytes_a - N * k * sv, N * k * sv),
+            "frac_probe": ach / mix_ceiling(probes, bytes_a - N * k * sv, N * k * sv),
+            "frac_torch_copy": ach / copy_gbs,
             "algorithmic_over_traffic": None if not traffic else bytes_a / traffic}
     it_bytes = cg_iteration_bytes(N, nnz, k, sv)
     it_gbs = it_bytes / ((ms_a + ms_b + ms_c) * 1e-3) / 1e9
@@ -670,6 +697,7 @@ def main():
                                    "Ritz guess)"},
         "roofline": roof,
         "copy_probe_GBs": copy_gbs,
+        "stream_probes_GBs": probes,
         "autotune": tune,
         "pcg_phases": phases,
         "phases": phases_other,

@@ -384,6 +384,17 @@ int ks_batch_destroy(ks_batch *b);
  * or ks_augmented_project). */
 int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *ms_host);
 
+/* HBM streaming probe: the bandwidth of plain coalesced streams (16-byte
+ * vectors, 4 in flight per thread, grid of 16 workgroups per CU) over
+ * buffers of `bytes` bytes each, as the practical ceiling next to the
+ * nominal 8 TB/s for the memory-bound kernels.  kind 0: read one buffer
+ * (per-workgroup sums), 1: copy, 2: triad c = a + s b; nontemporal != 0
+ * uses nontemporal loads and stores.  *gbs_host = (streams x bytes x reps) /
+ * time, timed with HIP events on `stream` after one warm-up pass.  The
+ * buffers are allocated and freed by the call (1 MiB <= bytes <= 64 GiB). */
+int ks_stream_probe(int64_t bytes, int32_t kind, int32_t nontemporal, int32_t reps, double *gbs_host,
+                    hipStream_t stream);
+
 /* Autotuner of the SpMM phase: on the current operator S (and the Poisson
  * operator K), times the SpMM phase of the block PCG for every kernel
  * candidate -- the row kernel with a row's nonzeros split over NG = 1, 2, 4,
@@ -394,8 +405,11 @@ int ks_time_kernel(ks_ctx *ctx, int32_t which, int32_t k, int32_t reps, double *
  * {NG fp64, NG fp32, NG Poisson, tile rows fp64, fp32, Poisson (0 = row
  * kernel chosen), tile threads fp64, fp32, Poisson, then row-kernel
  * ms[fp64|fp32|Poisson][NG], then tile-kernel ms[fp64|fp32|Poisson][rows]
- * [256|512|1024 threads] (-1: not available for this shape)}.  Requires a
- * prior ks_assemble. */
+ * [256|512|1024 threads] (-1: not available for this shape, -2: rejected,
+ * and row-kernel entries -2: rejected)}.  Every
+ * candidate's q = S p on a fixed p is compared with the first row kernel's;
+ * one that differs by more than 1e-12 (FP64) or 1e-5 (FP32) of max|q| is
+ * rejected.  Requires a prior ks_assemble. */
 int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 
 /* SpMM-phase kernels in use: out_host[0..8] = {NG fp64, NG fp32, NG Poisson

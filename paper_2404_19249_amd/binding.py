@@ -123,6 +123,7 @@ _SIGS = {
     "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),
+    "ks_stream_probe": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P]),
     "ks_interpolate": (C.c_int, [_P, C.POINTER(MeshDesc), _P, C.c_int32, C.c_int32, _P]),
     "ks_direct_scf": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                 C.c_double, C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(DirectReport)]),

@@ -408,3 +408,15 @@ class KSBatch:
         return outs, {"status": code, "seconds": st.seconds,
                       "system_seconds": list(st.system_seconds[:n]), "iters": list(st.iters[:n]),
                       "relres": list(st.relres[:n]), "sys_status": list(st.status[:n])}
+
+
+def stream_probe(kind="copy", nbytes=1 << 30, nontemporal=False, reps=10, stream=None):
+    """ks_stream_probe: GB/s of a plain coalesced stream over nbytes-byte
+    buffers (kind "read", "copy" or "triad"; read + write bytes counted)."""
+    import torch
+    lib = B.load_library()
+    st = stream or torch.cuda.current_stream()
+    out = C.c_double(0.0)
+    B.check(lib.ks_stream_probe(int(nbytes), {"read": 0, "copy": 1, "triad": 2}[kind], int(bool(nontemporal)),
+                                int(reps), C.byref(out), C.c_void_p(st.cuda_stream)), lib)
+    return out.value

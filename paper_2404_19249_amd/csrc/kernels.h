@@ -196,6 +196,11 @@ int launch_refine_prep(int N, int k, const double *W, const double *sc, const fl
 int launch_residual_tiled_norms(int N, int k, const Tiling &t, int tb, const int32_t *rowptr, const double *val,
                                 const double *X, double *Y, const double *B, double *part, hipStream_t s);
 size_t pcg_state_bytes(int k);
+// autotuner check of the SpMM phase on the work buffers of w: mode 0 fills
+// p with a fixed pattern, 1 copies q to ref ([N][k] of T), 2 returns
+// max|q - ref| / max|ref| in *dev_host (NaN in q: infinite)
+template <typename T>
+int pcg_phase_check(PCGWork &w, int N, int k, int mode, void *ref, double *dev_host, hipStream_t s);
 template <typename T>
 int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t *col, const T *val,
                    const int32_t *ord, const T *diag, T *X, PCGWork &w, int reps, float *ms,

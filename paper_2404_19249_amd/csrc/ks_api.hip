@@ -420,14 +420,15 @@ static int tile_index(int br) {
     if (TILE_BR[i] == br) return i;
   return -1;
 }
-// tile choice code: 3 * tiling index + workgroup size index (256, 512,
+// tile choice code: NTB * tiling index + workgroup size index (256, 512,
 // 1024 threads), -1 = row kernel
-static const int TILE_TB[3] = {256, 512, 1024};
+constexpr int NTB = 3;
+static const int TILE_TB[NTB] = {256, 512, 1024};
 static void apply_tiles(ks_ctx *c) {
   auto set = [&](PCGWork &w, int code) {
-    const int i = code >= 0 ? code / 3 : -1;
+    const int i = code >= 0 ? code / NTB : -1;
     w.til = (i >= 0 && c->til[i].nblk) ? &c->til[i] : nullptr;
-    w.til_tb = TILE_TB[code >= 0 ? code % 3 : 0];
+    w.til_tb = TILE_TB[code >= 0 ? code % NTB : 0];
   };
   set(c->pw64, c->tile64);
   set(c->pw32, c->tile32);
@@ -1211,7 +1212,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     // threads (Poisson, one column)
     auto tile_of = [&](int rows, int tb) {
       const int i = tile_index(rows);
-      return i >= 0 ? 3 * i + (tb == 1024 ? 2 : (tb == 512 ? 1 : 0)) : -1;
+      return i >= 0 ? NTB * i + (tb == 1024 ? 2 : (tb == 512 ? 1 : 0)) : -1;
     };
     c->tile64 = tile_of(85, 1024);
     c->tile32 = tile_of(85, 512);
@@ -1477,7 +1478,7 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
   if (k < 1 || k > c->k_max || reps < 1) return fail(KS_ERR_ARG, "bad k or reps");
   if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
   const int ngs[4] = {1, 2, 4, 8};
-  double t_row[3][4], t_til[3][3 * ks_ctx::NTILE];
+  double t_row[3][4], t_til[3][NTB * ks_ctx::NTILE];
   int best_ng[3] = {1, 1, 8}, best_tile[3] = {-1, -1, -1};
   PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
   c->rorder = nullptr;
@@ -1488,12 +1489,37 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
     const Tiling *keep = ws[w]->til;
     const int keep_db = ws[w]->til_tb;
     ws[w]->til = nullptr;
+    // every candidate's q = S p on a fixed p is compared with the first row
+    // kernel's; one that differs by more than rounding is never chosen
+    const bool f32 = w == 1;
+    if (which >= 3) ensure_s32(c);
+    const double dev_tol = f32 ? 1e-5 : 1e-12;
+    void *ref = nullptr;
+    if (hipMalloc(&ref, (f32 ? sizeof(float) : sizeof(double)) * (size_t)c->N * kk) != hipSuccess)
+      return fail(KS_ERR_NOMEM, "autotune: hipMalloc failed");
+    auto check = [&](int mode, double *dev) {
+      return f32 ? pcg_phase_check<float>(*ws[w], c->N, kk, mode, ref, dev, c->s)
+                 : pcg_phase_check<double>(*ws[w], c->N, kk, mode, ref, dev, c->s);
+    };
+    auto restore = [&]() {
+      ws[w]->til = keep;
+      ws[w]->til_tb = keep_db;
+      (void)hipFree(ref);
+    };
+    double dev = 0.0;
+    if (check(0, &dev) < 0) {
+      restore();
+      return fail(KS_ERR_HIP, "autotune check failed");
+    }
     for (int i = 0; i < 4; ++i) {
       float ms = 0.f;
-      if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0) {
-        ws[w]->til = keep;
-        ws[w]->til_tb = keep_db;
+      if (time_phase(c, which, kk, reps, ngs[i], &ms) < 0 || check(i == 0 ? 1 : 2, &dev) < 0) {
+        restore();
         return fail(KS_ERR_HIP, "autotune timing failed");
+      }
+      if (i > 0 && !(dev <= dev_tol)) {
+        t_row[w][i] = -2.0;  // wrong result: never chosen
+        continue;
       }
       t_row[w][i] = ms;
       if (ms < bt) {
@@ -1502,19 +1528,22 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
         best_tile[w] = -1;
       }
     }
-    for (int code = 0; code < 3 * ks_ctx::NTILE; ++code) {
-      const int i = code / 3;
+    for (int code = 0; code < NTB * ks_ctx::NTILE; ++code) {
+      const int i = code / NTB;
       t_til[w][code] = -1.0;
       if (!c->til[i].nblk) continue;
       ws[w]->til = &c->til[i];
-      ws[w]->til_tb = TILE_TB[code % 3];
+      ws[w]->til_tb = TILE_TB[code % NTB];
       float ms = 0.f;
       const int r = time_phase(c, which, kk, reps, 0, &ms);
       if (r == -3) continue;  // does not fit in LDS for this shape
-      if (r < 0) {
-        ws[w]->til = keep;
-        ws[w]->til_tb = keep_db;
+      if (r < 0 || check(2, &dev) < 0) {
+        restore();
         return fail(KS_ERR_HIP, "autotune timing failed");
+      }
+      if (!(dev <= dev_tol)) {
+        t_til[w][code] = -2.0;  // wrong result: never chosen
+        continue;
       }
       t_til[w][code] = ms;
       if (ms < bt) {
@@ -1522,8 +1551,7 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
         best_tile[w] = code;
       }
     }
-    ws[w]->til = keep;
-    ws[w]->til_tb = keep_db;
+    restore();
     // keep the configuration in use unless another is more than 3% faster:
     // closer timings are within the run-to-run noise
     const int cur = w == 0 ? c->tile64 : (w == 1 ? c->tile32 : c->tileP);
@@ -1539,10 +1567,10 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
   if (report_host) {
     for (int w = 0; w < 3; ++w) {
       report_host[w] = best_ng[w];
-      report_host[3 + w] = best_tile[w] >= 0 ? TILE_BR[best_tile[w] / 3] : 0;
-      report_host[6 + w] = best_tile[w] >= 0 ? TILE_TB[best_tile[w] % 3] : 0;
+      report_host[3 + w] = best_tile[w] >= 0 ? TILE_BR[best_tile[w] / NTB] : 0;
+      report_host[6 + w] = best_tile[w] >= 0 ? TILE_TB[best_tile[w] % NTB] : 0;
       for (int i = 0; i < 4; ++i) report_host[9 + w * 4 + i] = t_row[w][i];
-      for (int i = 0; i < 3 * ks_ctx::NTILE; ++i) report_host[21 + w * 3 * ks_ctx::NTILE + i] = t_til[w][i];
+      for (int i = 0; i < NTB * ks_ctx::NTILE; ++i) report_host[21 + w * NTB * ks_ctx::NTILE + i] = t_til[w][i];
     }
   }
   return KS_OK;

@@ -526,8 +526,7 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
     }
     const T *xs = reinterpret_cast<const T *>(t_smem + L.halo) + cg * VW;
     const unsigned char *xsb = t_smem + L.halo + cg * VW * sizeof(T);
-    for (int rs = rslot; active && rs < nr; rs += RPP) {
-      const uint2 m = rs == rslot ? m0 : rm2[r0 + rs];
+    auto do_row = [&](const uint2 m) {
       const int rr = (int)(m.x >> 24);  // longest rows first
       const int row = r0 + rr;
       const int jb = (int)(m.x & 0xffffu), len = (int)((m.x >> 16) & 0xffu);
@@ -535,35 +534,41 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
       T acc[VW];
       for (int v = 0; v < VW; ++v) acc[v] = T(0);
       // eight nonzeros per step: one aligned 16-byte read of their local
-      // indices; a tail of at most four takes one four-wide step (8-byte
-      // index read).  Slots past the row's end point at the zero halo row;
-      // their weights (the following entries of the LDS value image, finite)
-      // then add exact zeros.
-      auto step = [&](auto nu, int j) {
+      // indices, issued one step ahead so that it overlaps the previous
+      // step's gathers; a tail of at most four takes one four-wide step.
+      // Slots past the row's end point at the zero halo row; their weights
+      // (the following entries of the LDS value image, finite) then add
+      // exact zeros.  The run is padded to a multiple of eight entries, so
+      // the read ahead stays inside it.
+      auto step = [&](auto nu, const uint4 iw, int j) {
         constexpr int NU = decltype(nu)::value;
-        unsigned li[NU];
-        if constexpr (NU == 8) {
-          const uint4 iw = *reinterpret_cast<const uint4 *>(ir + j);
-          li[0] = iw.x & 0xffffu; li[1] = iw.x >> 16; li[2] = iw.y & 0xffffu; li[3] = iw.y >> 16;
-          li[4] = iw.z & 0xffffu; li[5] = iw.z >> 16; li[6] = iw.w & 0xffffu; li[7] = iw.w >> 16;
-        } else {
-          const uint2 iw = *reinterpret_cast<const uint2 *>(ir + j);
-          li[0] = iw.x & 0xffffu; li[1] = iw.x >> 16; li[2] = iw.y & 0xffffu; li[3] = iw.y >> 16;
-        }
+        unsigned li[8];
+        li[0] = iw.x & 0xffffu; li[1] = iw.x >> 16; li[2] = iw.y & 0xffffu; li[3] = iw.y >> 16;
+        li[4] = iw.z & 0xffffu; li[5] = iw.z >> 16; li[6] = iw.w & 0xffffu; li[7] = iw.w >> 16;
         T vv[NU];
+        VecT<T, VW> x[NU];
 #pragma unroll
         for (int u = 0; u < NU; ++u) vv[u] = vs[jb + j + u];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const VecT<T, VW> x = SC ? *reinterpret_cast<const VecT<T, VW> *>(xsb + li[u])
-                                   : *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], (unsigned)k));
-          for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x.v[v];
-        }
+        for (int u = 0; u < NU; ++u)
+          x[u] = SC ? *reinterpret_cast<const VecT<T, VW> *>(xsb + li[u])
+                    : *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(li[u], (unsigned)k));
+        // all of the step's LDS reads are issued before the first product
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+          for (int v = 0; v < VW; ++v) acc[v] += vv[u] * x[u].v[v];
       };
+      uint4 iw = make_uint4(0u, 0u, 0u, 0u);
+      if (len > 0) iw = *reinterpret_cast<const uint4 *>(ir);
       int j = 0;
-      for (; j + 8 <= len; j += 8) step(std::integral_constant<int, 8>{}, j);
-      if (len - j > 4) step(std::integral_constant<int, 8>{}, j);
-      else if (len - j > 0) step(std::integral_constant<int, 4>{}, j);
+      for (; j + 8 <= len; j += 8) {
+        const uint4 cur = iw;
+        if (j + 8 < len) iw = *reinterpret_cast<const uint4 *>(ir + j + 8);
+        step(std::integral_constant<int, 8>{}, cur, j);
+      }
+      if (len - j > 4) step(std::integral_constant<int, 8>{}, iw, j);
+      else if (len - j > 0) step(std::integral_constant<int, 4>{}, iw, j);
       if constexpr (MODE == 0) {
         const VecT<T, VW> p = *reinterpret_cast<const VecT<T, VW> *>(xs + __umul24(hs + rr, k));
         for (int v = 0; v < VW; ++v) apq[v] += (double)p.v[v] * (double)acc[v];
@@ -574,7 +579,12 @@ __global__ void __launch_bounds__(TB) k_tpcg_A(int N, int k, int ldp, int ldq, i
         for (int v = 0; v < VW; ++v) apq[v] += (double)acc[v] * (double)acc[v];
       }
       store_row<T, VW>(Q, row, ldq, cg * VW, k, acc);
-    }
+    };
+    // the first row of every lane comes with the block (no memory wait
+    // here: the next block's halo rows stay in flight during the compute);
+    // blocks taller than one pass load the later row slots
+    if (active && rslot < nr) do_row(m0);
+    for (int rs = rslot + RPP; active && rs < nr; rs += RPP) do_row(rm2[r0 + rs]);
   }
   if (MODE == 1 || part == nullptr) return;
   // per-workgroup column partials (fixed order): thread t holds columns
@@ -1347,6 +1357,66 @@ int pcg_time_phase(int N, int k, int phase, const int32_t *rowptr, const int32_t
   ng = fit_ng(k, vw, ng);
   KS_PCG_DISPATCH(time_phase_t, N, k, phase, rowptr, col, val, ord, diag, X, w, reps, ms, s)
 }
+// Autotuner check of the SpMM phase: a fixed input block p, the output of
+// the reference kernel kept, and every candidate's output compared with it.
+template <typename T>
+__global__ void k_fill_pattern(int64_t n, T *__restrict__ p) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (T)(1.0 + 0.5 * sin(0.37 * (double)(i % 100003)));
+}
+template <typename T>
+__global__ void k_max_dev(int64_t n, const T *__restrict__ q, const T *__restrict__ ref, double *out) {
+  __shared__ double sd[256], sr[256];
+  double d = 0.0, r = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = (double)q[i], b = (double)ref[i];
+    d = fmax(d, (a == a) ? fabs(a - b) : INFINITY);  // NaN counts as a mismatch
+    r = fmax(r, fabs(b));
+  }
+  sd[threadIdx.x] = d;
+  sr[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + o]);
+      sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = sd[0];
+    out[2 * blockIdx.x + 1] = sr[0];
+  }
+}
+template <typename T>
+int pcg_phase_check(PCGWork &w, int N, int k, int mode, void *ref, double *dev_host, hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  if (mode == 0) {
+    hipLaunchKernelGGL(k_fill_pattern<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       reinterpret_cast<T *>(w.P));
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  }
+  if (mode == 1)
+    return hipMemcpyAsync(ref, w.Q, sizeof(T) * n, hipMemcpyDeviceToDevice, s) == hipSuccess ? 0 : -2;
+  double *part = reinterpret_cast<double *>(w.part);  // at least 2 x 1024 doubles
+  hipLaunchKernelGGL(k_max_dev<T>, dim3(g), dim3(256), 0, s, n, reinterpret_cast<const T *>(w.Q),
+                     reinterpret_cast<const T *>(ref), part);
+  std::vector<double> h(2 * g);
+  if (hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * g, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -2;
+  double d = 0.0, r = 0.0;
+  for (unsigned b = 0; b < g; ++b) {
+    d = std::max(d, h[2 * b]);
+    r = std::max(r, h[2 * b + 1]);
+  }
+  *dev_host = r > 0.0 ? d / r : d;
+  return 0;
+}
+template int pcg_phase_check<double>(PCGWork &, int, int, int, void *, double *, hipStream_t);
+template int pcg_phase_check<float>(PCGWork &, int, int, int, void *, double *, hipStream_t);
+
 template int pcg_time_phase<double>(int, int, int, const int32_t *, const int32_t *, const double *,
                                     const int32_t *, const double *, double *, PCGWork &, int, float *,
                                     hipStream_t, int);

@@ -120,3 +120,42 @@ def test_fp32_operator_copy_is_the_rounded_operator():
     S = ctx.debug_buffer("S", ctx.nnz)
     S32 = ctx.debug_buffer("S32", half).view(torch.float32)[:ctx.nnz]
     assert torch.equal(S32, S.float())
+
+
+def test_stream_probe_reports_a_bandwidth_below_the_peak():
+    """ks_stream_probe: a plain stream cannot exceed the 8 TB/s HBM peak
+    (the buffers, 256 MiB each, are far larger than the caches), and bad
+    arguments are refused."""
+    from paper_2404_19249_amd import stream_probe, KSError
+    for kind in ("read", "copy", "triad"):
+        g = stream_probe(kind, 1 << 28, nontemporal=True, reps=3)
+        assert 500.0 < g < 8000.0, (kind, g)
+    with pytest.raises(KSError):
+        stream_probe("read", 1024)
+
+
+@pytest.mark.parametrize("k", [8, 24])
+def test_autotuned_kernels_agree_and_solve(k):
+    """ks_autotune checks every SpMM-phase candidate (row kernels, halo
+    tiles) against the first row kernel on a fixed block and never keeps one
+    that disagrees: on a mesh where the tile forms are available none is
+    rejected, and block solves with the chosen kernels reach the tolerance,
+    residuals recomputed on the host."""
+    w = make_workload("mixed", n=12, order=2, k=k)      # N = 12,167, two tile passes and more
+    ctx = _ctx(w, k_max=k, tol_solve=1e-10)
+    psi, lam = ctx.initial_guess(k)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    rep = ctx.autotune(k, reps=2)
+    print(rep)
+    for n in ("fp64", "fp32", "poisson"):
+        assert all(v != -2.0 for v in rep[f"row_ms_{n}"].values())
+        assert all(v != -2.0 for v in rep[f"tile_ms_{n}"].values())
+    assert rep["tile_ms_fp32"]["85x512"] > 0.0
+    S = _csr(ctx, 0)
+    rng = np.random.default_rng(7)
+    Bh = rng.standard_normal((ctx.N, k))
+    for prec in ("fp64", "mixed"):
+        X, st = ctx.block_solve_rhs(torch.tensor(Bh, device=DEV), precision=prec)
+        rel = np.linalg.norm(Bh - S @ X.cpu().numpy(), axis=0) / np.linalg.norm(Bh, axis=0)
+        assert st["converged"] and rel.max() <= 1e-10 * 1.0001, (prec, rel.max())
+    ctx.close()
