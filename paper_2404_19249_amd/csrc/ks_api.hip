@@ -2621,8 +2621,12 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
     if (nonlinear) {
       if (hartree) {
         // the inner fixed point cannot settle below the error the inexact
-        // Poisson solves leave in V_H: tie their tolerance to tol_inner
-        int r = hartree_solve(c, c->rho_in, &piters, std::min(c->opt.tol_poisson, 1e-4 * c->opt.tol_inner));
+        // Poisson solves leave in V_H: their tolerance follows the inner
+        // residual (1e-4 of the last one, between 1e-4 tol_inner and
+        // tol_poisson), so the last iterations solve to 1e-4 tol_inner
+        const double tol_p =
+            std::max(1e-4 * c->opt.tol_inner, std::min(c->opt.tol_poisson, it > 0 ? 1e-4 * res : INFINITY));
+        int r = hartree_solve(c, c->rho_in, &piters, std::min(c->opt.tol_poisson, tol_p));
         if (r < 0) return r;
       } else {
         launch_fill(nqt, 0.0, c->vh_q, s);
