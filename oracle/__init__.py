@@ -17,7 +17,9 @@ Parity status: every function is pinned by a CPU test (quadrature exactness,
 closed-form element matrices, global invariants, the hydrogen closed form,
 Gaussian Poisson and multipole closed forms, XC derivative identities,
 brute-force dense eigensolves on tiny meshes, the nested-mesh identity,
-Anderson's least-squares property and finite differences for the adjoint),
+Anderson's least-squares property and finite differences for the adjoint;
+the Hessian metric and node mover by exact recovery of linear and quadratic
+functions, the eigenvalue clamp, fixed points and energy descent),
 except the nonlinear inner SCF's physical value, which is pinned only through
 self-consistency properties ("parity unpinned" for its absolute energy).
 """
