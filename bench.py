@@ -414,6 +414,81 @@ def compare_leg(np, molecules=("lih", "ch4", "c6h6"), k_asm=4, tol=2e-4, max_ste
     return out
 
 
+def adaptive_leg(np, name="lih", sizes=(12, 16, 20, 24, 28, 34), eps=1e-3, h_min=0.25, h_max=2.0, omega=0.8,
+                 sweeps=20, tol=1e-6):
+    """Algorithm 2's mesh moving (Sec. 3.2) against fixed meshes of the same
+    size: on every level, the direct SCF (to a density change below tol) on
+    (a) the uniform Kuhn mesh of the box, (b) the mesh moved toward the
+    nuclei by the fixed map of the workloads, (c) the r-adapted mesh: the
+    previous level's displacement (moved minus uniform node positions) is
+    carried to the new uniform lattice (ks_interpolate_field over the
+    previous uniform lattice; the uniform lattice itself if that would
+    invert an element), then moved by `sweeps` spring sweeps under the metric
+    of sqrt(rho) of the previous level's solution (ks_mesh_metric on its own
+    mesh, carried to the new nodes by ks_interpolate_field, ks_move_nodes);
+    its orbitals carried over by Algorithm 1.  With the same number of
+    unknowns, a lower E_total is the better mesh (the discrete problem is a
+    Ritz-Galerkin approximation).  Level 1 of (c) is the uniform mesh."""
+    import dataclasses
+    import torch
+    from ks_inputs import make_workload
+    from ks_inputs.mesh import freudenthal_mesh
+    from paper_2404_19249_amd import KSContext, mesh_metric, move_nodes, interpolate_field
+    rows, prev, prev_lat, prev_disp = [], None, None, None
+
+    def min_det(x, el):
+        X = x[el[:, :4]]
+        J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+        return float(np.linalg.det(J).min())
+
+    for lev, n in enumerate(sizes):
+        w = make_workload(name, n=n)
+        lattice = freudenthal_mesh(n, w.mesh.L, 1)
+        row = {"level": lev + 1, "n": n, "elements": int(lattice.n_elems)}
+        meshes = {"uniform": lattice, "moved_to_nuclei": w.mesh}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if prev is None:
+            meshes["metric_moved"] = lattice
+        else:
+            pm, ppsi, _ = prev
+            start = lattice.coords
+            d = interpolate_field(prev_lat, torch.tensor(prev_disp, device="cuda"), lattice.coords).cpu().numpy()
+            if min_det(lattice.coords + d, lattice.elems) > 0.0:
+                start = lattice.coords + d
+            row["carried_displacement"] = start is not lattice.coords
+            M = mesh_metric(pm, ppsi, w.occ, eps, h_min, h_max)
+            Mn = interpolate_field(pm, M, start)
+            xs, hv = move_nodes(dataclasses.replace(lattice, coords=start), Mn, omega=omega, sweeps=sweeps)
+            meshes["metric_moved"] = dataclasses.replace(lattice, coords=xs, moved=True)
+            row["move_halvings"] = hv
+        torch.cuda.synchronize()
+        row["metric_and_move_s"] = time.perf_counter() - t0
+        for key, mesh in meshes.items():
+            wk = dataclasses.replace(w, mesh=mesh)
+            ctx = KSContext.from_workload(wk, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if key == "metric_moved" and prev is not None:
+                psi = ctx.interpolate(prev[0], prev[1], orthonormalize=True)
+                lam = prev[2].copy()
+            else:
+                psi, lam = ctx.initial_guess(w.k)
+            lam, rep = ctx.direct_scf(psi, lam, w.occ, tol=tol, max_scf=300, tol_eig=1e-8, max_eig=4000)
+            torch.cuda.synchronize()
+            row[key] = {"E_total": rep["E_total"], "lambda_1": float(lam[0]), "scf_iters": rep["scf_iters"],
+                        "converged": bool(rep["converged"]), "seconds": time.perf_counter() - t0}
+            if key == "metric_moved":
+                prev = (mesh, psi, lam)
+            ctx.close()
+        prev_lat, prev_disp = lattice, meshes["metric_moved"].coords - lattice.coords
+        log(f"[bench] adaptive {name} h_min={h_min} sweeps={sweeps} n={n}: " + ", ".join(
+            f"{key} {row[key]['E_total']:.5f}" for key in meshes) + f"; halvings {row.get('move_halvings', 0)}")
+        rows.append(row)
+    return {"molecule": name, "eps": eps, "h_min": h_min, "h_max": h_max, "omega": omega, "sweeps": sweeps,
+            "tol": tol, "levels": rows}
+
+
 def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
     """The differentiation workload: 20 nuclei, 96^3 hexes -> P1 tetrahedra
     (N = 857,375), N_occ = 40.  One step forward (with E_KS) and its adjoint
@@ -553,9 +628,10 @@ def main():
     ap.add_argument("--scf-run", action="store_true",
                     help="also run Algorithm 3 to convergence (density change < 2e-4) from the "
                          "coarse initial guess on the bench workload")
-    ap.add_argument("--mode", default="step", choices=["step", "solve", "compare"],
+    ap.add_argument("--mode", default="step", choices=["step", "solve", "compare", "adaptive"],
                     help="solve: skip the SCF steps (block solves and kernel timings only, "
-                         "for profiling); compare: only the mesh-sequence comparison")
+                         "for profiling); compare: only the mesh-sequence comparison; adaptive: "
+                         "only the metric-moved mesh sequence against fixed meshes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sharded "
@@ -569,6 +645,12 @@ def main():
 
     if args.mode == "compare":
         print(json.dumps({"compare": compare_leg(np)}), flush=True)
+        return
+    if args.mode == "adaptive":
+        runs = []
+        for name in ("lih", "ch4"):
+            runs.append(adaptive_leg(np, name))
+        print(json.dumps({"adaptive": runs}), flush=True)
         return
     t_setup = time.perf_counter()
     w = make_workload(args.workload, n=args.n)

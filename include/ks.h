@@ -275,6 +275,52 @@ int ks_scf_run(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const d
 int ks_interpolate(ks_ctx *ctx, const ks_mesh_desc *src, const double *psi_src, int32_t k, int32_t orthonormalize,
                    double *psi);
 
+/* ---- Mesh moving for Algorithm 2 (Sec. 3.2) --------------------------
+ * Three mesh-level calls (no context): the Hessian metric of the adaptive
+ * function sqrt(rho) (eqs. m1, m2), a metric spring node mover standing in
+ * for the remesher (Mshmet/Mmg3d in the paper), and P1 field interpolation
+ * between meshes (Algorithm 1).  Meshes are P1 (order 1; KS_ERR_ARG
+ * otherwise), given by host arrays as for ks_create; every call copies what
+ * it needs to the device, allocates its work buffers and frees them before
+ * returning, and is synchronous on `stream`. */
+typedef struct {
+  double eps;    /* epsilon of eq. m2 (L-infinity interpolation error target) */
+  double h_min;  /* shortest edge scale: eigenvalues capped at 1 / h_min^2 */
+  double h_max;  /* longest edge scale: eigenvalues raised to 1 / h_max^2 */
+} ks_metric_params;
+
+/* Eqs. m1-m2 at every node: u = sqrt(sum_i f_i psi_i^2) (zero on Dirichlet
+ * nodes); its gradient recovered as the volume-weighted average of the
+ * element gradients of its P1 interpolant around each node (the
+ * lumped-mass L2 projection), the same recovery applied to each component
+ * of that gradient, H the symmetric part; H = R Lambda R^T (Jacobi
+ * rotations), lambda~_i = min(max(C_d |lambda_i| / eps, 1 / h_max^2),
+ * 1 / h_min^2), C_d = 9/32, M = R Lambda~ R^T.  psi: device [N][k] over the
+ * non-Dirichlet nodes in ascending order (a context's orbital layout on
+ * this mesh); occ_host [k]; metric: device [n_nodes][6] = (xx, yy, zz, xy,
+ * xz, yz) of M, output. */
+int ks_mesh_metric(const ks_mesh_desc *mesh, const double *psi, int32_t k, const double *occ_host,
+                   const ks_metric_params *prm, double *metric, hipStream_t stream);
+
+/* Node mover: `sweeps` damped Jacobi sweeps on the spring energy
+ * sum over edges (a, b) of (x_b - x_a)^T (M_a + M_b)/2 (x_b - x_a) with the
+ * metric carried by the nodes: every non-Dirichlet node moves to
+ * (1 - w) x_a + w t_a, t_a the minimiser over x_a with the other nodes
+ * fixed; Dirichlet nodes stay.  A sweep that would leave an element with
+ * det J <= 0 is redone with w halved (at most 20 times; then KS_ERR_MESH).
+ * metric: device [n_nodes][6] as from ks_mesh_metric; 0 < omega < 2;
+ * coords_out_host [n_nodes][3] receives the moved nodes; halvings_host
+ * (may be NULL) the number of halvings over all sweeps. */
+int ks_move_nodes(const ks_mesh_desc *mesh, const double *metric, double omega, int32_t sweeps,
+                  double *coords_out_host, int32_t *halvings_host, hipStream_t stream);
+
+/* Algorithm 1 for a nodal field: the P1 interpolant on src of field
+ * (device [src n_nodes][m], every node including Dirichlet ones) evaluated
+ * at n_pts points (pts_host [n_pts][3]; located on the host as in
+ * ks_interpolate); out: device [n_pts][m]. */
+int ks_interpolate_field(const ks_mesh_desc *src, const double *field, int32_t m, int32_t n_pts,
+                         const double *pts_host, double *out, hipStream_t stream);
+
 /* The "direct" method that Sec. 4 compares Algorithm 3 with: the
  * self-consistent field iteration on the whole fine space.  Every pass
  * builds H(rho_in) = 1/2 K + M[V_ext + V_H(rho_in) + V_xc(rho_in)] (Sec. 3.1;

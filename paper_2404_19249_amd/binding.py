@@ -28,6 +28,10 @@ class MeshDesc(C.Structure):
                 ("dirichlet_host", C.POINTER(C.c_uint8)), ("L", C.c_double)]
 
 
+class MetricParams(C.Structure):
+    _fields_ = [("eps", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double)]
+
+
 class QuadDesc(C.Structure):
     _fields_ = [("n_q", C.c_int32), ("bary_host", C.POINTER(C.c_double)),
                 ("w_host", C.POINTER(C.c_double))]
@@ -123,6 +127,12 @@ _SIGS = {
     "ks_batch_destroy": (C.c_int, [_P]),
     "ks_scf_step": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                               C.c_int32, _P, C.POINTER(StepReport)]),
+    "ks_mesh_metric": (C.c_int, [C.POINTER(MeshDesc), _P, C.c_int32, C.POINTER(C.c_double),
+                                 C.POINTER(MetricParams), _P, _P]),
+    "ks_move_nodes": (C.c_int, [C.POINTER(MeshDesc), _P, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_int32), _P]),
+    "ks_interpolate_field": (C.c_int, [C.POINTER(MeshDesc), _P, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                       _P, _P]),
     "ks_stream_probe": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P]),
     "ks_interpolate": (C.c_int, [_P, C.POINTER(MeshDesc), _P, C.c_int32, C.c_int32, _P]),
     "ks_direct_scf": (C.c_int, [_P, _P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),

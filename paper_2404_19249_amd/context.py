@@ -420,3 +420,63 @@ def stream_probe(kind="copy", nbytes=1 << 30, nontemporal=False, reps=10, stream
     B.check(lib.ks_stream_probe(int(nbytes), {"read": 0, "copy": 1, "triad": 2}[kind], int(bool(nontemporal)),
                                 int(reps), C.byref(out), C.c_void_p(st.cuda_stream)), lib)
     return out.value
+
+
+class _HostMesh:
+    """Host arrays of a P1 mesh kept alive for one call, and its descriptor."""
+
+    def __init__(self, mesh):
+        self.co = _f64(mesh.coords)
+        self.el = _i32(mesh.elems)
+        self.di = np.ascontiguousarray(mesh.dirichlet, np.uint8)
+        self.desc = B.MeshDesc(self.co.shape[0], self.el.shape[0], int(getattr(mesh, "order", 1)),
+                               self.co.ctypes.data_as(C.POINTER(C.c_double)),
+                               self.el.ctypes.data_as(C.POINTER(C.c_int32)),
+                               self.di.ctypes.data_as(C.POINTER(C.c_uint8)), float(getattr(mesh, "L", 0.0)))
+
+
+def _stream(stream):
+    import torch
+    return C.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def mesh_metric(mesh, psi, occ, eps, h_min, h_max, stream=None):
+    """ks_mesh_metric: the metric of sqrt(rho) (eqs. m1-m2) at every node of
+    a P1 mesh; psi device [N][k] (non-Dirichlet nodes ascending).  Returns a
+    device tensor [n_nodes][6] (xx, yy, zz, xy, xz, yz)."""
+    import torch
+    lib = B.load_library()
+    hm = _HostMesh(mesh)
+    occ_a = _f64(occ)
+    out = torch.empty(hm.co.shape[0], 6, dtype=torch.float64, device=psi.device)
+    prm = B.MetricParams(float(eps), float(h_min), float(h_max))
+    B.check(lib.ks_mesh_metric(C.byref(hm.desc), C.c_void_p(psi.contiguous().data_ptr()), int(psi.shape[1]),
+                               B.dptr(occ_a), C.byref(prm), C.c_void_p(out.data_ptr()), _stream(stream)), lib)
+    return out
+
+
+def move_nodes(mesh, metric, omega=0.5, sweeps=1, stream=None):
+    """ks_move_nodes: the mesh's nodes after `sweeps` damped metric spring
+    sweeps (host [n_nodes][3]) and the number of step halvings."""
+    lib = B.load_library()
+    hm = _HostMesh(mesh)
+    out = np.empty((hm.co.shape[0], 3))
+    hv = C.c_int32(0)
+    B.check(lib.ks_move_nodes(C.byref(hm.desc), C.c_void_p(metric.contiguous().data_ptr()), float(omega),
+                              int(sweeps), B.dptr(out), C.byref(hv), _stream(stream)), lib)
+    return out, hv.value
+
+
+def interpolate_field(src_mesh, field, pts, stream=None):
+    """ks_interpolate_field: a P1 nodal field on src_mesh (device [n_nodes][m])
+    at the points pts (host [n][3]); returns a device tensor [n][m]."""
+    import torch
+    lib = B.load_library()
+    hm = _HostMesh(src_mesh)
+    P = _f64(pts)
+    f = field.contiguous()
+    m = 1 if f.dim() == 1 else int(f.shape[1])
+    out = torch.empty(P.shape[0], m, dtype=torch.float64, device=f.device)
+    B.check(lib.ks_interpolate_field(C.byref(hm.desc), C.c_void_p(f.data_ptr()), m, int(P.shape[0]), B.dptr(P),
+                                     C.c_void_p(out.data_ptr()), _stream(stream)), lib)
+    return out
