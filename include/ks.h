@@ -266,8 +266,9 @@ int ks_scf_run(ks_ctx *ctx, double *psi, double *lambda_host, int32_t k, const d
  * orbitals, P1 on src and zero on its Dirichlet nodes, are interpolated
  * there.  psi_src: device [N_src][k], rows = src's non-Dirichlet nodes in
  * ascending order (the orbital layout of a context on src); psi: device
- * [N][k] on this context.  The location runs on the host; two small device
- * buffers are allocated for the call.  orthonormalize != 0: the
+ * [N][k] on this context.  The search index (face neighbours, bucket grid)
+ * is built on the host; the location runs on the GPU, one thread per node;
+ * a few device buffers are allocated for the call.  orthonormalize != 0: the
  * interpolated columns are then made M-orthonormal on this mesh in column
  * order (Cholesky of Psi^T M Psi), as an SCF started from them expects;
  * KS_ERR_EIG if they are linearly dependent.  KS_ERR_ARG for a P2 source or
@@ -316,7 +317,7 @@ int ks_move_nodes(const ks_mesh_desc *mesh, const double *metric, double omega, 
 
 /* Algorithm 1 for a nodal field: the P1 interpolant on src of field
  * (device [src n_nodes][m], every node including Dirichlet ones) evaluated
- * at n_pts points (pts_host [n_pts][3]; located on the host as in
+ * at n_pts points (pts_host [n_pts][3]; located on the GPU as in
  * ks_interpolate); out: device [n_pts][m]. */
 int ks_interpolate_field(const ks_mesh_desc *src, const double *field, int32_t m, int32_t n_pts,
                          const double *pts_host, double *out, hipStream_t stream);

@@ -102,6 +102,15 @@ void launch_lincomb(int64_t n, int nvec, const double *coef_dev, const double *c
 // element's projection).
 int nonnested_weights(int ncv, const double *cv, int nct, const int32_t *ctet, int npts, const double *pts,
                       int32_t *vid, double *w);
+// the same location on the GPU for device points pts_dev [npts][3]; vid_dev,
+// w_dev device [npts][4]; the search index is built on the host from the
+// host mesh arrays.  0, -1 bad vertex ids, -2 degenerate weights, -3 device
+// allocation, -4 HIP error
+int nonnested_weights_device(int ncv, const double *cv, int nct, const int32_t *ctet, int npts, const double *pts_dev,
+                             int32_t *vid_dev, double *w_dev, hipStream_t s);
+void launch_interior_coords(int nn, const int32_t *node2int, const double *coords, double *pts, hipStream_t s);
+void launch_ell_from_vertices(int npts, const int32_t *vid, const double *w, const int32_t *sint, int32_t *idx,
+                              double *wo, hipStream_t s);
 
 // ------------------------------------------------------------- sparse / CG
 struct ColState;  // per-column PCG scalars, defined in spmm_cg.hip

@@ -2732,48 +2732,40 @@ extern "C" int ks_interpolate(ks_ctx *c, const ks_mesh_desc *src, const double *
     if (src->elems_host[i] < 0 || src->elems_host[i] >= src->n_nodes) return fail(KS_ERR_MESH, "source node id out of range");
   hipStream_t s = c->s;
   const int N = c->N;
-  // this mesh's interior node coordinates in storage order
-  std::vector<int32_t> n2i(c->n_nodes);
-  std::vector<double> xyz((size_t)c->n_nodes * 3);
-  HIPCHK(hipMemcpyAsync(n2i.data(), c->node2int, sizeof(int32_t) * c->n_nodes, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(xyz.data(), c->coords, sizeof(double) * xyz.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<double> pts((size_t)N * 3);
-  for (int v = 0; v < c->n_nodes; ++v)
-    if (n2i[v] >= 0)
-      for (int d = 0; d < 3; ++d) pts[3 * (size_t)n2i[v] + d] = xyz[3 * (size_t)v + d];
   // source unknowns: the non-Dirichlet nodes in ascending order
   std::vector<int32_t> sint(src->n_nodes, -1);
   int ns = 0;
   for (int v = 0; v < src->n_nodes; ++v)
     if (!src->dirichlet_host[v]) sint[v] = ns++;
-  std::vector<int32_t> vid((size_t)N * 4);
-  std::vector<double> wv((size_t)N * 4);
-  if (nonnested_weights(src->n_nodes, src->coords_host, src->n_elems, src->elems_host, N, pts.data(), vid.data(),
-                        wv.data()) < 0)
-    return fail(KS_ERR_MESH, "source mesh: bad element vertex ids");
-  std::vector<int32_t> idx((size_t)N * 4, -1);
-  std::vector<double> w((size_t)N * 4, 0.0);
-  for (size_t a = 0; a < idx.size(); ++a) {
-    const int u = sint[vid[a]];
-    if (u >= 0 && wv[a] != 0.0) {
-      idx[a] = u;
-      w[a] = wv[a];
-    }
-  }
-  int32_t *didx = nullptr;
-  double *dw = nullptr, *dg = nullptr;
-  const size_t kk = (size_t)k * k;
-  if (hipMalloc(&didx, sizeof(int32_t) * idx.size()) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
-  if (hipMalloc(&dw, sizeof(double) * (w.size() + 2 * kk)) != hipSuccess) {
-    (void)hipFree(didx);
+  int32_t *didx = nullptr, *dvid = nullptr, *dsint = nullptr;
+  double *dw = nullptr, *dg = nullptr, *dwv = nullptr, *dpts = nullptr;
+  const size_t kk = (size_t)k * k, n4 = (size_t)N * 4;
+  auto release = [&]() {
+    for (void *p : {(void *)didx, (void *)dvid, (void *)dsint, (void *)dw, (void *)dwv, (void *)dpts})
+      if (p) (void)hipFree(p);
+  };
+  if (hipMalloc(&didx, sizeof(int32_t) * n4) != hipSuccess || hipMalloc(&dvid, sizeof(int32_t) * n4) != hipSuccess ||
+      hipMalloc(&dsint, sizeof(int32_t) * sint.size()) != hipSuccess ||
+      hipMalloc(&dw, sizeof(double) * (n4 + 2 * kk)) != hipSuccess || hipMalloc(&dwv, sizeof(double) * n4) != hipSuccess ||
+      hipMalloc(&dpts, sizeof(double) * 3 * (size_t)N) != hipSuccess) {
+    release();
     return fail(KS_ERR_NOMEM, "hipMalloc failed");
   }
-  dg = dw + w.size();
+  dg = dw + n4;
   int rc = KS_OK;
-  hipError_t e = hipMemcpyAsync(didx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(dw, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(dsint, sint.data(), sizeof(int32_t) * sint.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
+    // this mesh's interior nodes (storage order) located in src on the GPU
+    launch_interior_coords(c->n_nodes, c->node2int, c->coords, dpts, s);
+    const int r = nonnested_weights_device(src->n_nodes, src->coords_host, src->n_elems, src->elems_host, N, dpts,
+                                           dvid, dwv, s);
+    if (r == -1) rc = fail(KS_ERR_MESH, "source mesh: bad element vertex ids");
+    else if (r == -3) rc = fail(KS_ERR_NOMEM, "hipMalloc failed");
+    else if (r == -2) rc = fail(KS_ERR_MESH, "point location: degenerate weights");
+    else if (r < -2) rc = fail(KS_ERR_HIP, "point location failed");
+    if (rc == KS_OK) launch_ell_from_vertices(N, dvid, dwv, dsint, didx, dw, s);
+  }
+  if (e == hipSuccess && rc == KS_OK) {
     launch_ellP_times(N, didx, dw, psi_src, k, k, 1.0, nullptr, 0, c->Xs, k, s);
     double *out = c->Xs;
     if (orthonormalize) {
@@ -2820,8 +2812,7 @@ extern "C" int ks_interpolate(ks_ctx *c, const ks_mesh_desc *src, const double *
       e = hipStreamSynchronize(s);
     }
   }
-  (void)hipFree(didx);
-  (void)hipFree(dw);
+  release();
   if (e != hipSuccess) return fail(KS_ERR_HIP, hipGetErrorString(e));
   if (rc != KS_OK) return rc;
   c->have_step = false;

@@ -415,17 +415,17 @@ extern "C" int ks_interpolate_field(const ks_mesh_desc *src, const double *field
   if (rc < 0) return rc;
   if (!field || !pts_host || !out || m < 1 || n_pts < 0) return set_error(KS_ERR_ARG, "null argument or m < 1");
   if (n_pts == 0) return KS_OK;
-  std::vector<int32_t> vid((size_t)n_pts * 4);
-  std::vector<double> w((size_t)n_pts * 4);
-  if (nonnested_weights(src->n_nodes, src->coords_host, src->n_elems, src->elems_host, n_pts, pts_host, vid.data(),
-                        w.data()) < 0)
-    return set_error(KS_ERR_MESH, "source mesh: bad element vertex ids");
   Scratch sc;
-  int32_t *dv = sc.get<int32_t>(vid.size());
-  double *dw = sc.get<double>(w.size());
-  if (!dv || !dw) return set_error(KS_ERR_NOMEM, "ks_interpolate_field: hipMalloc failed");
-  MCHK(hipMemcpyAsync(dv, vid.data(), sizeof(int32_t) * vid.size(), hipMemcpyHostToDevice, s));
-  MCHK(hipMemcpyAsync(dw, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, s));
+  int32_t *dv = sc.get<int32_t>((size_t)n_pts * 4);
+  double *dw = sc.get<double>((size_t)n_pts * 4), *dp = sc.get<double>((size_t)n_pts * 3);
+  if (!dv || !dw || !dp) return set_error(KS_ERR_NOMEM, "ks_interpolate_field: hipMalloc failed");
+  MCHK(hipMemcpyAsync(dp, pts_host, sizeof(double) * 3 * (size_t)n_pts, hipMemcpyHostToDevice, s));
+  const int r = nonnested_weights_device(src->n_nodes, src->coords_host, src->n_elems, src->elems_host, n_pts, dp, dv,
+                                         dw, s);
+  if (r == -1) return set_error(KS_ERR_MESH, "source mesh: bad element vertex ids");
+  if (r == -2) return set_error(KS_ERR_MESH, "point location: degenerate weights");
+  if (r == -3) return set_error(KS_ERR_NOMEM, "ks_interpolate_field: hipMalloc failed");
+  if (r < 0) return set_error(KS_ERR_HIP, "point location failed");
   hipLaunchKernelGGL(k_field_gather, dim3(blocks_for((int64_t)n_pts * m)), dim3(256), 0, s, n_pts, m, dv, dw, field,
                      out);
   MCHK(hipGetLastError());
