@@ -80,7 +80,7 @@ typedef struct {
 
 enum { KS_XC_NONE = 0, KS_XC_X = 1, KS_XC_X_PZ81 = 2 };
 enum { KS_HARTREE_OFF = 0, KS_HARTREE_MULTIPOLE = 1, KS_HARTREE_MULTIPOLE_LITERAL = 2 };
-enum { KS_PREC_FP64 = 0, KS_PREC_MIXED = 1 };
+enum { KS_PREC_FP64 = 0, KS_PREC_MIXED = 1, KS_PREC_FP64_BLOCK_CG = 2 };
 
 typedef struct {
   double mu;               /* shift of the BVPs; < 0 selects 8 M sum_k Z_k^2 (Sec. 4) */
@@ -172,7 +172,13 @@ typedef struct {
  * with S from the last ks_assemble, one Jacobi-preconditioned CG recurrence
  * per column sharing every SpMM, started at psi_old, stopped per column at
  * ||b_i - S x_i||_2 <= tol_solve ||b_i||_2.  precision = KS_PREC_MIXED runs
- * FP32 PCG inside FP64 iterative refinement (FP64 residuals).
+ * FP32 PCG inside FP64 iterative refinement (FP64 residuals);
+ * KS_PREC_FP64_BLOCK_CG runs O'Leary's block conjugate gradients in FP64
+ * (one Krylov block for all k columns: X += P alpha, R -= S P alpha with
+ * alpha = (P^T S P)^-1 (Z^T R), Z = D^-1 R, P = Z + P beta with
+ * beta = (Z_old^T R_old)^-1 (Z^T R), the k x k systems by Cholesky on the
+ * host), stopped when every column meets the tolerance; KS_ERR_BREAKDOWN
+ * when P^T S P or Z^T R loses positive definiteness (the block lost rank).
  * psi_old, psi_hat: device [N][k]; lambda_host [k]; st_host may be NULL.
  * Returns KS_NOT_CONVERGED if max_it_solve was reached. */
 int ks_block_solve(ks_ctx *ctx, const double *psi_old, const double *lambda_host, int32_t k,

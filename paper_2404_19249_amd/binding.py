@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "KS_OK", 1: "KS_NOT_CONVERGED", 2: "KS_WARN_DEGENERATE", -1: 
                 -6: "KS_ERR_EIG", -7: "KS_ERR_STATE"}
 XC = {"none": 0, "x_only": 1, "x_pz81": 2}
 HARTREE = {"off": 0, "multipole": 1, "multipole_literal": 2}
-PREC = {"fp64": 0, "mixed": 1}
+PREC = {"fp64": 0, "mixed": 1, "block_cg": 2}
 
 
 class MeshDesc(C.Structure):

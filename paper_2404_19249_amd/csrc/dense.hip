@@ -1155,4 +1155,15 @@ void launch_small_eig(int m, int k, const double *FA, int ldfa, const double *FB
                      theta, U, info);
 }
 
+// Z[i][j] = R[i][j] / d[i] (the Jacobi preconditioner applied to a block)
+__global__ void k_row_div(int64_t n, int k, const double *__restrict__ R, const double *__restrict__ d,
+                          double *__restrict__ Z) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) Z[t] = R[t] / d[t / k];
+}
+void launch_row_div(int N, int k, const double *R, const double *d, double *Z, hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  if (n > 0) hipLaunchKernelGGL(k_row_div, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, k, R, d, Z);
+}
+
 }  // namespace ks

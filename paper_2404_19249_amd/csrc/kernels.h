@@ -236,6 +236,8 @@ void launch_zu(int N, const int32_t *Pidx, const double *Pw, int n_H, const doub
 // lds, C m x k row-major, m k doubles <= 64 KB; -1 otherwise)
 int launch_tsmm(int N, int m, const double *S, int lds, const double *C, int k, double *Out, int ldo,
                 hipStream_t s);
+// Z = D^-1 R row by row (d: the diagonal), [N][k] row-major
+void launch_row_div(int N, int k, const double *R, const double *d, double *Z, hipStream_t s);
 // LOBPCG residual block: R = HX - MX diag(theta) (row stride ld), W = D^-1 R
 // (row stride ldw), per-block column sums of R^2 and MX^2 in part[b][2k];
 // returns the number of blocks (<= max_blocks), -1 if k > 256

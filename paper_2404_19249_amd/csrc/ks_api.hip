@@ -2202,6 +2202,108 @@ static int true_residual(ks_ctx *c, const double *B, const double *X, int k, dou
 }
 
 // S X = B from X (in/out), FP64 or FP32-in-FP64-refinement
+// Cholesky solve of the k x k SPD system G Y = H (row-major, host); false
+// if G is not positive definite
+static bool chol_solve(int k, std::vector<double> G, const std::vector<double> &H, std::vector<double> &Y) {
+  for (int j = 0; j < k; ++j) {
+    double d = G[(size_t)j * k + j];
+    for (int p = 0; p < j; ++p) d -= G[(size_t)j * k + p] * G[(size_t)j * k + p];
+    if (!(d > 0.0)) return false;
+    const double l = std::sqrt(d);
+    G[(size_t)j * k + j] = l;
+    for (int i = j + 1; i < k; ++i) {
+      double t = G[(size_t)i * k + j];
+      for (int p = 0; p < j; ++p) t -= G[(size_t)i * k + p] * G[(size_t)j * k + p];
+      G[(size_t)i * k + j] = t / l;
+    }
+  }
+  Y = H;
+  for (int c = 0; c < k; ++c) {
+    for (int i = 0; i < k; ++i) {  // L y = h
+      double t = Y[(size_t)i * k + c];
+      for (int p = 0; p < i; ++p) t -= G[(size_t)i * k + p] * Y[(size_t)p * k + c];
+      Y[(size_t)i * k + c] = t / G[(size_t)i * k + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {  // L^T y = y
+      double t = Y[(size_t)i * k + c];
+      for (int p = i + 1; p < k; ++p) t -= G[(size_t)p * k + i] * Y[(size_t)p * k + c];
+      Y[(size_t)i * k + c] = t / G[(size_t)i * k + i];
+    }
+  }
+  return true;
+}
+
+// O'Leary's block preconditioned CG in FP64 for S X = B (Jacobi
+// preconditioner); X holds the start on entry.  Work blocks: the FP64 PCG
+// buffers (R, P, P2 = Z, Q) and c->Wv.
+static int block_cg(ks_ctx *c, const double *B, double *X, int k, double tol, ks_solve_stats *st) {
+  const int N = c->N;
+  hipStream_t s = c->s;
+  double *R = static_cast<double *>(c->pw64.R), *P = static_cast<double *>(c->pw64.P);
+  double *Z = static_cast<double *>(c->pw64.P2), *Q = static_cast<double *>(c->pw64.Q), *T = c->Wv;
+  const size_t kk = (size_t)k * k;
+  double *dG = nullptr;
+  if (hipMalloc(&dG, sizeof(double) * 2 * kk) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  struct Free {
+    double *p;
+    ~Free() { (void)hipFree(p); }
+  } guard{dG};
+  std::vector<double> bn(k), rn(k), g1(kk), g2(kk), g3(kk), co(kk);
+  auto gram = [&](const double *A, const double *Bm, std::vector<double> &h) -> int {
+    launch_gemm_tn_sym(N, k, A, k, Bm, k, dG, k, c->gwork, s);
+    HIPCHK(hipMemcpyAsync(h.data(), dG, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return KS_OK;
+  };
+  auto colnorms = [&](const double *A, std::vector<double> &out) -> int {
+    const int nb = launch_colnorms(N, k, A, c->redpart, s);
+    TRY(reduce_small(c, c->redpart, nb, k, out.data()));
+    for (auto &v : out) v = std::sqrt(v);
+    return KS_OK;
+  };
+  // Out = A C (C k x k on the host)
+  auto times = [&](const double *A, const std::vector<double> &C, double *Out) -> int {
+    HIPCHK(hipMemcpyAsync(dG + kk, C.data(), sizeof(double) * kk, hipMemcpyHostToDevice, s));
+    if (launch_tsmm(N, k, A, k, dG + kk, k, Out, k, s) < 0) return fail(KS_ERR_ARG, "k too large for block CG");
+    return KS_OK;
+  };
+  TRY(colnorms(B, bn));
+  spmm_op(c, c->S, X, k, R, B);  // R = B - S X
+  launch_row_div(N, k, R, c->diagS, Z, s);
+  launch_axpby((int64_t)N * k, 1.0, Z, 0.0, P, s);
+  TRY(gram(Z, R, g2));
+  TRY(colnorms(R, rn));
+  auto done = [&]() {
+    for (int j = 0; j < k; ++j)
+      if (rn[j] > tol * bn[j]) return false;
+    return true;
+  };
+  int it = 0;
+  bool conv = done();
+  for (it = 0; !conv && it < c->opt.max_it_solve;) {
+    ++it;
+    spmm_op(c, c->S, P, k, Q, nullptr);
+    TRY(gram(P, Q, g1));
+    if (!chol_solve(k, g1, g2, co)) return fail(KS_ERR_BREAKDOWN, "block CG: P^T S P is not positive definite");
+    TRY(times(P, co, T));
+    launch_axpby((int64_t)N * k, 1.0, T, 1.0, X, s);
+    TRY(times(Q, co, T));
+    launch_axpby((int64_t)N * k, -1.0, T, 1.0, R, s);
+    TRY(colnorms(R, rn));
+    conv = done();
+    if (conv) break;
+    launch_row_div(N, k, R, c->diagS, Z, s);
+    TRY(gram(Z, R, g3));
+    if (!chol_solve(k, g2, g3, co)) return fail(KS_ERR_BREAKDOWN, "block CG: Z^T R is not positive definite");
+    TRY(times(P, co, T));
+    launch_combine3((int64_t)N * k, 1.0, Z, 1.0, T, 0.0, nullptr, P, s);
+    g2 = g3;
+  }
+  for (int j = 0; j < k && j < 64; ++j) st->iters[j] = it;
+  st->converged = conv ? 1 : 0;  // the caller recomputes the true residuals
+  return KS_OK;
+}
+
 static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precision, double tol,
                       ks_solve_stats *st) {
   hipStream_t s = c->s;
@@ -2210,7 +2312,11 @@ static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precisio
   std::memset(&loc, 0, sizeof(loc));
   HIPCHK(hipEventRecord(c->ev0, s));
   int conv = 0, brk = 0;
-  if (precision == KS_PREC_FP64) {
+  if (precision == KS_PREC_FP64_BLOCK_CG) {
+    TRY(block_cg(c, B, X, k, tol, &loc));
+    conv = loc.converged;
+    loc.refinements = 0;
+  } else if (precision == KS_PREC_FP64) {
     int r = pcg_solve<double>(c->N, k, c->rowptr, c->col, c->S, c->rorder, c->diagS, B, X, tol,
                               c->opt.max_it_solve, c->pw64, loc.iters, loc.relres, &conv, &brk, s,
                               c->ng64);
@@ -2297,7 +2403,8 @@ extern "C" int ks_block_solve_rhs(ks_ctx *c, const double *B, const double *X0, 
                                   int32_t precision, double tol, double *X, ks_solve_stats *st) {
   if (!c || !B || !X) return fail(KS_ERR_ARG, "null argument");
   if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
-  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED && precision != KS_PREC_FP64_BLOCK_CG)
+    return fail(KS_ERR_ARG, "bad precision");
   launch_rows_to_storage(c->N, k, B, c->Bv, c->int2nat, c->s);
   if (X0) launch_rows_to_storage(c->N, k, X0, c->Xs, c->int2nat, c->s);
   else HIPCHK(hipMemsetAsync(c->Xs, 0, sizeof(double) * c->N * k, c->s));
@@ -2322,7 +2429,8 @@ extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *la
                               int32_t precision, double *psi_hat, ks_solve_stats *st) {
   if (!c || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
   if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
-  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED && precision != KS_PREC_FP64_BLOCK_CG)
+    return fail(KS_ERR_ARG, "bad precision");
   launch_rows_to_storage(c->N, k, psi_old, c->PsiIn, c->int2nat, c->s);
   TRY(build_rhs(c, c->PsiIn, lambda_host, k, c->Bv));
   HIPCHK(hipMemcpyAsync(c->Xs, c->PsiIn, sizeof(double) * c->N * k, hipMemcpyDeviceToDevice, c->s));
@@ -2582,7 +2690,8 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
                            ks_step_report *rep) {
   if (!c || !psi || !lambda_host || !occ_host) return fail(KS_ERR_ARG, "null argument");
   if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
-  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED) return fail(KS_ERR_ARG, "bad precision");
+  if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED && precision != KS_PREC_FP64_BLOCK_CG)
+    return fail(KS_ERR_ARG, "bad precision");
   hipStream_t s = c->s;
   ks_step_report R;
   std::memset(&R, 0, sizeof(R));

@@ -337,3 +337,44 @@ def test_inner_iteration_cap_matches_oracle_and_blocks_backward():
         ctx.step_backward()
     assert e.value.code == -7
     ctx.close()
+
+
+@pytest.mark.parametrize("name,kw", CASES[:2])
+def test_block_cg_matches_oracle(name, kw):
+    """KS_PREC_FP64_BLOCK_CG (O'Leary's block CG, one Krylov block for all
+    columns) solves the same BVPs as the oracle's per-column PCG; its block
+    Krylov space holds every column's own, so it needs no more iterations
+    than the slowest column of the per-column recurrence (up to rounding)."""
+    w = make_workload(name, **kw)
+    ctx = _ctx(w)
+    p = KSProblem.from_workload(w)
+    th, Psi = initial_guess(p, w.k)
+    psi = torch.tensor(Psi, device=DEV)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    hat, st = ctx.block_solve(psi, th, precision="block_cg")
+    _, st_col = ctx.block_solve(psi, th, precision="fp64")
+    assert st["converged"]
+    from oracle.step import block_solve
+    rho = p.density(Psi)
+    veff = p.vext_q
+    if p.hartree or p.xc_mode != "none":
+        VH, _ = p.hartree_nodes(rho, p.boundary_data(rho), 1e-14)
+        _, vxc = lda_xc(rho, p.xc_mode)
+        veff = p.vext_q + p.at_quad(VH) + vxc
+    S = (0.5 * p.K_II + p.potential_matrix(veff) + p.mu * p.M_II).tocsr()
+    ref, its, rr = block_solve(p, S, Psi, th, tol=1e-13)
+    assert _rel(hat.cpu().numpy(), ref) < 1e-10
+    assert max(st["relres"]) < 1e-12
+    assert max(st["iters"]) <= max(st_col["iters"]) + 1
+
+
+def test_block_cg_with_one_column_is_pcg():
+    """With k = 1 the block recurrence is the scalar Jacobi-PCG recurrence."""
+    w = make_workload("small_molecule", n=6, k=1)
+    ctx = _ctx(w)
+    psi, lam = ctx.initial_guess(1)
+    ctx.assemble(psi, w.occ, want_fields=False)
+    a, st_a = ctx.block_solve(psi, lam, precision="block_cg")
+    b, st_b = ctx.block_solve(psi, lam, precision="fp64")
+    assert abs(st_a["iters"][0] - st_b["iters"][0]) <= 1
+    assert _rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-11
