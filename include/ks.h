@@ -188,6 +188,27 @@ int ks_block_solve(ks_ctx *ctx, const double *psi_old, const double *lambda_host
 int ks_block_solve_rhs(ks_ctx *ctx, const double *B, const double *X0, int32_t k,
                        int32_t precision, double tol, double *X, ks_solve_stats *st_host);
 
+/* Reverse mode through the truncated FP64 block solve (the derivative of
+ * what the solver returns, not of the exact S^-1 B; the paper has no
+ * derivatives).  Runs S X = B from X0 (NULL = zero) by per-column
+ * Jacobi-PCG, D = diag S, each column stopped at ||b - S x|| <= tol ||b||
+ * or after max_it iterations (tol = 0: exactly max_it), then for
+ * L = sum_ij Xbar_ij X_ij sweeps the recurrence backwards:
+ *   g_q = dL/dV_q, V the quadrature potential of S = 1/2 K + M[V] + mu M
+ *         (dS_ab/dV_q = w_q |J| phi_a phi_b), the preconditioner's
+ *         dependence on diag S included; device [n_e][n_q];
+ *   Bbar = dL/dB, device [N][k].
+ * The forward keeps the per-column scalars of every iteration on the host and
+ * the residual and direction blocks every `seg` iterations (0: 8) on the
+ * device; the reverse sweep recomputes each segment from its checkpoint
+ * (bit-identical kernels and coefficients).  Device memory: about
+ * (13 + 2 (seg + 1) + 2 K / seg) blocks of N x k doubles, allocated and freed
+ * by the call.  B, X0, Xbar, X: device [N][k] (API order); iters_host [k]
+ * (may be NULL) receives the per-column iteration counts.  Requires a prior
+ * ks_assemble. */
+int ks_block_solve_vjp(ks_ctx *ctx, const double *B, const double *X0, int32_t k, double tol, int32_t max_it,
+                       int32_t seg, const double *Xbar, double *X, double *g_q, double *Bbar, int32_t *iters_host);
+
 /* Galerkin projection onto the augmented space (eqs. st1-st7):
  * Z = [I_H^h | psi_tilde] with psi_tilde = psi_hat M-orthogonalised against
  * span(I_H^h) (same span); F = Z^T H Z for H = M (which = 0), A^L (1) or the

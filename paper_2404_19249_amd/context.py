@@ -191,6 +191,20 @@ class KSContext:
         s["status"] = code
         return X, s
 
+    def block_solve_vjp(self, Bm, Xbar, X0=None, tol=1e-10, max_it=500, seg=8):
+        """ks_block_solve_vjp: the truncated FP64 solve X of S X = Bm and, for
+        L = sum(Xbar * X), dL/dV at the quadrature points and dL/dBm."""
+        k = Bm.shape[1]
+        X = self.empty(self.N, k)
+        g = self.empty(self.n_elems, self.n_q)
+        Bbar = self.empty(self.N, k)
+        its = (C.c_int32 * k)()
+        B.check(self.lib.ks_block_solve_vjp(self.h, self._ptr(Bm.contiguous()),
+                                            self._ptr(None if X0 is None else X0.contiguous()), k, float(tol),
+                                            int(max_it), int(seg), self._ptr(Xbar.contiguous()), self._ptr(X),
+                                            self._ptr(g), self._ptr(Bbar), its), self.lib)
+        return X, g, Bbar, list(its)
+
     def augmented_project(self, psi_hat, which):
         k = psi_hat.shape[1]
         m = self.N_H + k

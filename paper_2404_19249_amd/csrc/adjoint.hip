@@ -117,6 +117,109 @@ void launch_grad_q(const int32_t *edof, int n_loc, int n_e, int n_q, const doubl
     hipLaunchKernelGGL((k_grad_q<10, 8>), gr, b, 0, s, edof, n_e, phi, w, absdet, A, B, k, rho, scale, g);
 }
 
+// Reverse mode through the truncated PCG (per-column coefficients).
+// Y = a o X + b o Y column by column (a, b device [k]; X may be null)
+__global__ void k_col_axpby(int64_t n, int k, const double *__restrict__ a, const double *__restrict__ X,
+                            const double *__restrict__ b, double *__restrict__ Y) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int c = (int)(t % k);
+  const double y = b[c] == 0.0 ? 0.0 : b[c] * Y[t];  // b = 0 never reads Y
+  Y[t] = (X ? a[c] * X[t] : 0.0) + y;
+}
+void launch_col_axpby(int N, int k, const double *a, const double *X, const double *b, double *Y, hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  if (n > 0) hipLaunchKernelGGL(k_col_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, k, a, X, b, Y);
+}
+// Rbar += Zbar / d row by row, and dbar[i] -= sum_c Zbar[i][c] Z[i][c] / d[i]
+__global__ void k_zbar_back(int N, int k, const double *__restrict__ Zbar, const double *__restrict__ Z,
+                            const double *__restrict__ d, double *__restrict__ Rbar, double *__restrict__ dbar) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double di = d[i];
+  double acc = 0.0;
+  for (int c = 0; c < k; ++c) {
+    const double zb = Zbar[(int64_t)i * k + c];
+    Rbar[(int64_t)i * k + c] += zb / di;
+    acc += zb * Z[(int64_t)i * k + c];
+  }
+  dbar[i] -= acc / di;
+}
+void launch_zbar_back(int N, int k, const double *Zbar, const double *Z, const double *d, double *Rbar, double *dbar,
+                      hipStream_t s) {
+  if (N > 0) hipLaunchKernelGGL(k_zbar_back, dim3((N + 255) / 256), dim3(256), 0, s, N, k, Zbar, Z, d, Rbar, dbar);
+}
+// g_q += scale w_q |J| sum_c A_c(x_q) B_c(x_q) (A, B [N][k] over interior nodes),
+// and with A = null: g_q += w_q |J| sum_a dbar[dof a] phi_a(x_q)^2 (B = dbar)
+template <int NLOC, int NQ>
+__global__ void __launch_bounds__(256) k_pair_accum(const int32_t *__restrict__ edof, int n_e,
+                                                    const double *__restrict__ phi, const double *__restrict__ w,
+                                                    const double *__restrict__ absdet, const double *__restrict__ A,
+                                                    const double *__restrict__ Bm, int k, double scale,
+                                                    double *__restrict__ g) {
+  __shared__ double s_phi[NQ * NLOC];
+  __shared__ double s_w[NQ];
+  for (int i = threadIdx.x; i < NQ * NLOC; i += blockDim.x) s_phi[i] = phi[i];
+  for (int i = threadIdx.x; i < NQ; i += blockDim.x) s_w[i] = w[i];
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_e) return;
+  int dof[NLOC];
+#pragma unroll
+  for (int a = 0; a < NLOC; ++a) dof[a] = edof[(int64_t)e * NLOC + a];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (A) {
+    for (int i = 0; i < k; ++i) {
+      double xa[NLOC], ya[NLOC];
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) {
+        xa[a] = dof[a] >= 0 ? A[(int64_t)dof[a] * k + i] : 0.0;
+        ya[a] = dof[a] >= 0 ? Bm[(int64_t)dof[a] * k + i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        double u = 0.0, v = 0.0;
+#pragma unroll
+        for (int a = 0; a < NLOC; ++a) {
+          u += s_phi[q * NLOC + a] * xa[a];
+          v += s_phi[q * NLOC + a] * ya[a];
+        }
+        acc[q] += u * v;
+      }
+    }
+  } else {
+    double da[NLOC];
+#pragma unroll
+    for (int a = 0; a < NLOC; ++a) da[a] = dof[a] >= 0 ? Bm[dof[a]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double u = 0.0;
+#pragma unroll
+      for (int a = 0; a < NLOC; ++a) u += da[a] * s_phi[q * NLOC + a] * s_phi[q * NLOC + a];
+      acc[q] = u;
+    }
+  }
+  const double dj = absdet[e];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) g[(int64_t)e * NQ + q] += scale * s_w[q] * dj * acc[q];
+}
+void launch_pair_accum(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi, const double *w,
+                       const double *absdet, const double *A, const double *B, int k, double scale, double *g,
+                       hipStream_t s) {
+  if (n_e <= 0) return;
+  dim3 gr((n_e + 255) / 256), b(256);
+  if (n_loc == 4 && n_q == 8)
+    hipLaunchKernelGGL((k_pair_accum<4, 8>), gr, b, 0, s, edof, n_e, phi, w, absdet, A, B, k, scale, g);
+  else if (n_loc == 10 && n_q == 27)
+    hipLaunchKernelGGL((k_pair_accum<10, 27>), gr, b, 0, s, edof, n_e, phi, w, absdet, A, B, k, scale, g);
+  else if (n_loc == 4 && n_q == 27)
+    hipLaunchKernelGGL((k_pair_accum<4, 27>), gr, b, 0, s, edof, n_e, phi, w, absdet, A, B, k, scale, g);
+  else if (n_loc == 10 && n_q == 8)
+    hipLaunchKernelGGL((k_pair_accum<10, 8>), gr, b, 0, s, edof, n_e, phi, w, absdet, A, B, k, scale, g);
+}
+
 // Partial sums over the quadrature points of g_q dV_ext(x_q)/dR_a for up to 8
 // nuclei (atoms a0 .. a0+na-1): dV/dR_a = -Z_a (x - R_a) / |x - R_a|^3.
 int force_blocks(int n_e) {

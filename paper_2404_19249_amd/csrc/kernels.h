@@ -330,6 +330,13 @@ void launch_force_partials(const double *coords, const int32_t *elems, int n_loc
                            const double *bary, const double *g, int a0, int na, const double *Z,
                            const double *R, double *part, hipStream_t s);
 int launch_coldots(int N, int k, const double *X, const double *Y, double *part, hipStream_t s);
+// reverse mode through the truncated PCG
+void launch_col_axpby(int N, int k, const double *a, const double *X, const double *b, double *Y, hipStream_t s);
+void launch_zbar_back(int N, int k, const double *Zbar, const double *Z, const double *d, double *Rbar, double *dbar,
+                      hipStream_t s);
+void launch_pair_accum(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi, const double *w,
+                       const double *absdet, const double *A, const double *B, int k, double scale, double *g,
+                       hipStream_t s);
 }  // namespace ks
 
 namespace ks {

@@ -2425,6 +2425,240 @@ static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, in
   return KS_OK;
 }
 
+// Reverse mode through the truncated FP64 per-column Jacobi-PCG (see
+// ks_block_solve_vjp in ks.h).  The forward keeps the per-column scalars of
+// every iteration on the host and (R, P) every `seg` iterations on the
+// device; the reverse sweep recomputes each segment's iterates from its
+// checkpoint with the same kernels and coefficients (bit-identical) and
+// runs the adjoint recurrence backwards through it.
+extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *X0_api, int32_t k, double tol,
+                                  int32_t max_it, int32_t seg, const double *Xbar_api, double *X_api, double *g_q,
+                                  double *Bbar_api, int32_t *iters_host) {
+  if (!c || !B_api || !Xbar_api || !X_api || !g_q || !Bbar_api) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (!(tol >= 0.0) || max_it < 1) return fail(KS_ERR_ARG, "need tol >= 0 and max_it >= 1");
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled: call ks_assemble first");
+  if (seg <= 0) seg = 8;
+  hipStream_t s = c->s;
+  const int N = c->N;
+  const size_t nk = (size_t)N * k;
+  // device work: B, X0, X, R, P, Z, Q, xbar, Rbar, Pbar, Zbar, Qbar, T, dbar, coefficients,
+  // checkpoints (grown as needed) and one segment of (R, P)
+  std::vector<void *> bufs;
+  auto dalloc = [&](size_t n) -> double * {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return static_cast<double *>(p);
+  };
+  struct Release {
+    std::vector<void *> &b;
+    ~Release() {
+      for (void *p : b) (void)hipFree(p);
+    }
+  } release{bufs};
+  double *B = dalloc(nk), *X0 = dalloc(nk), *X = dalloc(nk), *R = dalloc(nk), *P = dalloc(nk), *Z = dalloc(nk);
+  double *Q = dalloc(nk), *xb = dalloc(nk), *Rb = dalloc(nk), *Pb = dalloc(nk), *Zb = dalloc(nk), *Qb = dalloc(nk);
+  double *T = dalloc(nk), *dbar = dalloc(N), *coef = dalloc((size_t)16 * k);
+  double *segR = dalloc(nk * (seg + 1)), *segP = dalloc(nk * (seg + 1));
+  if (!B || !X0 || !X || !R || !P || !Z || !Q || !xb || !Rb || !Pb || !Zb || !Qb || !T || !dbar || !coef || !segR ||
+      !segP)
+    return fail(KS_ERR_NOMEM, "ks_block_solve_vjp: hipMalloc failed");
+  std::vector<double *> ckR, ckP;
+  launch_rows_to_storage(N, k, B_api, B, c->int2nat, s);
+  if (X0_api) launch_rows_to_storage(N, k, X0_api, X0, c->int2nat, s);
+  else launch_fill((int64_t)nk, 0.0, X0, s);
+  launch_rows_to_storage(N, k, Xbar_api, xb, c->int2nat, s);
+  const double *d = c->diagS;
+  // host-side coefficient slots: slot i of coef holds k values
+  std::vector<std::vector<double>> hc(16, std::vector<double>(k));
+  auto put = [&](int slot, const std::vector<double> &v) -> const double * {
+    hc[slot] = v;
+    (void)hipMemcpyAsync(coef + (size_t)slot * k, hc[slot].data(), sizeof(double) * k, hipMemcpyHostToDevice, s);
+    return coef + (size_t)slot * k;
+  };
+  auto dots = [&](const double *A, const double *Bm, std::vector<double> &out) -> int {
+    const int nb = launch_coldots(N, k, A, Bm, c->redpart, s);
+    out.assign(k, 0.0);
+    return reduce_small(c, c->redpart, nb, k, out.data());
+  };
+  auto norms = [&](const double *A, std::vector<double> &out) -> int {
+    const int nb = launch_colnorms(N, k, A, c->redpart, s);
+    out.assign(k, 0.0);
+    TRY(reduce_small(c, c->redpart, nb, k, out.data()));
+    for (auto &v : out) v = std::sqrt(v);
+    return KS_OK;
+  };
+  const std::vector<double> ones(k, 1.0), zeros(k, 0.0);
+  // forward: r_0 = b - S x_0, z_0 = D^-1 r_0, p_0 = z_0, rho_0 = r_0.z_0
+  launch_axpby((int64_t)nk, 1.0, X0, 0.0, X, s);
+  spmm_op(c, c->S, X, k, R, B);
+  launch_row_div(N, k, R, d, Z, s);
+  launch_axpby((int64_t)nk, 1.0, Z, 0.0, P, s);
+  std::vector<double> rho, bn, rn;
+  TRY(dots(R, Z, rho));
+  TRY(norms(B, bn));
+  TRY(norms(R, rn));
+  std::vector<char> active(k);
+  for (int j = 0; j < k; ++j) active[j] = rn[j] > tol * bn[j];
+  struct Step {
+    std::vector<char> act;
+    std::vector<double> alpha, beta, rho, sig;
+  };
+  std::vector<Step> steps;
+  auto checkpoint = [&]() -> int {
+    double *r = dalloc(nk), *p = dalloc(nk);
+    if (!r || !p) return fail(KS_ERR_NOMEM, "ks_block_solve_vjp: hipMalloc failed");
+    launch_axpby((int64_t)nk, 1.0, R, 0.0, r, s);
+    launch_axpby((int64_t)nk, 1.0, P, 0.0, p, s);
+    ckR.push_back(r);
+    ckP.push_back(p);
+    return KS_OK;
+  };
+  TRY(checkpoint());
+  // one forward iteration from (Rc, Pc) into (Rn, Pn) with the step's coefficients
+  auto advance = [&](const Step &st, const double *Rc, const double *Pc, double *Rn, double *Pn, bool keep_z) {
+    spmm_op(c, c->S, Pc, k, Q, nullptr);
+    if (Rn != Rc) launch_axpby((int64_t)nk, 1.0, Rc, 0.0, Rn, s);
+    std::vector<double> ma(k), pa(k), pb(k);
+    for (int j = 0; j < k; ++j) {
+      ma[j] = -st.alpha[j];
+      pa[j] = st.act[j] ? 1.0 : 0.0;
+      pb[j] = st.act[j] ? st.beta[j] : 1.0;
+    }
+    launch_col_axpby(N, k, put(0, ma), Q, put(1, ones), Rn, s);
+    launch_row_div(N, k, Rn, d, Z, s);
+    if (Pn != Pc) launch_axpby((int64_t)nk, 1.0, Pc, 0.0, Pn, s);
+    launch_col_axpby(N, k, put(2, pa), Z, put(3, pb), Pn, s);
+    (void)keep_z;
+    (void)hipStreamSynchronize(s);  // the host coefficient slots are reused by the next call
+  };
+  for (int it = 0; it < max_it; ++it) {
+    bool any = false;
+    for (int j = 0; j < k; ++j) any = any || active[j];
+    if (!any) break;
+    Step st;
+    st.act = active;
+    st.rho = rho;
+    spmm_op(c, c->S, P, k, Q, nullptr);
+    TRY(dots(P, Q, st.sig));
+    st.alpha.assign(k, 0.0);
+    for (int j = 0; j < k; ++j)
+      if (active[j]) st.alpha[j] = rho[j] / st.sig[j];
+    launch_col_axpby(N, k, put(4, st.alpha), P, put(5, ones), X, s);
+    // R, Z, P as advance() recomputes them (Q already holds S P)
+    std::vector<double> ma(k);
+    for (int j = 0; j < k; ++j) ma[j] = -st.alpha[j];
+    launch_col_axpby(N, k, put(0, ma), Q, put(1, ones), R, s);
+    launch_row_div(N, k, R, d, Z, s);
+    std::vector<double> rho_n;
+    TRY(dots(R, Z, rho_n));
+    st.beta.assign(k, 0.0);
+    std::vector<double> pa(k), pb(k);
+    for (int j = 0; j < k; ++j) {
+      if (active[j]) st.beta[j] = rho_n[j] / rho[j];
+      pa[j] = active[j] ? 1.0 : 0.0;
+      pb[j] = active[j] ? st.beta[j] : 1.0;
+    }
+    launch_col_axpby(N, k, put(2, pa), Z, put(3, pb), P, s);
+    for (int j = 0; j < k; ++j)
+      if (active[j]) rho[j] = rho_n[j];
+    steps.push_back(st);
+    if ((int)steps.size() % seg == 0) TRY(checkpoint());
+    TRY(norms(R, rn));
+    for (int j = 0; j < k; ++j) active[j] = active[j] && rn[j] > tol * bn[j];
+  }
+  const int K = (int)steps.size();
+  launch_rows_to_api(N, k, X, X_api, c->int2nat, s);
+  if (iters_host)
+    for (int j = 0; j < k; ++j) {
+      int n = 0;
+      for (const Step &st : steps) n += st.act[j] ? 1 : 0;
+      iters_host[j] = n;
+    }
+  // reverse sweep
+  launch_fill((int64_t)nk, 0.0, Rb, s);
+  launch_fill((int64_t)nk, 0.0, Pb, s);
+  launch_fill(N, 0.0, dbar, s);
+  launch_fill((int64_t)c->n_e * c->n_q, 0.0, g_q, s);
+  std::vector<double> rhobar(k, 0.0);
+  const int nseg = (K + seg - 1) / seg;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int j0 = sg * seg, j1 = std::min(K, j0 + seg);
+    // recompute the segment's iterates from its checkpoint
+    launch_axpby((int64_t)nk, 1.0, ckR[sg], 0.0, segR, s);
+    launch_axpby((int64_t)nk, 1.0, ckP[sg], 0.0, segP, s);
+    for (int j = j0; j < j1; ++j)
+      advance(steps[j], segR + nk * (j - j0), segP + nk * (j - j0), segR + nk * (j + 1 - j0),
+              segP + nk * (j + 1 - j0), false);
+    for (int j = j1 - 1; j >= j0; --j) {
+      const Step &st = steps[j];
+      const double *p = segP + nk * (j - j0), *r1 = segR + nk * (j + 1 - j0);
+      spmm_op(c, c->S, p, k, Q, nullptr);
+      launch_row_div(N, k, r1, d, Z, s);  // z_{j+1}
+      std::vector<double> a(k), betabar, alphabar, t1, t2;
+      for (int i = 0; i < k; ++i) a[i] = st.act[i] ? 1.0 : 0.0;
+      // p_{j+1} = z_{j+1} + beta p_j
+      launch_col_axpby(N, k, put(0, a), Pb, put(1, zeros), Zb, s);
+      TRY(dots(Pb, p, betabar));
+      std::vector<double> pbs(k);
+      for (int i = 0; i < k; ++i) {
+        betabar[i] *= a[i];
+        pbs[i] = st.act[i] ? st.beta[i] : 1.0;
+      }
+      launch_col_axpby(N, k, nullptr, nullptr, put(2, pbs), Pb, s);
+      // beta = rho_{j+1} / rho_j; rho_{j+1} = r_{j+1}.z_{j+1}
+      std::vector<double> rho1b(k), rhojb(k);
+      for (int i = 0; i < k; ++i) {
+        rho1b[i] = st.act[i] ? rhobar[i] + betabar[i] / st.rho[i] : 0.0;
+        rhojb[i] = st.act[i] ? -betabar[i] * st.beta[i] / st.rho[i] : 0.0;
+      }
+      launch_col_axpby(N, k, put(3, rho1b), Z, put(4, ones), Rb, s);
+      launch_col_axpby(N, k, put(5, rho1b), r1, put(6, ones), Zb, s);
+      // z_{j+1} = D^-1 r_{j+1}
+      launch_zbar_back(N, k, Zb, Z, d, Rb, dbar, s);
+      // r_{j+1} = r_j - alpha q; x_{j+1} = x_j + alpha p
+      TRY(dots(Rb, Q, t1));
+      TRY(dots(xb, p, t2));
+      alphabar.assign(k, 0.0);
+      std::vector<double> malpha(k);
+      for (int i = 0; i < k; ++i) {
+        alphabar[i] = st.act[i] ? -t1[i] + t2[i] : 0.0;
+        malpha[i] = -st.alpha[i];
+      }
+      launch_col_axpby(N, k, put(7, malpha), Rb, put(8, zeros), Qb, s);
+      launch_col_axpby(N, k, put(9, st.alpha), xb, put(10, ones), Pb, s);
+      // alpha = rho_j / sigma_j; sigma = p.q
+      std::vector<double> sigb(k);
+      for (int i = 0; i < k; ++i) {
+        rhojb[i] += st.act[i] ? alphabar[i] / st.sig[i] : 0.0;
+        sigb[i] = st.act[i] ? -alphabar[i] * st.alpha[i] / st.sig[i] : 0.0;
+      }
+      launch_col_axpby(N, k, put(11, sigb), Q, put(12, ones), Pb, s);
+      launch_col_axpby(N, k, put(13, sigb), p, put(14, ones), Qb, s);
+      // q = S p: pbar += S qbar, Sbar += qbar p^T -> g
+      spmm_op(c, c->S, Qb, k, T, nullptr);
+      launch_axpby((int64_t)nk, 1.0, T, 1.0, Pb, s);
+      launch_pair_accum(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, Qb, p, k, 1.0, g_q, s);
+      for (int i = 0; i < k; ++i)
+        if (st.act[i]) rhobar[i] = rhojb[i];
+      HIPCHK(hipStreamSynchronize(s));  // the coefficient slots are reused next step
+    }
+  }
+  // start: rho_0 = r_0.z_0, p_0 = z_0, z_0 = D^-1 r_0, r_0 = b - S x_0
+  const double *r0 = ckR[0];
+  launch_row_div(N, k, r0, d, Z, s);
+  launch_col_axpby(N, k, put(0, rhobar), Z, put(1, ones), Rb, s);
+  launch_axpby((int64_t)nk, 1.0, Pb, 0.0, Zb, s);
+  launch_col_axpby(N, k, put(2, rhobar), r0, put(3, ones), Zb, s);
+  launch_zbar_back(N, k, Zb, Z, d, Rb, dbar, s);
+  launch_rows_to_api(N, k, Rb, Bbar_api, c->int2nat, s);
+  launch_pair_accum(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, Rb, X0, k, -1.0, g_q, s);
+  launch_pair_accum(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, nullptr, dbar, 1, 1.0, g_q, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return KS_OK;
+}
+
 extern "C" int ks_block_solve(ks_ctx *c, const double *psi_old, const double *lambda_host, int32_t k,
                               int32_t precision, double *psi_hat, ks_solve_stats *st) {
   if (!c || !psi_old || !lambda_host || !psi_hat) return fail(KS_ERR_ARG, "null argument");
