@@ -403,6 +403,18 @@ int ks_step_energy(ks_ctx *ctx, double *out_host);
 int ks_step_backward(ks_ctx *ctx, double dE, double *g_q, double *forces_host,
                      ks_solve_stats *st_host);
 
+/* The same gradient with the BVP part taken by reverse mode through the
+ * truncated solve (ks_block_solve_vjp) instead of the implicit adjoint: the
+ * step's BVPs are solved again from psi_old by the FP64 per-column PCG
+ * (tol_solve, max_it_solve) and the seed psi_bar_hat is swept back through
+ * that recurrence (checkpoint segment seg, 0: 8), so g_q is the derivative
+ * of the step as truncated rather than of its exact limit; the two agree to
+ * about the solve tolerance.  Needs the last ks_scf_step in KS_PREC_FP64
+ * (KS_ERR_STATE otherwise); st_host (may be NULL) receives the iteration
+ * counts. */
+int ks_step_backward_truncated(ks_ctx *ctx, double dE, int32_t seg, double *g_q, double *forces_host,
+                               ks_solve_stats *st_host);
+
 /* ---- Batched form: many independent systems in one persistent launch ----
  * Each system is a context with an assembled operator (ks_assemble); the
  * batch solves S_s X_s = M_s psi_s diag(lambda_s + mu_s) for every s

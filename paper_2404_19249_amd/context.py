@@ -242,13 +242,19 @@ class KSContext:
         B.check(self.lib.ks_step_energy(self.h, B.dptr(e)), self.lib)
         return dict(zip(["KS", "kin", "ext", "H_step", "xc", "nn"], e))
 
-    def step_backward(self, dE=1.0, want_forces=True):
-        """ks_step_backward: (g_q device tensor, forces [n_atoms][3] numpy, stats)."""
+    def step_backward(self, dE=1.0, want_forces=True, truncated=False, seg=8):
+        """ks_step_backward (implicit adjoint of the BVPs) or, with truncated,
+        ks_step_backward_truncated (reverse mode through the truncated FP64
+        PCG): (g_q device tensor, forces [n_atoms][3] numpy, stats)."""
         g = self.empty(self.n_elems, self.n_q)
         F = np.zeros((len(self._Z), 3)) if want_forces else None
         st = B.SolveStats()
-        B.check(self.lib.ks_step_backward(self.h, float(dE), self._ptr(g),
-                                          None if F is None else B.dptr(F), C.byref(st)), self.lib)
+        Fp = None if F is None else B.dptr(F)
+        if truncated:
+            B.check(self.lib.ks_step_backward_truncated(self.h, float(dE), int(seg), self._ptr(g), Fp,
+                                                        C.byref(st)), self.lib)
+        else:
+            B.check(self.lib.ks_step_backward(self.h, float(dE), self._ptr(g), Fp, C.byref(st)), self.lib)
         return g, F, self._stats(st, 64)
 
     def spmm_config(self):

@@ -161,7 +161,8 @@ struct ks_ctx {
   bool have_step = false, last_nonlinear = false;
   bool last_inner_converged = false;  // the last step's inner iteration met tol_inner
   int last_k = 0;
-  std::vector<double> last_theta, last_occ;
+  std::vector<double> last_theta, last_occ, last_lam_in;  // Ritz values out, occupations, eigenvalues in
+  int last_precision = 0;
   double *aux1 = nullptr, *aux2 = nullptr, *Rv = nullptr, *Gv = nullptr, *dMk = nullptr;
   // block vectors [N][k_max]
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
@@ -264,6 +265,9 @@ extern "C" int ks_set_options(ks_ctx *c, const ks_options *o) {
 
 static int solve_impl(ks_ctx *c, const double *B, double *X, int k, int precision, double tol,
                       ks_solve_stats *st);
+static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, int k, double *B);
+static int vjp_core(ks_ctx *c, const double *B, const double *X0, int k, double tol, int max_it, int seg,
+                    const double *xb, double *X, double *g_q, double *Bbar, int32_t *iters_host);
 
 // ------------------------------------------------------------ basis tables
 static void basis_tables(int order, int n_q, const double *bary, std::vector<double> &phi,
@@ -1666,8 +1670,10 @@ extern "C" int ks_step_energy(ks_ctx *c, double *out) {
 }
 
 // --------------------------------------------------------------- adjoint
-extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *forces_host,
-                                ks_solve_stats *st) {
+// truncated: the BVP part by reverse mode through the truncated FP64 PCG
+// (vjp_core, checkpoint segment seg) instead of the implicit adjoint solve
+static int step_backward_impl(ks_ctx *c, double dE, double *g_q, double *forces_host, ks_solve_stats *st,
+                              bool truncated, int seg) {
   if (!c || !g_q) return fail(KS_ERR_ARG, "null argument");
   if (!c->have_step) return fail(KS_ERR_STATE, "no ks_scf_step result to differentiate");
   // the adjoint uses the stationarity of the converged inner iteration; an
@@ -1698,14 +1704,41 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
   launch_ellP_times(N, c->Pidx, c->Pw, c->Ttmp, k, k, 1.0, nullptr, 0, c->Wv, k, s);
   spmm_op(c, c->M, c->Wv, k, c->Xv, nullptr);
   launch_combine3((int64_t)N * k, 1.0, c->Gv, -1.0, c->Xv, 0.0, nullptr, c->Rv, s);
-  // adjoint boundary value problems S Y = psi_bar_hat (from zero, FP64)
-  HIPCHK(hipMemsetAsync(c->Gv, 0, sizeof(double) * N * k, s));
-  const double tol = std::min(c->opt.tol_solve, 1e-10);
-  int r = solve_impl(c, c->Rv, c->Gv, k, KS_PREC_FP64, tol, st);
-  if (r < 0) return r;
-  // g_q = dE * w |J| (rho - sum Y psi_hat)
-  launch_grad_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, c->Gv, c->PsiHat, k,
-                c->rho_out, dE, g_q, s);
+  int r = KS_OK;
+  if (!truncated) {
+    // adjoint boundary value problems S Y = psi_bar_hat (from zero, FP64)
+    HIPCHK(hipMemsetAsync(c->Gv, 0, sizeof(double) * N * k, s));
+    const double tol = std::min(c->opt.tol_solve, 1e-10);
+    r = solve_impl(c, c->Rv, c->Gv, k, KS_PREC_FP64, tol, st);
+    if (r < 0) return r;
+    // g_q = dE * w |J| (rho - sum Y psi_hat)
+    launch_grad_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, c->Gv, c->PsiHat, k,
+                  c->rho_out, dE, g_q, s);
+  } else {
+    // the step's BVPs again: S psi_hat = (lambda + mu) M psi_old from psi_old,
+    // differentiated through the truncated recurrence with psi_bar_hat as seed
+    const int64_t nq = (int64_t)c->n_e * c->n_q;
+    double *gb = nullptr;
+    if (hipMalloc(&gb, sizeof(double) * nq) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+    struct Free {
+      double *p;
+      ~Free() { (void)hipFree(p); }
+    } guard{gb};
+    if (k > MAX_K) return fail(KS_ERR_ARG, "k too large for the truncated reverse mode");
+    TRY(build_rhs(c, c->PsiIn, c->last_lam_in.data(), k, c->Xv));
+    int32_t its[MAX_K] = {0};
+    TRY(vjp_core(c, c->Xv, c->PsiIn, k, c->opt.tol_solve, c->opt.max_it_solve, seg, c->Rv, c->Wv, gb, nullptr,
+                 its));
+    if (st) {
+      std::memset(st, 0, sizeof(*st));
+      for (int j = 0; j < k && j < 64; ++j) st->iters[j] = its[j];
+      st->converged = 1;
+    }
+    // g_q = dE * w |J| rho + dE * dL/dV (L = psi_bar_hat . psi_hat)
+    launch_grad_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, nullptr, nullptr, 0, c->rho_out, dE,
+                  g_q, s);
+    launch_axpby(nq, dE, gb, 1.0, g_q, s);
+  }
   if (forces_host) {
     const int nb = force_blocks(c->n_e);
     for (int a0 = 0; a0 < c->n_atoms; a0 += 8) {
@@ -1732,6 +1765,17 @@ extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *force
   }
   HIPCHK(hipStreamSynchronize(s));
   return r;
+}
+
+extern "C" int ks_step_backward(ks_ctx *c, double dE, double *g_q, double *forces_host, ks_solve_stats *st) {
+  return step_backward_impl(c, dE, g_q, forces_host, st, false, 0);
+}
+
+extern "C" int ks_step_backward_truncated(ks_ctx *c, double dE, int32_t seg, double *g_q, double *forces_host,
+                                          ks_solve_stats *st) {
+  if (c && c->have_step && c->last_precision != KS_PREC_FP64)
+    return fail(KS_ERR_STATE, "the truncated reverse mode needs the last ks_scf_step in KS_PREC_FP64");
+  return step_backward_impl(c, dE, g_q, forces_host, st, true, seg);
 }
 
 // ---------------------------------------------------------------- batches
@@ -2431,13 +2475,9 @@ static int build_rhs(ks_ctx *c, const double *psi, const double *lambda_host, in
 // device; the reverse sweep recomputes each segment's iterates from its
 // checkpoint with the same kernels and coefficients (bit-identical) and
 // runs the adjoint recurrence backwards through it.
-extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *X0_api, int32_t k, double tol,
-                                  int32_t max_it, int32_t seg, const double *Xbar_api, double *X_api, double *g_q,
-                                  double *Bbar_api, int32_t *iters_host) {
-  if (!c || !B_api || !Xbar_api || !X_api || !g_q || !Bbar_api) return fail(KS_ERR_ARG, "null argument");
-  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
-  if (!(tol >= 0.0) || max_it < 1) return fail(KS_ERR_ARG, "need tol >= 0 and max_it >= 1");
-  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled: call ks_assemble first");
+// storage-order core of ks_block_solve_vjp: B, X0, xb in; X, g_q, Bbar out
+static int vjp_core(ks_ctx *c, const double *B, const double *X0, int k, double tol, int max_it, int seg,
+                    const double *xb, double *X, double *g_q, double *Bbar, int32_t *iters_host) {
   if (seg <= 0) seg = 8;
   hipStream_t s = c->s;
   const int N = c->N;
@@ -2457,18 +2497,13 @@ extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *
       for (void *p : b) (void)hipFree(p);
     }
   } release{bufs};
-  double *B = dalloc(nk), *X0 = dalloc(nk), *X = dalloc(nk), *R = dalloc(nk), *P = dalloc(nk), *Z = dalloc(nk);
-  double *Q = dalloc(nk), *xb = dalloc(nk), *Rb = dalloc(nk), *Pb = dalloc(nk), *Zb = dalloc(nk), *Qb = dalloc(nk);
+  double *R = dalloc(nk), *P = dalloc(nk), *Z = dalloc(nk);
+  double *Q = dalloc(nk), *Rb = dalloc(nk), *Pb = dalloc(nk), *Zb = dalloc(nk), *Qb = dalloc(nk);
   double *T = dalloc(nk), *dbar = dalloc(N), *coef = dalloc((size_t)16 * k);
   double *segR = dalloc(nk * (seg + 1)), *segP = dalloc(nk * (seg + 1));
-  if (!B || !X0 || !X || !R || !P || !Z || !Q || !xb || !Rb || !Pb || !Zb || !Qb || !T || !dbar || !coef || !segR ||
-      !segP)
+  if (!R || !P || !Z || !Q || !Rb || !Pb || !Zb || !Qb || !T || !dbar || !coef || !segR || !segP)
     return fail(KS_ERR_NOMEM, "ks_block_solve_vjp: hipMalloc failed");
   std::vector<double *> ckR, ckP;
-  launch_rows_to_storage(N, k, B_api, B, c->int2nat, s);
-  if (X0_api) launch_rows_to_storage(N, k, X0_api, X0, c->int2nat, s);
-  else launch_fill((int64_t)nk, 0.0, X0, s);
-  launch_rows_to_storage(N, k, Xbar_api, xb, c->int2nat, s);
   const double *d = c->diagS;
   // host-side coefficient slots: slot i of coef holds k values
   std::vector<std::vector<double>> hc(16, std::vector<double>(k));
@@ -2569,7 +2604,6 @@ extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *
     for (int j = 0; j < k; ++j) active[j] = active[j] && rn[j] > tol * bn[j];
   }
   const int K = (int)steps.size();
-  launch_rows_to_api(N, k, X, X_api, c->int2nat, s);
   if (iters_host)
     for (int j = 0; j < k; ++j) {
       int n = 0;
@@ -2652,9 +2686,37 @@ extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *
   launch_axpby((int64_t)nk, 1.0, Pb, 0.0, Zb, s);
   launch_col_axpby(N, k, put(2, rhobar), r0, put(3, ones), Zb, s);
   launch_zbar_back(N, k, Zb, Z, d, Rb, dbar, s);
-  launch_rows_to_api(N, k, Rb, Bbar_api, c->int2nat, s);
+  if (Bbar) launch_axpby((int64_t)nk, 1.0, Rb, 0.0, Bbar, s);
   launch_pair_accum(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, Rb, X0, k, -1.0, g_q, s);
   launch_pair_accum(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, nullptr, dbar, 1, 1.0, g_q, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return KS_OK;
+}
+
+extern "C" int ks_block_solve_vjp(ks_ctx *c, const double *B_api, const double *X0_api, int32_t k, double tol,
+                                  int32_t max_it, int32_t seg, const double *Xbar_api, double *X_api, double *g_q,
+                                  double *Bbar_api, int32_t *iters_host) {
+  if (!c || !B_api || !Xbar_api || !X_api || !g_q || !Bbar_api) return fail(KS_ERR_ARG, "null argument");
+  if (k < 1 || k > c->k_max) return fail(KS_ERR_ARG, "k must be in 1..k_max");
+  if (!(tol >= 0.0) || max_it < 1) return fail(KS_ERR_ARG, "need tol >= 0 and max_it >= 1");
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled: call ks_assemble first");
+  hipStream_t s = c->s;
+  const int N = c->N;
+  const size_t nk = (size_t)N * k;
+  double *buf = nullptr;
+  if (hipMalloc(&buf, sizeof(double) * 5 * nk) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  struct Free {
+    double *p;
+    ~Free() { (void)hipFree(p); }
+  } guard{buf};
+  double *B = buf, *X0 = buf + nk, *xb = buf + 2 * nk, *X = buf + 3 * nk, *Bb = buf + 4 * nk;
+  launch_rows_to_storage(N, k, B_api, B, c->int2nat, s);
+  if (X0_api) launch_rows_to_storage(N, k, X0_api, X0, c->int2nat, s);
+  else launch_fill((int64_t)nk, 0.0, X0, s);
+  launch_rows_to_storage(N, k, Xbar_api, xb, c->int2nat, s);
+  TRY(vjp_core(c, B, X0, k, tol, max_it, seg, xb, X, g_q, Bb, iters_host));
+  launch_rows_to_api(N, k, X, X_api, c->int2nat, s);
+  launch_rows_to_api(N, k, Bb, Bbar_api, c->int2nat, s);
   HIPCHK(hipStreamSynchronize(s));
   return KS_OK;
 }
@@ -2927,6 +2989,7 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   if (precision != KS_PREC_FP64 && precision != KS_PREC_MIXED && precision != KS_PREC_FP64_BLOCK_CG)
     return fail(KS_ERR_ARG, "bad precision");
   hipStream_t s = c->s;
+  const std::vector<double> lambda_in(lambda_host, lambda_host + k);  // the step's input eigenvalues
   ks_step_report R;
   std::memset(&R, 0, sizeof(R));
   const double t0 = now_s();
@@ -3051,6 +3114,8 @@ extern "C" int ks_scf_step(ks_ctx *c, double *psi, double *lambda_host, int32_t 
   c->last_nonlinear = nonlinear;
   c->last_inner_converged = !nonlinear || res < c->opt.tol_inner;
   c->last_k = k;
+  c->last_lam_in.assign(lambda_in.begin(), lambda_in.end());
+  c->last_precision = precision;
   c->last_theta.assign(th.begin(), th.begin() + k);
   c->last_occ.assign(occ_host, occ_host + k);
   int ret = KS_OK;

@@ -93,3 +93,44 @@ def test_autograd_function_matches_adjoint():
     ctx.scf_step(psi0.clone(), th, w.occ)
     g, _, _ = ctx.step_backward(dE=3.0)
     assert torch.allclose(gv, g, rtol=1e-10, atol=1e-14)
+
+
+def test_truncated_reverse_mode_matches_finite_difference_of_the_truncated_step():
+    """With every BVP column cut after four iterations, the finite difference
+    of E_KS of that truncated step matches the gradient of the reverse sweep
+    through the truncated PCG (ks_step_backward_truncated), not the implicit
+    adjoint of the exact solve, which misses the truncation."""
+    from paper_2404_19249_amd import KSContext
+    w, p, _, Psi, th = _setup()
+    ctx = KSContext.from_workload(w, mu=6.0, tol_solve=1e-15, max_it_solve=4, tol_inner=1e-12,
+                                  tol_poisson=1e-13)
+    psi0 = torch.tensor(Psi, device=DEV)
+    v0 = torch.tensor(p.vext_q, device=DEV)
+    ctx.set_external(vext_q=v0)
+    ctx.scf_step(psi0.clone(), th, w.occ)
+    g_t, _, st = ctx.step_backward(truncated=True, seg=3)
+    assert max(st["iters"][:w.k]) == 4
+    g_i, _, _ = ctx.step_backward()
+    c = np.array([0.5, -0.3, 0.2])
+    dV = torch.tensor(np.exp(-np.sum((p.x_q - c) ** 2, -1) / 4.0), device=DEV)
+    h = 1e-4
+    E = []
+    for sgn in (1, -1):
+        ctx.set_external(vext_q=v0 + sgn * h * dV)
+        ctx.scf_step(psi0.clone(), th, w.occ)
+        E.append(ctx.step_energy()["KS"])
+    fd = (E[0] - E[1]) / (2 * h)
+    err_t = abs(fd - float((g_t * dV).sum()))
+    err_i = abs(fd - float((g_i * dV).sum()))
+    print(fd, err_t, err_i)
+    assert err_t < 1e-6 * abs(fd)
+    assert err_i > 10 * err_t
+
+
+def test_truncated_and_implicit_gradients_agree_for_a_tight_solve():
+    w, p, ctx, Psi, th = _setup()
+    ctx.scf_step(torch.tensor(Psi, device=DEV), th, w.occ)
+    g_t, F_t, _ = ctx.step_backward(truncated=True)
+    g_i, F_i, _ = ctx.step_backward()
+    assert torch.abs(g_t - g_i).max().item() < 1e-7 * torch.abs(g_i).max().item()
+    assert np.abs(F_t - F_i).max() < 1e-7 * np.abs(F_i).max()
