@@ -11,13 +11,16 @@ the paper is silent or ambiguous the reading taken is stated where it is
 used.  Library primitives used as single steps: scipy.sparse products and
 COO->CSR summation (assembly is a sum over elements), numpy.linalg.eigh for
 the small dense eigenproblems, numpy.linalg.solve for the Anderson normal
-equations.
+equations; element-level shape derivatives by complex-step differentiation
+(numpy.linalg.det and inv on complex arrays).
 
 Parity status: every function is pinned by a CPU test (quadrature exactness,
 closed-form element matrices, global invariants, the hydrogen closed form,
 Gaussian Poisson and multipole closed forms, XC derivative identities,
 brute-force dense eigensolves on tiny meshes, the nested-mesh identity,
-Anderson's least-squares property and finite differences for the adjoint;
+Anderson's least-squares property and finite differences for the adjoint,
+for the reverse mode through the truncated PCG and for the derivative with
+respect to the mesh vertices (Pulay terms; rigid-motion invariance too);
 the Hessian metric and node mover by exact recovery of linear and quadratic
 functions, the eigenvalue clamp, fixed points and energy descent),
 except the nonlinear inner SCF's physical value, which is pinned only through

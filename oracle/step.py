@@ -124,6 +124,18 @@ class KSProblem:
             self.P = interpolation_in_mesh(self.coords[I], self.coarse.coords, self.coarse.elems,
                                            self.coarse.dirichlet)
 
+    def moved(self, coords):
+        """Copy of the problem with the mesh nodes at `coords` (same
+        connectivity) and the same coarse interpolation matrix P: the coarse
+        space is carried along by the moving mesh."""
+        import copy
+        q = copy.copy(self)
+        q.coords = np.asarray(coords, dtype=np.float64)
+        P = self.P
+        q.setup()
+        q.P = P
+        return q
+
     def with_external(self, vext_q=None, R=None):
         """Copy of the problem with another external potential at the
         quadrature points (or nuclei moved to R, which also changes E_nn);
@@ -290,7 +302,9 @@ class StepResult:
 
 
 def ks_scf_step(prob, Psi, lam, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-12,
-                max_inner=50, anderson_depth=5, anderson_beta=0.7, want_eks=True):
+                max_inner=50, anderson_depth=5, anderson_beta=0.7, want_eks=True, w_B=None):
+    """One step; w_B (optional) replaces the multipole boundary data of the
+    input density, for steps whose boundary data are held fixed."""
     Psi = np.asarray(Psi, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
     k = Psi.shape[1]
@@ -298,7 +312,7 @@ def ks_scf_step(prob, Psi, lam, tol_solve=1e-8, tol_inner=1e-8, tol_poisson=1e-1
     nonlinear = prob.hartree or prob.xc_mode != "none"
     # 1. Hamiltonian of the step's input density
     rho_l = prob.density(Psi)
-    w_B = prob.boundary_data(rho_l)
+    w_B = prob.boundary_data(rho_l) if w_B is None else np.asarray(w_B, dtype=np.float64)
     VH_l, _ = prob.hartree_nodes(rho_l, w_B, tol_poisson)
     eps_l, vxc_l = lda_xc(rho_l, prob.xc_mode)
     veff = prob.vext_q + prob.at_quad(VH_l) + vxc_l
