@@ -519,6 +519,20 @@ def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     R0 = np.array(w.atoms.R, dtype=np.float64)
+    # mesh-motion (Pulay) terms: nodes follow the nuclei with Gaussian weights
+    d2 = np.sum((np.asarray(w.mesh.coords)[:, None, :] - R0[None, :, :]) ** 2, axis=-1)
+    motion = torch.tensor(np.exp(-d2 / 4.0), device="cuda")
+    del d2
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    dX, _, Fm, st_m = ctx.step_backward_mesh(dE=1.0, motion=motion)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    del motion
+    pulay = {"mesh_backward_s": t4 - t3, "motion": "Gaussian weights exp(-|x - R_a|^2 / 4)",
+             "max_abs_dE_dX": float(dX.abs().max()),
+             "mesh_term_over_fixed_mesh_force": float(np.abs(Fm - F).max() / np.abs(F).max())}
+    del dX
     E = []
     for sgn in (1, -1):
         R = R0.copy()
@@ -537,7 +551,7 @@ def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
            "res_inner": rep["res_inner"], "adjoint_converged": bool(st["converged"]),
            "force_check": {"atom": atom, "axis": axis, "h": h, "adjoint": f_adj, "central_fd": f_fd,
                            "rel_err": abs(f_adj - f_fd) / max(abs(f_fd), 1e-300)},
-           "grad_q_values": int(g.numel())}
+           "grad_q_values": int(g.numel()), "pulay": pulay}
     ctx.close()
     return out
 

@@ -415,6 +415,29 @@ int ks_step_backward(ks_ctx *ctx, double dE, double *g_q, double *forces_host,
 int ks_step_backward_truncated(ks_ctx *ctx, double dE, int32_t seg, double *g_q, double *forces_host,
                                ks_solve_stats *st_host);
 
+/* Mesh-motion (Pulay) terms: the derivative of the most recent ks_scf_step's
+ * E_KS with respect to the vertex coordinates of the fine mesh, and nuclear
+ * forces for a mesh whose nodes follow the nuclei (the node moves of
+ * Algorithm 2, Sec. 3.2, made differentiable).  The step's inputs are held
+ * fixed: the nodal coefficients of psi^l, lambda^l, rho^l at the quadrature
+ * points, the Hartree boundary data w_B and the matrix of I_H^h (the coarse
+ * space moves with the mesh).  Besides the adjoint block solve of
+ * ks_step_backward it takes five Poisson solves (V_H of rho^l and of rho
+ * with and without w_B, two adjoint loads) and one element pass of the
+ * closed-form shape derivatives of the stiffness, mass and potential forms.
+ *   dEdX    device [n_nodes][3] (natural node order), dE * dE_KS/dX_n; zero
+ *           at P2 edge nodes (the geometry is the vertices'); may be NULL
+ *           when motion is given
+ *   motion  device [n_nodes][n_atoms] or NULL: node n moves by
+ *           motion[n][a] dR_a when nucleus a moves by dR_a; then forces_host
+ *           = F (fixed mesh, as ks_step_backward) - sum_n motion[n][a] dEdX_n
+ *   g_q     device [n_elems][n_q] or NULL; forces_host [n_atoms][3], needed
+ *           with motion
+ * KS_ERR_STATE as ks_step_backward, and when V_ext was given as a field
+ * (ks_set_external with vext_q: its gradient in x is unknown). */
+int ks_step_backward_mesh(ks_ctx *ctx, double dE, const double *motion, double *dEdX, double *g_q,
+                          double *forces_host, ks_solve_stats *st_host);
+
 /* ---- Batched form: many independent systems in one persistent launch ----
  * Each system is a context with an assembled operator (ks_assemble); the
  * batch solves S_s X_s = M_s psi_s diag(lambda_s + mu_s) for every s

@@ -135,6 +135,8 @@ _SIGS = {
                                        _P, _P]),
     "ks_step_backward_truncated": (C.c_int, [_P, C.c_double, C.c_int32, _P, C.POINTER(C.c_double),
                                              C.POINTER(SolveStats)]),
+    "ks_step_backward_mesh": (C.c_int, [_P, C.c_double, _P, _P, _P, C.POINTER(C.c_double),
+                                        C.POINTER(SolveStats)]),
     "ks_block_solve_vjp": (C.c_int, [_P, _P, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32, _P, _P, _P, _P,
                                      C.POINTER(C.c_int32)]),
     "ks_stream_probe": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), _P]),

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIBDIR = os.path.join(HERE, "_lib")
-SOURCES = ["ks_api.hip", "assemble.hip", "fields.hip", "spmm_cg.hip", "dense.hip", "adjoint.hip", "batch.hip", "multigrid.hip", "nonnested.hip", "eig_noalloc.hip", "probe.hip", "metric.hip"]
+SOURCES = ["ks_api.hip", "assemble.hip", "fields.hip", "spmm_cg.hip", "dense.hip", "adjoint.hip", "batch.hip", "multigrid.hip", "nonnested.hip", "eig_noalloc.hip", "probe.hip", "metric.hip", "pulay.hip"]
 ARCH = os.environ.get("KS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -257,6 +257,21 @@ class KSContext:
             B.check(self.lib.ks_step_backward(self.h, float(dE), self._ptr(g), Fp, C.byref(st)), self.lib)
         return g, F, self._stats(st, 64)
 
+    def step_backward_mesh(self, dE=1.0, motion=None):
+        """ks_step_backward_mesh: (dE/dX device [n_nodes][3], g_q device
+        tensor, forces [n_atoms][3] numpy, stats).  With motion (device
+        [n_nodes][n_atoms]: node n moves by motion[n][a] dR_a) the forces
+        carry the mesh-motion terms; without it they are the fixed-mesh
+        forces."""
+        dX = self.empty(self.n_nodes, 3)
+        g = self.empty(self.n_elems, self.n_q)
+        F = np.zeros((len(self._Z), 3))
+        st = B.SolveStats()
+        mp = None if motion is None else self._ptr(motion.contiguous())
+        B.check(self.lib.ks_step_backward_mesh(self.h, float(dE), mp, self._ptr(dX), self._ptr(g), B.dptr(F),
+                                               C.byref(st)), self.lib)
+        return dX, g, F, self._stats(st, 64)
+
     def spmm_config(self):
         """ks_spmm_config: the SpMM-phase kernel of each solver."""
         o = (C.c_int32 * 9)()

@@ -337,6 +337,33 @@ void launch_zbar_back(int N, int k, const double *Zbar, const double *Z, const d
 void launch_pair_accum(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi, const double *w,
                        const double *absdet, const double *A, const double *B, int k, double scale, double *g,
                        hipStream_t s);
+
+// ------------------------------------------- mesh-vertex derivative (pulay.hip)
+// pairs of the element forms: n interior block pairs (u[p], v[p]) [N][ld]
+// with per-column weights coef[p][i] = {wK, wM}; n_nodal pairs of nodal
+// fields over all nodes with stiffness weight nw[p]
+struct MeshGradPairs {
+  int n = 0, n_nodal = 0;
+  const double *u[4] = {}, *v[4] = {};
+  int ldu[4] = {}, ldv[4] = {};
+  const double *nu[3] = {}, *nv[3] = {};
+  double nw[3] = {};
+};
+void launch_pair_q(const int32_t *edof, int n_loc, int n_e, int n_q, const double *phi, const double *A, int lda,
+                   const double *B, int ldb, int k, double *out, hipStream_t s);
+void launch_pulay_fields(int64_t n, const double *rho, const double *rho_l, const double *eps, const double *vxc_l,
+                         const double *gam, const double *V0, const double *Vbc, const double *VHl, const double *W2,
+                         double *F, double *G, hipStream_t s);
+// per element [n_e][4 vertices][3]: scale * d/dX of the element forms
+bool launch_mesh_grad(const double *coords, const int32_t *elems, const int32_t *edof, int n_loc, int n_e, int n_q,
+                      const double *phi, const double *dphi, const double *w, const double *bary,
+                      const MeshGradPairs &pr, const double *coef, int k, const double *F, const double *G,
+                      int n_atoms, const double *Z, const double *R, double scale, double *out, hipStream_t s);
+void launch_vertex_gather(int n_nodes, const int32_t *ptr, const int32_t *rec, const double *per_elem, double *out,
+                          hipStream_t s);
+int motion_blocks(int n);
+void launch_motion_partials(int n_nodes, const double *Wm, int n_atoms, int a0, int na, const double *g, double *part,
+                            hipStream_t s);
 }  // namespace ks
 
 namespace ks {

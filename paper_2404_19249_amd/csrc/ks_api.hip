@@ -164,6 +164,9 @@ struct ks_ctx {
   std::vector<double> last_theta, last_occ, last_lam_in;  // Ritz values out, occupations, eigenvalues in
   int last_precision = 0;
   double *aux1 = nullptr, *aux2 = nullptr, *Rv = nullptr, *Gv = nullptr, *dMk = nullptr;
+  bool vext_atomic = true;  // V_ext is the nuclear potential of (hZ, hR), not a given field
+  // per node its (element, local vertex) records 4 e + v (mesh-vertex derivative)
+  int32_t *vinc_ptr = nullptr, *vinc_rec = nullptr;
   // block vectors [N][k_max]
   double *Bv = nullptr, *Xv = nullptr, *Wv = nullptr, *PsiHat = nullptr, *PsiNew = nullptr,
          *occ_d = nullptr, *scal = nullptr;
@@ -1611,8 +1614,10 @@ extern "C" int ks_set_external(ks_ctx *c, const double *vext_q, const double *R_
       }
     launch_vext(c->coords, c->elems, c->n_loc, c->n_e, c->n_q, c->qbary, c->n_atoms, c->dZ, c->dR,
                 c->vext_q, c->s);
+    c->vext_atomic = true;
   } else if (vext_q) {
     HIPCHK(hipMemcpyAsync(c->vext_q, vext_q, sizeof(double) * c->n_e * c->n_q, hipMemcpyDeviceToDevice, c->s));
+    c->vext_atomic = false;
   } else {
     return fail(KS_ERR_ARG, "nothing to set");
   }
@@ -1670,10 +1675,141 @@ extern "C" int ks_step_energy(ks_ctx *c, double *out) {
 }
 
 // --------------------------------------------------------------- adjoint
+// mesh-vertex derivative of the step (ks_step_backward_mesh): the output
+// dE/dX and optionally the node motion that follows the nuclei
+struct MeshReq {
+  const double *motion = nullptr;  // device [n_nodes][n_atoms] or null
+  double *dEdX = nullptr;          // device [n_nodes][3]
+};
+
+// per node the records 4 e + v of the elements that have it as vertex v,
+// in element order (built once per context)
+static int vertex_incidence(ks_ctx *c) {
+  if (c->vinc_ptr) return KS_OK;
+  const int ne = c->n_e, nl = c->n_loc, nn = c->n_nodes;
+  std::vector<int32_t> el((size_t)ne * nl);
+  HIPCHK(hipMemcpyAsync(el.data(), c->elems, sizeof(int32_t) * el.size(), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  std::vector<int32_t> ptr((size_t)nn + 1, 0);
+  for (int e = 0; e < ne; ++e)
+    for (int v = 0; v < 4; ++v) ptr[(size_t)el[(size_t)e * nl + v] + 1]++;
+  for (int n = 0; n < nn; ++n) ptr[n + 1] += ptr[n];
+  std::vector<int32_t> rec((size_t)std::max(ptr[nn], 1)), pos(ptr.begin(), ptr.end() - 1);
+  for (int e = 0; e < ne; ++e)
+    for (int v = 0; v < 4; ++v) rec[pos[el[(size_t)e * nl + v]]++] = 4 * e + v;
+  int32_t *dp = nullptr, *dr = nullptr;
+  TRY(c->alloc(&dp, ptr.size()));
+  TRY(c->alloc(&dr, rec.size()));
+  HIPCHK(hipMemcpyAsync(dp, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(dr, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  c->vinc_ptr = dp;
+  c->vinc_rec = dr;
+  return KS_OK;
+}
+
+// dE/dX at every node (device [n_nodes][3], scaled by dE) for the step just
+// differentiated: Y solves the adjoint BVPs, PC = P G^-1 P^T psi_bar_tilde.
+// Terms (inputs, boundary data and the matrix of I_H^h held fixed):
+//   stiffness pairs  (psi, psi) f/2, (Y, psi_hat) -1/2, (V_0, V_0) -1/(8 pi),
+//                    (W, V_bc) -1, (W2, V_H^l) +1;
+//   mass pairs       (psi, psi) -f theta, (Y, psi_hat) -mu, (PC, psi_tilde) -1,
+//                    (Y, psi^l) lambda^l + mu;
+//   fixed field      F = rho eps - gam V_xc^l + rho V_0 + (rho - rho^l/2) V_bc
+//                        - gam V_H^l - 4 pi rho^l W2,   gam = sum_i Y_i psi_hat_i;
+//   moving V_ext     with weight rho - gam;
+// V_0 = V_H[rho_out] with zero boundary values, V_bc the lift of w_B,
+// V_H^l = V_H[rho^l] with w_B, K_II W = <rho - rho^l/2, phi>, K_II W2 = <gam, phi>.
+static int mesh_gradient(ks_ctx *c, double dE, const double *PC, const double *Y, double *dEdX) {
+  hipStream_t s = c->s;
+  const int k = c->last_k, nH = c->N_H, nn = c->n_nodes;
+  const int64_t nqt = (int64_t)c->n_e * c->n_q;
+  TRY(vertex_incidence(c));
+  DevBuf tmp;
+  auto get = [&](int64_t n) -> double * {
+    void *q = nullptr;
+    if (hipMalloc(&q, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess) return nullptr;
+    tmp.ptrs.push_back(q);
+    return static_cast<double *>(q);
+  };
+  double *gam = get(nqt), *eps = get(nqt), *vxl = get(nqt), *scr = get(nqt), *F = get(nqt), *G = get(nqt),
+         *per = get((int64_t)c->n_e * 12), *coef = get(8 * (int64_t)k);
+  if (!gam || !eps || !vxl || !scr || !F || !G || !per || !coef) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  launch_pair_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, Y, k, c->PsiHat, k, k, gam, s);
+  launch_xc(nqt, c->rho_out, c->opt.xc_mode, eps, scr, s);
+  launch_xc(nqt, c->rho_l, c->opt.xc_mode, scr, vxl, s);
+  MeshGradPairs pr;
+  double *V0q = nullptr, *Vbcq = nullptr, *VHlq = nullptr, *W2q = nullptr;
+  if (c->opt.hartree_mode != KS_HARTREE_OFF) {
+    double *V0 = get(nn), *Vbc = get(nn), *VHl = get(nn), *W = get(nn), *W2 = get(nn), *wBs = get(c->NB);
+    V0q = get(nqt);
+    Vbcq = get(nqt);
+    VHlq = get(nqt);
+    W2q = get(nqt);
+    if (!V0 || !Vbc || !VHl || !W || !W2 || !wBs || !V0q || !Vbcq || !VHlq || !W2q)
+      return fail(KS_ERR_NOMEM, "hipMalloc failed");
+    const int64_t nb = std::max(1, c->NB);
+    HIPCHK(hipMemcpyAsync(wBs, c->wB, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+    struct RestoreWB {  // the step's boundary data are back in place on every exit
+      ks_ctx *c;
+      const double *src;
+      int64_t n;
+      ~RestoreWB() {
+        (void)hipMemcpyAsync(c->wB, src, sizeof(double) * n, hipMemcpyDeviceToDevice, c->s);
+        c->vh_warm = false;
+      }
+    } restore{c, wBs, nb};
+    auto solve = [&](const double *f, double *nodal, double *atq) -> int {
+      c->vh_warm = false;
+      int it = 0;
+      const int r = hartree_solve(c, f, &it);
+      if (r < 0) return r;
+      HIPCHK(hipMemcpyAsync(nodal, c->vh_nodes, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+      if (atq) HIPCHK(hipMemcpyAsync(atq, c->vh_q, sizeof(double) * nqt, hipMemcpyDeviceToDevice, s));
+      return KS_OK;
+    };
+    const double f4pi = 1.0 / (4.0 * M_PI);
+    TRY(solve(c->rho_l, VHl, VHlq));
+    launch_fill(nqt, 0.0, scr, s);
+    TRY(solve(scr, Vbc, Vbcq));
+    launch_fill(nb, 0.0, c->wB, s);
+    TRY(solve(c->rho_out, V0, V0q));
+    launch_combine3(nqt, f4pi, c->rho_out, -0.5 * f4pi, c->rho_l, 0.0, nullptr, scr, s);
+    TRY(solve(scr, W, nullptr));
+    launch_combine3(nqt, f4pi, gam, 0.0, nullptr, 0.0, nullptr, scr, s);
+    TRY(solve(scr, W2, W2q));
+    pr.n_nodal = 3;
+    pr.nu[0] = V0, pr.nv[0] = V0, pr.nw[0] = -1.0 / (8.0 * M_PI);
+    pr.nu[1] = W, pr.nv[1] = Vbc, pr.nw[1] = -1.0;
+    pr.nu[2] = W2, pr.nv[2] = VHl, pr.nw[2] = 1.0;
+  }
+  launch_pulay_fields(nqt, c->rho_out, c->rho_l, eps, vxl, gam, V0q, Vbcq, VHlq, W2q, F, G, s);
+  std::vector<double> cf((size_t)8 * k);
+  for (int i = 0; i < k; ++i) {
+    const double f = c->last_occ[i];
+    cf[(0 * k + i) * 2] = 0.5 * f, cf[(0 * k + i) * 2 + 1] = -f * c->last_theta[i];
+    cf[(1 * k + i) * 2] = -0.5, cf[(1 * k + i) * 2 + 1] = -c->mu;
+    cf[(2 * k + i) * 2] = 0.0, cf[(2 * k + i) * 2 + 1] = -1.0;
+    cf[(3 * k + i) * 2] = 0.0, cf[(3 * k + i) * 2 + 1] = c->last_lam_in[i] + c->mu;
+  }
+  HIPCHK(hipMemcpyAsync(coef, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice, s));
+  pr.n = 4;
+  pr.u[0] = c->PsiNew, pr.v[0] = c->PsiNew, pr.ldu[0] = k, pr.ldv[0] = k;
+  pr.u[1] = Y, pr.v[1] = c->PsiHat, pr.ldu[1] = k, pr.ldv[1] = k;
+  pr.u[2] = PC, pr.v[2] = c->Z + nH, pr.ldu[2] = k, pr.ldv[2] = c->mp;
+  pr.u[3] = Y, pr.v[3] = c->PsiIn, pr.ldu[3] = k, pr.ldv[3] = k;
+  if (!launch_mesh_grad(c->coords, c->elems, c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->dphi, c->qw, c->qbary,
+                        pr, coef, k, F, G, c->n_atoms, c->dZ, c->dR, dE, per, s))
+    return fail(KS_ERR_ARG, "no mesh-derivative kernel for this element order and quadrature");
+  launch_vertex_gather(nn, c->vinc_ptr, c->vinc_rec, per, dEdX, s);
+  HIPCHK(hipStreamSynchronize(s));  // before the temporaries are freed
+  return KS_OK;
+}
+
 // truncated: the BVP part by reverse mode through the truncated FP64 PCG
 // (vjp_core, checkpoint segment seg) instead of the implicit adjoint solve
 static int step_backward_impl(ks_ctx *c, double dE, double *g_q, double *forces_host, ks_solve_stats *st,
-                              bool truncated, int seg) {
+                              bool truncated, int seg, const MeshReq *mesh = nullptr) {
   if (!c || !g_q) return fail(KS_ERR_ARG, "null argument");
   if (!c->have_step) return fail(KS_ERR_STATE, "no ks_scf_step result to differentiate");
   // the adjoint uses the stationarity of the converged inner iteration; an
@@ -1706,6 +1842,16 @@ static int step_backward_impl(ks_ctx *c, double dE, double *g_q, double *forces_
   launch_combine3((int64_t)N * k, 1.0, c->Gv, -1.0, c->Xv, 0.0, nullptr, c->Rv, s);
   int r = KS_OK;
   if (!truncated) {
+    // P G^-1 P^T psi_bar_tilde (in Wv, which the solve overwrites) for the mesh terms
+    DevBuf pcb;
+    double *PC = nullptr;
+    if (mesh) {
+      void *q = nullptr;
+      if (hipMalloc(&q, sizeof(double) * N * k) != hipSuccess) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+      pcb.ptrs.push_back(q);
+      PC = static_cast<double *>(q);
+      HIPCHK(hipMemcpyAsync(PC, c->Wv, sizeof(double) * N * k, hipMemcpyDeviceToDevice, s));
+    }
     // adjoint boundary value problems S Y = psi_bar_hat (from zero, FP64)
     HIPCHK(hipMemsetAsync(c->Gv, 0, sizeof(double) * N * k, s));
     const double tol = std::min(c->opt.tol_solve, 1e-10);
@@ -1714,6 +1860,7 @@ static int step_backward_impl(ks_ctx *c, double dE, double *g_q, double *forces_
     // g_q = dE * w |J| (rho - sum Y psi_hat)
     launch_grad_q(c->edof, c->n_loc, c->n_e, c->n_q, c->phi, c->qw, c->absdet, c->Gv, c->PsiHat, k,
                   c->rho_out, dE, g_q, s);
+    if (mesh) TRY(mesh_gradient(c, dE, PC, c->Gv, mesh->dEdX));
   } else {
     // the step's BVPs again: S psi_hat = (lambda + mu) M psi_old from psi_old,
     // differentiated through the truncated recurrence with psi_bar_hat as seed
@@ -1762,6 +1909,18 @@ static int step_backward_impl(ks_ctx *c, double dE, double *g_q, double *forces_
         const double r3 = r2 * std::sqrt(r2);
         for (int t = 0; t < 3; ++t) forces_host[3 * a + t] += dE * c->hZ[a] * c->hZ[b] * d[t] / r3;
       }
+    // nodes that follow the nuclei: F_a -= sum_v motion[v][a] dE/dX_v
+    if (mesh && mesh->motion) {
+      const int nb = motion_blocks(c->n_nodes);
+      for (int a0 = 0; a0 < c->n_atoms; a0 += 8) {
+        const int na = std::min(8, c->n_atoms - a0);
+        launch_motion_partials(c->n_nodes, mesh->motion, c->n_atoms, a0, na, mesh->dEdX, c->redpart, s);
+        double f[24];
+        TRY(reduce_small(c, c->redpart, nb, 24, f));
+        for (int a = 0; a < na; ++a)
+          for (int d = 0; d < 3; ++d) forces_host[3 * (a0 + a) + d] -= f[3 * a + d];
+      }
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   return r;
@@ -1776,6 +1935,27 @@ extern "C" int ks_step_backward_truncated(ks_ctx *c, double dE, int32_t seg, dou
   if (c && c->have_step && c->last_precision != KS_PREC_FP64)
     return fail(KS_ERR_STATE, "the truncated reverse mode needs the last ks_scf_step in KS_PREC_FP64");
   return step_backward_impl(c, dE, g_q, forces_host, st, true, seg);
+}
+
+extern "C" int ks_step_backward_mesh(ks_ctx *c, double dE, const double *motion, double *dEdX, double *g_q,
+                                     double *forces_host, ks_solve_stats *st) {
+  if (!c || (!dEdX && !motion)) return fail(KS_ERR_ARG, "null argument: give dEdX, motion or both");
+  if (motion && !forces_host) return fail(KS_ERR_ARG, "motion given without forces_host");
+  if (!c->vext_atomic)
+    return fail(KS_ERR_STATE, "V_ext was set as a field; the mesh derivative needs the nuclear potential");
+  DevBuf tmp;
+  auto get = [&](int64_t n) -> double * {
+    void *q = nullptr;
+    if (hipMalloc(&q, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess) return nullptr;
+    tmp.ptrs.push_back(q);
+    return static_cast<double *>(q);
+  };
+  MeshReq m;
+  m.motion = motion;
+  m.dEdX = dEdX ? dEdX : get(3 * (int64_t)c->n_nodes);
+  if (!g_q) g_q = get((int64_t)c->n_e * c->n_q);
+  if (!m.dEdX || !g_q) return fail(KS_ERR_NOMEM, "hipMalloc failed");
+  return step_backward_impl(c, dE, g_q, forces_host, st, false, 0, &m);
 }
 
 // ---------------------------------------------------------------- batches
