@@ -222,18 +222,16 @@ void launch_assemble_potential(const int32_t *list, int count, int n_loc, int n_
 // block are visited longest incidence list first (rperm), so that the rows
 // of one wavefront have similar trip counts.  out = base + M[V] over the
 // interior pattern (base may be null), out32 = (float) out (may be null).
+// At most 96 VGPRs (5 waves per SIMD): the kernel waits on its gathers, and
+// the LDS image of the block's rows allows about ten waves per CU.
 template <int NLOC, int NQ>
-__global__ void __launch_bounds__(ASM_ROWS) k_assemble_rows(int N, const int32_t *__restrict__ rowptr,
-                                                            const int32_t *__restrict__ incptr,
-                                                            const IncRec<NLOC> *__restrict__ inc,
-                                                            const uint8_t *__restrict__ rperm,
-                                                            const double *__restrict__ absdet,
-                                                            const double *__restrict__ phiq,
-                                                            const double *__restrict__ phib,
-                                                            const double *__restrict__ w,
-                                                            const double *__restrict__ V,
-                                                            const double *__restrict__ base,
-                                                            double *__restrict__ out, float *__restrict__ out32) {
+__global__ void __launch_bounds__(ASM_ROWS) __attribute__((amdgpu_waves_per_eu(5)))
+k_assemble_rows(int N, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ incptr,
+                const IncRec<NLOC> *__restrict__ inc, const uint8_t *__restrict__ rperm,
+                const double *__restrict__ absdet, const double *__restrict__ phiq,
+                const double *__restrict__ phib, const double *__restrict__ w,
+                const double *__restrict__ V, const double *__restrict__ base,
+                double *__restrict__ out, float *__restrict__ out32) {
   extern __shared__ double s_acc[];
   __shared__ double s_wphi[NQ * NLOC];  // w_q phi_a(q)
   // workgroups are dealt to the 8 XCDs round robin: give each XCD a
@@ -252,56 +250,40 @@ __global__ void __launch_bounds__(ASM_ROWS) k_assemble_rows(int N, const int32_t
     const int row = r0 + rperm[r0 + threadIdx.x];
     double *acc = s_acc + (rowptr[row] - v0);
     const int jb = incptr[row], j1 = incptr[row + 1];
-    // two-deep pipeline: while incidence j is computed, the values of j + 1
-    // (|J|, V at the points) and the record of j + 2 are in flight
-    IncRec<NLOC> rc, rn;
-    double dj = 0.0, vq[NQ];
-    if (jb < j1) {
-      rc = inc[jb];
-      if (jb + 1 < j1) rn = inc[jb + 1];
-      const int e = (int)(rc.ea >> 4);
-      dj = absdet[e];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) vq[q] = V[(int64_t)e * NQ + q];
-    }
+    // quadrature points in chunks of QC: ten running sums and one chunk of
+    // products live at a time (fewer registers, more waves per SIMD)
+    constexpr int QC = NQ > 9 ? 9 : NQ;
     for (int j = jb; j < j1; ++j) {
-      const int a = (int)(rc.ea & 15u);
+      const IncRec<NLOC> rc = inc[j];
+      const int e = (int)(rc.ea >> 4), a = (int)(rc.ea & 15u);
+      const double dj = absdet[e];
+      const double *Ve = V + (int64_t)e * NQ;
       unsigned off[NLOC];
 #pragma unroll
       for (int b = 0; b < NLOC; ++b) off[b] = rc.off[b];
-      // d_q = w_q |J| V_q phi_a(q); then v_b = sum_q d_q phi_b(q), b by b,
-      // each sum in three independent chains (phi_b(q) is uniform over the
-      // workgroup: scalar operands)
-      double d[NQ];
+      double vb[NLOC];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) d[q] = dj * vq[q] * s_wphi[q * NLOC + a];
-      if (j + 1 < j1) {
-        rc = rn;
-        if (j + 2 < j1) rn = inc[j + 2];
-        const int e = (int)(rc.ea >> 4);
-        dj = absdet[e];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) vq[q] = V[(int64_t)e * NQ + q];
-      }
+      for (int b = 0; b < NLOC; ++b) vb[b] = 0.0;
 #pragma unroll 1
-      for (int b = 0; b < NLOC; ++b) {
-        const double *pb = phib + b * NQ;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int q0 = 0; q0 < NQ; q0 += QC) {
+        double d[QC];
 #pragma unroll
-        for (int q = 0; q + 2 < NQ; q += 3) {
-          s0 += d[q] * pb[q];
-          s1 += d[q + 1] * pb[q + 1];
-          s2 += d[q + 2] * pb[q + 2];
-        }
-        if constexpr (NQ % 3 >= 1) s0 += d[NQ - NQ % 3] * pb[NQ - NQ % 3];
-        if constexpr (NQ % 3 == 2) s1 += d[NQ - 1] * pb[NQ - 1];
-        const double v = (s0 + s1) + s2;
-        unsigned o = off[0];
+        for (int u = 0; u < QC; ++u)
+          d[u] = q0 + u < NQ ? dj * Ve[q0 + u] * s_wphi[(q0 + u) * NLOC + a] : 0.0;
 #pragma unroll
-        for (int t = 1; t < NLOC; ++t)
-          if (b == t) o = off[t];
-        if (o != 255u) acc[o] += v;
+        for (int b = 0; b < NLOC; ++b)
+#pragma unroll
+          for (int u = 0; u < QC; ++u)
+            if (q0 + u < NQ) vb[b] += d[u] * phib[b * NQ + q0 + u];
       }
+      // the incidence's slots are distinct: all reads, then all writes (one
+      // LDS round trip instead of one per slot; same order of additions)
+      double cur[NLOC];
+#pragma unroll
+      for (int b = 0; b < NLOC; ++b) cur[b] = off[b] != 255u ? acc[off[b]] : 0.0;
+#pragma unroll
+      for (int b = 0; b < NLOC; ++b)
+        if (off[b] != 255u) acc[off[b]] = cur[b] + vb[b];
     }
   }
   __syncthreads();

@@ -43,57 +43,103 @@ void launch_vext(const double *coords, const int32_t *elems, int n_loc, int n_e,
                        n_loc, n_e, n_q, bary, n_atoms, Z, R, out);
 }
 
-// rho_q = sum_i f_i (sum_a phi_qa X[node_a][i])^2, one lane per (element,
-// quadrature point): a block first stages its elements' nodal rows (all k
-// orbitals of each node, coalesced) in LDS; each lane then runs over the
-// orbitals with the element's values read as LDS broadcasts.  LPE lanes per
-// element (>= NQ), EPB = 256 / LPE elements per block.
+// rho_q = sum_i f_i (sum_a phi_qa X[node_a][i])^2 = sum_{a,b} phi_qa phi_qb G_ab
+// with G_ab = sum_i f_i X[node_a][i] X[node_b][i], the element's occupied
+// Gram matrix.  A block first stages its elements' nodal rows (all k orbitals
+// of each node, coalesced) in LDS, rows padded to an odd number of doubles so
+// that the ten rows of an element sit in distinct banks; the LPE lanes of an
+// element then form the NLOC (NLOC + 1) / 2 entries of G (lane l: pairs l,
+// l + LPE, ...), and lane q evaluates the quadratic form at point q:
+// (NP k + NP NQ) multiply-adds per element instead of NQ NLOC k.
+// EPB = 256 / LPE elements per block, LPE >= NQ.
 template <int NLOC, int NQ, int LPE>
 __global__ void __launch_bounds__(256) k_density(const int32_t *__restrict__ edof, int n_e,
                                                  const double *__restrict__ phi,
                                                  const double *__restrict__ X, int ldx, int k,
                                                  const double *__restrict__ occ,
                                                  double *__restrict__ rho) {
-  constexpr int EPB = 256 / LPE;
-  extern __shared__ double s_x[];  // [EPB][NLOC][k], then occ [k]
-  const int nk = NLOC * k;
+  constexpr int EPB = 256 / LPE, NP = NLOC * (NLOC + 1) / 2;
+  extern __shared__ double s_x[];  // [EPB][NLOC][kp], occ [k], G [EPB][NP]
+  const int kp = k | 1;
+  const int nk = NLOC * kp;
+  __shared__ int s_dof[EPB * NLOC];
   const int e0 = blockIdx.x * EPB;
-  for (int idx = threadIdx.x; idx < EPB * nk; idx += blockDim.x) {
-    const int el = idx / nk, r = idx - el * nk, a = r / k, i = r - a * k;
-    const int e = e0 + el;
-    double v = 0.0;
-    if (e < n_e) {
-      const int d = edof[(int64_t)e * NLOC + a];
-      if (d >= 0) v = X[(int64_t)d * ldx + i];
+  // the block's node indices in one coalesced read, then each thread's
+  // orbital values in batches of eight loads in flight before any store;
+  // idx -> (staged row, orbital) without an integer division by k: the float
+  // quotient is exact to far better than 1/(2k) for idx < EPB NLOC 64
+  for (int t = threadIdx.x; t < EPB * NLOC; t += blockDim.x)
+    s_dof[t] = e0 + t / NLOC < n_e ? edof[(int64_t)e0 * NLOC + t] : -1;
+  __syncthreads();
+  const float rk = 1.0f / (float)k;
+  const int total = EPB * NLOC * k;
+  for (int c0 = 0; c0 < total; c0 += 8 * 256) {
+    double v[8];
+    int dst[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = c0 + u * 256 + (int)threadIdx.x;
+      v[u] = 0.0;
+      dst[u] = -1;
+      if (idx < total) {
+        const int row = (int)(((float)idx + 0.5f) * rk), i = idx - row * k;
+        const int d = s_dof[row];
+        if (d >= 0) v[u] = X[(int64_t)d * ldx + i];
+        dst[u] = row * kp + i;  // row = el NLOC + a
+      }
     }
-    s_x[idx] = v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (dst[u] >= 0) s_x[dst[u]] = v[u];
   }
   double *s_occ = s_x + EPB * nk;
+  double *s_g = s_occ + k;
   for (int i = threadIdx.x; i < k; i += blockDim.x) s_occ[i] = occ[i];
   __syncthreads();
-  const int el = threadIdx.x / LPE, q = threadIdx.x - el * LPE, e = e0 + el;
-  if (q >= NQ || e >= n_e) return;
+  const int el = threadIdx.x / LPE, l = threadIdx.x - el * LPE, e = e0 + el;
+  const double *xe = s_x + el * nk;
+  for (int p = l; p < NP; p += LPE) {
+    int a = 0, rem = p;  // p -> (a, b), a <= b, upper triangle row by row
+    while (rem >= NLOC - a) {
+      rem -= NLOC - a;
+      ++a;
+    }
+    const double *xa = xe + a * kp, *xb = xe + (a + rem) * kp;
+    double g0 = 0.0, g1 = 0.0;
+    int i = 0;
+    for (; i + 1 < k; i += 2) {
+      g0 += (s_occ[i] * xa[i]) * xb[i];
+      g1 += (s_occ[i + 1] * xa[i + 1]) * xb[i + 1];
+    }
+    if (i < k) g0 += (s_occ[i] * xa[i]) * xb[i];
+    s_g[el * NP + p] = rem == 0 ? g0 + g1 : 2.0 * (g0 + g1);
+  }
+  __syncthreads();
+  if (l >= NQ || e >= n_e) return;
   double ph[NLOC];
 #pragma unroll
-  for (int a = 0; a < NLOC; ++a) ph[a] = phi[q * NLOC + a];
-  const double *xe = s_x + el * nk;
-  double r = 0.0;
-  for (int i = 0; i < k; ++i) {
-    double v = 0.0;
+  for (int a = 0; a < NLOC; ++a) ph[a] = phi[l * NLOC + a];
+  const double *ge = s_g + el * NP;
+  double r0 = 0.0, r1 = 0.0;
+  int p = 0;
 #pragma unroll
-    for (int a = 0; a < NLOC; ++a) v += ph[a] * xe[a * k + i];
-    r += s_occ[i] * v * v;
+  for (int a = 0; a < NLOC; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = a; b < NLOC; ++b, ++p) t += ge[p] * ph[b];
+    if (a & 1) r1 += ph[a] * t;
+    else r0 += ph[a] * t;
   }
-  rho[(int64_t)e * NQ + q] = r;
+  rho[(int64_t)e * NQ + l] = r0 + r1;
 }
 template <int NLOC, int NQ>
 static void density_t(const int32_t *edof, int n_e, const double *phi, const double *X, int ldx, int k,
                       const double *occ, double *rho, hipStream_t s) {
-  // 32 lanes per element for the 27-point rule or 10-node elements (keeps the
-  // staged block <= 40 KB at k = 64), else 16
+  // 32 lanes per element for the 27-point rule or 10-node elements (the
+  // staged block stays under 48 KB at k = 64), else 16
   constexpr int LPE = (NQ > 16 || NLOC == 10) ? 32 : 16;
   constexpr int EPB = 256 / LPE;
-  const size_t lds = sizeof(double) * ((size_t)EPB * NLOC * k + k);
+  const size_t lds = sizeof(double) * ((size_t)EPB * NLOC * (k | 1) + k + (size_t)EPB * NLOC * (NLOC + 1) / 2);
   hipLaunchKernelGGL((k_density<NLOC, NQ, LPE>), dim3((n_e + EPB - 1) / EPB), dim3(256), lds, s, edof, n_e, phi,
                      X, ldx, k, occ, rho);
 }
@@ -246,7 +292,7 @@ void launch_moments(const double *coords, const int32_t *elems, int n_loc, int n
 
 // out[j] = sum_b part[b][j]: all columns at once (threads t = g W + c take
 // rows b = g, g + G, ... of column c, eight loads in flight), then the G
-// group sums of each column in order; W = min(nvals, 1024) columns per pass
+// group sums of each column by a tree; W = min(nvals, 1024) columns per pass
 __global__ void __launch_bounds__(1024) k_reduce_cols(const double *__restrict__ part, int nblk,
                                                       int nvals, double *__restrict__ out) {
   __shared__ double sh[1024];
@@ -267,11 +313,17 @@ __global__ void __launch_bounds__(1024) k_reduce_cols(const double *__restrict__
     }
     sh[t] = a;
     __syncthreads();
-    if (t < W) {
-      double tot = 0.0;
-      for (int g = 0; g < G; ++g) tot += sh[g * W + t];
-      out[c0 + t] = tot;
+    // the G group sums of each column by a fixed-order tree
+    int span = 1;
+    while (span < G) span <<= 1;
+    for (int st = span >> 1; st >= 1; st >>= 1) {
+      if (t < G * W) {
+        const int g = t / W;
+        if (g < st && g + st < G) sh[t] += sh[t + st * W];
+      }
+      __syncthreads();
     }
+    if (t < W) out[c0 + t] = sh[t];
     __syncthreads();
   }
 }

@@ -392,7 +392,7 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
 void mg_destroy(Multigrid *mg);
 void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0);
 int mg_levels(const Multigrid *mg);
-// part: >= 256 doubles of device scratch; sc: >= 6 device doubles (CG scalars)
+// part: >= 1024 doubles of device scratch; sc: >= 6 device doubles (CG scalars)
 int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
            int *iters, double *relres, hipStream_t s);
 }  // namespace ks

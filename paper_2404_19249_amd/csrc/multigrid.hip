@@ -590,7 +590,7 @@ void mg_apply(Multigrid *mg, const double *b, double *x, hipStream_t s) { vcycle
 // (p.q, r.r) per iteration for the breakdown and stopping tests.
 // sc layout: [0] p.q, [1] r.r, [2] f.f, [3], [4] alternating r.z slots,
 // [5] r_new . z_old.
-constexpr int MG_NB = 256;  // partial-sum blocks of the vector kernels
+constexpr int MG_NB = 1024;  // partial-sum blocks of the vector kernels (4 per CU)
 
 // a . b per block (fixed order)
 __global__ void __launch_bounds__(256) k_mg_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
@@ -637,7 +637,7 @@ static int read_back(const double *sc, int slot, int cnt, double *h, hipStream_t
 
 // CG preconditioned by one V-cycle per iteration on level 0's operator:
 // A x = f from the warm start x, stopped at ||f - A x||_2 <= tol ||f||_2.
-// part: device scratch (>= 256 doubles); sc: device scalars (>= 6 doubles).
+// part: device scratch (>= 1024 doubles); sc: device scalars (>= 6 doubles).
 // Returns 0 converged, 1 iteration limit, -1 launch failure, -2 breakdown
 // (p.Ap <= 0).
 int mg_pcg(Multigrid *mg, const double *f, double *x, double tol, int max_it, double *part, double *sc,
