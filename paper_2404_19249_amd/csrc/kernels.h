@@ -384,11 +384,20 @@ namespace ks {
 // ------------------------------------------------------------ multigrid
 struct Multigrid;
 void kuhn_interp(const double *x, double L, int nH, int32_t *idx, double *w);
+// An optional first coarse level given by the caller: nc unknowns at
+// coordinates X [nc][3], reached from level 0 by the ELL-4 interpolation
+// Pi/Pw [n0][4] (-1: no entry).  For P2 meshes this is P1 on the mesh's own
+// vertices (nested, exact Galerkin operator: the P1 stiffness).
+struct MGFirst {
+  int nc = 0;
+  std::vector<int32_t> Pi;
+  std::vector<double> Pw, X;
+};
 Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d, const Tiling *til0,
                     int tb0,
                     const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
                     const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
-                    hipStream_t s);
+                    hipStream_t s, const MGFirst *first = nullptr);
 void mg_destroy(Multigrid *mg);
 void mg_set_tiling(Multigrid *mg, const Tiling *til0, int tb0);
 int mg_levels(const Multigrid *mg);

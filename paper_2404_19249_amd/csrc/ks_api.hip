@@ -1335,12 +1335,54 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
         return bail(fail(KS_ERR_HIP, "download failed"));
       for (int r = 0; r < N; ++r)
         for (int d = 0; d < 3; ++d) X[3 * (size_t)r + d] = mesh->coords_host[3 * (int64_t)interior_nodes[r] + d];
-      // cells per side of the first coarse level: the fine mesh's vertex
-      // lattice for P2 (P1 on the same vertices), half of it for P1
+      // P2: the first coarse level is P1 on the mesh's own vertices (nested:
+      // vertices inject, edge midpoints average their two ends, boundary
+      // vertices drop out), then uniform lattices of half the fine cells per
+      // side and coarser; P1: uniform lattices from half the fine cells
       const int side = (int)std::lround(std::cbrt((double)nn));
       const int nfine = std::max(1, (side - 1) / c->order);
-      const int n1 = c->order == 2 ? nfine : nfine / 2;
-      c->mg = mg_build(N, c->rowptr, c->col, c->K, c->pwP.til, c->pwP.til_tb, rowptr, colI, Kh, X, c->L, n1, s);
+      const int n1 = nfine / 2;
+      MGFirst first;
+      if (c->order == 2) {
+        std::vector<int32_t> vidx(nn, -1), e0(nn, -1), e1(nn, -1);
+        static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        std::vector<char> isv(nn, 0);
+        for (int64_t e = 0; e < ne; ++e) {
+          for (int a = 0; a < 4; ++a) isv[el[e * nl + a]] = 1;
+          for (int t = 0; t < 6; ++t) {
+            const int m = el[e * nl + 4 + t];
+            e0[m] = el[e * nl + E[t][0]];
+            e1[m] = el[e * nl + E[t][1]];
+          }
+        }
+        for (int r = 0; r < N; ++r)  // coarse unknowns in the fine storage order
+          if (isv[interior_nodes[r]]) vidx[interior_nodes[r]] = first.nc++;
+        first.Pi.assign((size_t)N * 4, -1);
+        first.Pw.assign((size_t)N * 4, 0.0);
+        first.X.resize((size_t)first.nc * 3);
+        bool ok = first.nc > 0;
+        for (int r = 0; r < N && ok; ++r) {
+          const int nd = interior_nodes[r];
+          if (vidx[nd] >= 0) {
+            first.Pi[4 * (size_t)r] = vidx[nd];
+            first.Pw[4 * (size_t)r] = 1.0;
+            for (int d = 0; d < 3; ++d) first.X[3 * (size_t)vidx[nd] + d] = mesh->coords_host[3 * (int64_t)nd + d];
+          } else if (e0[nd] >= 0) {
+            int t = 0;
+            for (const int v : {e0[nd], e1[nd]})
+              if (vidx[v] >= 0) {
+                first.Pi[4 * (size_t)r + t] = vidx[v];
+                first.Pw[4 * (size_t)r + t++] = 0.5;
+              }
+          } else {
+            ok = false;  // a node that is neither vertex nor edge midpoint
+          }
+        }
+        if (!ok) first = MGFirst();
+      }
+      c->mg = mg_build(N, c->rowptr, c->col, c->K, c->pwP.til, c->pwP.til_tb, rowptr, colI, Kh, X, c->L,
+                       c->order == 2 && first.nc > 0 ? n1 : (c->order == 2 ? nfine : n1), s,
+                       first.nc > 0 ? &first : nullptr);
     }
   }
   if (hipStreamSynchronize(s) != hipSuccess) return bail(fail(KS_ERR_HIP, "setup failed"));

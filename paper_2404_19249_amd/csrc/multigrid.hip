@@ -262,10 +262,53 @@ __global__ void __launch_bounds__(256) k_dense_matvec(int n, const double *__res
   if (lane == 0) x[row] = s;
 }
 
+// y = A x (b null) or y = b - A x for a matrix in column-major ELL form
+// ([w][n]: entry j of row i at j n + i, in the row's CSR order, padding with
+// value 0): one row per lane, so that the index, value and (on a lattice)
+// vector loads of a wavefront are coalesced; fixed summation order
+__global__ void __launch_bounds__(256) k_ell_spmv(int n, int w, const int32_t *__restrict__ col,
+                                                 const double *__restrict__ val, const double *__restrict__ x,
+                                                 const double *__restrict__ b, double *__restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < w; ++j) acc += val[(int64_t)j * n + i] * x[col[(int64_t)j * n + i]];
+    y[i] = b ? b[i] - acc : acc;
+  }
+}
+static void launch_ell_spmv(int n, int w, const int32_t *col, const double *val, const double *x, const double *b,
+                            double *y, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_ell_spmv, dim3(std::min(4096, (n + 255) / 256)), dim3(256), 0, s, n, w, col, val, x, b, y);
+}
+// column-major ELL copy of a host CSR matrix with n rows (padding: column 0,
+// value 0); false when a row is longer than max_w
+static bool to_ell(int n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                   const std::vector<double> &v, int max_w, int &w, std::vector<int32_t> &ec,
+                   std::vector<double> &ev) {
+  w = 0;
+  for (int i = 0; i < n; ++i) w = std::max(w, rp[i + 1] - rp[i]);
+  if (w > max_w || w == 0) return false;
+  ec.assign((size_t)w * n, 0);
+  ev.assign((size_t)w * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = rp[i]; j < rp[i + 1]; ++j) {
+      ec[(size_t)(j - rp[i]) * n + i] = ci[j];
+      ev[(size_t)(j - rp[i]) * n + i] = v[j];
+    }
+  return true;
+}
+constexpr int ELL_MAX_W = 64;
+
 struct MGLevel {
   int n = 0;
   const int32_t *rp = nullptr, *ci = nullptr;  // operator (level 0: the context's CSR)
   const double *val = nullptr;
+  // the operator in ELL form on the coarse levels (aw = 0: not built), and
+  // the restriction to the next level in ELL form (rw = 0: CSR only)
+  int aw = 0, rw = 0;
+  int32_t *acol = nullptr, *rcol = nullptr;
+  double *aval = nullptr, *rval = nullptr;
   double *dinv = nullptr;
   double lmax = 2.0;
   // transfer to the next coarser level: restriction R = P^T (CSR, rows =
@@ -313,12 +356,13 @@ int mg_levels(const Multigrid *mg) { return mg ? (int)mg->lv.size() : 0; }
 // Build the hierarchy.  Level 0 is the given operator (device CSR plus its
 // host copy for the Galerkin products); coords: the level-0 unknowns'
 // coordinates [n][3]; L: half side of the box; n1: cells per side of the
-// first coarse level.  Returns nullptr when no coarse level fits.
+// first uniform coarse level (after `first`, when given).  Returns nullptr
+// when no coarse level fits.
 Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const double *val_d, const Tiling *til0,
                     int tb0,
                     const std::vector<int32_t> &rp_h, const std::vector<int32_t> &ci_h,
                     const std::vector<double> &val_h, const std::vector<double> &coords, double L, int n1,
-                    hipStream_t s) {
+                    hipStream_t s, const MGFirst *first) {
   if (n1 < 2) return nullptr;
   Multigrid *mg = new Multigrid();
   mg->til0 = til0;
@@ -344,17 +388,25 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
   }
   std::vector<HostCSR> ops;
   ops.push_back(A);
+  bool use_first = first && first->nc > 0 && first->Pi.size() == (size_t)n0 * 4 &&
+                   first->Pw.size() == (size_t)n0 * 4 && first->X.size() == (size_t)first->nc * 3;
   while (true) {
     MGLevel &f = mg->lv.back();
     const HostCSR &Af = ops.back();
     f.lmax = lambda_max_jacobi(Af);
+    const bool from_first = use_first;
     const int ni = n_cells - 1;
-    const int nc = ni * ni * ni;
+    const int nc = from_first ? first->nc : ni * ni * ni;
     if (nc < 1) break;
     // interpolation of this level's nodes from the coarse mesh
     std::vector<int32_t> Pi((size_t)f.n * 4);
     std::vector<double> Pw((size_t)f.n * 4);
-    par_for(f.n, [&](int64_t i) { kuhn_interp(&X[3 * i], L, n_cells, &Pi[4 * i], &Pw[4 * i]); });
+    if (from_first) {
+      Pi = first->Pi;
+      Pw = first->Pw;
+    } else {
+      par_for(f.n, [&](int64_t i) { kuhn_interp(&X[3 * i], L, n_cells, &Pi[4 * i], &Pw[4 * i]); });
+    }
     HostCSR Ac = galerkin(Af, Pi, Pw, nc);
     // a coarse node no fine node interpolates from leaves a zero row: the
     // hierarchy is then unusable (the caller keeps the Jacobi-PCG solver)
@@ -393,6 +445,19 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
         hipMemcpyAsync(f.Pw, Pw.data(), sizeof(double) * Pw.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return bail();
+    {
+      std::vector<int32_t> ec;
+      std::vector<double> ev;
+      int w = 0;
+      if (to_ell(nc, Rrp, Rci, Rv, ELL_MAX_W, w, ec, ev)) {
+        if (!mg->alloc(&f.rcol, ec.size()) || !mg->alloc(&f.rval, ev.size())) return bail();
+        if (hipMemcpyAsync(f.rcol, ec.data(), sizeof(int32_t) * ec.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(f.rval, ev.data(), sizeof(double) * ev.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return bail();
+        f.rw = w;
+      }
+    }
     // the coarse level
     MGLevel cl;
     cl.n = nc;
@@ -407,20 +472,43 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
     cl.rp = crp;
     cl.ci = cci;
     cl.val = cv;
-    // node coordinates of the coarse level (interior lattice vertices)
+    {
+      std::vector<int32_t> ec;
+      std::vector<double> ev;
+      int w = 0;
+      if (to_ell(nc, Ac.rp, Ac.ci, Ac.v, ELL_MAX_W, w, ec, ev)) {
+        if (!mg->alloc(&cl.acol, ec.size()) || !mg->alloc(&cl.aval, ev.size())) return bail();
+        if (hipMemcpyAsync(cl.acol, ec.data(), sizeof(int32_t) * ec.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(cl.aval, ev.data(), sizeof(double) * ev.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return bail();
+        cl.aw = w;
+      }
+    }
+    // node coordinates of the coarse level (the given level's, else the
+    // interior lattice vertices)
     std::vector<double> Xc((size_t)nc * 3);
-    const double h = 2.0 * L / n_cells;
-    for (int kz = 0; kz < ni; ++kz)
-      for (int jy = 0; jy < ni; ++jy)
-        for (int ix = 0; ix < ni; ++ix) {
-          const size_t a = ix + (size_t)ni * (jy + (size_t)ni * kz);
-          Xc[3 * a] = -L + h * (ix + 1);
-          Xc[3 * a + 1] = -L + h * (jy + 1);
-          Xc[3 * a + 2] = -L + h * (kz + 1);
-        }
+    if (from_first) {
+      Xc = first->X;
+    } else {
+      const double h = 2.0 * L / n_cells;
+      for (int kz = 0; kz < ni; ++kz)
+        for (int jy = 0; jy < ni; ++jy)
+          for (int ix = 0; ix < ni; ++ix) {
+            const size_t a = ix + (size_t)ni * (jy + (size_t)ni * kz);
+            Xc[3 * a] = -L + h * (ix + 1);
+            Xc[3 * a + 1] = -L + h * (jy + 1);
+            Xc[3 * a + 2] = -L + h * (kz + 1);
+          }
+    }
     mg->lv.push_back(cl);
     ops.push_back(std::move(Ac));
     X.swap(Xc);
+    if (from_first) {
+      use_first = false;
+      if (nc <= 512 || n_cells < 2) break;
+      continue;  // the uniform levels start at n_cells
+    }
     if (nc <= 512 || n_cells < 4) break;  // coarsest: dense
     n_cells /= 2;
   }
@@ -498,6 +586,10 @@ Multigrid *mg_build(int n0, const int32_t *rp_d, const int32_t *ci_d, const doub
 // y = A x (b null) or y = b - A x on one level (halo tiles on level 0)
 static void lv_spmv(const Multigrid *mg, const MGLevel &v, const double *x, double *y, const double *b,
                     hipStream_t s) {
+  if (v.aw > 0) {
+    launch_ell_spmv(v.n, v.aw, v.acol, v.aval, x, b, y, s);
+    return;
+  }
   if (&v == &mg->lv[0] && mg->til0 &&
       launch_spmm_tiled(v.n, 1, *mg->til0, mg->tb0, v.rp, v.val, x, y, b, s) == 0)
     return;
@@ -522,6 +614,12 @@ static void mg_smooth(const Multigrid *mg, MGLevel &v, const double *b, bool zer
 }
 
 static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s);
+
+// b_c = R r = P^T r from level v to the next coarser level c
+static void restrict_to(const MGLevel &v, MGLevel &c, hipStream_t s) {
+  if (v.rw > 0) launch_ell_spmv(c.n, v.rw, v.rcol, v.rval, v.r, nullptr, c.b, s);
+  else launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);
+}
 
 // r32 = b32 - A x32 on level 0 (FP32 halo tiles); false if they cannot serve
 static bool spmv0_f32(const Multigrid *mg, hipStream_t s) {
@@ -549,7 +647,7 @@ static void vcycle0_f32(Multigrid *mg, const double *b, double *x, hipStream_t s
   spmv0_f32(mg, s);
   hipLaunchKernelGGL(k_f2d, dim3(g), dim3(256), 0, s, n, mg->r32, v.r);
   MGLevel &c = mg->lv[1];
-  launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);  // b_c = P^T r
+  restrict_to(v, c, s);  // b_c = P^T r
   vcycle(mg, 1, c.b, c.x, s);
   hipLaunchKernelGGL(k_prolong_add32, dim3(g), dim3(256), 0, s, n, v.Pidx, v.Pw, c.x, mg->x32);
   // post-smoothing
@@ -576,7 +674,7 @@ static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t
   mg_smooth(mg, v, b, true, s);
   lv_spmv(mg, v, v.x, v.r, b, s);  // r = b - A x
   MGLevel &c = mg->lv[l + 1];
-  launch_spmm(c.n, v.Rrp, v.Rci, v.Rv, v.r, 1, c.b, 1, 1, nullptr, 0, 0, nullptr, s);  // b_c = P^T r
+  restrict_to(v, c, s);  // b_c = P^T r
   vcycle(mg, l + 1, c.b, c.x, s);
   launch_ellP_times(v.n, v.Pidx, v.Pw, c.x, 1, 1, 1.0, v.x, 1, v.x, 1, s);  // x += P x_c
   mg_smooth(mg, v, b, false, s);

@@ -32,8 +32,9 @@ def test_hartree_multilevel_vcycle_matches_oracle():
     """V_H of the MG-preconditioned CG against the oracle's Jacobi-PCG
     solution of the same Poisson problem with the same multipole boundary
     data (Sec. 3.1, eq. bd), on a P2 mesh of 16^3 hexes whose hierarchy has
-    three levels: the fine P2 operator, P1 on 16^3 cells (smoothed, an
-    intermediate level) and P1 on 8^3 cells (343 unknowns, inverted)."""
+    three levels: the fine P2 operator, P1 on the mesh's own vertices
+    (nested; smoothed, an intermediate level) and P1 on a uniform lattice of
+    8^3 cells (343 unknowns, inverted)."""
     w = make_workload("small_molecule", n=16)
     ctx = _ctx(w)
     assert ctx.mg_levels == 3
