@@ -293,6 +293,79 @@ k_assemble_rows(int N, const int32_t *__restrict__ rowptr, const int32_t *__rest
     if (out32) out32[v0 + i] = (float)v;
   }
 }
+// Load vector in two passes.  Elements: be[e][a] = |J_e| sum_q w_q f_eq
+// phi_a(q), a block's elements' quadrature values read together (they are
+// contiguous, so the loads coalesce) and staged in LDS.  Rows: out[r] =
+// scale sum over the incidences (e, a) of interior row r of be[e][a], one
+// thread per row in ascending element order (the assembly's incidence
+// records): every element's values are read once, and the sum has a fixed
+// order.
+constexpr int LOAD_EPB = 128;  // elements per workgroup of the element pass
+template <int NLOC, int NQ>
+__global__ void __launch_bounds__(LOAD_EPB) k_load_elems(int n_e, const double *__restrict__ absdet,
+                                                        const double *__restrict__ phiq,
+                                                        const double *__restrict__ w,
+                                                        const double *__restrict__ f, double *__restrict__ be) {
+  __shared__ double s_wphi[NQ * NLOC];
+  __shared__ double s_f[LOAD_EPB * NQ];
+  for (int i = threadIdx.x; i < NQ * NLOC; i += blockDim.x) s_wphi[i] = w[i / NLOC] * phiq[i];
+  const int e0 = blockIdx.x * LOAD_EPB;
+  const int ne = min(LOAD_EPB, n_e - e0);
+  const double *fb = f + (int64_t)e0 * NQ;
+  for (int i = threadIdx.x; i < ne * NQ; i += blockDim.x) s_f[i] = fb[i];
+  __syncthreads();
+  if ((int)threadIdx.x >= ne) return;
+  const int e = e0 + threadIdx.x;
+  const double *fe = s_f + threadIdx.x * NQ;
+  const double dj = absdet[e];
+#pragma unroll
+  for (int a = 0; a < NLOC; ++a) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q + 2 < NQ; q += 3) {
+      s0 += s_wphi[q * NLOC + a] * fe[q];
+      s1 += s_wphi[(q + 1) * NLOC + a] * fe[q + 1];
+      s2 += s_wphi[(q + 2) * NLOC + a] * fe[q + 2];
+    }
+    if constexpr (NQ % 3 >= 1) s0 += s_wphi[(NQ - NQ % 3) * NLOC + a] * fe[NQ - NQ % 3];
+    if constexpr (NQ % 3 == 2) s1 += s_wphi[(NQ - 1) * NLOC + a] * fe[NQ - 1];
+    be[(int64_t)e * NLOC + a] = dj * ((s0 + s1) + s2);
+  }
+}
+template <int NLOC>
+__global__ void __launch_bounds__(256) k_load_gather(int N, const int32_t *__restrict__ incptr,
+                                                     const IncRec<NLOC> *__restrict__ inc,
+                                                     const double *__restrict__ be, double scale,
+                                                     double *__restrict__ out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < N; r += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = incptr[r]; j < incptr[r + 1]; ++j) {
+      const uint32_t ea = inc[j].ea;
+      acc += be[(int64_t)(ea >> 4) * NLOC + (ea & 15u)];
+    }
+    out[r] = scale * acc;
+  }
+}
+int launch_load_rows(int N, int n_e, int n_loc, int n_q, const int32_t *incptr, const void *inc,
+                     const double *absdet, const double *phi, const double *w, const double *f_q, double scale,
+                     double *be, double *out, hipStream_t s) {
+  if (N <= 0 || n_e <= 0) return 0;
+  dim3 ge((n_e + LOAD_EPB - 1) / LOAD_EPB), bk(LOAD_EPB), gr(std::min(8192, (N + 255) / 256)), br(256);
+#define KS_LR(NL, NQ)                                                                                   \
+  do {                                                                                                  \
+    hipLaunchKernelGGL((k_load_elems<NL, NQ>), ge, bk, 0, s, n_e, absdet, phi, w, f_q, be);             \
+    hipLaunchKernelGGL((k_load_gather<NL>), gr, br, 0, s, N, incptr, static_cast<const IncRec<NL> *>(inc), \
+                       be, scale, out);                                                                 \
+  } while (0)
+  if (n_loc == 4 && n_q == 8) KS_LR(4, 8);
+  else if (n_loc == 10 && n_q == 27) KS_LR(10, 27);
+  else if (n_loc == 4 && n_q == 27) KS_LR(4, 27);
+  else if (n_loc == 10 && n_q == 8) KS_LR(10, 8);
+  else return -1;
+#undef KS_LR
+  return 0;
+}
+
 size_t assemble_rows_lds_limit() { return 160 * 1024 - 27 * 10 * sizeof(double) - 1024; }
 int launch_assemble_rows(int N, int n_loc, int n_q, const int32_t *rowptr, const int32_t *incptr, const void *inc,
                          const uint8_t *rperm, size_t lds_bytes, const double *absdet, const double *phi,

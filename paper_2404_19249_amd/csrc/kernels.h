@@ -38,6 +38,13 @@ template <> struct __align__(8) IncRec<4> { uint32_t ea; uint8_t off[4]; };
 // value count (<= assemble_rows_lds_limit()).  Returns -1 when the shape has
 // no kernel or the LDS attribute cannot be set.
 size_t assemble_rows_lds_limit();
+// out[r] = scale sum_(e,a) |J_e| sum_q w_q f_eq phi_a(q) over the incidence
+// records of each interior row (the load vector, all of out written), via
+// per-element values in be [n_e][n_loc] (device scratch); -1 when the shape
+// has no kernel
+int launch_load_rows(int N, int n_e, int n_loc, int n_q, const int32_t *incptr, const void *inc,
+                     const double *absdet, const double *phi, const double *w, const double *f_q, double scale,
+                     double *be, double *out, hipStream_t s);
 // phi: [n_q][n_loc] basis values at the quadrature points; phib: the same
 // table b-major [n_loc][n_q]
 int launch_assemble_rows(int N, int n_loc, int n_q, const int32_t *rowptr, const int32_t *incptr, const void *inc,

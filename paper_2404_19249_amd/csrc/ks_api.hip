@@ -119,6 +119,7 @@ struct ks_ctx {
   int32_t *r_incptr = nullptr;
   uint8_t *r_inc = nullptr, *r_perm = nullptr;
   size_t r_lds = 0;
+  double *load_e = nullptr;  // per-element load values [n_e][n_loc] (row-form load vector)
   double *phib = nullptr;  // basis values b-major [n_loc][n_q] (row-form assembly)
   double *absdet = nullptr, *gl = nullptr, *phi = nullptr, *dphi = nullptr, *pairtab = nullptr,
          *qw = nullptr, *qbary = nullptr, *dZ = nullptr, *dR = nullptr;
@@ -356,11 +357,14 @@ static bool assemble_potential_all(ks_ctx *c, const double *Vq, double *out, con
 // tol <= 0: the context's tol_poisson
 static int hartree_solve(ks_ctx *c, const double *rho, int *iters, double tol = 0.0) {
   if (!(tol > 0.0)) tol = c->opt.tol_poisson;
-  launch_fill(c->N, 0.0, c->load, c->s);
-  for (int col = 0; col < c->n_colours; ++col) {
-    const int a = c->colour_off[col], b = c->colour_off[col + 1];
-    launch_load_vector(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->edof, c->absdet, c->phi,
-                       c->qw, rho, 4.0 * M_PI, c->load, c->s);
+  if (!c->r_lds || launch_load_rows(c->N, c->n_e, c->n_loc, c->n_q, c->r_incptr, c->r_inc, c->absdet, c->phi,
+                                    c->qw, rho, 4.0 * M_PI, c->load_e, c->load, c->s) != 0) {
+    launch_fill(c->N, 0.0, c->load, c->s);
+    for (int col = 0; col < c->n_colours; ++col) {
+      const int a = c->colour_off[col], b = c->colour_off[col + 1];
+      launch_load_vector(c->elem_perm + a, b - a, c->n_loc, c->n_q, c->edof, c->absdet, c->phi,
+                         c->qw, rho, 4.0 * M_PI, c->load, c->s);
+    }
   }
   // rhs = load - K_IB wB
   launch_spmm(c->N, c->rowptrB, c->colB, c->K + c->nnz, c->wB, 1, c->rhs, 1, 1, c->load, 1, 1, c->rorder, c->s);
@@ -1010,6 +1014,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     A_(r_incptr, r_incptr.size());
     A_(r_inc, r_inc.size());
     A_(r_perm, r_perm.size());
+    A_(load_e, (size_t)ne * nl);
   }
   A_(node2int, nn);
   A_(node2bnd, nn);
