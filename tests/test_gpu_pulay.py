@@ -1,8 +1,9 @@
 """GPU mesh-vertex derivative of one step (ks_step_backward_mesh): dE_KS/dX
 and the forces with mesh motion against the oracle (oracle/pulay.py, pinned
 by finite differences of its own step on moved meshes), on P1 and P2
-meshes; the rigid-motion identities on the GPU's own output; the refusal
-when V_ext was given as a field."""
+meshes and in the linear case (no Hartree, no exchange-correlation); the
+rigid-motion identities on the GPU's own output; the refusal when V_ext
+was given as a field."""
 import numpy as np
 import pytest
 
@@ -17,12 +18,12 @@ TIGHT = dict(tol_solve=1e-13, tol_inner=1e-12, tol_poisson=1e-13)
 DEV = "cuda:0"
 
 
-def _setup(order, k=2, n_H=3, mu=6.0):
+def _setup(order, k=2, n_H=3, mu=6.0, name="small_molecule"):
     from paper_2404_19249_amd import KSContext
     n = 5 if order == 1 else 3
-    w = make_workload("small_molecule", n=n, order=order, k=k)
+    w = make_workload(name, n=n, order=order, k=k)
     w.n_H = n_H
-    print(f"[case] pulay small_molecule n={n} order={order} k={k}", flush=True)
+    print(f"[case] pulay {name} n={n} order={order} k={k}", flush=True)
     p = KSProblem.from_workload(w, mu=mu)
     th, Psi = initial_guess(p, k)
     for _ in range(2):
@@ -37,9 +38,9 @@ def _motion(p):
     return p2_midpoint_field(p.elems, np.exp(-d2 / 4.0))
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_mesh_gradient_and_moving_mesh_forces_match_oracle(order):
-    w, p, ctx, Psi, th = _setup(order)
+@pytest.mark.parametrize("order,name", [(1, "small_molecule"), (2, "small_molecule"), (1, "hydrogen")])
+def test_mesh_gradient_and_moving_mesh_forces_match_oracle(order, name):
+    w, p, ctx, Psi, th = _setup(order, k=1 if name == "hydrogen" else 2, name=name)
     r = ks_scf_step(p, Psi, th, tol_solve=1e-14, tol_inner=1e-13, tol_poisson=1e-14)
     gX_ref = step_mesh_gradient(p, r, Psi, th)
     _, F_ref, _ = step_backward(p, r, tol=1e-14)

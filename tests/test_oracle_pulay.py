@@ -25,8 +25,11 @@ from oracle.pulay import step_mesh_gradient, forces_with_mesh_motion, p2_midpoin
 TIGHT = dict(tol_solve=1e-14, tol_inner=1e-13, tol_poisson=1e-14)
 
 
-def _setup(order):
-    w = make_workload("small_molecule", n=4 if order == 1 else 3, order=order, k=2)
+def _setup(order, name="small_molecule"):
+    if name == "hydrogen":  # the linear case: no Hartree, no exchange-correlation
+        w = make_workload("hydrogen", n=4, order=order, k=1)
+    else:
+        w = make_workload(name, n=4 if order == 1 else 3, order=order, k=2)
     w.n_H = 3
     p = KSProblem.from_workload(w, mu=6.0)
     th, Psi = initial_guess(p, 2)
@@ -43,9 +46,9 @@ def _energy(p, Psi, th, r, coords, R=None):
     return ks_scf_step(q, Psi, th, w_B=r.extra["w_B"], **TIGHT).energies["KS"]
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_mesh_gradient_matches_finite_differences(order):
-    p, Psi, th, r = _setup(order)
+@pytest.mark.parametrize("order,name", [(1, "small_molecule"), (2, "small_molecule"), (1, "hydrogen")])
+def test_mesh_gradient_matches_finite_differences(order, name):
+    p, Psi, th, r = _setup(order, name)
     gX = step_mesh_gradient(p, r, Psi, th)
     rng = np.random.default_rng(4)
     D = p2_midpoint_field(p.elems, rng.standard_normal(p.coords.shape))
