@@ -596,21 +596,38 @@ static void lv_spmv(const Multigrid *mg, const MGLevel &v, const double *x, doub
   launch_spmm(v.n, v.rp, v.ci, v.val, x, 1, y, 1, 1, b, 1, b ? 1 : 0, nullptr, s);
 }
 
-// Chebyshev smoothing (degree 2) of A x = b on level l; zero_init: x = 0 in
+// Chebyshev smoothing of degree MG_CHEB_DEG on the Jacobi-scaled operator,
+// targeting [lmax / 8, 1.1 lmax]: d_1 = D^-1 r_0 / theta, then
+// d_j = rho_j rho_{j-1} d_{j-1} + (2 rho_j / delta) D^-1 r_{j-1} with
+// rho_1 = 1 / sigma, rho_j = 1 / (2 sigma - rho_{j-1}); x += d_j each step
+constexpr int MG_CHEB_DEG = 2;
+struct ChebCoef {
+  double theta, delta, sigma;
+};
+static ChebCoef cheb_coef(double lmax) {
+  const double lo = lmax / 8.0, hi = 1.1 * lmax;
+  ChebCoef c;
+  c.theta = 0.5 * (hi + lo);
+  c.delta = 0.5 * (hi - lo);
+  c.sigma = c.theta / c.delta;
+  return c;
+}
+// smoothing of A x = b on level l; zero_init: x = 0 in
 static void mg_smooth(const Multigrid *mg, MGLevel &v, const double *b, bool zero_init, hipStream_t s) {
-  const double lo = v.lmax / 8.0, hi = 1.1 * v.lmax;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  // d_1 = D^-1 r / theta, x += d_1
+  const ChebCoef cc = cheb_coef(v.lmax);
   if (zero_init) {
-    launch_cheb(v.n, b, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 2, s);
+    launch_cheb(v.n, b, v.dinv, 0.0, 1.0 / cc.theta, v.d, v.x, 2, s);
   } else {
     lv_spmv(mg, v, v.x, v.r, b, s);
-    launch_cheb(v.n, v.r, v.dinv, 0.0, 1.0 / theta, v.d, v.x, 1, s);
+    launch_cheb(v.n, v.r, v.dinv, 0.0, 1.0 / cc.theta, v.d, v.x, 1, s);
   }
-  const double rho0 = 1.0 / sigma;
-  const double rho1 = 1.0 / (2.0 * sigma - rho0);
-  lv_spmv(mg, v, v.x, v.r, b, s);  // r = b - A x
-  launch_cheb(v.n, v.r, v.dinv, rho1 * rho0, 2.0 * rho1 / delta, v.d, v.x, 0, s);
+  double rho_prev = 1.0 / cc.sigma;
+  for (int j = 1; j < MG_CHEB_DEG; ++j) {
+    const double rho = 1.0 / (2.0 * cc.sigma - rho_prev);
+    lv_spmv(mg, v, v.x, v.r, b, s);  // r = b - A x
+    launch_cheb(v.n, v.r, v.dinv, rho * rho_prev, 2.0 * rho / cc.delta, v.d, v.x, 0, s);
+    rho_prev = rho;
+  }
 }
 
 static void vcycle(Multigrid *mg, int l, const double *b, double *x, hipStream_t s);
@@ -634,15 +651,21 @@ static bool spmv0_f32(const Multigrid *mg, hipStream_t s) {
 static void vcycle0_f32(Multigrid *mg, const double *b, double *x, hipStream_t s) {
   MGLevel &v = mg->lv[0];
   const int n = v.n;
-  const double lo = v.lmax / 8.0, hi = 1.1 * v.lmax;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  const ChebCoef cc = cheb_coef(v.lmax);
   const int g = std::min(4096, (n + 255) / 256);
+  auto cheb_rest = [&]() {  // steps 2 .. MG_CHEB_DEG after the first
+    double rho_prev = 1.0 / cc.sigma;
+    for (int j = 1; j < MG_CHEB_DEG; ++j) {
+      const double rho = 1.0 / (2.0 * cc.sigma - rho_prev);
+      spmv0_f32(mg, s);
+      launch_cheb32(n, mg->r32, mg->dinv32, rho * rho_prev, 2.0 * rho / cc.delta, mg->d32, mg->x32, 0, s);
+      rho_prev = rho;
+    }
+  };
   launch_to_float(n, b, mg->b32, s);
   // pre-smoothing from zero
-  launch_cheb32(n, mg->b32, mg->dinv32, 0.0, 1.0 / theta, mg->d32, mg->x32, 2, s);
-  spmv0_f32(mg, s);
-  launch_cheb32(n, mg->r32, mg->dinv32, rho1 * rho0, 2.0 * rho1 / delta, mg->d32, mg->x32, 0, s);
+  launch_cheb32(n, mg->b32, mg->dinv32, 0.0, 1.0 / cc.theta, mg->d32, mg->x32, 2, s);
+  cheb_rest();
   // residual to the next level
   spmv0_f32(mg, s);
   hipLaunchKernelGGL(k_f2d, dim3(g), dim3(256), 0, s, n, mg->r32, v.r);
@@ -652,9 +675,8 @@ static void vcycle0_f32(Multigrid *mg, const double *b, double *x, hipStream_t s
   hipLaunchKernelGGL(k_prolong_add32, dim3(g), dim3(256), 0, s, n, v.Pidx, v.Pw, c.x, mg->x32);
   // post-smoothing
   spmv0_f32(mg, s);
-  launch_cheb32(n, mg->r32, mg->dinv32, 0.0, 1.0 / theta, mg->d32, mg->x32, 1, s);
-  spmv0_f32(mg, s);
-  launch_cheb32(n, mg->r32, mg->dinv32, rho1 * rho0, 2.0 * rho1 / delta, mg->d32, mg->x32, 0, s);
+  launch_cheb32(n, mg->r32, mg->dinv32, 0.0, 1.0 / cc.theta, mg->d32, mg->x32, 1, s);
+  cheb_rest();
   hipLaunchKernelGGL(k_f2d, dim3(g), dim3(256), 0, s, n, mg->x32, x);
 }
 
