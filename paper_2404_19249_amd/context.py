@@ -267,6 +267,10 @@ class KSContext:
         g = self.empty(self.n_elems, self.n_q)
         F = np.zeros((len(self._Z), 3))
         st = B.SolveStats()
+        if motion is not None:
+            import torch
+            if motion.dtype != torch.float64 or tuple(motion.shape) != (self.n_nodes, len(self._Z)):
+                raise ValueError(f"motion must be float64 [n_nodes][n_atoms] = [{self.n_nodes}][{len(self._Z)}]")
         mp = None if motion is None else self._ptr(motion.contiguous())
         B.check(self.lib.ks_step_backward_mesh(self.h, float(dE), mp, self._ptr(dX), self._ptr(g), B.dptr(F),
                                                C.byref(st)), self.lib)

@@ -66,6 +66,11 @@ def test_rigid_motion_identities_on_the_gpu():
     assert np.abs(dX.sum(axis=0) - F.sum(axis=0)).max() < 1e-9 * s
     tq = np.cross(p.coords, dX).sum(axis=0) - np.cross(p.R, F).sum(axis=0)
     assert np.abs(tq).max() < 1e-9 * s * np.abs(p.coords).max()
+    # a motion array of the wrong type or shape is refused before the call
+    with pytest.raises(ValueError):
+        ctx.step_backward_mesh(motion=torch.zeros(ctx.n_nodes, len(p.Z), device=DEV, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        ctx.step_backward_mesh(motion=torch.zeros(ctx.n_nodes, len(p.Z) + 1, device=DEV, dtype=torch.float64))
     ctx.close()
 
 
