@@ -533,6 +533,17 @@ def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
              "max_abs_dE_dX": float(dX.abs().max()),
              "mesh_term_over_fixed_mesh_force": float(np.abs(Fm - F).max() / np.abs(F).max())}
     del dX
+    # reverse mode through the truncated FP64 PCG of the same step (checkpoints
+    # every 8 iterations), against the implicit adjoint
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    g_t, F_t, st_t = ctx.step_backward(dE=1.0, want_forces=True, truncated=True, seg=8)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    truncated = {"backward_s": t6 - t5, "seg": 8, "solve_iters_max": int(max(st_t["iters"][:w.k])),
+                 "force_rel_diff_vs_implicit": float(np.abs(F_t - F).max() / np.abs(F).max()),
+                 "grad_rel_diff_vs_implicit": float((g_t - g).abs().max() / g.abs().max())}
+    del g_t
     E = []
     for sgn in (1, -1):
         R = R0.copy()
@@ -551,7 +562,7 @@ def differentiation_leg(np, warm_steps=2, atom=0, axis=0, h=1e-4):
            "res_inner": rep["res_inner"], "adjoint_converged": bool(st["converged"]),
            "force_check": {"atom": atom, "axis": axis, "h": h, "adjoint": f_adj, "central_fd": f_fd,
                            "rel_err": abs(f_adj - f_fd) / max(abs(f_fd), 1e-300)},
-           "grad_q_values": int(g.numel()), "pulay": pulay}
+           "grad_q_values": int(g.numel()), "pulay": pulay, "truncated_reverse": truncated}
     ctx.close()
     return out
 
