@@ -225,3 +225,27 @@ def test_initial_guess_on_nested_mesh_is_the_coarse_mesh_problem():
         Kc, Mc = 0.5 * pc.K_II.toarray(), pc.M_II.toarray()
         assert np.abs(Kc @ U - (Mc @ U) * th[None, :]).max() < 1e-10
         assert np.abs(Psi.T @ (pf.M_II @ Psi) - np.eye(k)).max() < 1e-10
+
+
+def test_conditioned_pencil_equals_the_plain_formulation():
+    """The oracle M-orthogonalises psi_hat against span(P), scales the pencil
+    and drops the shift mu (its conditioning devices).  The plain form of the
+    step -- Z = [P | psi_hat] with psi_hat from a dense solve, the shifted
+    pencil (Z^T (A + mu M) Z, Z^T M Z), no scaling -- spans the same space and
+    must give the same Ritz values: in the linear case directly, in the
+    nonlinear case with the step's final Hamiltonian."""
+    for p, kw in ((_tiny_linear(k=3), dict(tol_solve=1e-14)),
+                  (_tiny_nonlinear(order=1, n=5), dict(tol_solve=1e-14, tol_inner=1e-12, tol_poisson=1e-14))):
+        k = 3 if not p.hartree else 5
+        th0, Psi = initial_guess(p, k)
+        r = ks_scf_step(p, Psi, th0, **kw)
+        Mm = p.M_II.toarray()
+        S = r.extra["S"].toarray()
+        Psi_hat = np.linalg.solve(S, (Mm @ Psi) * (th0 + p.mu)[None, :])
+        A = p.A_linear()
+        if p.hartree or p.xc_mode != "none":
+            A = A + p.potential_matrix(r.extra["vnl_in"])
+        A = A.toarray()
+        Z = np.hstack([p.P, Psi_hat])
+        lam = sla.eigh(Z.T @ (A + p.mu * Mm) @ Z, Z.T @ Mm @ Z, eigvals_only=True)[:k] - p.mu
+        assert np.abs(lam - r.lam).max() < 1e-9 * np.abs(lam).max()
