@@ -521,6 +521,23 @@ int ks_stream_probe(int64_t bytes, int32_t kind, int32_t nontemporal, int32_t re
  * rejected.  Requires a prior ks_assemble. */
 int ks_autotune(ks_ctx *ctx, int32_t k, int32_t reps, double *report_host);
 
+/* ks_autotune behind a cache file (a text file at `path`, host string).  Key:
+ * the device's architecture name, the element order, floor(log2 N), the
+ * rounded nonzeros per row of S, k, and the solver precision (fp64, fp32;
+ * poisson with k = 1).  Value: lanes per row, tile rows, tile threads (0 0:
+ * row kernel) and the time measured when the entry was written.  If the file
+ * holds entries for all three solvers under this key (the last matching
+ * line wins, lines that do not parse are skipped), each is checked as
+ * ks_autotune checks a candidate (the tiling exists, fits for this k and its
+ * q = S p agrees with the row kernel's) and applied: *hit_host = 1, nothing
+ * is timed.  Otherwise (missing file included) ks_autotune(ctx, k, reps)
+ * runs and its three choices are appended to the file in one write:
+ * *hit_host = 0.  hit_host may be NULL.  Errors: those of ks_autotune;
+ * KS_ERR_ARG for a NULL or empty path, or when the file cannot be appended to
+ * (the tuned choice is applied all the same).  Processes that share a file
+ * append whole entries; a file is never rewritten or truncated. */
+int ks_autotune_cached(ks_ctx *ctx, int32_t k, int32_t reps, const char *path, int32_t *hit_host);
+
 /* SpMM-phase kernels in use: out_host[0..8] = {NG fp64, NG fp32, NG Poisson
  * (row kernel lanes per row), tile rows fp64, fp32, Poisson (0 = row
  * kernel), tile workgroup threads fp64, fp32, Poisson}.  The tiled kernel is used only where its

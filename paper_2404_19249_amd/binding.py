@@ -112,6 +112,7 @@ _SIGS = {
     "ks_spmm_config": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "ks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "ks_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "ks_autotune_cached": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int32)]),
     "ks_set_external": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "ks_step_energy": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "ks_step_backward": (C.c_int, [_P, C.c_double, _P, C.POINTER(C.c_double), C.POINTER(SolveStats)]),

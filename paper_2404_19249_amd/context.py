@@ -4,6 +4,7 @@ Every method marshals torch tensors (device memory) and numpy arrays (host
 inputs) into one C ABI call; the arithmetic happens in the HIP kernels.
 """
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -302,6 +303,15 @@ class KSContext:
                                    for i, br in enumerate([32, 64, 85, 128, 170, 256])
                                    for j, tb in enumerate([256, 512, 1024])}
         return out
+
+    def autotune_cached(self, k, path, reps=10):
+        """ks_autotune_cached: apply the cached SpMM-phase choice for this
+        device, order, size class, nonzeros per row and k from the text file
+        at `path`, or tune and append it.  Returns True on a cache hit."""
+        hit = C.c_int32(0)
+        B.check(self.lib.ks_autotune_cached(self.h, int(k), int(reps), os.fsencode(path), C.byref(hit)),
+                self.lib)
+        return bool(hit.value)
 
     def debug_buffer(self, name, n):
         """Copy of an internal buffer (diagnostics)."""

@@ -959,9 +959,10 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       }
     }
   }
-  // candidate row schedule: interior rows in Morton (Z-curve) order of their
+  // row schedule: interior rows in Morton (Z-curve) order of their
   // coordinates, so the workgroups in flight sweep compact 3D regions.  The
-  // natural order is the default; ks_autotune selects between them.
+  // unknowns are already stored in that order, so the solvers run in storage
+  // order (rorder = nullptr) and this schedule stays unused.
   std::vector<int32_t> rorder(N);
   {
     for (int r = 0; r < N; ++r) rorder[r] = r;
@@ -1627,6 +1628,163 @@ extern "C" int ks_autotune(ks_ctx *c, int32_t k, int32_t reps, double *report_ho
       for (int i = 0; i < NTB * ks_ctx::NTILE; ++i) report_host[21 + w * NTB * ks_ctx::NTILE + i] = t_til[w][i];
     }
   }
+  return KS_OK;
+}
+
+// ------------------------------------------------------- autotune cache
+// One text line per tuned solver: arch order log2N nnz/row k precision ng
+// tile_rows tile_threads ms.  The key is everything before ng; the last
+// matching line wins; lines that do not parse are skipped.
+namespace {
+struct TuneKey {
+  std::string arch;
+  int order = 0, log2n = 0, nnz_row = 0, k = 0;
+};
+const char *const TUNE_PREC[3] = {"fp64", "fp32", "poisson"};
+
+bool tune_key(const ks_ctx *c, int k, TuneKey *key) {
+  int dev = 0;
+  if (hipStreamGetDevice(c->s, &dev) != hipSuccess) return false;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+  key->arch.clear();
+  for (const char *q = p.gcnArchName; *q && key->arch.size() < 200; ++q)
+    key->arch.push_back((*q == ' ' || *q == '\t') ? '_' : *q);
+  if (key->arch.empty()) key->arch = "unknown";
+  key->order = c->order;
+  key->log2n = 0;
+  while ((2LL << key->log2n) <= (long long)c->N) ++key->log2n;
+  key->nnz_row = (int)((c->nnz + c->N / 2) / std::max(c->N, 1));
+  key->k = k;
+  return true;
+}
+
+struct TuneEntry {
+  bool found = false;
+  int ng = 0, rows = 0, threads = 0;
+};
+
+// last entry of each precision for this key (k = 1 for the Poisson solver)
+void tune_lookup(const char *path, const TuneKey &key, TuneEntry e[3]) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512], arch[256], prec[32];
+  while (std::fgets(line, sizeof line, f)) {
+    int order, log2n, nnz_row, k, ng, rows, threads;
+    double ms;
+    if (line[0] == '#') continue;
+    if (std::sscanf(line, "%255s %d %d %d %d %31s %d %d %d %lf", arch, &order, &log2n, &nnz_row, &k,
+                    prec, &ng, &rows, &threads, &ms) != 10)
+      continue;
+    if (key.arch != arch || order != key.order || log2n != key.log2n || nnz_row != key.nnz_row) continue;
+    for (int w = 0; w < 3; ++w)
+      if (!std::strcmp(prec, TUNE_PREC[w]) && k == (w == 2 ? 1 : key.k)) e[w] = {true, ng, rows, threads};
+  }
+  std::fclose(f);
+}
+}  // namespace
+
+// Is (ng, code) usable for solver w with kk columns: the tiling exists and
+// fits, and q = S p on a fixed p agrees with the one-lane row kernel's (the
+// tolerances of ks_autotune).
+static int check_choice(ks_ctx *c, int w, int kk, int ng, int code, bool *ok) {
+  PCGWork *ws[3] = {&c->pw64, &c->pw32, &c->pwP};
+  PCGWork &pw = *ws[w];
+  const int which = w == 0 ? 0 : (w == 1 ? 3 : 6);
+  const bool f32 = w == 1;
+  *ok = false;
+  if (code >= 0 && !c->til[code / NTB].nblk) return KS_OK;
+  if (f32) ensure_s32(c);
+  void *ref = nullptr;
+  if (hipMalloc(&ref, (f32 ? sizeof(float) : sizeof(double)) * (size_t)c->N * kk) != hipSuccess)
+    return fail(KS_ERR_NOMEM, "autotune cache: hipMalloc failed");
+  const Tiling *keep = pw.til;
+  const int keep_tb = pw.til_tb;
+  auto check = [&](int mode, double *dev) {
+    return f32 ? pcg_phase_check<float>(pw, c->N, kk, mode, ref, dev, c->s)
+               : pcg_phase_check<double>(pw, c->N, kk, mode, ref, dev, c->s);
+  };
+  double dev = 0.0;
+  float ms = 0.f;
+  int r = check(0, &dev);
+  pw.til = nullptr;
+  if (r == 0) r = time_phase(c, which, kk, 1, 1, &ms);
+  if (r == 0) r = check(1, &dev);
+  if (r == 0) {
+    pw.til = code >= 0 ? &c->til[code / NTB] : nullptr;
+    pw.til_tb = TILE_TB[code >= 0 ? code % NTB : 0];
+    r = time_phase(c, which, kk, 1, ng, &ms);
+    if (r == 0) {
+      r = check(2, &dev);
+      *ok = r == 0 && dev <= (f32 ? 1e-5 : 1e-12);
+    } else if (r == -3) {
+      r = 0;  // does not fit in LDS for this shape
+    }
+  }
+  pw.til = keep;
+  pw.til_tb = keep_tb;
+  (void)hipFree(ref);
+  return r < 0 ? fail(KS_ERR_HIP, "autotune cache: check launch failed") : KS_OK;
+}
+
+extern "C" int ks_autotune_cached(ks_ctx *c, int32_t k, int32_t reps, const char *path, int32_t *hit_host) {
+  if (!c || !path || !*path) return fail(KS_ERR_ARG, "null context or cache path");
+  if (k < 1 || k > c->k_max || reps < 1) return fail(KS_ERR_ARG, "bad k or reps");
+  if (!c->have_S) return fail(KS_ERR_STATE, "no operator assembled");
+  if (hit_host) *hit_host = 0;
+  TuneKey key;
+  if (!tune_key(c, k, &key)) return fail(KS_ERR_HIP, "autotune cache: device query failed");
+  TuneEntry e[3];
+  tune_lookup(path, key, e);
+  bool hit = e[0].found && e[1].found && e[2].found;
+  int ng[3] = {1, 1, 1}, code[3] = {-1, -1, -1};
+  for (int w = 0; hit && w < 3; ++w) {
+    const int ti = e[w].rows ? tile_index(e[w].rows) : -1;
+    const int tb = e[w].threads == 256 ? 0 : (e[w].threads == 512 ? 1 : (e[w].threads == 1024 ? 2 : -1));
+    const bool ng_ok = e[w].ng == 1 || e[w].ng == 2 || e[w].ng == 4 || e[w].ng == 8;
+    if (!ng_ok || (e[w].rows && (ti < 0 || tb < 0))) {
+      hit = false;
+      break;
+    }
+    ng[w] = e[w].ng;
+    code[w] = e[w].rows ? NTB * ti + tb : -1;
+    bool ok = false;
+    TRY(check_choice(c, w, w == 2 ? 1 : k, ng[w], code[w], &ok));
+    hit = ok;
+  }
+  if (hit) {
+    c->rorder = nullptr;
+    c->ng64 = ng[0];
+    c->ng32 = ng[1];
+    c->ngP = ng[2];
+    c->tile64 = code[0];
+    c->tile32 = code[1];
+    c->tileP = code[2];
+    apply_tiles(c);
+    if (hit_host) *hit_host = 1;
+    return KS_OK;
+  }
+  std::vector<double> rep(21 + 3 * NTB * ks_ctx::NTILE);
+  TRY(ks_autotune(c, k, reps, rep.data()));
+  std::string text;
+  for (int w = 0; w < 3; ++w) {
+    const int g = (int)rep[w], rows = (int)rep[3 + w], tb = (int)rep[6 + w];
+    int gi = 0;
+    while (gi < 3 && (1 << gi) != g) ++gi;
+    const double ms = rows ? rep[21 + w * NTB * ks_ctx::NTILE + NTB * tile_index(rows) +
+                                 (tb == 256 ? 0 : (tb == 512 ? 1 : 2))]
+                           : rep[9 + w * 4 + gi];
+    char line[512];
+    std::snprintf(line, sizeof line, "%s %d %d %d %d %s %d %d %d %.6g\n", key.arch.c_str(), key.order,
+                  key.log2n, key.nnz_row, w == 2 ? 1 : k, TUNE_PREC[w], g, rows, tb, ms);
+    text += line;
+  }
+  // one append of all three lines, so that concurrent writers do not
+  // interleave within an entry
+  FILE *f = std::fopen(path, "a");
+  const bool wrote = f && std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  const bool closed = f && std::fclose(f) == 0;
+  if (!wrote || !closed) return fail(KS_ERR_ARG, "autotune cache: cannot append to the cache file");
   return KS_OK;
 }
 

@@ -134,6 +134,66 @@ def test_stream_probe_reports_a_bandwidth_below_the_peak():
         stream_probe("read", 1024)
 
 
+def test_autotune_cache_file(tmp_path):
+    """ks_autotune_cached: a missing file is a miss that tunes and appends one
+    entry (fp64, fp32 and Poisson lines) keyed by device, order, size class,
+    nonzeros per row and k; a second context of the same workload hits it
+    and ends with the same kernels without tuning; another k misses; an entry
+    naming a row block that does not exist, and lines that do not parse, are
+    skipped; a block solve with the cached kernels reaches its tolerance."""
+    k = 8
+    w = make_workload("mixed", n=12, order=2, k=k)
+    path = tmp_path / "spmm_tune.txt"
+
+    def fresh():
+        c = _ctx(w, k_max=k, tol_solve=1e-10)
+        psi, _ = c.initial_guess(k)
+        c.assemble(psi, w.occ, want_fields=False)
+        return c
+
+    a = fresh()
+    assert not a.autotune_cached(k, path, reps=2)
+    f = [ln.split() for ln in path.read_text().splitlines()]
+    assert [x[5] for x in f] == ["fp64", "fp32", "poisson"]
+    assert [int(x[4]) for x in f] == [k, k, 1]
+    assert all(len(x) == 10 and x[0].startswith("gfx") and x[1] == "2" for x in f)
+    log2n = int(f[0][2])
+    assert 2 ** log2n <= a.N < 2 ** (log2n + 1)
+    cfg = a.spmm_config()
+    for x, n in zip(f, ("fp64", "fp32", "poisson")):
+        assert (int(x[6]), int(x[7]), int(x[8])) == (cfg[f"ng_{n}"], cfg[f"tile_{n}"],
+                                                      cfg[f"tile_threads_{n}"]), (x, cfg)
+        assert float(x[9]) > 0.0
+    a.close()
+
+    b = fresh()
+    assert b.autotune_cached(k, path, reps=2)
+    assert b.spmm_config() == cfg
+    assert len(path.read_text().splitlines()) == 3
+    assert not b.autotune_cached(4, path, reps=2)
+    assert len(path.read_text().splitlines()) == 6
+    assert b.autotune_cached(4, path, reps=2)
+
+    bad = tmp_path / "bad.txt"
+    bad_fp64 = f[0][:7] + ["77", "512", "0.1"]
+    bad.write_text("not an entry\n" + " ".join(bad_fp64) + "\n" +
+                   "\n".join(" ".join(x) for x in f[1:]) + "\n")
+    assert not b.autotune_cached(k, bad, reps=2)
+    assert len(bad.read_text().splitlines()) == 4 + 3
+    assert b.autotune_cached(k, bad, reps=2)
+
+    S = _csr(b, 0)
+    rng = np.random.default_rng(11)
+    Bh = rng.standard_normal((b.N, k))
+    for prec in ("fp64", "mixed"):
+        X, st = b.block_solve_rhs(torch.tensor(Bh, device=DEV), precision=prec)
+        rel = np.linalg.norm(Bh - S @ X.cpu().numpy(), axis=0) / np.linalg.norm(Bh, axis=0)
+        assert st["converged"] and rel.max() <= 1e-10 * 1.0001, (prec, rel.max())
+    with pytest.raises(KSError):
+        b.autotune_cached(k, "", reps=2)
+    b.close()
+
+
 @pytest.mark.parametrize("k", [8, 24])
 def test_autotuned_kernels_agree_and_solve(k):
     """ks_autotune checks every SpMM-phase candidate (row kernels, halo
