@@ -309,6 +309,7 @@ def batched_leg(torch, np, reps=3):
            "p99_system_ms": float(np.percentile(ss, 99)), "max_system_ms": float(ss.max()),
            "sequential_device_ms": sum(seq) * 1e3, "speedup_vs_sequential": sum(seq) / t,
            "grid": b.grid, "autotune_best_ms": tuned_ms,
+           "tiled_systems": sum(1 for x in b.tile if x),
            "iteration_GBs": byt / t / 1e9, "relres_max": float(max(st["relres"])),
            "setup_s": setup}
     b.close()

@@ -446,7 +446,12 @@ int ks_step_backward_mesh(ks_ctx *ctx, double dE, const double *motion, double *
  * Workgroups form per-system teams proportional to nnz_s k_s (grid = the
  * resident workgroup count, or grid_req if smaller); the lanes-per-row split
  * of each system comes from its context's autotuned choice (ks_autotune) or
- * a rule by k.  Systems must outlive the batch and keep their operators. */
+ * a rule by k.  A system's products S_s P_s run through one of its
+ * context's halo tilings (row blocks staged in LDS) when that tiling's halo
+ * image (largest halo x k_s doubles) fits the LDS the launch can take at its
+ * grid; the largest such row block is the default, else row products from
+ * the CSR arrays.  Systems must outlive the batch and keep their
+ * operators. */
 typedef struct ks_batch ks_batch;
 typedef struct {
   double seconds;               /* whole launch (HIP events) */
@@ -458,8 +463,18 @@ typedef struct {
 } ks_batch_stats;
 int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t *k_host, int32_t grid_req,
                     ks_batch **out);
-/* grid_host: workgroups of the launch; team_host/ng_host [n] (may be NULL) */
-int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host, int32_t *ng_host);
+/* grid_host: workgroups of the launch; team_host/ng_host/tile_host [n] (each
+ * may be NULL): team size, lanes per row, and rows per halo-tile block of
+ * each system's products (0: row products) */
+int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host, int32_t *ng_host,
+                  int32_t *tile_host);
+/* Sets the layout by hand: ng_host [n] lanes per row (1, 2, 4 or 8, with
+ * lanes x k_s <= 64) and tile_host [n] rows per halo-tile block (0: row
+ * products; else 32, 64, 85, 128, 170 or 256, a tiling the system's context
+ * holds whose halo image fits the launch's LDS); either may be NULL to keep
+ * the current choice.  KS_ERR_ARG, with nothing changed, for a value that
+ * is not available.  Team sizes and the grid are kept. */
+int ks_batch_set_layout(ks_batch *b, const int32_t *ng_host, const int32_t *tile_host);
 /* psi_old[s], psi_hat[s]: device [N_s][k_s]; lambda_host[s]: host [k_s].
  * Host arrays of pointers. */
 int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
@@ -467,9 +482,10 @@ int ks_batch_block_solve(ks_batch *b, const double *const *psi_old,
                          ks_batch_stats *st_host);
 /* Autotuner of the batch layout on these inputs (same arguments as the
  * solve; outputs discarded).  For each candidate grid (the resident
- * workgroup count, 3/4, 1/2 and 1/4 of it): lanes per row per system from
- * one run at each candidate, then `rounds` feedback rounds that resize the
- * teams so that measured completion times equalise.  Keeps the fastest
+ * workgroup count, 3/4, 1/2 and 1/4 of it): lanes per row and product form
+ * (row products, or halo tiles of 32, 64, 128 or 256 rows where they fit)
+ * per system from one run at each candidate, then `rounds` feedback rounds
+ * that resize the teams so that measured completion times equalise.  Keeps the fastest
  * layout (and re-captures the graph for its grid); best_ms (host, may be
  * NULL) receives its launch time. */
 int ks_batch_autotune(ks_batch *b, const double *const *psi_old, const double *const *lambda_host,

@@ -120,7 +120,8 @@ _SIGS = {
     "ks_batch_create": (C.c_int, [C.c_int32, C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32,
                                   C.POINTER(_P)]),
     "ks_batch_info": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                C.POINTER(C.c_int32)]),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "ks_batch_set_layout": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ks_batch_block_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.POINTER(C.c_double)),
                                        C.POINTER(_P), C.POINTER(BatchStats)]),
     "ks_batch_autotune": (C.c_int, [_P, C.POINTER(_P), C.POINTER(C.POINTER(C.c_double)), C.c_int32,

@@ -423,8 +423,9 @@ class KSBatch:
         g = C.c_int32()
         team = (C.c_int32 * n)()
         ng = (C.c_int32 * n)()
-        B.check(self.lib.ks_batch_info(self.h, C.byref(g), team, ng), self.lib)
-        self.grid, self.team, self.ng = g.value, list(team), list(ng)
+        tile = (C.c_int32 * n)()
+        B.check(self.lib.ks_batch_info(self.h, C.byref(g), team, ng, tile), self.lib)
+        self.grid, self.team, self.ng, self.tile = g.value, list(team), list(ng), list(tile)
 
     def _args(self, psis, lams):
         n = len(self.ctxs)
@@ -435,6 +436,14 @@ class KSBatch:
         pp = (C.c_void_p * n)(*[c._ptr(p).value for c, p in zip(self.ctxs, psis)])
         ll = (C.POINTER(C.c_double) * n)(*[B.dptr(l) for l in lam_a])
         return pp, ll, lam_a
+
+    def set_layout(self, ng=None, tile=None):
+        """ks_batch_set_layout: lanes per row and halo-tile row block (0: row
+        products) per system; None keeps the current choice."""
+        n = len(self.ctxs)
+        arr = lambda v: None if v is None else (C.c_int32 * n)(*[int(x) for x in v])
+        B.check(self.lib.ks_batch_set_layout(self.h, arr(ng), arr(tile)), self.lib)
+        self._info()
 
     def autotune(self, psis, lams, rounds=3):
         """ks_batch_autotune on these inputs; returns the best launch time (ms)."""

@@ -23,6 +23,14 @@
 // issues loads of other workgroups' data only after it has observed every
 // arrival.  Everything else (the matrix, B, and the R, Q, X rows a
 // workgroup owns) uses ordinary cached accesses.
+//
+// Halo tiles.  A system whose context carries a row-block tiling (blocks of
+// BR consecutive storage rows, each with the sorted list of rows its
+// nonzeros touch and 16-bit local column indices) runs its products
+// through it: the team owns whole blocks, each block's halo rows of P are
+// loaded once, coherently, into LDS, and the rows then gather from LDS.
+// The coherent traffic per product drops from one load per nonzero and
+// column to one per halo row and column.
 #include "common.h"
 #include "kernels.h"
 #include <algorithm>
@@ -37,6 +45,11 @@ struct BatchSys {
   double *part;          // shared by all systems: [grid][3 phases][3 MAX_K]
   unsigned int *bar;     // [2]: arrival count since launch start, unused
   int N, k, ng, team0, team, max_iter;
+  // halo tiling (tile_br = 0: row products from the CSR arrays)
+  int tile_br, tile_nblk;
+  const int32_t *halo_ptr, *halo_col, *hself, *pptr;
+  const uint16_t *lcol;
+  const uint32_t *rmeta;
   double tol;
   int *iters;            // [k]
   double *relres;        // [k]
@@ -132,8 +145,55 @@ __device__ __forceinline__ void team_sum(const double *part, int team, int W, do
   __syncthreads();
 }
 
+// Q = S P on the rows of tile blocks [b0, b1) of system d through LDS
+// (s_halo: at least max_halo * k doubles), with this lane's share of the
+// p.q partial of column c added to apq
+__device__ __forceinline__ void batch_tiled_product(const BatchSys &d, int b0, int b1, int k, int c, int ng,
+                                                    int NG, bool valid, int slot, int wave, int RPW,
+                                                    double *s_halo, double &apq) {
+  const int BR = d.tile_br, rows_per_iter = (blockDim.x >> 6) * RPW;
+  for (int blk = b0; blk < b1; ++blk) {
+    const int hb = d.halo_ptr[blk], nh = d.halo_ptr[blk + 1] - hb;
+    for (int i = threadIdx.x; i < nh * k; i += blockDim.x) {
+      const int h = i / k, cc = i - h * k;
+      s_halo[i] = ld_coh(d.P + (int64_t)d.halo_col[hb + h] * k + cc);
+    }
+    __syncthreads();
+    const int rb = blk * BR, nr = min(BR, d.N - rb);
+    const int nz0 = d.rowptr[rb], p0 = d.pptr[blk], hs = d.hself[blk];
+    for (int sb = 0; sb < nr; sb += rows_per_iter) {
+      const int sl = sb + wave * RPW + slot;
+      const bool rv = valid && sl < nr;
+      double acc = 0.0;
+      int rr = 0;
+      if (rv) {
+        const uint32_t m0 = d.rmeta[2 * (int64_t)(rb + sl)], m1 = d.rmeta[2 * (int64_t)(rb + sl) + 1];
+        const int len = (int)((m0 >> 16) & 0xffu);
+        rr = (int)(m0 >> 24);
+        const double *v = d.val + nz0 + (m0 & 0xffffu);
+        const uint16_t *lc = d.lcol + p0 + m1;
+        double a1 = 0.0;
+        int j = ng;
+        for (; j + NG < len; j += 2 * NG) {
+          acc += v[j] * s_halo[(int)lc[j] * k + c];
+          a1 += v[j + NG] * s_halo[(int)lc[j + NG] * k + c];
+        }
+        if (j < len) acc += v[j] * s_halo[(int)lc[j] * k + c];
+        acc += a1;
+      }
+      for (int off = 1; off < NG; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (rv && ng == 0) {
+        d.Q[(int64_t)(rb + rr) * k + c] = acc;
+        apq += s_halo[(hs + rr) * k + c] * acc;
+      }
+    }
+    __syncthreads();  // the next block's halo overwrites s_halo
+  }
+}
+
 __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ systems,
                                                    const int *__restrict__ wg_sys) {
+  extern __shared__ double s_halo[];
   __shared__ double s_red[256];
   __shared__ double s_sum[3 * MAX_K];
   __shared__ double s_part[3 * MAX_K];
@@ -149,9 +209,19 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   const int slot = lane / LPR, rem = lane % LPR, c = rem / NG, ng = rem % NG;
   const bool valid = slot < RPW;
   const int rows_per_iter = (blockDim.x >> 6) * RPW;
-  // contiguous row range of this workgroup
-  const int chunk = (d.N + team - 1) / team;
-  const int r0 = rank * chunk, r1 = min(d.N, r0 + chunk);
+  // contiguous row range of this workgroup (whole tile blocks when tiled)
+  int r0, r1, b0 = 0, b1 = 0;
+  if (d.tile_br > 0) {
+    const int per = (d.tile_nblk + team - 1) / team;
+    b0 = min(d.tile_nblk, rank * per);
+    b1 = min(d.tile_nblk, b0 + per);
+    r0 = min(d.N, b0 * d.tile_br);
+    r1 = min(d.N, b1 * d.tile_br);
+  } else {
+    const int chunk = (d.N + team - 1) / team;
+    r0 = min(d.N, rank * chunk);
+    r1 = min(d.N, r0 + chunk);
+  }
   // partials of team member t (global workgroup team0 + t), phase ph
   const int W3 = 3 * k;
   constexpr int PS = 9 * MAX_K;
@@ -202,6 +272,9 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   for (; it < d.max_iter && s_flags[0] && !s_flags[1]; ++it) {
     // ---- A: Q = S P, p.q
     double apq = 0.0;
+    if (d.tile_br > 0)
+      batch_tiled_product(d, b0, b1, k, c, ng, NG, valid, slot, wave, RPW, s_halo, apq);
+    else
     for (int base = r0; base < r1; base += rows_per_iter) {
       const int row = base + wave * RPW + slot;
       const bool rv = valid && row < r1;
@@ -301,8 +374,8 @@ __global__ void k_batch_reset(BatchSys *systems, int n, unsigned long long *t0) 
 void launch_batch_reset(void *systems, int n, unsigned long long *t0, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, reinterpret_cast<BatchSys *>(systems), n, t0);
 }
-void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_pcg, dim3(grid), dim3(256), 0, s,
+void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_pcg, dim3(grid), dim3(256), lds, s,
                      reinterpret_cast<const BatchSys *>(systems), wg_sys);
 }
 size_t batch_sys_bytes() { return sizeof(BatchSys); }
@@ -315,6 +388,30 @@ int batch_resident_grid() {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
   return per_cu * cus;
 }
+// Largest dynamic LDS (bytes, multiple of 1 KiB, at most 64 KiB) with which
+// a grid of `grid` workgroups stays resident; -1 if the query fails.
+int64_t batch_lds_budget(int grid) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return -1;
+  const int need = (grid + cus - 1) / cus;  // workgroups per CU
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void *)k_batch_pcg, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024) !=
+        hipSuccess)
+      return -1;
+    attr_set = true;
+  }
+  for (int64_t lds = 64 * 1024; lds > 0; lds -= 1024) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_pcg, 256, (size_t)lds) !=
+        hipSuccess)
+      return -1;
+    if (per_cu >= need) return lds;
+  }
+  return 0;
+}
 
 // Host-side description of one system (filled by the runtime), packed into
 // the device table by pack_batch.
@@ -322,8 +419,16 @@ void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const 
                     const double *diag, const double *B, double *X, double *R, double *P, double *Q,
                     double *part, unsigned int *bar, int N, int k, int ng, int team0, int team,
                     int max_iter, double tol, int *iters, double *relres,
-                    unsigned long long *t_done, int *status) {
+                    unsigned long long *t_done, int *status, const Tiling *til) {
   BatchSys s;
+  s.tile_br = til ? til->BR : 0;
+  s.tile_nblk = til ? til->nblk : 0;
+  s.halo_ptr = til ? til->halo_ptr : nullptr;
+  s.halo_col = til ? til->halo_col : nullptr;
+  s.hself = til ? til->hself : nullptr;
+  s.pptr = til ? til->pptr : nullptr;
+  s.lcol = til ? til->lcol : nullptr;
+  s.rmeta = til ? til->rmeta : nullptr;
   s.rowptr = rowptr; s.col = col; s.val = val; s.diag = diag; s.B = B;
   s.X = X; s.R = R; s.P = P; s.Q = Q; s.part = part; s.bar = bar;
   s.N = N; s.k = k; s.ng = ng; s.team0 = team0; s.team = team; s.max_iter = max_iter;

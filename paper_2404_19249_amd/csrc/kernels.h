@@ -378,13 +378,17 @@ namespace ks {
 size_t batch_sys_bytes();
 size_t batch_part_stride();
 int batch_resident_grid();
+// dynamic LDS (bytes) the batched kernel can take with `grid` workgroups resident
+int64_t batch_lds_budget(int grid);
+// til: the system's halo tiling (nullptr: row products from the CSR arrays)
 void pack_batch_sys(void *dst, const int32_t *rowptr, const int32_t *col, const double *val,
                     const double *diag, const double *B, double *X, double *R, double *P, double *Q,
                     double *part, unsigned int *bar, int N, int k, int ng, int team0, int team,
                     int max_iter, double tol, int *iters, double *relres,
-                    unsigned long long *t_done, int *status);
+                    unsigned long long *t_done, int *status, const Tiling *til);
 void launch_batch_reset(void *systems, int n, unsigned long long *t0, hipStream_t s);
-void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, hipStream_t s);
+// lds: dynamic LDS bytes, at least max_halo * k * 8 of every tiled system
+void launch_batch_pcg(int grid, const void *systems, const int *wg_sys, size_t lds, hipStream_t s);
 }  // namespace ks
 
 namespace ks {

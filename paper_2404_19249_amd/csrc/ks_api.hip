@@ -2169,6 +2169,10 @@ struct ks_batch {
   hipStream_t s = nullptr;
   std::vector<ks_ctx *> sys;
   std::vector<int> k, team, team0, ng;
+  // per system the halo tiling its products use (index into the context's
+  // tilings, -1: row products) when it fits the launch's LDS
+  std::vector<int> tile;
+  size_t lds = 0;              // dynamic LDS of the launch (keeps `grid` resident)
   std::vector<double> weight;  // relative cost per system, drives the team split
   DevBuf mem;
   void *table = nullptr;
@@ -2203,6 +2207,30 @@ static int batch_ng_cap(int k, int ng) {
   return ng;
 }
 
+// the tiling system i uses under the current LDS budget (nullptr: row
+// products): tile ti when it exists and its halo image fits
+static const Tiling *batch_tiling(const ks_batch *b, int i, int ti) {
+  if (ti < 0 || ti >= ks_ctx::NTILE) return nullptr;
+  const Tiling &t = b->sys[i]->til[ti];
+  if (!t.nblk || (size_t)t.max_halo * b->k[i] * sizeof(double) > b->lds) return nullptr;
+  return &t;
+}
+// the launch's LDS budget for the current grid; every system's default
+// tiling: the largest row block whose halo image fits
+static int batch_set_grid(ks_batch *b, int grid, bool reset_tiles) {
+  b->grid = grid;
+  const int64_t lds = batch_lds_budget(grid);
+  if (lds < 0) return fail(KS_ERR_HIP, "batch: occupancy query failed");
+  b->lds = (size_t)lds;
+  if (reset_tiles)
+    for (int i = 0; i < b->n; ++i) {
+      b->tile[i] = -1;
+      for (int ti = ks_ctx::NTILE - 1; ti >= 0 && b->tile[i] < 0; --ti)
+        if (batch_tiling(b, i, ti)) b->tile[i] = ti;
+    }
+  return KS_OK;
+}
+
 // Teams proportional to the weights (largest remainders), at least one
 // workgroup each, summing to the grid; table and workgroup map uploaded.
 static int batch_layout(ks_batch *b) {
@@ -2235,7 +2263,8 @@ static int batch_layout(ks_batch *b) {
                    (double *)c->pw64.R, (double *)c->pw64.P, (double *)c->pw64.Q, b->part,
                    b->bar + 2 * i, c->N, b->k[i], b->ng[i], b->team0[i], b->team[i],
                    c->opt.max_it_solve, c->opt.tol_solve, b->iters + (size_t)i * MAX_K,
-                   b->relres + (size_t)i * MAX_K, b->t_done + i, b->status + i);
+                   b->relres + (size_t)i * MAX_K, b->t_done + i, b->status + i,
+                   batch_tiling(b, i, b->tile[i]));
   }
   // the launch reads these at its start: upload synchronously
   HIPCHK(hipMemcpyAsync(b->table, tab.data(), tab.size(), hipMemcpyHostToDevice, b->s));
@@ -2258,7 +2287,7 @@ static int batch_capture(ks_batch *b) {
   hipStream_t s = b->s;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   launch_batch_reset(b->table, b->n, b->t0, s);
-  launch_batch_pcg(b->grid, b->table, b->wg_sys, s);
+  launch_batch_pcg(b->grid, b->table, b->wg_sys, b->lds, s);
   HIPCHK(hipStreamEndCapture(s, &b->graph));
   HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   return KS_OK;
@@ -2294,9 +2323,11 @@ extern "C" int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t 
   }
   const int resident = batch_resident_grid();
   if (resident <= 0) return bail(fail(KS_ERR_HIP, "occupancy query failed"));
-  b->grid = grid_req > 0 ? std::min<int>(grid_req, resident) : resident;
-  if (b->grid < n) return bail(fail(KS_ERR_ARG, "more systems than resident workgroups"));
-  b->grid_max = b->grid;
+  const int grid = grid_req > 0 ? std::min<int>(grid_req, resident) : resident;
+  if (grid < n) return bail(fail(KS_ERR_ARG, "more systems than resident workgroups"));
+  b->grid_max = grid;
+  b->tile.assign(n, -1);
+  if (batch_set_grid(b, grid, true) < 0) return bail(KS_ERR_HIP);
   b->team.assign(n, 1);
   b->team0.assign(n, 0);
   if (b->alloc(reinterpret_cast<char **>(&b->table), batch_sys_bytes() * n) < 0 ||
@@ -2319,14 +2350,41 @@ extern "C" int ks_batch_create(int32_t n, ks_ctx *const *systems, const int32_t 
 }
 
 extern "C" int ks_batch_info(const ks_batch *b, int32_t *grid_host, int32_t *team_host,
-                             int32_t *ng_host) {
+                             int32_t *ng_host, int32_t *tile_host) {
   if (!b) return fail(KS_ERR_ARG, "null batch");
   if (grid_host) *grid_host = b->grid;
   for (int i = 0; i < b->n; ++i) {
     if (team_host) team_host[i] = b->team[i];
     if (ng_host) ng_host[i] = b->ng[i];
+    if (tile_host) {
+      const Tiling *t = batch_tiling(b, i, b->tile[i]);
+      tile_host[i] = t ? t->BR : 0;
+    }
   }
   return KS_OK;
+}
+
+extern "C" int ks_batch_set_layout(ks_batch *b, const int32_t *ng_host, const int32_t *tile_host) {
+  if (!b) return fail(KS_ERR_ARG, "null batch");
+  std::vector<int> ng = b->ng, tile = b->tile;
+  for (int i = 0; i < b->n; ++i) {
+    if (ng_host) {
+      const int g = ng_host[i];
+      if ((g != 1 && g != 2 && g != 4 && g != 8) || g * b->k[i] > 64)
+        return fail(KS_ERR_ARG, "lanes per row must be 1, 2, 4 or 8 with lanes x k <= 64");
+      ng[i] = g;
+    }
+    if (tile_host) {
+      const int rows = tile_host[i];
+      const int ti = rows ? tile_index(rows) : -1;
+      if (rows && !batch_tiling(b, i, ti))
+        return fail(KS_ERR_ARG, "system " + std::to_string(i) + " has no halo tiling of that row block fitting the launch's LDS");
+      tile[i] = ti;
+    }
+  }
+  b->ng = ng;
+  b->tile = tile;
+  return batch_layout(b);
 }
 
 // right-hand sides B_s = M_s psi_s diag(lambda_s + mu_s), X_s = psi_s
@@ -2425,7 +2483,7 @@ extern "C" int ks_batch_autotune(ks_batch *b, const double *const *psi_old,
   const std::vector<double> w0 = b->weight;
   double best = 1e300;
   int best_grid = b->grid;
-  std::vector<int> best_ng = b->ng;
+  std::vector<int> best_ng = b->ng, best_tile = b->tile;
   std::vector<double> best_w = b->weight;
   auto run = [&]() -> int {
     TRY(batch_layout(b));
@@ -2436,34 +2494,47 @@ extern "C" int ks_batch_autotune(ks_batch *b, const double *const *psi_old,
   for (int frac : {4, 3, 2, 1}) {
     const int g = b->grid_max * frac / 4;
     if (g < n) continue;
-    b->grid = g;
+    TRY(batch_set_grid(b, g, false));
     TRY(batch_capture(b));
     b->weight = w0;
     std::vector<double> t_best(n, 1e300);
-    std::vector<int> ng_best(b->ng);
-    for (int ng : {1, 2, 4, 8}) {
-      for (int i = 0; i < n; ++i) b->ng[i] = batch_ng_cap(b->k[i], ng);
-      TRY(run());
-      for (int i = 0; i < n; ++i)
-        if (st.system_seconds[i] < t_best[i]) {
-          t_best[i] = st.system_seconds[i];
-          ng_best[i] = b->ng[i];
+    std::vector<int> ng_best(b->ng), tile_best(b->tile);
+    // every system on the row products, then on each tiling that fits it
+    // (row blocks of 32, 64, 128 and 256 rows), at every lanes-per-row split
+    for (int ti : {-1, 0, 1, 3, 5})
+      for (int ng : {1, 2, 4, 8}) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) {
+          b->ng[i] = batch_ng_cap(b->k[i], ng);
+          b->tile[i] = batch_tiling(b, i, ti) ? ti : -1;
+          any = any || b->tile[i] >= 0;
         }
-    }
+        if (ti >= 0 && !any) continue;
+        TRY(run());
+        for (int i = 0; i < n; ++i)
+          if ((ti < 0 || b->tile[i] >= 0) && st.system_seconds[i] < t_best[i]) {
+            t_best[i] = st.system_seconds[i];
+            ng_best[i] = b->ng[i];
+            tile_best[i] = b->tile[i];
+          }
+      }
     b->ng = ng_best;
+    b->tile = tile_best;
     for (int r = 0; r < std::max(1, (int)rounds); ++r) {
       TRY(run());
       if (st.seconds < best) {
         best = st.seconds;
         best_grid = g;
         best_ng = b->ng;
+        best_tile = b->tile;
         best_w = b->weight;
       }
       for (int i = 0; i < n; ++i) b->weight[i] = std::max(st.system_seconds[i], 1e-7) * b->team[i];
     }
   }
-  b->grid = best_grid;
+  TRY(batch_set_grid(b, best_grid, false));
   b->ng = best_ng;
+  b->tile = best_tile;
   b->weight = best_w;
   TRY(batch_layout(b));
   TRY(batch_capture(b));

@@ -85,6 +85,42 @@ def test_batched_solve_follows_new_inputs_and_matches_oracle():
     b.close()
 
 
+def test_batched_row_and_tile_products_agree():
+    """Both product forms of the batched kernel -- row products from the CSR
+    arrays and halo tiles staged in LDS, at every row block a system can
+    take -- give the single-system solutions; a row block that does not exist
+    and a lanes-per-row split that does not fit are refused."""
+    from paper_2404_19249_amd import KSBatch, KSError
+    ws, ctxs, psis, lams = _systems(6, 9)
+    n = len(ws)
+    refs = [c.block_solve(p, l)[0].cpu().numpy() for c, p, l in zip(ctxs, psis, lams)]
+    b = KSBatch(ctxs, [w.k for w in ws], grid=4 * n)   # few workgroups: room in LDS
+    tiled = 0
+    for br in (0, 32, 64, 85, 128, 170, 256):
+        t = [0] * n
+        for i in range(n if br else 0):
+            t[i] = br
+            try:
+                b.set_layout(tile=t)
+            except KSError:
+                t[i] = 0
+        b.set_layout(tile=t)
+        assert b.tile == t
+        tiled += sum(1 for x in t if x)
+        print(f"[case] rows per tile {br}: tiled {t}", flush=True)
+        outs, st = b.block_solve(psis, lams)
+        assert st["status"] == 0
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert _rel(o.cpu().numpy(), r) < 1e-10, (br, i)
+            assert st["relres"][i] < 1e-12
+    assert tiled >= n
+    with pytest.raises(KSError):
+        b.set_layout(tile=[77] * n)
+    with pytest.raises(KSError):
+        b.set_layout(ng=[3] * n)
+    b.close()
+
+
 def test_batch_rejects_bad_arguments():
     from paper_2404_19249_amd import KSBatch, KSError
     ws, ctxs, psis, lams = _systems(2, 6)
