@@ -58,6 +58,7 @@ struct BatchSys {
 };
 
 constexpr long long SPIN_LIMIT = 1LL << 24;
+constexpr int VU = 4;  // rows per lane per round of the vector phases
 
 __device__ __forceinline__ double ld_coh(const double *p) {
   return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -98,13 +99,14 @@ template <bool COH>
 __device__ __forceinline__ double batch_row(int row, int c, int ng, int NG, const int32_t *rowptr,
                                             const int32_t *col, const double *val, const double *X,
                                             int k) {
+  constexpr int U = 8;  // gathers in flight per lane
   double acc = 0.0;
   const int jb = rowptr[row], je = rowptr[row + 1];
-  for (int j = jb + ng; j < je; j += 4 * NG) {
-    int ci[4];
-    double vv[4];
+  for (int j = jb + ng; j < je; j += U * NG) {
+    int ci[U];
+    double vv[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int jj = j + u * NG;
       const bool ok = jj < je;
       const int jc = ok ? jj : j;
@@ -113,7 +115,7 @@ __device__ __forceinline__ double batch_row(int row, int c, int ng, int NG, cons
       vv[u] = ok ? v : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const double *xp = X + (int64_t)ci[u] * k + c;
       acc += vv[u] * (COH ? ld_coh(xp) : *xp);
     }
@@ -301,14 +303,27 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     __syncthreads();
     // ---- B: R -= alpha Q ; r.z, r.r
     double brz = 0.0, brr = 0.0;
-    for (int base = r0; base < r1; base += rows_per_iter) {
-      const int row = base + wave * RPW + slot;
-      if (!(valid && row < r1 && ng == 0)) continue;
-      const int64_t ix = (int64_t)row * k + c;
-      const double r = d.R[ix] - s_alpha[c] * d.Q[ix];
-      d.R[ix] = r;
-      brr += r * r;
-      brz += r * (r / d.diag[row]);
+    // VU rows per lane per round, their loads issued together
+    for (int base = r0; base < r1; base += VU * rows_per_iter) {
+      double rv[VU], qv[VU], dv[VU];
+#pragma unroll
+      for (int u = 0; u < VU; ++u) {
+        const int row = base + u * rows_per_iter + wave * RPW + slot;
+        const bool ok = valid && row < r1 && ng == 0;
+        const int64_t ix = (int64_t)(ok ? row : 0) * k + (ok ? c : 0);
+        rv[u] = ok ? d.R[ix] : 0.0;
+        qv[u] = ok ? d.Q[ix] : 0.0;
+        dv[u] = ok ? d.diag[row] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < VU; ++u) {
+        const int row = base + u * rows_per_iter + wave * RPW + slot;
+        if (!(valid && row < r1 && ng == 0)) continue;
+        const double r = rv[u] - s_alpha[c] * qv[u];
+        d.R[(int64_t)row * k + c] = r;
+        brr += r * r;
+        brz += r * (r / dv[u]);
+      }
     }
     wg_cols(brz, own, c, k, LPR, RPW, s_red, s_part);
     wg_cols(brr, own, c, k, LPR, RPW, s_red, s_part + k);
@@ -338,13 +353,26 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     }
     __syncthreads();
     // ---- C: X += alpha P ; P = D^{-1} R + beta P
-    for (int base = r0; base < r1; base += rows_per_iter) {
-      const int row = base + wave * RPW + slot;
-      if (!(valid && row < r1 && ng == 0)) continue;
-      const int64_t ix = (int64_t)row * k + c;
-      const double p = ld_coh(d.P + ix);
-      d.X[ix] += s_alpha[c] * p;
-      st_coh(d.P + ix, d.R[ix] / d.diag[row] + s_beta[c] * p);
+    for (int base = r0; base < r1; base += VU * rows_per_iter) {
+      double pv[VU], xv[VU], rv[VU], dv[VU];
+#pragma unroll
+      for (int u = 0; u < VU; ++u) {
+        const int row = base + u * rows_per_iter + wave * RPW + slot;
+        const bool ok = valid && row < r1 && ng == 0;
+        const int64_t ix = (int64_t)(ok ? row : 0) * k + (ok ? c : 0);
+        pv[u] = ok ? ld_coh(d.P + ix) : 0.0;
+        xv[u] = ok ? d.X[ix] : 0.0;
+        rv[u] = ok ? d.R[ix] : 0.0;
+        dv[u] = ok ? d.diag[row] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < VU; ++u) {
+        const int row = base + u * rows_per_iter + wave * RPW + slot;
+        if (!(valid && row < r1 && ng == 0)) continue;
+        const int64_t ix = (int64_t)row * k + c;
+        d.X[ix] = xv[u] + s_alpha[c] * pv[u];
+        st_coh(d.P + ix, rv[u] / dv[u] + s_beta[c] * pv[u]);
+      }
     }
     if (s_flags[0] && !s_flags[1])
       if (!team_barrier(d.bar, team, d.status)) return;
