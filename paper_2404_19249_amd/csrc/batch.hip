@@ -137,12 +137,32 @@ __device__ __forceinline__ void wg_cols(double a, bool own, int c, int k, int LP
   __syncthreads();
 }
 
-// sum of the team's partials (fixed order) for W values -> s_sum
-__device__ __forceinline__ void team_sum(const double *part, int team, int W, double *s_sum) {
-  for (int i = threadIdx.x; i < W; i += blockDim.x) {
-    double s = 0.0;
-    for (int t = 0; t < team; ++t) s += ld_coh(part + (int64_t)t * 9 * MAX_K + i);
-    s_sum[i] = s;
+// sum of the team's partials for W <= blockDim values -> s_sum.  The
+// workgroup's threads split the members into S = blockDim / W strided
+// slices (four loads in flight per thread), then S partial sums per value
+// are added in slice order: the order depends only on (team, W, blockDim),
+// so every member of the team forms the same sums.  s_tmp: blockDim doubles.
+__device__ __forceinline__ void team_sum(const double *part, int team, int W, double *s_tmp,
+                                         double *s_sum) {
+  const int S = (int)blockDim.x / W, tid = threadIdx.x;
+  if (tid < S * W) {
+    const int j = tid % W;
+    const double *p = part + j;
+    const int64_t ps = 9 * MAX_K;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int t = tid / W;
+    for (; t + 3 * S < team; t += 4 * S) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += ld_coh(p + (int64_t)(t + u * S) * ps);
+    }
+    for (; t < team; t += S) a[0] += ld_coh(p + (int64_t)t * ps);
+    s_tmp[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  __syncthreads();
+  for (int j = tid; j < W; j += blockDim.x) {
+    double v = 0.0;
+    for (int q = 0; q < S; ++q) v += s_tmp[q * W + j];
+    s_sum[j] = v;
   }
   __syncthreads();
 }
@@ -252,7 +272,7 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
   wg_cols(arz, own, c, k, LPR, RPW, s_red, s_part + 2 * k);
   for (int i = threadIdx.x; i < W3; i += blockDim.x) st_coh(partI + (int64_t)rank * PS + i, s_part[i]);
   if (!team_barrier(d.bar, team, d.status)) return;
-  team_sum(partI, team, W3, s_sum);
+  team_sum(partI, team, W3, s_red, s_sum);
   for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
     s_bb[cc] = s_sum[cc];
     s_rr[cc] = s_sum[k + cc];
@@ -291,9 +311,9 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     wg_cols(apq, own, c, k, LPR, RPW, s_red, s_part);
     for (int i = threadIdx.x; i < k; i += blockDim.x) st_coh(partA + (int64_t)rank * PS + i, s_part[i]);
     if (!team_barrier(d.bar, team, d.status)) return;
+    team_sum(partA, team, k, s_red, s_sum);
     for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
-      double pq = 0.0;
-      for (int t = 0; t < team; ++t) pq += ld_coh(partA + (int64_t)t * PS + cc);
+      const double pq = s_sum[cc];
       s_alpha[cc] = 0.0;
       if (s_active[cc]) {
         if (!(pq > 0.0)) s_flags[1] = 1;
@@ -329,12 +349,9 @@ __global__ void __launch_bounds__(256) k_batch_pcg(const BatchSys *__restrict__ 
     wg_cols(brr, own, c, k, LPR, RPW, s_red, s_part + k);
     for (int i = threadIdx.x; i < 2 * k; i += blockDim.x) st_coh(partB + (int64_t)rank * PS + i, s_part[i]);
     if (!team_barrier(d.bar, team, d.status)) return;
+    team_sum(partB, team, 2 * k, s_red, s_sum);
     for (int cc = threadIdx.x; cc < k; cc += blockDim.x) {
-      double rz = 0.0, rr = 0.0;
-      for (int t = 0; t < team; ++t) {
-        rz += ld_coh(partB + (int64_t)t * PS + cc);
-        rr += ld_coh(partB + (int64_t)t * PS + k + cc);
-      }
+      const double rz = s_sum[cc], rr = s_sum[k + cc];
       if (s_active[cc]) {
         s_beta[cc] = rz / s_rz[cc];
         s_rz[cc] = rz;
