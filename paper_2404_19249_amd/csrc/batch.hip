@@ -175,10 +175,22 @@ __device__ __forceinline__ void batch_tiled_product(const BatchSys &d, int b0, i
                                                     double *s_halo, double &apq) {
   const int BR = d.tile_br, rows_per_iter = (blockDim.x >> 6) * RPW;
   for (int blk = b0; blk < b1; ++blk) {
-    const int hb = d.halo_ptr[blk], nh = d.halo_ptr[blk + 1] - hb;
-    for (int i = threadIdx.x; i < nh * k; i += blockDim.x) {
-      const int h = i / k, cc = i - h * k;
-      s_halo[i] = ld_coh(d.P + (int64_t)d.halo_col[hb + h] * k + cc);
+    const int hb = d.halo_ptr[blk], tot = (d.halo_ptr[blk + 1] - hb) * k;
+    // eight coherent loads in flight per thread before the LDS writes
+    constexpr int SU = 8;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += SU * (int)blockDim.x) {
+      double v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        const int h = i / k, cc = i - h * k;
+        v[u] = i < tot ? ld_coh(d.P + (int64_t)d.halo_col[hb + (i < tot ? h : 0)] * k + cc) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        if (i < tot) s_halo[i] = v[u];
+      }
     }
     __syncthreads();
     const int rb = blk * BR, nr = min(BR, d.N - rb);
