@@ -339,7 +339,8 @@ void launch_prec_diag(int N, double a, const double *dK, double b, const double 
 }
 
 // Coarse blocks of the projection F = Z^T H Z, Z = [P | T], P the coarse
-// interpolation in ELL form (4 (index, weight) per fine row).  One wavefront
+// interpolation in ELL form (4 (index, weight) per fine row, the valid
+// indices of a row distinct: the vertices of one coarse tetrahedron).  One wavefront
 // per block of CP_ROWS consecutive rows; the block's own coarse indices
 // (those of its rows' P rows, list `own`) and its neighbours' (those of the
 // P rows of its rows' columns, list `nbr`) are given.  Partials (fixed
@@ -361,8 +362,11 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
                                                          const int64_t *__restrict__ ptoff, double *__restrict__ pp,
                                                          double *__restrict__ pt, int ldt, int ldo) {
   extern __shared__ double s_dyn[];
-  double *s_t = s_dyn;                           // [CP_ROWS][ldt]: (H P)[i][nbr_v]
-  double *s_p = s_dyn + CP_ROWS * ldt;           // [CP_ROWS][ldo]: P[i][own_u]
+  // (H P)[i][nbr_v] at pitch lt = ldt + 1: slot ldt takes the products of
+  // absent (-1) P entries and is never read
+  const int lt = ldt + 1;
+  double *s_t = s_dyn;                           // [CP_ROWS][lt]
+  double *s_p = s_dyn + CP_ROWS * lt;            // [CP_ROWS][ldo]: P[i][own_u]
   double *s_y = s_p + CP_ROWS * ldo;             // [CP_ROWS][k]: Y[i][j]
   __shared__ int16_t s_map[256];                 // coarse index -> position in nbr (-1)
   __shared__ int16_t s_umap[256];                // coarse index -> position in own (-1)
@@ -373,7 +377,7 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
     s_map[i] = -1;
     s_umap[i] = -1;
   }
-  for (int i = t; i < CP_ROWS * (ldt + ldo); i += CP_ROWS) s_dyn[i] = 0.0;
+  for (int i = t; i < CP_ROWS * (lt + ldo); i += CP_ROWS) s_dyn[i] = 0.0;
   __syncthreads();
   for (int v = t; v < nv; v += CP_ROWS) s_map[nlist[v0 + v]] = (int16_t)v;
   for (int u = t; u < nu; u += CP_ROWS) s_umap[ulist[u0 + u]] = (int16_t)u;
@@ -386,7 +390,7 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
       const int I = Pidx[4 * (int64_t)i + c];
       if (I >= 0) s_p[t * ldo + s_umap[I]] = Pw[4 * (int64_t)i + c];
     }
-    double *ti = s_t + t * ldt;
+    double *ti = s_t + t * lt;
     const int jb = rowptr[i], je = rowptr[i + 1];
     // four nonzeros at a time: their columns, values and P rows are loaded
     // before any of them is accumulated
@@ -407,12 +411,18 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
         pa[u] = *reinterpret_cast<const double2 *>(Pw + 4 * (int64_t)j4[u]);
         pb[u] = *reinterpret_cast<const double2 *>(Pw + 4 * (int64_t)j4[u] + 2);
       }
+      // a P row's valid slots are distinct, so its four accumulators are
+      // read together, then written (one LDS round trip per nonzero, not
+      // four); nonzeros follow one another, as their slots may repeat
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (pi[u].x >= 0) ti[s_map[pi[u].x]] += h4[u] * pa[u].x;
-        if (pi[u].y >= 0) ti[s_map[pi[u].y]] += h4[u] * pa[u].y;
-        if (pi[u].z >= 0) ti[s_map[pi[u].z]] += h4[u] * pb[u].x;
-        if (pi[u].w >= 0) ti[s_map[pi[u].w]] += h4[u] * pb[u].y;
+        const int a0 = pi[u].x >= 0 ? s_map[pi[u].x] : ldt, a1 = pi[u].y >= 0 ? s_map[pi[u].y] : ldt;
+        const int a2 = pi[u].z >= 0 ? s_map[pi[u].z] : ldt, a3 = pi[u].w >= 0 ? s_map[pi[u].w] : ldt;
+        const double v0 = ti[a0], v1 = ti[a1], v2 = ti[a2], v3 = ti[a3];
+        ti[a0] = v0 + h4[u] * pa[u].x;
+        ti[a1] = v1 + h4[u] * pa[u].y;
+        ti[a2] = v2 + h4[u] * pb[u].x;
+        ti[a3] = v3 + h4[u] * pb[u].y;
       }
     }
   }
@@ -421,7 +431,7 @@ __global__ void __launch_bounds__(CP_ROWS) k_proj_coarse(int N, int n_H, int k, 
   for (int o = t; o < nu * nv; o += CP_ROWS) {
     const int u = o / nv, v = o - u * nv;
     double acc = 0.0;
-    for (int r = 0; r < nr; ++r) acc += s_p[r * ldo + u] * s_t[r * ldt + v];
+    for (int r = 0; r < nr; ++r) acc += s_p[r * ldo + u] * s_t[r * lt + v];
     ppb[o] = acc;
   }
   double *ptb = pt + ptoff[b];
@@ -466,7 +476,7 @@ int launch_proj_coarse(int N, int n_H, int k, int kmax, int nblk, int ldt, int l
                        const int64_t *ptoff, double *pp, double *pt, const int32_t *gpp_ptr, const int64_t *gpp_idx,
                        const int32_t *gpt_ptr, const int64_t *gpt_idx, double *F, int m, hipStream_t s) {
   if (n_H > 256 || k > kmax) return -1;
-  const size_t lds = sizeof(double) * (size_t)CP_ROWS * (ldt + ldo + k);
+  const size_t lds = sizeof(double) * (size_t)CP_ROWS * (ldt + 1 + ldo + k);
   if (lds > 60 * 1024) return -1;
   hipLaunchKernelGGL(k_proj_coarse, dim3(nblk), dim3(CP_ROWS), lds, s, N, n_H, k, kmax, rowptr, col, H, Pidx, Pw,
                      Y, uoff, ulist, noff, nlist, ppoff, ptoff, pp, pt, ldt, ldo);

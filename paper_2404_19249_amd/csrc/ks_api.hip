@@ -853,6 +853,15 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
       for (int j = 0; j < 4; ++j) {
         const int ci = cint[vid[4 * (size_t)r + j]];
         if (ci < 0 || wv[4 * (size_t)r + j] == 0.0) continue;  // coarse boundary vertex: no basis function
+        // an index seen before in this row (an element with a repeated
+        // vertex) takes the weight: the row's indices stay distinct
+        int dup = -1;
+        for (int q = 0; q < cnt; ++q)
+          if (Pidx[4 * (size_t)r + q] == ci) dup = q;
+        if (dup >= 0) {
+          Pw[4 * (size_t)r + dup] += wv[4 * (size_t)r + j];
+          continue;
+        }
         Pidx[4 * (size_t)r + cnt] = ci;
         Pw[4 * (size_t)r + cnt] = wv[4 * (size_t)r + j];
         ++cnt;
@@ -921,7 +930,7 @@ extern "C" int ks_create_nonnested(const ks_mesh_desc *mesh, const ks_mesh_desc 
     }
     cp_ldt = std::max(cp_ldt, 1);
     cp_ldo = std::max(cp_ldo, 1);
-    if (sizeof(double) * (size_t)CP_ROWS * (cp_ldt + cp_ldo + c->k_max) > 60 * 1024) cp_ok = 0;
+    if (sizeof(double) * (size_t)CP_ROWS * (cp_ldt + 1 + cp_ldo + c->k_max) > 60 * 1024) cp_ok = 0;
     if (cp_ok) {
       const int nH = c->N_H, km = c->k_max;
       cp_uoff.assign(cp_nblk + 1, 0);
