@@ -316,6 +316,12 @@ static int tile_index(int br);
 // Y = A X over ncols columns, X and Y with row pitches ldx, ldy (elements):
 // halo tiles over column chunks, else the row kernel
 static void spmm_cols(ks_ctx *c, const double *val, const double *X, int ldx, double *Y, int ldy, int ncols) {
+  // up to the solver's column count: one pass over the FP64 solver's tiling
+  // (the operator is read once), where its LDS image fits these columns
+  if (ncols <= c->k_max && c->pw64.til &&
+      launch_spmm_tiled_cols(c->N, ncols, ldx, ldy, ncols, *c->pw64.til, c->pw64.til_tb, c->rowptr, val, X, Y,
+                             nullptr, c->s) == 0)
+    return;
   const int ti = tile_index(c->proj_br);
   if (ti >= 0 && c->til[ti].nblk &&
       launch_spmm_tiled_cols(c->N, ncols, ldx, ldy, c->proj_kc, c->til[ti], c->proj_tb, c->rowptr, val, X, Y,
